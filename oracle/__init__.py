@@ -1,0 +1,258 @@
+"""FP64 CPU oracle of the Barnes-Hut step of "Accelerated FDPS".
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The GPU
+product (``paper_1907_02290_amd``) never imports it and it never imports the
+product.  The arithmetic lives in ``orc.c`` (plain C, FP64, no FMA
+contraction); this module only marshals numpy arrays through ctypes.
+
+Stage map (paper sections):
+  root / keys ...... section 4.3, local tree step 1 (root cell, Morton keys)
+  Tree(...) ........ section 4.3, steps 2-4 (stable sort, reorder, link),
+                     the moment pass, and the particle groups of section 2
+  make_lists ....... section 4.3 list construction, indices per section 4.1
+  refresh .......... section 4.2 reuse step (moments over frozen ranges)
+  force_lists ...... the kernel's sum over EPJ and SPJ of each list
+  force_direct ..... direct summation (what the tree approximates)
+  kick_drift ....... orbit integration (KDK leapfrog)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "orc.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+_lib = None
+
+
+def build_lib(force: bool = True) -> str:
+    """Compile ``orc.c`` into ``liborc.so`` with gcc (FP64, no contraction)."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-Wno-unused-parameter", _SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build_lib()
+    lib = C.CDLL(_LIB)
+    p = C.c_void_p
+    i64 = C.c_int64
+    d = C.c_double
+    lib.orc_root.argtypes = [i64, p, p, p, p, p]
+    lib.orc_keys.argtypes = [i64, p, p, p, p, C.c_int, p]
+    lib.orc_interleave.argtypes = [C.c_uint32] * 3
+    lib.orc_interleave.restype = C.c_uint64
+    lib.orc_deinterleave.argtypes = [C.c_uint64, C.c_int, p]
+    lib.orc_deinterleave.restype = None
+    lib.orc_build.argtypes = [i64, p, p, p, p, C.c_int, C.c_int]
+    lib.orc_build.restype = p
+    lib.orc_free.argtypes = [p]
+    lib.orc_free.restype = None
+    lib.orc_info.argtypes = [p, p, p]
+    lib.orc_get_keys.argtypes = [p, p, p]
+    lib.orc_get_cells.argtypes = [p] + [p] * 8
+    lib.orc_get_moments.argtypes = [p, p, p, p]
+    lib.orc_get_groups.argtypes = [p] + [p] * 6
+    lib.orc_make_lists.argtypes = [p, d, i64, p, p]
+    lib.orc_get_lists.argtypes = [p, p, p, p, p]
+    lib.orc_refresh.argtypes = [p, p, p, p, p]
+    lib.orc_force_lists.argtypes = [p, C.c_int, d, d, p, p, p, p]
+    lib.orc_force_direct.argtypes = [i64, p, p, p, p, d, d, i64, p, p, p, p, p]
+    lib.orc_kick_drift.argtypes = [i64, p, p, p, p, p, p, p, p, p, d, d, d, d]
+    lib.orc_num_threads.argtypes = []
+    for f in ("orc_root", "orc_keys", "orc_info", "orc_get_keys",
+              "orc_get_cells", "orc_get_moments", "orc_get_groups",
+              "orc_make_lists", "orc_get_lists", "orc_refresh",
+              "orc_force_lists", "orc_force_direct", "orc_kick_drift",
+              "orc_num_threads"):
+        getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError("oracle %s failed (rc=%d)" % (what, rc))
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def root(x, y, z):
+    """Root corner ``lo`` and exponent ``k`` (side ``L = 2**k``)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    lo = np.zeros(3)
+    k = C.c_int(0)
+    _check(_load().orc_root(x.size, _ptr(x), _ptr(y), _ptr(z), _ptr(lo),
+                            C.byref(k)), "root")
+    return lo, int(k.value)
+
+
+def keys(x, y, z, lo, k):
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    lo = _f64(lo)
+    out = np.zeros(x.size, dtype=np.uint64)
+    _check(_load().orc_keys(x.size, _ptr(x), _ptr(y), _ptr(z), _ptr(lo),
+                            int(k), _ptr(out)), "keys")
+    return out
+
+
+def interleave(qx, qy, qz) -> int:
+    return int(_load().orc_interleave(int(qx), int(qy), int(qz)))
+
+
+def deinterleave(key, level):
+    q = np.zeros(3, dtype=np.uint32)
+    _load().orc_deinterleave(int(key), int(level), _ptr(q))
+    return tuple(int(v) for v in q)
+
+
+class Tree:
+    """One construction step of the oracle: root, keys, sort, reorder,
+    link, moments and groups over FP64 particle arrays (input order)."""
+
+    def __init__(self, x, y, z, m, n_leaf=8, n_grp=64):
+        lib = _load()
+        self._x, self._y, self._z, self._m = (_f64(x), _f64(y), _f64(z),
+                                              _f64(m))
+        n = self._x.size
+        self._h = lib.orc_build(n, _ptr(self._x), _ptr(self._y),
+                                _ptr(self._z), _ptr(self._m), int(n_leaf),
+                                int(n_grp))
+        if not self._h:
+            raise RuntimeError("oracle build failed")
+        info = np.zeros(6, dtype=np.int64)
+        lo = np.zeros(3)
+        lib.orc_info(self._h, _ptr(info), _ptr(lo))
+        self.n, self.n_cell, self.n_groups, self.k = (int(v) for v in info[:4])
+        self.n_leaf, self.n_grp = int(info[4]), int(info[5])
+        self.lo = lo
+        self._sel = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _load().orc_free(h)
+            self._h = None
+
+    def keys(self):
+        key = np.zeros(self.n, dtype=np.uint64)
+        perm = np.zeros(self.n, dtype=np.uint32)
+        _check(_load().orc_get_keys(self._h, _ptr(key), _ptr(perm)), "keys")
+        return key, perm
+
+    def cells(self):
+        nc = self.n_cell
+        out = dict(prefix=np.zeros(nc, np.uint64), level=np.zeros(nc, np.uint8),
+                   begin=np.zeros(nc, np.uint32), count=np.zeros(nc, np.uint32),
+                   parent=np.zeros(nc, np.uint32), skip=np.zeros(nc, np.uint32),
+                   leaf=np.zeros(nc, np.uint8), ctr=np.zeros((nc, 3)))
+        _check(_load().orc_get_cells(self._h, *(_ptr(out[k]) for k in (
+            "prefix", "level", "begin", "count", "parent", "skip", "leaf",
+            "ctr"))), "cells")
+        return out
+
+    def moments(self):
+        nc = self.n_cell
+        mass, com, quad = np.zeros(nc), np.zeros((nc, 3)), np.zeros((nc, 6))
+        _check(_load().orc_get_moments(self._h, _ptr(mass), _ptr(com),
+                                       _ptr(quad)), "moments")
+        return mass, com, quad
+
+    def groups(self):
+        ng = self.n_groups
+        out = dict(cell=np.zeros(ng, np.uint32), begin=np.zeros(ng, np.uint32),
+                   count=np.zeros(ng, np.uint32), lo=np.zeros((ng, 3)),
+                   hi=np.zeros((ng, 3)), ctr=np.zeros((ng, 3)))
+        _check(_load().orc_get_groups(self._h, *(_ptr(out[k]) for k in (
+            "cell", "begin", "count", "lo", "hi", "ctr"))), "groups")
+        return out
+
+    def make_lists(self, theta, sel=None):
+        """Walk the selected groups (all when ``sel`` is None)."""
+        sizes = np.zeros(3, dtype=np.int64)
+        if sel is None:
+            rc = _load().orc_make_lists(self._h, float(theta), 0, None,
+                                        _ptr(sizes))
+        else:
+            s = np.ascontiguousarray(sel, dtype=np.int64)
+            rc = _load().orc_make_lists(self._h, float(theta), s.size,
+                                        _ptr(s), _ptr(sizes))
+        _check(rc, "make_lists")
+        self._sizes = sizes.copy()
+        return int(sizes[0]), int(sizes[1]), int(sizes[2])
+
+    def lists(self):
+        ns, ne, nsp = (int(v) for v in self._sizes)
+        eo = np.zeros(ns + 1, np.int64)
+        so = np.zeros(ns + 1, np.int64)
+        e = np.zeros(ne, np.uint32)
+        s = np.zeros(nsp, np.uint32)
+        _check(_load().orc_get_lists(self._h, _ptr(eo), _ptr(e), _ptr(so),
+                                     _ptr(s)), "lists")
+        return eo, e, so, s
+
+    def refresh(self, x, y, z, m):
+        """Reuse step: new positions (input order), frozen topology."""
+        self._x, self._y, self._z, self._m = (_f64(x), _f64(y), _f64(z),
+                                              _f64(m))
+        _check(_load().orc_refresh(self._h, _ptr(self._x), _ptr(self._y),
+                                   _ptr(self._z), _ptr(self._m)), "refresh")
+
+    def force_lists(self, order=1, eps=0.0, G=1.0):
+        """FP64 sum over the saved lists; NaN for particles of groups that
+        were not walked.  Input order."""
+        out = [np.full(self.n, np.nan) for _ in range(4)]
+        _check(_load().orc_force_lists(self._h, int(order), float(eps),
+                                       float(G), *(_ptr(a) for a in out)),
+               "force_lists")
+        return tuple(out)
+
+
+def force_direct(x, y, z, m, eps=0.0, G=1.0, targets=None):
+    x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
+    n = x.size
+    tgt = np.arange(n, dtype=np.int64) if targets is None else \
+        np.ascontiguousarray(targets, dtype=np.int64)
+    out = [np.zeros(tgt.size) for _ in range(4)]
+    _check(_load().orc_force_direct(n, _ptr(x), _ptr(y), _ptr(z), _ptr(m),
+                                    float(eps), float(G), tgt.size, _ptr(tgt),
+                                    *(_ptr(a) for a in out)), "force_direct")
+    return tuple(out)
+
+
+def kick_drift(pos, vel, acc, dt_kick, dt_drift, ext_mass=0.0, G=1.0):
+    """In place on ``pos`` and ``vel`` (lists of three FP64 arrays)."""
+    for a in list(pos) + list(vel):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    acc = [_f64(a) for a in acc]
+    n = pos[0].size
+    _check(_load().orc_kick_drift(n, *(_ptr(a) for a in pos),
+                                  *(_ptr(a) for a in vel),
+                                  *(_ptr(a) for a in acc), float(dt_kick),
+                                  float(dt_drift), float(ext_mass), float(G)),
+           "kick_drift")

@@ -1,0 +1,762 @@
+/*
+ * orc.c -- FP64 CPU oracle of the Barnes-Hut step of "Accelerated FDPS"
+ * (Iwasawa et al. 2019): root cell, Morton keys, stable key sort, reorder,
+ * octree link, multipole moments, particle groups, group-wise tree walk that
+ * emits index interaction lists, list forces, direct forces, kick-drift.
+ *
+ * TEST INFRASTRUCTURE ONLY: only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no code, header,
+ * table or helper with the GPU library, and the GPU library never calls it.
+ *
+ * Plain and slow on purpose: every stage follows the paper's description in
+ * its own order, in FP64, with no blocking or fusion.  Where the paper is
+ * silent the reading used is stated at the function.  Built with
+ * -ffp-contract=off so that every product and sum is rounded on its own.
+ *
+ * Readings of points the paper leaves open (all stated again in the design
+ * notes of the repository):
+ *   R1 root cell: cube anchored at the per-axis minimum, side L = 2^k, the
+ *      smallest power of two strictly larger than the largest extent.
+ *   R2 keys: 21 bits per axis, 63-bit key, x is the most significant bit of
+ *      every 3-bit digit.
+ *   R3 sort: stable, equal keys keep their input order.
+ *   R4 link: a cell is split iff it holds more than n_leaf particles and its
+ *      level is below 21; only non-empty octants become children; cells are
+ *      numbered in DFS pre-order, children in octant order.
+ *   R5 groups: a group is a cell that holds at most n_grp particles (or is a
+ *      leaf) and whose parent holds more than n_grp particles (or is the
+ *      root itself).
+ *   R6 opening test: distance from the group's tight box to the geometric
+ *      centre of the cell, accepted iff d^2 > (s/theta)^2 with s the side of
+ *      the cell; a cell whose particle range contains the group's is opened.
+ *   R7 softening: Plummer, also inside superparticle terms; the particle
+ *      itself is skipped (its pull is exactly zero, its potential is
+ *      excluded).
+ *   R8 quadrupole: second-order Taylor expansion of the softened kernel about
+ *      the centre of mass, with S_ab = sum m (x-X)_a (x-X)_b (not traceless).
+ */
+#include "orc.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define KEY_BITS 21
+#define MAX_LEVEL 21
+
+struct orc_tree {
+  int64_t n;
+  int n_leaf, n_grp;
+  double lo[3];
+  int k;
+  /* particles in sorted (Morton) order */
+  uint64_t* key;
+  uint32_t* perm; /* sorted position -> input index */
+  double *x, *y, *z, *m;
+  /* cells, DFS pre-order */
+  int64_t n_cell, cap_cell;
+  uint64_t* prefix;
+  uint8_t* level;
+  uint8_t* leaf;
+  uint32_t *begin, *count, *parent, *skip;
+  double* ctr; /* 3 per cell */
+  double* mass;
+  double* com;  /* 3 per cell */
+  double* quad; /* 6 per cell: xx yy zz xy xz yz */
+  /* groups */
+  int64_t n_groups;
+  uint32_t *g_cell, *g_begin, *g_count;
+  double *g_lo, *g_hi, *g_ctr; /* 3 per group */
+  /* lists over the last walked selection */
+  int have_lists;
+  int64_t n_sel;
+  int64_t* sel;
+  int64_t *epj_off, *spj_off;
+  uint32_t *epj, *spj;
+};
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------------- */
+/* Root cell (section 4.3: the root cell is fixed from the positions of all
+ * particles before the local tree is made).  Reading R1. */
+int orc_root(int64_t n, const double* x, const double* y, const double* z,
+             double lo[3], int* k) {
+  if (n <= 0 || !x || !y || !z || !lo || !k) return -1;
+  const double* p[3] = {x, y, z};
+  double ext = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double mn = p[a][0], mx = p[a][0];
+    for (int64_t i = 1; i < n; ++i) {
+      if (p[a][i] < mn) mn = p[a][i];
+      if (p[a][i] > mx) mx = p[a][i];
+    }
+    lo[a] = mn;
+    double e = mx - mn;
+    if (e > ext) ext = e;
+  }
+  if (!(ext >= 0.0) || isinf(ext)) return -1; /* NaN or inf input */
+  if (ext == 0.0) {
+    *k = 0;
+    return 0;
+  }
+  /* smallest k with 2^k > ext */
+  int kk;
+  frexp(ext, &kk);
+  while (ldexp(1.0, kk) <= ext) kk++;
+  while (ldexp(1.0, kk - 1) > ext) kk--;
+  *k = kk;
+  return 0;
+}
+
+uint64_t orc_interleave(uint32_t qx, uint32_t qy, uint32_t qz) {
+  uint64_t key = 0;
+  for (int b = 0; b < KEY_BITS; ++b) {
+    key |= (uint64_t)((qx >> b) & 1u) << (3 * b + 2);
+    key |= (uint64_t)((qy >> b) & 1u) << (3 * b + 1);
+    key |= (uint64_t)((qz >> b) & 1u) << (3 * b);
+  }
+  return key;
+}
+
+/* Integer cell coordinates (level bits per axis) of the level-`level` cell
+ * that holds `key`. */
+void orc_deinterleave(uint64_t key, int level, uint32_t q[3]) {
+  uint64_t p = key >> (3 * (MAX_LEVEL - level));
+  q[0] = q[1] = q[2] = 0;
+  for (int b = 0; b < level; ++b) {
+    q[0] |= (uint32_t)((p >> (3 * b + 2)) & 1u) << b;
+    q[1] |= (uint32_t)((p >> (3 * b + 1)) & 1u) << b;
+    q[2] |= (uint32_t)((p >> (3 * b)) & 1u) << b;
+  }
+}
+
+/* Morton keys (section 4.3, local tree step 1).  Reading R2: quantise the
+ * offset from the root corner to 21 bits per axis. */
+int orc_keys(int64_t n, const double* x, const double* y, const double* z,
+             const double lo[3], int k, uint64_t* key) {
+  if (n < 0 || (n > 0 && (!x || !y || !z || !key))) return -1;
+  const double scale = ldexp(1.0, KEY_BITS - k);
+  const double qmax = (double)((1u << KEY_BITS) - 1u);
+  const double* p[3] = {x, y, z};
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t q[3];
+    for (int a = 0; a < 3; ++a) {
+      double d = p[a][i] - lo[a];
+      double f = floor(d * scale);
+      if (f < 0.0) f = 0.0;
+      if (f > qmax) f = qmax;
+      q[a] = (uint32_t)f;
+    }
+    key[i] = orc_interleave(q[0], q[1], q[2]);
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Stable sort of key-index pairs (section 4.3, local tree step 2; reading
+ * R3).  qsort on (key, input index) pairs is the stable order because the
+ * second field breaks every tie. */
+typedef struct {
+  uint64_t key;
+  uint32_t idx;
+} kv_t;
+
+static int kv_cmp(const void* a, const void* b) {
+  const kv_t* u = (const kv_t*)a;
+  const kv_t* v = (const kv_t*)b;
+  if (u->key != v->key) return u->key < v->key ? -1 : 1;
+  if (u->idx != v->idx) return u->idx < v->idx ? -1 : 1;
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+static int grow_cells(orc_tree* t) {
+  int64_t cap = t->cap_cell ? 2 * t->cap_cell : 1024;
+#define GROW(ptr, type, per)                                         \
+  do {                                                               \
+    void* np = realloc(t->ptr, (size_t)cap * (per) * sizeof(type));  \
+    if (!np) return -1;                                              \
+    t->ptr = (type*)np;                                              \
+  } while (0)
+  GROW(prefix, uint64_t, 1);
+  GROW(level, uint8_t, 1);
+  GROW(leaf, uint8_t, 1);
+  GROW(begin, uint32_t, 1);
+  GROW(count, uint32_t, 1);
+  GROW(parent, uint32_t, 1);
+  GROW(skip, uint32_t, 1);
+  GROW(ctr, double, 3);
+#undef GROW
+  t->cap_cell = cap;
+  return 0;
+}
+
+/* Geometric centre of a cell: root corner + (2q+1) * L * 2^-(level+1). */
+static void cell_centre(const orc_tree* t, uint64_t first_key, int level,
+                        double out[3]) {
+  uint32_t q[3];
+  orc_deinterleave(first_key, level, q);
+  const double half = ldexp(1.0, t->k - level - 1);
+  for (int a = 0; a < 3; ++a)
+    out[a] = t->lo[a] + (2.0 * (double)q[a] + 1.0) * half;
+}
+
+/* Link (section 4.3, local tree step 4; reading R4): top-down, a cell over
+ * the sorted range [b, e) at `level`; children are the runs of equal
+ * next-level digit.  Recursion order gives DFS pre-order ids. */
+static int link_cell(orc_tree* t, int level, int64_t b, int64_t e,
+                     uint32_t parent_id) {
+  if (t->n_cell == t->cap_cell && grow_cells(t)) return -1;
+  const int64_t id = t->n_cell++;
+  t->prefix[id] = t->key[b] >> (3 * (MAX_LEVEL - level));
+  t->level[id] = (uint8_t)level;
+  t->begin[id] = (uint32_t)b;
+  t->count[id] = (uint32_t)(e - b);
+  t->parent[id] = parent_id;
+  cell_centre(t, t->key[b], level, &t->ctr[3 * id]);
+  const int split = (e - b) > t->n_leaf && level < MAX_LEVEL;
+  t->leaf[id] = (uint8_t)!split;
+  if (split) {
+    const int sh = 3 * (MAX_LEVEL - (level + 1));
+    int64_t cb = b;
+    for (uint64_t oct = 0; oct < 8; ++oct) {
+      const uint64_t want = (t->prefix[id] << 3) | oct;
+      int64_t ce = cb;
+      while (ce < e && (t->key[ce] >> sh) == want) ce++;
+      if (ce > cb) {
+        if (link_cell(t, level + 1, cb, ce, (uint32_t)id)) return -1;
+        cb = ce;
+      }
+    }
+    if (cb != e) return -1; /* keys not sorted: cannot happen */
+  }
+  t->skip[id] = (uint32_t)t->n_cell;
+  return 0;
+}
+
+/* Multipole moments of every cell over its particle range (section 4.3:
+ * moments are recomputed at every step, reuse steps included). */
+static void compute_moments(orc_tree* t) {
+  for (int64_t c = 0; c < t->n_cell; ++c) {
+    const int64_t b = t->begin[c], e = b + t->count[c];
+    double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int64_t i = b; i < e; ++i) {
+      M += t->m[i];
+      sx += t->m[i] * t->x[i];
+      sy += t->m[i] * t->y[i];
+      sz += t->m[i] * t->z[i];
+    }
+    double X[3];
+    if (M > 0.0) {
+      X[0] = sx / M;
+      X[1] = sy / M;
+      X[2] = sz / M;
+    } else {
+      X[0] = t->ctr[3 * c];
+      X[1] = t->ctr[3 * c + 1];
+      X[2] = t->ctr[3 * c + 2];
+    }
+    double S[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = b; i < e; ++i) {
+      const double dx = t->x[i] - X[0], dy = t->y[i] - X[1],
+                   dz = t->z[i] - X[2];
+      S[0] += t->m[i] * dx * dx;
+      S[1] += t->m[i] * dy * dy;
+      S[2] += t->m[i] * dz * dz;
+      S[3] += t->m[i] * dx * dy;
+      S[4] += t->m[i] * dx * dz;
+      S[5] += t->m[i] * dy * dz;
+    }
+    t->mass[c] = M;
+    memcpy(&t->com[3 * c], X, sizeof X);
+    memcpy(&t->quad[6 * c], S, sizeof S);
+  }
+}
+
+/* Particle groups (Barnes' vectorisation, section 2; reading R5). */
+static int make_groups(orc_tree* t) {
+  int64_t ng = 0;
+  for (int64_t c = 0; c < t->n_cell; ++c) {
+    const int small = t->count[c] <= (uint32_t)t->n_grp || t->leaf[c];
+    const int top = c == 0 || t->count[t->parent[c]] > (uint32_t)t->n_grp;
+    if (small && top) ng++;
+  }
+  t->n_groups = ng;
+  t->g_cell = (uint32_t*)malloc((size_t)(ng ? ng : 1) * sizeof(uint32_t));
+  t->g_begin = (uint32_t*)malloc((size_t)(ng ? ng : 1) * sizeof(uint32_t));
+  t->g_count = (uint32_t*)malloc((size_t)(ng ? ng : 1) * sizeof(uint32_t));
+  t->g_lo = (double*)malloc((size_t)(ng ? ng : 1) * 3 * sizeof(double));
+  t->g_hi = (double*)malloc((size_t)(ng ? ng : 1) * 3 * sizeof(double));
+  t->g_ctr = (double*)malloc((size_t)(ng ? ng : 1) * 3 * sizeof(double));
+  if (!t->g_cell || !t->g_begin || !t->g_count || !t->g_lo || !t->g_hi ||
+      !t->g_ctr)
+    return -1;
+  int64_t g = 0;
+  for (int64_t c = 0; c < t->n_cell; ++c) {
+    const int small = t->count[c] <= (uint32_t)t->n_grp || t->leaf[c];
+    const int top = c == 0 || t->count[t->parent[c]] > (uint32_t)t->n_grp;
+    if (!(small && top)) continue;
+    t->g_cell[g] = (uint32_t)c;
+    t->g_begin[g] = t->begin[c];
+    t->g_count[g] = t->count[c];
+    const int64_t b = t->begin[c], e = b + t->count[c];
+    const double* p[3] = {t->x, t->y, t->z};
+    for (int a = 0; a < 3; ++a) {
+      double mn = p[a][b], mx = p[a][b];
+      for (int64_t i = b + 1; i < e; ++i) {
+        if (p[a][i] < mn) mn = p[a][i];
+        if (p[a][i] > mx) mx = p[a][i];
+      }
+      t->g_lo[3 * g + a] = mn;
+      t->g_hi[3 * g + a] = mx;
+      t->g_ctr[3 * g + a] = t->ctr[3 * c + a];
+    }
+    g++;
+  }
+  return 0;
+}
+
+static void free_lists(orc_tree* t) {
+  free(t->sel);
+  free(t->epj_off);
+  free(t->spj_off);
+  free(t->epj);
+  free(t->spj);
+  t->sel = NULL;
+  t->epj_off = t->spj_off = NULL;
+  t->epj = t->spj = NULL;
+  t->have_lists = 0;
+  t->n_sel = 0;
+}
+
+void orc_free(orc_tree* t) {
+  if (!t) return;
+  free(t->key);
+  free(t->perm);
+  free(t->x);
+  free(t->y);
+  free(t->z);
+  free(t->m);
+  free(t->prefix);
+  free(t->level);
+  free(t->leaf);
+  free(t->begin);
+  free(t->count);
+  free(t->parent);
+  free(t->skip);
+  free(t->ctr);
+  free(t->mass);
+  free(t->com);
+  free(t->quad);
+  free(t->g_cell);
+  free(t->g_begin);
+  free(t->g_count);
+  free(t->g_lo);
+  free(t->g_hi);
+  free(t->g_ctr);
+  free_lists(t);
+  free(t);
+}
+
+/* Construction step up to the groups: root, keys, sort, reorder, link,
+ * moments, groups (section 4.3). */
+orc_tree* orc_build(int64_t n, const double* x, const double* y,
+                    const double* z, const double* m, int n_leaf, int n_grp) {
+  if (n <= 0 || n > 0xFFFFFFF0LL || !x || !y || !z || !m || n_leaf < 1 ||
+      n_grp < 1)
+    return NULL;
+  orc_tree* t = (orc_tree*)calloc(1, sizeof(orc_tree));
+  if (!t) return NULL;
+  t->n = n;
+  t->n_leaf = n_leaf;
+  t->n_grp = n_grp;
+  if (orc_root(n, x, y, z, t->lo, &t->k)) goto fail;
+
+  uint64_t* raw = (uint64_t*)malloc((size_t)n * sizeof(uint64_t));
+  kv_t* kv = (kv_t*)malloc((size_t)n * sizeof(kv_t));
+  if (!raw || !kv) {
+    free(raw);
+    free(kv);
+    goto fail;
+  }
+  orc_keys(n, x, y, z, t->lo, t->k, raw);
+  for (int64_t i = 0; i < n; ++i) {
+    kv[i].key = raw[i];
+    kv[i].idx = (uint32_t)i;
+  }
+  free(raw);
+  qsort(kv, (size_t)n, sizeof(kv_t), kv_cmp);
+
+  t->key = (uint64_t*)malloc((size_t)n * sizeof(uint64_t));
+  t->perm = (uint32_t*)malloc((size_t)n * sizeof(uint32_t));
+  t->x = (double*)malloc((size_t)n * sizeof(double));
+  t->y = (double*)malloc((size_t)n * sizeof(double));
+  t->z = (double*)malloc((size_t)n * sizeof(double));
+  t->m = (double*)malloc((size_t)n * sizeof(double));
+  if (!t->key || !t->perm || !t->x || !t->y || !t->z || !t->m) {
+    free(kv);
+    goto fail;
+  }
+  /* reorder (section 4.3, local tree step 3) */
+  for (int64_t i = 0; i < n; ++i) {
+    t->key[i] = kv[i].key;
+    t->perm[i] = kv[i].idx;
+    t->x[i] = x[kv[i].idx];
+    t->y[i] = y[kv[i].idx];
+    t->z[i] = z[kv[i].idx];
+    t->m[i] = m[kv[i].idx];
+  }
+  free(kv);
+
+  if (link_cell(t, 0, 0, n, 0xFFFFFFFFu)) goto fail;
+  t->mass = (double*)malloc((size_t)t->n_cell * sizeof(double));
+  t->com = (double*)malloc((size_t)t->n_cell * 3 * sizeof(double));
+  t->quad = (double*)malloc((size_t)t->n_cell * 6 * sizeof(double));
+  if (!t->mass || !t->com || !t->quad) goto fail;
+  compute_moments(t);
+  if (make_groups(t)) goto fail;
+  return t;
+fail:
+  orc_free(t);
+  return NULL;
+}
+
+int orc_info(const orc_tree* t, int64_t info[6], double lo[3]) {
+  if (!t || !info) return -1;
+  info[0] = t->n;
+  info[1] = t->n_cell;
+  info[2] = t->n_groups;
+  info[3] = t->k;
+  info[4] = t->n_leaf;
+  info[5] = t->n_grp;
+  if (lo) memcpy(lo, t->lo, 3 * sizeof(double));
+  return 0;
+}
+
+int orc_get_keys(const orc_tree* t, uint64_t* key, uint32_t* perm) {
+  if (!t) return -1;
+  if (key) memcpy(key, t->key, (size_t)t->n * sizeof(uint64_t));
+  if (perm) memcpy(perm, t->perm, (size_t)t->n * sizeof(uint32_t));
+  return 0;
+}
+
+int orc_get_cells(const orc_tree* t, uint64_t* prefix, uint8_t* level,
+                  uint32_t* begin, uint32_t* count, uint32_t* parent,
+                  uint32_t* skip, uint8_t* leaf, double* ctr3) {
+  if (!t) return -1;
+  const size_t nc = (size_t)t->n_cell;
+  if (prefix) memcpy(prefix, t->prefix, nc * sizeof(uint64_t));
+  if (level) memcpy(level, t->level, nc);
+  if (begin) memcpy(begin, t->begin, nc * sizeof(uint32_t));
+  if (count) memcpy(count, t->count, nc * sizeof(uint32_t));
+  if (parent) memcpy(parent, t->parent, nc * sizeof(uint32_t));
+  if (skip) memcpy(skip, t->skip, nc * sizeof(uint32_t));
+  if (leaf) memcpy(leaf, t->leaf, nc);
+  if (ctr3) memcpy(ctr3, t->ctr, nc * 3 * sizeof(double));
+  return 0;
+}
+
+int orc_get_moments(const orc_tree* t, double* mass, double* com3,
+                    double* quad6) {
+  if (!t) return -1;
+  const size_t nc = (size_t)t->n_cell;
+  if (mass) memcpy(mass, t->mass, nc * sizeof(double));
+  if (com3) memcpy(com3, t->com, nc * 3 * sizeof(double));
+  if (quad6) memcpy(quad6, t->quad, nc * 6 * sizeof(double));
+  return 0;
+}
+
+int orc_get_groups(const orc_tree* t, uint32_t* cell, uint32_t* begin,
+                   uint32_t* count, double* lo3, double* hi3, double* ctr3) {
+  if (!t) return -1;
+  const size_t ng = (size_t)t->n_groups;
+  if (cell) memcpy(cell, t->g_cell, ng * sizeof(uint32_t));
+  if (begin) memcpy(begin, t->g_begin, ng * sizeof(uint32_t));
+  if (count) memcpy(count, t->g_count, ng * sizeof(uint32_t));
+  if (lo3) memcpy(lo3, t->g_lo, ng * 3 * sizeof(double));
+  if (hi3) memcpy(hi3, t->g_hi, ng * 3 * sizeof(double));
+  if (ctr3) memcpy(ctr3, t->g_ctr, ng * 3 * sizeof(double));
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Group tree walk (section 4.3 "construct the interaction lists"; indirect
+ * addressing of section 4.1: the lists hold 32-bit indices).  Reading R6.
+ * DFS from the root over the pre-order cell array; `skip` jumps over a
+ * subtree.  When `fill` is zero only the list lengths are counted. */
+static void walk_group(const orc_tree* t, int64_t g, const double* rcrit2,
+                       int fill, uint32_t* epj, uint32_t* spj, int64_t* n_epj,
+                       int64_t* n_spj) {
+  const uint32_t gb = t->g_begin[g];
+  const uint64_t ge = (uint64_t)gb + t->g_count[g];
+  const double* glo = &t->g_lo[3 * g];
+  const double* ghi = &t->g_hi[3 * g];
+  int64_t ne = 0, ns = 0;
+  int64_t c = 0;
+  while (c < t->n_cell) {
+    const uint32_t cb = t->begin[c];
+    const uint64_t ce = (uint64_t)cb + t->count[c];
+    int open;
+    if (cb <= gb && ce >= ge) {
+      open = 1; /* the cell holds the group */
+    } else {
+      double d[3];
+      for (int a = 0; a < 3; ++a) {
+        const double cc = t->ctr[3 * c + a];
+        double v = 0.0;
+        const double below = glo[a] - cc;
+        const double above = cc - ghi[a];
+        if (below > v) v = below;
+        if (above > v) v = above;
+        d[a] = v;
+      }
+      const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+      open = !(d2 > rcrit2[t->level[c]]);
+    }
+    if (!open) {
+      if (fill) spj[ns] = (uint32_t)c;
+      ns++;
+      c = t->skip[c];
+    } else if (t->leaf[c]) {
+      for (uint64_t j = cb; j < ce; ++j) {
+        if (fill) epj[ne] = (uint32_t)j;
+        ne++;
+      }
+      c = t->skip[c];
+    } else {
+      c = c + 1;
+    }
+  }
+  *n_epj = ne;
+  *n_spj = ns;
+}
+
+int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
+                   const int64_t* sel, int64_t sizes[3]) {
+  if (!t || theta < 0.0 || !sizes) return -1;
+  free_lists(t);
+  const int64_t ns_all = sel ? n_sel : t->n_groups;
+  if (ns_all < 0) return -1;
+  t->n_sel = ns_all;
+  t->sel = (int64_t*)malloc((size_t)(ns_all ? ns_all : 1) * sizeof(int64_t));
+  t->epj_off = (int64_t*)malloc((size_t)(ns_all + 1) * sizeof(int64_t));
+  t->spj_off = (int64_t*)malloc((size_t)(ns_all + 1) * sizeof(int64_t));
+  if (!t->sel || !t->epj_off || !t->spj_off) return -1;
+  for (int64_t s = 0; s < ns_all; ++s) {
+    const int64_t g = sel ? sel[s] : s;
+    if (g < 0 || g >= t->n_groups) return -1;
+    t->sel[s] = g;
+  }
+  /* critical radius per level: (s_l / theta)^2 with s_l = L 2^-l */
+  double rcrit2[MAX_LEVEL + 1];
+  for (int l = 0; l <= MAX_LEVEL; ++l) {
+    const double r = ldexp(1.0, t->k - l) / theta;
+    rcrit2[l] = r * r;
+  }
+  /* count pass */
+  int64_t* ne = (int64_t*)malloc((size_t)(ns_all ? ns_all : 1) * sizeof(int64_t));
+  int64_t* ns = (int64_t*)malloc((size_t)(ns_all ? ns_all : 1) * sizeof(int64_t));
+  if (!ne || !ns) {
+    free(ne);
+    free(ns);
+    return -1;
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t s = 0; s < ns_all; ++s)
+    walk_group(t, t->sel[s], rcrit2, 0, NULL, NULL, &ne[s], &ns[s]);
+  t->epj_off[0] = t->spj_off[0] = 0;
+  for (int64_t s = 0; s < ns_all; ++s) {
+    t->epj_off[s + 1] = t->epj_off[s] + ne[s];
+    t->spj_off[s + 1] = t->spj_off[s] + ns[s];
+  }
+  free(ne);
+  free(ns);
+  t->epj = (uint32_t*)malloc((size_t)(t->epj_off[ns_all] + 1) * sizeof(uint32_t));
+  t->spj = (uint32_t*)malloc((size_t)(t->spj_off[ns_all] + 1) * sizeof(uint32_t));
+  if (!t->epj || !t->spj) return -1;
+  /* fill pass */
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t s = 0; s < ns_all; ++s) {
+    int64_t a, b;
+    walk_group(t, t->sel[s], rcrit2, 1, t->epj + t->epj_off[s],
+               t->spj + t->spj_off[s], &a, &b);
+  }
+  sizes[0] = ns_all;
+  sizes[1] = t->epj_off[ns_all];
+  sizes[2] = t->spj_off[ns_all];
+  t->have_lists = 1;
+  return 0;
+}
+
+int orc_get_lists(const orc_tree* t, int64_t* epj_off, uint32_t* epj,
+                  int64_t* spj_off, uint32_t* spj) {
+  if (!t || !t->have_lists) return -1;
+  const size_t s = (size_t)t->n_sel;
+  if (epj_off) memcpy(epj_off, t->epj_off, (s + 1) * sizeof(int64_t));
+  if (spj_off) memcpy(spj_off, t->spj_off, (s + 1) * sizeof(int64_t));
+  if (epj) memcpy(epj, t->epj, (size_t)t->epj_off[s] * sizeof(uint32_t));
+  if (spj) memcpy(spj, t->spj, (size_t)t->spj_off[s] * sizeof(uint32_t));
+  return 0;
+}
+
+/* Reuse step (section 4.2): particle order, cells, groups and lists stay as
+ * built; only the particle data and the moments are refreshed. */
+int orc_refresh(orc_tree* t, const double* x, const double* y,
+                const double* z, const double* m) {
+  if (!t || !x || !y || !z || !m) return -1;
+  for (int64_t i = 0; i < t->n; ++i) {
+    const uint32_t s = t->perm[i];
+    t->x[i] = x[s];
+    t->y[i] = y[s];
+    t->z[i] = z[s];
+    t->m[i] = m[s];
+  }
+  compute_moments(t);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Forces from the interaction lists (section 4.3: the kernel evaluates the
+ * pull of the EPJ and SPJ of each list on the particles of its group).
+ * Readings R7 and R8. */
+int orc_force_lists(const orc_tree* t, int order, double eps, double G,
+                    double* ax, double* ay, double* az, double* pot) {
+  if (!t || !t->have_lists || !ax || !ay || !az || !pot) return -1;
+  if (order != 1 && order != 2) return -1;
+  const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t s = 0; s < t->n_sel; ++s) {
+    const int64_t g = t->sel[s];
+    const int64_t b = t->g_begin[g], e = b + t->g_count[g];
+    for (int64_t i = b; i < e; ++i) {
+      const double xi = t->x[i], yi = t->y[i], zi = t->z[i];
+      double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
+      for (int64_t q = t->epj_off[s]; q < t->epj_off[s + 1]; ++q) {
+        const int64_t j = t->epj[q];
+        if (j == i) continue;
+        const double dx = t->x[j] - xi, dy = t->y[j] - yi, dz = t->z[j] - zi;
+        const double r2 = dx * dx + dy * dy + dz * dz + eps2;
+        const double rinv = 1.0 / sqrt(r2);
+        const double mr = G * t->m[j] * rinv;
+        const double mr3 = mr * rinv * rinv;
+        fx += mr3 * dx;
+        fy += mr3 * dy;
+        fz += mr3 * dz;
+        ph -= mr;
+      }
+      for (int64_t q = t->spj_off[s]; q < t->spj_off[s + 1]; ++q) {
+        const int64_t c = t->spj[q];
+        const double* X = &t->com[3 * c];
+        const double M = t->mass[c];
+        /* r points from the expansion centre to the particle */
+        const double r[3] = {xi - X[0], yi - X[1], zi - X[2]};
+        const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
+        const double f = 1.0 / sqrt(r2);
+        const double f2 = f * f, f3 = f2 * f;
+        double acc[3] = {-M * f3 * r[0], -M * f3 * r[1], -M * f3 * r[2]};
+        double phi = -M * f;
+        if (order == 2) {
+          const double* S = &t->quad[6 * c];
+          /* S r with S = [[xx,xy,xz],[xy,yy,yz],[xz,yz,zz]] */
+          const double Sr[3] = {S[0] * r[0] + S[3] * r[1] + S[4] * r[2],
+                                S[3] * r[0] + S[1] * r[1] + S[5] * r[2],
+                                S[4] * r[0] + S[5] * r[1] + S[2] * r[2]};
+          const double qq = r[0] * Sr[0] + r[1] * Sr[1] + r[2] * Sr[2];
+          const double tr = S[0] + S[1] + S[2];
+          const double f5 = f3 * f2, f7 = f5 * f2;
+          phi -= (3.0 * qq * f2 - tr) * f3 / 2.0;
+          for (int a = 0; a < 3; ++a)
+            acc[a] += 3.0 * Sr[a] * f5 - 7.5 * qq * r[a] * f7 +
+                      1.5 * tr * r[a] * f5;
+        }
+        fx += G * acc[0];
+        fy += G * acc[1];
+        fz += G * acc[2];
+        ph += G * phi;
+      }
+      const uint32_t o = t->perm[i];
+      ax[o] = fx;
+      ay[o] = fy;
+      az[o] = fz;
+      pot[o] = ph;
+    }
+  }
+  return 0;
+}
+
+/* Direct summation, the quantity the tree method approximates. */
+int orc_force_direct(int64_t n, const double* x, const double* y,
+                     const double* z, const double* m, double eps, double G,
+                     int64_t n_tgt, const int64_t* tgt, double* ax,
+                     double* ay, double* az, double* pot) {
+  if (n < 0 || n_tgt < 0 || !x || !y || !z || !m || !tgt || !ax || !ay ||
+      !az || !pot)
+    return -1;
+  const double eps2 = eps * eps;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+  for (int64_t s = 0; s < n_tgt; ++s) {
+    const int64_t i = tgt[s];
+    if (i < 0 || i >= n) {
+      bad = 1;
+      continue;
+    }
+    double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+      const double r2 = dx * dx + dy * dy + dz * dz + eps2;
+      const double rinv = 1.0 / sqrt(r2);
+      const double mr = G * m[j] * rinv;
+      const double mr3 = mr * rinv * rinv;
+      fx += mr3 * dx;
+      fy += mr3 * dy;
+      fz += mr3 * dz;
+      ph -= mr;
+    }
+    ax[s] = fx;
+    ay[s] = fy;
+    az[s] = fz;
+    pot[s] = ph;
+  }
+  return bad ? -1 : 0;
+}
+
+/* Kick-drift (section 4.3: after the force the orbits are integrated; the
+ * paper does not name the integrator -- KDK leapfrog is used, adjacent half
+ * kicks merged into one call). */
+int orc_kick_drift(int64_t n, double* x, double* y, double* z, double* vx,
+                   double* vy, double* vz, const double* ax,
+                   const double* ay, const double* az, double dt_kick,
+                   double dt_drift, double ext_mass, double G) {
+  if (n < 0 || !x || !y || !z || !vx || !vy || !vz || !ax || !ay || !az)
+    return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    double gx = ax[i], gy = ay[i], gz = az[i];
+    if (ext_mass != 0.0) {
+      const double r2 = x[i] * x[i] + y[i] * y[i] + z[i] * z[i];
+      const double r = sqrt(r2);
+      const double k = G * ext_mass / (r2 * r);
+      gx -= k * x[i];
+      gy -= k * y[i];
+      gz -= k * z[i];
+    }
+    vx[i] += gx * dt_kick;
+    vy[i] += gy * dt_kick;
+    vz[i] += gz * dt_kick;
+    x[i] += vx[i] * dt_drift;
+    y[i] += vy[i] * dt_drift;
+    z[i] += vz[i] * dt_drift;
+  }
+  return 0;
+}

@@ -1,0 +1,95 @@
+/*
+ * orc.h -- FP64 CPU oracle of the Barnes-Hut step with index interaction
+ * lists and list reuse (Iwasawa et al. 2019, "Accelerated FDPS").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The GPU product
+ * path never includes, links or calls anything declared here, and this code
+ * includes nothing from the GPU path.
+ *
+ * Conventions
+ *   - Particle positions/masses are FP64, G is an explicit argument.
+ *   - "input order" = the order of the arrays handed to orc_build.
+ *   - "sorted order" = Morton order produced by the stable key sort; list
+ *     ids for particles (EPJ) are sorted-order positions, list ids for
+ *     superparticles (SPJ) are cell ids (cells numbered in DFS pre-order).
+ *   - Every function returns 0 on success and a negative value on bad input
+ *     (NULL pointer, negative size, allocation failure).
+ */
+#ifndef ORC_H
+#define ORC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_tree orc_tree;
+
+/* Key helpers (section 4.3, local tree step 1). */
+int orc_root(int64_t n, const double* x, const double* y, const double* z,
+             double lo[3], int* k);
+int orc_keys(int64_t n, const double* x, const double* y, const double* z,
+             const double lo[3], int k, uint64_t* key);
+uint64_t orc_interleave(uint32_t qx, uint32_t qy, uint32_t qz);
+void orc_deinterleave(uint64_t key, int level, uint32_t q[3]);
+
+/* Tree: root cell, keys, sort, reorder, link, moments, groups
+ * (section 4.3 local tree steps 1-4 and the moment pass). */
+orc_tree* orc_build(int64_t n, const double* x, const double* y,
+                    const double* z, const double* m, int n_leaf, int n_grp);
+void orc_free(orc_tree* t);
+/* info[0]=n info[1]=n_cell info[2]=n_groups info[3]=k info[4]=n_leaf
+ * info[5]=n_grp; lo[3] = root corner. */
+int orc_info(const orc_tree* t, int64_t info[6], double lo[3]);
+int orc_get_keys(const orc_tree* t, uint64_t* key, uint32_t* perm);
+int orc_get_cells(const orc_tree* t, uint64_t* prefix, uint8_t* level,
+                  uint32_t* begin, uint32_t* count, uint32_t* parent,
+                  uint32_t* skip, uint8_t* leaf, double* ctr3);
+int orc_get_moments(const orc_tree* t, double* mass, double* com3,
+                    double* quad6);
+int orc_get_groups(const orc_tree* t, uint32_t* cell, uint32_t* begin,
+                   uint32_t* count, double* lo3, double* hi3, double* ctr3);
+
+/* Interaction lists (section 4.1 indirect addressing, section 4.3 list
+ * construction).  sel == NULL walks every group; otherwise only the n_sel
+ * listed groups, and the CSR is over that selection. */
+int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
+                   const int64_t* sel, int64_t sizes[3]);
+int orc_get_lists(const orc_tree* t, int64_t* epj_off, uint32_t* epj,
+                  int64_t* spj_off, uint32_t* spj);
+
+/* Reuse step (section 4.2): new positions/masses in INPUT order; the tree
+ * topology, cell geometry, groups and lists stay frozen, moments are
+ * recomputed over the frozen particle ranges. */
+int orc_refresh(orc_tree* t, const double* x, const double* y,
+                const double* z, const double* m);
+
+/* Forces from the saved lists of the selected groups (selection used by the
+ * last orc_make_lists).  order 1 = monopole SPJ, 2 = quadrupole SPJ.
+ * Outputs are written in INPUT order for members of the walked groups
+ * only; other entries are left untouched. */
+int orc_force_lists(const orc_tree* t, int order, double eps, double G,
+                    double* ax, double* ay, double* az, double* pot);
+
+/* Direct O(N^2) sum over all j != i for the n_tgt targets (input indices);
+ * outputs are indexed like tgt (length n_tgt). */
+int orc_force_direct(int64_t n, const double* x, const double* y,
+                     const double* z, const double* m, double eps, double G,
+                     int64_t n_tgt, const int64_t* tgt, double* ax,
+                     double* ay, double* az, double* pot);
+
+/* Kick-drift of the KDK leapfrog: v += a*dt_kick (plus the pull of a fixed
+ * point mass ext_mass at the origin), then x += v*dt_drift. */
+int orc_kick_drift(int64_t n, double* x, double* y, double* z, double* vx,
+                   double* vy, double* vz, const double* ax,
+                   const double* ay, const double* az, double dt_kick,
+                   double dt_drift, double ext_mass, double G);
+
+/* Threads the OpenMP runtime gives the per-group loops. */
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

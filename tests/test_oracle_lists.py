@@ -1,0 +1,159 @@
+"""Pins of the oracle's group walk and index interaction lists (sections 4.1
+and 4.3): coverage, the opening test seen from particle positions, a
+brute-force recursive walk on tiny inputs, theta -> 0, and the paper's
+list-length model (equation for <n_list> in section 6.2)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tree(orc, n, seed=1, n_leaf=8, n_grp=32, cube=False):
+    rng = np.random.default_rng(seed)
+    x, y, z = rng.standard_normal((3, n)) * (rng.uniform(0.2, 1, n) if cube
+                                             else 1.0)
+    m = rng.uniform(0.5, 1.5, n)
+    return orc.Tree(x, y, z, m, n_leaf=n_leaf, n_grp=n_grp), (x, y, z, m)
+
+
+def _children(c):
+    par = c["parent"].astype(np.int64)
+    kids = {}
+    for i in range(1, par.size):
+        kids.setdefault(int(par[i]), []).append(i)
+    return kids
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.7, 1.0])
+def test_coverage_exactly_once(orc, theta):
+    t, _ = _tree(orc, 4000, seed=2)
+    t.make_lists(theta)
+    eo, e, so, s = t.lists()
+    c = t.cells()
+    for g in range(t.n_groups):
+        hit = np.zeros(t.n, np.int64)
+        np.add.at(hit, e[eo[g]:eo[g + 1]], 1)
+        for cc in s[so[g]:so[g + 1]]:
+            b = int(c["begin"][cc])
+            hit[b:b + int(c["count"][cc])] += 1
+        assert np.all(hit == 1), g
+        # canonical order: ascending ids
+        assert np.all(np.diff(e[eo[g]:eo[g + 1]].astype(np.int64)) > 0)
+        assert np.all(np.diff(s[so[g]:so[g + 1]].astype(np.int64)) > 0)
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.8])
+def test_accepted_cells_far_from_every_member(orc, theta):
+    t, (x, y, z, m) = _tree(orc, 3000, seed=4)
+    t.make_lists(theta)
+    eo, e, so, s = t.lists()
+    c = t.cells()
+    g = t.groups()
+    key, perm = t.keys()
+    P = np.stack([x[perm], y[perm], z[perm]], 1)
+    kids = _children(c)
+    for gi in range(0, t.n_groups, 3):
+        b, n_i = int(g["begin"][gi]), int(g["count"][gi])
+        mem = P[b:b + n_i]
+        for cc in s[so[gi]:so[gi + 1]]:
+            side = 2.0 ** (t.k - int(c["level"][cc]))
+            d = np.sqrt(((mem - c["ctr"][cc]) ** 2).sum(1)).min()
+            assert d > side / theta * (1 - 1e-12)
+            # the cell does not hold the group
+            cb, cn = int(c["begin"][cc]), int(c["count"][cc])
+            assert not (cb <= b and cb + cn >= b + n_i)
+            # its parent was opened: either holds the group or is too close
+            p = int(c["parent"][cc])
+            pb, pn = int(c["begin"][p]), int(c["count"][p])
+            if not (pb <= b and pb + pn >= b + n_i):
+                pside = 2.0 ** (t.k - int(c["level"][p]))
+                dp = np.sqrt(((mem - c["ctr"][p]) ** 2).sum(1)).min()
+                # the box is at most as far as the nearest member
+                bx = np.maximum(0, np.maximum(g["lo"][gi] - c["ctr"][p],
+                                              c["ctr"][p] - g["hi"][gi]))
+                assert (bx ** 2).sum() <= (pside / theta) ** 2 or dp <= pside / theta
+
+
+def _brute_walk(t, c, g, gi, theta):
+    """Recursive walk over explicit children, emitting in visiting order."""
+    kids = _children(c)
+    gb, gn = int(g["begin"][gi]), int(g["count"][gi])
+    lo, hi = g["lo"][gi], g["hi"][gi]
+    epj, spj = [], []
+
+    def visit(cc):
+        cb, cn = int(c["begin"][cc]), int(c["count"][cc])
+        holds = cb <= gb and cb + cn >= gb + gn
+        if not holds:
+            side = 2.0 ** (t.k - int(c["level"][cc]))
+            d = np.maximum(0.0, np.maximum(lo - c["ctr"][cc], c["ctr"][cc] - hi))
+            if float((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) > (side / theta) ** 2:
+                spj.append(cc)
+                return
+        if c["leaf"][cc]:
+            epj.extend(range(cb, cb + cn))
+            return
+        for k in kids.get(cc, []):
+            visit(k)
+
+    visit(0)
+    return epj, spj
+
+
+@pytest.mark.parametrize("n", [2, 17, 64])
+@pytest.mark.parametrize("theta", [0.4, 0.9])
+def test_brute_force_recursive_walk(orc, n, theta):
+    t, _ = _tree(orc, n, seed=n, n_leaf=2, n_grp=4)
+    t.make_lists(theta)
+    eo, e, so, s = t.lists()
+    c, g = t.cells(), t.groups()
+    for gi in range(t.n_groups):
+        be, bs = _brute_walk(t, c, g, gi, theta)
+        assert e[eo[gi]:eo[gi + 1]].tolist() == be
+        assert s[so[gi]:so[gi + 1]].tolist() == bs
+
+
+def test_theta_zero_opens_everything(orc):
+    t, _ = _tree(orc, 700, seed=8)
+    t.make_lists(0.0)
+    eo, e, so, s = t.lists()
+    assert s.size == 0
+    for gi in range(t.n_groups):
+        np.testing.assert_array_equal(e[eo[gi]:eo[gi + 1]], np.arange(t.n))
+
+
+def test_selection_matches_full_walk(orc):
+    t, _ = _tree(orc, 2500, seed=12)
+    t.make_lists(0.5)
+    full = t.lists()
+    sel = np.array([0, 5, 7, t.n_groups - 1])
+    t.make_lists(0.5, sel)
+    eo, e, so, s = t.lists()
+    for k, gi in enumerate(sel):
+        np.testing.assert_array_equal(
+            e[eo[k]:eo[k + 1]], full[1][full[0][gi]:full[0][gi + 1]])
+        np.testing.assert_array_equal(
+            s[so[k]:so[k + 1]], full[3][full[2][gi]:full[2][gi + 1]])
+
+
+def test_mean_list_length_order_of_paper_model(orc):
+    """Order-of-magnitude pin only: the model was fitted for the paper's own
+    opening test; the exact lengths are not fixed by the paper."""
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as f:
+        pc = json.load(f)["n_list_model"]
+    import workloads
+    n = 1 << 15
+    d = workloads.uniform_sphere(n, 99)
+    t = orc.Tree(d["x"], d["y"], d["z"], d["m"], n_leaf=16, n_grp=64)
+    theta = 0.5
+    ng, ne, ns = t.make_lists(theta)
+    n_i = n / ng
+    model = (n_i + pc["c1"] * n_i ** (2 / 3) / theta
+             + pc["c2_over_pi"] * np.pi * n_i ** (1 / 3) / theta ** 2
+             + pc["c3_over_pi"] * np.pi / theta ** 3
+             * np.log2(theta / pc["c4"] * (n ** (1 / 3) - n_i ** (1 / 3))))
+    mean = (ne + ns) / ng
+    assert model / 3 < mean < model * 3, (mean, model)
