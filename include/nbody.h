@@ -1,0 +1,194 @@
+/*
+ * nbody.h -- C ABI of libnbody_hip.so, a GPU-resident (MI355X, gfx950)
+ * Barnes-Hut gravity step after "Accelerated FDPS" (Iwasawa et al. 2019):
+ * Morton keys, radix sort, octree, group-wise walk emitting 32-bit index
+ * interaction lists (section 4.1), one multiwalk force launch over all
+ * groups (section 3), and reuse of the lists over several steps (section
+ * 4.2), with a kick-drift leapfrog in FP64.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns an int status: NB_OK (0) or a negative nb_status.
+ *     On error nothing of the caller's memory has been written beyond what
+ *     the call documents, and nb_last_error() describes the failure.
+ *   - The library owns all device memory it allocates; the caller owns every
+ *     buffer it passes and keeps ownership (inputs are copied in, outputs are
+ *     copied out).  Host pointers are plain CPU memory; where a call takes
+ *     `on_device`, a non-zero value means the pointers are device pointers
+ *     on the context's GPU (for example torch.Tensor.data_ptr()).
+ *   - Particle arrays use the caller's ORIGINAL order unless a call says
+ *     INTERNAL order.  Internally the particles are kept in the Morton order
+ *     of the last tree build; list ids refer to that internal order.
+ *   - Work is enqueued on the context's HIP stream (the one given in
+ *     nb_config.stream, or a stream the library creates).  Calls that return
+ *     data to host memory synchronise that stream.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nb_ctx nb_ctx;
+
+typedef enum nb_status {
+  NB_OK = 0,
+  NB_ERR_INPUT = -1, /* bad argument: NULL, size, NaN/inf position, range */
+  NB_ERR_OOM = -2,   /* device or host allocation failed */
+  NB_ERR_LIST = -3,  /* a list id out of range or a list pool overflow */
+  NB_ERR_STATE = -4, /* call order violated (e.g. REUSE_LIST before any
+                        MAKE_LIST_FOR_REUSE, or no particles) */
+  NB_ERR_HIP = -5    /* a HIP runtime call failed */
+} nb_status;
+
+/* Reuse modes of the paper's top-level force call (section 5): make lists
+ * and discard them, make lists and keep them, or reuse the kept lists. */
+typedef enum nb_mode {
+  NB_MAKE_LIST = 0,
+  NB_MAKE_LIST_FOR_REUSE = 1,
+  NB_REUSE_LIST = 2
+} nb_mode;
+
+typedef struct nb_config {
+  double theta;    /* opening angle of the Barnes-Hut test (section 2); 0
+                      opens every cell.  Must be >= 0. */
+  double eps;      /* Plummer softening length, > 0 */
+  double G;        /* gravitational constant */
+  double ext_mass; /* fixed point mass at the origin added in kick-drift
+                      (0 = none); unsoftened */
+  int32_t n_leaf;  /* a cell holding more than n_leaf particles is split
+                      (section 6.1 uses 16); 1..64 */
+  int32_t n_grp;   /* largest particle group sharing one list (section 3,
+                      Barnes' vectorisation); 1..65536 */
+  int32_t order;   /* superparticle expansion: 1 monopole, 2 quadrupole */
+  int32_t flags;   /* bit 0: record per-phase GPU timers (HIP events) */
+  void* stream;    /* hipStream_t to launch on; NULL = the library's own */
+} nb_config;
+
+/* Phase ids of the per-phase timers (nb_get_timing). */
+enum {
+  NB_PH_ROOT = 0,  /* root cell: bounding cube                 */
+  NB_PH_KEYS,      /* Morton keys                               */
+  NB_PH_SORT,      /* radix sort of key-index pairs             */
+  NB_PH_REORDER,   /* reorder particles into Morton order       */
+  NB_PH_LINK,      /* octree cells, DFS order                   */
+  NB_PH_MOMENTS,   /* multipole moments                         */
+  NB_PH_GROUPS,    /* particle groups and their boxes           */
+  NB_PH_WALK,      /* tree walk -> index interaction lists      */
+  NB_PH_FORCE,     /* multiwalk force kernel                    */
+  NB_PH_KICK,      /* kick-drift                                */
+  NB_PH_COUNT
+};
+
+/* ---- lifetime --------------------------------------------------------- */
+
+/* Create a context on the current HIP device.  cfg is copied.
+ * Errors: NB_ERR_INPUT (cfg out of range), NB_ERR_HIP, NB_ERR_OOM. */
+int nb_create(const nb_config* cfg, nb_ctx** out);
+
+/* Destroy a context and free its device memory (NULL is a no-op). */
+void nb_destroy(nb_ctx* ctx);
+
+/* Replace the configuration (theta, eps, n_leaf, n_grp, order, ...).
+ * Invalidates the tree and the lists; particles are kept. */
+int nb_set_config(nb_ctx* ctx, const nb_config* cfg);
+
+/* Copy in n particles: positions, velocities and masses (FP64, original
+ * order, 7 arrays of n doubles).  1 <= n < 2^31.  Invalidates the tree and
+ * the lists.  Errors: NB_ERR_INPUT (NULL, n out of range), NB_ERR_OOM. */
+int nb_set_particles(nb_ctx* ctx, int64_t n, const double* x,
+                     const double* y, const double* z, const double* vx,
+                     const double* vy, const double* vz, const double* m,
+                     int on_device);
+
+/* ---- the step ----------------------------------------------------------
+ * Construction step (section 4.3): root cell, Morton keys, radix sort,
+ * reorder, link, moments, groups.  Particles move into Morton order.
+ * Errors: NB_ERR_STATE (no particles), NB_ERR_INPUT (a non-finite position),
+ * NB_ERR_OOM, NB_ERR_HIP. */
+int nb_build_tree(nb_ctx* ctx);
+
+/* Group-wise tree walk emitting index interaction lists (sections 4.1 and
+ * 4.3).  NB_MAKE_LIST keeps them for the current positions only,
+ * NB_MAKE_LIST_FOR_REUSE also keeps them for later NB_REUSE_LIST steps;
+ * NB_REUSE_LIST is accepted when reusable lists exist and does nothing.
+ * Requires a tree built on the current positions (NB_ERR_STATE). */
+int nb_make_lists(nb_ctx* ctx, nb_mode mode);
+
+/* The paper's top-level force call (section 5).  NB_MAKE_LIST and
+ * NB_MAKE_LIST_FOR_REUSE run nb_build_tree, nb_make_lists(mode) and the
+ * force kernel.  NB_REUSE_LIST (section 4.2) recomputes the moments of the
+ * frozen tree from the current positions and runs the force kernel on the
+ * kept lists; particles are not re-sorted.  Forces (acceleration including
+ * G, and potential excluding the self term) stay on the device until read.
+ * Errors: NB_ERR_STATE (REUSE_LIST without reusable lists or after
+ * nb_set_particles), plus those of the stages. */
+int nb_compute_forces(nb_ctx* ctx, nb_mode mode);
+
+/* Kick-drift of the KDK leapfrog in FP64: v += (a + a_ext) * dt_kick, then
+ * x += v * dt_drift, with a the last computed forces and a_ext the pull of
+ * cfg.ext_mass at the origin.  Requires computed forces (NB_ERR_STATE).
+ * Invalidates the tree for new lists; kept lists stay reusable. */
+int nb_kick_drift(nb_ctx* ctx, double dt_kick, double dt_drift);
+
+/* ---- readback (synchronises the stream) --------------------------------
+ * internal = 0: original order; 1: internal (Morton) order. */
+int nb_get_forces(nb_ctx* ctx, double* ax, double* ay, double* az,
+                  double* pot, int internal);
+int nb_get_state(nb_ctx* ctx, double* x, double* y, double* z, double* vx,
+                 double* vy, double* vz, int internal);
+
+/* info[0] n, [1] cells, [2] groups, [3] EPJ entries, [4] SPJ entries,
+ * [5] interactions of the current lists (sum over groups of
+ * n_i * (n_epj + n_spj)), [6] force evaluations so far, [7] total
+ * interactions evaluated so far, [8] root exponent k, [9] force work items.
+ * info must hold 10 values. */
+int nb_get_info(nb_ctx* ctx, int64_t* info);
+
+/* Root corner lo[3] and exponent k of the last tree (side 2^k). */
+int nb_get_root(nb_ctx* ctx, double* lo, int32_t* k);
+
+/* Sorted keys (n) and, for each sorted position, the ORIGINAL index of the
+ * particle there (n). */
+int nb_get_keys(nb_ctx* ctx, uint64_t* key, uint32_t* orig);
+
+/* Cell arrays in DFS pre-order, each of length info[1]; any may be NULL.
+ * parent of the root is 0xFFFFFFFF; skip = id after the subtree; ctr3 =
+ * geometric centres (3 per cell). */
+int nb_get_cells(nb_ctx* ctx, uint8_t* level, uint32_t* begin,
+                 uint32_t* count, uint32_t* parent, uint32_t* skip,
+                 uint8_t* leaf, double* ctr3);
+
+/* Moments per cell: mass, centre of mass (3), second moments about the
+ * centre of mass (6: xx yy zz xy xz yz).  Any may be NULL. */
+int nb_get_moments(nb_ctx* ctx, double* mass, double* com3, double* quad6);
+
+/* Groups (length info[2]): cell id, first particle, count, tight box
+ * lo3/hi3 and centre ctr3 (3 per group).  Any may be NULL. */
+int nb_get_groups(nb_ctx* ctx, uint32_t* cell, uint32_t* begin,
+                  uint32_t* count, double* lo3, double* hi3, double* ctr3);
+
+/* Lists in CSR form: epj_off/spj_off hold info[2]+1 offsets, epj/spj hold
+ * info[3]/info[4] ids (EPJ = internal particle positions, SPJ = cell ids),
+ * ascending within each group.  Any may be NULL. */
+int nb_get_lists(nb_ctx* ctx, int64_t* epj_off, uint32_t* epj,
+                 int64_t* spj_off, uint32_t* spj);
+
+/* Accumulated GPU milliseconds per phase (NB_PH_COUNT values) and the
+ * number of timed intervals per phase (may be NULL), since the last reset;
+ * needs cfg.flags bit 0.  reset != 0 clears the counters after reading. */
+int nb_get_timing(nb_ctx* ctx, double* ms, int64_t* calls, int reset);
+
+/* Description of the last error on this context ("" if none). */
+const char* nb_last_error(const nb_ctx* ctx);
+
+/* Library version string. */
+const char* nb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBODY_H */

@@ -1,0 +1,13 @@
+"""MI355X-native (gfx950, HIP) Barnes-Hut step with index interaction lists,
+one multiwalk force launch and list reuse, after "Accelerated FDPS"
+(Iwasawa et al. 2019).  The work happens in ``libnbody_hip.so``; this
+package only binds it (``nbody``) and builds it (``_build``)."""
+from .nbody import (Context, NbError, NB_MAKE_LIST, NB_MAKE_LIST_FOR_REUSE,
+                    NB_REUSE_LIST, NB_OK, NB_ERR_INPUT, NB_ERR_OOM,
+                    NB_ERR_LIST, NB_ERR_STATE, NB_ERR_HIP, PHASES, load,
+                    version, LIB_PATH)
+
+__all__ = ["Context", "NbError", "NB_MAKE_LIST", "NB_MAKE_LIST_FOR_REUSE",
+           "NB_REUSE_LIST", "NB_OK", "NB_ERR_INPUT", "NB_ERR_OOM",
+           "NB_ERR_LIST", "NB_ERR_STATE", "NB_ERR_HIP", "PHASES", "load",
+           "version", "LIB_PATH"]

@@ -1,0 +1,703 @@
+// nb_api.hip -- the C ABI of libnbody_hip.so: context, memory, the
+// construction / reuse state machine of the paper's reuse modes (section 4.2
+// and section 5), host synchronisation points and readback.
+//
+// A construction step synchronises with the host three times, to size
+// buffers: after the cell count, after the group count and level histogram,
+// and after the list lengths.  A reuse step does not synchronise.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "nb_internal.h"
+
+namespace nb {
+
+int set_err(nb_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+int hip_check(nb_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return NB_OK;
+  return set_err(c, NB_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static hipEvent_t take_event(nb_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+static void resolve_timers(nb_ctx* c) {
+  for (auto& t : c->timers) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.b) == hipSuccess &&
+        hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      c->ph_ms[t.phase] += ms;
+      c->ph_calls[t.phase] += 1;
+    } else {
+      (void)hipGetLastError();
+    }
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->timers.clear();
+}
+
+void timer_begin(nb_ctx* c, int phase, hipEvent_t* a) {
+  (void)phase;
+  *a = nullptr;
+  if (!(c->cfg.flags & 1)) return;
+  hipEvent_t e = take_event(c);
+  if (e && hipEventRecord(e, c->stream) == hipSuccess) {
+    *a = e;
+  } else if (e) {
+    (void)hipGetLastError();
+    c->ev_pool.push_back(e);
+  }
+}
+
+void timer_end(nb_ctx* c, int phase, hipEvent_t a) {
+  if (!a) return;
+  hipEvent_t b = take_event(c);
+  if (!b || hipEventRecord(b, c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    c->ev_pool.push_back(a);
+    if (b) c->ev_pool.push_back(b);
+    return;
+  }
+  c->timers.push_back(TimerRec{phase, a, b});
+  if (c->timers.size() > 4096) resolve_timers(c);
+}
+
+struct Timed {
+  nb_ctx* c;
+  int ph;
+  hipEvent_t a;
+  Timed(nb_ctx* c_, int ph_) : c(c_), ph(ph_) { timer_begin(c, ph, &a); }
+  ~Timed() { timer_end(c, ph, a); }
+};
+
+static int check_cfg(nb_ctx* c, const nb_config* cfg) {
+  if (!cfg) return set_err(c, NB_ERR_INPUT, "config is NULL");
+  if (!(cfg->theta >= 0.0) || !std::isfinite(cfg->theta))
+    return set_err(c, NB_ERR_INPUT, "theta must be finite and >= 0");
+  if (!(cfg->eps > 0.0) || !std::isfinite(cfg->eps))
+    return set_err(c, NB_ERR_INPUT, "eps must be finite and > 0");
+  if (!std::isfinite(cfg->G) || !std::isfinite(cfg->ext_mass))
+    return set_err(c, NB_ERR_INPUT, "G and ext_mass must be finite");
+  if (cfg->n_leaf < 1 || cfg->n_leaf > 64)
+    return set_err(c, NB_ERR_INPUT, "n_leaf must be in 1..64");
+  if (cfg->n_grp < 1 || cfg->n_grp > 65536)
+    return set_err(c, NB_ERR_INPUT, "n_grp must be in 1..65536");
+  if (cfg->order != 1 && cfg->order != 2)
+    return set_err(c, NB_ERR_INPUT, "order must be 1 or 2");
+  return NB_OK;
+}
+
+// Copy `bytes` from device to the pinned staging buffer at `off` (async).
+static int stage_d2h(nb_ctx* c, size_t off, const void* src, size_t bytes) {
+  return hip_check(c,
+                   hipMemcpyAsync(static_cast<char*>(c->h_small) + off, src,
+                                  bytes, hipMemcpyDeviceToHost, c->stream),
+                   "staging copy");
+}
+
+static int sync(nb_ctx* c) {
+  return hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
+}
+
+static int build_tree(nb_ctx* c) {
+  if (!c->have_particles)
+    return set_err(c, NB_ERR_STATE, "no particles set");
+  int rc;
+  c->tree_valid = c->positions_fresh = false;
+  c->lists_valid = c->lists_reusable = c->forces_valid = false;
+  {
+    Timed t(c, NB_PH_ROOT);
+    if ((rc = launch_root(c))) return rc;
+  }
+  {
+    Timed t(c, NB_PH_KEYS);
+    if ((rc = launch_keys(c))) return rc;
+  }
+  {
+    Timed t(c, NB_PH_SORT);
+    if ((rc = radix_sort(c, c->n))) return rc;
+  }
+  {
+    Timed t(c, NB_PH_REORDER);
+    if ((rc = launch_reorder(c))) return rc;
+  }
+  {
+    Timed t(c, NB_PH_LINK);
+    if ((rc = launch_link_count(c))) return rc;
+  }
+  // sync 1: number of cells, root exponent, finiteness of the input
+  if ((rc = stage_d2h(c, 0, c->cstart.p + c->n, sizeof(uint32_t)))) return rc;
+  if ((rc = stage_d2h(c, 8, &c->root.p->k, 2 * sizeof(int32_t)))) return rc;
+  if ((rc = sync(c))) return rc;
+  {
+    const uint32_t* h = static_cast<const uint32_t*>(c->h_small);
+    const int32_t* hk = reinterpret_cast<const int32_t*>(
+        static_cast<const char*>(c->h_small) + 8);
+    if (hk[1]) return set_err(c, NB_ERR_INPUT, "non-finite particle position");
+    c->k = hk[0];
+    c->n_cell = h[0];
+  }
+  if (c->n_cell < 1 || c->n_cell >= (int64_t)kNone)
+    return set_err(c, NB_ERR_HIP, "cell count out of range (%lld)",
+                   (long long)c->n_cell);
+  {
+    Timed t(c, NB_PH_LINK);
+    if ((rc = launch_link_fill(c))) return rc;
+  }
+  {
+    Timed t(c, NB_PH_GROUPS);
+    if ((rc = launch_group_flags(c))) return rc;
+  }
+  // sync 2: level histogram (leaves in the last bucket) and group count
+  if ((rc = stage_d2h(c, 0, c->lvl_cnt.p, (kLevels + 1) * sizeof(uint32_t))))
+    return rc;
+  if ((rc = stage_d2h(c, 256, c->gflag.p + c->n_cell, sizeof(uint32_t))))
+    return rc;
+  if ((rc = sync(c))) return rc;
+  {
+    const uint32_t* h = static_cast<const uint32_t*>(c->h_small);
+    c->n_leaves = h[kLevels];
+    int64_t off = c->n_leaves;
+    for (int l = kMaxLevel; l >= 0; --l) {
+      c->lvl_count[l] = h[l];
+      c->lvl_off[l] = off;
+      off += h[l];
+    }
+    c->lvl_off[kLevels] = off;
+    c->n_groups = h[64];
+    if (off != c->n_cell || c->n_groups < 1)
+      return set_err(c, NB_ERR_HIP, "inconsistent tree (%lld/%lld cells)",
+                     (long long)off, (long long)c->n_cell);
+  }
+  {
+    Timed t(c, NB_PH_GROUPS);
+    if ((rc = launch_level_lists(c))) return rc;
+  }
+  {
+    Timed t(c, NB_PH_MOMENTS);
+    if ((rc = launch_moments(c))) return rc;
+  }
+  {
+    Timed t(c, NB_PH_GROUPS);
+    if ((rc = launch_group_fill(c))) return rc;
+  }
+  c->tree_valid = c->positions_fresh = true;
+  return NB_OK;
+}
+
+static int make_lists(nb_ctx* c, nb_mode mode) {
+  if (mode == NB_REUSE_LIST)
+    return c->lists_reusable ? NB_OK
+                             : set_err(c, NB_ERR_STATE, "no reusable lists");
+  if (mode != NB_MAKE_LIST && mode != NB_MAKE_LIST_FOR_REUSE)
+    return set_err(c, NB_ERR_INPUT, "bad mode %d", (int)mode);
+  if (!c->tree_valid || !c->positions_fresh)
+    return set_err(c, NB_ERR_STATE, "lists need a tree of the current positions");
+  int rc;
+  c->lists_valid = c->lists_reusable = false;
+  {
+    Timed t(c, NB_PH_WALK);
+    if ((rc = launch_walk(c, false))) return rc;
+    if ((rc = launch_list_stats(c))) return rc;
+  }
+  // sync 3: list totals, interaction count, force work items
+  if ((rc = stage_d2h(c, 0, c->epj_off.p + c->n_groups, 8))) return rc;
+  if ((rc = stage_d2h(c, 8, c->spj_off.p + c->n_groups, 8))) return rc;
+  if ((rc = stage_d2h(c, 16, c->red.p, 8))) return rc;
+  if ((rc = stage_d2h(c, 24, c->g_chunks.p + c->n_groups, 4))) return rc;
+  if ((rc = sync(c))) return rc;
+  {
+    const uint64_t* h = static_cast<const uint64_t*>(c->h_small);
+    c->n_epj = (int64_t)h[0];
+    c->n_spj = (int64_t)h[1];
+    c->n_inter = (int64_t)h[2];
+    c->n_wi = static_cast<const uint32_t*>(c->h_small)[6];
+  }
+  if ((rc = reserve(c, c->epj, (size_t)c->n_epj + 1))) return rc;
+  if ((rc = reserve(c, c->spj, (size_t)c->n_spj + 1))) return rc;
+  {
+    Timed t(c, NB_PH_WALK);
+    if ((rc = launch_walk(c, true))) return rc;
+  }
+  c->lists_valid = true;
+  c->lists_reusable = mode == NB_MAKE_LIST_FOR_REUSE;
+  return NB_OK;
+}
+
+}  // namespace nb
+
+using namespace nb;
+
+extern "C" {
+
+const char* nb_version(void) { return "nbody_hip 0.1 (gfx950)"; }
+
+const char* nb_last_error(const nb_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : "no context";
+}
+
+int nb_create(const nb_config* cfg, nb_ctx** out) {
+  if (!out) return NB_ERR_INPUT;
+  *out = nullptr;
+  int rc = check_cfg(nullptr, cfg);
+  if (rc) return rc;
+  nb_ctx* c = new (std::nothrow) nb_ctx();
+  if (!c) return NB_ERR_OOM;
+  c->cfg = *cfg;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return NB_ERR_HIP;
+  }
+  if (cfg->stream) {
+    c->stream = static_cast<hipStream_t>(cfg->stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      delete c;
+      return NB_ERR_HIP;
+    }
+    c->own_stream = true;
+  }
+  if (hipHostMalloc(&c->h_small, 4096, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return NB_ERR_OOM;
+  }
+  *out = c;
+  return NB_OK;
+}
+
+void nb_destroy(nb_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& t : c->timers) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  release(c->pos); release(c->pos2);
+  release(c->vx); release(c->vy); release(c->vz);
+  release(c->vx2); release(c->vy2); release(c->vz2);
+  release(c->orig); release(c->orig2); release(c->acc);
+  release(c->key); release(c->key2); release(c->val); release(c->val2);
+  release(c->hist); release(c->dtot); release(c->root); release(c->bbox_part);
+  release(c->lam); release(c->lmin); release(c->cstart);
+  release(c->c_meta); release(c->c_parent); release(c->c_geo);
+  release(c->c_mom); release(c->c_quad); release(c->c_pm);
+  release(c->lvl_cells); release(c->lvl_cnt);
+  release(c->gflag); release(c->g_cell); release(c->g_begin);
+  release(c->g_count); release(c->g_lo); release(c->g_hi);
+  release(c->g_chunks); release(c->wi);
+  release(c->cnt_e); release(c->cnt_s); release(c->epj_off);
+  release(c->spj_off); release(c->epj); release(c->spj);
+  release(c->scan_tmp); release(c->red);
+  if (c->h_small) (void)hipHostFree(c->h_small);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+int nb_set_config(nb_ctx* c, const nb_config* cfg) {
+  if (!c) return NB_ERR_INPUT;
+  int rc = check_cfg(c, cfg);
+  if (rc) return rc;
+  void* keep_stream = c->cfg.stream;
+  c->cfg = *cfg;
+  c->cfg.stream = keep_stream;  // the stream is fixed at creation
+  c->tree_valid = c->positions_fresh = false;
+  c->lists_valid = c->lists_reusable = false;
+  return NB_OK;
+}
+
+int nb_set_particles(nb_ctx* c, int64_t n, const double* x, const double* y,
+                     const double* z, const double* vx, const double* vy,
+                     const double* vz, const double* m, int on_device) {
+  if (!c) return NB_ERR_INPUT;
+  if (n < 1 || n >= 0x7FFFFFFFLL)
+    return set_err(c, NB_ERR_INPUT, "n out of range (%lld)", (long long)n);
+  if (!x || !y || !z || !vx || !vy || !vz || !m)
+    return set_err(c, NB_ERR_INPUT, "NULL particle array");
+  c->have_particles = false;
+  c->tree_valid = c->positions_fresh = false;
+  c->lists_valid = c->lists_reusable = c->forces_valid = false;
+  const size_t un = (size_t)n;
+  int rc = reserve(c, c->pos, un);
+  if (!rc) rc = reserve(c, c->vx, un);
+  if (!rc) rc = reserve(c, c->vy, un);
+  if (!rc) rc = reserve(c, c->vz, un);
+  if (!rc) rc = reserve(c, c->orig, un);
+  if (!rc) rc = reserve(c, c->acc, un);
+  if (rc) return rc;
+  c->n = n;
+  const size_t bytes = un * sizeof(double);
+  if (on_device) {
+    rc = launch_pack(c, x, y, z, m);
+    if (rc) return rc;
+    rc = hip_check(c, hipMemcpyAsync(c->vx.p, vx, bytes,
+                                     hipMemcpyDeviceToDevice, c->stream),
+                   "vx copy");
+    if (!rc) rc = hip_check(c, hipMemcpyAsync(c->vy.p, vy, bytes,
+                                              hipMemcpyDeviceToDevice,
+                                              c->stream), "vy copy");
+    if (!rc) rc = hip_check(c, hipMemcpyAsync(c->vz.p, vz, bytes,
+                                              hipMemcpyDeviceToDevice,
+                                              c->stream), "vz copy");
+    if (!rc) rc = sync(c);
+    if (rc) return rc;
+  } else {
+    std::vector<double4> hp(un);
+    std::vector<uint32_t> ho(un);
+    for (size_t i = 0; i < un; ++i) {
+      hp[i] = make_double4(x[i], y[i], z[i], m[i]);
+      ho[i] = (uint32_t)i;
+    }
+    rc = sync(c);
+    if (!rc) rc = hip_check(c, hipMemcpy(c->pos.p, hp.data(), un * sizeof(double4),
+                                         hipMemcpyHostToDevice), "pos upload");
+    if (!rc) rc = hip_check(c, hipMemcpy(c->orig.p, ho.data(), un * 4,
+                                         hipMemcpyHostToDevice), "orig upload");
+    if (!rc) rc = hip_check(c, hipMemcpy(c->vx.p, vx, bytes,
+                                         hipMemcpyHostToDevice), "vx upload");
+    if (!rc) rc = hip_check(c, hipMemcpy(c->vy.p, vy, bytes,
+                                         hipMemcpyHostToDevice), "vy upload");
+    if (!rc) rc = hip_check(c, hipMemcpy(c->vz.p, vz, bytes,
+                                         hipMemcpyHostToDevice), "vz upload");
+    if (rc) return rc;
+  }
+  c->have_particles = true;
+  return NB_OK;
+}
+
+int nb_build_tree(nb_ctx* c) {
+  if (!c) return NB_ERR_INPUT;
+  return build_tree(c);
+}
+
+int nb_make_lists(nb_ctx* c, nb_mode mode) {
+  if (!c) return NB_ERR_INPUT;
+  return make_lists(c, mode);
+}
+
+int nb_compute_forces(nb_ctx* c, nb_mode mode) {
+  if (!c) return NB_ERR_INPUT;
+  int rc;
+  if (mode == NB_REUSE_LIST) {
+    if (!c->have_particles || !c->tree_valid || !c->lists_reusable)
+      return set_err(c, NB_ERR_STATE,
+                     "REUSE_LIST needs lists made with MAKE_LIST_FOR_REUSE");
+    Timed t(c, NB_PH_MOMENTS);
+    if ((rc = launch_moments(c))) return rc;
+  } else if (mode == NB_MAKE_LIST || mode == NB_MAKE_LIST_FOR_REUSE) {
+    if ((rc = build_tree(c))) return rc;
+    if ((rc = make_lists(c, mode))) return rc;
+  } else {
+    return set_err(c, NB_ERR_INPUT, "bad mode %d", (int)mode);
+  }
+  {
+    Timed t(c, NB_PH_FORCE);
+    if ((rc = launch_force(c))) return rc;
+  }
+  c->forces_valid = true;
+  c->force_evals += 1;
+  c->total_inter += c->n_inter;
+  return NB_OK;
+}
+
+int nb_kick_drift(nb_ctx* c, double dt_kick, double dt_drift) {
+  if (!c) return NB_ERR_INPUT;
+  if (!std::isfinite(dt_kick) || !std::isfinite(dt_drift))
+    return set_err(c, NB_ERR_INPUT, "non-finite time step");
+  if (!c->forces_valid)
+    return set_err(c, NB_ERR_STATE, "kick-drift needs computed forces");
+  int rc;
+  {
+    Timed t(c, NB_PH_KICK);
+    if ((rc = launch_kick_drift(c, dt_kick, dt_drift))) return rc;
+  }
+  if (dt_drift != 0.0) {
+    c->positions_fresh = false;
+    if (!c->lists_reusable) c->lists_valid = false;
+  }
+  return NB_OK;
+}
+
+int nb_get_forces(nb_ctx* c, double* ax, double* ay, double* az, double* pot,
+                  int internal) {
+  if (!c) return NB_ERR_INPUT;
+  if (!ax || !ay || !az || !pot)
+    return set_err(c, NB_ERR_INPUT, "NULL output array");
+  if (!c->forces_valid) return set_err(c, NB_ERR_STATE, "no forces computed");
+  const size_t n = (size_t)c->n;
+  std::vector<float4> a(n);
+  std::vector<uint32_t> o(n);
+  int rc = sync(c);
+  if (!rc) rc = hip_check(c, hipMemcpy(a.data(), c->acc.p, n * sizeof(float4),
+                                       hipMemcpyDeviceToHost), "acc readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(o.data(), c->orig.p, n * 4,
+                                       hipMemcpyDeviceToHost), "orig readback");
+  if (rc) return rc;
+  for (size_t i = 0; i < n; ++i) {
+    const size_t d = internal ? i : o[i];
+    ax[d] = a[i].x;
+    ay[d] = a[i].y;
+    az[d] = a[i].z;
+    pot[d] = a[i].w;
+  }
+  return NB_OK;
+}
+
+int nb_get_state(nb_ctx* c, double* x, double* y, double* z, double* vx,
+                 double* vy, double* vz, int internal) {
+  if (!c) return NB_ERR_INPUT;
+  if (!x || !y || !z || !vx || !vy || !vz)
+    return set_err(c, NB_ERR_INPUT, "NULL output array");
+  if (!c->have_particles) return set_err(c, NB_ERR_STATE, "no particles set");
+  const size_t n = (size_t)c->n;
+  std::vector<double4> p(n);
+  std::vector<double> v[3];
+  std::vector<uint32_t> o(n);
+  for (auto& a : v) a.resize(n);
+  int rc = sync(c);
+  if (!rc) rc = hip_check(c, hipMemcpy(p.data(), c->pos.p, n * sizeof(double4),
+                                       hipMemcpyDeviceToHost), "pos readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(v[0].data(), c->vx.p, n * 8,
+                                       hipMemcpyDeviceToHost), "vx readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(v[1].data(), c->vy.p, n * 8,
+                                       hipMemcpyDeviceToHost), "vy readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(v[2].data(), c->vz.p, n * 8,
+                                       hipMemcpyDeviceToHost), "vz readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(o.data(), c->orig.p, n * 4,
+                                       hipMemcpyDeviceToHost), "orig readback");
+  if (rc) return rc;
+  for (size_t i = 0; i < n; ++i) {
+    const size_t d = internal ? i : o[i];
+    x[d] = p[i].x;
+    y[d] = p[i].y;
+    z[d] = p[i].z;
+    vx[d] = v[0][i];
+    vy[d] = v[1][i];
+    vz[d] = v[2][i];
+  }
+  return NB_OK;
+}
+
+int nb_get_info(nb_ctx* c, int64_t* info) {
+  if (!c || !info) return NB_ERR_INPUT;
+  info[0] = c->n;
+  info[1] = c->tree_valid ? c->n_cell : 0;
+  info[2] = c->tree_valid ? c->n_groups : 0;
+  info[3] = c->lists_valid ? c->n_epj : 0;
+  info[4] = c->lists_valid ? c->n_spj : 0;
+  info[5] = c->lists_valid ? c->n_inter : 0;
+  info[6] = c->force_evals;
+  info[7] = c->total_inter;
+  info[8] = c->k;
+  info[9] = c->n_wi;
+  return NB_OK;
+}
+
+int nb_get_root(nb_ctx* c, double* lo, int32_t* k) {
+  if (!c || !lo || !k) return NB_ERR_INPUT;
+  if (!c->tree_valid) return set_err(c, NB_ERR_STATE, "no tree");
+  Root r;
+  int rc = sync(c);
+  if (!rc) rc = hip_check(c, hipMemcpy(&r, c->root.p, sizeof r,
+                                       hipMemcpyDeviceToHost), "root readback");
+  if (rc) return rc;
+  for (int a = 0; a < 3; ++a) lo[a] = r.lo[a];
+  *k = r.k;
+  return NB_OK;
+}
+
+int nb_get_keys(nb_ctx* c, uint64_t* key, uint32_t* orig) {
+  if (!c) return NB_ERR_INPUT;
+  if (!c->tree_valid) return set_err(c, NB_ERR_STATE, "no tree");
+  int rc = sync(c);
+  if (!rc && key)
+    rc = hip_check(c, hipMemcpy(key, c->key.p, (size_t)c->n * 8,
+                                hipMemcpyDeviceToHost), "key readback");
+  if (!rc && orig)
+    rc = hip_check(c, hipMemcpy(orig, c->orig.p, (size_t)c->n * 4,
+                                hipMemcpyDeviceToHost), "orig readback");
+  return rc;
+}
+
+int nb_get_cells(nb_ctx* c, uint8_t* level, uint32_t* begin, uint32_t* count,
+                 uint32_t* parent, uint32_t* skip, uint8_t* leaf,
+                 double* ctr3) {
+  if (!c) return NB_ERR_INPUT;
+  if (!c->tree_valid) return set_err(c, NB_ERR_STATE, "no tree");
+  const size_t nc = (size_t)c->n_cell;
+  std::vector<uint4> m(nc);
+  std::vector<uint32_t> p(nc);
+  std::vector<double4> g(nc);
+  int rc = sync(c);
+  if (!rc) rc = hip_check(c, hipMemcpy(m.data(), c->c_meta.p, nc * 16,
+                                       hipMemcpyDeviceToHost), "cell readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(p.data(), c->c_parent.p, nc * 4,
+                                       hipMemcpyDeviceToHost), "cell readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(g.data(), c->c_geo.p, nc * 32,
+                                       hipMemcpyDeviceToHost), "cell readback");
+  if (rc) return rc;
+  for (size_t i = 0; i < nc; ++i) {
+    if (level) level[i] = (uint8_t)(m[i].w & 255u);
+    if (begin) begin[i] = m[i].x;
+    if (count) count[i] = m[i].y - m[i].x;
+    if (parent) parent[i] = p[i];
+    if (skip) skip[i] = m[i].z;
+    if (leaf) leaf[i] = (uint8_t)((m[i].w >> 8) & 1u);
+    if (ctr3) {
+      ctr3[3 * i] = g[i].x;
+      ctr3[3 * i + 1] = g[i].y;
+      ctr3[3 * i + 2] = g[i].z;
+    }
+  }
+  return NB_OK;
+}
+
+int nb_get_moments(nb_ctx* c, double* mass, double* com3, double* quad6) {
+  if (!c) return NB_ERR_INPUT;
+  if (!c->tree_valid) return set_err(c, NB_ERR_STATE, "no tree");
+  const size_t nc = (size_t)c->n_cell;
+  std::vector<double4> pm(nc);
+  std::vector<float4> q(2 * nc);
+  int rc = sync(c);
+  if (!rc) rc = hip_check(c, hipMemcpy(pm.data(), c->c_pm.p, nc * 32,
+                                       hipMemcpyDeviceToHost), "moment readback");
+  if (!rc && quad6 && c->cfg.order == 2)
+    rc = hip_check(c, hipMemcpy(q.data(), c->c_quad.p, nc * 32,
+                                hipMemcpyDeviceToHost), "moment readback");
+  if (rc) return rc;
+  for (size_t i = 0; i < nc; ++i) {
+    if (mass) mass[i] = pm[i].w;
+    if (com3) {
+      com3[3 * i] = pm[i].x;
+      com3[3 * i + 1] = pm[i].y;
+      com3[3 * i + 2] = pm[i].z;
+    }
+    if (quad6) {
+      const bool qd = c->cfg.order == 2;
+      const float4 a = qd ? q[2 * i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 b = qd ? q[2 * i + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const double v[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
+      for (int k = 0; k < 6; ++k) quad6[6 * i + k] = v[k];
+    }
+  }
+  return NB_OK;
+}
+
+int nb_get_groups(nb_ctx* c, uint32_t* cell, uint32_t* begin, uint32_t* count,
+                  double* lo3, double* hi3, double* ctr3) {
+  if (!c) return NB_ERR_INPUT;
+  if (!c->tree_valid) return set_err(c, NB_ERR_STATE, "no tree");
+  const size_t ng = (size_t)c->n_groups;
+  std::vector<uint32_t> gc(ng), gb(ng), gn(ng);
+  std::vector<double4> lo(ng), hi(ng);
+  int rc = sync(c);
+  if (!rc) rc = hip_check(c, hipMemcpy(gc.data(), c->g_cell.p, ng * 4,
+                                       hipMemcpyDeviceToHost), "group readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(gb.data(), c->g_begin.p, ng * 4,
+                                       hipMemcpyDeviceToHost), "group readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(gn.data(), c->g_count.p, ng * 4,
+                                       hipMemcpyDeviceToHost), "group readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(lo.data(), c->g_lo.p, ng * 32,
+                                       hipMemcpyDeviceToHost), "group readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(hi.data(), c->g_hi.p, ng * 32,
+                                       hipMemcpyDeviceToHost), "group readback");
+  if (rc) return rc;
+  std::vector<double4> geo;
+  if (ctr3) {
+    geo.resize((size_t)c->n_cell);
+    rc = hip_check(c, hipMemcpy(geo.data(), c->c_geo.p, geo.size() * 32,
+                                hipMemcpyDeviceToHost), "group readback");
+    if (rc) return rc;
+  }
+  for (size_t g = 0; g < ng; ++g) {
+    if (cell) cell[g] = gc[g];
+    if (begin) begin[g] = gb[g];
+    if (count) count[g] = gn[g];
+    if (lo3) {
+      lo3[3 * g] = lo[g].x;
+      lo3[3 * g + 1] = lo[g].y;
+      lo3[3 * g + 2] = lo[g].z;
+    }
+    if (hi3) {
+      hi3[3 * g] = hi[g].x;
+      hi3[3 * g + 1] = hi[g].y;
+      hi3[3 * g + 2] = hi[g].z;
+    }
+    if (ctr3) {
+      ctr3[3 * g] = geo[gc[g]].x;
+      ctr3[3 * g + 1] = geo[gc[g]].y;
+      ctr3[3 * g + 2] = geo[gc[g]].z;
+    }
+  }
+  return NB_OK;
+}
+
+int nb_get_lists(nb_ctx* c, int64_t* epj_off, uint32_t* epj,
+                 int64_t* spj_off, uint32_t* spj) {
+  if (!c) return NB_ERR_INPUT;
+  if (!c->lists_valid) return set_err(c, NB_ERR_STATE, "no lists");
+  const size_t ng = (size_t)c->n_groups;
+  int rc = sync(c);
+  if (!rc && epj_off)
+    rc = hip_check(c, hipMemcpy(epj_off, c->epj_off.p, (ng + 1) * 8,
+                                hipMemcpyDeviceToHost), "list readback");
+  if (!rc && spj_off)
+    rc = hip_check(c, hipMemcpy(spj_off, c->spj_off.p, (ng + 1) * 8,
+                                hipMemcpyDeviceToHost), "list readback");
+  if (!rc && epj && c->n_epj)
+    rc = hip_check(c, hipMemcpy(epj, c->epj.p, (size_t)c->n_epj * 4,
+                                hipMemcpyDeviceToHost), "list readback");
+  if (!rc && spj && c->n_spj)
+    rc = hip_check(c, hipMemcpy(spj, c->spj.p, (size_t)c->n_spj * 4,
+                                hipMemcpyDeviceToHost), "list readback");
+  return rc;
+}
+
+int nb_get_timing(nb_ctx* c, double* ms, int64_t* calls, int reset) {
+  if (!c || !ms) return NB_ERR_INPUT;
+  resolve_timers(c);
+  for (int p = 0; p < NB_PH_COUNT; ++p) {
+    ms[p] = c->ph_ms[p];
+    if (calls) calls[p] = c->ph_calls[p];
+  }
+  if (reset) {
+    for (int p = 0; p < NB_PH_COUNT; ++p) {
+      c->ph_ms[p] = 0.0;
+      c->ph_calls[p] = 0;
+    }
+  }
+  return NB_OK;
+}
+
+}  // extern "C"

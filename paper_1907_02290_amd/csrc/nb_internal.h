@@ -1,0 +1,187 @@
+// nb_internal.h -- private declarations of libnbody_hip.so (gfx950).
+// Shared by the library's own translation units only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nbody.h"
+
+namespace nb {
+
+constexpr int kKeyBits = 21;   // bits per axis in a Morton key
+constexpr int kMaxLevel = 21;  // deepest tree level
+constexpr int kLevels = kMaxLevel + 1;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Root cell of the last construction step, resident on the device.
+struct Root {
+  double lo[3];
+  double rcrit2[kLevels];  // (side_l / theta)^2 per level
+  int32_t k;               // side of the root cube = 2^k
+  int32_t bad;             // non-zero: a non-finite coordinate was seen
+};
+
+// A device buffer that only grows.
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t cap = 0;
+};
+
+struct TimerRec {
+  int phase;
+  hipEvent_t a, b;
+};
+
+}  // namespace nb
+
+struct nb_ctx {
+  nb_config cfg;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  std::string err;
+
+  // sizes of the current particle set, tree and lists
+  int64_t n = 0, n_cell = 0, n_groups = 0, n_wi = 0, n_leaves = 0;
+  int64_t n_epj = 0, n_spj = 0, n_inter = 0;
+  int64_t force_evals = 0, total_inter = 0;
+  int32_t k = 0;
+  // internal cells per level (construction order: deepest level first)
+  int64_t lvl_count[nb::kLevels] = {0};
+  int64_t lvl_off[nb::kLevels + 1] = {0};
+
+  // state machine
+  bool have_particles = false;
+  bool tree_valid = false;       // cells/groups exist for the particle order
+  bool positions_fresh = false;  // positions unchanged since the tree build
+  bool lists_valid = false;      // lists match the tree
+  bool lists_reusable = false;   // built with NB_MAKE_LIST_FOR_REUSE
+  bool forces_valid = false;
+
+  // particles, internal order (double-buffered for the reorder)
+  nb::DBuf<double4> pos, pos2;  // x, y, z, m
+  nb::DBuf<double> vx, vy, vz, vx2, vy2, vz2;
+  nb::DBuf<uint32_t> orig, orig2;  // original index per internal slot
+  nb::DBuf<float4> acc;            // ax, ay, az, pot (G applied)
+
+  // keys and sort
+  nb::DBuf<uint64_t> key, key2;
+  nb::DBuf<uint32_t> val, val2;
+  nb::DBuf<uint32_t> hist;   // 256 x blocks
+  nb::DBuf<uint32_t> dtot;   // 256 digit totals
+  nb::DBuf<nb::Root> root;
+  nb::DBuf<double> bbox_part;
+
+  // link
+  nb::DBuf<uint8_t> lam, lmin;
+  nb::DBuf<uint32_t> cstart;  // cells starting at each particle -> scanned
+
+  // cells (DFS pre-order)
+  nb::DBuf<uint4> c_meta;    // begin, end, skip, level | leaf << 8
+  nb::DBuf<uint32_t> c_parent;
+  nb::DBuf<double4> c_geo;   // geometric centre xyz, rcrit2 of the level
+  nb::DBuf<float4> c_mom;    // COM offset from the centre (FP32), mass
+  nb::DBuf<float4> c_quad;   // 2 per cell: xx yy zz xy | xz yz 0 0
+  nb::DBuf<double4> c_pm;    // absolute COM (FP64) and mass: SPJ record
+  nb::DBuf<uint32_t> lvl_cells;  // leaves first, then internal by level
+  nb::DBuf<uint32_t> lvl_cnt;    // device histogram, kLevels + 1
+
+  // groups
+  nb::DBuf<uint32_t> gflag;  // n_cell + 1, scanned
+  nb::DBuf<uint32_t> g_cell, g_begin, g_count;
+  nb::DBuf<double4> g_lo, g_hi;  // tight box of the members (w unused)
+  nb::DBuf<uint32_t> g_chunks;  // n_groups + 1, scanned
+  nb::DBuf<uint4> wi;           // force work items: group, first, count
+
+  // lists
+  nb::DBuf<uint32_t> cnt_e, cnt_s;
+  nb::DBuf<uint64_t> epj_off, spj_off;
+  nb::DBuf<uint32_t> epj, spj;
+
+  // scan / reduction scratch
+  nb::DBuf<uint64_t> scan_tmp;
+  nb::DBuf<uint64_t> red;  // small reductions (interaction count, ...)
+  void* h_small = nullptr; // pinned host staging (4 KiB)
+
+  // timing
+  std::vector<nb::TimerRec> timers;
+  std::vector<hipEvent_t> ev_pool;
+  double ph_ms[NB_PH_COUNT] = {0};
+  int64_t ph_calls[NB_PH_COUNT] = {0};
+};
+
+namespace nb {
+
+// ---- error helpers (nb_api.hip) ----
+int set_err(nb_ctx* c, int code, const char* fmt, ...);
+int hip_check(nb_ctx* c, hipError_t e, const char* what);
+
+template <class T>
+int reserve(nb_ctx* c, DBuf<T>& b, size_t n) {
+  if (n <= b.cap) return NB_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    if (e != hipSuccess) return hip_check(c, e, "hipFree");
+  }
+  size_t want = n + n / 4 + 64;
+  void* p = nullptr;
+  if (hipMalloc(&p, want * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(c, NB_ERR_OOM, "device allocation of %zu bytes failed",
+                   want * sizeof(T));
+  }
+  b.p = static_cast<T*>(p);
+  b.cap = want;
+  return NB_OK;
+}
+
+template <class T>
+void release(DBuf<T>& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+// timers (nb_api.hip)
+void timer_begin(nb_ctx* c, int phase, hipEvent_t* a);
+void timer_end(nb_ctx* c, int phase, hipEvent_t a);
+
+// ---- stage launchers; all enqueue on c->stream and return a status ----
+// nb_scan.hip
+int scan_u32(nb_ctx* c, const uint32_t* in, uint32_t* out, int64_t n);
+int scan_u32_to_u64(nb_ctx* c, const uint32_t* in, uint64_t* out, int64_t n);
+int radix_sort(nb_ctx* c, int64_t n);  // key/val -> key/val (sorted)
+// nb_tree.hip
+int launch_root(nb_ctx* c);
+int launch_keys(nb_ctx* c);
+int launch_reorder(nb_ctx* c);
+int launch_link_count(nb_ctx* c);
+int launch_link_fill(nb_ctx* c);
+int launch_level_lists(nb_ctx* c);
+int launch_moments(nb_ctx* c);
+int launch_group_flags(nb_ctx* c);
+int launch_group_fill(nb_ctx* c);
+// nb_walk.hip
+int launch_walk(nb_ctx* c, bool fill);
+int launch_list_stats(nb_ctx* c);
+// nb_force.hip
+int launch_force(nb_ctx* c);
+// nb_step.hip
+int launch_kick_drift(nb_ctx* c, double dt_kick, double dt_drift);
+int launch_pack(nb_ctx* c, const double* x, const double* y, const double* z,
+                const double* m);
+int fill_u32(nb_ctx* c, uint32_t* p, int64_t n, uint32_t v);
+
+inline unsigned grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace nb

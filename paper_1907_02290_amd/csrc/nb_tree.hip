@@ -1,0 +1,682 @@
+// nb_tree.hip -- construction step of the local tree on the GPU
+// (section 4.3): root cell, Morton keys, reorder, link, moments, groups.
+//
+// Compiled with -ffp-contract=off: the root cube, the keys, the cell centres
+// and the group boxes must come out bit-identical to a plain FP64 reference.
+//
+// Link without a per-level loop.  With keys sorted, the level-l cell holding
+// particle i has more than n_leaf particles iff some window of n_leaf + 1
+// consecutive keys that covers i shares its first l digits.  So the leaf
+// level of i is lam(i) = min(21, 1 + max over windows covering i of the
+// digits shared by the window's end keys), and the cells that begin at i are
+// the levels lmin(i)..lam(i), where lmin(i) is one more than the digits i
+// shares with i-1.  An exclusive scan of lam - lmin + 1 numbers every cell in
+// DFS pre-order (sorted by begin, then level); the end of a cell is found by
+// a galloping search in the sorted keys (the paper's binary search), and the
+// first cell starting at or after that end is the cell after its subtree.
+#include "nb_internal.h"
+
+namespace nb {
+namespace {
+
+// --- Morton helpers: 21 bits per axis, x most significant in every digit ---
+__device__ inline uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;
+  x = (x | x << 32) & 0x1f00000000ffffull;
+  x = (x | x << 16) & 0x1f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ inline uint32_t compact3(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+  x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+  x = (x ^ (x >> 32)) & 0x1fffffull;
+  return (uint32_t)x;
+}
+
+// Number of leading 3-bit digits two 63-bit keys share (21 if equal).
+__device__ inline int shared_levels(uint64_t a, uint64_t b) {
+  const uint64_t d = a ^ b;
+  if (d == 0) return kMaxLevel;
+  return (__clzll((long long)d) - 1) / 3;
+}
+
+// ---------------------------------------------------------------------------
+// Root cell: per-axis min / max of the positions (exact), then the cube.
+constexpr int kBboxThreads = 256;
+constexpr int kBboxBlocks = 1024;
+
+__device__ inline double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ void __launch_bounds__(kBboxThreads)
+k_bbox_partial(const double4* __restrict__ pos, int64_t n,
+               double* __restrict__ part) {
+  __shared__ double s[kBboxThreads / 64][7];
+  double mn[3] = {INFINITY, INFINITY, INFINITY};
+  double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double bad = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double4 p = pos[i];
+    const double v[3] = {p.x, p.y, p.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (!isfinite(v[a])) bad = 1.0;
+      mn[a] = fmin(mn[a], v[a]);
+      mx[a] = fmax(mx[a], v[a]);
+    }
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double r[7];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r[a] = wave_min(mn[a]);
+    r[3 + a] = wave_max(mx[a]);
+  }
+  r[6] = wave_max(bad);
+  if (lane == 0)
+    for (int a = 0; a < 7; ++a) s[w][a] = r[a];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < kBboxThreads / 64; ++q) {
+      for (int a = 0; a < 3; ++a) {
+        s[0][a] = fmin(s[0][a], s[q][a]);
+        s[0][3 + a] = fmax(s[0][3 + a], s[q][3 + a]);
+      }
+      s[0][6] = fmax(s[0][6], s[q][6]);
+    }
+    for (int a = 0; a < 7; ++a) part[blockIdx.x * 8 + a] = s[0][a];
+  }
+}
+
+// rr = (1/theta)*(1/theta) from the host: (2^e/theta)^2 rounds to
+// 2^(2e) * rr exactly, so rcrit2[l] = ldexp(rr, 2(k - l)).
+__global__ void k_bbox_final(const double* __restrict__ part, int nb,
+                             double rr, Root* __restrict__ root) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double mn[3] = {INFINITY, INFINITY, INFINITY};
+  double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double bad = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    for (int a = 0; a < 3; ++a) {
+      mn[a] = fmin(mn[a], part[b * 8 + a]);
+      mx[a] = fmax(mx[a], part[b * 8 + 3 + a]);
+    }
+    bad = fmax(bad, part[b * 8 + 6]);
+  }
+  double ext = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    root->lo[a] = mn[a];
+    const double e = mx[a] - mn[a];
+    if (e > ext) ext = e;
+  }
+  int k = 0;
+  if (ext > 0.0 && isfinite(ext)) {
+    frexp(ext, &k);
+    while (ldexp(1.0, k) <= ext) k++;
+    while (ldexp(1.0, k - 1) > ext) k--;
+  }
+  root->k = k;
+  root->bad = (bad != 0.0 || !isfinite(ext)) ? 1 : 0;
+  for (int l = 0; l < kLevels; ++l) root->rcrit2[l] = ldexp(rr, 2 * (k - l));
+}
+
+// ---------------------------------------------------------------------------
+// Morton keys: q = floor((x - lo) * 2^(21 - k)), clamped to 21 bits.
+__global__ void __launch_bounds__(256)
+k_keys(const double4* __restrict__ pos, int64_t n,
+       const Root* __restrict__ root, uint64_t* __restrict__ key) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double scale = ldexp(1.0, kKeyBits - root->k);
+  const double qmax = (double)((1u << kKeyBits) - 1u);
+  const double4 p = pos[i];
+  const double v[3] = {p.x, p.y, p.z};
+  uint32_t q[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double d = __dsub_rn(v[a], root->lo[a]);
+    double f = floor(__dmul_rn(d, scale));
+    f = f < 0.0 ? 0.0 : (f > qmax ? qmax : f);
+    q[a] = (uint32_t)f;
+  }
+  key[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+}
+
+// Reorder: gather the particle state into Morton order (section 4.3, local
+// tree step 3).  val holds, per sorted slot, the slot it came from.
+__global__ void __launch_bounds__(256)
+k_gather(int64_t n, const uint32_t* __restrict__ val,
+         const double4* __restrict__ pos, const double* __restrict__ vx,
+         const double* __restrict__ vy, const double* __restrict__ vz,
+         const uint32_t* __restrict__ orig, double4* __restrict__ pos2,
+         double* __restrict__ vx2, double* __restrict__ vy2,
+         double* __restrict__ vz2, uint32_t* __restrict__ orig2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t s = val[i];
+  pos2[i] = pos[s];
+  vx2[i] = vx[s];
+  vy2[i] = vy[s];
+  vz2[i] = vz[s];
+  orig2[i] = orig[s];
+}
+
+// ---------------------------------------------------------------------------
+// Link, pass 1: leaf level lam(i), first level lmin(i) of a cell beginning
+// at i, and the number of cells beginning at i.
+__global__ void __launch_bounds__(256)
+k_link_count(const uint64_t* __restrict__ key, int64_t n, int n_leaf,
+             uint8_t* __restrict__ lam, uint8_t* __restrict__ lmin,
+             uint32_t* __restrict__ cstart) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int M = -1;
+  const int64_t s0 = i - n_leaf > 0 ? i - n_leaf : 0;
+  for (int64_t s = s0; s <= i; ++s) {
+    if (s + n_leaf < n) {
+      const int v = shared_levels(key[s], key[s + n_leaf]);
+      M = v > M ? v : M;
+    }
+  }
+  const int la = M < 0 ? 0 : (M + 1 < kMaxLevel ? M + 1 : kMaxLevel);
+  const int lm = i == 0 ? 0 : shared_levels(key[i - 1], key[i]) + 1;
+  lam[i] = (uint8_t)la;
+  lmin[i] = (uint8_t)lm;
+  cstart[i] = la >= lm ? (uint32_t)(la - lm + 1) : 0u;
+}
+
+// First index >= lo whose key differs from `pre` in its top digits
+// (keys[lo-1] shares them).
+__device__ inline int64_t gallop_end(const uint64_t* __restrict__ key,
+                                     int64_t n, int64_t lo, uint64_t pre,
+                                     int sh) {
+  int64_t a = lo, b = n, step = 1;
+  for (;;) {
+    const int64_t probe = a + step - 1;
+    if (probe >= n) {
+      b = n;
+      break;
+    }
+    if ((key[probe] >> sh) != pre) {
+      b = probe;
+      break;
+    }
+    a = probe + 1;
+    step <<= 1;
+  }
+  while (a < b) {
+    const int64_t mid = a + ((b - a) >> 1);
+    if ((key[mid] >> sh) == pre)
+      a = mid + 1;
+    else
+      b = mid;
+  }
+  return a;
+}
+
+// First index <= hi whose key shares `pre` (keys[hi] does).
+__device__ inline int64_t gallop_begin(const uint64_t* __restrict__ key,
+                                       int64_t hi, uint64_t pre, int sh) {
+  int64_t in = hi, out = -1, step = 1;
+  for (;;) {
+    const int64_t probe = in - step;
+    if (probe < 0) {
+      out = -1;
+      break;
+    }
+    if ((key[probe] >> sh) != pre) {
+      out = probe;
+      break;
+    }
+    in = probe;
+    step <<= 1;
+  }
+  while (in - out > 1) {
+    const int64_t mid = out + ((in - out) >> 1);
+    if ((key[mid] >> sh) == pre)
+      in = mid;
+    else
+      out = mid;
+  }
+  return in;
+}
+
+// Link, pass 2: write every cell (DFS pre-order id = S[i] + l - lmin(i)).
+__global__ void __launch_bounds__(256)
+k_link_fill(const uint64_t* __restrict__ key, int64_t n,
+            const uint8_t* __restrict__ lam, const uint8_t* __restrict__ lmin,
+            const uint32_t* __restrict__ S, const Root* __restrict__ root,
+            uint4* __restrict__ meta, uint32_t* __restrict__ parent,
+            double4* __restrict__ geo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int la = lam[i], lm = lmin[i];
+  if (la < lm) return;
+  const uint32_t base = S[i];
+  const uint64_t ki = key[i];
+  const int k = root->k;
+  int64_t end = i + 1;
+  for (int l = la; l >= lm; --l) {
+    const uint32_t id = base + (uint32_t)(l - lm);
+    const int sh = 3 * (kMaxLevel - l);
+    const uint64_t pre = ki >> sh;
+    end = gallop_end(key, n, end, pre, sh);
+    uint32_t par;
+    if (l > lm) {
+      par = id - 1;
+    } else if (l == 0) {
+      par = kNone;
+    } else {
+      const int psh = 3 * (kMaxLevel - (l - 1));
+      const int64_t b = gallop_begin(key, i, ki >> psh, psh);
+      par = S[b] + (uint32_t)((l - 1) - (int)lmin[b]);
+    }
+    const uint32_t skip = S[end];
+    meta[id] = make_uint4((uint32_t)i, (uint32_t)end, skip,
+                          (uint32_t)l | (l == la ? 256u : 0u));
+    parent[id] = par;
+    // geometric centre: lo + (2q + 1) * 2^(k - l - 1)
+    const double half = ldexp(1.0, k - l - 1);
+    const uint32_t qx = compact3(pre >> 2), qy = compact3(pre >> 1),
+                   qz = compact3(pre);
+    double4 gc;
+    gc.x = __dadd_rn(root->lo[0], __dmul_rn(2.0 * (double)qx + 1.0, half));
+    gc.y = __dadd_rn(root->lo[1], __dmul_rn(2.0 * (double)qy + 1.0, half));
+    gc.z = __dadd_rn(root->lo[2], __dmul_rn(2.0 * (double)qz + 1.0, half));
+    gc.w = root->rcrit2[l];
+    geo[id] = gc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Groups (Barnes' vectorisation): a cell holding at most n_grp particles (or
+// a leaf) whose parent holds more than n_grp.  Also the level histogram of
+// internal cells (bucket kLevels holds the leaves).
+__global__ void __launch_bounds__(256)
+k_group_flags(int64_t n_cell, const uint4* __restrict__ meta,
+              const uint32_t* __restrict__ parent, int n_grp,
+              uint32_t* __restrict__ gflag, uint32_t* __restrict__ lvl_cnt) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cell) return;
+  const uint4 m = meta[c];
+  const uint32_t cnt = m.y - m.x;
+  const bool leaf = (m.w >> 8) & 1u;
+  bool top = true;
+  if (c != 0) {
+    const uint4 pm = meta[parent[c]];
+    top = (pm.y - pm.x) > (uint32_t)n_grp;
+  }
+  gflag[c] = ((cnt <= (uint32_t)n_grp || leaf) && top) ? 1u : 0u;
+  atomicAdd(&lvl_cnt[leaf ? kLevels : (m.w & 255u)], 1u);
+}
+
+__global__ void __launch_bounds__(256)
+k_level_scatter(int64_t n_cell, const uint4* __restrict__ meta,
+                uint32_t* __restrict__ cursor, uint32_t* __restrict__ out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cell) return;
+  const uint32_t w = meta[c].w;
+  const uint32_t b = ((w >> 8) & 1u) ? (uint32_t)kLevels : (w & 255u);
+  out[atomicAdd(&cursor[b], 1u)] = (uint32_t)c;
+}
+
+__global__ void __launch_bounds__(256)
+k_group_fill(int64_t n_cell, const uint32_t* __restrict__ gscan,
+             const uint4* __restrict__ meta, uint32_t* __restrict__ g_cell,
+             uint32_t* __restrict__ g_begin, uint32_t* __restrict__ g_count,
+             uint32_t* __restrict__ chunks) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cell) return;
+  const uint32_t g = gscan[c];
+  if (gscan[c + 1] == g) return;
+  const uint4 m = meta[c];
+  g_cell[g] = (uint32_t)c;
+  g_begin[g] = m.x;
+  g_count[g] = m.y - m.x;
+  chunks[g] = (m.y - m.x + 63u) / 64u;
+}
+
+// One wave per group: exact FP64 min / max of the member positions.
+__global__ void __launch_bounds__(256)
+k_group_box(int64_t n_groups, const uint32_t* __restrict__ g_begin,
+            const uint32_t* __restrict__ g_count,
+            const double4* __restrict__ pos, double4* __restrict__ g_lo,
+            double4* __restrict__ g_hi) {
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= n_groups) return;
+  const uint32_t b = g_begin[g], cnt = g_count[g];
+  double mn[3] = {INFINITY, INFINITY, INFINITY};
+  double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (uint32_t j = lane; j < cnt; j += 64) {
+    const double4 p = pos[b + j];
+    mn[0] = fmin(mn[0], p.x);
+    mn[1] = fmin(mn[1], p.y);
+    mn[2] = fmin(mn[2], p.z);
+    mx[0] = fmax(mx[0], p.x);
+    mx[1] = fmax(mx[1], p.y);
+    mx[2] = fmax(mx[2], p.z);
+  }
+  for (int a = 0; a < 3; ++a) {
+    mn[a] = wave_min(mn[a]);
+    mx[a] = wave_max(mx[a]);
+  }
+  if (lane == 0) {
+    g_lo[g] = make_double4(mn[0], mn[1], mn[2], 0.0);
+    g_hi[g] = make_double4(mx[0], mx[1], mx[2], 0.0);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_make_wi(int64_t n_groups, const uint32_t* __restrict__ g_begin,
+          const uint32_t* __restrict__ g_count,
+          const uint32_t* __restrict__ choff, uint4* __restrict__ wi) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_groups) return;
+  const uint32_t b = g_begin[g], cnt = g_count[g];
+  uint32_t o = choff[g];
+  for (uint32_t s = 0; s < cnt; s += 64, ++o) {
+    const uint32_t len = cnt - s < 64u ? cnt - s : 64u;
+    wi[o] = make_uint4((uint32_t)g, b + s, len, 0u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Moments (section 4.3: recomputed at every step, reuse steps included).
+// Offsets from the cell's geometric centre are formed in FP64 and kept in
+// FP32; parents combine their children with the parallel-axis rule in FP32
+// (the child-to-parent centre shift is an exact power of two).
+template <bool QUAD>
+__global__ void __launch_bounds__(256)
+k_mom_leaf(int64_t cnt, const uint32_t* __restrict__ list,
+           const uint4* __restrict__ meta, const double4* __restrict__ geo,
+           const double4* __restrict__ pos, float4* __restrict__ mom,
+           float4* __restrict__ quad, double4* __restrict__ pm) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  const uint32_t c = list[t];
+  const uint4 m = meta[c];
+  const double4 g = geo[c];
+  float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+  for (uint32_t p = m.x; p < m.y; ++p) {
+    const double4 P = pos[p];
+    const float w = (float)P.w;
+    const float dx = (float)(P.x - g.x), dy = (float)(P.y - g.y),
+                dz = (float)(P.z - g.z);
+    M += w;
+    sx = fmaf(w, dx, sx);
+    sy = fmaf(w, dy, sy);
+    sz = fmaf(w, dz, sz);
+  }
+  const float inv = M > 0.f ? 1.0f / M : 0.f;
+  const float ox = sx * inv, oy = sy * inv, oz = sz * inv;
+  mom[c] = make_float4(ox, oy, oz, M);
+  pm[c] = make_double4(g.x + (double)ox, g.y + (double)oy, g.z + (double)oz,
+                       (double)M);
+  if (QUAD) {
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
+    for (uint32_t p = m.x; p < m.y; ++p) {
+      const double4 P = pos[p];
+      const float w = (float)P.w;
+      const float dx = (float)(P.x - g.x) - ox, dy = (float)(P.y - g.y) - oy,
+                  dz = (float)(P.z - g.z) - oz;
+      s0 = fmaf(w * dx, dx, s0);
+      s1 = fmaf(w * dy, dy, s1);
+      s2 = fmaf(w * dz, dz, s2);
+      s3 = fmaf(w * dx, dy, s3);
+      s4 = fmaf(w * dx, dz, s4);
+      s5 = fmaf(w * dy, dz, s5);
+    }
+    quad[2 * (int64_t)c] = make_float4(s0, s1, s2, s3);
+    quad[2 * (int64_t)c + 1] = make_float4(s4, s5, 0.f, 0.f);
+  }
+}
+
+// Next sibling; a skip id that does not advance ends the loop.
+__device__ inline uint32_t next_child(const uint4* __restrict__ meta,
+                                      uint32_t k, uint32_t stop) {
+  const uint32_t s = meta[k].z;
+  return s > k ? s : stop;
+}
+
+template <bool QUAD>
+__global__ void __launch_bounds__(256)
+k_mom_internal(int64_t cnt, const uint32_t* __restrict__ list,
+               const uint4* __restrict__ meta,
+               const double4* __restrict__ geo, float4* __restrict__ mom,
+               float4* __restrict__ quad, double4* __restrict__ pm) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  const uint32_t c = list[t];
+  const uint32_t stop = meta[c].z;
+  const double4 g = geo[c];
+  float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+  for (uint32_t k = c + 1; k < stop; k = next_child(meta, k, stop)) {
+    const float4 mk = mom[k];
+    const double4 gk = geo[k];
+    const float dx = (float)(gk.x - g.x) + mk.x;
+    const float dy = (float)(gk.y - g.y) + mk.y;
+    const float dz = (float)(gk.z - g.z) + mk.z;
+    M += mk.w;
+    sx = fmaf(mk.w, dx, sx);
+    sy = fmaf(mk.w, dy, sy);
+    sz = fmaf(mk.w, dz, sz);
+  }
+  const float inv = M > 0.f ? 1.0f / M : 0.f;
+  const float ox = sx * inv, oy = sy * inv, oz = sz * inv;
+  mom[c] = make_float4(ox, oy, oz, M);
+  pm[c] = make_double4(g.x + (double)ox, g.y + (double)oy, g.z + (double)oz,
+                       (double)M);
+  if (QUAD) {
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
+    for (uint32_t k = c + 1; k < stop; k = next_child(meta, k, stop)) {
+      const float4 mk = mom[k];
+      const double4 gk = geo[k];
+      const float4 qa = quad[2 * (int64_t)k];
+      const float4 qb = quad[2 * (int64_t)k + 1];
+      const float dx = (float)(gk.x - g.x) + mk.x - ox;
+      const float dy = (float)(gk.y - g.y) + mk.y - oy;
+      const float dz = (float)(gk.z - g.z) + mk.z - oz;
+      const float w = mk.w;
+      s0 += qa.x + w * dx * dx;
+      s1 += qa.y + w * dy * dy;
+      s2 += qa.z + w * dz * dz;
+      s3 += qa.w + w * dx * dy;
+      s4 += qb.x + w * dx * dz;
+      s5 += qb.y + w * dy * dz;
+    }
+    quad[2 * (int64_t)c] = make_float4(s0, s1, s2, s3);
+    quad[2 * (int64_t)c + 1] = make_float4(s4, s5, 0.f, 0.f);
+  }
+}
+
+}  // namespace
+
+int launch_root(nb_ctx* c) {
+  int rc = reserve(c, c->bbox_part, (size_t)kBboxBlocks * 8);
+  if (!rc) rc = reserve(c, c->root, 1);
+  if (rc) return rc;
+  int nb = (int)grid_for(c->n, kBboxThreads);
+  if (nb > kBboxBlocks) nb = kBboxBlocks;
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kBboxThreads), 0,
+                     c->stream, (const double4*)c->pos.p, c->n,
+                     c->bbox_part.p);
+  const double r1 = 1.0 / c->cfg.theta;
+  const double rr = r1 * r1;
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, c->stream,
+                     (const double*)c->bbox_part.p, nb, rr, c->root.p);
+  return hip_check(c, hipGetLastError(), "root launch");
+}
+
+int launch_keys(nb_ctx* c) {
+  int rc = reserve(c, c->key, (size_t)c->n);
+  if (!rc) rc = reserve(c, c->val, (size_t)c->n);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_keys, dim3(grid_for(c->n, 256)), dim3(256), 0,
+                     c->stream, (const double4*)c->pos.p, c->n,
+                     (const Root*)c->root.p, c->key.p);
+  return hip_check(c, hipGetLastError(), "keys launch");
+}
+
+int launch_reorder(nb_ctx* c) {
+  const size_t n = (size_t)c->n;
+  int rc = reserve(c, c->pos2, n);
+  if (!rc) rc = reserve(c, c->vx2, n);
+  if (!rc) rc = reserve(c, c->vy2, n);
+  if (!rc) rc = reserve(c, c->vz2, n);
+  if (!rc) rc = reserve(c, c->orig2, n);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(c->n, 256)), dim3(256), 0,
+                     c->stream, c->n, (const uint32_t*)c->val.p,
+                     (const double4*)c->pos.p, (const double*)c->vx.p,
+                     (const double*)c->vy.p, (const double*)c->vz.p,
+                     (const uint32_t*)c->orig.p, c->pos2.p, c->vx2.p,
+                     c->vy2.p, c->vz2.p, c->orig2.p);
+  std::swap(c->pos, c->pos2);
+  std::swap(c->vx, c->vx2);
+  std::swap(c->vy, c->vy2);
+  std::swap(c->vz, c->vz2);
+  std::swap(c->orig, c->orig2);
+  return hip_check(c, hipGetLastError(), "reorder launch");
+}
+
+int launch_link_count(nb_ctx* c) {
+  const size_t n = (size_t)c->n;
+  int rc = reserve(c, c->lam, n);
+  if (!rc) rc = reserve(c, c->lmin, n);
+  if (!rc) rc = reserve(c, c->cstart, n + 1);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_link_count, dim3(grid_for(c->n, 256)), dim3(256), 0,
+                     c->stream, (const uint64_t*)c->key.p, c->n,
+                     (int)c->cfg.n_leaf, c->lam.p, c->lmin.p, c->cstart.p);
+  rc = hip_check(c, hipGetLastError(), "link count launch");
+  if (rc) return rc;
+  return scan_u32(c, c->cstart.p, c->cstart.p, c->n);
+}
+
+int launch_link_fill(nb_ctx* c) {
+  const size_t nc = (size_t)c->n_cell;
+  int rc = reserve(c, c->c_meta, nc);
+  if (!rc) rc = reserve(c, c->c_parent, nc);
+  if (!rc) rc = reserve(c, c->c_geo, nc);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_link_fill, dim3(grid_for(c->n, 256)), dim3(256), 0,
+                     c->stream, (const uint64_t*)c->key.p, c->n,
+                     (const uint8_t*)c->lam.p, (const uint8_t*)c->lmin.p,
+                     (const uint32_t*)c->cstart.p, (const Root*)c->root.p,
+                     c->c_meta.p, c->c_parent.p, c->c_geo.p);
+  return hip_check(c, hipGetLastError(), "link fill launch");
+}
+
+// Group flags + level histogram, then the scan of the flags.  The host reads
+// the histogram and the group count afterwards.
+int launch_group_flags(nb_ctx* c) {
+  const size_t nc = (size_t)c->n_cell;
+  int rc = reserve(c, c->gflag, nc + 1);
+  if (!rc) rc = reserve(c, c->lvl_cnt, kLevels + 1);
+  if (rc) return rc;
+  rc = fill_u32(c, c->lvl_cnt.p, kLevels + 1, 0u);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_group_flags, dim3(grid_for(c->n_cell, 256)), dim3(256),
+                     0, c->stream, c->n_cell, (const uint4*)c->c_meta.p,
+                     (const uint32_t*)c->c_parent.p, (int)c->cfg.n_grp,
+                     c->gflag.p, c->lvl_cnt.p);
+  rc = hip_check(c, hipGetLastError(), "group flags launch");
+  if (rc) return rc;
+  return scan_u32(c, c->gflag.p, c->gflag.p, c->n_cell);
+}
+
+// Needs c->lvl_off filled by the host (leaves first, then levels 20..0).
+int launch_level_lists(nb_ctx* c) {
+  int rc = reserve(c, c->lvl_cells, (size_t)c->n_cell);
+  if (rc) return rc;
+  uint32_t* h = static_cast<uint32_t*>(c->h_small);
+  for (int l = 0; l < kLevels; ++l) h[l] = (uint32_t)c->lvl_off[l];
+  h[kLevels] = 0;  // leaves start the list
+  rc = hip_check(c, hipMemcpyAsync(c->lvl_cnt.p, h,
+                                   (kLevels + 1) * sizeof(uint32_t),
+                                   hipMemcpyHostToDevice, c->stream),
+                 "level cursor upload");
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(c->n_cell, 256)),
+                     dim3(256), 0, c->stream, c->n_cell,
+                     (const uint4*)c->c_meta.p, c->lvl_cnt.p, c->lvl_cells.p);
+  // the staging buffer is reused by later calls: wait for the copy
+  rc = hip_check(c, hipStreamSynchronize(c->stream), "level cursor sync");
+  if (rc) return rc;
+  return hip_check(c, hipGetLastError(), "level scatter launch");
+}
+
+int launch_moments(nb_ctx* c) {
+  const size_t nc = (size_t)c->n_cell;
+  int rc = reserve(c, c->c_mom, nc);
+  if (!rc) rc = reserve(c, c->c_pm, nc);
+  if (!rc) rc = reserve(c, c->c_quad, 2 * nc);
+  if (rc) return rc;
+  const bool quad = c->cfg.order == 2;
+  auto leaf = quad ? k_mom_leaf<true> : k_mom_leaf<false>;
+  auto inner = quad ? k_mom_internal<true> : k_mom_internal<false>;
+  if (c->n_leaves > 0)
+    hipLaunchKernelGGL(leaf, dim3(grid_for(c->n_leaves, 256)), dim3(256), 0,
+                       c->stream, c->n_leaves, (const uint32_t*)c->lvl_cells.p,
+                       (const uint4*)c->c_meta.p, (const double4*)c->c_geo.p,
+                       (const double4*)c->pos.p, c->c_mom.p, c->c_quad.p,
+                       c->c_pm.p);
+  for (int l = kMaxLevel - 1; l >= 0; --l) {
+    const int64_t cnt = c->lvl_count[l];
+    if (cnt == 0) continue;
+    hipLaunchKernelGGL(inner, dim3(grid_for(cnt, 256)), dim3(256), 0,
+                       c->stream, cnt,
+                       (const uint32_t*)c->lvl_cells.p + c->lvl_off[l],
+                       (const uint4*)c->c_meta.p, (const double4*)c->c_geo.p,
+                       c->c_mom.p, c->c_quad.p, c->c_pm.p);
+  }
+  return hip_check(c, hipGetLastError(), "moments launch");
+}
+
+int launch_group_fill(nb_ctx* c) {
+  const size_t ng = (size_t)c->n_groups;
+  int rc = reserve(c, c->g_cell, ng);
+  if (!rc) rc = reserve(c, c->g_begin, ng);
+  if (!rc) rc = reserve(c, c->g_count, ng);
+  if (!rc) rc = reserve(c, c->g_lo, ng);
+  if (!rc) rc = reserve(c, c->g_hi, ng);
+  if (!rc) rc = reserve(c, c->g_chunks, ng + 1);
+  if (!rc) rc = reserve(c, c->wi, ng + (size_t)c->n / 64 + 1);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_group_fill, dim3(grid_for(c->n_cell, 256)), dim3(256),
+                     0, c->stream, c->n_cell, (const uint32_t*)c->gflag.p,
+                     (const uint4*)c->c_meta.p, c->g_cell.p, c->g_begin.p,
+                     c->g_count.p, c->g_chunks.p);
+  hipLaunchKernelGGL(k_group_box, dim3(grid_for(c->n_groups, 4)), dim3(256),
+                     0, c->stream, c->n_groups, (const uint32_t*)c->g_begin.p,
+                     (const uint32_t*)c->g_count.p, (const double4*)c->pos.p,
+                     c->g_lo.p, c->g_hi.p);
+  rc = hip_check(c, hipGetLastError(), "group fill launch");
+  if (rc) return rc;
+  rc = scan_u32(c, c->g_chunks.p, c->g_chunks.p, c->n_groups);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_make_wi, dim3(grid_for(c->n_groups, 256)), dim3(256),
+                     0, c->stream, c->n_groups, (const uint32_t*)c->g_begin.p,
+                     (const uint32_t*)c->g_count.p,
+                     (const uint32_t*)c->g_chunks.p, c->wi.p);
+  return hip_check(c, hipGetLastError(), "work item launch");
+}
+
+}  // namespace nb

@@ -1,0 +1,267 @@
+"""ctypes binding of ``libnbody_hip.so`` (declared in ``include/nbody.h``).
+
+Argument marshalling only: every stage of the step runs in the library's
+HIP kernels.  There is no CPU fallback -- if the library is missing the
+import of a context raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnbody_hip.so")
+
+NB_OK = 0
+NB_ERR_INPUT = -1
+NB_ERR_OOM = -2
+NB_ERR_LIST = -3
+NB_ERR_STATE = -4
+NB_ERR_HIP = -5
+
+NB_MAKE_LIST = 0
+NB_MAKE_LIST_FOR_REUSE = 1
+NB_REUSE_LIST = 2
+
+PHASES = ("root", "keys", "sort", "reorder", "link", "moments", "groups",
+          "walk", "force", "kick")
+
+STATUS = {NB_OK: "NB_OK", NB_ERR_INPUT: "NB_ERR_INPUT",
+          NB_ERR_OOM: "NB_ERR_OOM", NB_ERR_LIST: "NB_ERR_LIST",
+          NB_ERR_STATE: "NB_ERR_STATE", NB_ERR_HIP: "NB_ERR_HIP"}
+
+
+class NbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class nb_config(C.Structure):
+    _fields_ = [("theta", C.c_double), ("eps", C.c_double), ("G", C.c_double),
+                ("ext_mass", C.c_double), ("n_leaf", C.c_int32),
+                ("n_grp", C.c_int32), ("order", C.c_int32),
+                ("flags", C.c_int32), ("stream", C.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load the library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            "libnbody_hip.so is not built (%s); run __graft_entry__.build()"
+            % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    p, i64, i32, d = C.c_void_p, C.c_int64, C.c_int, C.c_double
+    sig = {
+        "nb_create": ([p, p], i32),
+        "nb_destroy": ([p], None),
+        "nb_set_config": ([p, p], i32),
+        "nb_set_particles": ([p, i64] + [p] * 7 + [i32], i32),
+        "nb_build_tree": ([p], i32),
+        "nb_make_lists": ([p, i32], i32),
+        "nb_compute_forces": ([p, i32], i32),
+        "nb_kick_drift": ([p, d, d], i32),
+        "nb_get_forces": ([p, p, p, p, p, i32], i32),
+        "nb_get_state": ([p] + [p] * 6 + [i32], i32),
+        "nb_get_info": ([p, p], i32),
+        "nb_get_root": ([p, p, p], i32),
+        "nb_get_keys": ([p, p, p], i32),
+        "nb_get_cells": ([p] + [p] * 7, i32),
+        "nb_get_moments": ([p, p, p, p], i32),
+        "nb_get_groups": ([p] + [p] * 6, i32),
+        "nb_get_lists": ([p, p, p, p, p], i32),
+        "nb_get_timing": ([p, p, p, i32], i32),
+        "nb_last_error": ([p], C.c_char_p),
+        "nb_version": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def version() -> str:
+    return load().nb_version().decode()
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+class Context:
+    """One GPU-resident particle system (``nb_ctx``)."""
+
+    def __init__(self, theta=0.5, eps=0.01, G=1.0, n_leaf=8, n_grp=64,
+                 order=1, ext_mass=0.0, timing=False, stream=None):
+        self._lib = load()
+        self._cfg = nb_config(theta, eps, G, ext_mass, n_leaf, n_grp, order,
+                              1 if timing else 0, stream)
+        h = C.c_void_p()
+        rc = self._lib.nb_create(C.byref(self._cfg), C.byref(h))
+        if rc != NB_OK:
+            raise NbError(rc, "nb_create failed")
+        self._h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.nb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, rc):
+        if rc != NB_OK:
+            raise NbError(rc, self.last_error())
+        return rc
+
+    def last_error(self) -> str:
+        return self._lib.nb_last_error(self._h).decode()
+
+    @property
+    def config(self):
+        c = self._cfg
+        return dict(theta=c.theta, eps=c.eps, G=c.G, ext_mass=c.ext_mass,
+                    n_leaf=c.n_leaf, n_grp=c.n_grp, order=c.order)
+
+    def set_config(self, **kw):
+        for k, v in kw.items():
+            if k == "timing":
+                self._cfg.flags = 1 if v else 0
+            else:
+                setattr(self._cfg, k, v)
+        self._chk(self._lib.nb_set_config(self._h, C.byref(self._cfg)))
+
+    # ---- particles ----
+    def set_particles(self, x, y, z, vx, vy, vz, m):
+        arrs = [x, y, z, vx, vy, vz, m]
+        if _is_torch(x) and x.is_cuda:
+            import torch
+            arrs = [a.to(torch.float64).contiguous() for a in arrs]
+            self._keep = arrs  # alive until the copy has completed
+            ptrs = [C.c_void_p(a.data_ptr()) for a in arrs]
+            n = arrs[0].numel()
+            rc = self._lib.nb_set_particles(self._h, n, *ptrs, 1)
+            self._keep = None
+        else:
+            arrs = [np.ascontiguousarray(np.asarray(a), dtype=np.float64)
+                    for a in arrs]
+            n = arrs[0].size
+            if any(a.size != n for a in arrs):
+                raise ValueError("particle arrays differ in length")
+            rc = self._lib.nb_set_particles(self._h, n,
+                                            *(_ptr(a) for a in arrs), 0)
+        self._chk(rc)
+        self.n = n
+
+    # ---- the step ----
+    def build_tree(self):
+        self._chk(self._lib.nb_build_tree(self._h))
+
+    def make_lists(self, mode=NB_MAKE_LIST_FOR_REUSE):
+        self._chk(self._lib.nb_make_lists(self._h, int(mode)))
+
+    def compute_forces(self, mode=NB_MAKE_LIST):
+        self._chk(self._lib.nb_compute_forces(self._h, int(mode)))
+
+    def kick_drift(self, dt_kick, dt_drift):
+        self._chk(self._lib.nb_kick_drift(self._h, float(dt_kick),
+                                          float(dt_drift)))
+
+    # ---- readback ----
+    def get_forces(self, internal=False):
+        out = [np.empty(self.n) for _ in range(4)]
+        self._chk(self._lib.nb_get_forces(self._h, *(_ptr(a) for a in out),
+                                          1 if internal else 0))
+        return tuple(out)
+
+    def get_state(self, internal=False):
+        out = [np.empty(self.n) for _ in range(6)]
+        self._chk(self._lib.nb_get_state(self._h, *(_ptr(a) for a in out),
+                                         1 if internal else 0))
+        return tuple(out)
+
+    def get_info(self):
+        a = np.zeros(10, dtype=np.int64)
+        self._chk(self._lib.nb_get_info(self._h, _ptr(a)))
+        keys = ("n", "n_cell", "n_groups", "n_epj", "n_spj", "n_inter",
+                "force_evals", "total_inter", "k", "n_wi")
+        return {k: int(v) for k, v in zip(keys, a)}
+
+    def get_root(self):
+        lo = np.zeros(3)
+        k = C.c_int32(0)
+        self._chk(self._lib.nb_get_root(self._h, _ptr(lo), C.byref(k)))
+        return lo, int(k.value)
+
+    def get_keys(self):
+        key = np.zeros(self.n, np.uint64)
+        orig = np.zeros(self.n, np.uint32)
+        self._chk(self._lib.nb_get_keys(self._h, _ptr(key), _ptr(orig)))
+        return key, orig
+
+    def get_cells(self):
+        nc = self.get_info()["n_cell"]
+        out = dict(level=np.zeros(nc, np.uint8), begin=np.zeros(nc, np.uint32),
+                   count=np.zeros(nc, np.uint32),
+                   parent=np.zeros(nc, np.uint32),
+                   skip=np.zeros(nc, np.uint32), leaf=np.zeros(nc, np.uint8),
+                   ctr=np.zeros((nc, 3)))
+        self._chk(self._lib.nb_get_cells(self._h, *(_ptr(out[k]) for k in (
+            "level", "begin", "count", "parent", "skip", "leaf", "ctr"))))
+        return out
+
+    def get_moments(self):
+        nc = self.get_info()["n_cell"]
+        mass, com, quad = np.zeros(nc), np.zeros((nc, 3)), np.zeros((nc, 6))
+        self._chk(self._lib.nb_get_moments(self._h, _ptr(mass), _ptr(com),
+                                           _ptr(quad)))
+        return mass, com, quad
+
+    def get_groups(self):
+        ng = self.get_info()["n_groups"]
+        out = dict(cell=np.zeros(ng, np.uint32), begin=np.zeros(ng, np.uint32),
+                   count=np.zeros(ng, np.uint32), lo=np.zeros((ng, 3)),
+                   hi=np.zeros((ng, 3)), ctr=np.zeros((ng, 3)))
+        self._chk(self._lib.nb_get_groups(self._h, *(_ptr(out[k]) for k in (
+            "cell", "begin", "count", "lo", "hi", "ctr"))))
+        return out
+
+    def get_lists(self):
+        info = self.get_info()
+        ng, ne, ns = info["n_groups"], info["n_epj"], info["n_spj"]
+        eo = np.zeros(ng + 1, np.int64)
+        so = np.zeros(ng + 1, np.int64)
+        e = np.zeros(ne, np.uint32)
+        s = np.zeros(ns, np.uint32)
+        self._chk(self._lib.nb_get_lists(self._h, _ptr(eo), _ptr(e), _ptr(so),
+                                         _ptr(s)))
+        return eo, e, so, s
+
+    def get_timing(self, reset=False):
+        ms = np.zeros(len(PHASES))
+        calls = np.zeros(len(PHASES), np.int64)
+        self._chk(self._lib.nb_get_timing(self._h, _ptr(ms), _ptr(calls),
+                                          1 if reset else 0))
+        return {p: (float(t), int(c)) for p, t, c in zip(PHASES, ms, calls)}

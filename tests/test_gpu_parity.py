@@ -1,0 +1,354 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bit-exact: root cube, Morton keys, sort permutation, cells (level, begin,
+count, parent, skip, leaf, centre), groups (cell, range, tight box, centre)
+and the CSR interaction lists.  Within tolerance: moments (FP32 offsets) and
+forces (FP32 kernel vs FP64 sum over the same lists: median relative error
+<= 1e-5)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+import paper_1907_02290_amd as nb
+
+pytestmark = pytest.mark.gpu
+
+FORCE_MEDIAN_TOL = 1e-5   # FP32 kernel vs FP64 list sum, median
+FORCE_P99_TOL = 1e-3
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _clustered(n, seed):
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal((3, n)) ** 3
+    p[:, : n // 10] = 0.25  # many identical positions: level-21 leaves
+    v = np.zeros((3, n))
+    return dict(x=p[0].copy(), y=p[1].copy(), z=p[2].copy(), vx=v[0].copy(),
+                vy=v[1].copy(), vz=v[2].copy(), m=rng.uniform(0.5, 2.0, n))
+
+
+def system(kind, n, seed=0):
+    if kind == "plummer":
+        return workloads.plummer(n, workloads.seed_for(1, seed))
+    if kind == "disk":
+        return workloads.disk_halo(n // 2, n - n // 2, workloads.seed_for(3, seed))
+    if kind == "ring":
+        return workloads.ring(n, workloads.seed_for(4, seed))
+    if kind == "sphere":
+        return workloads.uniform_sphere(n, workloads.seed_for(6, seed))
+    if kind == "clustered":
+        return _clustered(n, 11 + seed)
+    raise KeyError(kind)
+
+
+CASES = [("plummer", 4096), ("plummer", 1), ("plummer", 2), ("plummer", 9),
+         ("plummer", 65), ("plummer", 1000), ("plummer", 65537),
+         ("clustered", 3000), ("disk", 20000), ("ring", 12345),
+         ("sphere", 5000)]
+
+
+def gpu_ctx(d, theta=0.5, eps=1 / 64, n_leaf=8, n_grp=64, order=1,
+            ext_mass=0.0):
+    ctx = nb.Context(theta=theta, eps=eps, n_leaf=n_leaf, n_grp=n_grp,
+                     order=order, ext_mass=ext_mass)
+    ctx.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
+                      d["m"])
+    return ctx
+
+
+def compare_tree(ctx, t, check_perm=True, prev_orig=None):
+    lo, k = ctx.get_root()
+    assert k == t.k
+    np.testing.assert_array_equal(lo, t.lo)
+    key, orig = ctx.get_keys()
+    okey, operm = t.keys()
+    np.testing.assert_array_equal(key, okey)
+    if check_perm:
+        want = operm if prev_orig is None else prev_orig[operm]
+        np.testing.assert_array_equal(orig, want)
+    c, oc = ctx.get_cells(), t.cells()
+    assert c["begin"].size == t.n_cell
+    for f in ("level", "begin", "count", "parent", "skip", "leaf", "ctr"):
+        np.testing.assert_array_equal(c[f], oc[f], err_msg=f)
+    g, og = ctx.get_groups(), t.groups()
+    assert g["cell"].size == t.n_groups
+    for f in ("cell", "begin", "count", "lo", "hi", "ctr"):
+        np.testing.assert_array_equal(g[f], og[f], err_msg=f)
+
+
+def compare_lists(ctx, t):
+    eo, e, so, s = ctx.get_lists()
+    oeo, oe, oso, os_ = t.lists()
+    np.testing.assert_array_equal(eo, oeo)
+    np.testing.assert_array_equal(so, oso)
+    np.testing.assert_array_equal(e, oe)
+    np.testing.assert_array_equal(s, os_)
+
+
+def force_errors(got, ref, mask=None):
+    ax, ay, az, pot = got
+    rx, ry, rz, rp = ref
+    if mask is None:
+        mask = np.isfinite(rx)
+    num = np.sqrt((ax - rx) ** 2 + (ay - ry) ** 2 + (az - rz) ** 2)[mask]
+    den = np.sqrt(rx ** 2 + ry ** 2 + rz ** 2)[mask]
+    ok = den > 0
+    ea = num[ok] / den[ok]
+    ep = (np.abs(pot - rp)[mask] / np.abs(rp)[mask])[np.abs(rp)[mask] > 0]
+    return ea, ep
+
+
+def check_forces(got, ref, mask=None, what=""):
+    ea, ep = force_errors(got, ref, mask)
+    if ea.size == 0:
+        return
+    say("  %s acc rel err: median %.2e p99 %.2e max %.2e | pot median %.2e"
+        % (what, np.median(ea), np.percentile(ea, 99), ea.max(),
+           np.median(ep) if ep.size else 0.0))
+    assert np.median(ea) <= FORCE_MEDIAN_TOL
+    assert np.percentile(ea, 99) <= FORCE_P99_TOL
+    if ep.size:
+        assert np.median(ep) <= FORCE_MEDIAN_TOL
+
+
+@pytest.mark.parametrize("kind,n", CASES)
+def test_tree_groups_lists_bit_exact(kind, n):
+    say("case tree/lists %s n=%d" % (kind, n))
+    d = system(kind, n)
+    with gpu_ctx(d) as ctx:
+        ctx.build_tree()
+        ctx.make_lists(nb.NB_MAKE_LIST_FOR_REUSE)
+        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 64)
+        t.make_lists(0.5)
+        compare_tree(ctx, t)
+        compare_lists(ctx, t)
+        info = ctx.get_info()
+        eo, e, so, s = t.lists()
+        gc = t.groups()["count"].astype(np.int64)
+        inter = int((gc * (np.diff(eo) + np.diff(so))).sum())
+        assert info["n_inter"] == inter
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, 0.7, 1.0])
+@pytest.mark.parametrize("n_leaf,n_grp", [(1, 1), (4, 8), (8, 33), (16, 100),
+                                          (8, 512)])
+def test_lists_bit_exact_theta_and_sizes(theta, n_leaf, n_grp):
+    say("case lists theta=%g n_leaf=%d n_grp=%d" % (theta, n_leaf, n_grp))
+    d = system("plummer", 3000, seed=2)
+    with gpu_ctx(d, theta=theta, n_leaf=n_leaf, n_grp=n_grp) as ctx:
+        ctx.build_tree()
+        ctx.make_lists(nb.NB_MAKE_LIST)
+        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], n_leaf, n_grp)
+        t.make_lists(theta)
+        compare_tree(ctx, t)
+        compare_lists(ctx, t)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_moments_within_fp32_tolerance(order):
+    say("case moments order=%d" % order)
+    d = system("plummer", 20000, seed=3)
+    with gpu_ctx(d, order=order) as ctx:
+        ctx.build_tree()
+        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 64)
+        M, X, S = ctx.get_moments()
+        oM, oX, oS = t.moments()
+        lev = t.cells()["level"].astype(np.int64)
+        side = 2.0 ** (t.k - lev)
+        np.testing.assert_allclose(M, oM, rtol=1e-6)
+        assert np.all(np.abs(X - oX).max(1) <= 1e-5 * side)
+        if order == 2:
+            scale = (oM * side ** 2)[:, None]
+            assert np.all(np.abs(S - oS) <= 1e-5 * scale + 1e-30)
+
+
+@pytest.mark.parametrize("kind,n", CASES)
+@pytest.mark.parametrize("order", [1, 2])
+def test_forces_match_fp64_list_sum(kind, n, order):
+    say("case forces %s n=%d order=%d" % (kind, n, order))
+    d = system(kind, n)
+    with gpu_ctx(d, order=order) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        got = ctx.get_forces()
+        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 64)
+        t.make_lists(0.5)
+        ref = t.force_lists(order, 1 / 64, 1.0)
+        if n == 1:
+            assert [float(a[0]) for a in got] == [0.0, 0.0, 0.0, 0.0]
+            return
+        check_forces(got, ref, what="%s/%d/o%d" % (kind, n, order))
+
+
+@pytest.mark.parametrize("n_grp", [1, 5, 20, 33, 64, 100, 512])
+def test_forces_lane_slices_and_chunks(n_grp):
+    say("case forces n_grp=%d" % n_grp)
+    d = system("plummer", 6000, seed=5)
+    for order in (1, 2):
+        with gpu_ctx(d, n_grp=n_grp, order=order) as ctx:
+            ctx.compute_forces(nb.NB_MAKE_LIST)
+            got = ctx.get_forces()
+        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, n_grp)
+        t.make_lists(0.5)
+        check_forces(got, t.force_lists(order, 1 / 64, 1.0),
+                     what="n_grp=%d o%d" % (n_grp, order))
+
+
+def test_theta_zero_matches_direct_sum():
+    say("case theta=0 vs direct")
+    d = system("plummer", 4096, seed=7)
+    with gpu_ctx(d, theta=0.0) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST)
+        got = ctx.get_forces()
+    ref = oracle.force_direct(d["x"], d["y"], d["z"], d["m"], 1 / 64, 1.0)
+    check_forces(got, ref, what="theta0")
+
+
+def test_kick_drift_matches_oracle():
+    say("case kick-drift")
+    d = system("plummer", 5000, seed=8)
+    with gpu_ctx(d, ext_mass=0.3) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        acc = ctx.get_forces()[:3]
+        s0 = [a.copy() for a in ctx.get_state()]
+        ctx.kick_drift(0.01, 0.02)
+        s1 = ctx.get_state()
+    pos, vel = s0[:3], s0[3:]
+    oracle.kick_drift(pos, vel, acc, 0.01, 0.02, ext_mass=0.3)
+    for a, b in zip(list(pos) + list(vel), s1):
+        np.testing.assert_allclose(b, a, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_reuse_steps_match_oracle_refresh(order):
+    say("case reuse order=%d" % order)
+    d = system("plummer", 8000, seed=9)
+    dt = 1 / 64
+    with gpu_ctx(d, order=order) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 64)
+        t.make_lists(0.5)
+        info0 = ctx.get_info()
+        for step in range(3):
+            ctx.kick_drift(dt / 2 if step == 0 else dt, dt)
+            ctx.compute_forces(nb.NB_REUSE_LIST)
+            x, y, z, vx, vy, vz = ctx.get_state()
+            t.refresh(x, y, z, d["m"])
+            check_forces(ctx.get_forces(), t.force_lists(order, 1 / 64, 1.0),
+                         what="reuse step %d" % step)
+        info = ctx.get_info()
+        assert info["force_evals"] == 4
+        assert info["total_inter"] == 4 * info0["n_inter"]
+
+
+def test_second_construction_after_steps():
+    say("case rebuild after steps")
+    d = system("disk", 16000, seed=1)
+    dt = 1 / 32
+    with gpu_ctx(d, eps=0.01) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        for step in range(4):
+            ctx.kick_drift(dt, dt)
+            ctx.compute_forces(nb.NB_REUSE_LIST)
+        ctx.kick_drift(dt, dt)
+        # the sort sees the particles in the internal order of the last build
+        x, y, z, _, _, _ = ctx.get_state(internal=True)
+        _, prev_orig = ctx.get_keys()
+        ms = d["m"][prev_orig]
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        t = oracle.Tree(x, y, z, ms, 8, 64)
+        t.make_lists(0.5)
+        compare_tree(ctx, t, prev_orig=prev_orig)
+        compare_lists(ctx, t)
+        got = ctx.get_forces(internal=True)
+        ref = t.force_lists(1, 0.01, 1.0)
+        _, perm = t.keys()
+        # oracle outputs are in its input order = previous internal order;
+        # map the GPU's new internal order back to it
+        inv = np.empty_like(perm)
+        inv[perm] = np.arange(perm.size)
+        got_prev = tuple(a[inv] for a in got)
+        check_forces(got_prev, ref, what="rebuild")
+
+
+def test_error_paths():
+    say("case error paths")
+    d = system("plummer", 500)
+    with gpu_ctx(d) as ctx:
+        with pytest.raises(nb.NbError) as e:
+            ctx.compute_forces(nb.NB_REUSE_LIST)
+        assert e.value.code == nb.NB_ERR_STATE
+        with pytest.raises(nb.NbError) as e:
+            ctx.make_lists(nb.NB_MAKE_LIST)
+        assert e.value.code == nb.NB_ERR_STATE
+        with pytest.raises(nb.NbError) as e:
+            ctx.kick_drift(0.1, 0.1)
+        assert e.value.code == nb.NB_ERR_STATE
+        ctx.compute_forces(nb.NB_MAKE_LIST)
+        ctx.kick_drift(0.1, 0.1)
+        with pytest.raises(nb.NbError) as e:  # lists were not kept
+            ctx.compute_forces(nb.NB_REUSE_LIST)
+        assert e.value.code == nb.NB_ERR_STATE
+        with pytest.raises(nb.NbError) as e:  # tree of old positions
+            ctx.make_lists(nb.NB_MAKE_LIST)
+        assert e.value.code == nb.NB_ERR_STATE
+    bad = dict(d)
+    bad["x"] = d["x"].copy()
+    bad["x"][17] = np.nan
+    with gpu_ctx(bad) as ctx:
+        with pytest.raises(nb.NbError) as e:
+            ctx.build_tree()
+        assert e.value.code == nb.NB_ERR_INPUT
+    with pytest.raises(nb.NbError) as e:
+        nb.Context().set_particles(*([np.zeros(0)] * 7))
+    assert e.value.code == nb.NB_ERR_INPUT
+
+
+def test_device_resident_input_matches_host_input():
+    say("case device input")
+    import torch
+    d = system("plummer", 4096, seed=4)
+    with gpu_ctx(d) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST)
+        ref = ctx.get_forces()
+    dev = {k: torch.from_numpy(v).cuda() for k, v in d.items()}
+    with nb.Context(theta=0.5, eps=1 / 64) as ctx:
+        ctx.set_particles(dev["x"], dev["y"], dev["z"], dev["vx"], dev["vy"],
+                          dev["vz"], dev["m"])
+        ctx.compute_forces(nb.NB_MAKE_LIST)
+        got = ctx.get_forces()
+    for a, b in zip(got, ref):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,order,sample", [("plummer_1m", 2, 256),
+                                               ("disk_4m", 1, 256)])
+def test_full_size_sampled(name, order, sample):
+    """Full-size systems in the benchmark's launch configuration: keys, tree
+    and groups compared whole; lists and forces on sampled groups."""
+    say("case full size %s" % name)
+    d, p = workloads.make(name)
+    with gpu_ctx(d, theta=p["theta"], eps=p["eps"], n_leaf=p["n_leaf"],
+                 n_grp=p["n_grp"], order=order) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        say("  gpu done", ctx.get_info())
+        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], p["n_leaf"],
+                        p["n_grp"])
+        compare_tree(ctx, t)
+        rng = np.random.default_rng(1)
+        sel = np.sort(rng.choice(t.n_groups, size=min(sample, t.n_groups),
+                                 replace=False))
+        t.make_lists(p["theta"], sel)
+        oeo, oe, oso, os_ = t.lists()
+        eo, e, so, s = ctx.get_lists()
+        for k, g in enumerate(sel):
+            np.testing.assert_array_equal(e[eo[g]:eo[g + 1]],
+                                          oe[oeo[k]:oeo[k + 1]])
+            np.testing.assert_array_equal(s[so[g]:so[g + 1]],
+                                          os_[oso[k]:oso[k + 1]])
+        ref = t.force_lists(order, p["eps"], 1.0)
+        mask = np.isfinite(ref[0])
+        check_forces(ctx.get_forces(), ref, mask, what=name)
