@@ -1,0 +1,252 @@
+"""Benchmark: GPU-resident Barnes-Hut leapfrog steps with list reuse.
+
+Workload (default): disk galaxy, N = 2^22 (2^21 exponential-disk particles +
+2^21 Hernquist-halo particles, halo particles 10x heavier), theta = 0.5,
+eps = 0.01, dt = 1/128, interaction lists rebuilt every 4 steps (a
+construction step every 4 steps, reuse steps in between).
+
+One timed step = kick-drift + (construction step: root, keys, sort, reorder,
+link, moments, groups, walk | reuse step: moments) + multiwalk force kernel.
+Inputs are resident in HBM before timing starts.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--n-grp G]
+                  [--no-cpu-baseline] [--copy-probe MiB]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_OP = 23              # flops per interaction (the paper's convention)
+FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector peak
+WORKLOAD = "disk_4m"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--n-grp", type=int, default=None)
+    ap.add_argument("--n-leaf", type=int, default=None)
+    ap.add_argument("--reuse", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also run a plain device copy of this many MiB "
+                         "(reference kernel for HBM counters)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU "
+              "path (requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    import paper_1907_02290_amd as nb
+
+    d, p = workloads.make(args.workload, n=args.n)
+    n_grp = args.n_grp or p["n_grp"]
+    n_leaf = args.n_leaf or p["n_leaf"]
+    reuse = args.reuse or p.get("reuse", 4)
+    dt = p["dt"]
+    n = d["x"].size
+    log("workload %s n=%d theta=%g eps=%g n_leaf=%d n_grp=%d reuse=%d"
+        % (args.workload, n, p["theta"], p["eps"], n_leaf, n_grp, reuse))
+
+    torch.cuda.set_device(0)
+    dev = {k: torch.from_numpy(v).cuda() for k, v in d.items()}
+    ctx = nb.Context(theta=p["theta"], eps=p["eps"], n_leaf=n_leaf,
+                     n_grp=n_grp, order=p["order"],
+                     ext_mass=p.get("ext_mass", 0.0), timing=True)
+    ctx.set_particles(dev["x"], dev["y"], dev["z"], dev["vx"], dev["vy"],
+                      dev["vz"], dev["m"])
+    del dev
+
+    # KDK leapfrog with merged half kicks.  Step g (g >= 1): kick (dt/2 for
+    # g = 1, else dt), drift dt, forces; a construction step when g is a
+    # multiple of `reuse`, a reuse step otherwise.  Forces at t = 0 come
+    # from an untimed construction step.
+    step_no = [1]
+
+    def step():
+        g = step_no[0]
+        mode = nb.NB_MAKE_LIST_FOR_REUSE if g % reuse == 0 else \
+            nb.NB_REUSE_LIST
+        ctx.kick_drift(dt / 2 if g == 1 else dt, dt)
+        ctx.compute_forces(mode)
+        step_no[0] += 1
+
+    ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+    # warm up, then start timing on a construction step so the timed steps
+    # hold whole reuse cycles
+    warm = 0
+    while warm < args.warmup or step_no[0] % reuse != 0:
+        step()
+        warm += 1
+    torch.cuda.synchronize()
+    ctx.get_timing(reset=True)
+    info0 = ctx.get_info()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    info1 = ctx.get_info()
+    timing = ctx.get_timing(reset=True)
+    elapsed = t1 - t0
+    inter = info1["total_inter"] - info0["total_inter"]
+    evals = info1["force_evals"] - info0["force_evals"]
+    value = inter / elapsed
+    ms_step = elapsed / args.steps * 1e3
+    f_ms, f_calls = timing["force"]
+    f_avg_s = f_ms / max(f_calls, 1) * 1e-3
+    inter_per_launch = inter / max(evals, 1)
+    achieved = N_OP * inter_per_launch / f_avg_s / 1e12 if f_avg_s > 0 else 0
+    log("timed %d steps in %.3f s: %.3f ms/step, %.3e interactions/s"
+        % (args.steps, elapsed, ms_step, value))
+    log("phase ms: " + ", ".join("%s %.2f/%d" % (k, v[0], v[1])
+                                 for k, v in timing.items()))
+
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe * (1 << 20) // 4, dtype=torch.float32,
+                        device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: %d MiB" % args.copy_probe)
+
+    # force error of one construction step vs the FP64 oracle, and the
+    # CPU baseline on a bounded sample of groups
+    ctx.kick_drift(dt, dt)
+    ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+    gx, gy, gz, gp = ctx.get_forces()
+    x, y, z, _, _, _ = ctx.get_state()
+    info_last = ctx.get_info()
+    ctx.close()
+
+    force_err = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        tb = time.perf_counter()
+        t = oracle.Tree(x, y, z, d["m"], n_leaf, n_grp)
+        t_build = time.perf_counter() - tb
+        rng = np.random.default_rng(12345)
+        gcount = t.groups()["count"].astype(np.int64)
+
+        def run(sel):
+            ta = time.perf_counter()
+            ng, ne, ns = t.make_lists(p["theta"], sel)
+            f = t.force_lists(p["order"], p["eps"], 1.0)
+            eo, e, so, s = t.lists()
+            it = int((gcount[sel] * (np.diff(eo) + np.diff(so))).sum())
+            return time.perf_counter() - ta, it, f
+
+        probe = np.sort(rng.choice(t.n_groups, size=min(64, t.n_groups),
+                                   replace=False))
+        tp, ip, _ = run(probe)
+        rate = ip / max(tp, 1e-6)
+        per_group = ip / probe.size
+        want = int(min(t.n_groups, max(64, args.cpu_seconds * rate /
+                                       max(per_group, 1))))
+        sel = np.sort(rng.choice(t.n_groups, size=want, replace=False))
+        tc, ic, f = run(sel)
+        mask = np.isfinite(f[0])
+        num = np.sqrt((gx - f[0]) ** 2 + (gy - f[1]) ** 2 +
+                      (gz - f[2]) ** 2)[mask]
+        den = np.sqrt(f[0] ** 2 + f[1] ** 2 + f[2] ** 2)[mask]
+        ea = num[den > 0] / den[den > 0]
+        ep = (np.abs(gp - f[3])[mask] / np.abs(f[3])[mask])
+        force_err = {"median": float(np.median(ea)),
+                     "p99": float(np.percentile(ea, 99)),
+                     "max": float(ea.max()),
+                     "pot_median": float(np.median(ep)),
+                     "particles": int(mask.sum()),
+                     "reference": "FP64 oracle sum over the same lists"}
+        cpu = {"value": ic / tc, "unit": "interactions/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "FP64 oracle walk + list-force sum over %d of %d "
+                         "groups (%d particles, %.3e interactions) of one "
+                         "construction step of the same workload; oracle "
+                         "tree build (%.1f s, all N) not counted"
+                         % (sel.size, t.n_groups, int(gcount[sel].sum()),
+                            ic, t_build),
+               "seconds": tc}
+        log("cpu baseline: %.3e interactions/s on %d threads (%.1f s); "
+            "force err median %.2e" % (cpu["value"], cpu["cores"], tc,
+                                       force_err["median"]))
+
+    out = {
+        "metric": "interactions/s at N=2^22, theta=0.5 (lists reused every "
+                  "4 steps); ms/step and rel force err vs FP64 oracle beside",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": warm,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (force kernel); f64 (keys, tree, walk, integration)",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: exponential disk 2^21 + Hernquist halo 2^21 "
+                        "(halo particles 10x heavier), eps 0.01, dt 1/128"
+                        % args.workload if args.workload == "disk_4m"
+                        else args.workload,
+            "n": n, "theta": p["theta"], "eps": p["eps"], "n_leaf": n_leaf,
+            "n_grp": n_grp, "order": p["order"], "reuse_every": reuse,
+            "groups": info_last["n_groups"], "cells": info_last["n_cell"],
+            "mean_n_i": n / max(info_last["n_groups"], 1),
+            "mean_list": (info_last["n_epj"] + info_last["n_spj"]) /
+                         max(info_last["n_groups"], 1),
+            "force_evals": evals,
+        },
+        "roofline": {
+            "kernel": "k_force (multiwalk force, monopole)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": None,
+            "flops_per_launch": N_OP * inter_per_launch,
+            "avg_launch_ms": f_avg_s * 1e3,
+        },
+        "cpu_baseline": cpu,
+        "force_err": force_err,
+        "phase_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
+        "interactions_per_s_frac_of_fp32_peak": value * N_OP /
+                                                (FP32_PEAK_TFLOPS * 1e12),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

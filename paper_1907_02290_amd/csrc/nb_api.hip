@@ -173,31 +173,27 @@ static int build_tree(nb_ctx* c) {
   {
     Timed t(c, NB_PH_GROUPS);
     if ((rc = launch_group_flags(c))) return rc;
+    if ((rc = launch_level_lists(c))) return rc;
   }
-  // sync 2: level histogram (leaves in the last bucket) and group count
-  if ((rc = stage_d2h(c, 0, c->lvl_cnt.p, (kLevels + 1) * sizeof(uint32_t))))
-    return rc;
-  if ((rc = stage_d2h(c, 256, c->gflag.p + c->n_cell, sizeof(uint32_t))))
+  // sync 2: where each level starts in the level lists (the leaves are
+  // bucket kLevels) and the group count
+  if ((rc = stage_d2h(c, 0, c->red.p, (kLevels + 2) * sizeof(uint32_t))))
     return rc;
   if ((rc = sync(c))) return rc;
   {
     const uint32_t* h = static_cast<const uint32_t*>(c->h_small);
-    c->n_leaves = h[kLevels];
-    int64_t off = c->n_leaves;
-    for (int l = kMaxLevel; l >= 0; --l) {
-      c->lvl_count[l] = h[l];
-      c->lvl_off[l] = off;
-      off += h[l];
+    for (int b = 0; b <= kLevels; ++b) {
+      c->lvl_off[b] = h[b];
+      const int64_t next = b < kLevels ? (int64_t)h[b + 1] : c->n_cell;
+      c->lvl_count[b] = next - (int64_t)h[b];
+      if (c->lvl_count[b] < 0)
+        return set_err(c, NB_ERR_HIP, "inconsistent level histogram");
     }
-    c->lvl_off[kLevels] = off;
-    c->n_groups = h[64];
-    if (off != c->n_cell || c->n_groups < 1)
-      return set_err(c, NB_ERR_HIP, "inconsistent tree (%lld/%lld cells)",
-                     (long long)off, (long long)c->n_cell);
-  }
-  {
-    Timed t(c, NB_PH_GROUPS);
-    if ((rc = launch_level_lists(c))) return rc;
+    c->n_leaves = c->lvl_count[kLevels];
+    c->n_groups = h[kLevels + 1];
+    if (c->n_groups < 1 || h[0] != 0)
+      return set_err(c, NB_ERR_HIP, "inconsistent tree (%lld groups)",
+                     (long long)c->n_groups);
   }
   {
     Timed t(c, NB_PH_MOMENTS);
@@ -230,17 +226,21 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
   if ((rc = stage_d2h(c, 0, c->epj_off.p + c->n_groups, 8))) return rc;
   if ((rc = stage_d2h(c, 8, c->spj_off.p + c->n_groups, 8))) return rc;
   if ((rc = stage_d2h(c, 16, c->red.p, 8))) return rc;
-  if ((rc = stage_d2h(c, 24, c->g_chunks.p + c->n_groups, 4))) return rc;
+  if ((rc = stage_d2h(c, 24, c->tok_off.p + c->n_groups, 8))) return rc;
+  if ((rc = stage_d2h(c, 32, c->g_chunks.p + c->n_groups, 4))) return rc;
   if ((rc = sync(c))) return rc;
+  int64_t n_tok;
   {
     const uint64_t* h = static_cast<const uint64_t*>(c->h_small);
     c->n_epj = (int64_t)h[0];
     c->n_spj = (int64_t)h[1];
     c->n_inter = (int64_t)h[2];
-    c->n_wi = static_cast<const uint32_t*>(c->h_small)[6];
+    n_tok = (int64_t)h[3];
+    c->n_wi = static_cast<const uint32_t*>(c->h_small)[8];
   }
   if ((rc = reserve(c, c->epj, (size_t)c->n_epj + 1))) return rc;
   if ((rc = reserve(c, c->spj, (size_t)c->n_spj + 1))) return rc;
+  if ((rc = reserve(c, c->tok, (size_t)n_tok + 1))) return rc;
   {
     Timed t(c, NB_PH_WALK);
     if ((rc = launch_walk(c, true))) return rc;
@@ -311,14 +311,15 @@ void nb_destroy(nb_ctx* c) {
   release(c->key); release(c->key2); release(c->val); release(c->val2);
   release(c->hist); release(c->dtot); release(c->root); release(c->bbox_part);
   release(c->lam); release(c->lmin); release(c->cstart);
-  release(c->c_meta); release(c->c_parent); release(c->c_geo);
+  release(c->c_rec);
   release(c->c_mom); release(c->c_quad); release(c->c_pm);
-  release(c->lvl_cells); release(c->lvl_cnt);
+  release(c->lvl_cells); release(c->bucket);
   release(c->gflag); release(c->g_cell); release(c->g_begin);
   release(c->g_count); release(c->g_lo); release(c->g_hi);
   release(c->g_chunks); release(c->wi);
-  release(c->cnt_e); release(c->cnt_s); release(c->epj_off);
-  release(c->spj_off); release(c->epj); release(c->spj);
+  release(c->cnt_e); release(c->cnt_s); release(c->cnt_t);
+  release(c->epj_off); release(c->spj_off); release(c->tok_off);
+  release(c->epj); release(c->spj); release(c->tok);
   release(c->scan_tmp); release(c->red);
   if (c->h_small) (void)hipHostFree(c->h_small);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -556,28 +557,24 @@ int nb_get_cells(nb_ctx* c, uint8_t* level, uint32_t* begin, uint32_t* count,
   if (!c) return NB_ERR_INPUT;
   if (!c->tree_valid) return set_err(c, NB_ERR_STATE, "no tree");
   const size_t nc = (size_t)c->n_cell;
-  std::vector<uint4> m(nc);
-  std::vector<uint32_t> p(nc);
-  std::vector<double4> g(nc);
+  std::vector<CellRec> r(nc);
   int rc = sync(c);
-  if (!rc) rc = hip_check(c, hipMemcpy(m.data(), c->c_meta.p, nc * 16,
-                                       hipMemcpyDeviceToHost), "cell readback");
-  if (!rc) rc = hip_check(c, hipMemcpy(p.data(), c->c_parent.p, nc * 4,
-                                       hipMemcpyDeviceToHost), "cell readback");
-  if (!rc) rc = hip_check(c, hipMemcpy(g.data(), c->c_geo.p, nc * 32,
+  if (!rc) rc = hip_check(c, hipMemcpy(r.data(), c->c_rec.p,
+                                       nc * sizeof(CellRec),
                                        hipMemcpyDeviceToHost), "cell readback");
   if (rc) return rc;
   for (size_t i = 0; i < nc; ++i) {
-    if (level) level[i] = (uint8_t)(m[i].w & 255u);
-    if (begin) begin[i] = m[i].x;
-    if (count) count[i] = m[i].y - m[i].x;
-    if (parent) parent[i] = p[i];
-    if (skip) skip[i] = m[i].z;
-    if (leaf) leaf[i] = (uint8_t)((m[i].w >> 8) & 1u);
+    const uint4 m = r[i].meta;
+    if (level) level[i] = (uint8_t)(m.w & 255u);
+    if (begin) begin[i] = m.x;
+    if (count) count[i] = m.y - m.x;
+    if (parent) parent[i] = r[i].aux.x;
+    if (skip) skip[i] = m.z;
+    if (leaf) leaf[i] = (uint8_t)((m.w >> 8) & 1u);
     if (ctr3) {
-      ctr3[3 * i] = g[i].x;
-      ctr3[3 * i + 1] = g[i].y;
-      ctr3[3 * i + 2] = g[i].z;
+      ctr3[3 * i] = r[i].geo.x;
+      ctr3[3 * i + 1] = r[i].geo.y;
+      ctr3[3 * i + 2] = r[i].geo.z;
     }
   }
   return NB_OK;
@@ -633,10 +630,11 @@ int nb_get_groups(nb_ctx* c, uint32_t* cell, uint32_t* begin, uint32_t* count,
   if (!rc) rc = hip_check(c, hipMemcpy(hi.data(), c->g_hi.p, ng * 32,
                                        hipMemcpyDeviceToHost), "group readback");
   if (rc) return rc;
-  std::vector<double4> geo;
+  std::vector<CellRec> rec;
   if (ctr3) {
-    geo.resize((size_t)c->n_cell);
-    rc = hip_check(c, hipMemcpy(geo.data(), c->c_geo.p, geo.size() * 32,
+    rec.resize((size_t)c->n_cell);
+    rc = hip_check(c, hipMemcpy(rec.data(), c->c_rec.p,
+                                rec.size() * sizeof(CellRec),
                                 hipMemcpyDeviceToHost), "group readback");
     if (rc) return rc;
   }
@@ -655,9 +653,9 @@ int nb_get_groups(nb_ctx* c, uint32_t* cell, uint32_t* begin, uint32_t* count,
       hi3[3 * g + 2] = hi[g].z;
     }
     if (ctr3) {
-      ctr3[3 * g] = geo[gc[g]].x;
-      ctr3[3 * g + 1] = geo[gc[g]].y;
-      ctr3[3 * g + 2] = geo[gc[g]].z;
+      ctr3[3 * g] = rec[gc[g]].geo.x;
+      ctr3[3 * g + 1] = rec[gc[g]].geo.y;
+      ctr3[3 * g + 2] = rec[gc[g]].geo.z;
     }
   }
   return NB_OK;

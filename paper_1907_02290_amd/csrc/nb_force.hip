@@ -8,12 +8,13 @@
 //  * one i-particle per lane, as FP32 offsets from the group centre (the
 //    FP64 subtraction is done once per particle and once per list entry);
 //  * a group of n_i < 33 particles is replicated over r = 64 / n_i lane
-//    slices; slice s takes list entries s, s + r, ... of every tile and the
-//    slices are summed through LDS at the end;
-//  * the list is walked in tiles of 64 entries: each lane gathers one entry
-//    by index (particle by slot, superparticle by cell id -- the same
-//    {x, y, z, m} FP64 record), converts it to FP32 offsets and stores it in
-//    LDS; every lane then reads the tile back as broadcasts;
+//    slices; each slice sums its own block of every tile and the slices are
+//    added through LDS at the end;
+//  * the list is walked in tiles of 64 min(r, 4) entries: each lane gathers
+//    entries by index (particle by slot, superparticle by cell id -- the
+//    same {x, y, z, m} FP64 record), converts them to FP32 offsets and
+//    stores them in LDS; the lanes of a slice then read its block back as
+//    broadcasts;
 //  * FP32 arithmetic with per-tile partial sums added into the totals;
 //    the potential of the particle on itself is removed at the end;
 //  * workgroup ids are remapped so that each XCD (workgroups are dealt out
@@ -71,18 +72,54 @@ __device__ __forceinline__ void quadr(const float4 j, const float4 qa,
   ph -= fmaf(j.w, f, 0.5f * fmaf(3.0f * q, f2, -t) * f3);
 }
 
+// Sum of one slice's block of `cnt` tile entries (cnt <= 64).  Full blocks
+// take the unrolled path; LDS offsets are then immediates.
 template <int ORDER>
-__global__ void __launch_bounds__(64)
+__device__ __forceinline__ void slice_sum(const float4* __restrict__ t,
+                                          const float4* __restrict__ q,
+                                          int cnt, float xi, float yi,
+                                          float zi, float eps2, float& ax,
+                                          float& ay, float& az, float& ph) {
+  float tx = 0.f, ty = 0.f, tz = 0.f, tp = 0.f;
+  if (ORDER == 1) {
+    if (cnt == kTile) {
+#pragma unroll 8
+      for (int k = 0; k < kTile; ++k)
+        mono(t[k], xi, yi, zi, eps2, tx, ty, tz, tp);
+    } else {
+#pragma unroll 4
+      for (int k = 0; k < cnt; ++k)
+        mono(t[k], xi, yi, zi, eps2, tx, ty, tz, tp);
+    }
+  } else {
+    for (int k = 0; k < cnt; ++k)
+      quadr(t[k], q[2 * k], q[2 * k + 1], xi, yi, zi, eps2, tx, ty, tz, tp);
+  }
+  ax += tx;
+  ay += ty;
+  az += tz;
+  ph += tp;
+}
+
+constexpr int kMaxSlices = 4;
+constexpr int kBigTile = kTile * kMaxSlices;
+
+// One group chunk per wavefront.  With r = 64 / n_i lane slices (r <= 4),
+// a tile holds 64 r list entries and slice s sums entries [64 s, 64 s + 64):
+// every slice does the same unrolled work per tile as a full group does.
+// For r > 4 the 256-entry tile is cut into r near-equal blocks.
+template <int ORDER>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_force(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
-        const uint32_t* __restrict__ g_cell, const double4* __restrict__ geo,
+        const uint32_t* __restrict__ g_cell, const CellRec* __restrict__ rec,
         const uint64_t* __restrict__ epj_off,
         const uint32_t* __restrict__ epj,
         const uint64_t* __restrict__ spj_off,
         const uint32_t* __restrict__ spj, const double4* __restrict__ pos,
         const double4* __restrict__ pm, const float4* __restrict__ quad,
         float eps2, float G, float4* __restrict__ acc) {
-  __shared__ float4 tile[kTile];
-  __shared__ float4 tq[ORDER == 2 ? 2 * kTile : 1];
+  __shared__ float4 tile[kBigTile];
+  __shared__ float4 tq[ORDER == 2 ? 2 * kBigTile : 1];
   __shared__ float4 red[kTile];
 
   const uint32_t bid = blockIdx.x;
@@ -90,13 +127,18 @@ k_force(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
   if (w >= n_wi) return;  // uniform over the workgroup
   const uint4 it = wi[w];
   const int lane = threadIdx.x;
-  const int ni = (int)it.z;          // 1..64
-  const int r = kTile / ni;          // lane slices
+  const int ni = (int)it.z;            // 1..64
+  const int r = kTile / ni;            // lane slices
   const int sl = lane / ni;
   const int ii = lane - sl * ni;
   const bool act = sl < r;
+  const int q = r < kMaxSlices ? r : kMaxSlices;  // tile = 64 q entries
+  const int T = kTile * q;
+  // this slice's block of a full tile
+  const int blk0 = r <= kMaxSlices ? sl * kTile : (sl * T) / r;
+  const int blk1 = r <= kMaxSlices ? blk0 + kTile : ((sl + 1) * T) / r;
   const uint32_t g = it.x;
-  const double4 cg = geo[g_cell[g]];
+  const double4 cg = rec[g_cell[g]].geo;
 
   float xi = 0.f, yi = 0.f, zi = 0.f, mi = 0.f;
   if (act) {
@@ -106,71 +148,96 @@ k_force(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
     zi = (float)(p.z - cg.z);
     mi = (float)p.w;
   }
-  const uint64_t e0 = epj_off[g], ne = epj_off[g + 1] - e0;
-  const uint64_t s0 = spj_off[g], ns = spj_off[g + 1] - s0;
-  const uint64_t nl = ORDER == 1 ? ne + ns : ne;
+  // list entries are addressed relative to the group's list: [0, ne) are
+  // particles, [ne, ne + ns) superparticles
+  const uint64_t e0 = epj_off[g];
+  const uint32_t ne = (uint32_t)(epj_off[g + 1] - e0);
+  const uint64_t s0 = spj_off[g];
+  const uint32_t ns = (uint32_t)(spj_off[g + 1] - s0);
+  const uint32_t* __restrict__ ida = epj + e0;
+  const uint32_t* __restrict__ idb = spj + s0;
+  const uint32_t nl = ORDER == 1 ? ne + ns : ne;
+
+  // ids of the tile starting at tb (slot u of this lane), kNone past the end
+  auto load_ids = [&](uint32_t tb, uint32_t* id) {
+#pragma unroll
+    for (int u = 0; u < kMaxSlices; ++u) {
+      id[u] = kNone;
+      const uint32_t e = tb + (uint32_t)(u * kTile + lane);
+      if (u < q && e < nl) id[u] = e < ne ? ida[e] : idb[e - ne];
+    }
+  };
 
   float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-  for (uint64_t tb = 0; tb < nl; tb += kTile) {
-    const uint64_t q = tb + lane;
-    float4 jd = make_float4(0.f, 0.f, 0.f, 0.f);  // massless padding
-    if (q < nl) {
-      double4 P;
-      if (q < ne)
-        P = pos[epj[e0 + q]];
-      else
-        P = pm[spj[s0 + (q - ne)]];
-      jd = make_float4((float)(P.x - cg.x), (float)(P.y - cg.y),
-                       (float)(P.z - cg.z), (float)P.w);
+  uint32_t nid[kMaxSlices];
+  load_ids(0, nid);
+  for (uint32_t tb = 0; tb < nl; tb += (uint32_t)T) {
+    uint32_t cid[kMaxSlices];
+    double4 P[kMaxSlices];
+#pragma unroll
+    for (int u = 0; u < kMaxSlices; ++u) {
+      cid[u] = nid[u];
+      const uint32_t e = tb + (uint32_t)(u * kTile + lane);
+      if (cid[u] != kNone) P[u] = e < ne ? pos[cid[u]] : pm[cid[u]];
+    }
+    // the next tile's ids arrive while this tile is staged and summed
+    if (tb + (uint32_t)T < nl) load_ids(tb + (uint32_t)T, nid);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kMaxSlices; ++u) {
+      if (u < q) {
+        float4 jd = make_float4(0.f, 0.f, 0.f, 0.f);  // massless padding
+        if (cid[u] != kNone)
+          jd = make_float4((float)(P[u].x - cg.x), (float)(P[u].y - cg.y),
+                           (float)(P[u].z - cg.z), (float)P[u].w);
+        tile[u * kTile + lane] = jd;
+      }
     }
     __syncthreads();
-    tile[lane] = jd;
-    __syncthreads();
     if (act) {
-      float tx = 0.f, ty = 0.f, tz = 0.f, tp = 0.f;
-      if (r == 1) {
-#pragma unroll 8
-        for (int k = 0; k < kTile; ++k)
-          mono(tile[k], xi, yi, zi, eps2, tx, ty, tz, tp);
-      } else {
-        for (int k = sl; k < kTile; k += r)
-          mono(tile[k], xi, yi, zi, eps2, tx, ty, tz, tp);
-      }
-      ax += tx;
-      ay += ty;
-      az += tz;
-      ph += tp;
+      const int valid = nl - tb < (uint32_t)T ? (int)(nl - tb) : T;
+      const int hi = blk1 < valid ? blk1 : valid;
+      const int cnt = hi > blk0 ? hi - blk0 : 0;
+      slice_sum<1>(tile + blk0, nullptr, cnt, xi, yi, zi, eps2, ax, ay, az,
+                   ph);
     }
   }
   if (ORDER == 2) {
-    for (uint64_t tb = 0; tb < ns; tb += kTile) {
-      const uint64_t q = tb + lane;
-      float4 jd = make_float4(0.f, 0.f, 0.f, 0.f);
-      float4 qa = make_float4(0.f, 0.f, 0.f, 0.f);
-      float4 qb = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (q < ns) {
-        const uint32_t cc = spj[s0 + q];
-        const double4 P = pm[cc];
-        jd = make_float4((float)(P.x - cg.x), (float)(P.y - cg.y),
-                         (float)(P.z - cg.z), (float)P.w);
-        qa = quad[2 * (int64_t)cc];
-        qb = quad[2 * (int64_t)cc + 1];
-        qb.z = qa.x + qa.y + qa.z;
+    for (uint32_t tb = 0; tb < ns; tb += (uint32_t)T) {
+      uint32_t cid[kMaxSlices];
+#pragma unroll
+      for (int u = 0; u < kMaxSlices; ++u) {
+        const uint32_t e = tb + (uint32_t)(u * kTile + lane);
+        cid[u] = (u < q && e < ns) ? idb[e] : kNone;
       }
       __syncthreads();
-      tile[lane] = jd;
-      tq[2 * lane] = qa;
-      tq[2 * lane + 1] = qb;
+#pragma unroll
+      for (int u = 0; u < kMaxSlices; ++u) {
+        if (u < q) {
+          float4 jd = make_float4(0.f, 0.f, 0.f, 0.f);
+          float4 qa = make_float4(0.f, 0.f, 0.f, 0.f);
+          float4 qb = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (cid[u] != kNone) {
+            const double4 Q = pm[cid[u]];
+            jd = make_float4((float)(Q.x - cg.x), (float)(Q.y - cg.y),
+                             (float)(Q.z - cg.z), (float)Q.w);
+            qa = quad[2 * (int64_t)cid[u]];
+            qb = quad[2 * (int64_t)cid[u] + 1];
+            qb.z = qa.x + qa.y + qa.z;
+          }
+          const int slot = u * kTile + lane;
+          tile[slot] = jd;
+          tq[2 * slot] = qa;
+          tq[2 * slot + 1] = qb;
+        }
+      }
       __syncthreads();
       if (act) {
-        float tx = 0.f, ty = 0.f, tz = 0.f, tp = 0.f;
-        for (int k = sl; k < kTile; k += r)
-          quadr(tile[k], tq[2 * k], tq[2 * k + 1], xi, yi, zi, eps2, tx, ty,
-                tz, tp);
-        ax += tx;
-        ay += ty;
-        az += tz;
-        ph += tp;
+        const int valid = ns - tb < (uint32_t)T ? (int)(ns - tb) : T;
+        const int hi = blk1 < valid ? blk1 : valid;
+        const int cnt = hi > blk0 ? hi - blk0 : 0;
+        slice_sum<2>(tile + blk0, tq + 2 * blk0, cnt, xi, yi, zi, eps2, ax,
+                     ay, az, ph);
       }
     }
   }
@@ -212,7 +279,7 @@ int launch_force(nb_ctx* c) {
   auto k = c->cfg.order == 2 ? k_force<2> : k_force<1>;
   hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kTile), 0, c->stream,
                      (const uint4*)c->wi.p, c->n_wi, per_xcd,
-                     (const uint32_t*)c->g_cell.p, (const double4*)c->c_geo.p,
+                     (const uint32_t*)c->g_cell.p, (const CellRec*)c->c_rec.p,
                      (const uint64_t*)c->epj_off.p, (const uint32_t*)c->epj.p,
                      (const uint64_t*)c->spj_off.p, (const uint32_t*)c->spj.p,
                      (const double4*)c->pos.p, (const double4*)c->c_pm.p,

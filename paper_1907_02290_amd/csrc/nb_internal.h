@@ -25,6 +25,17 @@ struct Root {
   int32_t bad;             // non-zero: a non-finite coordinate was seen
 };
 
+// One tree cell, 64-byte aligned so that a walk visit touches one line.
+//   geo  = geometric centre (x, y, z) and (side / theta)^2 of its level
+//   meta = first particle, one past the last, id after the subtree,
+//          level | leaf << 8
+//   aux  = parent id (kNone for the root), unused x3
+struct __attribute__((aligned(64))) CellRec {
+  double4 geo;
+  uint4 meta;
+  uint4 aux;
+};
+
 // A device buffer that only grows.
 template <class T>
 struct DBuf {
@@ -51,8 +62,9 @@ struct nb_ctx {
   int64_t n_epj = 0, n_spj = 0, n_inter = 0;
   int64_t force_evals = 0, total_inter = 0;
   int32_t k = 0;
-  // internal cells per level (construction order: deepest level first)
-  int64_t lvl_count[nb::kLevels] = {0};
+  // internal cells per level and where each level starts in lvl_cells;
+  // index kLevels holds the leaves
+  int64_t lvl_count[nb::kLevels + 1] = {0};
   int64_t lvl_off[nb::kLevels + 1] = {0};
 
   // state machine
@@ -82,14 +94,12 @@ struct nb_ctx {
   nb::DBuf<uint32_t> cstart;  // cells starting at each particle -> scanned
 
   // cells (DFS pre-order)
-  nb::DBuf<uint4> c_meta;    // begin, end, skip, level | leaf << 8
-  nb::DBuf<uint32_t> c_parent;
-  nb::DBuf<double4> c_geo;   // geometric centre xyz, rcrit2 of the level
+  nb::DBuf<nb::CellRec> c_rec;
   nb::DBuf<float4> c_mom;    // COM offset from the centre (FP32), mass
   nb::DBuf<float4> c_quad;   // 2 per cell: xx yy zz xy | xz yz 0 0
   nb::DBuf<double4> c_pm;    // absolute COM (FP64) and mass: SPJ record
-  nb::DBuf<uint32_t> lvl_cells;  // leaves first, then internal by level
-  nb::DBuf<uint32_t> lvl_cnt;    // device histogram, kLevels + 1
+  nb::DBuf<uint32_t> lvl_cells;  // cell ids grouped by level, leaves last
+  nb::DBuf<uint32_t> bucket;     // per-block level histograms, scanned
 
   // groups
   nb::DBuf<uint32_t> gflag;  // n_cell + 1, scanned
@@ -99,9 +109,9 @@ struct nb_ctx {
   nb::DBuf<uint4> wi;           // force work items: group, first, count
 
   // lists
-  nb::DBuf<uint32_t> cnt_e, cnt_s;
-  nb::DBuf<uint64_t> epj_off, spj_off;
-  nb::DBuf<uint32_t> epj, spj;
+  nb::DBuf<uint32_t> cnt_e, cnt_s, cnt_t;
+  nb::DBuf<uint64_t> epj_off, spj_off, tok_off;
+  nb::DBuf<uint32_t> epj, spj, tok;  // tok: walk tokens per group
 
   // scan / reduction scratch
   nb::DBuf<uint64_t> scan_tmp;
@@ -164,7 +174,7 @@ int launch_keys(nb_ctx* c);
 int launch_reorder(nb_ctx* c);
 int launch_link_count(nb_ctx* c);
 int launch_link_fill(nb_ctx* c);
-int launch_level_lists(nb_ctx* c);
+int launch_level_lists(nb_ctx* c);  // enqueues; no host sync
 int launch_moments(nb_ctx* c);
 int launch_group_flags(nb_ctx* c);
 int launch_group_fill(nb_ctx* c);

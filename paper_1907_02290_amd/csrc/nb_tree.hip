@@ -106,23 +106,48 @@ k_bbox_partial(const double4* __restrict__ pos, int64_t n,
 
 // rr = (1/theta)*(1/theta) from the host: (2^e/theta)^2 rounds to
 // 2^(2e) * rr exactly, so rcrit2[l] = ldexp(rr, 2(k - l)).
-__global__ void k_bbox_final(const double* __restrict__ part, int nb,
-                             double rr, Root* __restrict__ root) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block of 256 threads reduces the per-block partials (min / max are
+// exact, so the reduction order does not matter).
+__global__ void __launch_bounds__(kBboxThreads)
+k_bbox_final(const double* __restrict__ part, int nb, double rr,
+             Root* __restrict__ root) {
+  __shared__ double s[kBboxThreads / 64][7];
   double mn[3] = {INFINITY, INFINITY, INFINITY};
   double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
   double bad = 0.0;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = threadIdx.x; b < nb; b += kBboxThreads) {
     for (int a = 0; a < 3; ++a) {
       mn[a] = fmin(mn[a], part[b * 8 + a]);
       mx[a] = fmax(mx[a], part[b * 8 + 3 + a]);
     }
     bad = fmax(bad, part[b * 8 + 6]);
   }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int a = 0; a < 3; ++a) {
+    mn[a] = wave_min(mn[a]);
+    mx[a] = wave_max(mx[a]);
+  }
+  bad = wave_max(bad);
+  if (lane == 0) {
+    for (int a = 0; a < 3; ++a) {
+      s[w][a] = mn[a];
+      s[w][3 + a] = mx[a];
+    }
+    s[w][6] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int q = 1; q < kBboxThreads / 64; ++q) {
+    for (int a = 0; a < 3; ++a) {
+      s[0][a] = fmin(s[0][a], s[q][a]);
+      s[0][3 + a] = fmax(s[0][3 + a], s[q][3 + a]);
+    }
+    s[0][6] = fmax(s[0][6], s[q][6]);
+  }
   double ext = 0.0;
   for (int a = 0; a < 3; ++a) {
-    root->lo[a] = mn[a];
-    const double e = mx[a] - mn[a];
+    root->lo[a] = s[0][a];
+    const double e = s[0][3 + a] - s[0][a];
     if (e > ext) ext = e;
   }
   int k = 0;
@@ -132,7 +157,7 @@ __global__ void k_bbox_final(const double* __restrict__ part, int nb,
     while (ldexp(1.0, k - 1) > ext) k--;
   }
   root->k = k;
-  root->bad = (bad != 0.0 || !isfinite(ext)) ? 1 : 0;
+  root->bad = (s[0][6] != 0.0 || !isfinite(ext)) ? 1 : 0;
   for (int l = 0; l < kLevels; ++l) root->rcrit2[l] = ldexp(rr, 2 * (k - l));
 }
 
@@ -262,8 +287,7 @@ __global__ void __launch_bounds__(256)
 k_link_fill(const uint64_t* __restrict__ key, int64_t n,
             const uint8_t* __restrict__ lam, const uint8_t* __restrict__ lmin,
             const uint32_t* __restrict__ S, const Root* __restrict__ root,
-            uint4* __restrict__ meta, uint32_t* __restrict__ parent,
-            double4* __restrict__ geo) {
+            CellRec* __restrict__ rec) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int la = lam[i], lm = lmin[i];
@@ -288,68 +312,121 @@ k_link_fill(const uint64_t* __restrict__ key, int64_t n,
       par = S[b] + (uint32_t)((l - 1) - (int)lmin[b]);
     }
     const uint32_t skip = S[end];
-    meta[id] = make_uint4((uint32_t)i, (uint32_t)end, skip,
-                          (uint32_t)l | (l == la ? 256u : 0u));
-    parent[id] = par;
     // geometric centre: lo + (2q + 1) * 2^(k - l - 1)
     const double half = ldexp(1.0, k - l - 1);
     const uint32_t qx = compact3(pre >> 2), qy = compact3(pre >> 1),
                    qz = compact3(pre);
-    double4 gc;
-    gc.x = __dadd_rn(root->lo[0], __dmul_rn(2.0 * (double)qx + 1.0, half));
-    gc.y = __dadd_rn(root->lo[1], __dmul_rn(2.0 * (double)qy + 1.0, half));
-    gc.z = __dadd_rn(root->lo[2], __dmul_rn(2.0 * (double)qz + 1.0, half));
-    gc.w = root->rcrit2[l];
-    geo[id] = gc;
+    CellRec r;
+    r.geo.x = __dadd_rn(root->lo[0], __dmul_rn(2.0 * (double)qx + 1.0, half));
+    r.geo.y = __dadd_rn(root->lo[1], __dmul_rn(2.0 * (double)qy + 1.0, half));
+    r.geo.z = __dadd_rn(root->lo[2], __dmul_rn(2.0 * (double)qz + 1.0, half));
+    r.geo.w = root->rcrit2[l];
+    r.meta = make_uint4((uint32_t)i, (uint32_t)end, skip,
+                        (uint32_t)l | (l == la ? 256u : 0u));
+    r.aux = make_uint4(par, 0u, 0u, 0u);
+    rec[id] = r;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Groups (Barnes' vectorisation): a cell holding at most n_grp particles (or
-// a leaf) whose parent holds more than n_grp.  Also the level histogram of
-// internal cells (bucket kLevels holds the leaves).
+// a leaf) whose parent holds more than n_grp.
 __global__ void __launch_bounds__(256)
-k_group_flags(int64_t n_cell, const uint4* __restrict__ meta,
-              const uint32_t* __restrict__ parent, int n_grp,
-              uint32_t* __restrict__ gflag, uint32_t* __restrict__ lvl_cnt) {
+k_group_flags(int64_t n_cell, const CellRec* __restrict__ rec, int n_grp,
+              uint32_t* __restrict__ gflag) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_cell) return;
-  const uint4 m = meta[c];
+  const uint4 m = rec[c].meta;
   const uint32_t cnt = m.y - m.x;
   const bool leaf = (m.w >> 8) & 1u;
   bool top = true;
   if (c != 0) {
-    const uint4 pm = meta[parent[c]];
+    const uint4 pm = rec[rec[c].aux.x].meta;
     top = (pm.y - pm.x) > (uint32_t)n_grp;
   }
   gflag[c] = ((cnt <= (uint32_t)n_grp || leaf) && top) ? 1u : 0u;
-  atomicAdd(&lvl_cnt[leaf ? kLevels : (m.w & 255u)], 1u);
 }
 
-__global__ void __launch_bounds__(256)
-k_level_scatter(int64_t n_cell, const uint4* __restrict__ meta,
-                uint32_t* __restrict__ cursor, uint32_t* __restrict__ out) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cell) return;
-  const uint32_t w = meta[c].w;
-  const uint32_t b = ((w >> 8) & 1u) ? (uint32_t)kLevels : (w & 255u);
-  out[atomicAdd(&cursor[b], 1u)] = (uint32_t)c;
+// Cells grouped by level (bucket kLevels = leaves) with a counting sort:
+// per-block histograms in LDS, a scan over (bucket, block), then a scatter.
+// The order inside a bucket is irrelevant: each cell's moments only need
+// its children, which sit one level deeper.
+constexpr int kBuckets = kLevels + 1;
+constexpr int kBkThreads = 256;
+constexpr int kBkItems = 4;
+constexpr int kBkTile = kBkThreads * kBkItems;
+
+__device__ inline uint32_t bucket_of(uint32_t w) {
+  return ((w >> 8) & 1u) ? (uint32_t)kLevels : (w & 255u);
 }
+
+__global__ void __launch_bounds__(kBkThreads)
+k_bucket_hist(int64_t n_cell, const CellRec* __restrict__ rec,
+              uint32_t* __restrict__ hist, int nblk) {
+  __shared__ uint32_t h[kBuckets];
+  if (threadIdx.x < kBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kBkItems; ++j) {
+    const int64_t c = (int64_t)blockIdx.x * kBkTile + j * kBkThreads + threadIdx.x;
+    if (c < n_cell) atomicAdd(&h[bucket_of(rec[c].meta.w)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBuckets)
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kBkThreads)
+k_bucket_scatter(int64_t n_cell, const CellRec* __restrict__ rec,
+                 const uint32_t* __restrict__ hist, int nblk,
+                 uint32_t* __restrict__ out) {
+  __shared__ uint32_t base[kBuckets];
+  __shared__ uint32_t cnt[kBuckets];
+  if (threadIdx.x < kBuckets) {
+    base[threadIdx.x] = hist[(int64_t)threadIdx.x * nblk + blockIdx.x];
+    cnt[threadIdx.x] = 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kBkItems; ++j) {
+    const int64_t c = (int64_t)blockIdx.x * kBkTile + j * kBkThreads + threadIdx.x;
+    if (c < n_cell) {
+      const uint32_t b = bucket_of(rec[c].meta.w);
+      out[base[b] + atomicAdd(&cnt[b], 1u)] = (uint32_t)c;
+    }
+  }
+}
+
+// Bucket starts and the group count, gathered for one host read.
+__global__ void k_bucket_starts(const uint32_t* __restrict__ hist, int nblk,
+                                const uint32_t* __restrict__ gflag,
+                                int64_t n_cell, uint32_t* __restrict__ out) {
+  const int t = threadIdx.x;
+  if (t < kBuckets) out[t] = hist[(int64_t)t * nblk];
+  if (t == kBuckets) out[t] = gflag[n_cell];
+}
+
+// Chunks of a group for the force kernel: whole 64-particle chunks, then the
+// remainder split as the table says (see chunk_table()).
+struct ChunkTable {
+  uint32_t e[64];  // remainder n: count << 24 | size0 | size1 << 8 | size2 << 16
+};
 
 __global__ void __launch_bounds__(256)
 k_group_fill(int64_t n_cell, const uint32_t* __restrict__ gscan,
-             const uint4* __restrict__ meta, uint32_t* __restrict__ g_cell,
-             uint32_t* __restrict__ g_begin, uint32_t* __restrict__ g_count,
-             uint32_t* __restrict__ chunks) {
+             const CellRec* __restrict__ rec, ChunkTable tab,
+             uint32_t* __restrict__ g_cell, uint32_t* __restrict__ g_begin,
+             uint32_t* __restrict__ g_count, uint32_t* __restrict__ chunks) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n_cell) return;
   const uint32_t g = gscan[c];
   if (gscan[c + 1] == g) return;
-  const uint4 m = meta[c];
+  const uint4 m = rec[c].meta;
+  const uint32_t n = m.y - m.x;
   g_cell[g] = (uint32_t)c;
   g_begin[g] = m.x;
-  g_count[g] = m.y - m.x;
-  chunks[g] = (m.y - m.x + 63u) / 64u;
+  g_count[g] = n;
+  chunks[g] = n / 64u + (tab.e[n % 64u] >> 24);
 }
 
 // One wave per group: exact FP64 min / max of the member positions.
@@ -385,15 +462,20 @@ k_group_box(int64_t n_groups, const uint32_t* __restrict__ g_begin,
 
 __global__ void __launch_bounds__(256)
 k_make_wi(int64_t n_groups, const uint32_t* __restrict__ g_begin,
-          const uint32_t* __restrict__ g_count,
+          const uint32_t* __restrict__ g_count, ChunkTable tab,
           const uint32_t* __restrict__ choff, uint4* __restrict__ wi) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_groups) return;
-  const uint32_t b = g_begin[g], cnt = g_count[g];
+  uint32_t b = g_begin[g];
+  const uint32_t cnt = g_count[g];
   uint32_t o = choff[g];
-  for (uint32_t s = 0; s < cnt; s += 64, ++o) {
-    const uint32_t len = cnt - s < 64u ? cnt - s : 64u;
-    wi[o] = make_uint4((uint32_t)g, b + s, len, 0u);
+  for (uint32_t s = 0; s + 64u <= cnt; s += 64u, ++o, b += 64u)
+    wi[o] = make_uint4((uint32_t)g, b, 64u, 0u);
+  const uint32_t t = tab.e[cnt % 64u];
+  for (uint32_t k = 0; k < (t >> 24); ++k, ++o) {
+    const uint32_t len = (t >> (8 * k)) & 255u;
+    wi[o] = make_uint4((uint32_t)g, b, len, 0u);
+    b += len;
   }
 }
 
@@ -405,14 +487,14 @@ k_make_wi(int64_t n_groups, const uint32_t* __restrict__ g_begin,
 template <bool QUAD>
 __global__ void __launch_bounds__(256)
 k_mom_leaf(int64_t cnt, const uint32_t* __restrict__ list,
-           const uint4* __restrict__ meta, const double4* __restrict__ geo,
-           const double4* __restrict__ pos, float4* __restrict__ mom,
-           float4* __restrict__ quad, double4* __restrict__ pm) {
+           const CellRec* __restrict__ rec, const double4* __restrict__ pos,
+           float4* __restrict__ mom, float4* __restrict__ quad,
+           double4* __restrict__ pm) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cnt) return;
   const uint32_t c = list[t];
-  const uint4 m = meta[c];
-  const double4 g = geo[c];
+  const uint4 m = rec[c].meta;
+  const double4 g = rec[c].geo;
   float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
   for (uint32_t p = m.x; p < m.y; ++p) {
     const double4 P = pos[p];
@@ -449,27 +531,26 @@ k_mom_leaf(int64_t cnt, const uint32_t* __restrict__ list,
 }
 
 // Next sibling; a skip id that does not advance ends the loop.
-__device__ inline uint32_t next_child(const uint4* __restrict__ meta,
+__device__ inline uint32_t next_child(const CellRec* __restrict__ rec,
                                       uint32_t k, uint32_t stop) {
-  const uint32_t s = meta[k].z;
+  const uint32_t s = rec[k].meta.z;
   return s > k ? s : stop;
 }
 
 template <bool QUAD>
 __global__ void __launch_bounds__(256)
 k_mom_internal(int64_t cnt, const uint32_t* __restrict__ list,
-               const uint4* __restrict__ meta,
-               const double4* __restrict__ geo, float4* __restrict__ mom,
+               const CellRec* __restrict__ rec, float4* __restrict__ mom,
                float4* __restrict__ quad, double4* __restrict__ pm) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cnt) return;
   const uint32_t c = list[t];
-  const uint32_t stop = meta[c].z;
-  const double4 g = geo[c];
+  const uint32_t stop = rec[c].meta.z;
+  const double4 g = rec[c].geo;
   float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-  for (uint32_t k = c + 1; k < stop; k = next_child(meta, k, stop)) {
+  for (uint32_t k = c + 1; k < stop; k = next_child(rec, k, stop)) {
     const float4 mk = mom[k];
-    const double4 gk = geo[k];
+    const double4 gk = rec[k].geo;
     const float dx = (float)(gk.x - g.x) + mk.x;
     const float dy = (float)(gk.y - g.y) + mk.y;
     const float dz = (float)(gk.z - g.z) + mk.z;
@@ -485,9 +566,9 @@ k_mom_internal(int64_t cnt, const uint32_t* __restrict__ list,
                        (double)M);
   if (QUAD) {
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
-    for (uint32_t k = c + 1; k < stop; k = next_child(meta, k, stop)) {
+    for (uint32_t k = c + 1; k < stop; k = next_child(rec, k, stop)) {
       const float4 mk = mom[k];
-      const double4 gk = geo[k];
+      const double4 gk = rec[k].geo;
       const float4 qa = quad[2 * (int64_t)k];
       const float4 qb = quad[2 * (int64_t)k + 1];
       const float dx = (float)(gk.x - g.x) + mk.x - ox;
@@ -519,7 +600,7 @@ int launch_root(nb_ctx* c) {
                      c->bbox_part.p);
   const double r1 = 1.0 / c->cfg.theta;
   const double rr = r1 * r1;
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, c->stream,
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBboxThreads), 0, c->stream,
                      (const double*)c->bbox_part.p, nb, rr, c->root.p);
   return hip_check(c, hipGetLastError(), "root launch");
 }
@@ -571,56 +652,51 @@ int launch_link_count(nb_ctx* c) {
 }
 
 int launch_link_fill(nb_ctx* c) {
-  const size_t nc = (size_t)c->n_cell;
-  int rc = reserve(c, c->c_meta, nc);
-  if (!rc) rc = reserve(c, c->c_parent, nc);
-  if (!rc) rc = reserve(c, c->c_geo, nc);
+  int rc = reserve(c, c->c_rec, (size_t)c->n_cell);
   if (rc) return rc;
   hipLaunchKernelGGL(k_link_fill, dim3(grid_for(c->n, 256)), dim3(256), 0,
                      c->stream, (const uint64_t*)c->key.p, c->n,
                      (const uint8_t*)c->lam.p, (const uint8_t*)c->lmin.p,
                      (const uint32_t*)c->cstart.p, (const Root*)c->root.p,
-                     c->c_meta.p, c->c_parent.p, c->c_geo.p);
+                     c->c_rec.p);
   return hip_check(c, hipGetLastError(), "link fill launch");
 }
 
-// Group flags + level histogram, then the scan of the flags.  The host reads
-// the histogram and the group count afterwards.
+// Group flags and their scan.
 int launch_group_flags(nb_ctx* c) {
-  const size_t nc = (size_t)c->n_cell;
-  int rc = reserve(c, c->gflag, nc + 1);
-  if (!rc) rc = reserve(c, c->lvl_cnt, kLevels + 1);
-  if (rc) return rc;
-  rc = fill_u32(c, c->lvl_cnt.p, kLevels + 1, 0u);
+  int rc = reserve(c, c->gflag, (size_t)c->n_cell + 1);
   if (rc) return rc;
   hipLaunchKernelGGL(k_group_flags, dim3(grid_for(c->n_cell, 256)), dim3(256),
-                     0, c->stream, c->n_cell, (const uint4*)c->c_meta.p,
-                     (const uint32_t*)c->c_parent.p, (int)c->cfg.n_grp,
-                     c->gflag.p, c->lvl_cnt.p);
+                     0, c->stream, c->n_cell, (const CellRec*)c->c_rec.p,
+                     (int)c->cfg.n_grp, c->gflag.p);
   rc = hip_check(c, hipGetLastError(), "group flags launch");
   if (rc) return rc;
   return scan_u32(c, c->gflag.p, c->gflag.p, c->n_cell);
 }
 
-// Needs c->lvl_off filled by the host (leaves first, then levels 20..0).
+// Level lists by counting sort; also stages the bucket starts and the group
+// count in c->red (as u32) for the host to read.
 int launch_level_lists(nb_ctx* c) {
+  const int nblk = (int)grid_for(c->n_cell, kBkTile);
   int rc = reserve(c, c->lvl_cells, (size_t)c->n_cell);
+  if (!rc) rc = reserve(c, c->bucket, (size_t)kBuckets * nblk + 1);
+  if (!rc) rc = reserve(c, c->red, 16);
   if (rc) return rc;
-  uint32_t* h = static_cast<uint32_t*>(c->h_small);
-  for (int l = 0; l < kLevels; ++l) h[l] = (uint32_t)c->lvl_off[l];
-  h[kLevels] = 0;  // leaves start the list
-  rc = hip_check(c, hipMemcpyAsync(c->lvl_cnt.p, h,
-                                   (kLevels + 1) * sizeof(uint32_t),
-                                   hipMemcpyHostToDevice, c->stream),
-                 "level cursor upload");
+  hipLaunchKernelGGL(k_bucket_hist, dim3(nblk), dim3(kBkThreads), 0,
+                     c->stream, c->n_cell, (const CellRec*)c->c_rec.p,
+                     c->bucket.p, nblk);
+  rc = hip_check(c, hipGetLastError(), "bucket launch");
   if (rc) return rc;
-  hipLaunchKernelGGL(k_level_scatter, dim3(grid_for(c->n_cell, 256)),
-                     dim3(256), 0, c->stream, c->n_cell,
-                     (const uint4*)c->c_meta.p, c->lvl_cnt.p, c->lvl_cells.p);
-  // the staging buffer is reused by later calls: wait for the copy
-  rc = hip_check(c, hipStreamSynchronize(c->stream), "level cursor sync");
+  rc = scan_u32(c, c->bucket.p, c->bucket.p, (int64_t)kBuckets * nblk);
   if (rc) return rc;
-  return hip_check(c, hipGetLastError(), "level scatter launch");
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(nblk), dim3(kBkThreads), 0,
+                     c->stream, c->n_cell, (const CellRec*)c->c_rec.p,
+                     (const uint32_t*)c->bucket.p, nblk, c->lvl_cells.p);
+  hipLaunchKernelGGL(k_bucket_starts, dim3(1), dim3(64), 0, c->stream,
+                     (const uint32_t*)c->bucket.p, nblk,
+                     (const uint32_t*)c->gflag.p, c->n_cell,
+                     reinterpret_cast<uint32_t*>(c->red.p));
+  return hip_check(c, hipGetLastError(), "bucket scatter launch");
 }
 
 int launch_moments(nb_ctx* c) {
@@ -634,23 +710,58 @@ int launch_moments(nb_ctx* c) {
   auto inner = quad ? k_mom_internal<true> : k_mom_internal<false>;
   if (c->n_leaves > 0)
     hipLaunchKernelGGL(leaf, dim3(grid_for(c->n_leaves, 256)), dim3(256), 0,
-                       c->stream, c->n_leaves, (const uint32_t*)c->lvl_cells.p,
-                       (const uint4*)c->c_meta.p, (const double4*)c->c_geo.p,
-                       (const double4*)c->pos.p, c->c_mom.p, c->c_quad.p,
-                       c->c_pm.p);
+                       c->stream, c->n_leaves,
+                       (const uint32_t*)c->lvl_cells.p + c->lvl_off[kLevels],
+                       (const CellRec*)c->c_rec.p, (const double4*)c->pos.p,
+                       c->c_mom.p, c->c_quad.p, c->c_pm.p);
   for (int l = kMaxLevel - 1; l >= 0; --l) {
     const int64_t cnt = c->lvl_count[l];
     if (cnt == 0) continue;
     hipLaunchKernelGGL(inner, dim3(grid_for(cnt, 256)), dim3(256), 0,
                        c->stream, cnt,
                        (const uint32_t*)c->lvl_cells.p + c->lvl_off[l],
-                       (const uint4*)c->c_meta.p, (const double4*)c->c_geo.p,
-                       c->c_mom.p, c->c_quad.p, c->c_pm.p);
+                       (const CellRec*)c->c_rec.p, c->c_mom.p, c->c_quad.p,
+                       c->c_pm.p);
   }
   return hip_check(c, hipGetLastError(), "moments launch");
 }
 
+// How to split the last n < 64 particles of a group into work items.  A
+// chunk of s particles runs on r = 64 / s lane slices, so a list entry
+// costs about 14 / r vector instructions plus a fixed share for staging it
+// in LDS; the split minimises the sum (dynamic programming over n).  For
+// example 40 -> 8 + 32, 33 -> 1 + 32, 63 -> 63.
+static ChunkTable chunk_table() {
+  ChunkTable t;
+  const double stage = 0.5;
+  double best[64];
+  int pick[64];
+  best[0] = 0.0;
+  pick[0] = 0;
+  for (int n = 1; n < 64; ++n) {
+    best[n] = 1e30;
+    pick[n] = n;
+    for (int s = 1; s <= n; ++s) {
+      const double cst = 14.0 / (64 / s) + stage + best[n - s];
+      if (cst < best[n] - 1e-12) {
+        best[n] = cst;
+        pick[n] = s;
+      }
+    }
+  }
+  t.e[0] = 0;
+  for (int n = 1; n < 64; ++n) {
+    uint32_t e = 0, cnt = 0;
+    int r = n;
+    for (; r > 0 && cnt < 3; r -= pick[r]) e |= (uint32_t)pick[r] << (8 * cnt++);
+    // the chunks must cover all n particles; otherwise keep one chunk
+    t.e[n] = r == 0 ? (e | cnt << 24) : ((uint32_t)n | 1u << 24);
+  }
+  return t;
+}
+
 int launch_group_fill(nb_ctx* c) {
+  static const ChunkTable tab = chunk_table();
   const size_t ng = (size_t)c->n_groups;
   int rc = reserve(c, c->g_cell, ng);
   if (!rc) rc = reserve(c, c->g_begin, ng);
@@ -658,12 +769,12 @@ int launch_group_fill(nb_ctx* c) {
   if (!rc) rc = reserve(c, c->g_lo, ng);
   if (!rc) rc = reserve(c, c->g_hi, ng);
   if (!rc) rc = reserve(c, c->g_chunks, ng + 1);
-  if (!rc) rc = reserve(c, c->wi, ng + (size_t)c->n / 64 + 1);
+  if (!rc) rc = reserve(c, c->wi, 3 * ng + (size_t)c->n / 64 + 1);
   if (rc) return rc;
   hipLaunchKernelGGL(k_group_fill, dim3(grid_for(c->n_cell, 256)), dim3(256),
                      0, c->stream, c->n_cell, (const uint32_t*)c->gflag.p,
-                     (const uint4*)c->c_meta.p, c->g_cell.p, c->g_begin.p,
-                     c->g_count.p, c->g_chunks.p);
+                     (const CellRec*)c->c_rec.p, tab, c->g_cell.p,
+                     c->g_begin.p, c->g_count.p, c->g_chunks.p);
   hipLaunchKernelGGL(k_group_box, dim3(grid_for(c->n_groups, 4)), dim3(256),
                      0, c->stream, c->n_groups, (const uint32_t*)c->g_begin.p,
                      (const uint32_t*)c->g_count.p, (const double4*)c->pos.p,
@@ -674,7 +785,7 @@ int launch_group_fill(nb_ctx* c) {
   if (rc) return rc;
   hipLaunchKernelGGL(k_make_wi, dim3(grid_for(c->n_groups, 256)), dim3(256),
                      0, c->stream, c->n_groups, (const uint32_t*)c->g_begin.p,
-                     (const uint32_t*)c->g_count.p,
+                     (const uint32_t*)c->g_count.p, tab,
                      (const uint32_t*)c->g_chunks.p, c->wi.p);
   return hip_check(c, hipGetLastError(), "work item launch");
 }

@@ -9,44 +9,70 @@
 // with (side / theta)^2 in FP64, evaluated term by term (no fused
 // multiply-add: this file is built with -ffp-contract=off and uses explicit
 // rounding intrinsics), so that lists are bit-identical to an FP64 reference.
-// A cell whose particle range holds the group is always opened.  A count
-// pass, an exclusive scan and a fill pass make the CSR lists without
-// atomics; ids come out in ascending order.
+// A cell whose particle range holds the group is always opened.
+//
+// Count pass, exclusive scans, fill pass: no atomics, ids in ascending
+// order.  The fill pass writes one token per accepted cell (SPJ) or opened
+// leaf, in walk order, staged per lane in LDS and written out in aligned
+// 64-byte segments; a second kernel, one wave per group, splits the tokens
+// into the SPJ list and the particle ids (EPJ) of the opened leaves, with
+// whole wavefronts writing contiguous stretches.
+// Workgroups are remapped so that each XCD walks a contiguous stretch of
+// groups (Morton order), whose tree paths share that XCD's L2.
 #include "nb_internal.h"
 
 namespace nb {
 namespace {
 
+constexpr int kWalkThreads = 256;
+
+__device__ inline int64_t xcd_block(int64_t nblk) {
+  const int64_t per = (nblk + 7) / 8;
+  return (int64_t)(blockIdx.x & 7u) * per + (int64_t)(blockIdx.x >> 3);
+}
+
+// Tokens of the fill pass: an accepted cell (SPJ) is its id, an opened
+// leaf is its id with the top bit set.
+constexpr uint32_t kLeafTag = 0x80000000u;
+constexpr int kSeg = 16;  // tokens per 64-byte output segment
+
 template <bool FILL>
-__global__ void __launch_bounds__(256)
-k_walk(int64_t n_groups, int64_t n_cell, const uint32_t* __restrict__ g_begin,
+__global__ void __launch_bounds__(kWalkThreads)
+k_walk(int64_t n_groups, int64_t nblk, int64_t n_cell,
+       const uint32_t* __restrict__ g_begin,
        const uint32_t* __restrict__ g_count, const double4* __restrict__ g_lo,
-       const double4* __restrict__ g_hi, const uint4* __restrict__ meta,
-       const double4* __restrict__ geo, uint32_t* __restrict__ cnt_e,
-       uint32_t* __restrict__ cnt_s, const uint64_t* __restrict__ epj_off,
-       const uint64_t* __restrict__ spj_off, uint32_t* __restrict__ epj,
-       uint32_t* __restrict__ spj) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+       const double4* __restrict__ g_hi, const CellRec* __restrict__ rec,
+       uint32_t* __restrict__ cnt_e, uint32_t* __restrict__ cnt_s,
+       uint32_t* __restrict__ cnt_t, const uint64_t* __restrict__ tok_off,
+       uint32_t* __restrict__ tok) {
+  // per-lane staging of the token stream: a lane writes its tokens out one
+  // aligned 64-byte segment at a time, so that partially written lines do
+  // not pile up in L2 (one open line per group otherwise)
+  __shared__ uint32_t stage[FILL ? kSeg : 1][kWalkThreads];
+  const int64_t blk = xcd_block(nblk);
+  if (blk >= nblk) return;
+  const int64_t g = blk * kWalkThreads + threadIdx.x;
   if (g >= n_groups) return;
   const uint32_t gb = g_begin[g];
   const uint32_t ge = gb + g_count[g];
   const double4 lo = g_lo[g], hi = g_hi[g];
-  uint32_t* pe = nullptr;
-  uint32_t* ps = nullptr;
+  uint32_t* dst = nullptr;
+  uint64_t out = 0;   // next output slot of this lane
+  int sc = 0;         // staged tokens
   if (FILL) {
-    pe = epj + epj_off[g];
-    ps = spj + spj_off[g];
+    out = tok_off[g];
+    dst = tok;
   }
-  uint32_t ne = 0, ns = 0;
+  uint32_t ne = 0, ns = 0, nl = 0;
   uint32_t c = 0;
   const uint32_t nc = (uint32_t)n_cell;
   while (c < nc) {
-    const uint4 m = meta[c];
+    const uint4 m = rec[c].meta;
+    const double4 cc = rec[c].geo;
     bool open;
     if (m.x <= gb && m.y >= ge) {
       open = true;
     } else {
-      const double4 cc = geo[c];
       double dx = 0.0, dy = 0.0, dz = 0.0, t;
       t = __dsub_rn(lo.x, cc.x);
       if (t > dx) dx = t;
@@ -60,27 +86,97 @@ k_walk(int64_t n_groups, int64_t n_cell, const uint32_t* __restrict__ g_begin,
       if (t > dz) dz = t;
       t = __dsub_rn(cc.z, hi.z);
       if (t > dz) dz = t;
-      const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
-                                  __dmul_rn(dz, dz));
+      const double d2 =
+          __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                    __dmul_rn(dz, dz));
       open = !(d2 > cc.w);
     }
+    const bool leaf = (m.w >> 8) & 1u;
     // skip ids always point past the cell; the guard keeps a damaged tree
     // from looping forever
-    const uint32_t next = (!open || ((m.w >> 8) & 1u)) ? m.z : c + 1;
+    const uint32_t next = (!open || leaf) ? m.z : c + 1;
     if (next <= c) break;
-    if (!open) {
-      if (FILL) ps[ns] = c;
-      ++ns;
-    } else if ((m.w >> 8) & 1u) {
-      if (FILL)
-        for (uint32_t j = m.x; j < m.y; ++j) pe[ne + (j - m.x)] = j;
-      ne += m.y - m.x;
+    if (!open || leaf) {
+      if (!open)
+        ++ns;
+      else {
+        ++nl;
+        ne += m.y - m.x;
+      }
+      if (FILL) {
+        stage[sc][threadIdx.x] = open ? (c | kLeafTag) : c;
+        ++sc;
+        if (((out + sc) & (kSeg - 1)) == 0) {
+          if (sc == kSeg) {
+            uint4* d4 = reinterpret_cast<uint4*>(dst + out);
+#pragma unroll
+            for (int q = 0; q < kSeg / 4; ++q)
+              d4[q] = make_uint4(stage[4 * q][threadIdx.x],
+                                 stage[4 * q + 1][threadIdx.x],
+                                 stage[4 * q + 2][threadIdx.x],
+                                 stage[4 * q + 3][threadIdx.x]);
+          } else {
+            for (int q = 0; q < sc; ++q) dst[out + q] = stage[q][threadIdx.x];
+          }
+          out += sc;
+          sc = 0;
+        }
+      }
     }
     c = next;
   }
-  if (!FILL) {
+  if (FILL) {
+    for (int q = 0; q < sc; ++q) dst[out + q] = stage[q][threadIdx.x];
+  } else {
     cnt_e[g] = ne;
     cnt_s[g] = ns;
+    cnt_t[g] = ns + nl;
+  }
+}
+
+// One wave per group: the token stream -> SPJ ids and EPJ particle ids.
+// Tokens are read in chunks of 64; accepted cells are compacted with a
+// ballot, opened leaves are expanded using a wave scan of their sizes, so
+// every chunk lands in contiguous stretches of both lists.
+__global__ void __launch_bounds__(256)
+k_expand(int64_t n_groups, int64_t nblk, const uint64_t* __restrict__ tok_off,
+         const uint32_t* __restrict__ tok, const CellRec* __restrict__ rec,
+         const uint64_t* __restrict__ epj_off,
+         const uint64_t* __restrict__ spj_off, uint32_t* __restrict__ epj,
+         uint32_t* __restrict__ spj) {
+  const int64_t blk = xcd_block(nblk);
+  if (blk >= nblk) return;
+  const int64_t g = blk * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= n_groups) return;
+  const uint64_t t0 = tok_off[g], t1 = tok_off[g + 1];
+  uint64_t oe = epj_off[g], os = spj_off[g];
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (uint64_t cb = t0; cb < t1; cb += 64) {
+    const uint64_t q = cb + lane;
+    const bool ok = q < t1;
+    const uint32_t tk = ok ? tok[q] : 0u;
+    const bool is_leaf = ok && (tk & kLeafTag);
+    const bool is_spj = ok && !(tk & kLeafTag);
+    const uint64_t sm = __ballot(is_spj);
+    if (is_spj) spj[os + __popcll(sm & lt)] = tk;
+    os += __popcll(sm);
+    uint32_t b = 0, n = 0;
+    if (is_leaf) {
+      const uint4 m = rec[tk & ~kLeafTag].meta;
+      b = m.x;
+      n = m.y - m.x;
+    }
+    uint32_t inc = n;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t t = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += t;
+    }
+    const uint32_t total = __shfl(inc, 63, 64);
+    uint32_t* dst = epj + oe + (inc - n);
+    for (uint32_t j = 0; j < n; ++j) dst[j] = b + j;
+    oe += total;
   }
 }
 
@@ -113,26 +209,42 @@ int launch_walk(nb_ctx* c, bool fill) {
   const size_t ng = (size_t)c->n_groups;
   int rc = reserve(c, c->cnt_e, ng);
   if (!rc) rc = reserve(c, c->cnt_s, ng);
+  if (!rc) rc = reserve(c, c->cnt_t, ng);
   if (!rc) rc = reserve(c, c->epj_off, ng + 1);
   if (!rc) rc = reserve(c, c->spj_off, ng + 1);
+  if (!rc) rc = reserve(c, c->tok_off, ng + 1);
   if (rc) return rc;
+  if (c->n_cell >= (int64_t)kLeafTag)
+    return set_err(c, NB_ERR_INPUT, "too many cells for 31-bit list tokens");
+  const int64_t nblk = grid_for(c->n_groups, kWalkThreads);
+  const int64_t launch = (nblk + 7) / 8 * 8;
   auto k = fill ? k_walk<true> : k_walk<false>;
-  hipLaunchKernelGGL(k, dim3(grid_for(c->n_groups, 256)), dim3(256), 0,
-                     c->stream, c->n_groups, c->n_cell,
+  hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
+                     c->stream, c->n_groups, nblk, c->n_cell,
                      (const uint32_t*)c->g_begin.p,
                      (const uint32_t*)c->g_count.p, (const double4*)c->g_lo.p,
-                     (const double4*)c->g_hi.p, (const uint4*)c->c_meta.p,
-                     (const double4*)c->c_geo.p, c->cnt_e.p, c->cnt_s.p,
+                     (const double4*)c->g_hi.p, (const CellRec*)c->c_rec.p,
+                     c->cnt_e.p, c->cnt_s.p, c->cnt_t.p,
+                     (const uint64_t*)c->tok_off.p, c->tok.p);
+  int rc2 = hip_check(c, hipGetLastError(), "walk launch");
+  if (rc2 || !fill) return rc2;
+  const int64_t eblk = grid_for(c->n_groups, 4);
+  const int64_t elaunch = (eblk + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_expand, dim3((unsigned)elaunch), dim3(256), 0,
+                     c->stream, c->n_groups, eblk,
+                     (const uint64_t*)c->tok_off.p,
+                     (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
                      (const uint64_t*)c->epj_off.p,
                      (const uint64_t*)c->spj_off.p, c->epj.p, c->spj.p);
-  return hip_check(c, hipGetLastError(), "walk launch");
+  return hip_check(c, hipGetLastError(), "expand launch");
 }
 
 // After the count pass: CSR offsets and the interaction count (red[0]).
 int launch_list_stats(nb_ctx* c) {
   int rc = scan_u32_to_u64(c, c->cnt_e.p, c->epj_off.p, c->n_groups);
   if (!rc) rc = scan_u32_to_u64(c, c->cnt_s.p, c->spj_off.p, c->n_groups);
-  if (!rc) rc = reserve(c, c->red, 8);
+  if (!rc) rc = scan_u32_to_u64(c, c->cnt_t.p, c->tok_off.p, c->n_groups);
+  if (!rc) rc = reserve(c, c->red, 16);
   if (rc) return rc;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream,
                      (unsigned long long*)c->red.p, 8);

@@ -58,6 +58,14 @@ def load():
         raise RuntimeError(
             "libnbody_hip.so is not built (%s); run __graft_entry__.build()"
             % LIB_PATH)
+    # PyTorch ships its own HIP runtime under the same soname as the one the
+    # library links.  Loading torch first makes the dynamic linker bind the
+    # library to torch's runtime, so the process holds a single HIP runtime
+    # and torch's streams and device pointers are valid in the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     p, i64, i32, d = C.c_void_p, C.c_int64, C.c_int, C.c_double
     sig = {

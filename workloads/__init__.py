@@ -215,7 +215,8 @@ def make(name, n=None, seed=None, replicate=0):
     plummer_4k   Plummer N=4096 (eps 1/64, theta 0.5, monopole, leaf 8, n_grp 64)
     plummer_1m   Plummer N=2^20 (eps 1/256, dt 1/128)
     disk_4m      disk 2^21 + halo 2^21 (eps 0.01, theta 0.5, lists reused
-                 every 4 steps, dt 1/128)
+                 every 4 steps, dt 1/128; n_grp 256, the fastest step of a
+                 sweep over 32..1024 on MI355X)
     ring_8m      ring N=2^23 (eps 1e-4, dt 2 pi/256, central mass 1)
     sphere_4m    cold uniform sphere N=2^22 (leaf 16)
     ``n`` overrides the particle count (same recipe, smaller system).
@@ -234,7 +235,7 @@ def make(name, n=None, seed=None, replicate=0):
         nn = n or (1 << 22)
         s = seed if seed is not None else seed_for(3, replicate)
         return disk_halo(nn // 2, nn - nn // 2, s), dict(
-            eps=0.01, theta=0.5, order=1, n_leaf=8, n_grp=64, dt=1.0 / 128,
+            eps=0.01, theta=0.5, order=1, n_leaf=8, n_grp=256, dt=1.0 / 128,
             reuse=4)
     if name == "ring_8m":
         nn = n or (1 << 23)
