@@ -31,6 +31,25 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector peak
 WORKLOAD = "disk_4m"
 
 
+def recorded_traffic():
+    """Force-kernel HBM bytes per launch from the committed counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1907_02290_amd", "csrc", "nb_force.hip")
+    prof = os.path.join(ROOT, "profiles", "disk_4m_hbm_counters.md")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch=([0-9.eE+-]+) source_sha256=(\w+)",
+                  text)
+    if not m or m.group(2) != sha:
+        return None
+    return float(m.group(1))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -46,7 +65,7 @@ def parse():
     ap.add_argument("--n-leaf", type=int, default=None)
     ap.add_argument("--reuse", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB "
                          "(reference kernel for HBM counters)")
@@ -227,6 +246,7 @@ def main():
             "mean_list": (info_last["n_epj"] + info_last["n_spj"]) /
                          max(info_last["n_groups"], 1),
             "force_evals": evals,
+            "force_work_items": info_last["n_wi"],
         },
         "roofline": {
             "kernel": "k_force (multiwalk force, monopole)",
@@ -235,7 +255,11 @@ def main():
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": (recorded_traffic()
+                        if args.workload == WORKLOAD and n_grp == 256 and
+                        args.n is None else None),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + "
+                            "WRITE_SIZE x 1.0, scaled on a 1 GiB copy)",
             "flops_per_launch": N_OP * inter_per_launch,
             "avg_launch_ms": f_avg_s * 1e3,
         },
