@@ -64,7 +64,9 @@ typedef struct nb_config {
   int32_t n_grp;   /* largest particle group sharing one list (section 3,
                       Barnes' vectorisation); 1..65536 */
   int32_t order;   /* superparticle expansion: 1 monopole, 2 quadrupole */
-  int32_t flags;   /* bit 0: record per-phase GPU timers (HIP events) */
+  int32_t flags;   /* bit 0: record per-phase GPU timers (HIP events);
+                      bit 1: run the reuse steps of nb_step from a captured
+                      HIP graph */
   void* stream;    /* hipStream_t to launch on; NULL = the library's own */
 } nb_config;
 
@@ -80,8 +82,11 @@ enum {
   NB_PH_WALK,      /* tree walk -> index interaction lists      */
   NB_PH_FORCE,     /* multiwalk force kernel                    */
   NB_PH_KICK,      /* kick-drift                                */
+  NB_PH_GRAPH,     /* a reuse step replayed from a HIP graph     */
   NB_PH_COUNT
 };
+
+enum { NB_FLAG_TIMING = 1, NB_FLAG_GRAPH = 2 };
 
 /* ---- lifetime --------------------------------------------------------- */
 
@@ -103,6 +108,15 @@ int nb_set_particles(nb_ctx* ctx, int64_t n, const double* x,
                      const double* y, const double* z, const double* vx,
                      const double* vy, const double* vz, const double* m,
                      int on_device);
+
+/* Split the particles into independent systems: system s is particles
+ * [off[s], off[s + 1]) of the original order (off holds n_sys + 1 values,
+ * off[0] = 0, off[n_sys] = n, every system non-empty).  Each system gets its
+ * own root cell, tree, groups and lists and feels only its own particles;
+ * all systems share every kernel launch.  nb_set_particles resets to one
+ * system.  Invalidates the tree and the lists.
+ * Errors: NB_ERR_STATE (no particles), NB_ERR_INPUT (bad offsets). */
+int nb_set_systems(nb_ctx* ctx, int64_t n_sys, const int64_t* off);
 
 /* ---- the step ----------------------------------------------------------
  * Construction step (section 4.3): root cell, Morton keys, radix sort,
@@ -134,6 +148,15 @@ int nb_compute_forces(nb_ctx* ctx, nb_mode mode);
  * Invalidates the tree for new lists; kept lists stay reusable. */
 int nb_kick_drift(nb_ctx* ctx, double dt_kick, double dt_drift);
 
+/* One leapfrog step: nb_kick_drift(dt_kick, dt_drift) then
+ * nb_compute_forces(mode).  With NB_FLAG_GRAPH, the first NB_REUSE_LIST step
+ * after a construction step captures kick-drift, moments and force kernel
+ * into a HIP graph on the context's stream, and later reuse steps with the
+ * same time steps replay it (one launch per step); a construction step, a
+ * new configuration or other time steps drop the graph.  Results are the
+ * same as without the flag.  Errors: those of the two calls. */
+int nb_step(nb_ctx* ctx, nb_mode mode, double dt_kick, double dt_drift);
+
 /* ---- readback (synchronises the stream) --------------------------------
  * internal = 0: original order; 1: internal (Morton) order. */
 int nb_get_forces(nb_ctx* ctx, double* ax, double* ay, double* az,
@@ -144,20 +167,24 @@ int nb_get_state(nb_ctx* ctx, double* x, double* y, double* z, double* vx,
 /* info[0] n, [1] cells, [2] groups, [3] EPJ entries, [4] SPJ entries,
  * [5] interactions of the current lists (sum over groups of
  * n_i * (n_epj + n_spj)), [6] force evaluations so far, [7] total
- * interactions evaluated so far, [8] root exponent k, [9] force work items.
- * info must hold 10 values. */
+ * interactions evaluated so far, [8] root exponent k of system 0, [9] force
+ * work items, [10] systems.  info must hold 11 values. */
 int nb_get_info(nb_ctx* ctx, int64_t* info);
 
-/* Root corner lo[3] and exponent k of the last tree (side 2^k). */
+/* Root corner lo[3] and exponent k of the last tree (side 2^k); with
+ * several systems, those of system 0. */
 int nb_get_root(nb_ctx* ctx, double* lo, int32_t* k);
+
+/* Root corners (3 per system) and exponents (1 per system). */
+int nb_get_roots(nb_ctx* ctx, double* lo3, int32_t* k);
 
 /* Sorted keys (n) and, for each sorted position, the ORIGINAL index of the
  * particle there (n). */
 int nb_get_keys(nb_ctx* ctx, uint64_t* key, uint32_t* orig);
 
-/* Cell arrays in DFS pre-order, each of length info[1]; any may be NULL.
- * parent of the root is 0xFFFFFFFF; skip = id after the subtree; ctr3 =
- * geometric centres (3 per cell). */
+/* Cell arrays in DFS pre-order (system after system), each of length
+ * info[1]; any may be NULL.  The parent of a root is 0xFFFFFFFF; skip = id
+ * after the subtree; ctr3 = geometric centres (3 per cell). */
 int nb_get_cells(nb_ctx* ctx, uint8_t* level, uint32_t* begin,
                  uint32_t* count, uint32_t* parent, uint32_t* skip,
                  uint8_t* leaf, double* ctr3);

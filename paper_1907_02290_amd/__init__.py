@@ -4,10 +4,11 @@ one multiwalk force launch and list reuse, after "Accelerated FDPS"
 package only binds it (``nbody``) and builds it (``_build``)."""
 from .nbody import (Context, NbError, NB_MAKE_LIST, NB_MAKE_LIST_FOR_REUSE,
                     NB_REUSE_LIST, NB_OK, NB_ERR_INPUT, NB_ERR_OOM,
-                    NB_ERR_LIST, NB_ERR_STATE, NB_ERR_HIP, PHASES, load,
-                    version, LIB_PATH)
+                    NB_ERR_LIST, NB_ERR_STATE, NB_ERR_HIP, NB_FLAG_TIMING,
+                    NB_FLAG_GRAPH, PHASES, load, version, LIB_PATH)
 
 __all__ = ["Context", "NbError", "NB_MAKE_LIST", "NB_MAKE_LIST_FOR_REUSE",
            "NB_REUSE_LIST", "NB_OK", "NB_ERR_INPUT", "NB_ERR_OOM",
-           "NB_ERR_LIST", "NB_ERR_STATE", "NB_ERR_HIP", "PHASES", "load",
+           "NB_ERR_LIST", "NB_ERR_STATE", "NB_ERR_HIP", "NB_FLAG_TIMING",
+           "NB_FLAG_GRAPH", "PHASES", "load",
            "version", "LIB_PATH"]

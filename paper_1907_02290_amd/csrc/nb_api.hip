@@ -125,10 +125,18 @@ static int sync(nb_ctx* c) {
   return hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
 }
 
+static void drop_graph(nb_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+}
+
 static int build_tree(nb_ctx* c) {
   if (!c->have_particles)
     return set_err(c, NB_ERR_STATE, "no particles set");
   int rc;
+  drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = c->forces_valid = false;
   {
@@ -299,6 +307,7 @@ int nb_create(const nb_config* cfg, nb_ctx** out) {
 void nb_destroy(nb_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
   for (auto& t : c->timers) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
@@ -310,6 +319,8 @@ void nb_destroy(nb_ctx* c) {
   release(c->orig); release(c->orig2); release(c->acc);
   release(c->key); release(c->key2); release(c->val); release(c->val2);
   release(c->hist); release(c->dtot); release(c->root); release(c->bbox_part);
+  release(c->bbox_chunks); release(c->bbox_first); release(c->seg);
+  release(c->sys_off); release(c->croot);
   release(c->lam); release(c->lmin); release(c->cstart);
   release(c->c_rec);
   release(c->c_mom); release(c->c_quad); release(c->c_pm);
@@ -333,6 +344,7 @@ int nb_set_config(nb_ctx* c, const nb_config* cfg) {
   void* keep_stream = c->cfg.stream;
   c->cfg = *cfg;
   c->cfg.stream = keep_stream;  // the stream is fixed at creation
+  drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = false;
   return NB_OK;
@@ -347,6 +359,7 @@ int nb_set_particles(nb_ctx* c, int64_t n, const double* x, const double* y,
   if (!x || !y || !z || !vx || !vy || !vz || !m)
     return set_err(c, NB_ERR_INPUT, "NULL particle array");
   c->have_particles = false;
+  drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = c->forces_valid = false;
   const size_t un = (size_t)n;
@@ -393,8 +406,31 @@ int nb_set_particles(nb_ctx* c, int64_t n, const double* x, const double* y,
                                          hipMemcpyHostToDevice), "vz upload");
     if (rc) return rc;
   }
+  c->n_sys = 1;
+  c->h_sys_off.assign({0, n});
+  rc = launch_seg_fill(c);
+  if (rc) return rc;
   c->have_particles = true;
   return NB_OK;
+}
+
+int nb_set_systems(nb_ctx* c, int64_t n_sys, const int64_t* off) {
+  if (!c) return NB_ERR_INPUT;
+  if (!c->have_particles)
+    return set_err(c, NB_ERR_STATE, "set the particles before the systems");
+  if (n_sys < 1 || n_sys > c->n || !off)
+    return set_err(c, NB_ERR_INPUT, "bad system count %lld", (long long)n_sys);
+  if (off[0] != 0 || off[n_sys] != c->n)
+    return set_err(c, NB_ERR_INPUT, "system offsets must run from 0 to n");
+  for (int64_t s = 0; s < n_sys; ++s)
+    if (off[s + 1] <= off[s])
+      return set_err(c, NB_ERR_INPUT, "system %lld is empty", (long long)s);
+  drop_graph(c);
+  c->tree_valid = c->positions_fresh = false;
+  c->lists_valid = c->lists_reusable = false;
+  c->n_sys = n_sys;
+  c->h_sys_off.assign(off, off + n_sys + 1);
+  return launch_seg_fill(c);
 }
 
 int nb_build_tree(nb_ctx* c) {
@@ -447,6 +483,72 @@ int nb_kick_drift(nb_ctx* c, double dt_kick, double dt_drift) {
     c->positions_fresh = false;
     if (!c->lists_reusable) c->lists_valid = false;
   }
+  return NB_OK;
+}
+
+// The kernels of one reuse step: kick-drift, moments of the frozen tree,
+// force on the kept lists.
+static int enqueue_reuse_step(nb_ctx* c, double dtk, double dtd) {
+  int rc = launch_kick_drift(c, dtk, dtd);
+  if (!rc) rc = launch_moments(c);
+  if (!rc) rc = launch_force(c);
+  return rc;
+}
+
+int nb_step(nb_ctx* c, nb_mode mode, double dt_kick, double dt_drift) {
+  if (!c) return NB_ERR_INPUT;
+  const bool graph = (c->cfg.flags & NB_FLAG_GRAPH) != 0;
+  if (!(graph && mode == NB_REUSE_LIST)) {
+    int rc = nb_kick_drift(c, dt_kick, dt_drift);
+    if (!rc) rc = nb_compute_forces(c, mode);
+    return rc;
+  }
+  if (!std::isfinite(dt_kick) || !std::isfinite(dt_drift))
+    return set_err(c, NB_ERR_INPUT, "non-finite time step");
+  if (!c->forces_valid)
+    return set_err(c, NB_ERR_STATE, "kick-drift needs computed forces");
+  if (!c->have_particles || !c->tree_valid || !c->lists_reusable)
+    return set_err(c, NB_ERR_STATE,
+                   "REUSE_LIST needs lists made with MAKE_LIST_FOR_REUSE");
+  int rc;
+  if (c->graph_exec &&
+      (c->graph_dtk != dt_kick || c->graph_dtd != dt_drift))
+    drop_graph(c);
+  if (!c->graph_exec) {
+    // buffers are already sized by the construction step, so nothing is
+    // allocated while the stream is being captured
+    rc = hip_check(c, hipStreamBeginCapture(c->stream,
+                                            hipStreamCaptureModeRelaxed),
+                   "graph capture");
+    if (rc) return rc;
+    const int rq = enqueue_reuse_step(c, dt_kick, dt_drift);
+    hipGraph_t gr = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->stream, &gr);
+    if (rq) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rq;
+    }
+    rc = hip_check(c, ee, "graph capture end");
+    if (rc) return rc;
+    c->graph = gr;
+    rc = hip_check(c, hipGraphInstantiate(&c->graph_exec, gr, nullptr,
+                                          nullptr, 0), "graph instantiate");
+    if (rc) {
+      drop_graph(c);
+      return rc;
+    }
+    c->graph_dtk = dt_kick;
+    c->graph_dtd = dt_drift;
+  }
+  {
+    Timed t(c, NB_PH_GRAPH);
+    rc = hip_check(c, hipGraphLaunch(c->graph_exec, c->stream), "graph launch");
+    if (rc) return rc;
+  }
+  if (dt_drift != 0.0) c->positions_fresh = false;
+  c->forces_valid = true;
+  c->force_evals += 1;
+  c->total_inter += c->n_inter;
   return NB_OK;
 }
 
@@ -522,6 +624,7 @@ int nb_get_info(nb_ctx* c, int64_t* info) {
   info[7] = c->total_inter;
   info[8] = c->k;
   info[9] = c->n_wi;
+  info[10] = c->n_sys;
   return NB_OK;
 }
 
@@ -535,6 +638,22 @@ int nb_get_root(nb_ctx* c, double* lo, int32_t* k) {
   if (rc) return rc;
   for (int a = 0; a < 3; ++a) lo[a] = r.lo[a];
   *k = r.k;
+  return NB_OK;
+}
+
+int nb_get_roots(nb_ctx* c, double* lo3, int32_t* k) {
+  if (!c || !lo3 || !k) return NB_ERR_INPUT;
+  if (!c->tree_valid) return set_err(c, NB_ERR_STATE, "no tree");
+  std::vector<Root> r((size_t)c->n_sys);
+  int rc = sync(c);
+  if (!rc) rc = hip_check(c, hipMemcpy(r.data(), c->root.p,
+                                       r.size() * sizeof(Root),
+                                       hipMemcpyDeviceToHost), "root readback");
+  if (rc) return rc;
+  for (size_t s = 0; s < r.size(); ++s) {
+    for (int a = 0; a < 3; ++a) lo3[3 * s + a] = r[s].lo[a];
+    k[s] = r[s].k;
+  }
   return NB_OK;
 }
 

@@ -59,6 +59,11 @@ struct nb_ctx {
 
   // sizes of the current particle set, tree and lists
   int64_t n = 0, n_cell = 0, n_groups = 0, n_wi = 0, n_leaves = 0;
+  // independent systems: particles [sys_off[s], sys_off[s + 1]) form
+  // system s (one system unless nb_set_systems says otherwise)
+  int64_t n_sys = 1;
+  std::vector<int64_t> h_sys_off;
+  std::vector<int4> h_bbox_chunks;  // system, begin, end, first partial
   int64_t n_epj = 0, n_spj = 0, n_inter = 0;
   int64_t force_evals = 0, total_inter = 0;
   int32_t k = 0;
@@ -86,8 +91,13 @@ struct nb_ctx {
   nb::DBuf<uint32_t> val, val2;
   nb::DBuf<uint32_t> hist;   // 256 x blocks
   nb::DBuf<uint32_t> dtot;   // 256 digit totals
-  nb::DBuf<nb::Root> root;
+  nb::DBuf<nb::Root> root;        // one per system
   nb::DBuf<double> bbox_part;
+  nb::DBuf<int4> bbox_chunks;     // bbox work: {system, begin, end, 0}
+  nb::DBuf<uint32_t> bbox_first;  // per system: first chunk, n_sys + 1
+  nb::DBuf<uint32_t> seg;         // system of each slot
+  nb::DBuf<uint32_t> sys_off;     // n_sys + 1 slot offsets
+  nb::DBuf<uint32_t> croot;       // n_sys + 1: first cell of each system
 
   // link
   nb::DBuf<uint8_t> lam, lmin;
@@ -117,6 +127,11 @@ struct nb_ctx {
   nb::DBuf<uint64_t> scan_tmp;
   nb::DBuf<uint64_t> red;  // small reductions (interaction count, ...)
   void* h_small = nullptr; // pinned host staging (4 KiB)
+
+  // captured reuse step (NB_FLAG_GRAPH)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  double graph_dtk = 0.0, graph_dtd = 0.0;
 
   // timing
   std::vector<nb::TimerRec> timers;
@@ -177,6 +192,8 @@ int launch_link_fill(nb_ctx* c);
 int launch_level_lists(nb_ctx* c);  // enqueues; no host sync
 int launch_moments(nb_ctx* c);
 int launch_group_flags(nb_ctx* c);
+int launch_sys_roots(nb_ctx* c);
+int launch_seg_fill(nb_ctx* c);
 int launch_group_fill(nb_ctx* c);
 // nb_walk.hip
 int launch_walk(nb_ctx* c, bool fill);

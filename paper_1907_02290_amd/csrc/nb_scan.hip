@@ -7,6 +7,8 @@
 // wave64 ballots (the lanes that share a digit are found bit by bit), stages
 // the block's keys in LDS in digit order and writes them out so that equal
 // digits land in contiguous, coalesced runs.
+#include <utility>
+
 #include "nb_internal.h"
 
 namespace nb {
@@ -130,8 +132,21 @@ constexpr int kRsWaves = kRsThreads / 64;
 constexpr int kRsRows = 16;                      // rows of 64 keys per wave
 constexpr int kRsTile = kRsThreads * kRsRows;    // 4096 keys per block
 
+// Digit of an element: 8 bits of its Morton key, or (SYS) 8 bits of the
+// system id of the slot it came from -- the last passes group the systems
+// while keeping each system's Morton order.
+template <bool SYS>
+__device__ inline uint32_t rs_digit(uint64_t k, uint32_t v,
+                                    const uint32_t* __restrict__ seg,
+                                    int shift) {
+  return SYS ? (seg[v] >> shift) & 255u : (uint32_t)(k >> shift) & 255u;
+}
+
+template <bool SYS>
 __global__ void __launch_bounds__(kRsThreads)
-k_rs_upsweep(const uint64_t* __restrict__ key, int64_t n, int shift,
+k_rs_upsweep(const uint64_t* __restrict__ key,
+             const uint32_t* __restrict__ val,
+             const uint32_t* __restrict__ seg, int64_t n, int shift,
              uint32_t* __restrict__ hist, int nblk) {
   __shared__ uint32_t h[kRsWaves][256];
   const int t = threadIdx.x, w = t >> 6;
@@ -142,7 +157,10 @@ k_rs_upsweep(const uint64_t* __restrict__ key, int64_t n, int shift,
   for (int j = 0; j < kRsRows; ++j) {
     const int64_t idx = base + (int64_t)j * kRsThreads + t;
     if (idx < n) {
-      const uint32_t d = (uint32_t)(key[idx] >> shift) & 255u;
+      const uint32_t d =
+          rs_digit<SYS>(SYS ? 0ull : key[idx],
+                        SYS ? (val ? val[idx] : (uint32_t)idx) : 0u, seg,
+                        shift);
       atomicAdd(&h[w][d], 1u);
     }
   }
@@ -173,9 +191,11 @@ k_rs_scan_digit(uint32_t* __restrict__ hist, int nblk,
   if (threadIdx.x == 0) dtot[blockIdx.x] = tot;
 }
 
+template <bool SYS>
 __global__ void __launch_bounds__(kRsThreads)
 k_rs_downsweep(const uint64_t* __restrict__ key_in,
                const uint32_t* __restrict__ val_in,
+               const uint32_t* __restrict__ seg,
                uint64_t* __restrict__ key_out, uint32_t* __restrict__ val_out,
                int64_t n, int shift, const uint32_t* __restrict__ hist,
                const uint32_t* __restrict__ dtot, int nblk) {
@@ -206,7 +226,7 @@ k_rs_downsweep(const uint64_t* __restrict__ key_in,
   for (int j = 0; j < kRsRows; ++j) {
     const int64_t idx = base + (int64_t)(w * kRsRows + j) * 64 + lane;
     const bool ok = idx < n;
-    const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
+    const uint32_t d = ok ? rs_digit<SYS>(k[j], v[j], seg, shift) : 0u;
     uint64_t peer = __ballot(ok);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -250,7 +270,7 @@ k_rs_downsweep(const uint64_t* __restrict__ key_in,
   for (int j = 0; j < kRsRows; ++j) {
     const int64_t idx = base + (int64_t)(w * kRsRows + j) * 64 + lane;
     if (idx < n) {
-      const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
+      const uint32_t d = rs_digit<SYS>(k[j], v[j], seg, shift);
       const uint32_t p = lbase[w][d] + loc[j];
       s_key[p] = k[j];
       s_val[p] = v[j];
@@ -261,7 +281,7 @@ k_rs_downsweep(const uint64_t* __restrict__ key_in,
   const int tile_n = (int)(rem < kRsTile ? rem : kRsTile);
   for (int i = t; i < tile_n; i += kRsThreads) {
     const uint64_t kk = s_key[i];
-    const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+    const uint32_t d = rs_digit<SYS>(kk, s_val[i], seg, shift);
     const uint32_t dest = gbase[d] + (uint32_t)i;
     key_out[dest] = kk;
     val_out[dest] = s_val[i];
@@ -280,8 +300,9 @@ int scan_u32_to_u64(nb_ctx* c, const uint32_t* in, uint64_t* out, int64_t n) {
 
 // Sorts c->key / c->val (first n entries) ascending by key, stably; the
 // initial values are the slot indices 0..n-1.  Eight 8-bit passes cover the
-// 63-bit keys; after an even number of passes the result is back in
-// c->key / c->val.
+// 63-bit keys.  With several systems, one more stable pass per 8 bits of the
+// system id groups the systems (each keeps its slots [off_s, off_s+1)).  The
+// result is left in c->key / c->val.
 int radix_sort(nb_ctx* c, int64_t n) {
   const int nblk = (int)((n + kRsTile - 1) / kRsTile);
   int rc = reserve(c, c->hist, (size_t)256 * nblk);
@@ -289,35 +310,51 @@ int radix_sort(nb_ctx* c, int64_t n) {
   if (!rc) rc = reserve(c, c->key2, (size_t)n);
   if (!rc) rc = reserve(c, c->val2, (size_t)n);
   if (rc) return rc;
+  int sys_passes = 0;
+  for (int64_t m = c->n_sys - 1; m > 0; m >>= 8) ++sys_passes;
   uint64_t* kin = c->key.p;
   uint64_t* kout = c->key2.p;
   uint32_t* vin = nullptr;  // first pass: implicit iota
   uint32_t* vout = c->val2.p;
-  for (int pass = 0; pass < 8; ++pass) {
-    const int shift = 8 * pass;
-    hipLaunchKernelGGL(k_rs_upsweep, dim3(nblk), dim3(kRsThreads), 0,
-                       c->stream, (const uint64_t*)kin, n, shift, c->hist.p,
-                       nblk);
+  const uint32_t* seg = c->seg.p;
+  for (int pass = 0; pass < 8 + sys_passes; ++pass) {
+    const bool sys = pass >= 8;
+    const int shift = sys ? 8 * (pass - 8) : 8 * pass;
+    if (sys) {
+      hipLaunchKernelGGL(k_rs_upsweep<true>, dim3(nblk), dim3(kRsThreads), 0,
+                         c->stream, (const uint64_t*)kin, (const uint32_t*)vin,
+                         seg, n, shift, c->hist.p, nblk);
+    } else {
+      hipLaunchKernelGGL(k_rs_upsweep<false>, dim3(nblk), dim3(kRsThreads), 0,
+                         c->stream, (const uint64_t*)kin, (const uint32_t*)vin,
+                         seg, n, shift, c->hist.p, nblk);
+    }
     hipLaunchKernelGGL(k_rs_scan_digit, dim3(256), dim3(256), 0, c->stream,
                        c->hist.p, nblk, c->dtot.p);
-    hipLaunchKernelGGL(k_rs_downsweep, dim3(nblk), dim3(kRsThreads), 0,
-                       c->stream, (const uint64_t*)kin, (const uint32_t*)vin,
-                       kout, vout, n, shift, (const uint32_t*)c->hist.p,
-                       (const uint32_t*)c->dtot.p, nblk);
-    uint64_t* tk = kin;
-    kin = kout;
-    kout = tk;
+    if (sys) {
+      hipLaunchKernelGGL(k_rs_downsweep<true>, dim3(nblk), dim3(kRsThreads),
+                         0, c->stream, (const uint64_t*)kin,
+                         (const uint32_t*)vin, seg, kout, vout, n, shift,
+                         (const uint32_t*)c->hist.p,
+                         (const uint32_t*)c->dtot.p, nblk);
+    } else {
+      hipLaunchKernelGGL(k_rs_downsweep<false>, dim3(nblk), dim3(kRsThreads),
+                         0, c->stream, (const uint64_t*)kin,
+                         (const uint32_t*)vin, seg, kout, vout, n, shift,
+                         (const uint32_t*)c->hist.p,
+                         (const uint32_t*)c->dtot.p, nblk);
+    }
+    std::swap(kin, kout);
     if (pass == 0) {
       vin = vout;
       vout = c->val.p;
     } else {
-      uint32_t* tv = vin;
-      vin = vout;
-      vout = tv;
+      std::swap(vin, vout);
     }
   }
-  // after 8 passes: kin == c->key.p, vin == ? (pass0 wrote val2, pass1 val,
-  // ..., pass7 wrote val) -> vin == c->val.p
+  // the sorted data is in (kin, vin); make it c->key / c->val
+  if (kin != c->key.p) std::swap(c->key, c->key2);
+  if (vin != c->val.p) std::swap(c->val, c->val2);
   if (kin != c->key.p || vin != c->val.p)
     return set_err(c, NB_ERR_HIP, "radix sort buffer parity");
   return hip_check(c, hipGetLastError(), "radix sort launch");

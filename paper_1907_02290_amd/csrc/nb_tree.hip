@@ -14,6 +14,8 @@
 // DFS pre-order (sorted by begin, then level); the end of a cell is found by
 // a galloping search in the sorted keys (the paper's binary search), and the
 // first cell starting at or after that end is the cell after its subtree.
+#include <algorithm>
+
 #include "nb_internal.h"
 
 namespace nb {
@@ -50,7 +52,6 @@ __device__ inline int shared_levels(uint64_t a, uint64_t b) {
 // ---------------------------------------------------------------------------
 // Root cell: per-axis min / max of the positions (exact), then the cube.
 constexpr int kBboxThreads = 256;
-constexpr int kBboxBlocks = 1024;
 
 __device__ inline double wave_min(double v) {
 #pragma unroll
@@ -63,15 +64,17 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
+// Per-chunk partials; a chunk lies inside one system.
 __global__ void __launch_bounds__(kBboxThreads)
-k_bbox_partial(const double4* __restrict__ pos, int64_t n,
-               double* __restrict__ part) {
+k_bbox_partial(const double4* __restrict__ pos,
+               const int4* __restrict__ chunks, double* __restrict__ part) {
   __shared__ double s[kBboxThreads / 64][7];
+  const int4 ch = chunks[blockIdx.x];
   double mn[3] = {INFINITY, INFINITY, INFINITY};
   double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
   double bad = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)ch.y + threadIdx.x; i < (int64_t)ch.z;
+       i += blockDim.x) {
     const double4 p = pos[i];
     const double v[3] = {p.x, p.y, p.z};
 #pragma unroll
@@ -100,27 +103,29 @@ k_bbox_partial(const double4* __restrict__ pos, int64_t n,
       }
       s[0][6] = fmax(s[0][6], s[q][6]);
     }
-    for (int a = 0; a < 7; ++a) part[blockIdx.x * 8 + a] = s[0][a];
+    for (int a = 0; a < 7; ++a) part[(int64_t)blockIdx.x * 8 + a] = s[0][a];
   }
 }
 
 // rr = (1/theta)*(1/theta) from the host: (2^e/theta)^2 rounds to
 // 2^(2e) * rr exactly, so rcrit2[l] = ldexp(rr, 2(k - l)).
-// One block of 256 threads reduces the per-block partials (min / max are
-// exact, so the reduction order does not matter).
+// One block of 256 threads per system reduces that system's chunk partials
+// (min / max are exact, so the reduction order does not matter).
 __global__ void __launch_bounds__(kBboxThreads)
-k_bbox_final(const double* __restrict__ part, int nb, double rr,
-             Root* __restrict__ root) {
+k_bbox_final(const double* __restrict__ part,
+             const uint32_t* __restrict__ first, double rr,
+             Root* __restrict__ roots) {
   __shared__ double s[kBboxThreads / 64][7];
+  const uint32_t b0 = first[blockIdx.x], b1 = first[blockIdx.x + 1];
   double mn[3] = {INFINITY, INFINITY, INFINITY};
   double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
   double bad = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBboxThreads) {
+  for (uint32_t b = b0 + threadIdx.x; b < b1; b += kBboxThreads) {
     for (int a = 0; a < 3; ++a) {
-      mn[a] = fmin(mn[a], part[b * 8 + a]);
-      mx[a] = fmax(mx[a], part[b * 8 + 3 + a]);
+      mn[a] = fmin(mn[a], part[(int64_t)b * 8 + a]);
+      mx[a] = fmax(mx[a], part[(int64_t)b * 8 + 3 + a]);
     }
-    bad = fmax(bad, part[b * 8 + 6]);
+    bad = fmax(bad, part[(int64_t)b * 8 + 6]);
   }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int a = 0; a < 3; ++a) {
@@ -144,6 +149,7 @@ k_bbox_final(const double* __restrict__ part, int nb, double rr,
     }
     s[0][6] = fmax(s[0][6], s[q][6]);
   }
+  Root* root = roots + blockIdx.x;
   double ext = 0.0;
   for (int a = 0; a < 3; ++a) {
     root->lo[a] = s[0][a];
@@ -161,13 +167,23 @@ k_bbox_final(const double* __restrict__ part, int nb, double rr,
   for (int l = 0; l < kLevels; ++l) root->rcrit2[l] = ldexp(rr, 2 * (k - l));
 }
 
+// Any system with a non-finite coordinate -> roots[0].bad (read by the host).
+__global__ void k_bbox_bad(Root* __restrict__ roots, int64_t n_sys) {
+  if (threadIdx.x != 0) return;
+  int bad = 0;
+  for (int64_t s = 0; s < n_sys; ++s) bad |= roots[s].bad;
+  roots[0].bad = bad;
+}
+
 // ---------------------------------------------------------------------------
 // Morton keys: q = floor((x - lo) * 2^(21 - k)), clamped to 21 bits.
 __global__ void __launch_bounds__(256)
 k_keys(const double4* __restrict__ pos, int64_t n,
-       const Root* __restrict__ root, uint64_t* __restrict__ key) {
+       const Root* __restrict__ roots, const uint32_t* __restrict__ seg,
+       uint64_t* __restrict__ key) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const Root* root = roots + seg[i];
   const double scale = ldexp(1.0, kKeyBits - root->k);
   const double qmax = (double)((1u << kKeyBits) - 1u);
   const double4 p = pos[i];
@@ -205,22 +221,29 @@ k_gather(int64_t n, const uint32_t* __restrict__ val,
 // ---------------------------------------------------------------------------
 // Link, pass 1: leaf level lam(i), first level lmin(i) of a cell beginning
 // at i, and the number of cells beginning at i.
+// Link, pass 1: leaf level lam(i), first level lmin(i) of a cell beginning
+// at i, and the number of cells beginning at i.  Windows and neighbours
+// never reach across the particle's system: each system has its own root.
 __global__ void __launch_bounds__(256)
 k_link_count(const uint64_t* __restrict__ key, int64_t n, int n_leaf,
+             const uint32_t* __restrict__ seg,
+             const uint32_t* __restrict__ sys_off,
              uint8_t* __restrict__ lam, uint8_t* __restrict__ lmin,
              uint32_t* __restrict__ cstart) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const uint32_t si = seg[i];
+  const int64_t sb = sys_off[si], se = sys_off[si + 1];
   int M = -1;
-  const int64_t s0 = i - n_leaf > 0 ? i - n_leaf : 0;
+  const int64_t s0 = i - n_leaf > sb ? i - n_leaf : sb;
   for (int64_t s = s0; s <= i; ++s) {
-    if (s + n_leaf < n) {
+    if (s + n_leaf < se) {
       const int v = shared_levels(key[s], key[s + n_leaf]);
       M = v > M ? v : M;
     }
   }
   const int la = M < 0 ? 0 : (M + 1 < kMaxLevel ? M + 1 : kMaxLevel);
-  const int lm = i == 0 ? 0 : shared_levels(key[i - 1], key[i]) + 1;
+  const int lm = i == sb ? 0 : shared_levels(key[i - 1], key[i]) + 1;
   lam[i] = (uint8_t)la;
   lmin[i] = (uint8_t)lm;
   cstart[i] = la >= lm ? (uint32_t)(la - lm + 1) : 0u;
@@ -255,14 +278,15 @@ __device__ inline int64_t gallop_end(const uint64_t* __restrict__ key,
   return a;
 }
 
-// First index <= hi whose key shares `pre` (keys[hi] does).
+// First index in [lo_bound, hi] whose key shares `pre` (keys[hi] does).
 __device__ inline int64_t gallop_begin(const uint64_t* __restrict__ key,
-                                       int64_t hi, uint64_t pre, int sh) {
-  int64_t in = hi, out = -1, step = 1;
+                                       int64_t lo_bound, int64_t hi,
+                                       uint64_t pre, int sh) {
+  int64_t in = hi, out = lo_bound - 1, step = 1;
   for (;;) {
     const int64_t probe = in - step;
-    if (probe < 0) {
-      out = -1;
+    if (probe < lo_bound) {
+      out = lo_bound - 1;
       break;
     }
     if ((key[probe] >> sh) != pre) {
@@ -285,13 +309,18 @@ __device__ inline int64_t gallop_begin(const uint64_t* __restrict__ key,
 // Link, pass 2: write every cell (DFS pre-order id = S[i] + l - lmin(i)).
 __global__ void __launch_bounds__(256)
 k_link_fill(const uint64_t* __restrict__ key, int64_t n,
+            const uint32_t* __restrict__ seg,
+            const uint32_t* __restrict__ sys_off,
             const uint8_t* __restrict__ lam, const uint8_t* __restrict__ lmin,
-            const uint32_t* __restrict__ S, const Root* __restrict__ root,
+            const uint32_t* __restrict__ S, const Root* __restrict__ roots,
             CellRec* __restrict__ rec) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int la = lam[i], lm = lmin[i];
   if (la < lm) return;
+  const uint32_t si = seg[i];
+  const int64_t sb = sys_off[si], se = sys_off[si + 1];
+  const Root* root = roots + si;
   const uint32_t base = S[i];
   const uint64_t ki = key[i];
   const int k = root->k;
@@ -300,7 +329,7 @@ k_link_fill(const uint64_t* __restrict__ key, int64_t n,
     const uint32_t id = base + (uint32_t)(l - lm);
     const int sh = 3 * (kMaxLevel - l);
     const uint64_t pre = ki >> sh;
-    end = gallop_end(key, n, end, pre, sh);
+    end = gallop_end(key, se, end, pre, sh);
     uint32_t par;
     if (l > lm) {
       par = id - 1;
@@ -308,7 +337,7 @@ k_link_fill(const uint64_t* __restrict__ key, int64_t n,
       par = kNone;
     } else {
       const int psh = 3 * (kMaxLevel - (l - 1));
-      const int64_t b = gallop_begin(key, i, ki >> psh, psh);
+      const int64_t b = gallop_begin(key, sb, i, ki >> psh, psh);
       par = S[b] + (uint32_t)((l - 1) - (int)lmin[b]);
     }
     const uint32_t skip = S[end];
@@ -328,6 +357,31 @@ k_link_fill(const uint64_t* __restrict__ key, int64_t n,
   }
 }
 
+// First cell of every system (its root) and the total: croot[s] = S[off_s].
+__global__ void k_sys_roots(const uint32_t* __restrict__ S,
+                            const uint32_t* __restrict__ sys_off,
+                            int64_t n_sys, uint32_t* __restrict__ croot) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s <= n_sys) croot[s] = S[sys_off[s]];
+}
+
+// System of every slot from the system offsets.
+__global__ void __launch_bounds__(256)
+k_seg_fill(const uint32_t* __restrict__ sys_off, int64_t n_sys, int64_t n,
+           uint32_t* __restrict__ seg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t lo = 0, hi = n_sys;  // last s with sys_off[s] <= i
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)sys_off[mid] <= i)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  seg[i] = (uint32_t)lo;
+}
+
 // ---------------------------------------------------------------------------
 // Groups (Barnes' vectorisation): a cell holding at most n_grp particles (or
 // a leaf) whose parent holds more than n_grp.
@@ -339,8 +393,8 @@ k_group_flags(int64_t n_cell, const CellRec* __restrict__ rec, int n_grp,
   const uint4 m = rec[c].meta;
   const uint32_t cnt = m.y - m.x;
   const bool leaf = (m.w >> 8) & 1u;
-  bool top = true;
-  if (c != 0) {
+  bool top = true;  // a system's root has no parent
+  if ((m.w & 255u) != 0) {
     const uint4 pm = rec[rec[c].aux.x].meta;
     top = (pm.y - pm.x) > (uint32_t)n_grp;
   }
@@ -589,19 +643,25 @@ k_mom_internal(int64_t cnt, const uint32_t* __restrict__ list,
 
 }  // namespace
 
+// The chunk table (system, first, end) of the bounding-box pass is built on
+// the host whenever the particles or the systems change.
 int launch_root(nb_ctx* c) {
-  int rc = reserve(c, c->bbox_part, (size_t)kBboxBlocks * 8);
-  if (!rc) rc = reserve(c, c->root, 1);
+  const size_t nch = c->h_bbox_chunks.size();
+  int rc = reserve(c, c->bbox_part, nch * 8);
+  if (!rc) rc = reserve(c, c->root, (size_t)c->n_sys);
   if (rc) return rc;
-  int nb = (int)grid_for(c->n, kBboxThreads);
-  if (nb > kBboxBlocks) nb = kBboxBlocks;
-  hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kBboxThreads), 0,
-                     c->stream, (const double4*)c->pos.p, c->n,
-                     c->bbox_part.p);
+  hipLaunchKernelGGL(k_bbox_partial, dim3((unsigned)nch), dim3(kBboxThreads),
+                     0, c->stream, (const double4*)c->pos.p,
+                     (const int4*)c->bbox_chunks.p, c->bbox_part.p);
   const double r1 = 1.0 / c->cfg.theta;
   const double rr = r1 * r1;
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBboxThreads), 0, c->stream,
-                     (const double*)c->bbox_part.p, nb, rr, c->root.p);
+  hipLaunchKernelGGL(k_bbox_final, dim3((unsigned)c->n_sys),
+                     dim3(kBboxThreads), 0, c->stream,
+                     (const double*)c->bbox_part.p,
+                     (const uint32_t*)c->bbox_first.p, rr, c->root.p);
+  if (c->n_sys > 1)
+    hipLaunchKernelGGL(k_bbox_bad, dim3(1), dim3(64), 0, c->stream, c->root.p,
+                       c->n_sys);
   return hip_check(c, hipGetLastError(), "root launch");
 }
 
@@ -611,8 +671,47 @@ int launch_keys(nb_ctx* c) {
   if (rc) return rc;
   hipLaunchKernelGGL(k_keys, dim3(grid_for(c->n, 256)), dim3(256), 0,
                      c->stream, (const double4*)c->pos.p, c->n,
-                     (const Root*)c->root.p, c->key.p);
+                     (const Root*)c->root.p, (const uint32_t*)c->seg.p,
+                     c->key.p);
   return hip_check(c, hipGetLastError(), "keys launch");
+}
+
+// Upload the system offsets and the bounding-box chunk table, and fill the
+// per-slot system ids.  Called by nb_set_particles / nb_set_systems.
+int launch_seg_fill(nb_ctx* c) {
+  constexpr int64_t kChunk = 16384;
+  std::vector<uint32_t> off(c->n_sys + 1), first(c->n_sys + 1);
+  c->h_bbox_chunks.clear();
+  for (int64_t s = 0; s < c->n_sys; ++s) {
+    off[s] = (uint32_t)c->h_sys_off[s];
+    first[s] = (uint32_t)c->h_bbox_chunks.size();
+    for (int64_t b = c->h_sys_off[s]; b < c->h_sys_off[s + 1]; b += kChunk) {
+      const int64_t e = std::min(b + kChunk, c->h_sys_off[s + 1]);
+      c->h_bbox_chunks.push_back(make_int4((int)s, (int)b, (int)e, 0));
+    }
+  }
+  off[c->n_sys] = (uint32_t)c->n;
+  first[c->n_sys] = (uint32_t)c->h_bbox_chunks.size();
+  int rc = reserve(c, c->sys_off, off.size());
+  if (!rc) rc = reserve(c, c->bbox_first, first.size());
+  if (!rc) rc = reserve(c, c->bbox_chunks, c->h_bbox_chunks.size());
+  if (!rc) rc = reserve(c, c->seg, (size_t)c->n);
+  if (!rc) rc = reserve(c, c->croot, (size_t)c->n_sys + 1);
+  if (rc) return rc;
+  rc = hip_check(c, hipMemcpy(c->sys_off.p, off.data(), off.size() * 4,
+                              hipMemcpyHostToDevice), "system upload");
+  if (!rc) rc = hip_check(c, hipMemcpy(c->bbox_first.p, first.data(),
+                                       first.size() * 4,
+                                       hipMemcpyHostToDevice), "system upload");
+  if (!rc) rc = hip_check(c, hipMemcpy(c->bbox_chunks.p,
+                                       c->h_bbox_chunks.data(),
+                                       c->h_bbox_chunks.size() * sizeof(int4),
+                                       hipMemcpyHostToDevice), "system upload");
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_seg_fill, dim3(grid_for(c->n, 256)), dim3(256), 0,
+                     c->stream, (const uint32_t*)c->sys_off.p, c->n_sys, c->n,
+                     c->seg.p);
+  return hip_check(c, hipGetLastError(), "system fill launch");
 }
 
 int launch_reorder(nb_ctx* c) {
@@ -645,7 +744,9 @@ int launch_link_count(nb_ctx* c) {
   if (rc) return rc;
   hipLaunchKernelGGL(k_link_count, dim3(grid_for(c->n, 256)), dim3(256), 0,
                      c->stream, (const uint64_t*)c->key.p, c->n,
-                     (int)c->cfg.n_leaf, c->lam.p, c->lmin.p, c->cstart.p);
+                     (int)c->cfg.n_leaf, (const uint32_t*)c->seg.p,
+                     (const uint32_t*)c->sys_off.p, c->lam.p, c->lmin.p,
+                     c->cstart.p);
   rc = hip_check(c, hipGetLastError(), "link count launch");
   if (rc) return rc;
   return scan_u32(c, c->cstart.p, c->cstart.p, c->n);
@@ -656,9 +757,13 @@ int launch_link_fill(nb_ctx* c) {
   if (rc) return rc;
   hipLaunchKernelGGL(k_link_fill, dim3(grid_for(c->n, 256)), dim3(256), 0,
                      c->stream, (const uint64_t*)c->key.p, c->n,
+                     (const uint32_t*)c->seg.p, (const uint32_t*)c->sys_off.p,
                      (const uint8_t*)c->lam.p, (const uint8_t*)c->lmin.p,
                      (const uint32_t*)c->cstart.p, (const Root*)c->root.p,
                      c->c_rec.p);
+  hipLaunchKernelGGL(k_sys_roots, dim3(grid_for(c->n_sys + 1, 256)),
+                     dim3(256), 0, c->stream, (const uint32_t*)c->cstart.p,
+                     (const uint32_t*)c->sys_off.p, c->n_sys, c->croot.p);
   return hip_check(c, hipGetLastError(), "link fill launch");
 }
 

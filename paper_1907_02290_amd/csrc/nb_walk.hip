@@ -42,6 +42,7 @@ k_walk(int64_t n_groups, int64_t nblk, int64_t n_cell,
        const uint32_t* __restrict__ g_begin,
        const uint32_t* __restrict__ g_count, const double4* __restrict__ g_lo,
        const double4* __restrict__ g_hi, const CellRec* __restrict__ rec,
+       const uint32_t* __restrict__ seg, const uint32_t* __restrict__ croot,
        uint32_t* __restrict__ cnt_e, uint32_t* __restrict__ cnt_s,
        uint32_t* __restrict__ cnt_t, const uint64_t* __restrict__ tok_off,
        uint32_t* __restrict__ tok) {
@@ -64,8 +65,10 @@ k_walk(int64_t n_groups, int64_t nblk, int64_t n_cell,
     dst = tok;
   }
   uint32_t ne = 0, ns = 0, nl = 0;
-  uint32_t c = 0;
-  const uint32_t nc = (uint32_t)n_cell;
+  // the walk covers the cells of the group's own system
+  const uint32_t sys = seg[gb];
+  uint32_t c = croot[sys];
+  const uint32_t nc = croot[sys + 1];
   while (c < nc) {
     const uint4 m = rec[c].meta;
     const double4 cc = rec[c].geo;
@@ -224,6 +227,7 @@ int launch_walk(nb_ctx* c, bool fill) {
                      (const uint32_t*)c->g_begin.p,
                      (const uint32_t*)c->g_count.p, (const double4*)c->g_lo.p,
                      (const double4*)c->g_hi.p, (const CellRec*)c->c_rec.p,
+                     (const uint32_t*)c->seg.p, (const uint32_t*)c->croot.p,
                      c->cnt_e.p, c->cnt_s.p, c->cnt_t.p,
                      (const uint64_t*)c->tok_off.p, c->tok.p);
   int rc2 = hip_check(c, hipGetLastError(), "walk launch");

@@ -26,7 +26,9 @@ NB_MAKE_LIST_FOR_REUSE = 1
 NB_REUSE_LIST = 2
 
 PHASES = ("root", "keys", "sort", "reorder", "link", "moments", "groups",
-          "walk", "force", "kick")
+          "walk", "force", "kick", "graph")
+NB_FLAG_TIMING = 1
+NB_FLAG_GRAPH = 2
 
 STATUS = {NB_OK: "NB_OK", NB_ERR_INPUT: "NB_ERR_INPUT",
           NB_ERR_OOM: "NB_ERR_OOM", NB_ERR_LIST: "NB_ERR_LIST",
@@ -77,10 +79,13 @@ def load():
         "nb_make_lists": ([p, i32], i32),
         "nb_compute_forces": ([p, i32], i32),
         "nb_kick_drift": ([p, d, d], i32),
+        "nb_step": ([p, i32, d, d], i32),
         "nb_get_forces": ([p, p, p, p, p, i32], i32),
         "nb_get_state": ([p] + [p] * 6 + [i32], i32),
         "nb_get_info": ([p, p], i32),
         "nb_get_root": ([p, p, p], i32),
+        "nb_get_roots": ([p, p, p], i32),
+        "nb_set_systems": ([p, i64, p], i32),
         "nb_get_keys": ([p, p, p], i32),
         "nb_get_cells": ([p] + [p] * 7, i32),
         "nb_get_moments": ([p, p, p, p], i32),
@@ -114,16 +119,20 @@ class Context:
     """One GPU-resident particle system (``nb_ctx``)."""
 
     def __init__(self, theta=0.5, eps=0.01, G=1.0, n_leaf=8, n_grp=64,
-                 order=1, ext_mass=0.0, timing=False, stream=None):
+                 order=1, ext_mass=0.0, timing=False, graph=False,
+                 stream=None):
         self._lib = load()
+        flags = (NB_FLAG_TIMING if timing else 0) | \
+            (NB_FLAG_GRAPH if graph else 0)
         self._cfg = nb_config(theta, eps, G, ext_mass, n_leaf, n_grp, order,
-                              1 if timing else 0, stream)
+                              flags, stream)
         h = C.c_void_p()
         rc = self._lib.nb_create(C.byref(self._cfg), C.byref(h))
         if rc != NB_OK:
             raise NbError(rc, "nb_create failed")
         self._h = h
         self.n = 0
+        self.n_sys = 1
 
     def close(self):
         if getattr(self, "_h", None):
@@ -156,7 +165,11 @@ class Context:
     def set_config(self, **kw):
         for k, v in kw.items():
             if k == "timing":
-                self._cfg.flags = 1 if v else 0
+                self._cfg.flags = (self._cfg.flags & ~NB_FLAG_TIMING) | \
+                    (NB_FLAG_TIMING if v else 0)
+            elif k == "graph":
+                self._cfg.flags = (self._cfg.flags & ~NB_FLAG_GRAPH) | \
+                    (NB_FLAG_GRAPH if v else 0)
             else:
                 setattr(self._cfg, k, v)
         self._chk(self._lib.nb_set_config(self._h, C.byref(self._cfg)))
@@ -182,6 +195,13 @@ class Context:
                                             *(_ptr(a) for a in arrs), 0)
         self._chk(rc)
         self.n = n
+        self.n_sys = 1
+
+    def set_systems(self, offsets):
+        """Independent systems: particles [off[s], off[s+1]) form system s."""
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        self._chk(self._lib.nb_set_systems(self._h, off.size - 1, _ptr(off)))
+        self.n_sys = off.size - 1
 
     # ---- the step ----
     def build_tree(self):
@@ -192,6 +212,11 @@ class Context:
 
     def compute_forces(self, mode=NB_MAKE_LIST):
         self._chk(self._lib.nb_compute_forces(self._h, int(mode)))
+
+    def step(self, mode, dt_kick, dt_drift):
+        """Kick-drift then forces; reuse steps may replay a HIP graph."""
+        self._chk(self._lib.nb_step(self._h, int(mode), float(dt_kick),
+                                    float(dt_drift)))
 
     def kick_drift(self, dt_kick, dt_drift):
         self._chk(self._lib.nb_kick_drift(self._h, float(dt_kick),
@@ -211,10 +236,10 @@ class Context:
         return tuple(out)
 
     def get_info(self):
-        a = np.zeros(10, dtype=np.int64)
+        a = np.zeros(11, dtype=np.int64)
         self._chk(self._lib.nb_get_info(self._h, _ptr(a)))
         keys = ("n", "n_cell", "n_groups", "n_epj", "n_spj", "n_inter",
-                "force_evals", "total_inter", "k", "n_wi")
+                "force_evals", "total_inter", "k", "n_wi", "n_sys")
         return {k: int(v) for k, v in zip(keys, a)}
 
     def get_root(self):
@@ -222,6 +247,13 @@ class Context:
         k = C.c_int32(0)
         self._chk(self._lib.nb_get_root(self._h, _ptr(lo), C.byref(k)))
         return lo, int(k.value)
+
+    def get_roots(self):
+        ns = self.get_info()["n_sys"]
+        lo = np.zeros((ns, 3))
+        k = np.zeros(ns, np.int32)
+        self._chk(self._lib.nb_get_roots(self._h, _ptr(lo), _ptr(k)))
+        return lo, k
 
     def get_keys(self):
         key = np.zeros(self.n, np.uint64)

@@ -62,3 +62,21 @@ def test_uniform_sphere_cold():
     r = np.sqrt(d["x"] ** 2 + d["y"] ** 2 + d["z"] ** 2)
     assert r.max() <= 1.05  # recentred on the centre of mass
     assert np.all(d["vx"] == 0)
+
+
+def test_king_model_virial_and_tidal_radius(orc):
+    d = workloads.king(3000, 21)
+    r = np.sqrt(d["x"] ** 2 + d["y"] ** 2 + d["z"] ** 2)
+    # W0 = 6: tidal radius about 17.8 King radii (concentration c = 1.25)
+    assert 14.0 < r.max() < 18.5
+    _, _, _, pot = orc.force_direct(d["x"], d["y"], d["z"], d["m"], 0.0, 1.0)
+    W = 0.5 * (d["m"] * pot).sum()
+    K = 0.5 * (d["m"] * (d["vx"] ** 2 + d["vy"] ** 2 + d["vz"] ** 2)).sum()
+    assert 0.9 < 2 * K / abs(W) < 1.1
+
+
+def test_clusters_offsets():
+    c = workloads.clusters(6, 3, lo_exp=6, hi_exp=9)
+    off = c["offsets"]
+    assert off[0] == 0 and off[-1] == c["x"].size and np.all(np.diff(off) > 0)
+    assert np.all(np.diff(off) >= 2 ** 6 - 1)

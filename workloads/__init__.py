@@ -20,8 +20,15 @@ Systems
                  with the isotropic Jeans dispersion of the Hernquist model.
   ring           planetesimal ring on Keplerian orbits around a unit central
                  mass at the origin, Rayleigh-distributed e and i.
+  king           King (1966) model with central potential W0: the
+                 dimensionless Poisson equation integrated to the tidal
+                 radius, radii from the enclosed mass, speeds by rejection
+                 from the lowered-isothermal distribution function.
+  clusters       many independent Plummer / King systems (separate trees).
 """
 from __future__ import annotations
+
+import functools
 
 import numpy as np
 from scipy import special
@@ -208,6 +215,86 @@ def ring(n, seed, a_lo=0.9, a_hi=1.1, sigma_e=1e-3, sigma_i=1e-3,
     return _pack(x, y, z, vx, vy, vz, m, recentre=False)
 
 
+@functools.lru_cache(maxsize=8)
+def _king_profile(W0):
+    """Dimensionless King (1966) model: radius grid r (King radius 1),
+    potential W(r) >= 0 and enclosed mass mu(r) = r^2 (-dW/dr), integrated
+    out to the tidal radius where W = 0."""
+    from scipy.integrate import solve_ivp
+    from scipy.special import erf
+
+    def rho(W):
+        W = np.maximum(W, 0.0)
+        return np.exp(W) * erf(np.sqrt(W)) - np.sqrt(4.0 * W / np.pi) * (
+            1.0 + 2.0 * W / 3.0)
+
+    rho0 = rho(np.array(W0))
+
+    def rhs(r, y):
+        W, dW = y
+        return [dW, -9.0 * rho(np.array(W)) / rho0 - 2.0 * dW / r]
+
+    def edge(r, y):
+        return y[0]
+    edge.terminal = True
+    edge.direction = -1
+    r0 = 1e-6
+    sol = solve_ivp(rhs, (r0, 1e3), [W0 - 1.5 * r0 * r0, -3.0 * r0],
+                    events=edge, max_step=0.01, rtol=1e-9, atol=1e-12,
+                    dense_output=True)
+    rt = sol.t_events[0][0]
+    r = np.linspace(r0, rt, 20001)
+    W, dW = sol.sol(r)
+    return r, np.maximum(W, 0.0), r * r * (-dW)
+
+
+def king(n, seed, W0=6.0, M=1.0, r0=1.0, G=1.0):
+    """Equal-mass King model with central potential W0 and King radius r0:
+    radii from the enclosed-mass profile, speeds by rejection from the
+    lowered-isothermal distribution function f ~ exp(W - v^2/2) - 1."""
+    rng = _rng(seed)
+    r, W, mu = _king_profile(W0)
+    mu_t = mu[-1]
+    sigma = np.sqrt(G * M / (r0 * mu_t))       # velocity unit
+    u = rng.uniform(0.0, mu_t, n)
+    rad = np.interp(u, mu, r)
+    Wr = np.interp(rad, r, W)
+    ux, uy, uz = _isotropic(rng, n)
+    v = np.empty(n)
+    todo = np.arange(n)
+    while todo.size:
+        w = Wr[todo]
+        vmax = np.sqrt(2.0 * w)
+        vv = rng.uniform(0.0, 1.0, todo.size) * vmax
+        # bound of v^2 (e^(W - v^2/2) - 1) on [0, vmax]: below W e^W
+        g = vv * vv * np.expm1(w - 0.5 * vv * vv)
+        ok = rng.uniform(0.0, 1.0, todo.size) * (2.0 * w * np.exp(w) + 1e-300) < g
+        v[todo[ok]] = vv[ok]
+        todo = todo[~ok]
+    wx, wy, wz = _isotropic(rng, n)
+    m = np.full(n, M / n)
+    return _pack(r0 * rad * ux, r0 * rad * uy, r0 * rad * uz,
+                 sigma * v * wx, sigma * v * wy, sigma * v * wz, m)
+
+
+def clusters(n_sys, seed, lo_exp=10, hi_exp=18):
+    """Independent clusters: N_k = round(2^U), U ~ U[lo_exp, hi_exp]; each
+    a Plummer or a King (W0 = 6) model by a fair coin, mass 1, scale 1.
+    Returns the concatenated arrays and the system offsets."""
+    rng = _rng(seed)
+    sizes = np.round(2.0 ** rng.uniform(lo_exp, hi_exp, n_sys)).astype(int)
+    kinds = rng.integers(0, 2, n_sys)
+    parts = []
+    for k in range(n_sys):
+        sub = int(rng.integers(0, 2 ** 62))
+        parts.append(plummer(int(sizes[k]), sub) if kinds[k] == 0 else
+                     king(int(sizes[k]), sub))
+    out = {key: np.concatenate([p[key] for p in parts]) for key in parts[0]}
+    out["offsets"] = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    out["kinds"] = np.where(kinds == 0, "plummer", "king")
+    return out
+
+
 # Named workloads: (generator, kwargs) plus run parameters.
 def make(name, n=None, seed=None, replicate=0):
     """Build one of the named workloads.
@@ -218,6 +305,8 @@ def make(name, n=None, seed=None, replicate=0):
                  every 4 steps, dt 1/128; n_grp 256, the fastest step of a
                  sweep over 32..1024 on MI355X)
     ring_8m      ring N=2^23 (eps 1e-4, dt 2 pi/256, central mass 1)
+    clusters_64  64 independent Plummer / King(W0 = 6) clusters, N log-uniform
+                 in [2^10, 2^18] (eps 0.01, dt 1/128)
     sphere_4m    cold uniform sphere N=2^22 (leaf 16)
     ``n`` overrides the particle count (same recipe, smaller system).
     """
@@ -243,6 +332,10 @@ def make(name, n=None, seed=None, replicate=0):
         return ring(nn, s), dict(eps=1e-4, theta=0.5, order=1, n_leaf=8,
                                  n_grp=64, dt=2.0 * np.pi / 256,
                                  ext_mass=1.0)
+    if name == "clusters_64":
+        s = seed if seed is not None else seed_for(5, replicate)
+        return clusters(64, s), dict(eps=0.01, theta=0.5, order=1, n_leaf=8,
+                                     n_grp=64, dt=1.0 / 128, reuse=4)
     if name == "sphere_4m":
         nn = n or (1 << 22)
         s = seed if seed is not None else seed_for(6, replicate)
