@@ -26,6 +26,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "orc.c")
+_SRC_MLP = os.path.join(_HERE, "mlp.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 _lib = None
 
@@ -37,7 +38,7 @@ def build_lib(force: bool = True) -> str:
     tmp = _LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off",
            "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-Wno-unused-parameter", _SRC, "-o", tmp, "-lm"]
+           "-Wno-unused-parameter", _SRC, _SRC_MLP, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
     return _LIB
@@ -75,11 +76,19 @@ def _load():
     lib.orc_force_direct.argtypes = [i64, p, p, p, p, d, d, i64, p, p, p, p, p]
     lib.orc_kick_drift.argtypes = [i64, p, p, p, p, p, p, p, p, p, d, d, d, d]
     lib.orc_num_threads.argtypes = []
+    lib.orc_group_margins.argtypes = [p, d, p, p]
+    lib.orc_group_stale.argtypes = [p, d, p, p, p, p, p, p]
+    lib.orc_mlp_nparam.argtypes = []
+    lib.orc_mlp_forward.argtypes = [p, i64, p, p]
+    lib.orc_mlp_loss_grad.argtypes = [p, i64, p, p, p, p]
+    lib.orc_adam.argtypes = [p, p, p, p, i64, d, d, d, d]
     for f in ("orc_root", "orc_keys", "orc_info", "orc_get_keys",
               "orc_get_cells", "orc_get_moments", "orc_get_groups",
               "orc_make_lists", "orc_get_lists", "orc_refresh",
               "orc_force_lists", "orc_force_direct", "orc_kick_drift",
-              "orc_num_threads"):
+              "orc_num_threads", "orc_group_margins", "orc_group_stale",
+              "orc_mlp_nparam", "orc_mlp_forward", "orc_mlp_loss_grad",
+              "orc_adam"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -223,6 +232,26 @@ class Tree:
         _check(_load().orc_refresh(self._h, _ptr(self._x), _ptr(self._y),
                                    _ptr(self._z), _ptr(self._m)), "refresh")
 
+    def margins(self, theta):
+        """Opening-test margins (amin, omax) of every group's walk."""
+        amin = np.zeros(self.n_groups)
+        omax = np.zeros(self.n_groups)
+        _check(_load().orc_group_margins(self._h, float(theta), _ptr(amin),
+                                         _ptr(omax)), "margins")
+        return amin, omax
+
+    def stale(self, theta, x, y, z):
+        """Groups whose walk with the current box (positions in input
+        order) gives another list than the kept one; also the boxes."""
+        x, y, z = _f64(x), _f64(y), _f64(z)
+        st = np.zeros(self.n_groups, np.uint8)
+        lo = np.zeros((self.n_groups, 3))
+        hi = np.zeros((self.n_groups, 3))
+        _check(_load().orc_group_stale(self._h, float(theta), _ptr(x),
+                                       _ptr(y), _ptr(z), _ptr(st), _ptr(lo),
+                                       _ptr(hi)), "stale")
+        return st.astype(bool), lo, hi
+
     def force_lists(self, order=1, eps=0.0, G=1.0):
         """FP64 sum over the saved lists; NaN for particles of groups that
         were not walked.  Input order."""
@@ -231,6 +260,40 @@ class Tree:
                                        float(G), *(_ptr(a) for a in out)),
                "force_lists")
         return tuple(out)
+
+
+def mlp_nparam() -> int:
+    return int(_load().orc_mlp_nparam())
+
+
+def mlp_forward(w, x):
+    w = _f64(w)
+    x = _f64(x).reshape(-1, 12)
+    p = np.zeros(x.shape[0])
+    _check(_load().orc_mlp_forward(_ptr(w), x.shape[0], _ptr(x), _ptr(p)),
+           "mlp_forward")
+    return p
+
+
+def mlp_loss_grad(w, x, y):
+    w = _f64(w)
+    x = _f64(x).reshape(-1, 12)
+    y = _f64(y)
+    loss = np.zeros(1)
+    g = np.zeros(mlp_nparam())
+    _check(_load().orc_mlp_loss_grad(_ptr(w), x.shape[0], _ptr(x), _ptr(y),
+                                     _ptr(loss), _ptr(g)), "mlp_loss_grad")
+    return float(loss[0]), g
+
+
+def adam(w, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step in place on w, m, v (FP64 arrays)."""
+    for a in (w, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    _check(_load().orc_adam(_ptr(w), _ptr(g), _ptr(m), _ptr(v), int(t),
+                            float(lr), float(beta1), float(beta2), float(eps)),
+           "adam")
 
 
 def force_direct(x, y, z, m, eps=0.0, G=1.0, targets=None):

@@ -490,17 +490,25 @@ int orc_get_groups(const orc_tree* t, uint32_t* cell, uint32_t* begin,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Opening-test margins of a walk: the smallest d^2 / rcrit^2 over accepted
+ * cells (>= 1 when any) and the largest over opened cells that do not hold
+ * the group (< 1).  A list stays what a new walk would make as long as no
+ * cell crosses d^2 = rcrit^2. */
+typedef struct {
+  double amin, omax;
+} orc_margin;
+
 /* Group tree walk (section 4.3 "construct the interaction lists"; indirect
  * addressing of section 4.1: the lists hold 32-bit indices).  Reading R6.
  * DFS from the root over the pre-order cell array; `skip` jumps over a
  * subtree.  When `fill` is zero only the list lengths are counted. */
-static void walk_group(const orc_tree* t, int64_t g, const double* rcrit2,
-                       int fill, uint32_t* epj, uint32_t* spj, int64_t* n_epj,
-                       int64_t* n_spj) {
+static void walk_box(const orc_tree* t, int64_t g, const double* glo,
+                     const double* ghi, const double* rcrit2, int fill,
+                     uint32_t* epj, uint32_t* spj, int64_t* n_epj,
+                     int64_t* n_spj, orc_margin* mg) {
   const uint32_t gb = t->g_begin[g];
   const uint64_t ge = (uint64_t)gb + t->g_count[g];
-  const double* glo = &t->g_lo[3 * g];
-  const double* ghi = &t->g_hi[3 * g];
+  double amin = INFINITY, omax = -INFINITY;
   int64_t ne = 0, ns = 0;
   int64_t c = 0;
   while (c < t->n_cell) {
@@ -521,7 +529,14 @@ static void walk_group(const orc_tree* t, int64_t g, const double* rcrit2,
         d[a] = v;
       }
       const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-      open = !(d2 > rcrit2[t->level[c]]);
+      const double rc = rcrit2[t->level[c]];
+      open = !(d2 > rc);
+      const double ratio = d2 / rc;
+      if (open) {
+        if (ratio > omax) omax = ratio;
+      } else if (ratio < amin) {
+        amin = ratio;
+      }
     }
     if (!open) {
       if (fill) spj[ns] = (uint32_t)c;
@@ -539,6 +554,96 @@ static void walk_group(const orc_tree* t, int64_t g, const double* rcrit2,
   }
   *n_epj = ne;
   *n_spj = ns;
+  if (mg) {
+    mg->amin = amin;
+    mg->omax = omax;
+  }
+}
+
+static void walk_group(const orc_tree* t, int64_t g, const double* rcrit2,
+                       int fill, uint32_t* epj, uint32_t* spj, int64_t* n_epj,
+                       int64_t* n_spj) {
+  walk_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g], rcrit2, fill, epj, spj,
+           n_epj, n_spj, NULL);
+}
+
+static void crit_radii(const orc_tree* t, double theta, double* rcrit2) {
+  for (int l = 0; l <= MAX_LEVEL; ++l) {
+    const double r = ldexp(1.0, t->k - l) / theta;
+    rcrit2[l] = r * r;
+  }
+}
+
+/* Opening-test margins of every group's build-time walk (see orc_margin);
+ * amin = +inf when nothing was accepted, omax = -inf when nothing but the
+ * group's own ancestors and cells was opened. */
+int orc_group_margins(const orc_tree* t, double theta, double* amin,
+                      double* omax) {
+  if (!t || !amin || !omax || theta < 0.0) return -1;
+  double rcrit2[MAX_LEVEL + 1];
+  crit_radii(t, theta, rcrit2);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t g = 0; g < t->n_groups; ++g) {
+    int64_t a, b;
+    orc_margin mg;
+    walk_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g], rcrit2, 0, NULL, NULL,
+             &a, &b, &mg);
+    amin[g] = mg.amin;
+    omax[g] = mg.omax;
+  }
+  return 0;
+}
+
+/* Staleness after particles moved (reuse steps, section 4.2): for every
+ * group, walk the frozen tree (cells, centres, skip ids as built) with the
+ * group's CURRENT tight box, taken from positions x, y, z in input order,
+ * and report whether that list differs from the kept one (needs lists of
+ * every group from orc_make_lists).  Also returns the current boxes. */
+int orc_group_stale(const orc_tree* t, double theta, const double* x,
+                    const double* y, const double* z, uint8_t* stale,
+                    double* lo3, double* hi3) {
+  if (!t || !x || !y || !z || !stale || !t->have_lists ||
+      t->n_sel != t->n_groups)
+    return -1;
+  double rcrit2[MAX_LEVEL + 1];
+  crit_radii(t, theta, rcrit2);
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+  for (int64_t g = 0; g < t->n_groups; ++g) {
+    const int64_t b = t->g_begin[g], e = b + t->g_count[g];
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      const double* p = a == 0 ? x : (a == 1 ? y : z);
+      lo[a] = hi[a] = p[t->perm[b]];
+      for (int64_t i = b + 1; i < e; ++i) {
+        const double v = p[t->perm[i]];
+        if (v < lo[a]) lo[a] = v;
+        if (v > hi[a]) hi[a] = v;
+      }
+    }
+    if (lo3) memcpy(&lo3[3 * g], lo, sizeof lo);
+    if (hi3) memcpy(&hi3[3 * g], hi, sizeof hi);
+    int64_t ne, ns;
+    walk_box(t, g, lo, hi, rcrit2, 0, NULL, NULL, &ne, &ns, NULL);
+    const int64_t oe = t->epj_off[g + 1] - t->epj_off[g];
+    const int64_t os = t->spj_off[g + 1] - t->spj_off[g];
+    int differs = ne != oe || ns != os;
+    if (!differs) {
+      uint32_t* ee = (uint32_t*)malloc((size_t)(ne + 1) * sizeof(uint32_t));
+      uint32_t* ss = (uint32_t*)malloc((size_t)(ns + 1) * sizeof(uint32_t));
+      if (!ee || !ss) {
+        bad = 1;
+      } else {
+        walk_box(t, g, lo, hi, rcrit2, 1, ee, ss, &ne, &ns, NULL);
+        differs = memcmp(ee, t->epj + t->epj_off[g], (size_t)ne * 4) != 0 ||
+                  memcmp(ss, t->spj + t->spj_off[g], (size_t)ns * 4) != 0;
+      }
+      free(ee);
+      free(ss);
+    }
+    stale[g] = (uint8_t)differs;
+  }
+  return bad ? -1 : 0;
 }
 
 int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
@@ -559,10 +664,7 @@ int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
   }
   /* critical radius per level: (s_l / theta)^2 with s_l = L 2^-l */
   double rcrit2[MAX_LEVEL + 1];
-  for (int l = 0; l <= MAX_LEVEL; ++l) {
-    const double r = ldexp(1.0, t->k - l) / theta;
-    rcrit2[l] = r * r;
-  }
+  crit_radii(t, theta, rcrit2);
   /* count pass */
   int64_t* ne = (int64_t*)malloc((size_t)(ns_all ? ns_all : 1) * sizeof(int64_t));
   int64_t* ns = (int64_t*)malloc((size_t)(ns_all ? ns_all : 1) * sizeof(int64_t));

@@ -59,6 +59,29 @@ int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
 int orc_get_lists(const orc_tree* t, int64_t* epj_off, uint32_t* epj,
                   int64_t* spj_off, uint32_t* spj);
 
+/* Opening-test margins of the build-time walk of every group: amin = the
+ * smallest d^2/rcrit^2 over accepted cells (+inf if none), omax = the
+ * largest over opened cells that do not hold the group (-inf if none). */
+int orc_group_margins(const orc_tree* t, double theta, double* amin,
+                      double* omax);
+
+/* For every group, walk the frozen tree with the group's current tight box
+ * (positions in INPUT order) and flag the group when that list differs from
+ * the kept one (lists of all groups required).  lo3/hi3 may be NULL. */
+int orc_group_stale(const orc_tree* t, double theta, const double* x,
+                    const double* y, const double* z, uint8_t* stale,
+                    double* lo3, double* hi3);
+
+/* Rebuild predictor (mlp.c): 12-64-64-1 perceptron, tanh hidden layers,
+ * logistic output, mean binary cross-entropy, Adam.  Parameter layout:
+ * W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3. */
+int orc_mlp_nparam(void);
+int orc_mlp_forward(const double* w, int64_t n, const double* x, double* p);
+int orc_mlp_loss_grad(const double* w, int64_t n, const double* x,
+                      const double* y, double* loss, double* grad);
+int orc_adam(double* w, const double* g, double* m, double* v, int64_t t,
+             double lr, double beta1, double beta2, double eps);
+
 /* Reuse step (section 4.2): new positions/masses in INPUT order; the tree
  * topology, cell geometry, groups and lists stay frozen, moments are
  * recomputed over the frozen particle ranges. */
