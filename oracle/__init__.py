@@ -76,18 +76,20 @@ def _load():
     lib.orc_force_direct.argtypes = [i64, p, p, p, p, d, d, i64, p, p, p, p, p]
     lib.orc_kick_drift.argtypes = [i64, p, p, p, p, p, p, p, p, p, d, d, d, d]
     lib.orc_num_threads.argtypes = []
-    lib.orc_group_margins.argtypes = [p, d, p, p]
-    lib.orc_group_stale.argtypes = [p, d, p, p, p, p, p, p]
+    lib.orc_group_margins.argtypes = [p, p, p]
+    lib.orc_group_stale.argtypes = [p, d, p, p, p]
+    lib.orc_refresh_lists.argtypes = [p, d, i64, p, p]
+    lib.orc_group_features.argtypes = [p, C.c_int, p, p]
     lib.orc_mlp_nparam.argtypes = []
     lib.orc_mlp_forward.argtypes = [p, i64, p, p]
-    lib.orc_mlp_loss_grad.argtypes = [p, i64, p, p, p, p]
+    lib.orc_mlp_loss_grad.argtypes = [p, i64, p, p, d, p, p]
     lib.orc_adam.argtypes = [p, p, p, p, i64, d, d, d, d]
     for f in ("orc_root", "orc_keys", "orc_info", "orc_get_keys",
               "orc_get_cells", "orc_get_moments", "orc_get_groups",
               "orc_make_lists", "orc_get_lists", "orc_refresh",
               "orc_force_lists", "orc_force_direct", "orc_kick_drift",
               "orc_num_threads", "orc_group_margins", "orc_group_stale",
-              "orc_mlp_nparam", "orc_mlp_forward", "orc_mlp_loss_grad",
+              "orc_refresh_lists", "orc_group_features", "orc_mlp_nparam", "orc_mlp_forward", "orc_mlp_loss_grad",
               "orc_adam"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -232,25 +234,43 @@ class Tree:
         _check(_load().orc_refresh(self._h, _ptr(self._x), _ptr(self._y),
                                    _ptr(self._z), _ptr(self._m)), "refresh")
 
-    def margins(self, theta):
-        """Opening-test margins (amin, omax) of every group's walk."""
-        amin = np.zeros(self.n_groups)
-        omax = np.zeros(self.n_groups)
-        _check(_load().orc_group_margins(self._h, float(theta), _ptr(amin),
-                                         _ptr(omax)), "margins")
-        return amin, omax
+    def margins(self):
+        """Opening-test slacks (sa, so) of the walk that made each group's
+        list, in length units (+inf where no cell of that kind)."""
+        sa = np.zeros(self.n_groups)
+        so = np.zeros(self.n_groups)
+        _check(_load().orc_group_margins(self._h, _ptr(sa), _ptr(so)),
+               "margins")
+        return sa, so
 
-    def stale(self, theta, x, y, z):
-        """Groups whose walk with the current box (positions in input
-        order) gives another list than the kept one; also the boxes."""
-        x, y, z = _f64(x), _f64(y), _f64(z)
+    def stale(self, theta):
+        """Groups whose walk with their current box and the current cell
+        centres gives another list than the kept one; also the boxes."""
         st = np.zeros(self.n_groups, np.uint8)
         lo = np.zeros((self.n_groups, 3))
         hi = np.zeros((self.n_groups, 3))
-        _check(_load().orc_group_stale(self._h, float(theta), _ptr(x),
-                                       _ptr(y), _ptr(z), _ptr(st), _ptr(lo),
-                                       _ptr(hi)), "stale")
+        _check(_load().orc_group_stale(self._h, float(theta), _ptr(st),
+                                       _ptr(lo), _ptr(hi)), "stale")
         return st.astype(bool), lo, hi
+
+    def refresh_lists(self, theta, sel):
+        """Walk the listed groups again with their current boxes."""
+        sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
+        sizes = np.zeros(3, np.int64)
+        _check(_load().orc_refresh_lists(self._h, float(theta), sel.size,
+                                         _ptr(sel), _ptr(sizes)),
+               "refresh_lists")
+        self._sizes = sizes.copy()
+        return int(sizes[0]), int(sizes[1]), int(sizes[2])
+
+    def features(self, kmax, age):
+        """The 12 rebuild-predictor inputs per group (FP64, [G, 12])."""
+        age = np.ascontiguousarray(np.asarray(age, dtype=np.int32))
+        assert age.shape == (self.n_groups,)
+        f = np.zeros((self.n_groups, 12))
+        _check(_load().orc_group_features(self._h, int(kmax), _ptr(age),
+                                          _ptr(f)), "features")
+        return f
 
     def force_lists(self, order=1, eps=0.0, G=1.0):
         """FP64 sum over the saved lists; NaN for particles of groups that
@@ -275,14 +295,15 @@ def mlp_forward(w, x):
     return p
 
 
-def mlp_loss_grad(w, x, y):
+def mlp_loss_grad(w, x, y, pos_weight=1.0):
     w = _f64(w)
     x = _f64(x).reshape(-1, 12)
     y = _f64(y)
     loss = np.zeros(1)
     g = np.zeros(mlp_nparam())
     _check(_load().orc_mlp_loss_grad(_ptr(w), x.shape[0], _ptr(x), _ptr(y),
-                                     _ptr(loss), _ptr(g)), "mlp_loss_grad")
+                                     float(pos_weight), _ptr(loss), _ptr(g)),
+           "mlp_loss_grad")
     return float(loss[0]), g
 
 

@@ -11,7 +11,8 @@
  *   W1 [64][12] row-major, b1 [64], W2 [64][64] row-major, b2 [64],
  *   w3 [64], b3 [1].
  *   h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), p = 1 / (1 + exp(-(w3.h2 + b3)))
- *   loss = -(1/n) sum_i [y_i log p_i + (1 - y_i) log(1 - p_i)]
+ *   loss = -(1/n) sum_i [w y_i log p_i + (1 - y_i) log(1 - p_i)],
+ *   w = pos_weight (1 for the plain cross-entropy)
  */
 #include <math.h>
 #include <stdint.h>
@@ -56,8 +57,10 @@ int orc_mlp_forward(const double* w, int64_t n, const double* x, double* p) {
 
 /* Mean cross-entropy and its gradient by back-propagation. */
 int orc_mlp_loss_grad(const double* w, int64_t n, const double* x,
-                      const double* y, double* loss, double* grad) {
-  if (!w || n <= 0 || !x || !y || !loss || !grad) return -1;
+                      const double* y, double pos_weight, double* loss,
+                      double* grad) {
+  if (!w || n <= 0 || !x || !y || !loss || !grad || !(pos_weight > 0.0))
+    return -1;
   memset(grad, 0, sizeof(double) * MLP_NPARAM);
   double h1[NH], h2[NH], d2[NH], d1[NH], p;
   double L = 0.0;
@@ -65,9 +68,11 @@ int orc_mlp_loss_grad(const double* w, int64_t n, const double* x,
     const double* xi = x + NIN * i;
     forward_one(w, xi, h1, h2, &p);
     const double pc = p < 1e-300 ? 1e-300 : (p > 1.0 - 1e-16 ? 1.0 - 1e-16 : p);
-    L -= y[i] * log(pc) + (1.0 - y[i]) * log(1.0 - pc);
-    /* dL/dz for the logistic output with cross-entropy */
-    const double dz = (p - y[i]) / (double)n;
+    L -= pos_weight * y[i] * log(pc) + (1.0 - y[i]) * log(1.0 - pc);
+    /* dL/dz of the weighted cross-entropy through the logistic output:
+     * p (w y + 1 - y) - w y  (= p - y when w = 1) */
+    const double wy = pos_weight * y[i];
+    const double dz = (p * (wy + 1.0 - y[i]) - wy) / (double)n;
     grad[OFF_B3] += dz;
     for (int k = 0; k < NH; ++k) {
       grad[OFF_W3 + k] += dz * h2[k];

@@ -65,11 +65,15 @@ struct orc_tree {
   double* ctr; /* 3 per cell */
   double* mass;
   double* com;  /* 3 per cell */
+  double* com0; /* 3 per cell: centres of mass at construction */
   double* quad; /* 6 per cell: xx yy zz xy xz yz */
-  /* groups */
+  /* groups; g_lo/g_hi is the box the group's current list was walked
+   * with (the construction-time box until a list refresh) */
   int64_t n_groups;
   uint32_t *g_cell, *g_begin, *g_count;
   double *g_lo, *g_hi, *g_ctr; /* 3 per group */
+  double* g_tau0;              /* 3 per group: cell shift at that walk */
+  double *g_sa, *g_so;         /* opening-test slacks of that walk */
   /* lists over the last walked selection */
   int have_lists;
   int64_t n_sel;
@@ -298,8 +302,11 @@ static int make_groups(orc_tree* t) {
   t->g_lo = (double*)malloc((size_t)(ng ? ng : 1) * 3 * sizeof(double));
   t->g_hi = (double*)malloc((size_t)(ng ? ng : 1) * 3 * sizeof(double));
   t->g_ctr = (double*)malloc((size_t)(ng ? ng : 1) * 3 * sizeof(double));
+  t->g_tau0 = (double*)calloc((size_t)(ng ? ng : 1) * 3, sizeof(double));
+  t->g_sa = (double*)malloc((size_t)(ng ? ng : 1) * sizeof(double));
+  t->g_so = (double*)malloc((size_t)(ng ? ng : 1) * sizeof(double));
   if (!t->g_cell || !t->g_begin || !t->g_count || !t->g_lo || !t->g_hi ||
-      !t->g_ctr)
+      !t->g_ctr || !t->g_tau0 || !t->g_sa || !t->g_so)
     return -1;
   int64_t g = 0;
   for (int64_t c = 0; c < t->n_cell; ++c) {
@@ -307,6 +314,7 @@ static int make_groups(orc_tree* t) {
     const int top = c == 0 || t->count[t->parent[c]] > (uint32_t)t->n_grp;
     if (!(small && top)) continue;
     t->g_cell[g] = (uint32_t)c;
+    t->g_sa[g] = t->g_so[g] = INFINITY;
     t->g_begin[g] = t->begin[c];
     t->g_count[g] = t->count[c];
     const int64_t b = t->begin[c], e = b + t->count[c];
@@ -357,6 +365,7 @@ void orc_free(orc_tree* t) {
   free(t->ctr);
   free(t->mass);
   free(t->com);
+  free(t->com0);
   free(t->quad);
   free(t->g_cell);
   free(t->g_begin);
@@ -364,6 +373,9 @@ void orc_free(orc_tree* t) {
   free(t->g_lo);
   free(t->g_hi);
   free(t->g_ctr);
+  free(t->g_tau0);
+  free(t->g_sa);
+  free(t->g_so);
   free_lists(t);
   free(t);
 }
@@ -421,9 +433,11 @@ orc_tree* orc_build(int64_t n, const double* x, const double* y,
   if (link_cell(t, 0, 0, n, 0xFFFFFFFFu)) goto fail;
   t->mass = (double*)malloc((size_t)t->n_cell * sizeof(double));
   t->com = (double*)malloc((size_t)t->n_cell * 3 * sizeof(double));
+  t->com0 = (double*)malloc((size_t)t->n_cell * 3 * sizeof(double));
   t->quad = (double*)malloc((size_t)t->n_cell * 6 * sizeof(double));
-  if (!t->mass || !t->com || !t->quad) goto fail;
+  if (!t->mass || !t->com || !t->com0 || !t->quad) goto fail;
   compute_moments(t);
+  memcpy(t->com0, t->com, (size_t)t->n_cell * 3 * sizeof(double));
   if (make_groups(t)) goto fail;
   return t;
 fail:
@@ -490,13 +504,24 @@ int orc_get_groups(const orc_tree* t, uint32_t* cell, uint32_t* begin,
 }
 
 /* ---------------------------------------------------------------------- */
-/* Opening-test margins of a walk: the smallest d^2 / rcrit^2 over accepted
- * cells (>= 1 when any) and the largest over opened cells that do not hold
- * the group (< 1).  A list stays what a new walk would make as long as no
- * cell crosses d^2 = rcrit^2. */
+/* Opening-test slack of a walk, in length units: sa = the smallest
+ * |box - centre| - rcrit over accepted cells, so = the smallest
+ * rcrit - |box - centre| over opened cells that do not hold the group
+ * (+inf when there is none).  No cell changes side before the box or a
+ * centre has moved by the slack. */
 typedef struct {
-  double amin, omax;
-} orc_margin;
+  double sa, so;
+} orc_slack;
+
+/* Centre of cell c for the opening test.  Reuse with per-group list
+ * refresh (an extension; the paper reuses whole lists, section 4.2): cells
+ * keep their particle ranges and each cell's geometric centre is carried
+ * along by the displacement of its centre of mass since construction, so
+ * that a rigid motion changes no list.  Right after construction the
+ * displacement is exactly zero and the test is the plain one. */
+static void cell_shift(const orc_tree* t, int64_t c, double tr[3]) {
+  for (int a = 0; a < 3; ++a) tr[a] = t->com[3 * c + a] - t->com0[3 * c + a];
+}
 
 /* Group tree walk (section 4.3 "construct the interaction lists"; indirect
  * addressing of section 4.1: the lists hold 32-bit indices).  Reading R6.
@@ -505,10 +530,10 @@ typedef struct {
 static void walk_box(const orc_tree* t, int64_t g, const double* glo,
                      const double* ghi, const double* rcrit2, int fill,
                      uint32_t* epj, uint32_t* spj, int64_t* n_epj,
-                     int64_t* n_spj, orc_margin* mg) {
+                     int64_t* n_spj, orc_slack* mg) {
   const uint32_t gb = t->g_begin[g];
   const uint64_t ge = (uint64_t)gb + t->g_count[g];
-  double amin = INFINITY, omax = -INFINITY;
+  double sa = INFINITY, so = INFINITY;
   int64_t ne = 0, ns = 0;
   int64_t c = 0;
   while (c < t->n_cell) {
@@ -518,9 +543,10 @@ static void walk_box(const orc_tree* t, int64_t g, const double* glo,
     if (cb <= gb && ce >= ge) {
       open = 1; /* the cell holds the group */
     } else {
-      double d[3];
+      double tr[3], d[3];
+      cell_shift(t, c, tr);
       for (int a = 0; a < 3; ++a) {
-        const double cc = t->ctr[3 * c + a];
+        const double cc = t->ctr[3 * c + a] + tr[a];
         double v = 0.0;
         const double below = glo[a] - cc;
         const double above = cc - ghi[a];
@@ -531,11 +557,13 @@ static void walk_box(const orc_tree* t, int64_t g, const double* glo,
       const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
       const double rc = rcrit2[t->level[c]];
       open = !(d2 > rc);
-      const double ratio = d2 / rc;
-      if (open) {
-        if (ratio > omax) omax = ratio;
-      } else if (ratio < amin) {
-        amin = ratio;
+      if (mg) {
+        const double dd = sqrt(d2), rr = sqrt(rc);
+        if (open) {
+          if (rr - dd < so) so = rr - dd;
+        } else if (dd - rr < sa) {
+          sa = dd - rr;
+        }
       }
     }
     if (!open) {
@@ -555,16 +583,9 @@ static void walk_box(const orc_tree* t, int64_t g, const double* glo,
   *n_epj = ne;
   *n_spj = ns;
   if (mg) {
-    mg->amin = amin;
-    mg->omax = omax;
+    mg->sa = sa;
+    mg->so = so;
   }
-}
-
-static void walk_group(const orc_tree* t, int64_t g, const double* rcrit2,
-                       int fill, uint32_t* epj, uint32_t* spj, int64_t* n_epj,
-                       int64_t* n_spj) {
-  walk_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g], rcrit2, fill, epj, spj,
-           n_epj, n_spj, NULL);
 }
 
 static void crit_radii(const orc_tree* t, double theta, double* rcrit2) {
@@ -574,53 +595,59 @@ static void crit_radii(const orc_tree* t, double theta, double* rcrit2) {
   }
 }
 
-/* Opening-test margins of every group's build-time walk (see orc_margin);
- * amin = +inf when nothing was accepted, omax = -inf when nothing but the
- * group's own ancestors and cells was opened. */
-int orc_group_margins(const orc_tree* t, double theta, double* amin,
-                      double* omax) {
-  if (!t || !amin || !omax || theta < 0.0) return -1;
-  double rcrit2[MAX_LEVEL + 1];
-  crit_radii(t, theta, rcrit2);
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t g = 0; g < t->n_groups; ++g) {
-    int64_t a, b;
-    orc_margin mg;
-    walk_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g], rcrit2, 0, NULL, NULL,
-             &a, &b, &mg);
-    amin[g] = mg.amin;
-    omax[g] = mg.omax;
+/* Tight box of group g's particles at their current positions. */
+static void group_box(const orc_tree* t, int64_t g, double lo[3],
+                      double hi[3]) {
+  const int64_t b = t->g_begin[g], e = b + t->g_count[g];
+  const double* p[3] = {t->x, t->y, t->z};
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = hi[a] = p[a][b];
+    for (int64_t i = b + 1; i < e; ++i) {
+      if (p[a][i] < lo[a]) lo[a] = p[a][i];
+      if (p[a][i] > hi[a]) hi[a] = p[a][i];
+    }
   }
+}
+
+/* Walk group g with box (lo, hi) and record what the features need. */
+static void walk_record(orc_tree* t, int64_t g, const double* rcrit2,
+                        int fill, uint32_t* epj, uint32_t* spj, int64_t* ne,
+                        int64_t* ns) {
+  orc_slack mg;
+  walk_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g], rcrit2, fill, epj, spj,
+           ne, ns, &mg);
+  if (!fill) {
+    t->g_sa[g] = mg.sa;
+    t->g_so[g] = mg.so;
+    cell_shift(t, t->g_cell[g], &t->g_tau0[3 * g]);
+  }
+}
+
+int orc_group_margins(const orc_tree* t, double* sa, double* so) {
+  if (!t || !sa || !so) return -1;
+  memcpy(sa, t->g_sa, (size_t)t->n_groups * sizeof(double));
+  memcpy(so, t->g_so, (size_t)t->n_groups * sizeof(double));
   return 0;
 }
 
-/* Staleness after particles moved (reuse steps, section 4.2): for every
- * group, walk the frozen tree (cells, centres, skip ids as built) with the
- * group's CURRENT tight box, taken from positions x, y, z in input order,
- * and report whether that list differs from the kept one (needs lists of
- * every group from orc_make_lists).  Also returns the current boxes. */
-int orc_group_stale(const orc_tree* t, double theta, const double* x,
-                    const double* y, const double* z, uint8_t* stale,
+static int full_lists(const orc_tree* t) {
+  return t->have_lists && t->n_sel == t->n_groups;
+}
+
+/* Staleness of a kept list (reuse steps): walk the tree with the group's
+ * current tight box and the current cell centres and report whether that
+ * list differs from the kept one (needs lists of every group).  Also
+ * returns the current boxes. */
+int orc_group_stale(const orc_tree* t, double theta, uint8_t* stale,
                     double* lo3, double* hi3) {
-  if (!t || !x || !y || !z || !stale || !t->have_lists ||
-      t->n_sel != t->n_groups)
-    return -1;
+  if (!t || !stale || !full_lists(t)) return -1;
   double rcrit2[MAX_LEVEL + 1];
   crit_radii(t, theta, rcrit2);
   int bad = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
   for (int64_t g = 0; g < t->n_groups; ++g) {
-    const int64_t b = t->g_begin[g], e = b + t->g_count[g];
     double lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-      const double* p = a == 0 ? x : (a == 1 ? y : z);
-      lo[a] = hi[a] = p[t->perm[b]];
-      for (int64_t i = b + 1; i < e; ++i) {
-        const double v = p[t->perm[i]];
-        if (v < lo[a]) lo[a] = v;
-        if (v > hi[a]) hi[a] = v;
-      }
-    }
+    group_box(t, g, lo, hi);
     if (lo3) memcpy(&lo3[3 * g], lo, sizeof lo);
     if (hi3) memcpy(&hi3[3 * g], hi, sizeof hi);
     int64_t ne, ns;
@@ -644,6 +671,143 @@ int orc_group_stale(const orc_tree* t, double theta, const double* x,
     stale[g] = (uint8_t)differs;
   }
   return bad ? -1 : 0;
+}
+
+/* Per-group list refresh: the listed groups (ascending ids) get their box
+ * set to the current tight box and their list walked again; every other
+ * list is kept as it is. */
+int orc_refresh_lists(orc_tree* t, double theta, int64_t n_sel,
+                      const int64_t* sel, int64_t sizes[3]) {
+  if (!t || !sizes || n_sel < 0 || (n_sel > 0 && !sel) || !full_lists(t))
+    return -1;
+  const int64_t G = t->n_groups;
+  uint8_t* pick = (uint8_t*)calloc((size_t)(G ? G : 1), 1);
+  int64_t* ne = (int64_t*)malloc((size_t)(G ? G : 1) * sizeof(int64_t));
+  int64_t* ns = (int64_t*)malloc((size_t)(G ? G : 1) * sizeof(int64_t));
+  int64_t* eo = (int64_t*)malloc((size_t)(G + 1) * sizeof(int64_t));
+  int64_t* so = (int64_t*)malloc((size_t)(G + 1) * sizeof(int64_t));
+  uint32_t *ee = NULL, *ss = NULL;
+  int rc = -1;
+  if (!pick || !ne || !ns || !eo || !so) goto out;
+  for (int64_t i = 0; i < n_sel; ++i) {
+    if (sel[i] < 0 || sel[i] >= G || (i > 0 && sel[i] <= sel[i - 1])) goto out;
+    pick[sel[i]] = 1;
+  }
+  double rcrit2[MAX_LEVEL + 1];
+  crit_radii(t, theta, rcrit2);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t g = 0; g < G; ++g) {
+    if (pick[g]) {
+      group_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g]);
+      walk_record(t, g, rcrit2, 0, NULL, NULL, &ne[g], &ns[g]);
+    } else {
+      ne[g] = t->epj_off[g + 1] - t->epj_off[g];
+      ns[g] = t->spj_off[g + 1] - t->spj_off[g];
+    }
+  }
+  eo[0] = so[0] = 0;
+  for (int64_t g = 0; g < G; ++g) {
+    eo[g + 1] = eo[g] + ne[g];
+    so[g + 1] = so[g] + ns[g];
+  }
+  ee = (uint32_t*)malloc((size_t)(eo[G] + 1) * sizeof(uint32_t));
+  ss = (uint32_t*)malloc((size_t)(so[G] + 1) * sizeof(uint32_t));
+  if (!ee || !ss) goto out;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t g = 0; g < G; ++g) {
+    if (pick[g]) {
+      int64_t a, b;
+      walk_record(t, g, rcrit2, 1, ee + eo[g], ss + so[g], &a, &b);
+    } else {
+      memcpy(ee + eo[g], t->epj + t->epj_off[g], (size_t)ne[g] * 4);
+      memcpy(ss + so[g], t->spj + t->spj_off[g], (size_t)ns[g] * 4);
+    }
+  }
+  free(t->epj);
+  free(t->spj);
+  free(t->epj_off);
+  free(t->spj_off);
+  t->epj = ee;
+  t->spj = ss;
+  t->epj_off = eo;
+  t->spj_off = so;
+  ee = ss = NULL;
+  eo = so = NULL;
+  sizes[0] = G;
+  sizes[1] = t->epj_off[G];
+  sizes[2] = t->spj_off[G];
+  rc = 0;
+out:
+  free(pick);
+  free(ne);
+  free(ns);
+  free(eo);
+  free(so);
+  free(ee);
+  free(ss);
+  return rc;
+}
+
+/* Ratio a / b capped at 1e6 (0 / 0 = 0, x / 0 = cap). */
+static double capped(double a, double b) {
+  const double cap = 1e6;
+  if (b > 0.0) {
+    const double q = a / b;
+    return q < cap ? q : cap;
+  }
+  return a > 0.0 ? cap : 0.0;
+}
+
+/* The 12 inputs of the rebuild predictor for every group (row-major,
+ * 12 per group).  With s the side of the group's cell, (lo, hi) its current
+ * box, (lo0, hi0), tau0, sa, so the box, cell shift and slacks of the walk
+ * that made its list, dtau = (current cell shift) - tau0:
+ *   e_a   = max(|lo_a - lo0_a - dtau_a|, |hi_a - hi0_a - dtau_a|)
+ *   E = |e|, B = |dtau|, grow = max_a max(0, (hi - lo)_a - (hi0 - lo0)_a)
+ *   f0 = min(age, kmax) / kmax
+ *   f1..f4 = log1p of E/sa, E/so, B/sa, B/so   (ratios capped at 1e6)
+ *   f5, f6 = log1p(E / s), log1p(B / s)
+ *   f7, f8 = log1p of sa/s, so/s                (capped)
+ *   f9 = log1p(grow / s)
+ *   f10 = log2(n_i) / 6, f11 = log2(1 + list length) / 16 */
+int orc_group_features(const orc_tree* t, int kmax, const int32_t* age,
+                       double* feat) {
+  if (!t || kmax < 1 || !age || !feat || !full_lists(t)) return -1;
+  for (int64_t g = 0; g < t->n_groups; ++g) {
+    const uint32_t c = t->g_cell[g];
+    const double s = ldexp(1.0, t->k - t->level[c]);
+    double lo[3], hi[3], tr[3], e[3], dt[3];
+    group_box(t, g, lo, hi);
+    cell_shift(t, c, tr);
+    double grow = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      dt[a] = tr[a] - t->g_tau0[3 * g + a];
+      const double dl = fabs((lo[a] - t->g_lo[3 * g + a]) - dt[a]);
+      const double dh = fabs((hi[a] - t->g_hi[3 * g + a]) - dt[a]);
+      e[a] = dl > dh ? dl : dh;
+      const double w = (hi[a] - lo[a]) - (t->g_hi[3 * g + a] - t->g_lo[3 * g + a]);
+      if (w > grow) grow = w;
+    }
+    const double E = sqrt((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]);
+    const double B = sqrt((dt[0] * dt[0] + dt[1] * dt[1]) + dt[2] * dt[2]);
+    const double sa = t->g_sa[g], so = t->g_so[g];
+    const int64_t nl = (t->epj_off[g + 1] - t->epj_off[g]) +
+                       (t->spj_off[g + 1] - t->spj_off[g]);
+    double* f = feat + 12 * g;
+    f[0] = (double)(age[g] < kmax ? (age[g] > 0 ? age[g] : 0) : kmax) / kmax;
+    f[1] = log1p(capped(E, sa));
+    f[2] = log1p(capped(E, so));
+    f[3] = log1p(capped(B, sa));
+    f[4] = log1p(capped(B, so));
+    f[5] = log1p(E / s);
+    f[6] = log1p(B / s);
+    f[7] = log1p(capped(sa, s));
+    f[8] = log1p(capped(so, s));
+    f[9] = log1p(grow / s);
+    f[10] = log2((double)t->g_count[g]) / 6.0;
+    f[11] = log2(1.0 + (double)nl) / 16.0;
+  }
+  return 0;
 }
 
 int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
@@ -675,7 +839,7 @@ int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
   }
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t s = 0; s < ns_all; ++s)
-    walk_group(t, t->sel[s], rcrit2, 0, NULL, NULL, &ne[s], &ns[s]);
+    walk_record(t, t->sel[s], rcrit2, 0, NULL, NULL, &ne[s], &ns[s]);
   t->epj_off[0] = t->spj_off[0] = 0;
   for (int64_t s = 0; s < ns_all; ++s) {
     t->epj_off[s + 1] = t->epj_off[s] + ne[s];
@@ -690,8 +854,8 @@ int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t s = 0; s < ns_all; ++s) {
     int64_t a, b;
-    walk_group(t, t->sel[s], rcrit2, 1, t->epj + t->epj_off[s],
-               t->spj + t->spj_off[s], &a, &b);
+    walk_record(t, t->sel[s], rcrit2, 1, t->epj + t->epj_off[s],
+                t->spj + t->spj_off[s], &a, &b);
   }
   sizes[0] = ns_all;
   sizes[1] = t->epj_off[ns_all];

@@ -59,26 +59,42 @@ int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
 int orc_get_lists(const orc_tree* t, int64_t* epj_off, uint32_t* epj,
                   int64_t* spj_off, uint32_t* spj);
 
-/* Opening-test margins of the build-time walk of every group: amin = the
- * smallest d^2/rcrit^2 over accepted cells (+inf if none), omax = the
- * largest over opened cells that do not hold the group (-inf if none). */
-int orc_group_margins(const orc_tree* t, double theta, double* amin,
-                      double* omax);
+/* Reuse with per-group list refresh (an extension of section 4.2's list
+ * reuse).  Cells keep their particle ranges; in every opening test the
+ * geometric centre of a cell is moved by the displacement of its centre of
+ * mass since construction (zero right after construction).  Positions come
+ * from the last orc_build / orc_refresh.  All need lists of every group. */
 
-/* For every group, walk the frozen tree with the group's current tight box
- * (positions in INPUT order) and flag the group when that list differs from
- * the kept one (lists of all groups required).  lo3/hi3 may be NULL. */
-int orc_group_stale(const orc_tree* t, double theta, const double* x,
-                    const double* y, const double* z, uint8_t* stale,
+/* Opening-test slacks of the walk that made each group's list: sa = the
+ * smallest |box - centre| - rcrit over accepted cells, so = the smallest
+ * rcrit - |box - centre| over opened cells that do not hold the group;
+ * +inf when there is no such cell. */
+int orc_group_margins(const orc_tree* t, double* sa, double* so);
+
+/* stale[g] = 1 when a walk with the group's current tight box differs from
+ * its kept list.  lo3/hi3 (current boxes) may be NULL. */
+int orc_group_stale(const orc_tree* t, double theta, uint8_t* stale,
                     double* lo3, double* hi3);
+
+/* Walk the n_sel listed groups (ascending ids) again with their current
+ * boxes, keep every other list.  sizes = {n_groups, n_epj, n_spj}. */
+int orc_refresh_lists(orc_tree* t, double theta, int64_t n_sel,
+                      const int64_t* sel, int64_t sizes[3]);
+
+/* The 12 predictor inputs per group (definitions in orc.c); age[g] = reuse
+ * steps since the group's list was walked, kmax >= 1. */
+int orc_group_features(const orc_tree* t, int kmax, const int32_t* age,
+                       double* feat);
 
 /* Rebuild predictor (mlp.c): 12-64-64-1 perceptron, tanh hidden layers,
  * logistic output, mean binary cross-entropy, Adam.  Parameter layout:
- * W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3. */
+ * W1[64][12], b1[64], W2[64][64], b2[64], w3[64], b3.  pos_weight
+ * multiplies the loss terms of positive labels. */
 int orc_mlp_nparam(void);
 int orc_mlp_forward(const double* w, int64_t n, const double* x, double* p);
 int orc_mlp_loss_grad(const double* w, int64_t n, const double* x,
-                      const double* y, double* loss, double* grad);
+                      const double* y, double pos_weight, double* loss,
+                      double* grad);
 int orc_adam(double* w, const double* g, double* m, double* v, int64_t t,
              double lr, double beta1, double beta2, double eps);
 

@@ -25,6 +25,19 @@ def test_zero_weights_closed_form(orc):
     assert np.all(g[:-1] == 0.0)
 
 
+def test_zero_weights_positive_weight(orc):
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((40, 12))
+    y = (rng.uniform(size=40) > 0.6).astype(float)
+    w = np.zeros(NP)
+    loss, g = orc.mlp_loss_grad(w, x, y, pos_weight=3.0)
+    yb = y.mean()
+    assert loss == pytest.approx(np.log(2.0) * (3.0 * yb + 1.0 - yb),
+                                 rel=1e-14)
+    assert g[-1] == pytest.approx(np.mean(0.5 * (3 * y + 1 - y) - 3 * y),
+                                  rel=1e-13)
+
+
 def test_output_bias_only(orc):
     w = np.zeros(NP)
     w[-1] = 1.3
@@ -49,12 +62,13 @@ def test_single_path_closed_form(orc):
     assert orc.mlp_forward(w, x)[0] == pytest.approx(want, rel=1e-15)
 
 
-def test_gradient_matches_finite_differences(orc):
+@pytest.mark.parametrize("pw", [1.0, 4.0])
+def test_gradient_matches_finite_differences(orc, pw):
     rng = np.random.default_rng(3)
     w = rng.standard_normal(NP) * 0.3
     x = rng.standard_normal((20, 12))
     y = (rng.uniform(size=20) > 0.5).astype(float)
-    _, g = orc.mlp_loss_grad(w, x, y)
+    _, g = orc.mlp_loss_grad(w, x, y, pw)
     idx = np.concatenate([rng.choice(768, 40, replace=False),
                           768 + np.arange(0, 64, 9),
                           832 + rng.choice(4096, 40, replace=False),
@@ -65,7 +79,8 @@ def test_gradient_matches_finite_differences(orc):
         wp, wm = w.copy(), w.copy()
         wp[k] += h
         wm[k] -= h
-        fd = (orc.mlp_loss_grad(wp, x, y)[0] - orc.mlp_loss_grad(wm, x, y)[0]) / (2 * h)
+        fd = (orc.mlp_loss_grad(wp, x, y, pw)[0] -
+              orc.mlp_loss_grad(wm, x, y, pw)[0]) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(g[k])) + 1e-9, k
 
 
@@ -105,23 +120,24 @@ def _children(c):
     return kids
 
 
-def _brute_walk_box(t, c, gb, gn, lo, hi, theta):
-    kids = _children(c)
-    epj, spj, rat_a, rat_o = [], [], [], []
+def _brute_walk(t, c, kids, shift, gb, gn, lo, hi, theta):
+    """Recursive walk (an independent restatement of the stackless one):
+    returns EPJ ids, SPJ ids and the two opening-test slacks."""
+    epj, spj, sa, so = [], [], [np.inf], [np.inf]
 
     def visit(cc):
         cb, cn = int(c["begin"][cc]), int(c["count"][cc])
-        holds = cb <= gb and cb + cn >= gb + gn
-        if not holds:
+        if not (cb <= gb and cb + cn >= gb + gn):
             side = 2.0 ** (t.k - int(c["level"][cc]))
-            d = np.maximum(0.0, np.maximum(lo - c["ctr"][cc], c["ctr"][cc] - hi))
-            d2 = float((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2])
-            r2 = (side / theta) ** 2
-            if d2 > r2:
+            ctr = c["ctr"][cc] + shift[cc]
+            d = np.maximum(0.0, np.maximum(lo - ctr, ctr - hi))
+            dist = float(np.sqrt(d @ d))
+            r = side / theta
+            if dist > r:
                 spj.append(cc)
-                rat_a.append(d2 / r2)
+                sa[0] = min(sa[0], dist - r)
                 return
-            rat_o.append(d2 / r2)
+            so[0] = min(so[0], r - dist)
         if c["leaf"][cc]:
             epj.extend(range(cb, cb + cn))
             return
@@ -129,44 +145,141 @@ def _brute_walk_box(t, c, gb, gn, lo, hi, theta):
             visit(k)
 
     visit(0)
-    return epj, spj, min(rat_a, default=np.inf), max(rat_o, default=-np.inf)
+    return epj, spj, sa[0], so[0]
 
 
-def test_margins_and_staleness_against_brute_force(orc):
-    rng = np.random.default_rng(8)
-    n = 300
+def _setup(orc, n=300, seed=8, theta=0.6):
+    rng = np.random.default_rng(seed)
     x, y, z = rng.standard_normal((3, n))
-    m = np.ones(n)
+    m = np.full(n, 1.0 / n)
     t = orc.Tree(x, y, z, m, n_leaf=4, n_grp=8)
-    theta = 0.6
     t.make_lists(theta)
+    return rng, (x, y, z, m), t
+
+
+def test_slacks_against_brute_force(orc):
+    theta = 0.6
+    _, _, t = _setup(orc, theta=theta)
     c, g = t.cells(), t.groups()
-    key, perm = t.keys()
-    amin, omax = t.margins(theta)
+    kids = _children(c)
+    sa, so = t.margins()
+    zero = np.zeros((t.n_cell, 3))
+    eo, e, so_, s = t.lists()
     for gi in range(t.n_groups):
         b, cnt = int(g["begin"][gi]), int(g["count"][gi])
-        _, _, a, o = _brute_walk_box(t, c, b, cnt, g["lo"][gi], g["hi"][gi],
-                                     theta)
-        assert amin[gi] == pytest.approx(a, rel=1e-12) or amin[gi] == a
-        assert omax[gi] == pytest.approx(o, rel=1e-12) or omax[gi] == o
-        assert amin[gi] > 1.0 and omax[gi] <= 1.0
-    # unmoved particles: nothing is stale
-    st, lo, hi = t.stale(theta, x, y, z)
+        pe, ps, a, o = _brute_walk(t, c, kids, zero, b, cnt, g["lo"][gi],
+                                   g["hi"][gi], theta)
+        assert pe == e[eo[gi]:eo[gi + 1]].tolist()
+        assert ps == s[so_[gi]:so_[gi + 1]].tolist()
+        assert sa[gi] == pytest.approx(a, rel=1e-12, abs=1e-15)
+        assert so[gi] == pytest.approx(o, rel=1e-12, abs=1e-15)
+        assert sa[gi] > 0.0 and so[gi] >= 0.0
+
+
+def test_unmoved_particles_are_not_stale(orc):
+    _, (x, y, z, m), t = _setup(orc)
+    t.refresh(x, y, z, m)
+    st, lo, _ = t.stale(0.6)
     assert not st.any()
-    np.testing.assert_array_equal(lo, g["lo"])
-    # moved particles: the flag says whether a walk with the new box differs
-    v = rng.standard_normal((3, n)) * 0.05
-    xn, yn, zn = x + v[0], y + v[1], z + v[2]
-    st, lo, hi = t.stale(theta, xn, yn, zn)
-    eo, e, so, s = t.lists()
+    np.testing.assert_array_equal(lo, t.groups()["lo"])
+    f = t.features(8, np.full(t.n_groups, 3))
+    np.testing.assert_array_equal(f[:, 0], 3.0 / 8.0)
+    # no box change and no cell shift: the motion features vanish
+    np.testing.assert_array_equal(f[:, [1, 2, 3, 4, 5, 6, 9]], 0.0)
+
+
+def test_rigid_motion_changes_no_list(orc):
+    # coordinates on a 2^-30 grid, a shift on the same grid: every shifted
+    # position is exact, so only the centre-of-mass division rounds
+    rng = np.random.default_rng(11)
+    n = 400
+    q = lambda a: np.round(a * 2.0**30) / 2.0**30
+    x, y, z = q(rng.standard_normal((3, n)))
+    m = np.full(n, 2.0**-9)
+    t = orc.Tree(x, y, z, m, n_leaf=4, n_grp=8)
+    t.make_lists(0.5)
+    v = np.array([0.25, -0.375, 0.125])
+    t.refresh(x + v[0], y + v[1], z + v[2], m)
+    st, _, _ = t.stale(0.5)
+    assert not st.any()
+    f = t.features(4, np.ones(t.n_groups, np.int32))
+    g = t.groups()
+    c = t.cells()
+    side = 2.0 ** (t.k - c["level"][g["cell"]].astype(float))
+    assert np.all(f[:, [1, 2, 5, 9]] < 1e-12)
+    np.testing.assert_allclose(f[:, 6], np.log1p(np.linalg.norm(v) / side),
+                               rtol=1e-12)
+
+
+def test_stale_and_refresh_against_brute_force(orc):
+    theta = 0.6
+    rng, (x, y, z, m), t = _setup(orc, theta=theta)
+    _, com0, _ = t.moments()
+    c, g = t.cells(), t.groups()
+    kids = _children(c)
+    eo0, e0, so0, s0 = t.lists()
+    # a shear flow plus noise: lists change for some groups, not all
+    xn = x + 0.04 * y + 0.01 * rng.standard_normal(x.size)
+    yn, zn = y.copy(), z + 0.01 * rng.standard_normal(x.size)
+    t.refresh(xn, yn, zn, m)
+    _, com, _ = t.moments()
+    shift = com - com0
+    key, perm = t.keys()
+    st, lo, hi = t.stale(theta)
     assert st.any() and not st.all()
+    walked = {}
     for gi in range(t.n_groups):
         b, cnt = int(g["begin"][gi]), int(g["count"][gi])
-        pe, ps, _, _ = _brute_walk_box(t, c, b, cnt, lo[gi], hi[gi], theta)
-        same = (pe == e[eo[gi]:eo[gi + 1]].tolist() and
-                ps == s[so[gi]:so[gi + 1]].tolist())
-        assert st[gi] == (not same), gi
         members = perm[b:b + cnt]
         np.testing.assert_array_equal(lo[gi], [xn[members].min(),
                                                yn[members].min(),
                                                zn[members].min()])
+        pe, ps, a, o = _brute_walk(t, c, kids, shift, b, cnt, lo[gi], hi[gi],
+                                   theta)
+        walked[gi] = (pe, ps, a, o)
+        same = (pe == e0[eo0[gi]:eo0[gi + 1]].tolist() and
+                ps == s0[so0[gi]:so0[gi + 1]].tolist())
+        assert st[gi] == (not same), gi
+    # refresh every other stale group
+    sel = np.flatnonzero(st)[::2]
+    t.refresh_lists(theta, sel)
+    eo, e, so_, s = t.lists()
+    sa, so = t.margins()
+    gg = t.groups()
+    for gi in range(t.n_groups):
+        if gi in set(sel.tolist()):
+            pe, ps, a, o = walked[gi]
+            assert pe == e[eo[gi]:eo[gi + 1]].tolist()
+            assert ps == s[so_[gi]:so_[gi + 1]].tolist()
+            assert sa[gi] == pytest.approx(a, rel=1e-12, abs=1e-15)
+            assert so[gi] == pytest.approx(o, rel=1e-12, abs=1e-15)
+            np.testing.assert_array_equal(gg["lo"][gi], lo[gi])
+        else:
+            assert e[eo[gi]:eo[gi + 1]].tolist() == \
+                e0[eo0[gi]:eo0[gi + 1]].tolist()
+            assert s[so_[gi]:so_[gi + 1]].tolist() == \
+                s0[so0[gi]:so0[gi + 1]].tolist()
+    st2, _, _ = t.stale(theta)
+    np.testing.assert_array_equal(st2, st & ~np.isin(np.arange(t.n_groups),
+                                                     sel))
+    # refreshed groups start from their new box: no box change, no shift
+    f = t.features(8, np.zeros(t.n_groups, np.int32))
+    assert np.all(f[sel][:, [1, 2, 3, 4, 5, 6, 9]] == 0.0)
+
+
+def test_feature_counts_and_caps(orc):
+    _, _, t = _setup(orc)
+    g = t.groups()
+    eo, _, so, _ = t.lists()
+    sa, so_ = t.margins()
+    f = t.features(4, np.array([0, 9] * (t.n_groups // 2) +
+                               [2] * (t.n_groups % 2), np.int32))
+    np.testing.assert_allclose(f[:, 10], np.log2(g["count"]) / 6, rtol=1e-15)
+    nl = np.diff(eo) + np.diff(so)
+    np.testing.assert_allclose(f[:, 11], np.log2(1.0 + nl) / 16, rtol=1e-15)
+    assert set(np.unique(f[:, 0])) <= {0.0, 0.5, 1.0}
+    # slacks of +inf (no accepted / no opened cell) hit the cap
+    cap = np.log1p(1e6)
+    assert np.all(f[np.isinf(sa), 7] == cap)
+    assert np.all(f[np.isinf(so_), 8] == cap)
+    assert np.all(f[:, 7:9] <= cap)
