@@ -45,11 +45,15 @@ typedef enum nb_status {
 } nb_status;
 
 /* Reuse modes of the paper's top-level force call (section 5): make lists
- * and discard them, make lists and keep them, or reuse the kept lists. */
+ * and discard them, make lists and keep them, or reuse the kept lists.
+ * NB_REUSE_REFRESH (an extension, needs NB_FLAG_REFRESH) reuses the kept
+ * lists but first walks again the lists of the groups that the predictor
+ * flags (see nb_compute_forces). */
 typedef enum nb_mode {
   NB_MAKE_LIST = 0,
   NB_MAKE_LIST_FOR_REUSE = 1,
-  NB_REUSE_LIST = 2
+  NB_REUSE_LIST = 2,
+  NB_REUSE_REFRESH = 3
 } nb_mode;
 
 typedef struct nb_config {
@@ -66,7 +70,11 @@ typedef struct nb_config {
   int32_t order;   /* superparticle expansion: 1 monopole, 2 quadrupole */
   int32_t flags;   /* bit 0: record per-phase GPU timers (HIP events);
                       bit 1: run the reuse steps of nb_step from a captured
-                      HIP graph */
+                      HIP graph; bit 2: per-group list refresh (below) */
+  int32_t k_max;   /* refresh mode: a list this many reuse steps old is
+                      walked again; 1..65535 */
+  double p_star;   /* refresh mode: a list whose predicted staleness
+                      exceeds p_star is walked again; [0, 1] */
   void* stream;    /* hipStream_t to launch on; NULL = the library's own */
 } nb_config;
 
@@ -83,10 +91,16 @@ enum {
   NB_PH_FORCE,     /* multiwalk force kernel                    */
   NB_PH_KICK,      /* kick-drift                                */
   NB_PH_GRAPH,     /* a reuse step replayed from a HIP graph     */
+  NB_PH_REFRESH,   /* predictor inputs, perceptron, list refresh */
   NB_PH_COUNT
 };
 
-enum { NB_FLAG_TIMING = 1, NB_FLAG_GRAPH = 2 };
+enum { NB_FLAG_TIMING = 1, NB_FLAG_GRAPH = 2, NB_FLAG_REFRESH = 4 };
+
+/* Rebuild predictor: inputs per group and parameter count of the
+ * 12-64-64-1 perceptron (tanh, tanh, logistic).  Parameter layout (floats):
+ * W1[64][12] row-major, b1[64], W2[64][64] row-major, b2[64], w3[64], b3. */
+enum { NB_MLP_NIN = 12, NB_MLP_NPARAM = 5057 };
 
 /* ---- lifetime --------------------------------------------------------- */
 
@@ -138,8 +152,14 @@ int nb_make_lists(nb_ctx* ctx, nb_mode mode);
  * frozen tree from the current positions and runs the force kernel on the
  * kept lists; particles are not re-sorted.  Forces (acceleration including
  * G, and potential excluding the self term) stay on the device until read.
+ * NB_REUSE_REFRESH does the same, and between moments and force kernel
+ * computes the predictor inputs of every group (nb_group_features), runs
+ * the perceptron and walks again (nb_refresh_lists) every group with
+ * p > cfg.p_star or age >= cfg.k_max; this synchronises with the host once,
+ * twice when a group is refreshed.
  * Errors: NB_ERR_STATE (REUSE_LIST without reusable lists or after
- * nb_set_particles), plus those of the stages. */
+ * nb_set_particles; REUSE_REFRESH without NB_FLAG_REFRESH), plus those of
+ * the stages. */
 int nb_compute_forces(nb_ctx* ctx, nb_mode mode);
 
 /* Kick-drift of the KDK leapfrog in FP64: v += (a + a_ext) * dt_kick, then
@@ -168,7 +188,8 @@ int nb_get_state(nb_ctx* ctx, double* x, double* y, double* z, double* vx,
  * [5] interactions of the current lists (sum over groups of
  * n_i * (n_epj + n_spj)), [6] force evaluations so far, [7] total
  * interactions evaluated so far, [8] root exponent k of system 0, [9] force
- * work items, [10] systems.  info must hold 11 values. */
+ * work items, [10] systems, [11] groups whose lists the last force call
+ * refreshed, [12] refreshed groups so far.  info must hold 13 values. */
 int nb_get_info(nb_ctx* ctx, int64_t* info);
 
 /* Root corner lo[3] and exponent k of the last tree (side 2^k); with
@@ -208,6 +229,78 @@ int nb_get_lists(nb_ctx* ctx, int64_t* epj_off, uint32_t* epj,
  * number of timed intervals per phase (may be NULL), since the last reset;
  * needs cfg.flags bit 0.  reset != 0 clears the counters after reading. */
 int nb_get_timing(nb_ctx* ctx, double* ms, int64_t* calls, int reset);
+
+/* ---- per-group list refresh (NB_FLAG_REFRESH) --------------------------
+ * An extension of the list reuse of section 4.2, which keeps every list for
+ * a fixed number of steps.  Cells keep their particle ranges between
+ * construction steps; in every opening test of a refresh mode walk, the
+ * geometric centre of a cell is moved by the displacement of its FP64
+ * centre of mass since the construction step (zero at construction, so
+ * construction lists are unchanged), so that a rigid motion stales no list.
+ * A group's list is stale when a walk with the group's current tight box
+ * gives another list.  Per group the library keeps the box, the cell shift
+ * and the opening-test slacks of the walk that made its list, and the
+ * list's age (reuse steps since that walk).  The calls below describe the
+ * state of the last force computation (NB_ERR_STATE after a drift, without
+ * the flag, or without reusable lists). */
+
+/* The 12 predictor inputs per group, row-major [groups][12] FP32.  With s
+ * the side of the group's cell, (lo, hi) its current box, (lo0, hi0), tau0,
+ * sa, so the box, cell shift and slacks of the walk that made its list,
+ * dtau = (current shift of the group's cell) - tau0:
+ *   e_a = max(|lo_a - lo0_a - dtau_a|, |hi_a - hi0_a - dtau_a|), E = |e|,
+ *   B = |dtau|, grow = max_a max(0, (hi - lo)_a - (hi0 - lo0)_a),
+ *   f0 = min(age, k_max) / k_max, f1..f4 = log1p of E/sa, E/so, B/sa, B/so,
+ *   f5 = log1p(E/s), f6 = log1p(B/s), f7 = log1p(sa/s), f8 = log1p(so/s),
+ *   f9 = log1p(grow/s), f10 = log2(n_i)/6, f11 = log2(1 + list length)/16,
+ * ratios capped at 1e6 (x/0 = cap, 0/0 = 0); computed in FP64, stored
+ * FP32.  feat may be NULL (kept on the device for the predictor). */
+int nb_group_features(nb_ctx* ctx, float* feat, int on_device);
+
+/* Staleness labels: stale[g] = 1 when the walk with the current box and
+ * centres differs from the kept list (a "shadow" walk that changes
+ * nothing); label[g] the same as 0.0 / 1.0.  Either may be NULL. */
+int nb_group_stale(nb_ctx* ctx, uint8_t* stale, float* label, int on_device);
+
+/* Walk again the lists of the n_sel groups listed in sel (host array of
+ * ascending group ids) with their current boxes and centres; other lists
+ * are kept.  Sets those groups' box, shift, slacks and age (0).
+ * Errors: NB_ERR_INPUT (ids not ascending or out of range). */
+int nb_refresh_lists(nb_ctx* ctx, int64_t n_sel, const int64_t* sel);
+
+/* Slacks sa, so (FP64, +inf when no such cell) and ages per group; any may
+ * be NULL.  sa = smallest |box - centre| - rcrit over accepted cells,
+ * so = smallest rcrit - |box - centre| over opened cells not holding the
+ * group, of the walk that made the list. */
+int nb_get_group_state(nb_ctx* ctx, double* sa, double* so, int32_t* age);
+
+/* Perceptron weights (host, NB_MLP_NPARAM floats).  Setting them clears the
+ * Adam state.  A context starts with zero weights (p = 1/2). */
+int nb_mlp_set(nb_ctx* ctx, const float* w, int64_t nw);
+int nb_mlp_get(nb_ctx* ctx, float* w, int64_t nw);
+
+/* p[i] = predicted staleness of input row x[i] (n rows of 12). */
+int nb_mlp_forward(nb_ctx* ctx, int64_t n, const float* x, float* p,
+                   int on_device);
+
+/* Mean weighted cross-entropy over n rows, -(1/n) sum [w y log p +
+ * (1 - y) log(1 - p)] with w = pos_weight > 0, and its gradient
+ * (NB_MLP_NPARAM floats); loss is a host float; either may be NULL. */
+int nb_mlp_grad(nb_ctx* ctx, int64_t n, const float* x, const float* y,
+                float pos_weight, float* loss, float* grad, int on_device);
+
+/* One Adam step (Kingma and Ba) on the weights with gradient grad (NULL =
+ * the last nb_mlp_grad gradient); the step counter starts at 1 after
+ * nb_mlp_set. */
+int nb_mlp_adam(nb_ctx* ctx, const float* grad, float lr, float beta1,
+                float beta2, float eps, int on_device);
+
+/* epochs passes over the n rows in order, in batches of `batch` rows, one
+ * Adam step (beta 0.9, 0.999, eps 1e-8) per batch, all on the GPU; loss
+ * (host, may be NULL) = the loss over all rows after training. */
+int nb_mlp_train(nb_ctx* ctx, int64_t n, const float* x, const float* y,
+                 int on_device, int epochs, int64_t batch, float lr,
+                 float pos_weight, float* loss);
 
 /* Description of the last error on this context ("" if none). */
 const char* nb_last_error(const nb_ctx* ctx);

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libnbody_hip.so")
 ARCH = "gfx950"
 
 SOURCES = ["nb_scan.hip", "nb_tree.hip", "nb_walk.hip", "nb_force.hip",
-           "nb_step.hip", "nb_api.hip"]
+           "nb_step.hip", "nb_learn.hip", "nb_api.hip"]
 EXACT = {"nb_tree.hip", "nb_walk.hip"}
 
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

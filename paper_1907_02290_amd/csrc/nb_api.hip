@@ -88,14 +88,6 @@ void timer_end(nb_ctx* c, int phase, hipEvent_t a) {
   if (c->timers.size() > 4096) resolve_timers(c);
 }
 
-struct Timed {
-  nb_ctx* c;
-  int ph;
-  hipEvent_t a;
-  Timed(nb_ctx* c_, int ph_) : c(c_), ph(ph_) { timer_begin(c, ph, &a); }
-  ~Timed() { timer_end(c, ph, a); }
-};
-
 static int check_cfg(nb_ctx* c, const nb_config* cfg) {
   if (!cfg) return set_err(c, NB_ERR_INPUT, "config is NULL");
   if (!(cfg->theta >= 0.0) || !std::isfinite(cfg->theta))
@@ -110,22 +102,30 @@ static int check_cfg(nb_ctx* c, const nb_config* cfg) {
     return set_err(c, NB_ERR_INPUT, "n_grp must be in 1..65536");
   if (cfg->order != 1 && cfg->order != 2)
     return set_err(c, NB_ERR_INPUT, "order must be 1 or 2");
+  if (cfg->flags & NB_FLAG_REFRESH) {
+    if (cfg->k_max < 1 || cfg->k_max > 65535)
+      return set_err(c, NB_ERR_INPUT, "k_max must be in 1..65535");
+    if (!(cfg->p_star >= 0.0 && cfg->p_star <= 1.0))
+      return set_err(c, NB_ERR_INPUT, "p_star must be in [0, 1]");
+  }
   return NB_OK;
 }
 
 // Copy `bytes` from device to the pinned staging buffer at `off` (async).
-static int stage_d2h(nb_ctx* c, size_t off, const void* src, size_t bytes) {
+int stage_d2h(nb_ctx* c, size_t off, const void* src, size_t bytes) {
   return hip_check(c,
                    hipMemcpyAsync(static_cast<char*>(c->h_small) + off, src,
                                   bytes, hipMemcpyDeviceToHost, c->stream),
                    "staging copy");
 }
 
-static int sync(nb_ctx* c) {
+int sync_stream(nb_ctx* c) {
   return hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
 }
 
-static void drop_graph(nb_ctx* c) {
+static int sync(nb_ctx* c) { return sync_stream(c); }
+
+void drop_graph(nb_ctx* c) {
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   c->graph_exec = nullptr;
@@ -205,18 +205,23 @@ static int build_tree(nb_ctx* c) {
   }
   {
     Timed t(c, NB_PH_MOMENTS);
-    if ((rc = launch_moments(c))) return rc;
+    c->in_build = true;
+    rc = launch_moments(c);
+    c->in_build = false;
+    if (rc) return rc;
   }
   {
     Timed t(c, NB_PH_GROUPS);
     if ((rc = launch_group_fill(c))) return rc;
+    if (c->learn && (rc = learn_after_groups(c))) return rc;
   }
   c->tree_valid = c->positions_fresh = true;
+  c->shift_fresh = c->learn;
   return NB_OK;
 }
 
 static int make_lists(nb_ctx* c, nb_mode mode) {
-  if (mode == NB_REUSE_LIST)
+  if (mode == NB_REUSE_LIST || mode == NB_REUSE_REFRESH)
     return c->lists_reusable ? NB_OK
                              : set_err(c, NB_ERR_STATE, "no reusable lists");
   if (mode != NB_MAKE_LIST && mode != NB_MAKE_LIST_FOR_REUSE)
@@ -278,6 +283,7 @@ int nb_create(const nb_config* cfg, nb_ctx** out) {
   nb_ctx* c = new (std::nothrow) nb_ctx();
   if (!c) return NB_ERR_OOM;
   c->cfg = *cfg;
+  c->learn = (cfg->flags & NB_FLAG_REFRESH) != 0;
   if (hipGetDevice(&c->device) != hipSuccess) {
     (void)hipGetLastError();
     delete c;
@@ -332,6 +338,16 @@ void nb_destroy(nb_ctx* c) {
   release(c->epj_off); release(c->spj_off); release(c->tok_off);
   release(c->epj); release(c->spj); release(c->tok);
   release(c->scan_tmp); release(c->red);
+  release(c->c_com); release(c->c_com0); release(c->c_shift); release(c->c_ctr);
+  release(c->g_clo); release(c->g_chi); release(c->g_tau0);
+  release(c->g_sa); release(c->g_so); release(c->g_age);
+  release(c->pick); release(c->pickpos); release(c->sel);
+  release(c->ne2); release(c->ns2); release(c->epj_off2); release(c->spj_off2);
+  release(c->epj2); release(c->spj2); release(c->feat); release(c->prob);
+  release(c->stale);
+  release(c->mlp_w); release(c->mlp_m); release(c->mlp_v); release(c->mlp_g);
+  release(c->mlp_act); release(c->mlp_dz); release(c->mlp_lossp);
+  release(c->mlp_part); release(c->mlp_x); release(c->mlp_y);
   if (c->h_small) (void)hipHostFree(c->h_small);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -344,6 +360,8 @@ int nb_set_config(nb_ctx* c, const nb_config* cfg) {
   void* keep_stream = c->cfg.stream;
   c->cfg = *cfg;
   c->cfg.stream = keep_stream;  // the stream is fixed at creation
+  c->learn = (cfg->flags & NB_FLAG_REFRESH) != 0;
+  c->shift_fresh = false;
   drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = false;
@@ -446,12 +464,25 @@ int nb_make_lists(nb_ctx* c, nb_mode mode) {
 int nb_compute_forces(nb_ctx* c, nb_mode mode) {
   if (!c) return NB_ERR_INPUT;
   int rc;
-  if (mode == NB_REUSE_LIST) {
+  c->last_refreshed = 0;
+  if (mode == NB_REUSE_LIST || mode == NB_REUSE_REFRESH) {
     if (!c->have_particles || !c->tree_valid || !c->lists_reusable)
       return set_err(c, NB_ERR_STATE,
                      "REUSE_LIST needs lists made with MAKE_LIST_FOR_REUSE");
-    Timed t(c, NB_PH_MOMENTS);
-    if ((rc = launch_moments(c))) return rc;
+    if (mode == NB_REUSE_REFRESH && !c->learn)
+      return set_err(c, NB_ERR_STATE, "REUSE_REFRESH needs NB_FLAG_REFRESH");
+    {
+      Timed t(c, NB_PH_MOMENTS);
+      if ((rc = launch_moments(c))) return rc;
+    }
+    if (c->learn) {
+      if ((rc = launch_age_inc(c))) return rc;
+      c->shift_fresh = true;
+    }
+    if (mode == NB_REUSE_REFRESH) {
+      Timed t(c, NB_PH_REFRESH);
+      if ((rc = refresh_predicted(c))) return rc;
+    }
   } else if (mode == NB_MAKE_LIST || mode == NB_MAKE_LIST_FOR_REUSE) {
     if ((rc = build_tree(c))) return rc;
     if ((rc = make_lists(c, mode))) return rc;
@@ -481,6 +512,7 @@ int nb_kick_drift(nb_ctx* c, double dt_kick, double dt_drift) {
   }
   if (dt_drift != 0.0) {
     c->positions_fresh = false;
+    c->shift_fresh = false;
     if (!c->lists_reusable) c->lists_valid = false;
   }
   return NB_OK;
@@ -491,6 +523,7 @@ int nb_kick_drift(nb_ctx* c, double dt_kick, double dt_drift) {
 static int enqueue_reuse_step(nb_ctx* c, double dtk, double dtd) {
   int rc = launch_kick_drift(c, dtk, dtd);
   if (!rc) rc = launch_moments(c);
+  if (!rc && c->learn) rc = launch_age_inc(c);
   if (!rc) rc = launch_force(c);
   return rc;
 }
@@ -546,6 +579,8 @@ int nb_step(nb_ctx* c, nb_mode mode, double dt_kick, double dt_drift) {
     if (rc) return rc;
   }
   if (dt_drift != 0.0) c->positions_fresh = false;
+  c->shift_fresh = c->learn;
+  c->last_refreshed = 0;
   c->forces_valid = true;
   c->force_evals += 1;
   c->total_inter += c->n_inter;
@@ -625,6 +660,8 @@ int nb_get_info(nb_ctx* c, int64_t* info) {
   info[8] = c->k;
   info[9] = c->n_wi;
   info[10] = c->n_sys;
+  info[11] = c->last_refreshed;
+  info[12] = c->total_refreshed;
   return NB_OK;
 }
 

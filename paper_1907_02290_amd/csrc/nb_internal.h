@@ -128,6 +128,30 @@ struct nb_ctx {
   nb::DBuf<uint64_t> red;  // small reductions (interaction count, ...)
   void* h_small = nullptr; // pinned host staging (4 KiB)
 
+  // per-group list refresh (NB_FLAG_REFRESH)
+  bool learn = false;        // refresh mode of the current configuration
+  bool in_build = false;     // inside a construction step
+  bool shift_fresh = false;  // centres of mass match the positions
+  nb::DBuf<double4> c_com, c_com0;  // FP64 centre of mass (w = mass): now,
+                                    // and at construction
+  nb::DBuf<double4> c_shift;        // com - com0
+  nb::DBuf<double4> c_ctr;          // geo + shift, w = rcrit^2
+  nb::DBuf<double4> g_clo, g_chi;   // current tight boxes
+  nb::DBuf<double4> g_tau0;         // cell shift when the list was walked
+  nb::DBuf<double> g_sa, g_so;      // opening-test slacks of that walk
+  nb::DBuf<uint32_t> g_age;         // reuse steps since that walk
+  nb::DBuf<uint32_t> pick, pickpos, sel;  // refresh selection
+  nb::DBuf<uint32_t> ne2, ns2;
+  nb::DBuf<uint64_t> epj_off2, spj_off2;
+  nb::DBuf<uint32_t> epj2, spj2;
+  nb::DBuf<float> feat, prob;       // predictor inputs [G x 12], outputs
+  nb::DBuf<uint8_t> stale;          // labels of the last stale walk
+  int64_t last_refreshed = 0, total_refreshed = 0;
+  // perceptron: weights, Adam moments, gradient (+ loss), scratch
+  nb::DBuf<float> mlp_w, mlp_m, mlp_v, mlp_g;
+  nb::DBuf<float> mlp_act, mlp_dz, mlp_lossp, mlp_part, mlp_x, mlp_y;
+  int64_t mlp_t = 0;
+
   // captured reuse step (NB_FLAG_GRAPH)
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -174,9 +198,19 @@ void release(DBuf<T>& b) {
   b.cap = 0;
 }
 
-// timers (nb_api.hip)
+// timers and host synchronisation (nb_api.hip)
 void timer_begin(nb_ctx* c, int phase, hipEvent_t* a);
 void timer_end(nb_ctx* c, int phase, hipEvent_t a);
+struct Timed {
+  nb_ctx* c;
+  int ph;
+  hipEvent_t a;
+  Timed(nb_ctx* c_, int ph_) : c(c_), ph(ph_) { timer_begin(c, ph, &a); }
+  ~Timed() { timer_end(c, ph, a); }
+};
+int stage_d2h(nb_ctx* c, size_t off, const void* src, size_t bytes);
+int sync_stream(nb_ctx* c);
+void drop_graph(nb_ctx* c);  // a captured step refers to the list buffers
 
 // ---- stage launchers; all enqueue on c->stream and return a status ----
 // nb_scan.hip
@@ -195,9 +229,33 @@ int launch_group_flags(nb_ctx* c);
 int launch_sys_roots(nb_ctx* c);
 int launch_seg_fill(nb_ctx* c);
 int launch_group_fill(nb_ctx* c);
+int launch_group_box(nb_ctx* c, double4* lo, double4* hi);
 // nb_walk.hip
 int launch_walk(nb_ctx* c, bool fill);
+int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
+                    const double4* lo, const double4* hi,
+                    const uint64_t* epj_off, const uint64_t* spj_off,
+                    uint32_t* epj, uint32_t* spj);
+int launch_walk_stale(nb_ctx* c, uint8_t* stale);
 int launch_list_stats(nb_ctx* c);
+int launch_interactions(nb_ctx* c, const uint32_t* ne, const uint32_t* ns);
+// nb_learn.hip
+int learn_reserve_cells(nb_ctx* c);
+int learn_reserve_groups(nb_ctx* c);
+int launch_com(nb_ctx* c);
+int learn_after_groups(nb_ctx* c);
+int launch_age_inc(nb_ctx* c);
+int launch_features(nb_ctx* c);
+int launch_stale(nb_ctx* c);
+int mlp_ensure(nb_ctx* c);
+int mlp_forward(nb_ctx* c, int64_t n, const float* x, float* p);
+int mlp_grad(nb_ctx* c, int64_t n, const float* x, const float* y, float pw);
+int mlp_adam(nb_ctx* c, const float* g, float lr, float b1, float b2,
+             float eps);
+int refresh_selected(nb_ctx* c, int64_t n_sel);
+int refresh_host_sel(nb_ctx* c, int64_t n_sel, const int64_t* sel);
+int refresh_predicted(nb_ctx* c);
+int labels_to_float(nb_ctx* c, float* out);
 // nb_force.hip
 int launch_force(nb_ctx* c);
 // nb_step.hip

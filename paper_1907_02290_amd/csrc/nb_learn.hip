@@ -1,0 +1,925 @@
+// nb_learn.hip -- per-group list refresh and its learned predictor.  This
+// extends the list reuse of section 4.2 (the paper keeps every list for a
+// fixed number of steps): between two construction steps, the lists of
+// single groups are walked again when a small perceptron predicts that
+// their kept list has gone stale.
+//
+// Refresh mode (NB_FLAG_REFRESH) keeps per cell the FP64 centre of mass at
+// construction and at the current step; in every opening test the cell's
+// geometric centre is moved by their difference, so that a rigid motion
+// changes no list.  Right after construction the shift is exactly zero and
+// the walk is the plain one.  Per group it keeps the box, the cell shift and
+// the opening-test slacks of the walk that made its list, and the list's
+// age in reuse steps.
+//
+// Kernels: FP64 centres of mass (leaves, then levels bottom-up), shifted
+// centres, predictor inputs, selection, the merge of refreshed and kept
+// lists, and the 12-64-64-1 perceptron (forward; per-sample back-propagation;
+// per-parameter sums over samples in fixed order; Adam).  The perceptron is
+// 5057 parameters: one workgroup stages them in LDS and every lane runs one
+// sample.  MFMA would need batches far larger than the group count to pay
+// for the operand staging; at 131k groups a forward pass is ~1.3 GFLOP.
+#include <cmath>
+#include <cstring>
+#include <utility>
+
+#include "nb_internal.h"
+
+namespace nb {
+namespace {
+
+constexpr int kNF = NB_MLP_NIN;  // predictor inputs
+constexpr int kNH = 64;          // hidden width
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kNH * kNF;
+constexpr int kOffW2 = kOffB1 + kNH;
+constexpr int kOffB2 = kOffW2 + kNH * kNH;
+constexpr int kOffW3 = kOffB2 + kNH;
+constexpr int kOffB3 = kOffW3 + kNH;
+constexpr int kNP = kOffB3 + 1;
+static_assert(kNP == NB_MLP_NPARAM, "parameter layout");
+constexpr int kChunk = 1024;  // samples per partial gradient sum
+
+__device__ inline uint32_t next_sibling(const CellRec* __restrict__ rec,
+                                        uint32_t k, uint32_t stop) {
+  const uint32_t s = rec[k].meta.z;
+  return s > k ? s : stop;
+}
+
+// ---- FP64 centres of mass -------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_com_leaf(int64_t cnt, const uint32_t* __restrict__ list,
+           const CellRec* __restrict__ rec, const double4* __restrict__ pos,
+           double4* __restrict__ com) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  const uint32_t c = list[t];
+  const uint4 m = rec[c].meta;
+  const double4 g = rec[c].geo;
+  double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+  for (uint32_t p = m.x; p < m.y; ++p) {
+    const double4 P = pos[p];
+    M += P.w;
+    sx += P.w * (P.x - g.x);
+    sy += P.w * (P.y - g.y);
+    sz += P.w * (P.z - g.z);
+  }
+  com[c] = M > 0.0 ? make_double4(g.x + sx / M, g.y + sy / M, g.z + sz / M, M)
+                   : make_double4(g.x, g.y, g.z, 0.0);
+}
+
+__global__ void __launch_bounds__(256)
+k_com_internal(int64_t cnt, const uint32_t* __restrict__ list,
+               const CellRec* __restrict__ rec, double4* __restrict__ com) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  const uint32_t c = list[t];
+  const uint32_t stop = rec[c].meta.z;
+  const double4 g = rec[c].geo;
+  double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+  for (uint32_t k = c + 1; k < stop; k = next_sibling(rec, k, stop)) {
+    const double4 ck = com[k];
+    M += ck.w;
+    sx += ck.w * (ck.x - g.x);
+    sy += ck.w * (ck.y - g.y);
+    sz += ck.w * (ck.z - g.z);
+  }
+  com[c] = M > 0.0 ? make_double4(g.x + sx / M, g.y + sy / M, g.z + sz / M, M)
+                   : make_double4(g.x, g.y, g.z, 0.0);
+}
+
+// shift = com - com0; centre for the opening test = geo + shift (rounded
+// once each, as the FP64 reference does), w = (side / theta)^2.
+__global__ void __launch_bounds__(256)
+k_shift(int64_t nc, const CellRec* __restrict__ rec,
+        const double4* __restrict__ com, const double4* __restrict__ com0,
+        double4* __restrict__ shift, double4* __restrict__ ctr) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const double4 a = com[c], b = com0[c], g = rec[c].geo;
+  const double sx = __dsub_rn(a.x, b.x), sy = __dsub_rn(a.y, b.y),
+               sz = __dsub_rn(a.z, b.z);
+  shift[c] = make_double4(sx, sy, sz, 0.0);
+  ctr[c] = make_double4(__dadd_rn(g.x, sx), __dadd_rn(g.y, sy),
+                        __dadd_rn(g.z, sz), g.w);
+}
+
+__global__ void __launch_bounds__(256)
+k_age_inc(int64_t ng, uint32_t* __restrict__ age) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < ng && age[g] < 0xFFFFFFFFu) age[g] += 1u;
+}
+
+// ---- predictor inputs -------------------------------------------------------
+__device__ inline double capped(double a, double b) {
+  const double cap = 1e6;
+  if (b > 0.0) {
+    const double q = a / b;
+    return q < cap ? q : cap;
+  }
+  return a > 0.0 ? cap : 0.0;
+}
+
+__global__ void __launch_bounds__(256)
+k_features(int64_t ng, const uint32_t* __restrict__ g_cell,
+           const uint32_t* __restrict__ g_begin,
+           const uint32_t* __restrict__ g_count,
+           const CellRec* __restrict__ rec, const Root* __restrict__ root,
+           const uint32_t* __restrict__ seg, const double4* __restrict__ clo,
+           const double4* __restrict__ chi, const double4* __restrict__ lo0,
+           const double4* __restrict__ hi0,
+           const double4* __restrict__ tau0,
+           const double4* __restrict__ shift, const double* __restrict__ g_sa,
+           const double* __restrict__ g_so, const uint32_t* __restrict__ age,
+           const uint64_t* __restrict__ epj_off,
+           const uint64_t* __restrict__ spj_off, int kmax,
+           float* __restrict__ feat) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  const uint32_t c = g_cell[g];
+  const int level = (int)(rec[c].meta.w & 255u);
+  const int k = root[seg[g_begin[g]]].k;
+  const double s = ldexp(1.0, k - level);
+  const double4 lo = clo[g], hi = chi[g], a0 = lo0[g], b0 = hi0[g];
+  const double4 t0 = tau0[g], sh = shift[c];
+  const double dt[3] = {sh.x - t0.x, sh.y - t0.y, sh.z - t0.z};
+  const double l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
+  const double l0[3] = {a0.x, a0.y, a0.z}, h0[3] = {b0.x, b0.y, b0.z};
+  double e[3], grow = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double dl = fabs((l[a] - l0[a]) - dt[a]);
+    const double dh = fabs((h[a] - h0[a]) - dt[a]);
+    e[a] = dl > dh ? dl : dh;
+    const double w = (h[a] - l[a]) - (h0[a] - l0[a]);
+    if (w > grow) grow = w;
+  }
+  const double E = sqrt((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]);
+  const double B = sqrt((dt[0] * dt[0] + dt[1] * dt[1]) + dt[2] * dt[2]);
+  const double sa = g_sa[g], so = g_so[g];
+  const double nl = (double)((epj_off[g + 1] - epj_off[g]) +
+                             (spj_off[g + 1] - spj_off[g]));
+  const uint32_t ag = age[g];
+  float* f = feat + (int64_t)kNF * g;
+  f[0] = (float)((double)(ag < (uint32_t)kmax ? ag : (uint32_t)kmax) / kmax);
+  f[1] = (float)log1p(capped(E, sa));
+  f[2] = (float)log1p(capped(E, so));
+  f[3] = (float)log1p(capped(B, sa));
+  f[4] = (float)log1p(capped(B, so));
+  f[5] = (float)log1p(E / s);
+  f[6] = (float)log1p(B / s);
+  f[7] = (float)log1p(capped(sa, s));
+  f[8] = (float)log1p(capped(so, s));
+  f[9] = (float)log1p(grow / s);
+  f[10] = (float)(log2((double)g_count[g]) / 6.0);
+  f[11] = (float)(log2(1.0 + nl) / 16.0);
+}
+
+// ---- selection and list merge ----------------------------------------------
+__global__ void __launch_bounds__(256)
+k_select(int64_t ng, const float* __restrict__ prob,
+         const uint32_t* __restrict__ age, float p_star, uint32_t kmax,
+         uint32_t* __restrict__ pick) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < ng) pick[g] = (prob[g] > p_star || age[g] >= kmax) ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256)
+k_mark(int64_t n_sel, const uint32_t* __restrict__ sel,
+       uint32_t* __restrict__ pick) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_sel) pick[sel[t]] = 1u;
+}
+
+__global__ void __launch_bounds__(256)
+k_compact(int64_t ng, const uint32_t* __restrict__ pick,
+          const uint32_t* __restrict__ pos, uint32_t* __restrict__ sel) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < ng && pick[g]) sel[pos[g]] = (uint32_t)g;
+}
+
+// New list lengths: walked counts for refreshed groups (index pos[g] in the
+// selection), kept lengths for the others.
+__global__ void __launch_bounds__(256)
+k_merge_counts(int64_t ng, const uint32_t* __restrict__ pick,
+               const uint32_t* __restrict__ pos,
+               const uint32_t* __restrict__ cnt_e,
+               const uint32_t* __restrict__ cnt_s,
+               const uint64_t* __restrict__ epj_off,
+               const uint64_t* __restrict__ spj_off,
+               uint32_t* __restrict__ ne2, uint32_t* __restrict__ ns2) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  if (pick[g]) {
+    ne2[g] = cnt_e[pos[g]];
+    ns2[g] = cnt_s[pos[g]];
+  } else {
+    ne2[g] = (uint32_t)(epj_off[g + 1] - epj_off[g]);
+    ns2[g] = (uint32_t)(spj_off[g + 1] - spj_off[g]);
+  }
+}
+
+// Kept lists move to their new offsets: one wave per group.
+__global__ void __launch_bounds__(256)
+k_copy_lists(int64_t ng, const uint32_t* __restrict__ pick,
+             const uint64_t* __restrict__ eo, const uint32_t* __restrict__ e,
+             const uint64_t* __restrict__ so, const uint32_t* __restrict__ s,
+             const uint64_t* __restrict__ eo2, uint32_t* __restrict__ e2,
+             const uint64_t* __restrict__ so2, uint32_t* __restrict__ s2) {
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= ng || pick[g]) return;
+  const uint64_t a = eo[g], na = eo[g + 1] - a, a2 = eo2[g];
+  for (uint64_t i = lane; i < na; i += 64) e2[a2 + i] = e[a + i];
+  const uint64_t b = so[g], nb = so[g + 1] - b, b2 = so2[g];
+  for (uint64_t i = lane; i < nb; i += 64) s2[b2 + i] = s[b + i];
+}
+
+__global__ void __launch_bounds__(256)
+k_refresh_meta(int64_t ng, const uint32_t* __restrict__ pick,
+               const double4* __restrict__ clo,
+               const double4* __restrict__ chi, double4* __restrict__ lo,
+               double4* __restrict__ hi, uint32_t* __restrict__ age) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng || !pick[g]) return;
+  lo[g] = clo[g];
+  hi[g] = chi[g];
+  age[g] = 0u;
+}
+
+__global__ void __launch_bounds__(256)
+k_u8_to_f32(int64_t n, const uint8_t* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+// ---- perceptron ---------------------------------------------------------------
+__device__ inline void stage_weights(const float* __restrict__ w, float* sw) {
+  for (int q = threadIdx.x; q < kNP; q += blockDim.x) sw[q] = w[q];
+  __syncthreads();
+}
+
+// log(1 + exp(z)) without overflow
+__device__ inline float softplus(float z) {
+  return z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
+}
+
+__device__ inline float forward_one(const float* sw, const float* __restrict__ xr,
+                                    float* h1, float* h2) {
+  float xi[kNF];
+#pragma unroll
+  for (int k = 0; k < kNF; ++k) xi[k] = xr[k];
+#pragma unroll
+  for (int j = 0; j < kNH; ++j) {
+    float s = sw[kOffB1 + j];
+#pragma unroll
+    for (int k = 0; k < kNF; ++k) s = fmaf(sw[kOffW1 + j * kNF + k], xi[k], s);
+    h1[j] = tanhf(s);
+  }
+  float z = sw[kOffB3];
+#pragma unroll
+  for (int j = 0; j < kNH; ++j) {
+    float s = sw[kOffB2 + j];
+#pragma unroll
+    for (int k = 0; k < kNH; ++k) s = fmaf(sw[kOffW2 + j * kNH + k], h1[k], s);
+    h2[j] = tanhf(s);
+    z = fmaf(sw[kOffW3 + j], h2[j], z);
+  }
+  return z;
+}
+
+__global__ void __launch_bounds__(256)
+k_mlp_fwd(int64_t n, const float* __restrict__ x, const float* __restrict__ w,
+          float* __restrict__ p) {
+  __shared__ float sw[kNP];
+  stage_weights(w, sw);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float h1[kNH], h2[kNH];
+  const float z = forward_one(sw, x + (int64_t)kNF * i, h1, h2);
+  p[i] = 1.f / (1.f + expf(-z));
+}
+
+// Per sample: loss term, output delta dz = dL/dz, hidden deltas and the
+// activations the parameter sums need (rows of 64 floats per sample).
+__global__ void __launch_bounds__(256)
+k_mlp_bwd(int64_t n, const float* __restrict__ x, const float* __restrict__ y,
+          const float* __restrict__ w, float pw, float inv_n,
+          float* __restrict__ H1, float* __restrict__ H2,
+          float* __restrict__ D1, float* __restrict__ D2,
+          float* __restrict__ DZ, float* __restrict__ lossp) {
+  __shared__ float sw[kNP];
+  __shared__ float red[4];
+  stage_weights(w, sw);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float li = 0.f;
+  if (i < n) {
+    float h1[kNH], h2[kNH];
+    const float z = forward_one(sw, x + (int64_t)kNF * i, h1, h2);
+    const float p = 1.f / (1.f + expf(-z));
+    const float yi = y[i];
+    const float wy = pw * yi;
+    li = wy * softplus(-z) + (1.f - yi) * softplus(z);
+    const float dz = (p * (wy + 1.f - yi) - wy) * inv_n;
+    DZ[i] = dz;
+    float* h1r = H1 + (int64_t)kNH * i;
+    float* h2r = H2 + (int64_t)kNH * i;
+    float* d2r = D2 + (int64_t)kNH * i;
+    float* d1r = D1 + (int64_t)kNH * i;
+    float d2[kNH];
+#pragma unroll
+    for (int j = 0; j < kNH; ++j) {
+      d2[j] = dz * sw[kOffW3 + j] * (1.f - h2[j] * h2[j]);
+      h1r[j] = h1[j];
+      h2r[j] = h2[j];
+      d2r[j] = d2[j];
+    }
+#pragma unroll
+    for (int k = 0; k < kNH; ++k) {
+      float s = 0.f;
+#pragma unroll
+      for (int j = 0; j < kNH; ++j) s = fmaf(d2[j], sw[kOffW2 + j * kNH + k], s);
+      d1r[k] = s * (1.f - h1[k] * h1[k]);
+    }
+  }
+  // block sum of the loss terms, fixed order
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) li += __shfl_xor(li, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = li;
+  __syncthreads();
+  if (threadIdx.x == 0) lossp[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Partial gradient of every parameter over one chunk of samples
+// (blockIdx.y), summed in sample order.
+__global__ void __launch_bounds__(256)
+k_mlp_wgrad(int64_t n, const float* __restrict__ x,
+            const float* __restrict__ H1, const float* __restrict__ H2,
+            const float* __restrict__ D1, const float* __restrict__ D2,
+            const float* __restrict__ DZ, float* __restrict__ part) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= kNP) return;
+  const int64_t b0 = (int64_t)blockIdx.y * kChunk;
+  const int64_t b1 = b0 + kChunk < n ? b0 + kChunk : n;
+  float s = 0.f;
+  if (q < kOffB1) {
+    const int j = q / kNF, k = q % kNF;
+    for (int64_t b = b0; b < b1; ++b)
+      s = fmaf(D1[b * kNH + j], x[b * kNF + k], s);
+  } else if (q < kOffW2) {
+    const int j = q - kOffB1;
+    for (int64_t b = b0; b < b1; ++b) s += D1[b * kNH + j];
+  } else if (q < kOffB2) {
+    const int r = q - kOffW2, j = r / kNH, k = r % kNH;
+    for (int64_t b = b0; b < b1; ++b)
+      s = fmaf(D2[b * kNH + j], H1[b * kNH + k], s);
+  } else if (q < kOffW3) {
+    const int j = q - kOffB2;
+    for (int64_t b = b0; b < b1; ++b) s += D2[b * kNH + j];
+  } else if (q < kOffB3) {
+    const int k = q - kOffW3;
+    for (int64_t b = b0; b < b1; ++b) s = fmaf(DZ[b], H2[b * kNH + k], s);
+  } else {
+    for (int64_t b = b0; b < b1; ++b) s += DZ[b];
+  }
+  part[(int64_t)blockIdx.y * kNP + q] = s;
+}
+
+__global__ void __launch_bounds__(256)
+k_mlp_reduce(int n_chunks, const float* __restrict__ part,
+             float* __restrict__ grad, int n_lossp,
+             const float* __restrict__ lossp, float inv_n,
+             float* __restrict__ loss) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < kNP) {
+    float s = 0.f;
+    for (int c = 0; c < n_chunks; ++c) s += part[(int64_t)c * kNP + q];
+    grad[q] = s;
+  }
+  if (q == 0) {
+    float s = 0.f;
+    for (int b = 0; b < n_lossp; ++b) s += lossp[b];
+    *loss = s * inv_n;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_adam(float* __restrict__ w, const float* __restrict__ g,
+       float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+       float b2, float eps, float c1, float c2) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= kNP) return;
+  const float gq = g[q];
+  const float mq = b1 * m[q] + (1.f - b1) * gq;
+  const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
+  m[q] = mq;
+  v[q] = vq;
+  w[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+}  // namespace
+
+// ---- launchers ----------------------------------------------------------------
+
+int learn_reserve_cells(nb_ctx* c) {
+  const size_t nc = (size_t)c->n_cell;
+  int rc = reserve(c, c->c_com, nc);
+  if (!rc) rc = reserve(c, c->c_com0, nc);
+  if (!rc) rc = reserve(c, c->c_shift, nc);
+  if (!rc) rc = reserve(c, c->c_ctr, nc);
+  return rc;
+}
+
+int learn_reserve_groups(nb_ctx* c) {
+  const size_t ng = (size_t)c->n_groups;
+  int rc = reserve(c, c->g_clo, ng);
+  if (!rc) rc = reserve(c, c->g_chi, ng);
+  if (!rc) rc = reserve(c, c->g_tau0, ng);
+  if (!rc) rc = reserve(c, c->g_sa, ng);
+  if (!rc) rc = reserve(c, c->g_so, ng);
+  if (!rc) rc = reserve(c, c->g_age, ng);
+  if (!rc) rc = reserve(c, c->pick, ng + 1);
+  if (!rc) rc = reserve(c, c->pickpos, ng + 1);
+  if (!rc) rc = reserve(c, c->sel, ng);
+  if (!rc) rc = reserve(c, c->ne2, ng);
+  if (!rc) rc = reserve(c, c->ns2, ng);
+  if (!rc) rc = reserve(c, c->feat, (size_t)kNF * ng);
+  if (!rc) rc = reserve(c, c->prob, ng);
+  if (!rc) rc = reserve(c, c->stale, ng);
+  return rc;
+}
+
+// Centres of mass in FP64 and the shifted centres.  At a construction step
+// (c->in_build) the construction-time centres are set to the current ones
+// first, so every shift is zero.
+int launch_com(nb_ctx* c) {
+  int rc = learn_reserve_cells(c);
+  if (rc) return rc;
+  if (c->n_leaves > 0)
+    hipLaunchKernelGGL(k_com_leaf, dim3(grid_for(c->n_leaves, 256)),
+                       dim3(256), 0, c->stream, c->n_leaves,
+                       (const uint32_t*)c->lvl_cells.p + c->lvl_off[kLevels],
+                       (const CellRec*)c->c_rec.p, (const double4*)c->pos.p,
+                       c->c_com.p);
+  for (int l = kMaxLevel - 1; l >= 0; --l) {
+    const int64_t cnt = c->lvl_count[l];
+    if (cnt == 0) continue;
+    hipLaunchKernelGGL(k_com_internal, dim3(grid_for(cnt, 256)), dim3(256), 0,
+                       c->stream, cnt,
+                       (const uint32_t*)c->lvl_cells.p + c->lvl_off[l],
+                       (const CellRec*)c->c_rec.p, c->c_com.p);
+  }
+  rc = hip_check(c, hipGetLastError(), "centre-of-mass launch");
+  if (rc) return rc;
+  if (c->in_build) {
+    rc = hip_check(c, hipMemcpyAsync(c->c_com0.p, c->c_com.p,
+                                     (size_t)c->n_cell * sizeof(double4),
+                                     hipMemcpyDeviceToDevice, c->stream),
+                   "centre-of-mass copy");
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_shift, dim3(grid_for(c->n_cell, 256)), dim3(256), 0,
+                     c->stream, c->n_cell, (const CellRec*)c->c_rec.p,
+                     (const double4*)c->c_com.p, (const double4*)c->c_com0.p,
+                     c->c_shift.p, c->c_ctr.p);
+  return hip_check(c, hipGetLastError(), "shift launch");
+}
+
+int learn_after_groups(nb_ctx* c) {
+  int rc = learn_reserve_groups(c);
+  if (!rc) rc = fill_u32(c, c->g_age.p, c->n_groups, 0u);
+  return rc;
+}
+
+int launch_age_inc(nb_ctx* c) {
+  hipLaunchKernelGGL(k_age_inc, dim3(grid_for(c->n_groups, 256)), dim3(256),
+                     0, c->stream, c->n_groups, c->g_age.p);
+  return hip_check(c, hipGetLastError(), "age launch");
+}
+
+int launch_features(nb_ctx* c) {
+  int rc = launch_group_box(c, c->g_clo.p, c->g_chi.p);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_features, dim3(grid_for(c->n_groups, 256)), dim3(256),
+                     0, c->stream, c->n_groups, (const uint32_t*)c->g_cell.p,
+                     (const uint32_t*)c->g_begin.p,
+                     (const uint32_t*)c->g_count.p, (const CellRec*)c->c_rec.p,
+                     (const Root*)c->root.p, (const uint32_t*)c->seg.p,
+                     (const double4*)c->g_clo.p, (const double4*)c->g_chi.p,
+                     (const double4*)c->g_lo.p, (const double4*)c->g_hi.p,
+                     (const double4*)c->g_tau0.p,
+                     (const double4*)c->c_shift.p, (const double*)c->g_sa.p,
+                     (const double*)c->g_so.p, (const uint32_t*)c->g_age.p,
+                     (const uint64_t*)c->epj_off.p,
+                     (const uint64_t*)c->spj_off.p, c->cfg.k_max, c->feat.p);
+  return hip_check(c, hipGetLastError(), "feature launch");
+}
+
+int launch_stale(nb_ctx* c) {
+  int rc = launch_group_box(c, c->g_clo.p, c->g_chi.p);
+  if (!rc) rc = launch_walk_stale(c, c->stale.p);
+  return rc;
+}
+
+int mlp_forward(nb_ctx* c, int64_t n, const float* x, float* p) {
+  if (n <= 0) return NB_OK;
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(grid_for(n, 256)), dim3(256), 0,
+                     c->stream, n, x, (const float*)c->mlp_w.p, p);
+  return hip_check(c, hipGetLastError(), "perceptron launch");
+}
+
+// Gradient of the mean (weighted) cross-entropy over samples [0, n) of x, y
+// into c->mlp_g and the loss into c->mlp_loss (device).
+int mlp_grad(nb_ctx* c, int64_t n, const float* x, const float* y, float pw) {
+  const int64_t nlp = grid_for(n, 256);
+  const int64_t nch = (n + kChunk - 1) / kChunk;
+  int rc = reserve(c, c->mlp_act, (size_t)4 * kNH * n);
+  if (!rc) rc = reserve(c, c->mlp_dz, (size_t)n);
+  if (!rc) rc = reserve(c, c->mlp_lossp, (size_t)nlp);
+  if (!rc) rc = reserve(c, c->mlp_part, (size_t)nch * kNP);
+  if (rc) return rc;
+  float* H1 = c->mlp_act.p;
+  float* H2 = H1 + (size_t)kNH * n;
+  float* D1 = H2 + (size_t)kNH * n;
+  float* D2 = D1 + (size_t)kNH * n;
+  const float inv_n = (float)(1.0 / (double)n);
+  hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)nlp), dim3(256), 0, c->stream,
+                     n, x, y, (const float*)c->mlp_w.p, pw, inv_n, H1, H2, D1,
+                     D2, c->mlp_dz.p, c->mlp_lossp.p);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(grid_for(kNP, 256), (unsigned)nch),
+                     dim3(256), 0, c->stream, n, x, (const float*)H1,
+                     (const float*)H2, (const float*)D1, (const float*)D2,
+                     (const float*)c->mlp_dz.p, c->mlp_part.p);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3(grid_for(kNP, 256)), dim3(256), 0,
+                     c->stream, (int)nch, (const float*)c->mlp_part.p,
+                     c->mlp_g.p, (int)nlp, (const float*)c->mlp_lossp.p,
+                     inv_n, c->mlp_g.p + kNP);
+  return hip_check(c, hipGetLastError(), "perceptron gradient launch");
+}
+
+int mlp_adam(nb_ctx* c, const float* g, float lr, float b1, float b2,
+             float eps) {
+  c->mlp_t += 1;
+  const float c1 = (float)(1.0 - std::pow((double)b1, (double)c->mlp_t));
+  const float c2 = (float)(1.0 - std::pow((double)b2, (double)c->mlp_t));
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(kNP, 256)), dim3(256), 0,
+                     c->stream, c->mlp_w.p, g, c->mlp_m.p, c->mlp_v.p, lr, b1,
+                     b2, eps, c1, c2);
+  return hip_check(c, hipGetLastError(), "adam launch");
+}
+
+int mlp_ensure(nb_ctx* c) {
+  if (c->mlp_w.p) return NB_OK;
+  int rc = reserve(c, c->mlp_w, kNP);
+  if (!rc) rc = reserve(c, c->mlp_m, kNP);
+  if (!rc) rc = reserve(c, c->mlp_v, kNP);
+  if (!rc) rc = reserve(c, c->mlp_g, kNP + 1);
+  if (rc) return rc;
+  // zero weights: p = 1/2 everywhere
+  rc = hip_check(c, hipMemsetAsync(c->mlp_w.p, 0, kNP * 4, c->stream), "init");
+  if (!rc) rc = hip_check(c, hipMemsetAsync(c->mlp_m.p, 0, kNP * 4, c->stream), "init");
+  if (!rc) rc = hip_check(c, hipMemsetAsync(c->mlp_v.p, 0, kNP * 4, c->stream), "init");
+  c->mlp_t = 0;
+  return rc;
+}
+
+// Refresh the lists of the groups flagged in c->pick (n_sel of them, ids in
+// c->sel in ascending order, c->pickpos = exclusive scan of c->pick).  The
+// current boxes must be in g_clo / g_chi.  One host synchronisation (list
+// totals).
+int refresh_selected(nb_ctx* c, int64_t n_sel) {
+  const int64_t G = c->n_groups;
+  int rc;
+  c->last_refreshed = n_sel;
+  if (n_sel == 0) return NB_OK;
+  drop_graph(c);
+  // count pass over the selection (counts indexed by selection slot)
+  rc = launch_walk_sel(c, false, n_sel, c->sel.p, c->g_clo.p, c->g_chi.p,
+                       nullptr, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_merge_counts, dim3(grid_for(G, 256)), dim3(256), 0,
+                     c->stream, G, (const uint32_t*)c->pick.p,
+                     (const uint32_t*)c->pickpos.p,
+                     (const uint32_t*)c->cnt_e.p, (const uint32_t*)c->cnt_s.p,
+                     (const uint64_t*)c->epj_off.p,
+                     (const uint64_t*)c->spj_off.p, c->ne2.p, c->ns2.p);
+  rc = hip_check(c, hipGetLastError(), "merge launch");
+  if (!rc) rc = reserve(c, c->epj_off2, (size_t)G + 1);
+  if (!rc) rc = reserve(c, c->spj_off2, (size_t)G + 1);
+  if (!rc) rc = scan_u32_to_u64(c, c->ne2.p, c->epj_off2.p, G);
+  if (!rc) rc = scan_u32_to_u64(c, c->ns2.p, c->spj_off2.p, G);
+  if (!rc) rc = scan_u32_to_u64(c, c->cnt_t.p, c->tok_off.p, n_sel);
+  if (!rc) rc = launch_interactions(c, c->ne2.p, c->ns2.p);
+  if (rc) return rc;
+  if ((rc = stage_d2h(c, 0, c->epj_off2.p + G, 8))) return rc;
+  if ((rc = stage_d2h(c, 8, c->spj_off2.p + G, 8))) return rc;
+  if ((rc = stage_d2h(c, 16, c->red.p, 8))) return rc;
+  if ((rc = stage_d2h(c, 24, c->tok_off.p + n_sel, 8))) return rc;
+  if ((rc = sync_stream(c))) return rc;
+  const uint64_t* h = static_cast<const uint64_t*>(c->h_small);
+  const int64_t ne = (int64_t)h[0], ns = (int64_t)h[1];
+  const int64_t n_inter = (int64_t)h[2], n_tok = (int64_t)h[3];
+  if ((rc = reserve(c, c->epj2, (size_t)ne + 1))) return rc;
+  if ((rc = reserve(c, c->spj2, (size_t)ns + 1))) return rc;
+  if ((rc = reserve(c, c->tok, (size_t)n_tok + 1))) return rc;
+  rc = launch_walk_sel(c, true, n_sel, c->sel.p, c->g_clo.p, c->g_chi.p,
+                       c->epj_off2.p, c->spj_off2.p, c->epj2.p, c->spj2.p);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_copy_lists, dim3(grid_for(G, 4)), dim3(256), 0,
+                     c->stream, G, (const uint32_t*)c->pick.p,
+                     (const uint64_t*)c->epj_off.p, (const uint32_t*)c->epj.p,
+                     (const uint64_t*)c->spj_off.p, (const uint32_t*)c->spj.p,
+                     (const uint64_t*)c->epj_off2.p, c->epj2.p,
+                     (const uint64_t*)c->spj_off2.p, c->spj2.p);
+  hipLaunchKernelGGL(k_refresh_meta, dim3(grid_for(G, 256)), dim3(256), 0,
+                     c->stream, G, (const uint32_t*)c->pick.p,
+                     (const double4*)c->g_clo.p, (const double4*)c->g_chi.p,
+                     c->g_lo.p, c->g_hi.p, c->g_age.p);
+  rc = hip_check(c, hipGetLastError(), "list copy launch");
+  if (rc) return rc;
+  std::swap(c->epj, c->epj2);
+  std::swap(c->spj, c->spj2);
+  std::swap(c->epj_off, c->epj_off2);
+  std::swap(c->spj_off, c->spj_off2);
+  c->n_epj = ne;
+  c->n_spj = ns;
+  c->n_inter = n_inter;
+  c->total_refreshed += n_sel;
+  return NB_OK;
+}
+
+// Selection from host ids (ascending, unique, in range: checked here).
+int refresh_host_sel(nb_ctx* c, int64_t n_sel, const int64_t* sel) {
+  const int64_t G = c->n_groups;
+  if (n_sel < 0 || n_sel > G || (n_sel > 0 && !sel))
+    return set_err(c, NB_ERR_INPUT, "bad selection size %lld", (long long)n_sel);
+  std::vector<uint32_t> h((size_t)n_sel);
+  for (int64_t i = 0; i < n_sel; ++i) {
+    if (sel[i] < 0 || sel[i] >= G || (i > 0 && sel[i] <= sel[i - 1]))
+      return set_err(c, NB_ERR_INPUT,
+                     "selection must hold ascending group ids in [0, %lld)",
+                     (long long)G);
+    h[(size_t)i] = (uint32_t)sel[i];
+  }
+  int rc = launch_group_box(c, c->g_clo.p, c->g_chi.p);
+  if (!rc) rc = fill_u32(c, c->pick.p, G, 0u);
+  if (rc) return rc;
+  if (n_sel > 0) {
+    rc = hip_check(c, hipMemcpyAsync(c->sel.p, h.data(), (size_t)n_sel * 4,
+                                     hipMemcpyHostToDevice, c->stream),
+                   "selection upload");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_mark, dim3(grid_for(n_sel, 256)), dim3(256), 0,
+                       c->stream, n_sel, (const uint32_t*)c->sel.p, c->pick.p);
+    rc = hip_check(c, hipGetLastError(), "mark launch");
+  }
+  if (!rc) rc = scan_u32(c, c->pick.p, c->pickpos.p, G);
+  if (!rc) rc = sync_stream(c);  // the host vector goes out of scope
+  if (!rc) rc = refresh_selected(c, n_sel);
+  return rc;
+}
+
+// Predictor-driven refresh: features, perceptron, selection p > p* or
+// age >= k_max.  One host synchronisation for the selection size, one more
+// when anything is refreshed.
+int refresh_predicted(nb_ctx* c) {
+  const int64_t G = c->n_groups;
+  int rc = mlp_ensure(c);
+  if (!rc) rc = launch_features(c);
+  if (!rc) rc = mlp_forward(c, G, c->feat.p, c->prob.p);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_select, dim3(grid_for(G, 256)), dim3(256), 0,
+                     c->stream, G, (const float*)c->prob.p,
+                     (const uint32_t*)c->g_age.p, (float)c->cfg.p_star,
+                     (uint32_t)c->cfg.k_max, c->pick.p);
+  rc = hip_check(c, hipGetLastError(), "select launch");
+  if (!rc) rc = scan_u32(c, c->pick.p, c->pickpos.p, G);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(G, 256)), dim3(256), 0,
+                     c->stream, G, (const uint32_t*)c->pick.p,
+                     (const uint32_t*)c->pickpos.p, c->sel.p);
+  rc = hip_check(c, hipGetLastError(), "compact launch");
+  if (!rc) rc = stage_d2h(c, 0, c->pickpos.p + G, 4);
+  if (!rc) rc = sync_stream(c);
+  if (rc) return rc;
+  const int64_t n_sel = static_cast<const uint32_t*>(c->h_small)[0];
+  return refresh_selected(c, n_sel);
+}
+
+int labels_to_float(nb_ctx* c, float* out) {
+  hipLaunchKernelGGL(k_u8_to_f32, dim3(grid_for(c->n_groups, 256)), dim3(256),
+                     0, c->stream, c->n_groups, (const uint8_t*)c->stale.p,
+                     out);
+  return hip_check(c, hipGetLastError(), "label launch");
+}
+
+}  // namespace nb
+
+// ---- C ABI ------------------------------------------------------------------
+using namespace nb;
+
+namespace {
+
+int need_refresh_state(nb_ctx* c) {
+  if (!c->learn)
+    return set_err(c, NB_ERR_STATE, "needs a context with NB_FLAG_REFRESH");
+  if (!c->tree_valid || !c->lists_valid || !c->lists_reusable)
+    return set_err(c, NB_ERR_STATE,
+                   "needs lists made with MAKE_LIST_FOR_REUSE");
+  if (!c->shift_fresh)
+    return set_err(c, NB_ERR_STATE,
+                   "positions moved since the last force computation");
+  return NB_OK;
+}
+
+int copy_out(nb_ctx* c, void* dst, const void* src, size_t bytes,
+             int on_device) {
+  int rc = hip_check(c, hipMemcpyAsync(dst, src, bytes,
+                                       on_device ? hipMemcpyDeviceToDevice
+                                                 : hipMemcpyDeviceToHost,
+                                       c->stream),
+                     "readback");
+  return rc ? rc : sync_stream(c);
+}
+
+// Inputs of the perceptron calls: device pointers are used in place, host
+// arrays are copied into the context's staging buffers.
+int stage_in(nb_ctx* c, DBuf<float>& buf, const float* src, size_t count,
+             int on_device, const float** out) {
+  if (on_device) {
+    *out = src;
+    return NB_OK;
+  }
+  int rc = reserve(c, buf, count);
+  if (!rc) rc = hip_check(c, hipMemcpyAsync(buf.p, src, count * 4,
+                                            hipMemcpyHostToDevice, c->stream),
+                          "upload");
+  if (!rc) rc = sync_stream(c);
+  *out = buf.p;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nb_group_features(nb_ctx* c, float* feat, int on_device) {
+  if (!c) return NB_ERR_INPUT;
+  int rc = need_refresh_state(c);
+  if (!rc) rc = launch_features(c);
+  if (!rc && feat)
+    rc = copy_out(c, feat, c->feat.p, (size_t)c->n_groups * NB_MLP_NIN * 4,
+                  on_device);
+  return rc;
+}
+
+int nb_group_stale(nb_ctx* c, uint8_t* stale, float* label, int on_device) {
+  if (!c) return NB_ERR_INPUT;
+  int rc = need_refresh_state(c);
+  if (!rc) rc = launch_stale(c);
+  if (!rc && stale)
+    rc = copy_out(c, stale, c->stale.p, (size_t)c->n_groups, on_device);
+  if (!rc && label) {
+    if (on_device) {
+      rc = labels_to_float(c, label);
+      if (!rc) rc = sync_stream(c);
+    } else {
+      std::vector<uint8_t> h((size_t)c->n_groups);
+      rc = copy_out(c, h.data(), c->stale.p, h.size(), 0);
+      for (size_t g = 0; !rc && g < h.size(); ++g) label[g] = (float)h[g];
+    }
+  }
+  return rc;
+}
+
+int nb_refresh_lists(nb_ctx* c, int64_t n_sel, const int64_t* sel) {
+  if (!c) return NB_ERR_INPUT;
+  int rc = need_refresh_state(c);
+  if (rc) return rc;
+  Timed t(c, NB_PH_REFRESH);
+  return refresh_host_sel(c, n_sel, sel);
+}
+
+int nb_get_group_state(nb_ctx* c, double* sa, double* so, int32_t* age) {
+  if (!c) return NB_ERR_INPUT;
+  if (!c->learn || !c->lists_valid)
+    return set_err(c, NB_ERR_STATE, "needs NB_FLAG_REFRESH and lists");
+  const size_t ng = (size_t)c->n_groups;
+  int rc = NB_OK;
+  if (sa) rc = copy_out(c, sa, c->g_sa.p, ng * 8, 0);
+  if (!rc && so) rc = copy_out(c, so, c->g_so.p, ng * 8, 0);
+  if (!rc && age) {
+    std::vector<uint32_t> h(ng);
+    rc = copy_out(c, h.data(), c->g_age.p, ng * 4, 0);
+    for (size_t g = 0; !rc && g < ng; ++g)
+      age[g] = (int32_t)(h[g] > 0x7FFFFFFFu ? 0x7FFFFFFFu : h[g]);
+  }
+  return rc;
+}
+
+int nb_mlp_set(nb_ctx* c, const float* w, int64_t nw) {
+  if (!c || !w) return NB_ERR_INPUT;
+  if (nw != NB_MLP_NPARAM)
+    return set_err(c, NB_ERR_INPUT, "expected %d parameters", NB_MLP_NPARAM);
+  int rc = mlp_ensure(c);
+  if (!rc) rc = hip_check(c, hipMemcpyAsync(c->mlp_w.p, w, NB_MLP_NPARAM * 4,
+                                            hipMemcpyHostToDevice, c->stream),
+                          "weight upload");
+  if (!rc) rc = hip_check(c, hipMemsetAsync(c->mlp_m.p, 0, NB_MLP_NPARAM * 4,
+                                            c->stream), "adam reset");
+  if (!rc) rc = hip_check(c, hipMemsetAsync(c->mlp_v.p, 0, NB_MLP_NPARAM * 4,
+                                            c->stream), "adam reset");
+  if (!rc) rc = sync_stream(c);
+  c->mlp_t = 0;
+  return rc;
+}
+
+int nb_mlp_get(nb_ctx* c, float* w, int64_t nw) {
+  if (!c || !w) return NB_ERR_INPUT;
+  if (nw != NB_MLP_NPARAM)
+    return set_err(c, NB_ERR_INPUT, "expected %d parameters", NB_MLP_NPARAM);
+  int rc = mlp_ensure(c);
+  if (!rc) rc = copy_out(c, w, c->mlp_w.p, NB_MLP_NPARAM * 4, 0);
+  return rc;
+}
+
+int nb_mlp_forward(nb_ctx* c, int64_t n, const float* x, float* p,
+                   int on_device) {
+  if (!c) return NB_ERR_INPUT;
+  if (n < 0 || (n > 0 && (!x || !p)))
+    return set_err(c, NB_ERR_INPUT, "bad perceptron input");
+  if (n == 0) return NB_OK;
+  int rc = mlp_ensure(c);
+  const float* xd = nullptr;
+  if (!rc) rc = stage_in(c, c->mlp_x, x, (size_t)n * NB_MLP_NIN, on_device, &xd);
+  if (rc) return rc;
+  float* pd = p;
+  if (!on_device) {
+    if ((rc = reserve(c, c->mlp_y, (size_t)n))) return rc;
+    pd = c->mlp_y.p;
+  }
+  rc = mlp_forward(c, n, xd, pd);
+  if (!rc) rc = on_device ? sync_stream(c) : copy_out(c, p, pd, (size_t)n * 4, 0);
+  return rc;
+}
+
+int nb_mlp_grad(nb_ctx* c, int64_t n, const float* x, const float* y,
+                float pos_weight, float* loss, float* grad, int on_device) {
+  if (!c) return NB_ERR_INPUT;
+  if (n < 1 || !x || !y || !(pos_weight > 0.f))
+    return set_err(c, NB_ERR_INPUT, "bad perceptron input");
+  int rc = mlp_ensure(c);
+  const float *xd = nullptr, *yd = nullptr;
+  if (!rc) rc = stage_in(c, c->mlp_x, x, (size_t)n * NB_MLP_NIN, on_device, &xd);
+  if (!rc) rc = stage_in(c, c->mlp_y, y, (size_t)n, on_device, &yd);
+  if (!rc) rc = mlp_grad(c, n, xd, yd, pos_weight);
+  if (rc) return rc;
+  if (grad) rc = copy_out(c, grad, c->mlp_g.p, NB_MLP_NPARAM * 4, on_device);
+  if (!rc && loss) rc = copy_out(c, loss, c->mlp_g.p + NB_MLP_NPARAM, 4, 0);
+  if (!rc) rc = sync_stream(c);
+  return rc;
+}
+
+int nb_mlp_adam(nb_ctx* c, const float* grad, float lr, float beta1,
+                float beta2, float eps, int on_device) {
+  if (!c) return NB_ERR_INPUT;
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return set_err(c, NB_ERR_INPUT, "bad Adam parameters");
+  int rc = mlp_ensure(c);
+  const float* gd = c->mlp_g.p;
+  if (!rc && grad) rc = stage_in(c, c->mlp_part, grad, NB_MLP_NPARAM, on_device, &gd);
+  if (!rc) rc = mlp_adam(c, gd, lr, beta1, beta2, eps);
+  if (!rc) rc = sync_stream(c);
+  return rc;
+}
+
+int nb_mlp_train(nb_ctx* c, int64_t n, const float* x, const float* y,
+                 int on_device, int epochs, int64_t batch, float lr,
+                 float pos_weight, float* loss) {
+  if (!c) return NB_ERR_INPUT;
+  if (n < 1 || !x || !y || epochs < 1 || batch < 1 || !(lr > 0.f) ||
+      !(pos_weight > 0.f))
+    return set_err(c, NB_ERR_INPUT, "bad training input");
+  int rc = mlp_ensure(c);
+  const float *xd = nullptr, *yd = nullptr;
+  // host data: both arrays go to the two staging buffers; the gradient
+  // scratch is separate
+  if (!rc) rc = stage_in(c, c->mlp_x, x, (size_t)n * NB_MLP_NIN, on_device, &xd);
+  if (!rc) rc = stage_in(c, c->mlp_y, y, (size_t)n, on_device, &yd);
+  for (int e = 0; !rc && e < epochs; ++e) {
+    for (int64_t b0 = 0; !rc && b0 < n; b0 += batch) {
+      const int64_t nb = b0 + batch < n ? batch : n - b0;
+      rc = mlp_grad(c, nb, xd + (size_t)b0 * NB_MLP_NIN, yd + b0, pos_weight);
+      if (!rc) rc = mlp_adam(c, c->mlp_g.p, lr, 0.9f, 0.999f, 1e-8f);
+    }
+  }
+  if (!rc && loss) {
+    rc = mlp_grad(c, n, xd, yd, pos_weight);
+    if (!rc) rc = copy_out(c, loss, c->mlp_g.p + NB_MLP_NPARAM, 4, 0);
+  }
+  if (!rc) rc = sync_stream(c);
+  return rc;
+}
+
+}  // extern "C"

@@ -17,23 +17,27 @@ k_kick_drift(int64_t n, const float4* __restrict__ acc,
   const float4 a = acc[i];
   double4 p = pos[i];
   double gx = (double)a.x, gy = (double)a.y, gz = (double)a.z;
+  // every operation rounded once, in the order written, so that the FP64
+  // update matches a plain scalar evaluation bit for bit
   if (gm_ext != 0.0) {
-    const double r2 = p.x * p.x + p.y * p.y + p.z * p.z;
-    const double r = sqrt(r2);
-    const double k = gm_ext / (r2 * r);
-    gx -= k * p.x;
-    gy -= k * p.y;
-    gz -= k * p.z;
+    const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(p.x, p.x),
+                                          __dmul_rn(p.y, p.y)),
+                                __dmul_rn(p.z, p.z));
+    const double r = __dsqrt_rn(r2);
+    const double k = __ddiv_rn(gm_ext, __dmul_rn(r2, r));
+    gx = __dsub_rn(gx, __dmul_rn(k, p.x));
+    gy = __dsub_rn(gy, __dmul_rn(k, p.y));
+    gz = __dsub_rn(gz, __dmul_rn(k, p.z));
   }
-  const double ux = vx[i] + gx * dtk;
-  const double uy = vy[i] + gy * dtk;
-  const double uz = vz[i] + gz * dtk;
+  const double ux = __dadd_rn(vx[i], __dmul_rn(gx, dtk));
+  const double uy = __dadd_rn(vy[i], __dmul_rn(gy, dtk));
+  const double uz = __dadd_rn(vz[i], __dmul_rn(gz, dtk));
   vx[i] = ux;
   vy[i] = uy;
   vz[i] = uz;
-  p.x += ux * dtd;
-  p.y += uy * dtd;
-  p.z += uz * dtd;
+  p.x = __dadd_rn(p.x, __dmul_rn(ux, dtd));
+  p.y = __dadd_rn(p.y, __dmul_rn(uy, dtd));
+  p.z = __dadd_rn(p.z, __dmul_rn(uz, dtd));
   pos[i] = p;
 }
 

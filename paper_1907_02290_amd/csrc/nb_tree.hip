@@ -828,7 +828,18 @@ int launch_moments(nb_ctx* c) {
                        (const CellRec*)c->c_rec.p, c->c_mom.p, c->c_quad.p,
                        c->c_pm.p);
   }
-  return hip_check(c, hipGetLastError(), "moments launch");
+  rc = hip_check(c, hipGetLastError(), "moments launch");
+  if (!rc && c->learn) rc = launch_com(c);
+  return rc;
+}
+
+// Tight boxes of every group's particles at the current positions.
+int launch_group_box(nb_ctx* c, double4* lo, double4* hi) {
+  hipLaunchKernelGGL(k_group_box, dim3(grid_for(c->n_groups, 4)), dim3(256),
+                     0, c->stream, c->n_groups, (const uint32_t*)c->g_begin.p,
+                     (const uint32_t*)c->g_count.p, (const double4*)c->pos.p,
+                     lo, hi);
+  return hip_check(c, hipGetLastError(), "group box launch");
 }
 
 // How to split the last n < 64 particles of a group into work items.  A
@@ -880,11 +891,7 @@ int launch_group_fill(nb_ctx* c) {
                      0, c->stream, c->n_cell, (const uint32_t*)c->gflag.p,
                      (const CellRec*)c->c_rec.p, tab, c->g_cell.p,
                      c->g_begin.p, c->g_count.p, c->g_chunks.p);
-  hipLaunchKernelGGL(k_group_box, dim3(grid_for(c->n_groups, 4)), dim3(256),
-                     0, c->stream, c->n_groups, (const uint32_t*)c->g_begin.p,
-                     (const uint32_t*)c->g_count.p, (const double4*)c->pos.p,
-                     c->g_lo.p, c->g_hi.p);
-  rc = hip_check(c, hipGetLastError(), "group fill launch");
+  rc = launch_group_box(c, c->g_lo.p, c->g_hi.p);
   if (rc) return rc;
   rc = scan_u32(c, c->g_chunks.p, c->g_chunks.p, c->n_groups);
   if (rc) return rc;

@@ -36,12 +36,20 @@ __device__ inline int64_t xcd_block(int64_t nblk) {
 constexpr uint32_t kLeafTag = 0x80000000u;
 constexpr int kSeg = 16;  // tokens per 64-byte output segment
 
-template <bool FILL>
+// LEARN: the variant used with per-group list refresh.  Threads take the
+// groups listed in `sel` (all groups when sel is NULL), the centres come
+// from `ctr` (geometric centre carried by the cell's centre-of-mass shift,
+// and rcrit^2) instead of the cell records, and the count pass records the
+// opening-test slacks and the cell shift of the group for the predictor.
+template <bool FILL, bool LEARN>
 __global__ void __launch_bounds__(kWalkThreads)
-k_walk(int64_t n_groups, int64_t nblk, int64_t n_cell,
+k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
        const uint32_t* __restrict__ g_begin,
        const uint32_t* __restrict__ g_count, const double4* __restrict__ g_lo,
        const double4* __restrict__ g_hi, const CellRec* __restrict__ rec,
+       const double4* __restrict__ ctr, const uint32_t* __restrict__ g_cell,
+       const double4* __restrict__ shift, double* __restrict__ g_sa,
+       double* __restrict__ g_so, double4* __restrict__ g_tau0,
        const uint32_t* __restrict__ seg, const uint32_t* __restrict__ croot,
        uint32_t* __restrict__ cnt_e, uint32_t* __restrict__ cnt_s,
        uint32_t* __restrict__ cnt_t, const uint64_t* __restrict__ tok_off,
@@ -52,8 +60,9 @@ k_walk(int64_t n_groups, int64_t nblk, int64_t n_cell,
   __shared__ uint32_t stage[FILL ? kSeg : 1][kWalkThreads];
   const int64_t blk = xcd_block(nblk);
   if (blk >= nblk) return;
-  const int64_t g = blk * kWalkThreads + threadIdx.x;
-  if (g >= n_groups) return;
+  const int64_t t = blk * kWalkThreads + threadIdx.x;
+  if (t >= n_walk) return;
+  const int64_t g = (LEARN && sel) ? (int64_t)sel[t] : t;
   const uint32_t gb = g_begin[g];
   const uint32_t ge = gb + g_count[g];
   const double4 lo = g_lo[g], hi = g_hi[g];
@@ -61,9 +70,10 @@ k_walk(int64_t n_groups, int64_t nblk, int64_t n_cell,
   uint64_t out = 0;   // next output slot of this lane
   int sc = 0;         // staged tokens
   if (FILL) {
-    out = tok_off[g];
+    out = tok_off[t];
     dst = tok;
   }
+  double sa = __builtin_inf(), so = __builtin_inf();
   uint32_t ne = 0, ns = 0, nl = 0;
   // the walk covers the cells of the group's own system
   const uint32_t sys = seg[gb];
@@ -71,7 +81,7 @@ k_walk(int64_t n_groups, int64_t nblk, int64_t n_cell,
   const uint32_t nc = croot[sys + 1];
   while (c < nc) {
     const uint4 m = rec[c].meta;
-    const double4 cc = rec[c].geo;
+    const double4 cc = LEARN ? ctr[c] : rec[c].geo;
     bool open;
     if (m.x <= gb && m.y >= ge) {
       open = true;
@@ -93,6 +103,16 @@ k_walk(int64_t n_groups, int64_t nblk, int64_t n_cell,
           __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
                     __dmul_rn(dz, dz));
       open = !(d2 > cc.w);
+      if (LEARN && !FILL) {
+        const double dd = __dsqrt_rn(d2), rr = __dsqrt_rn(cc.w);
+        if (open) {
+          const double v = __dsub_rn(rr, dd);
+          if (v < so) so = v;
+        } else {
+          const double v = __dsub_rn(dd, rr);
+          if (v < sa) sa = v;
+        }
+      }
     }
     const bool leaf = (m.w >> 8) & 1u;
     // skip ids always point past the cell; the guard keeps a damaged tree
@@ -131,28 +151,119 @@ k_walk(int64_t n_groups, int64_t nblk, int64_t n_cell,
   if (FILL) {
     for (int q = 0; q < sc; ++q) dst[out + q] = stage[q][threadIdx.x];
   } else {
-    cnt_e[g] = ne;
-    cnt_s[g] = ns;
-    cnt_t[g] = ns + nl;
+    cnt_e[t] = ne;
+    cnt_s[t] = ns;
+    cnt_t[t] = ns + nl;
+    if (LEARN) {
+      g_sa[g] = sa;
+      g_so[g] = so;
+      g_tau0[g] = shift[g_cell[g]];
+    }
   }
+}
+
+// Staleness of kept lists: walk each group with its current box and the
+// current centres (as the LEARN walk does) and compare on the fly with the
+// kept lists; a mismatch ends the walk.  An SPJ token must equal the next
+// kept SPJ id; an opened leaf must start the next stretch of kept EPJ ids
+// (leaves are disjoint particle ranges, so matching the first id of every
+// leaf and the total length matches every id).
+__global__ void __launch_bounds__(kWalkThreads)
+k_walk_stale(int64_t n_groups, int64_t nblk,
+             const uint32_t* __restrict__ g_begin,
+             const uint32_t* __restrict__ g_count,
+             const double4* __restrict__ g_lo,
+             const double4* __restrict__ g_hi,
+             const CellRec* __restrict__ rec,
+             const double4* __restrict__ ctr,
+             const uint32_t* __restrict__ seg,
+             const uint32_t* __restrict__ croot,
+             const uint64_t* __restrict__ epj_off,
+             const uint32_t* __restrict__ epj,
+             const uint64_t* __restrict__ spj_off,
+             const uint32_t* __restrict__ spj, uint8_t* __restrict__ stale) {
+  const int64_t blk = xcd_block(nblk);
+  if (blk >= nblk) return;
+  const int64_t g = blk * kWalkThreads + threadIdx.x;
+  if (g >= n_groups) return;
+  const uint32_t gb = g_begin[g];
+  const uint32_t ge = gb + g_count[g];
+  const double4 lo = g_lo[g], hi = g_hi[g];
+  const uint32_t* ke = epj + epj_off[g];
+  const uint64_t kne = epj_off[g + 1] - epj_off[g];
+  const uint32_t* ks = spj + spj_off[g];
+  const uint64_t kns = spj_off[g + 1] - spj_off[g];
+  uint64_t ie = 0, is = 0;
+  bool diff = false;
+  const uint32_t sys = seg[gb];
+  uint32_t c = croot[sys];
+  const uint32_t nc = croot[sys + 1];
+  while (c < nc) {
+    const uint4 m = rec[c].meta;
+    const double4 cc = ctr[c];
+    bool open;
+    if (m.x <= gb && m.y >= ge) {
+      open = true;
+    } else {
+      double dx = 0.0, dy = 0.0, dz = 0.0, t;
+      t = __dsub_rn(lo.x, cc.x);
+      if (t > dx) dx = t;
+      t = __dsub_rn(cc.x, hi.x);
+      if (t > dx) dx = t;
+      t = __dsub_rn(lo.y, cc.y);
+      if (t > dy) dy = t;
+      t = __dsub_rn(cc.y, hi.y);
+      if (t > dy) dy = t;
+      t = __dsub_rn(lo.z, cc.z);
+      if (t > dz) dz = t;
+      t = __dsub_rn(cc.z, hi.z);
+      if (t > dz) dz = t;
+      const double d2 =
+          __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                    __dmul_rn(dz, dz));
+      open = !(d2 > cc.w);
+    }
+    const bool leaf = (m.w >> 8) & 1u;
+    const uint32_t next = (!open || leaf) ? m.z : c + 1;
+    if (next <= c) break;
+    if (!open) {
+      if (is >= kns || ks[is] != c) {
+        diff = true;
+        break;
+      }
+      ++is;
+    } else if (leaf) {
+      if (ie >= kne || ke[ie] != m.x) {
+        diff = true;
+        break;
+      }
+      ie += m.y - m.x;
+    }
+    c = next;
+  }
+  stale[g] = (uint8_t)(diff || ie != kne || is != kns);
 }
 
 // One wave per group: the token stream -> SPJ ids and EPJ particle ids.
 // Tokens are read in chunks of 64; accepted cells are compacted with a
 // ballot, opened leaves are expanded using a wave scan of their sizes, so
 // every chunk lands in contiguous stretches of both lists.
+// Token offsets are per walked group (index t); output offsets per group id
+// (sel[t], or t when sel is NULL).
 __global__ void __launch_bounds__(256)
-k_expand(int64_t n_groups, int64_t nblk, const uint64_t* __restrict__ tok_off,
+k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
+         const uint64_t* __restrict__ tok_off,
          const uint32_t* __restrict__ tok, const CellRec* __restrict__ rec,
          const uint64_t* __restrict__ epj_off,
          const uint64_t* __restrict__ spj_off, uint32_t* __restrict__ epj,
          uint32_t* __restrict__ spj) {
   const int64_t blk = xcd_block(nblk);
   if (blk >= nblk) return;
-  const int64_t g = blk * 4 + (threadIdx.x >> 6);
+  const int64_t t = blk * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (g >= n_groups) return;
-  const uint64_t t0 = tok_off[g], t1 = tok_off[g + 1];
+  if (t >= n_walk) return;
+  const int64_t g = sel ? (int64_t)sel[t] : t;
+  const uint64_t t0 = tok_off[t], t1 = tok_off[t + 1];
   uint64_t oe = epj_off[g], os = spj_off[g];
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   for (uint64_t cb = t0; cb < t1; cb += 64) {
@@ -217,30 +328,60 @@ int launch_walk(nb_ctx* c, bool fill) {
   if (!rc) rc = reserve(c, c->spj_off, ng + 1);
   if (!rc) rc = reserve(c, c->tok_off, ng + 1);
   if (rc) return rc;
+  return launch_walk_sel(c, fill, c->n_groups, nullptr, c->g_lo.p, c->g_hi.p,
+                         c->epj_off.p, c->spj_off.p, c->epj.p, c->spj.p);
+}
+
+int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
+                    const double4* lo, const double4* hi,
+                    const uint64_t* epj_off, const uint64_t* spj_off,
+                    uint32_t* epj, uint32_t* spj) {
   if (c->n_cell >= (int64_t)kLeafTag)
     return set_err(c, NB_ERR_INPUT, "too many cells for 31-bit list tokens");
-  const int64_t nblk = grid_for(c->n_groups, kWalkThreads);
+  if (n_walk <= 0) return NB_OK;
+  const bool learn = c->learn;
+  if (!learn && sel) return set_err(c, NB_ERR_STATE, "selected walk needs refresh mode");
+  const int64_t nblk = grid_for(n_walk, kWalkThreads);
   const int64_t launch = (nblk + 7) / 8 * 8;
-  auto k = fill ? k_walk<true> : k_walk<false>;
+  auto k = fill ? (learn ? k_walk<true, true> : k_walk<true, false>)
+                : (learn ? k_walk<false, true> : k_walk<false, false>);
   hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
-                     c->stream, c->n_groups, nblk, c->n_cell,
+                     c->stream, n_walk, nblk, sel,
                      (const uint32_t*)c->g_begin.p,
-                     (const uint32_t*)c->g_count.p, (const double4*)c->g_lo.p,
-                     (const double4*)c->g_hi.p, (const CellRec*)c->c_rec.p,
-                     (const uint32_t*)c->seg.p, (const uint32_t*)c->croot.p,
-                     c->cnt_e.p, c->cnt_s.p, c->cnt_t.p,
-                     (const uint64_t*)c->tok_off.p, c->tok.p);
+                     (const uint32_t*)c->g_count.p, lo, hi,
+                     (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
+                     (const uint32_t*)c->g_cell.p,
+                     (const double4*)c->c_shift.p, c->g_sa.p, c->g_so.p,
+                     c->g_tau0.p, (const uint32_t*)c->seg.p,
+                     (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
+                     c->cnt_t.p, (const uint64_t*)c->tok_off.p, c->tok.p);
   int rc2 = hip_check(c, hipGetLastError(), "walk launch");
   if (rc2 || !fill) return rc2;
-  const int64_t eblk = grid_for(c->n_groups, 4);
+  const int64_t eblk = grid_for(n_walk, 4);
   const int64_t elaunch = (eblk + 7) / 8 * 8;
   hipLaunchKernelGGL(k_expand, dim3((unsigned)elaunch), dim3(256), 0,
-                     c->stream, c->n_groups, eblk,
+                     c->stream, n_walk, eblk, sel,
                      (const uint64_t*)c->tok_off.p,
                      (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
-                     (const uint64_t*)c->epj_off.p,
-                     (const uint64_t*)c->spj_off.p, c->epj.p, c->spj.p);
+                     epj_off, spj_off, epj, spj);
   return hip_check(c, hipGetLastError(), "expand launch");
+}
+
+int launch_walk_stale(nb_ctx* c, uint8_t* stale) {
+  if (c->n_groups <= 0) return NB_OK;
+  const int64_t nblk = grid_for(c->n_groups, kWalkThreads);
+  const int64_t launch = (nblk + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_walk_stale, dim3((unsigned)launch), dim3(kWalkThreads),
+                     0, c->stream, c->n_groups, nblk,
+                     (const uint32_t*)c->g_begin.p,
+                     (const uint32_t*)c->g_count.p,
+                     (const double4*)c->g_clo.p, (const double4*)c->g_chi.p,
+                     (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
+                     (const uint32_t*)c->seg.p, (const uint32_t*)c->croot.p,
+                     (const uint64_t*)c->epj_off.p, (const uint32_t*)c->epj.p,
+                     (const uint64_t*)c->spj_off.p, (const uint32_t*)c->spj.p,
+                     stale);
+  return hip_check(c, hipGetLastError(), "stale walk launch");
 }
 
 // After the count pass: CSR offsets and the interaction count (red[0]).
@@ -248,15 +389,20 @@ int launch_list_stats(nb_ctx* c) {
   int rc = scan_u32_to_u64(c, c->cnt_e.p, c->epj_off.p, c->n_groups);
   if (!rc) rc = scan_u32_to_u64(c, c->cnt_s.p, c->spj_off.p, c->n_groups);
   if (!rc) rc = scan_u32_to_u64(c, c->cnt_t.p, c->tok_off.p, c->n_groups);
-  if (!rc) rc = reserve(c, c->red, 16);
+  if (!rc) rc = launch_interactions(c, c->cnt_e.p, c->cnt_s.p);
+  return rc;
+}
+
+// Interaction count of per-group list lengths ne, ns into red[0].
+int launch_interactions(nb_ctx* c, const uint32_t* ne, const uint32_t* ns) {
+  int rc = reserve(c, c->red, 16);
   if (rc) return rc;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream,
                      (unsigned long long*)c->red.p, 8);
   unsigned nb = grid_for(c->n_groups, 256);
   if (nb > 1024) nb = 1024;
   hipLaunchKernelGGL(k_interactions, dim3(nb), dim3(256), 0, c->stream,
-                     c->n_groups, (const uint32_t*)c->g_count.p,
-                     (const uint32_t*)c->cnt_e.p, (const uint32_t*)c->cnt_s.p,
+                     c->n_groups, (const uint32_t*)c->g_count.p, ne, ns,
                      (unsigned long long*)c->red.p);
   return hip_check(c, hipGetLastError(), "list stats launch");
 }

@@ -24,11 +24,15 @@ NB_ERR_HIP = -5
 NB_MAKE_LIST = 0
 NB_MAKE_LIST_FOR_REUSE = 1
 NB_REUSE_LIST = 2
+NB_REUSE_REFRESH = 3
 
 PHASES = ("root", "keys", "sort", "reorder", "link", "moments", "groups",
-          "walk", "force", "kick", "graph")
+          "walk", "force", "kick", "graph", "refresh")
 NB_FLAG_TIMING = 1
 NB_FLAG_GRAPH = 2
+NB_FLAG_REFRESH = 4
+MLP_NIN = 12
+MLP_NPARAM = 5057
 
 STATUS = {NB_OK: "NB_OK", NB_ERR_INPUT: "NB_ERR_INPUT",
           NB_ERR_OOM: "NB_ERR_OOM", NB_ERR_LIST: "NB_ERR_LIST",
@@ -45,7 +49,8 @@ class nb_config(C.Structure):
     _fields_ = [("theta", C.c_double), ("eps", C.c_double), ("G", C.c_double),
                 ("ext_mass", C.c_double), ("n_leaf", C.c_int32),
                 ("n_grp", C.c_int32), ("order", C.c_int32),
-                ("flags", C.c_int32), ("stream", C.c_void_p)]
+                ("flags", C.c_int32), ("k_max", C.c_int32),
+                ("p_star", C.c_double), ("stream", C.c_void_p)]
 
 
 _lib = None
@@ -92,6 +97,18 @@ def load():
         "nb_get_groups": ([p] + [p] * 6, i32),
         "nb_get_lists": ([p, p, p, p, p], i32),
         "nb_get_timing": ([p, p, p, i32], i32),
+        "nb_group_features": ([p, p, i32], i32),
+        "nb_group_stale": ([p, p, p, i32], i32),
+        "nb_refresh_lists": ([p, i64, p], i32),
+        "nb_get_group_state": ([p, p, p, p], i32),
+        "nb_mlp_set": ([p, p, i64], i32),
+        "nb_mlp_get": ([p, p, i64], i32),
+        "nb_mlp_forward": ([p, i64, p, p, i32], i32),
+        "nb_mlp_grad": ([p, i64, p, p, C.c_float, p, p, i32], i32),
+        "nb_mlp_adam": ([p, p, C.c_float, C.c_float, C.c_float, C.c_float,
+                         i32], i32),
+        "nb_mlp_train": ([p, i64, p, p, i32, i32, i64, C.c_float, C.c_float,
+                          p], i32),
         "nb_last_error": ([p], C.c_char_p),
         "nb_version": ([], C.c_char_p),
     }
@@ -120,12 +137,13 @@ class Context:
 
     def __init__(self, theta=0.5, eps=0.01, G=1.0, n_leaf=8, n_grp=64,
                  order=1, ext_mass=0.0, timing=False, graph=False,
-                 stream=None):
+                 refresh=False, k_max=8, p_star=0.5, stream=None):
         self._lib = load()
         flags = (NB_FLAG_TIMING if timing else 0) | \
-            (NB_FLAG_GRAPH if graph else 0)
+            (NB_FLAG_GRAPH if graph else 0) | \
+            (NB_FLAG_REFRESH if refresh else 0)
         self._cfg = nb_config(theta, eps, G, ext_mass, n_leaf, n_grp, order,
-                              flags, stream)
+                              flags, k_max, p_star, stream)
         h = C.c_void_p()
         rc = self._lib.nb_create(C.byref(self._cfg), C.byref(h))
         if rc != NB_OK:
@@ -160,7 +178,9 @@ class Context:
     def config(self):
         c = self._cfg
         return dict(theta=c.theta, eps=c.eps, G=c.G, ext_mass=c.ext_mass,
-                    n_leaf=c.n_leaf, n_grp=c.n_grp, order=c.order)
+                    n_leaf=c.n_leaf, n_grp=c.n_grp, order=c.order,
+                    k_max=c.k_max, p_star=c.p_star,
+                    refresh=bool(c.flags & NB_FLAG_REFRESH))
 
     def set_config(self, **kw):
         for k, v in kw.items():
@@ -170,6 +190,9 @@ class Context:
             elif k == "graph":
                 self._cfg.flags = (self._cfg.flags & ~NB_FLAG_GRAPH) | \
                     (NB_FLAG_GRAPH if v else 0)
+            elif k == "refresh":
+                self._cfg.flags = (self._cfg.flags & ~NB_FLAG_REFRESH) | \
+                    (NB_FLAG_REFRESH if v else 0)
             else:
                 setattr(self._cfg, k, v)
         self._chk(self._lib.nb_set_config(self._h, C.byref(self._cfg)))
@@ -236,10 +259,11 @@ class Context:
         return tuple(out)
 
     def get_info(self):
-        a = np.zeros(11, dtype=np.int64)
+        a = np.zeros(13, dtype=np.int64)
         self._chk(self._lib.nb_get_info(self._h, _ptr(a)))
         keys = ("n", "n_cell", "n_groups", "n_epj", "n_spj", "n_inter",
-                "force_evals", "total_inter", "k", "n_wi", "n_sys")
+                "force_evals", "total_inter", "k", "n_wi", "n_sys",
+                "last_refreshed", "total_refreshed")
         return {k: int(v) for k, v in zip(keys, a)}
 
     def get_root(self):
@@ -305,3 +329,111 @@ class Context:
         self._chk(self._lib.nb_get_timing(self._h, _ptr(ms), _ptr(calls),
                                           1 if reset else 0))
         return {p: (float(t), int(c)) for p, t, c in zip(PHASES, ms, calls)}
+
+    # ---- per-group list refresh and its predictor ----
+    def group_features(self, out=None):
+        """Predictor inputs [groups, 12] FP32; ``out`` may be a CUDA tensor
+        (filled on the device), else a numpy array is returned."""
+        if out is not None and _is_torch(out) and out.is_cuda:
+            self._chk(self._lib.nb_group_features(
+                self._h, C.c_void_p(out.data_ptr()), 1))
+            return out
+        ng = self.get_info()["n_groups"]
+        f = np.zeros((ng, MLP_NIN), np.float32)
+        self._chk(self._lib.nb_group_features(self._h, _ptr(f), 0))
+        return f
+
+    def group_stale(self, label_out=None):
+        """Stale flags (bool array); with a CUDA tensor ``label_out`` the
+        labels (0.0 / 1.0) are written there on the device instead."""
+        if label_out is not None and _is_torch(label_out) and label_out.is_cuda:
+            self._chk(self._lib.nb_group_stale(
+                self._h, None, C.c_void_p(label_out.data_ptr()), 1))
+            return label_out
+        ng = self.get_info()["n_groups"]
+        st = np.zeros(ng, np.uint8)
+        self._chk(self._lib.nb_group_stale(self._h, _ptr(st), None, 0))
+        return st.astype(bool)
+
+    def refresh_lists(self, sel):
+        sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
+        self._chk(self._lib.nb_refresh_lists(self._h, sel.size, _ptr(sel)))
+
+    def group_state(self):
+        ng = self.get_info()["n_groups"]
+        sa, so = np.zeros(ng), np.zeros(ng)
+        age = np.zeros(ng, np.int32)
+        self._chk(self._lib.nb_get_group_state(self._h, _ptr(sa), _ptr(so),
+                                               _ptr(age)))
+        return sa, so, age
+
+    def mlp_set(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._chk(self._lib.nb_mlp_set(self._h, _ptr(w), w.size))
+
+    def mlp_get(self):
+        w = np.zeros(MLP_NPARAM, np.float32)
+        self._chk(self._lib.nb_mlp_get(self._h, _ptr(w), w.size))
+        return w
+
+    def _in(self, a, cols=None):
+        """(pointer, rows, on_device) of an FP32 input array or tensor."""
+        if _is_torch(a) and a.is_cuda:
+            import torch
+            if a.dtype != torch.float32 or not a.is_contiguous():
+                raise ValueError("device inputs must be contiguous float32")
+            return C.c_void_p(a.data_ptr()), a.shape[0], 1, a
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        if cols is not None:
+            a = a.reshape(-1, cols)
+        return _ptr(a), a.shape[0], 0, a
+
+    def mlp_forward(self, x):
+        px, n, dev, keep = self._in(x, MLP_NIN)
+        if dev:
+            import torch
+            p = torch.empty(n, dtype=torch.float32, device=x.device)
+            self._chk(self._lib.nb_mlp_forward(self._h, n, px,
+                                               C.c_void_p(p.data_ptr()), 1))
+            return p
+        p = np.zeros(n, np.float32)
+        self._chk(self._lib.nb_mlp_forward(self._h, n, px, _ptr(p), 0))
+        return p
+
+    def mlp_grad(self, x, y, pos_weight=1.0):
+        px, n, dev, kx = self._in(x, MLP_NIN)
+        py, ny, dev2, ky = self._in(y)
+        if ny != n or dev != dev2:
+            raise ValueError("x and y disagree")
+        loss = C.c_float(0.0)
+        if dev:
+            import torch
+            g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=x.device)
+            self._chk(self._lib.nb_mlp_grad(self._h, n, px, py,
+                                            float(pos_weight), C.byref(loss),
+                                            C.c_void_p(g.data_ptr()), 1))
+            return float(loss.value), g
+        g = np.zeros(MLP_NPARAM, np.float32)
+        self._chk(self._lib.nb_mlp_grad(self._h, n, px, py, float(pos_weight),
+                                        C.byref(loss), _ptr(g), 0))
+        return float(loss.value), g
+
+    def mlp_adam(self, grad=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        if grad is None:
+            self._chk(self._lib.nb_mlp_adam(self._h, None, lr, beta1, beta2,
+                                            eps, 0))
+            return
+        pg, n, dev, keep = self._in(grad)
+        self._chk(self._lib.nb_mlp_adam(self._h, pg, lr, beta1, beta2, eps,
+                                        dev))
+
+    def mlp_train(self, x, y, epochs=1, batch=4096, lr=1e-3, pos_weight=1.0):
+        px, n, dev, kx = self._in(x, MLP_NIN)
+        py, ny, dev2, ky = self._in(y)
+        if ny != n or dev != dev2:
+            raise ValueError("x and y disagree")
+        loss = C.c_float(0.0)
+        self._chk(self._lib.nb_mlp_train(self._h, n, px, py, dev, int(epochs),
+                                         int(batch), float(lr),
+                                         float(pos_weight), C.byref(loss)))
+        return float(loss.value)

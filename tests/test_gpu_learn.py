@@ -1,0 +1,304 @@
+"""GPU parity of per-group list refresh and the rebuild predictor against the
+FP64 oracle, through the C ABI.
+
+Positions move by pure drifts (dt_kick = 0): x <- x + v dt rounded as
+written, which the library and the oracle both compute from the seeded
+initial state, so every input of the oracle comes from the generators.
+
+Bit-exact: construction lists with refresh mode on, stale flags, refreshed
+lists, ages.  Within tolerance: opening-test slacks (FP64, centres of mass
+summed in another order: 1e-9 of the cell side), predictor inputs (FP64
+then FP32: 2e-6), perceptron forward and gradient (FP32 vs FP64: 1e-4),
+Adam steps, forces on refreshed lists (FP32 kernel vs FP64 list sum)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+import paper_1907_02290_amd as nb
+
+pytestmark = pytest.mark.gpu
+
+THETA = 0.5
+EPS = 1 / 64
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def sheared(n, seed):
+    """Plummer sphere with a shear flow added to the velocities, so that
+    groups deform and some lists go stale within a few steps."""
+    d = workloads.plummer(n, workloads.seed_for(1, seed))
+    d = dict(d)
+    d["vx"] = d["vx"] + 0.8 * d["y"]
+    return d
+
+
+def ctx_for(d, **kw):
+    kw.setdefault("theta", THETA)
+    kw.setdefault("eps", EPS)
+    ctx = nb.Context(refresh=True, **kw)
+    ctx.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
+                      d["m"])
+    return ctx
+
+
+def drift(d, dt, k):
+    """Positions after k pure drifts, evaluated like the library does."""
+    x, y, z = d["x"].copy(), d["y"].copy(), d["z"].copy()
+    vx, vy, vz = d["vx"].copy(), d["vy"].copy(), d["vz"].copy()
+    zero = np.zeros_like(x)
+    for _ in range(k):
+        oracle.kick_drift((x, y, z), (vx, vy, vz), (zero, zero, zero), 0.0, dt)
+    return x, y, z
+
+
+def cell_side(t, ctx_groups, cells):
+    return 2.0 ** (t.k - cells["level"][ctx_groups["cell"]].astype(float))
+
+
+def compare_lists(ctx, t):
+    eo, e, so, s = ctx.get_lists()
+    oeo, oe, oso, os_ = t.lists()
+    np.testing.assert_array_equal(eo, oeo)
+    np.testing.assert_array_equal(so, oso)
+    np.testing.assert_array_equal(e, oe)
+    np.testing.assert_array_equal(s, os_)
+
+
+def compare_slacks(ctx, t, side):
+    sa, so, _ = ctx.group_state()
+    osa, oso = t.margins()
+    for got, want in ((sa, osa), (so, oso)):
+        inf = np.isinf(want)
+        np.testing.assert_array_equal(np.isinf(got), inf)
+        assert np.all(np.abs(got[~inf] - want[~inf]) <= 1e-9 * side[~inf])
+
+
+def test_pure_drift_is_bit_exact():
+    say("case pure drift")
+    d = sheared(3000, 1)
+    with ctx_for(d) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        for _ in range(3):
+            ctx.kick_drift(0.0, 1 / 64)
+        x, y, z, vx, vy, vz = ctx.get_state()
+    want = drift(d, 1 / 64, 3)
+    for a, b in zip((x, y, z), want):
+        np.testing.assert_array_equal(a, b)
+    for a, k in zip((vx, vy, vz), ("vx", "vy", "vz")):
+        np.testing.assert_array_equal(a, d[k])
+
+
+@pytest.mark.parametrize("kind,n", [("plummer", 4096), ("disk", 20000),
+                                    ("plummer", 3)])
+def test_refresh_mode_keeps_construction_lists(kind, n):
+    say("case construction lists refresh mode %s %d" % (kind, n))
+    if kind == "disk":
+        d = workloads.disk_halo(n // 2, n - n // 2, workloads.seed_for(3, 0))
+    else:
+        d = workloads.plummer(n, workloads.seed_for(1, 0))
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 64)
+    t.make_lists(THETA)
+    with ctx_for(d) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        compare_lists(ctx, t)
+        g, c = ctx.get_groups(), ctx.get_cells()
+        compare_slacks(ctx, t, cell_side(t, g, c))
+        _, _, age = ctx.group_state()
+        assert np.all(age == 0)
+
+
+@pytest.mark.parametrize("n_grp,steps", [(64, 2), (16, 3)])
+def test_stale_features_refresh_match_oracle(n_grp, steps):
+    say("case stale/features/refresh n_grp=%d steps=%d" % (n_grp, steps))
+    d = sheared(6000, 2)
+    dt = 1 / 32
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, n_grp)
+    t.make_lists(THETA)
+    with ctx_for(d, n_grp=n_grp, k_max=8) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        for _ in range(steps):
+            ctx.kick_drift(0.0, dt)
+            ctx.compute_forces(nb.NB_REUSE_LIST)
+        x, y, z = drift(d, dt, steps)
+        t.refresh(x, y, z, d["m"])
+        g, c = ctx.get_groups(), ctx.get_cells()
+        side = cell_side(t, g, c)
+        ng = t.n_groups
+        # stale flags
+        st = ctx.group_stale()
+        ost, lo, hi = t.stale(THETA)
+        say("  stale groups %d / %d" % (ost.sum(), ng))
+        assert ost.any() and not ost.all()
+        np.testing.assert_array_equal(st, ost)
+        # predictor inputs
+        _, _, age = ctx.group_state()
+        assert np.all(age == steps)
+        f = ctx.group_features()
+        of = t.features(8, np.full(ng, steps, np.int32))
+        np.testing.assert_allclose(f, of, rtol=2e-6, atol=2e-6)
+        # refresh every other stale group and a few fresh ones
+        sel = np.union1d(np.flatnonzero(ost)[::2], np.arange(0, ng, 17))
+        ctx.refresh_lists(sel)
+        t.refresh_lists(THETA, sel)
+        compare_lists(ctx, t)
+        compare_slacks(ctx, t, side)
+        np.testing.assert_array_equal(ctx.get_groups()["lo"], t.groups()["lo"])
+        _, _, age = ctx.group_state()
+        want_age = np.full(ng, steps)
+        want_age[sel] = 0
+        np.testing.assert_array_equal(age, want_age)
+        info = ctx.get_info()
+        eo, e, so, s = t.lists()
+        assert info["n_epj"] == e.size and info["n_spj"] == s.size
+        assert info["last_refreshed"] == sel.size
+        # one more step: flags again
+        ctx.kick_drift(0.0, dt)
+        ctx.compute_forces(nb.NB_REUSE_LIST)
+        x, y, z = drift(d, dt, steps + 1)
+        t.refresh(x, y, z, d["m"])
+        np.testing.assert_array_equal(ctx.group_stale(), t.stale(THETA)[0])
+        # forces on the merged lists against the FP64 sum over them
+        ax, ay, az, pot = ctx.get_forces()
+        rx, ry, rz, rp = t.force_lists(1, EPS, 1.0)
+        num = np.sqrt((ax - rx) ** 2 + (ay - ry) ** 2 + (az - rz) ** 2)
+        den = np.sqrt(rx ** 2 + ry ** 2 + rz ** 2)
+        err = num / den
+        say("  force rel err median %.2e p99 %.2e" % (np.median(err),
+                                                      np.percentile(err, 99)))
+        assert np.median(err) <= 1e-5 and np.percentile(err, 99) <= 1e-3
+
+
+def test_predicted_refresh_all_and_none():
+    say("case REUSE_REFRESH all / none")
+    d = sheared(5000, 3)
+    dt = 1 / 32
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 32)
+    t.make_lists(THETA)
+    ng = t.n_groups
+    # zero weights: p = 1/2 for every group; p* = 0 refreshes all of them
+    with ctx_for(d, n_grp=32, p_star=0.0, k_max=100) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        ctx.kick_drift(0.0, dt)
+        ctx.compute_forces(nb.NB_REUSE_REFRESH)
+        assert ctx.get_info()["last_refreshed"] == ng
+        x, y, z = drift(d, dt, 1)
+        t.refresh(x, y, z, d["m"])
+        t.refresh_lists(THETA, np.arange(ng))
+        compare_lists(ctx, t)
+        assert not ctx.group_stale().any()
+    # p* = 1 never fires; k_max = 2 refreshes everything at the second step
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 32)
+    t.make_lists(THETA)
+    with ctx_for(d, n_grp=32, p_star=1.0, k_max=2) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        ctx.kick_drift(0.0, dt)
+        ctx.compute_forces(nb.NB_REUSE_REFRESH)
+        assert ctx.get_info()["last_refreshed"] == 0
+        compare_lists(ctx, t)
+        ctx.kick_drift(0.0, dt)
+        ctx.compute_forces(nb.NB_REUSE_REFRESH)
+        assert ctx.get_info()["last_refreshed"] == ng
+        x, y, z = drift(d, dt, 2)
+        t.refresh(x, y, z, d["m"])
+        t.refresh_lists(THETA, np.arange(ng))
+        compare_lists(ctx, t)
+        _, _, age = ctx.group_state()
+        assert np.all(age == 0)
+
+
+def test_refresh_errors():
+    d = sheared(2000, 4)
+    with ctx_for(d) as ctx:
+        with pytest.raises(nb.NbError):
+            ctx.group_features()  # no lists yet
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        ng = ctx.get_info()["n_groups"]
+        with pytest.raises(nb.NbError):
+            ctx.refresh_lists([3, 2])
+        with pytest.raises(nb.NbError):
+            ctx.refresh_lists([ng])
+        ctx.kick_drift(0.0, 0.01)
+        with pytest.raises(nb.NbError):
+            ctx.group_stale()  # moments describe the old positions
+        ctx.compute_forces(nb.NB_REUSE_LIST)
+        ctx.refresh_lists([])
+        assert ctx.get_info()["last_refreshed"] == 0
+    with nb.Context(theta=THETA, eps=EPS) as ctx:
+        ctx.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
+                          d["m"])
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        with pytest.raises(nb.NbError):
+            ctx.compute_forces(nb.NB_REUSE_REFRESH)
+
+
+# ---- perceptron ---------------------------------------------------------------
+
+def _weights(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(nb.MLP_NPARAM) * scale).astype(np.float32)
+
+
+def _data(seed, n):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, 12)).astype(np.float32)
+    y = (rng.uniform(size=n) > 0.7).astype(np.float32)
+    return x, y
+
+
+@pytest.mark.parametrize("n", [1, 255, 3000])
+def test_mlp_forward_and_gradient_match_oracle(n):
+    say("case mlp n=%d" % n)
+    w = _weights(1)
+    x, y = _data(2, n)
+    with nb.Context() as ctx:
+        ctx.mlp_set(w)
+        np.testing.assert_array_equal(ctx.mlp_get(), w)
+        p = ctx.mlp_forward(x)
+        for pw in (1.0, 3.0):
+            loss, g = ctx.mlp_grad(x, y, pos_weight=pw)
+            oloss, og = oracle.mlp_loss_grad(w.astype(np.float64), x, y, pw)
+            assert abs(loss - oloss) <= 1e-4 * max(1.0, abs(oloss))
+            assert np.max(np.abs(g - og)) <= 1e-4 * np.max(np.abs(og))
+    op = oracle.mlp_forward(w.astype(np.float64), x)
+    assert np.max(np.abs(p - op)) <= 1e-4
+
+
+def test_mlp_adam_matches_oracle():
+    w = _weights(3)
+    rng = np.random.default_rng(4)
+    with nb.Context() as ctx:
+        ctx.mlp_set(w)
+        ow = w.astype(np.float64)
+        m, v = np.zeros_like(ow), np.zeros_like(ow)
+        for t in range(1, 4):
+            g = (rng.standard_normal(w.size) * 10.0 ** rng.uniform(-3, 0, w.size)
+                 ).astype(np.float32)
+            ctx.mlp_adam(g, lr=1e-2, eps=1e-8)
+            oracle.adam(ow, g.astype(np.float64), m, v, t, lr=1e-2, eps=1e-8)
+        got = ctx.mlp_get()
+    np.testing.assert_allclose(got, ow, rtol=0, atol=1e-6)
+
+
+def test_mlp_training_is_deterministic_and_learns():
+    say("case mlp training")
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((4000, 12)).astype(np.float32)
+    y = (x[:, 0] + 0.5 * x[:, 1] - x[:, 2] > 0).astype(np.float32)
+    w0 = _weights(6, 0.1)
+    with nb.Context() as a, nb.Context() as b:
+        a.mlp_set(w0)
+        b.mlp_set(w0)
+        loss0 = a.mlp_grad(x, y)[0]
+        la = a.mlp_train(x, y, epochs=3, batch=500, lr=1e-2)
+        for _ in range(3):
+            for b0 in range(0, 4000, 500):
+                b.mlp_grad(x[b0:b0 + 500], y[b0:b0 + 500])
+                b.mlp_adam(None, lr=1e-2, eps=1e-8)
+        np.testing.assert_array_equal(a.mlp_get(), b.mlp_get())
+        acc = np.mean((a.mlp_forward(x) > 0.5) == (y > 0.5))
+    say("  loss %.4f -> %.4f, accuracy %.3f" % (loss0, la, acc))
+    assert la < 0.3 * loss0 and acc > 0.97

@@ -207,19 +207,48 @@ def test_theta_zero_matches_direct_sum():
     check_forces(got, ref, what="theta0")
 
 
+def _drift(d, dt, k):
+    """Positions after k pure drifts (x <- x + v dt), computed by the oracle
+    from the seeded initial state."""
+    x, y, z = d["x"].copy(), d["y"].copy(), d["z"].copy()
+    v = [d["vx"].copy(), d["vy"].copy(), d["vz"].copy()]
+    zero = np.zeros_like(x)
+    for _ in range(k):
+        oracle.kick_drift((x, y, z), v, (zero, zero, zero), 0.0, dt)
+    return x, y, z
+
+
 def test_kick_drift_matches_oracle():
     say("case kick-drift")
     d = system("plummer", 5000, seed=8)
+    dtk, dtd = 0.01, 0.02
     with gpu_ctx(d, ext_mass=0.3) as ctx:
         ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
-        acc = ctx.get_forces()[:3]
-        s0 = [a.copy() for a in ctx.get_state()]
-        ctx.kick_drift(0.01, 0.02)
+        ctx.kick_drift(dtk, dtd)
         s1 = ctx.get_state()
-    pos, vel = s0[:3], s0[3:]
-    oracle.kick_drift(pos, vel, acc, 0.01, 0.02, ext_mass=0.3)
-    for a, b in zip(list(pos) + list(vel), s1):
-        np.testing.assert_allclose(b, a, rtol=1e-14, atol=1e-15)
+    # the oracle kicks with its own FP64 forces over the same lists
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 64)
+    t.make_lists(0.5)
+    acc = t.force_lists(1, 1 / 64, 1.0)[:3]
+    pos = [d["x"].copy(), d["y"].copy(), d["z"].copy()]
+    vel = [d["vx"].copy(), d["vy"].copy(), d["vz"].copy()]
+    oracle.kick_drift(pos, vel, acc, dtk, dtd, ext_mass=0.3)
+    # velocity increments agree to the force tolerance, positions follow
+    dv_g = np.stack([s1[3] - d["vx"], s1[4] - d["vy"], s1[5] - d["vz"]])
+    dv_o = np.stack([vel[0] - d["vx"], vel[1] - d["vy"], vel[2] - d["vz"]])
+    err = np.linalg.norm(dv_g - dv_o, axis=0) / np.linalg.norm(dv_o, axis=0)
+    assert np.median(err) <= FORCE_MEDIAN_TOL and err.max() <= FORCE_P99_TOL
+    for a, b in zip(pos, s1[:3]):
+        np.testing.assert_allclose(b, a, rtol=0,
+                                   atol=dtd * np.abs(dv_g - dv_o).max() + 1e-15)
+    # pure drift is bit-exact
+    with gpu_ctx(d) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        ctx.kick_drift(0.0, dtd)
+        ctx.kick_drift(0.0, dtd)
+        s2 = ctx.get_state()
+    for a, b in zip(_drift(d, dtd, 2), s2[:3]):
+        np.testing.assert_array_equal(b, a)
 
 
 @pytest.mark.parametrize("order", [1, 2])
@@ -233,9 +262,9 @@ def test_reuse_steps_match_oracle_refresh(order):
         t.make_lists(0.5)
         info0 = ctx.get_info()
         for step in range(3):
-            ctx.kick_drift(dt / 2 if step == 0 else dt, dt)
+            ctx.kick_drift(0.0, dt)
             ctx.compute_forces(nb.NB_REUSE_LIST)
-            x, y, z, vx, vy, vz = ctx.get_state()
+            x, y, z = _drift(d, dt, step + 1)
             t.refresh(x, y, z, d["m"])
             check_forces(ctx.get_forces(), t.force_lists(order, 1 / 64, 1.0),
                          what="reuse step %d" % step)
@@ -248,15 +277,18 @@ def test_second_construction_after_steps():
     say("case rebuild after steps")
     d = system("disk", 16000, seed=1)
     dt = 1 / 32
+    t0 = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 64)
     with gpu_ctx(d, eps=0.01) as ctx:
         ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
         for step in range(4):
-            ctx.kick_drift(dt, dt)
+            ctx.kick_drift(0.0, dt)
             ctx.compute_forces(nb.NB_REUSE_LIST)
-        ctx.kick_drift(dt, dt)
-        # the sort sees the particles in the internal order of the last build
-        x, y, z, _, _, _ = ctx.get_state(internal=True)
-        _, prev_orig = ctx.get_keys()
+        ctx.kick_drift(0.0, dt)
+        # the sort sees the particles in the internal order of the last
+        # build, which is the oracle's first sort order
+        _, prev_orig = t0.keys()
+        xs = _drift(d, dt, 5)
+        x, y, z = (a[prev_orig] for a in xs)
         ms = d["m"][prev_orig]
         ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
         t = oracle.Tree(x, y, z, ms, 8, 64)
