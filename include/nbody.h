@@ -237,8 +237,11 @@ int nb_get_timing(nb_ctx* ctx, double* ms, int64_t* calls, int reset);
  * geometric centre of a cell is moved by the displacement of its FP64
  * centre of mass since the construction step (zero at construction, so
  * construction lists are unchanged), so that a rigid motion stales no list.
- * A group's list is stale when a walk with the group's current tight box
- * gives another list.  Per group the library keeps the box, the cell shift
+ * A group's list is stale (at tolerance tau >= 0) when one of its
+ * superparticles fails the opening test at the relaxed angle theta (1 + tau)
+ * from the group's current tight box; particles are exact and cells that a
+ * fresh walk would accept higher up only cost work, so neither makes a list
+ * stale.  Per group the library keeps the box, the cell shift
  * and the opening-test slacks of the walk that made its list, and the
  * list's age (reuse steps since that walk).  The calls below describe the
  * state of the last force computation (NB_ERR_STATE after a drift, without
@@ -257,10 +260,13 @@ int nb_get_timing(nb_ctx* ctx, double* ms, int64_t* calls, int reset);
  * FP32.  feat may be NULL (kept on the device for the predictor). */
 int nb_group_features(nb_ctx* ctx, float* feat, int on_device);
 
-/* Staleness labels: stale[g] = 1 when the walk with the current box and
- * centres differs from the kept list (a "shadow" walk that changes
- * nothing); label[g] the same as 0.0 / 1.0.  Either may be NULL. */
-int nb_group_stale(nb_ctx* ctx, uint8_t* stale, float* label, int on_device);
+/* Staleness labels at tolerance tau: stale[g] = 1 when a superparticle of
+ * the kept list fails the opening test at angle theta (1 + tau) from the
+ * group's current box and the cell's current centre (a check that changes
+ * nothing); label[g] the same as 0.0 / 1.0.  Either may be NULL.
+ * Errors: NB_ERR_INPUT (tau < 0 or not finite, theta = 0). */
+int nb_group_stale(nb_ctx* ctx, double tau, uint8_t* stale, float* label,
+                   int on_device);
 
 /* Walk again the lists of the n_sel groups listed in sel (host array of
  * ascending group ids) with their current boxes and centres; other lists

@@ -77,7 +77,7 @@ def _load():
     lib.orc_kick_drift.argtypes = [i64, p, p, p, p, p, p, p, p, p, d, d, d, d]
     lib.orc_num_threads.argtypes = []
     lib.orc_group_margins.argtypes = [p, p, p]
-    lib.orc_group_stale.argtypes = [p, d, p, p, p]
+    lib.orc_group_stale.argtypes = [p, d, d, p, p, p]
     lib.orc_refresh_lists.argtypes = [p, d, i64, p, p]
     lib.orc_group_features.argtypes = [p, C.c_int, p, p]
     lib.orc_mlp_nparam.argtypes = []
@@ -243,14 +243,14 @@ class Tree:
                "margins")
         return sa, so
 
-    def stale(self, theta):
-        """Groups whose walk with their current box and the current cell
-        centres gives another list than the kept one; also the boxes."""
+    def stale(self, theta, tau=0.0):
+        """Groups with a kept superparticle that fails the opening test at
+        angle theta (1 + tau) from the current box; also the boxes."""
         st = np.zeros(self.n_groups, np.uint8)
         lo = np.zeros((self.n_groups, 3))
         hi = np.zeros((self.n_groups, 3))
-        _check(_load().orc_group_stale(self._h, float(theta), _ptr(st),
-                                       _ptr(lo), _ptr(hi)), "stale")
+        _check(_load().orc_group_stale(self._h, float(theta), float(tau),
+                                       _ptr(st), _ptr(lo), _ptr(hi)), "stale")
         return st.astype(bool), lo, hi
 
     def refresh_lists(self, theta, sel):

@@ -634,43 +634,45 @@ static int full_lists(const orc_tree* t) {
   return t->have_lists && t->n_sel == t->n_groups;
 }
 
-/* Staleness of a kept list (reuse steps): walk the tree with the group's
- * current tight box and the current cell centres and report whether that
- * list differs from the kept one (needs lists of every group).  Also
- * returns the current boxes. */
-int orc_group_stale(const orc_tree* t, double theta, uint8_t* stale,
-                    double* lo3, double* hi3) {
-  if (!t || !stale || !full_lists(t)) return -1;
+/* Staleness of a kept list (reuse steps): a group's list is stale when one
+ * of its superparticles no longer passes the opening test at the relaxed
+ * angle theta (1 + tau), measured from the group's current tight box to the
+ * cell's current centre (tau = 0: a fresh walk would open that cell).
+ * Particles (EPJ) are exact and cells that a fresh walk would accept
+ * higher up only cost work, so neither makes a list stale.  Needs lists of
+ * every group; also returns the current boxes. */
+int orc_group_stale(const orc_tree* t, double theta, double tau,
+                    uint8_t* stale, double* lo3, double* hi3) {
+  if (!t || !stale || !full_lists(t) || !(tau >= 0.0)) return -1;
+  const double th = theta * (1.0 + tau);
   double rcrit2[MAX_LEVEL + 1];
-  crit_radii(t, theta, rcrit2);
-  int bad = 0;
-#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+  crit_radii(t, th, rcrit2);
+#pragma omp parallel for schedule(dynamic, 16)
   for (int64_t g = 0; g < t->n_groups; ++g) {
     double lo[3], hi[3];
     group_box(t, g, lo, hi);
     if (lo3) memcpy(&lo3[3 * g], lo, sizeof lo);
     if (hi3) memcpy(&hi3[3 * g], hi, sizeof hi);
-    int64_t ne, ns;
-    walk_box(t, g, lo, hi, rcrit2, 0, NULL, NULL, &ne, &ns, NULL);
-    const int64_t oe = t->epj_off[g + 1] - t->epj_off[g];
-    const int64_t os = t->spj_off[g + 1] - t->spj_off[g];
-    int differs = ne != oe || ns != os;
-    if (!differs) {
-      uint32_t* ee = (uint32_t*)malloc((size_t)(ne + 1) * sizeof(uint32_t));
-      uint32_t* ss = (uint32_t*)malloc((size_t)(ns + 1) * sizeof(uint32_t));
-      if (!ee || !ss) {
-        bad = 1;
-      } else {
-        walk_box(t, g, lo, hi, rcrit2, 1, ee, ss, &ne, &ns, NULL);
-        differs = memcmp(ee, t->epj + t->epj_off[g], (size_t)ne * 4) != 0 ||
-                  memcmp(ss, t->spj + t->spj_off[g], (size_t)ns * 4) != 0;
+    int bad = 0;
+    for (int64_t j = t->spj_off[g]; j < t->spj_off[g + 1] && !bad; ++j) {
+      const uint32_t c = t->spj[j];
+      double tr[3], d[3];
+      cell_shift(t, c, tr);
+      for (int a = 0; a < 3; ++a) {
+        const double cc = t->ctr[3 * c + a] + tr[a];
+        double v = 0.0;
+        const double below = lo[a] - cc;
+        const double above = cc - hi[a];
+        if (below > v) v = below;
+        if (above > v) v = above;
+        d[a] = v;
       }
-      free(ee);
-      free(ss);
+      const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+      bad = !(d2 > rcrit2[t->level[c]]);
     }
-    stale[g] = (uint8_t)differs;
+    stale[g] = (uint8_t)bad;
   }
-  return bad ? -1 : 0;
+  return 0;
 }
 
 /* Per-group list refresh: the listed groups (ascending ids) get their box

@@ -71,10 +71,11 @@ int orc_get_lists(const orc_tree* t, int64_t* epj_off, uint32_t* epj,
  * +inf when there is no such cell. */
 int orc_group_margins(const orc_tree* t, double* sa, double* so);
 
-/* stale[g] = 1 when a walk with the group's current tight box differs from
- * its kept list.  lo3/hi3 (current boxes) may be NULL. */
-int orc_group_stale(const orc_tree* t, double theta, uint8_t* stale,
-                    double* lo3, double* hi3);
+/* stale[g] = 1 when a superparticle of the group's kept list fails the
+ * opening test at angle theta (1 + tau), tau >= 0, measured from the
+ * group's current tight box.  lo3/hi3 (current boxes) may be NULL. */
+int orc_group_stale(const orc_tree* t, double theta, double tau,
+                    uint8_t* stale, double* lo3, double* hi3);
 
 /* Walk the n_sel listed groups (ascending ids) again with their current
  * boxes, keep every other list.  sizes = {n_groups, n_epj, n_spj}. */

@@ -236,7 +236,6 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                     const double4* lo, const double4* hi,
                     const uint64_t* epj_off, const uint64_t* spj_off,
                     uint32_t* epj, uint32_t* spj);
-int launch_walk_stale(nb_ctx* c, uint8_t* stale);
 int launch_list_stats(nb_ctx* c);
 int launch_interactions(nb_ctx* c, const uint32_t* ne, const uint32_t* ns);
 // nb_learn.hip
@@ -246,7 +245,7 @@ int launch_com(nb_ctx* c);
 int learn_after_groups(nb_ctx* c);
 int launch_age_inc(nb_ctx* c);
 int launch_features(nb_ctx* c);
-int launch_stale(nb_ctx* c);
+int launch_stale(nb_ctx* c, double tau);
 int mlp_ensure(nb_ctx* c);
 int mlp_forward(nb_ctx* c, int64_t n, const float* x, float* p);
 int mlp_grad(nb_ctx* c, int64_t n, const float* x, const float* y, float pw);

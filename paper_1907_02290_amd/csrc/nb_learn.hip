@@ -10,7 +10,9 @@
 // changes no list.  Right after construction the shift is exactly zero and
 // the walk is the plain one.  Per group it keeps the box, the cell shift and
 // the opening-test slacks of the walk that made its list, and the list's
-// age in reuse steps.
+// age in reuse steps.  A kept list is stale at tolerance tau when one of its
+// superparticles fails the opening test at angle theta (1 + tau): that is
+// what the predictor learns to foresee without checking the list.
 //
 // Kernels: FP64 centres of mass (leaves, then levels bottom-up), shifted
 // centres, predictor inputs, selection, the merge of refreshed and kept
@@ -173,6 +175,51 @@ k_features(int64_t ng, const uint32_t* __restrict__ g_cell,
   f[9] = (float)log1p(grow / s);
   f[10] = (float)(log2((double)g_count[g]) / 6.0);
   f[11] = (float)(log2(1.0 + nl) / 16.0);
+}
+
+// ---- staleness labels -------------------------------------------------------
+// A kept list is stale when one of its superparticles fails the opening
+// test at the relaxed angle theta (1 + tau) from the group's current box and
+// the cell's current centre.  (side / theta')^2 = 2^(2 (k - level)) rr with
+// rr = (1 / theta')^2 rounded as (side / theta')^2 would be (power-of-two
+// scaling is exact).
+__global__ void __launch_bounds__(256)
+k_check_lists(int64_t ng, const uint32_t* __restrict__ g_begin,
+              const double4* __restrict__ clo,
+              const double4* __restrict__ chi,
+              const CellRec* __restrict__ rec,
+              const double4* __restrict__ ctr, const Root* __restrict__ root,
+              const uint32_t* __restrict__ seg,
+              const uint64_t* __restrict__ spj_off,
+              const uint32_t* __restrict__ spj, double rr,
+              uint8_t* __restrict__ stale) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  const double4 lo = clo[g], hi = chi[g];
+  const int k = root[seg[g_begin[g]]].k;
+  bool bad = false;
+  for (uint64_t j = spj_off[g], e = spj_off[g + 1]; j < e && !bad; ++j) {
+    const uint32_t c = spj[j];
+    const double4 cc = ctr[c];
+    const int level = (int)(rec[c].meta.w & 255u);
+    double dx = 0.0, dy = 0.0, dz = 0.0, t;
+    t = __dsub_rn(lo.x, cc.x);
+    if (t > dx) dx = t;
+    t = __dsub_rn(cc.x, hi.x);
+    if (t > dx) dx = t;
+    t = __dsub_rn(lo.y, cc.y);
+    if (t > dy) dy = t;
+    t = __dsub_rn(cc.y, hi.y);
+    if (t > dy) dy = t;
+    t = __dsub_rn(lo.z, cc.z);
+    if (t > dz) dz = t;
+    t = __dsub_rn(cc.z, hi.z);
+    if (t > dz) dz = t;
+    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                __dmul_rn(dz, dz));
+    bad = !(d2 > ldexp(rr, 2 * (k - level)));
+  }
+  stale[g] = (uint8_t)bad;
 }
 
 // ---- selection and list merge ----------------------------------------------
@@ -515,10 +562,20 @@ int launch_features(nb_ctx* c) {
   return hip_check(c, hipGetLastError(), "feature launch");
 }
 
-int launch_stale(nb_ctx* c) {
+int launch_stale(nb_ctx* c, double tau) {
   int rc = launch_group_box(c, c->g_clo.p, c->g_chi.p);
-  if (!rc) rc = launch_walk_stale(c, c->stale.p);
-  return rc;
+  if (rc) return rc;
+  const double th = c->cfg.theta * (1.0 + tau);
+  const double r1 = 1.0 / th;
+  const double rr = r1 * r1;
+  hipLaunchKernelGGL(k_check_lists, dim3(grid_for(c->n_groups, 256)),
+                     dim3(256), 0, c->stream, c->n_groups,
+                     (const uint32_t*)c->g_begin.p, (const double4*)c->g_clo.p,
+                     (const double4*)c->g_chi.p, (const CellRec*)c->c_rec.p,
+                     (const double4*)c->c_ctr.p, (const Root*)c->root.p,
+                     (const uint32_t*)c->seg.p, (const uint64_t*)c->spj_off.p,
+                     (const uint32_t*)c->spj.p, rr, c->stale.p);
+  return hip_check(c, hipGetLastError(), "list check launch");
 }
 
 int mlp_forward(nb_ctx* c, int64_t n, const float* x, float* p) {
@@ -773,10 +830,15 @@ int nb_group_features(nb_ctx* c, float* feat, int on_device) {
   return rc;
 }
 
-int nb_group_stale(nb_ctx* c, uint8_t* stale, float* label, int on_device) {
+int nb_group_stale(nb_ctx* c, double tau, uint8_t* stale, float* label,
+                   int on_device) {
   if (!c) return NB_ERR_INPUT;
+  if (!(tau >= 0.0) || !std::isfinite(tau))
+    return set_err(c, NB_ERR_INPUT, "tau must be finite and >= 0");
+  if (c->cfg.theta <= 0.0)
+    return set_err(c, NB_ERR_INPUT, "staleness needs theta > 0");
   int rc = need_refresh_state(c);
-  if (!rc) rc = launch_stale(c);
+  if (!rc) rc = launch_stale(c, tau);
   if (!rc && stale)
     rc = copy_out(c, stale, c->stale.p, (size_t)c->n_groups, on_device);
   if (!rc && label) {

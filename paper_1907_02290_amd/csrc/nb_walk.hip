@@ -162,88 +162,6 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   }
 }
 
-// Staleness of kept lists: walk each group with its current box and the
-// current centres (as the LEARN walk does) and compare on the fly with the
-// kept lists; a mismatch ends the walk.  An SPJ token must equal the next
-// kept SPJ id; an opened leaf must start the next stretch of kept EPJ ids
-// (leaves are disjoint particle ranges, so matching the first id of every
-// leaf and the total length matches every id).
-__global__ void __launch_bounds__(kWalkThreads)
-k_walk_stale(int64_t n_groups, int64_t nblk,
-             const uint32_t* __restrict__ g_begin,
-             const uint32_t* __restrict__ g_count,
-             const double4* __restrict__ g_lo,
-             const double4* __restrict__ g_hi,
-             const CellRec* __restrict__ rec,
-             const double4* __restrict__ ctr,
-             const uint32_t* __restrict__ seg,
-             const uint32_t* __restrict__ croot,
-             const uint64_t* __restrict__ epj_off,
-             const uint32_t* __restrict__ epj,
-             const uint64_t* __restrict__ spj_off,
-             const uint32_t* __restrict__ spj, uint8_t* __restrict__ stale) {
-  const int64_t blk = xcd_block(nblk);
-  if (blk >= nblk) return;
-  const int64_t g = blk * kWalkThreads + threadIdx.x;
-  if (g >= n_groups) return;
-  const uint32_t gb = g_begin[g];
-  const uint32_t ge = gb + g_count[g];
-  const double4 lo = g_lo[g], hi = g_hi[g];
-  const uint32_t* ke = epj + epj_off[g];
-  const uint64_t kne = epj_off[g + 1] - epj_off[g];
-  const uint32_t* ks = spj + spj_off[g];
-  const uint64_t kns = spj_off[g + 1] - spj_off[g];
-  uint64_t ie = 0, is = 0;
-  bool diff = false;
-  const uint32_t sys = seg[gb];
-  uint32_t c = croot[sys];
-  const uint32_t nc = croot[sys + 1];
-  while (c < nc) {
-    const uint4 m = rec[c].meta;
-    const double4 cc = ctr[c];
-    bool open;
-    if (m.x <= gb && m.y >= ge) {
-      open = true;
-    } else {
-      double dx = 0.0, dy = 0.0, dz = 0.0, t;
-      t = __dsub_rn(lo.x, cc.x);
-      if (t > dx) dx = t;
-      t = __dsub_rn(cc.x, hi.x);
-      if (t > dx) dx = t;
-      t = __dsub_rn(lo.y, cc.y);
-      if (t > dy) dy = t;
-      t = __dsub_rn(cc.y, hi.y);
-      if (t > dy) dy = t;
-      t = __dsub_rn(lo.z, cc.z);
-      if (t > dz) dz = t;
-      t = __dsub_rn(cc.z, hi.z);
-      if (t > dz) dz = t;
-      const double d2 =
-          __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
-                    __dmul_rn(dz, dz));
-      open = !(d2 > cc.w);
-    }
-    const bool leaf = (m.w >> 8) & 1u;
-    const uint32_t next = (!open || leaf) ? m.z : c + 1;
-    if (next <= c) break;
-    if (!open) {
-      if (is >= kns || ks[is] != c) {
-        diff = true;
-        break;
-      }
-      ++is;
-    } else if (leaf) {
-      if (ie >= kne || ke[ie] != m.x) {
-        diff = true;
-        break;
-      }
-      ie += m.y - m.x;
-    }
-    c = next;
-  }
-  stale[g] = (uint8_t)(diff || ie != kne || is != kns);
-}
-
 // One wave per group: the token stream -> SPJ ids and EPJ particle ids.
 // Tokens are read in chunks of 64; accepted cells are compacted with a
 // ballot, opened leaves are expanded using a wave scan of their sizes, so
@@ -365,23 +283,6 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                      (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
                      epj_off, spj_off, epj, spj);
   return hip_check(c, hipGetLastError(), "expand launch");
-}
-
-int launch_walk_stale(nb_ctx* c, uint8_t* stale) {
-  if (c->n_groups <= 0) return NB_OK;
-  const int64_t nblk = grid_for(c->n_groups, kWalkThreads);
-  const int64_t launch = (nblk + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_walk_stale, dim3((unsigned)launch), dim3(kWalkThreads),
-                     0, c->stream, c->n_groups, nblk,
-                     (const uint32_t*)c->g_begin.p,
-                     (const uint32_t*)c->g_count.p,
-                     (const double4*)c->g_clo.p, (const double4*)c->g_chi.p,
-                     (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
-                     (const uint32_t*)c->seg.p, (const uint32_t*)c->croot.p,
-                     (const uint64_t*)c->epj_off.p, (const uint32_t*)c->epj.p,
-                     (const uint64_t*)c->spj_off.p, (const uint32_t*)c->spj.p,
-                     stale);
-  return hip_check(c, hipGetLastError(), "stale walk launch");
 }
 
 // After the count pass: CSR offsets and the interaction count (red[0]).

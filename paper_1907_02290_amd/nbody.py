@@ -98,7 +98,7 @@ def load():
         "nb_get_lists": ([p, p, p, p, p], i32),
         "nb_get_timing": ([p, p, p, i32], i32),
         "nb_group_features": ([p, p, i32], i32),
-        "nb_group_stale": ([p, p, p, i32], i32),
+        "nb_group_stale": ([p, d, p, p, i32], i32),
         "nb_refresh_lists": ([p, i64, p], i32),
         "nb_get_group_state": ([p, p, p, p], i32),
         "nb_mlp_set": ([p, p, i64], i32),
@@ -343,16 +343,18 @@ class Context:
         self._chk(self._lib.nb_group_features(self._h, _ptr(f), 0))
         return f
 
-    def group_stale(self, label_out=None):
-        """Stale flags (bool array); with a CUDA tensor ``label_out`` the
-        labels (0.0 / 1.0) are written there on the device instead."""
+    def group_stale(self, tau=0.0, label_out=None):
+        """Stale flags at tolerance ``tau`` (bool array); with a CUDA tensor
+        ``label_out`` the labels (0.0 / 1.0) are written there instead."""
         if label_out is not None and _is_torch(label_out) and label_out.is_cuda:
             self._chk(self._lib.nb_group_stale(
-                self._h, None, C.c_void_p(label_out.data_ptr()), 1))
+                self._h, float(tau), None, C.c_void_p(label_out.data_ptr()),
+                1))
             return label_out
         ng = self.get_info()["n_groups"]
         st = np.zeros(ng, np.uint8)
-        self._chk(self._lib.nb_group_stale(self._h, _ptr(st), None, 0))
+        self._chk(self._lib.nb_group_stale(self._h, float(tau), _ptr(st),
+                                           None, 0))
         return st.astype(bool)
 
     def refresh_lists(self, sel):

@@ -5,8 +5,9 @@ Positions move by pure drifts (dt_kick = 0): x <- x + v dt rounded as
 written, which the library and the oracle both compute from the seeded
 initial state, so every input of the oracle comes from the generators.
 
-Bit-exact: construction lists with refresh mode on, stale flags, refreshed
-lists, ages.  Within tolerance: opening-test slacks (FP64, centres of mass
+Bit-exact: construction lists with refresh mode on, stale flags (kept
+superparticles checked against the relaxed opening test), refreshed lists,
+ages.  Within tolerance: opening-test slacks (FP64, centres of mass
 summed in another order: 1e-9 of the cell side), predictor inputs (FP64
 then FP32: 2e-6), perceptron forward and gradient (FP32 vs FP64: 1e-4),
 Adam steps, forces on refreshed lists (FP32 kernel vs FP64 list sum)."""
@@ -115,7 +116,7 @@ def test_refresh_mode_keeps_construction_lists(kind, n):
 def test_stale_features_refresh_match_oracle(n_grp, steps):
     say("case stale/features/refresh n_grp=%d steps=%d" % (n_grp, steps))
     d = sheared(6000, 2)
-    dt = 1 / 32
+    dt = 1 / 64
     t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, n_grp)
     t.make_lists(THETA)
     with ctx_for(d, n_grp=n_grp, k_max=8) as ctx:
@@ -129,11 +130,13 @@ def test_stale_features_refresh_match_oracle(n_grp, steps):
         side = cell_side(t, g, c)
         ng = t.n_groups
         # stale flags
-        st = ctx.group_stale()
+        for tau in (0.0, 0.05, 0.1):
+            st = ctx.group_stale(tau)
+            ost, lo, hi = t.stale(THETA, tau)
+            say("  tau %.2f: stale groups %d / %d" % (tau, ost.sum(), ng))
+            np.testing.assert_array_equal(st, ost)
         ost, lo, hi = t.stale(THETA)
-        say("  stale groups %d / %d" % (ost.sum(), ng))
         assert ost.any() and not ost.all()
-        np.testing.assert_array_equal(st, ost)
         # predictor inputs
         _, _, age = ctx.group_state()
         assert np.all(age == steps)
@@ -161,6 +164,8 @@ def test_stale_features_refresh_match_oracle(n_grp, steps):
         x, y, z = drift(d, dt, steps + 1)
         t.refresh(x, y, z, d["m"])
         np.testing.assert_array_equal(ctx.group_stale(), t.stale(THETA)[0])
+        np.testing.assert_array_equal(ctx.group_stale(0.1),
+                                      t.stale(THETA, 0.1)[0])
         # forces on the merged lists against the FP64 sum over them
         ax, ay, az, pot = ctx.get_forces()
         rx, ry, rz, rp = t.force_lists(1, EPS, 1.0)
@@ -221,6 +226,8 @@ def test_refresh_errors():
             ctx.refresh_lists([3, 2])
         with pytest.raises(nb.NbError):
             ctx.refresh_lists([ng])
+        with pytest.raises(nb.NbError):
+            ctx.group_stale(-0.1)
         ctx.kick_drift(0.0, 0.01)
         with pytest.raises(nb.NbError):
             ctx.group_stale()  # moments describe the old positions

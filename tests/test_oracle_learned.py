@@ -181,6 +181,8 @@ def test_unmoved_particles_are_not_stale(orc):
     t.refresh(x, y, z, m)
     st, lo, _ = t.stale(0.6)
     assert not st.any()
+    # tau = 0 fires exactly where a kept superparticle fails the test: none
+    # right after construction
     np.testing.assert_array_equal(lo, t.groups()["lo"])
     f = t.features(8, np.full(t.n_groups, 3))
     np.testing.assert_array_equal(f[:, 0], 3.0 / 8.0)
@@ -211,6 +213,22 @@ def test_rigid_motion_changes_no_list(orc):
                                rtol=1e-12)
 
 
+def _violations(t, kids_unused, shift, lo, hi, theta, tau, eo_so):
+    """Direct check of every kept superparticle (vectorised restatement)."""
+    c = t.cells()
+    _, so, s = eo_so
+    side = 2.0 ** (t.k - c["level"].astype(float))
+    r2 = (side / (theta * (1.0 + tau))) ** 2
+    ctr = c["ctr"] + shift
+    out = np.zeros(t.n_groups, bool)
+    for g in range(t.n_groups):
+        cs = s[so[g]:so[g + 1]].astype(np.int64)
+        d = np.maximum(0.0, np.maximum(lo[g] - ctr[cs], ctr[cs] - hi[g]))
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        out[g] = bool(np.any(~(d2 > r2[cs])))
+    return out
+
+
 def test_stale_and_refresh_against_brute_force(orc):
     theta = 0.6
     rng, (x, y, z, m), t = _setup(orc, theta=theta)
@@ -218,15 +236,23 @@ def test_stale_and_refresh_against_brute_force(orc):
     c, g = t.cells(), t.groups()
     kids = _children(c)
     eo0, e0, so0, s0 = t.lists()
-    # a shear flow plus noise: lists change for some groups, not all
-    xn = x + 0.04 * y + 0.01 * rng.standard_normal(x.size)
-    yn, zn = y.copy(), z + 0.01 * rng.standard_normal(x.size)
+    # a shear flow plus noise: some lists go stale, not all
+    xn = x + 0.15 * y + 0.03 * rng.standard_normal(x.size)
+    yn, zn = y.copy(), z + 0.03 * rng.standard_normal(x.size)
     t.refresh(xn, yn, zn, m)
     _, com, _ = t.moments()
     shift = com - com0
     key, perm = t.keys()
     st, lo, hi = t.stale(theta)
+    st1, _, _ = t.stale(theta, 0.1)
     assert st.any() and not st.all()
+    assert st1.any() and not np.array_equal(st1, st)
+    assert not np.any(st1 & ~st)               # monotone in tau
+    assert not t.stale(theta, 1e6)[0].any()
+    np.testing.assert_array_equal(
+        st, _violations(t, kids, shift, lo, hi, theta, 0.0, (eo0, so0, s0)))
+    np.testing.assert_array_equal(
+        st1, _violations(t, kids, shift, lo, hi, theta, 0.1, (eo0, so0, s0)))
     walked = {}
     for gi in range(t.n_groups):
         b, cnt = int(g["begin"][gi]), int(g["count"][gi])
@@ -239,9 +265,11 @@ def test_stale_and_refresh_against_brute_force(orc):
         walked[gi] = (pe, ps, a, o)
         same = (pe == e0[eo0[gi]:eo0[gi + 1]].tolist() and
                 ps == s0[so0[gi]:so0[gi + 1]].tolist())
-        assert st[gi] == (not same), gi
-    # refresh every other stale group
-    sel = np.flatnonzero(st)[::2]
+        # a violated superparticle means a fresh walk opens it
+        if st[gi]:
+            assert not same, gi
+    # refresh every other stale group and a few fresh ones
+    sel = np.union1d(np.flatnonzero(st)[::2], np.arange(0, t.n_groups, 7))
     t.refresh_lists(theta, sel)
     eo, e, so_, s = t.lists()
     sa, so = t.margins()
