@@ -46,14 +46,16 @@ typedef enum nb_status {
 
 /* Reuse modes of the paper's top-level force call (section 5): make lists
  * and discard them, make lists and keep them, or reuse the kept lists.
- * NB_REUSE_REFRESH (an extension, needs NB_FLAG_REFRESH) reuses the kept
- * lists but first walks again the lists of the groups that the predictor
- * flags (see nb_compute_forces). */
+ * NB_REUSE_REFRESH and NB_REUSE_CHECK (extensions, need NB_FLAG_REFRESH)
+ * reuse the kept lists but first walk again the lists of the groups that
+ * the predictor flags, or that the exact staleness check flags (see
+ * nb_compute_forces). */
 typedef enum nb_mode {
   NB_MAKE_LIST = 0,
   NB_MAKE_LIST_FOR_REUSE = 1,
   NB_REUSE_LIST = 2,
-  NB_REUSE_REFRESH = 3
+  NB_REUSE_REFRESH = 3,
+  NB_REUSE_CHECK = 4
 } nb_mode;
 
 typedef struct nb_config {
@@ -75,6 +77,8 @@ typedef struct nb_config {
                       walked again; 1..65535 */
   double p_star;   /* refresh mode: a list whose predicted staleness
                       exceeds p_star is walked again; [0, 1] */
+  double tau;      /* refresh mode: staleness tolerance of NB_REUSE_CHECK
+                      (see nb_group_stale); >= 0 */
   void* stream;    /* hipStream_t to launch on; NULL = the library's own */
 } nb_config;
 
@@ -156,10 +160,12 @@ int nb_make_lists(nb_ctx* ctx, nb_mode mode);
  * computes the predictor inputs of every group (nb_group_features), runs
  * the perceptron and walks again (nb_refresh_lists) every group with
  * p > cfg.p_star or age >= cfg.k_max; this synchronises with the host once,
- * twice when a group is refreshed.
+ * twice when a group is refreshed.  NB_REUSE_CHECK does the same with the
+ * exact staleness check at tolerance cfg.tau (nb_group_stale) in place of
+ * the predictor.
  * Errors: NB_ERR_STATE (REUSE_LIST without reusable lists or after
- * nb_set_particles; REUSE_REFRESH without NB_FLAG_REFRESH), plus those of
- * the stages. */
+ * nb_set_particles; REUSE_REFRESH or REUSE_CHECK without NB_FLAG_REFRESH),
+ * plus those of the stages. */
 int nb_compute_forces(nb_ctx* ctx, nb_mode mode);
 
 /* Kick-drift of the KDK leapfrog in FP64: v += (a + a_ext) * dt_kick, then

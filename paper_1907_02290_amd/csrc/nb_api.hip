@@ -107,6 +107,8 @@ static int check_cfg(nb_ctx* c, const nb_config* cfg) {
       return set_err(c, NB_ERR_INPUT, "k_max must be in 1..65535");
     if (!(cfg->p_star >= 0.0 && cfg->p_star <= 1.0))
       return set_err(c, NB_ERR_INPUT, "p_star must be in [0, 1]");
+    if (!(cfg->tau >= 0.0) || !std::isfinite(cfg->tau))
+      return set_err(c, NB_ERR_INPUT, "tau must be finite and >= 0");
   }
   return NB_OK;
 }
@@ -221,7 +223,8 @@ static int build_tree(nb_ctx* c) {
 }
 
 static int make_lists(nb_ctx* c, nb_mode mode) {
-  if (mode == NB_REUSE_LIST || mode == NB_REUSE_REFRESH)
+  if (mode == NB_REUSE_LIST || mode == NB_REUSE_REFRESH ||
+      mode == NB_REUSE_CHECK)
     return c->lists_reusable ? NB_OK
                              : set_err(c, NB_ERR_STATE, "no reusable lists");
   if (mode != NB_MAKE_LIST && mode != NB_MAKE_LIST_FOR_REUSE)
@@ -465,12 +468,16 @@ int nb_compute_forces(nb_ctx* c, nb_mode mode) {
   if (!c) return NB_ERR_INPUT;
   int rc;
   c->last_refreshed = 0;
-  if (mode == NB_REUSE_LIST || mode == NB_REUSE_REFRESH) {
+  if (mode == NB_REUSE_LIST || mode == NB_REUSE_REFRESH ||
+      mode == NB_REUSE_CHECK) {
     if (!c->have_particles || !c->tree_valid || !c->lists_reusable)
       return set_err(c, NB_ERR_STATE,
                      "REUSE_LIST needs lists made with MAKE_LIST_FOR_REUSE");
-    if (mode == NB_REUSE_REFRESH && !c->learn)
-      return set_err(c, NB_ERR_STATE, "REUSE_REFRESH needs NB_FLAG_REFRESH");
+    if (mode != NB_REUSE_LIST && !c->learn)
+      return set_err(c, NB_ERR_STATE,
+                     "REUSE_REFRESH and REUSE_CHECK need NB_FLAG_REFRESH");
+    if (mode == NB_REUSE_CHECK && !(c->cfg.theta > 0.0))
+      return set_err(c, NB_ERR_INPUT, "REUSE_CHECK needs theta > 0");
     {
       Timed t(c, NB_PH_MOMENTS);
       if ((rc = launch_moments(c))) return rc;
@@ -482,6 +489,9 @@ int nb_compute_forces(nb_ctx* c, nb_mode mode) {
     if (mode == NB_REUSE_REFRESH) {
       Timed t(c, NB_PH_REFRESH);
       if ((rc = refresh_predicted(c))) return rc;
+    } else if (mode == NB_REUSE_CHECK) {
+      Timed t(c, NB_PH_REFRESH);
+      if ((rc = refresh_checked(c))) return rc;
     }
   } else if (mode == NB_MAKE_LIST || mode == NB_MAKE_LIST_FOR_REUSE) {
     if ((rc = build_tree(c))) return rc;

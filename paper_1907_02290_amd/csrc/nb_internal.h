@@ -254,6 +254,7 @@ int mlp_adam(nb_ctx* c, const float* g, float lr, float b1, float b2,
 int refresh_selected(nb_ctx* c, int64_t n_sel);
 int refresh_host_sel(nb_ctx* c, int64_t n_sel, const int64_t* sel);
 int refresh_predicted(nb_ctx* c);
+int refresh_checked(nb_ctx* c);
 int labels_to_float(nb_ctx* c, float* out);
 // nb_force.hip
 int launch_force(nb_ctx* c);

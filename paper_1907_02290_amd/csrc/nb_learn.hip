@@ -232,6 +232,14 @@ k_select(int64_t ng, const float* __restrict__ prob,
 }
 
 __global__ void __launch_bounds__(256)
+k_select_stale(int64_t ng, const uint8_t* __restrict__ stale,
+               const uint32_t* __restrict__ age, uint32_t kmax,
+               uint32_t* __restrict__ pick) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < ng) pick[g] = (stale[g] || age[g] >= kmax) ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256)
 k_mark(int64_t n_sel, const uint32_t* __restrict__ sel,
        uint32_t* __restrict__ pick) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -761,6 +769,28 @@ int refresh_predicted(nb_ctx* c) {
   if (rc) return rc;
   const int64_t n_sel = static_cast<const uint32_t*>(c->h_small)[0];
   return refresh_selected(c, n_sel);
+}
+
+// Refresh driven by the exact check at tolerance cfg.tau (or the age).
+int refresh_checked(nb_ctx* c) {
+  const int64_t G = c->n_groups;
+  int rc = launch_stale(c, c->cfg.tau);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_select_stale, dim3(grid_for(G, 256)), dim3(256), 0,
+                     c->stream, G, (const uint8_t*)c->stale.p,
+                     (const uint32_t*)c->g_age.p, (uint32_t)c->cfg.k_max,
+                     c->pick.p);
+  rc = hip_check(c, hipGetLastError(), "select launch");
+  if (!rc) rc = scan_u32(c, c->pick.p, c->pickpos.p, G);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(G, 256)), dim3(256), 0,
+                     c->stream, G, (const uint32_t*)c->pick.p,
+                     (const uint32_t*)c->pickpos.p, c->sel.p);
+  rc = hip_check(c, hipGetLastError(), "compact launch");
+  if (!rc) rc = stage_d2h(c, 0, c->pickpos.p + G, 4);
+  if (!rc) rc = sync_stream(c);
+  if (rc) return rc;
+  return refresh_selected(c, static_cast<const uint32_t*>(c->h_small)[0]);
 }
 
 int labels_to_float(nb_ctx* c, float* out) {

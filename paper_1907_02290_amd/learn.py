@@ -1,0 +1,261 @@
+"""Learned per-group list refresh: label collection, training of the
+staleness predictor on the GPU, threshold choice, and runs of the reuse
+policies that the predictor is compared with.
+
+Every computation goes through the library's C ABI (``nbody.Context``); this
+module only sequences the calls and keeps the training rows in device
+tensors.
+
+Policies (``run_policy``):
+  * ``fixed``   -- the paper's reuse (section 4.2): a construction step every
+                   ``k`` steps, the kept lists in between;
+  * ``learned`` -- a construction step every ``k`` steps, and in between each
+                   group's list is walked again when the predictor's p exceeds
+                   ``p_star`` or the list is ``k_max`` steps old
+                   (NB_REUSE_REFRESH);
+  * ``checked`` -- the same with the exact staleness check instead of the
+                   predictor (the check reads every kept superparticle each
+                   step; a reference for what the predictor approximates).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import nbody as nb
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def make_context(d, theta, eps, n_leaf=8, n_grp=64, order=1, ext_mass=0.0,
+                 k_max=16, p_star=0.5, tau=0.1, offsets=None, timing=False):
+    ctx = nb.Context(theta=theta, eps=eps, n_leaf=n_leaf, n_grp=n_grp,
+                     order=order, ext_mass=ext_mass, refresh=True,
+                     k_max=k_max, p_star=p_star, tau=tau, timing=timing)
+    ctx.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
+                      d["m"])
+    if offsets is not None:
+        ctx.set_systems(offsets)
+    return ctx
+
+
+def collect(ctx, steps, dt, tau, rebuild_every, device="cuda"):
+    """Leapfrog steps with the paper's fixed reuse (construction every
+    ``rebuild_every`` steps); after every reuse step the predictor inputs and
+    the staleness labels at tolerance ``tau`` of all groups are appended.
+    Returns (X [rows, 12], Y [rows]) as device tensors."""
+    torch = _torch()
+    xs, ys = [], []
+    ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+    for s in range(1, steps + 1):
+        dtk = dt / 2 if s == 1 else dt
+        if s % rebuild_every == 0:
+            ctx.step(nb.NB_MAKE_LIST_FOR_REUSE, dtk, dt)
+            continue
+        ctx.step(nb.NB_REUSE_LIST, dtk, dt)
+        ng = ctx.get_info()["n_groups"]
+        x = torch.empty((ng, nb.MLP_NIN), dtype=torch.float32, device=device)
+        y = torch.empty(ng, dtype=torch.float32, device=device)
+        ctx.group_features(out=x)
+        ctx.group_stale(tau, label_out=y)
+        xs.append(x)
+        ys.append(y)
+    return torch.cat(xs), torch.cat(ys)
+
+
+def init_weights(seed, scale=None):
+    """Glorot-style random weights (W1, W2, w3 scaled by fan-in), zero
+    biases, FP32."""
+    rng = np.random.default_rng(seed)
+    w = np.zeros(nb.MLP_NPARAM, np.float32)
+    o = 0
+    for rows, cols in ((64, 12), (64, 64), (1, 64)):
+        k = rows * cols
+        sc = scale if scale is not None else 1.0 / np.sqrt(cols)
+        w[o:o + k] = rng.standard_normal(k) * sc
+        o += k
+        o += rows  # biases stay zero
+    return w
+
+
+def train(ctx, X, Y, epochs=20, batch=8192, lr=2e-3, pos_weight=None,
+          seed=0):
+    """Shuffle the rows once (seeded), then train on the GPU.  pos_weight
+    defaults to the negative/positive ratio (capped at 50).  Returns the
+    final loss."""
+    torch = _torch()
+    n = X.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    perm = torch.randperm(n, generator=g).to(X.device)
+    Xs = X[perm].contiguous()
+    Ys = Y[perm].contiguous()
+    if pos_weight is None:
+        pos = float(Ys.sum().item())
+        pos_weight = min(50.0, max(1.0, (n - pos) / max(pos, 1.0)))
+    return ctx.mlp_train(Xs, Ys, epochs=epochs, batch=batch, lr=lr,
+                         pos_weight=pos_weight)
+
+
+def choose_threshold(p, y, recall=0.98):
+    """Largest p* such that the rows with p > p* hold at least ``recall`` of
+    the positive labels (host arrays)."""
+    p = np.asarray(p, np.float64)
+    y = np.asarray(y) > 0.5
+    if not y.any():
+        return 1.0
+    ps = np.sort(p[y])
+    # p* just below the (1 - recall) quantile of the positives' scores
+    k = int(np.floor((1.0 - recall) * ps.size))
+    return float(np.nextafter(ps[k], -np.inf)) if k < ps.size else 0.0
+
+
+def classify(p, y, p_star):
+    p = np.asarray(p)
+    y = np.asarray(y) > 0.5
+    flag = p > p_star
+    tp = int(np.sum(flag & y))
+    return dict(recall=tp / max(1, int(y.sum())),
+                flagged=float(flag.mean()), positives=float(y.mean()),
+                precision=tp / max(1, int(flag.sum())))
+
+
+def run_policy(ctx, policy, steps, dt, k, tau, measure=True, sync=True):
+    """Run ``steps`` leapfrog steps under a policy (see module doc).  With
+    ``measure`` the staleness of the lists the force kernel used is checked
+    after every step (outside the timed region).  Returns a dict with the
+    wall time of the steps, walks (groups whose list was walked: all groups
+    at a construction step, refreshed groups otherwise), and the mean stale
+    fraction."""
+    import torch
+    walks = 0
+    stale = []
+    t_run = 0.0
+    refreshed = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+    walks += ctx.get_info()["n_groups"]
+    torch.cuda.synchronize()
+    t_run += time.perf_counter() - t0
+    for s in range(1, steps + 1):
+        dtk = dt / 2 if s == 1 else dt
+        t0 = time.perf_counter()
+        if s % k == 0:
+            ctx.step(nb.NB_MAKE_LIST_FOR_REUSE, dtk, dt)
+            walks += ctx.get_info()["n_groups"]
+        elif policy == "fixed":
+            ctx.step(nb.NB_REUSE_LIST, dtk, dt)
+        elif policy == "learned":
+            ctx.step(nb.NB_REUSE_REFRESH, dtk, dt)
+            r = ctx.get_info()["last_refreshed"]
+            walks += r
+            refreshed += r
+        elif policy == "checked":
+            ctx.step(nb.NB_REUSE_CHECK, dtk, dt)
+            r = ctx.get_info()["last_refreshed"]
+            walks += r
+            refreshed += r
+        else:
+            raise ValueError(policy)
+        if sync:
+            torch.cuda.synchronize()
+        t_run += time.perf_counter() - t0
+        if measure and s % k != 0:
+            stale.append(float(np.mean(ctx.group_stale(tau))))
+    ng = ctx.get_info()["n_groups"]
+    return dict(policy=policy, k=k, steps=steps, seconds=t_run,
+                ms_per_step=1e3 * t_run / (steps + 1),
+                walks_per_step=walks / (steps + 1),
+                walk_fraction=walks / (steps + 1) / max(1, ng),
+                refreshed=refreshed,
+                stale_mean=float(np.mean(stale)) if stale else 0.0,
+                stale_max=float(np.max(stale)) if stale else 0.0)
+
+
+def evaluate(workload="disk_4m", n=1 << 18, tau=0.1, k_tree=16,
+             collect_cycles=3, recall=0.98, epochs=30, batch=8192, lr=2e-3,
+             steps=64, fixed=(1, 2, 4, 8, 16), log=print):
+    """Train the predictor on one realisation of a workload (seed 0) and
+    compare the reuse policies on another (seed 1).  Returns a list of
+    result dicts: the training summary, then one per policy."""
+    import torch
+    import workloads
+    d0, p = workloads.make(workload, n=n, replicate=0)
+    d1, _ = workloads.make(workload, n=n, replicate=1)
+    common = dict(theta=p["theta"], eps=p["eps"], n_leaf=p["n_leaf"],
+                  n_grp=p["n_grp"], order=p["order"],
+                  ext_mass=p.get("ext_mass", 0.0), tau=tau)
+    dt = p["dt"]
+    out = []
+    with make_context(d0, k_max=k_tree, offsets=d0.get("offsets"),
+                      **common) as ctx:
+        ctx.mlp_set(init_weights(0))
+        t0 = time.perf_counter()
+        X, Y = collect(ctx, collect_cycles * k_tree, dt, tau, k_tree)
+        torch.cuda.synchronize()
+        t_collect = time.perf_counter() - t0
+        n_rows = X.shape[0]
+        cut = (2 * n_rows) // 3
+        t0 = time.perf_counter()
+        loss = train(ctx, X[:cut].contiguous(), Y[:cut].contiguous(),
+                     epochs=epochs, batch=batch, lr=lr)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        pv = ctx.mlp_forward(X[cut:].contiguous()).cpu().numpy()
+        yv = Y[cut:].cpu().numpy()
+        p_star = choose_threshold(pv, yv, recall)
+        w = ctx.mlp_get()
+    stats = classify(pv, yv, p_star)
+    summary = dict(kind="training", workload=workload, n=int(d0["x"].size),
+                   tau=tau, k_tree=k_tree, rows=int(n_rows),
+                   train_rows=int(cut), positives=float(Y.mean().item()),
+                   loss=loss, p_star=p_star, collect_s=t_collect,
+                   train_s=t_train, validation=stats)
+    log(summary)
+    out.append(summary)
+    runs = [("fixed", k) for k in fixed] + [("checked", k_tree),
+                                            ("learned", k_tree)]
+    for policy, k in runs:
+        with make_context(d1, k_max=k_tree, p_star=min(1.0, max(0.0, p_star)),
+                          offsets=d1.get("offsets"), **common) as ctx:
+            ctx.mlp_set(w)
+            r = run_policy(ctx, policy, steps, dt, k, tau)
+        r.update(kind="policy", workload=workload, n=int(d1["x"].size),
+                 tau=tau)
+        log(r)
+        out.append(r)
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import os
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--workload", default="disk_4m")
+    ap.add_argument("--n", type=int, default=1 << 18)
+    ap.add_argument("--tau", type=float, default=0.1)
+    ap.add_argument("--k-tree", type=int, default=16)
+    ap.add_argument("--cycles", type=int, default=3)
+    ap.add_argument("--recall", type=float, default=0.98)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=64)
+    a = ap.parse_args(argv)
+    res = evaluate(a.workload, a.n, a.tau, a.k_tree, a.cycles, a.recall,
+                   a.epochs, steps=a.steps,
+                   log=lambda r: print(json.dumps(r), file=sys.stderr,
+                                       flush=True))
+    for r in res:
+        print(json.dumps(r), flush=True)
+
+
+if __name__ == "__main__":
+    main()

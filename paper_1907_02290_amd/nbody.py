@@ -25,6 +25,7 @@ NB_MAKE_LIST = 0
 NB_MAKE_LIST_FOR_REUSE = 1
 NB_REUSE_LIST = 2
 NB_REUSE_REFRESH = 3
+NB_REUSE_CHECK = 4
 
 PHASES = ("root", "keys", "sort", "reorder", "link", "moments", "groups",
           "walk", "force", "kick", "graph", "refresh")
@@ -50,7 +51,8 @@ class nb_config(C.Structure):
                 ("ext_mass", C.c_double), ("n_leaf", C.c_int32),
                 ("n_grp", C.c_int32), ("order", C.c_int32),
                 ("flags", C.c_int32), ("k_max", C.c_int32),
-                ("p_star", C.c_double), ("stream", C.c_void_p)]
+                ("p_star", C.c_double), ("tau", C.c_double),
+                ("stream", C.c_void_p)]
 
 
 _lib = None
@@ -137,13 +139,13 @@ class Context:
 
     def __init__(self, theta=0.5, eps=0.01, G=1.0, n_leaf=8, n_grp=64,
                  order=1, ext_mass=0.0, timing=False, graph=False,
-                 refresh=False, k_max=8, p_star=0.5, stream=None):
+                 refresh=False, k_max=8, p_star=0.5, tau=0.0, stream=None):
         self._lib = load()
         flags = (NB_FLAG_TIMING if timing else 0) | \
             (NB_FLAG_GRAPH if graph else 0) | \
             (NB_FLAG_REFRESH if refresh else 0)
         self._cfg = nb_config(theta, eps, G, ext_mass, n_leaf, n_grp, order,
-                              flags, k_max, p_star, stream)
+                              flags, k_max, p_star, tau, stream)
         h = C.c_void_p()
         rc = self._lib.nb_create(C.byref(self._cfg), C.byref(h))
         if rc != NB_OK:
@@ -179,7 +181,7 @@ class Context:
         c = self._cfg
         return dict(theta=c.theta, eps=c.eps, G=c.G, ext_mass=c.ext_mass,
                     n_leaf=c.n_leaf, n_grp=c.n_grp, order=c.order,
-                    k_max=c.k_max, p_star=c.p_star,
+                    k_max=c.k_max, p_star=c.p_star, tau=c.tau,
                     refresh=bool(c.flags & NB_FLAG_REFRESH))
 
     def set_config(self, **kw):

@@ -309,3 +309,36 @@ def test_mlp_training_is_deterministic_and_learns():
         acc = np.mean((a.mlp_forward(x) > 0.5) == (y > 0.5))
     say("  loss %.4f -> %.4f, accuracy %.3f" % (loss0, la, acc))
     assert la < 0.3 * loss0 and acc > 0.97
+
+
+def test_checked_refresh_matches_oracle():
+    say("case REUSE_CHECK")
+    d = sheared(6000, 5)
+    dt = 1 / 64
+    tau = 0.05
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 32)
+    t.make_lists(THETA)
+    ng = t.n_groups
+    age = np.zeros(ng, int)
+    with ctx_for(d, n_grp=32, tau=tau, k_max=5) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        total = 0
+        for s in range(1, 7):
+            ctx.kick_drift(0.0, dt)
+            ctx.compute_forces(nb.NB_REUSE_CHECK)
+            x, y, z = drift(d, dt, s)
+            t.refresh(x, y, z, d["m"])
+            age += 1
+            sel = np.flatnonzero(t.stale(THETA, tau)[0] | (age >= 5))
+            t.refresh_lists(THETA, sel)
+            age[sel] = 0
+            info = ctx.get_info()
+            say("  step %d refreshed %d / %d" % (s, info["last_refreshed"], ng))
+            assert info["last_refreshed"] == sel.size
+            total += sel.size
+            compare_lists(ctx, t)
+            _, _, gage = ctx.group_state()
+            np.testing.assert_array_equal(gage, age)
+            # after the step no kept list is stale at tau
+            assert not ctx.group_stale(tau).any()
+        assert ctx.get_info()["total_refreshed"] == total
