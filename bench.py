@@ -61,9 +61,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--n", type=int, default=None)
-    ap.add_argument("--n-grp", type=int, default=None)
+    ap.add_argument("--n-grp", default=None,
+                    help="group size, or 'auto' to run the autotuner first "
+                         "(untimed)")
     ap.add_argument("--n-leaf", type=int, default=None)
     ap.add_argument("--reuse", type=int, default=None)
+    ap.add_argument("--graph", action="store_true",
+                    help="replay reuse steps from a captured HIP graph")
+    ap.add_argument("--latency-steps", type=int, default=32,
+                    help="steps timed one by one afterwards (p50/p99)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -86,7 +92,15 @@ def main():
     import paper_1907_02290_amd as nb
 
     d, p = workloads.make(args.workload, n=args.n)
-    n_grp = args.n_grp or p["n_grp"]
+    tuned = None
+    if args.n_grp == "auto":
+        from paper_1907_02290_amd import tune
+        tuned = tune.tune(args.workload, args.n, log=log)
+        n_grp = tuned["best"]["n_grp"]
+        log("autotuner: n_grp %d (%.3f ms/step)" % (n_grp,
+                                                    tuned["best_ms_per_step"]))
+    else:
+        n_grp = int(args.n_grp) if args.n_grp else p["n_grp"]
     n_leaf = args.n_leaf or p["n_leaf"]
     reuse = args.reuse or p.get("reuse", 4)
     dt = p["dt"]
@@ -98,10 +112,15 @@ def main():
     dev = {k: torch.from_numpy(v).cuda() for k, v in d.items()}
     ctx = nb.Context(theta=p["theta"], eps=p["eps"], n_leaf=n_leaf,
                      n_grp=n_grp, order=p["order"],
-                     ext_mass=p.get("ext_mass", 0.0), timing=True)
+                     ext_mass=p.get("ext_mass", 0.0), timing=True,
+                     graph=args.graph)
     ctx.set_particles(dev["x"], dev["y"], dev["z"], dev["vx"], dev["vy"],
                       dev["vz"], dev["m"])
     del dev
+    n_sys = 1
+    if "offsets" in d:
+        ctx.set_systems(d["offsets"])
+        n_sys = d["offsets"].size - 1
 
     # KDK leapfrog with merged half kicks.  Step g (g >= 1): kick (dt/2 for
     # g = 1, else dt), drift dt, forces; a construction step when g is a
@@ -113,9 +132,9 @@ def main():
         g = step_no[0]
         mode = nb.NB_MAKE_LIST_FOR_REUSE if g % reuse == 0 else \
             nb.NB_REUSE_LIST
-        ctx.kick_drift(dt / 2 if g == 1 else dt, dt)
-        ctx.compute_forces(mode)
+        ctx.step(mode, dt / 2 if g == 1 else dt, dt)
         step_no[0] += 1
+        return mode
 
     ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
     # forces of the initial (seeded) state, checked against the FP64 oracle
@@ -154,6 +173,30 @@ def main():
         % (args.steps, elapsed, ms_step, value))
     log("phase ms: " + ", ".join("%s %.2f/%d" % (k, v[0], v[1])
                                  for k, v in timing.items()))
+
+    # latency: steps timed one by one (host clock around a device-wide
+    # synchronisation), construction and reuse steps apart
+    lat = {"construction": [], "reuse": []}
+    for _ in range(args.latency_steps):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        mode = step()
+        torch.cuda.synchronize()
+        kind = "reuse" if mode == nb.NB_REUSE_LIST else "construction"
+        lat[kind].append((time.perf_counter() - ta) * 1e3)
+    every = lat["construction"] + lat["reuse"]
+    latency = {"steps": len(every)}
+    for k, v in (("all", every), ("construction", lat["construction"]),
+                 ("reuse", lat["reuse"])):
+        if v:
+            latency[k] = {"p50_ms": float(np.percentile(v, 50)),
+                          "p99_ms": float(np.percentile(v, 99)),
+                          "count": len(v)}
+    if n_sys > 1:
+        latency["note"] = ("the %d systems advance together, so every "
+                           "system's step latency is the batch step time"
+                           % n_sys)
+    log("latency: " + json.dumps(latency))
 
     if args.copy_probe:
         a = torch.empty(args.copy_probe * (1 << 20) // 4, dtype=torch.float32,
@@ -248,7 +291,11 @@ def main():
                          max(info_last["n_groups"], 1),
             "force_evals": evals,
             "force_work_items": info_last["n_wi"],
+            "n_grp_autotuned": tuned is not None,
+            "systems": n_sys,
+            "graph": bool(args.graph),
         },
+        "step_latency": latency,
         "roofline": {
             "kernel": "k_force (multiwalk force, monopole)",
             "bound": "alu",
