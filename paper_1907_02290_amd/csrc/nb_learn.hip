@@ -183,6 +183,8 @@ k_features(int64_t ng, const uint32_t* __restrict__ g_cell,
 // the cell's current centre.  (side / theta')^2 = 2^(2 (k - level)) rr with
 // rr = (1 / theta')^2 rounded as (side / theta')^2 would be (power-of-two
 // scaling is exact).
+// One wave per group: the lanes test 64 kept superparticles at a time and a
+// ballot ends the group at the first failing stretch.
 __global__ void __launch_bounds__(256)
 k_check_lists(int64_t ng, const uint32_t* __restrict__ g_begin,
               const double4* __restrict__ clo,
@@ -193,33 +195,42 @@ k_check_lists(int64_t ng, const uint32_t* __restrict__ g_begin,
               const uint64_t* __restrict__ spj_off,
               const uint32_t* __restrict__ spj, double rr,
               uint8_t* __restrict__ stale) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (g >= ng) return;
   const double4 lo = clo[g], hi = chi[g];
   const int k = root[seg[g_begin[g]]].k;
   bool bad = false;
-  for (uint64_t j = spj_off[g], e = spj_off[g + 1]; j < e && !bad; ++j) {
-    const uint32_t c = spj[j];
-    const double4 cc = ctr[c];
-    const int level = (int)(rec[c].meta.w & 255u);
-    double dx = 0.0, dy = 0.0, dz = 0.0, t;
-    t = __dsub_rn(lo.x, cc.x);
-    if (t > dx) dx = t;
-    t = __dsub_rn(cc.x, hi.x);
-    if (t > dx) dx = t;
-    t = __dsub_rn(lo.y, cc.y);
-    if (t > dy) dy = t;
-    t = __dsub_rn(cc.y, hi.y);
-    if (t > dy) dy = t;
-    t = __dsub_rn(lo.z, cc.z);
-    if (t > dz) dz = t;
-    t = __dsub_rn(cc.z, hi.z);
-    if (t > dz) dz = t;
-    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
-                                __dmul_rn(dz, dz));
-    bad = !(d2 > ldexp(rr, 2 * (k - level)));
+  for (uint64_t j0 = spj_off[g], e = spj_off[g + 1]; j0 < e; j0 += 64) {
+    const uint64_t j = j0 + lane;
+    bool b = false;
+    if (j < e) {
+      const uint32_t c = spj[j];
+      const double4 cc = ctr[c];
+      const int level = (int)(rec[c].meta.w & 255u);
+      double dx = 0.0, dy = 0.0, dz = 0.0, t;
+      t = __dsub_rn(lo.x, cc.x);
+      if (t > dx) dx = t;
+      t = __dsub_rn(cc.x, hi.x);
+      if (t > dx) dx = t;
+      t = __dsub_rn(lo.y, cc.y);
+      if (t > dy) dy = t;
+      t = __dsub_rn(cc.y, hi.y);
+      if (t > dy) dy = t;
+      t = __dsub_rn(lo.z, cc.z);
+      if (t > dz) dz = t;
+      t = __dsub_rn(cc.z, hi.z);
+      if (t > dz) dz = t;
+      const double d2 = __dadd_rn(
+          __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+      b = !(d2 > ldexp(rr, 2 * (k - level)));
+    }
+    if (__ballot(b)) {
+      bad = true;
+      break;
+    }
   }
-  stale[g] = (uint8_t)bad;
+  if (lane == 0) stale[g] = (uint8_t)bad;
 }
 
 // ---- selection and list merge ----------------------------------------------
@@ -576,7 +587,7 @@ int launch_stale(nb_ctx* c, double tau) {
   const double th = c->cfg.theta * (1.0 + tau);
   const double r1 = 1.0 / th;
   const double rr = r1 * r1;
-  hipLaunchKernelGGL(k_check_lists, dim3(grid_for(c->n_groups, 256)),
+  hipLaunchKernelGGL(k_check_lists, dim3(grid_for(c->n_groups, 4)),
                      dim3(256), 0, c->stream, c->n_groups,
                      (const uint32_t*)c->g_begin.p, (const double4*)c->g_clo.p,
                      (const double4*)c->g_chi.p, (const CellRec*)c->c_rec.p,

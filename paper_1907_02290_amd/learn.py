@@ -123,24 +123,82 @@ def classify(p, y, p_star):
                 precision=tp / max(1, int(flag.sum())))
 
 
-def run_policy(ctx, policy, steps, dt, k, tau, measure=True, sync=True):
+class Reference:
+    """Direct-sum forces (theta = 0: every list holds every particle of the
+    system) through the same library, for the error of a policy's forces at
+    the positions it reached."""
+
+    def __init__(self, eps, G=1.0, ext_mass=0.0, n_grp=256, offsets=None):
+        self.ctx = nb.Context(theta=0.0, eps=eps, G=G, n_leaf=8, n_grp=n_grp,
+                              order=1, ext_mass=ext_mass)
+        self.offsets = offsets
+        self.ext_mass = ext_mass
+        self.G = G
+
+    def close(self):
+        self.ctx.close()
+
+    def forces(self, x, y, z, m):
+        zero = np.zeros_like(x)
+        self.ctx.set_particles(x, y, z, zero, zero, zero, m)
+        if self.offsets is not None:
+            self.ctx.set_systems(self.offsets)
+        self.ctx.compute_forces(nb.NB_MAKE_LIST)
+        return self.ctx.get_forces()
+
+    def energy(self, x, y, z, vx, vy, vz, m, pot):
+        kin = 0.5 * np.sum(m * (vx * vx + vy * vy + vz * vz))
+        e = kin + 0.5 * np.sum(m * pot)
+        if self.ext_mass:
+            e -= self.G * self.ext_mass * np.sum(m / np.sqrt(x * x + y * y +
+                                                             z * z))
+        return float(e)
+
+
+def force_error(got, ref):
+    ax, ay, az = got[:3]
+    rx, ry, rz = ref[:3]
+    num = np.sqrt((ax - rx) ** 2 + (ay - ry) ** 2 + (az - rz) ** 2)
+    den = np.sqrt(rx * rx + ry * ry + rz * rz)
+    ok = den > 0
+    return num[ok] / den[ok]
+
+
+def run_policy(ctx, policy, steps, dt, k, tau, measure=True, ref=None,
+               m=None, err_every=4):
     """Run ``steps`` leapfrog steps under a policy (see module doc).  With
     ``measure`` the staleness of the lists the force kernel used is checked
-    after every step (outside the timed region).  Returns a dict with the
-    wall time of the steps, walks (groups whose list was walked: all groups
-    at a construction step, refreshed groups otherwise), and the mean stale
-    fraction."""
+    after every reuse step, and with ``ref`` (a Reference) the forces are
+    compared with the direct sum every ``err_every`` steps and the energy
+    is evaluated; all of that outside the timed region.  Returns a dict with
+    the wall time of the steps, list walks per step (all groups at a
+    construction step, refreshed groups otherwise), stale fractions, force
+    errors and the relative energy change."""
     import torch
     walks = 0
     stale = []
+    errs = []
+    energies = []
     t_run = 0.0
     refreshed = 0
+
+    def check(s):
+        if ref is None or s % err_every:
+            return
+        x, y, z, vx, vy, vz = ctx.get_state()
+        got = ctx.get_forces()
+        r = ref.forces(x, y, z, m)
+        e = force_error(got, r)
+        errs.append((float(np.median(e)), float(np.percentile(e, 99))))
+        energies.append(ref.energy(x, y, z, vx, vy, vz, m, r[3]))
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
     walks += ctx.get_info()["n_groups"]
     torch.cuda.synchronize()
     t_run += time.perf_counter() - t0
+    check(0)
     for s in range(1, steps + 1):
         dtk = dt / 2 if s == 1 else dt
         t0 = time.perf_counter()
@@ -161,19 +219,27 @@ def run_policy(ctx, policy, steps, dt, k, tau, measure=True, sync=True):
             refreshed += r
         else:
             raise ValueError(policy)
-        if sync:
-            torch.cuda.synchronize()
+        torch.cuda.synchronize()
         t_run += time.perf_counter() - t0
         if measure and s % k != 0:
             stale.append(float(np.mean(ctx.group_stale(tau))))
+        check(s)
     ng = ctx.get_info()["n_groups"]
-    return dict(policy=policy, k=k, steps=steps, seconds=t_run,
-                ms_per_step=1e3 * t_run / (steps + 1),
-                walks_per_step=walks / (steps + 1),
-                walk_fraction=walks / (steps + 1) / max(1, ng),
-                refreshed=refreshed,
-                stale_mean=float(np.mean(stale)) if stale else 0.0,
-                stale_max=float(np.max(stale)) if stale else 0.0)
+    out = dict(policy=policy, k=k, steps=steps, seconds=t_run,
+               ms_per_step=1e3 * t_run / (steps + 1),
+               walks_per_step=walks / (steps + 1),
+               walk_fraction=walks / (steps + 1) / max(1, ng),
+               refreshed=refreshed,
+               stale_mean=float(np.mean(stale)) if stale else 0.0,
+               stale_max=float(np.max(stale)) if stale else 0.0)
+    if errs:
+        e = np.array(errs)
+        out.update(force_err_median=float(e[:, 0].mean()),
+                   force_err_p99=float(e[:, 1].mean()),
+                   force_err_p99_max=float(e[:, 1].max()),
+                   energy_rel_change=abs(energies[-1] - energies[0]) /
+                   abs(energies[0]))
+    return out
 
 
 def evaluate(workload="disk_4m", n=1 << 18, tau=0.1, k_tree=16,
@@ -219,15 +285,19 @@ def evaluate(workload="disk_4m", n=1 << 18, tau=0.1, k_tree=16,
     out.append(summary)
     runs = [("fixed", k) for k in fixed] + [("checked", k_tree),
                                             ("learned", k_tree)]
+    ref = Reference(p["eps"], ext_mass=p.get("ext_mass", 0.0),
+                    offsets=d1.get("offsets"))
     for policy, k in runs:
         with make_context(d1, k_max=k_tree, p_star=min(1.0, max(0.0, p_star)),
                           offsets=d1.get("offsets"), **common) as ctx:
             ctx.mlp_set(w)
-            r = run_policy(ctx, policy, steps, dt, k, tau)
+            r = run_policy(ctx, policy, steps, dt, k, tau, ref=ref,
+                           m=d1["m"])
         r.update(kind="policy", workload=workload, n=int(d1["x"].size),
                  tau=tau)
         log(r)
         out.append(r)
+    ref.close()
     return out
 
 
