@@ -1,9 +1,11 @@
 """Build ``libnbody_hip.so`` (HIP, gfx950) in-tree with hipcc.
 
 Every translation unit is compiled with packed-FP32 instructions disabled.
-The tree and walk units are also compiled without floating-point
-contraction, because keys, cell centres, boxes and the opening test must be
-bit-identical to an FP64 reference.
+The tree, walk, integration and refresh units are also compiled without
+floating-point contraction (the rounding intrinsics are plain operations
+that the compiler could otherwise fuse), because keys, cell centres, boxes,
+the opening test and the position update must be bit-identical to an FP64
+reference.
 """
 from __future__ import annotations
 
@@ -19,7 +21,7 @@ ARCH = "gfx950"
 
 SOURCES = ["nb_scan.hip", "nb_tree.hip", "nb_walk.hip", "nb_force.hip",
            "nb_step.hip", "nb_learn.hip", "nb_api.hip"]
-EXACT = {"nb_tree.hip", "nb_walk.hip"}
+EXACT = {"nb_tree.hip", "nb_walk.hip", "nb_step.hip", "nb_learn.hip"}
 
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
