@@ -25,6 +25,8 @@ namespace nb {
 namespace {
 
 constexpr int kWalkThreads = 256;
+// launches with fewer groups than this walk one group per wavefront
+constexpr int64_t kWaveWalkBelow = 1 << 30;
 
 __device__ inline int64_t xcd_block(int64_t nblk) {
   const int64_t per = (nblk + 7) / 8;
@@ -162,6 +164,139 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   }
 }
 
+// Wave-cooperative walk: one wavefront per group, for launches with too
+// few groups to fill the device one thread per group.  The lanes take 64
+// consecutive cells of the pre-order array and evaluate the opening test of
+// each; a cell is one the stackless walk visits unless an earlier cell of
+// the window that ends the walk there (accepted, or an opened leaf) has a
+// subtree reaching past it -- an exclusive prefix maximum of those subtree
+// ends.  (Earlier windows cannot hide a cell: the window starts at a visited
+// cell, whose ancestors were all opened.)  The next window starts at the
+// later of the window's end and the farthest such subtree end.  Tokens come
+// out in pre-order, exactly as from the one-thread walk.
+template <bool FILL, bool LEARN>
+__global__ void __launch_bounds__(256)
+k_walk_wave(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
+            const uint32_t* __restrict__ g_begin,
+            const uint32_t* __restrict__ g_count,
+            const double4* __restrict__ g_lo, const double4* __restrict__ g_hi,
+            const CellRec* __restrict__ rec, const double4* __restrict__ ctr,
+            const uint32_t* __restrict__ g_cell,
+            const double4* __restrict__ shift, double* __restrict__ g_sa,
+            double* __restrict__ g_so, double4* __restrict__ g_tau0,
+            const uint32_t* __restrict__ seg,
+            const uint32_t* __restrict__ croot, uint32_t* __restrict__ cnt_e,
+            uint32_t* __restrict__ cnt_s, uint32_t* __restrict__ cnt_t,
+            const uint64_t* __restrict__ tok_off, uint32_t* __restrict__ tok) {
+  const int64_t blk = xcd_block(nblk);
+  if (blk >= nblk) return;
+  const int64_t t = blk * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= n_walk) return;  // uniform over the wave
+  const int64_t g = (LEARN && sel) ? (int64_t)sel[t] : t;
+  const uint32_t gb = g_begin[g];
+  const uint32_t ge = gb + g_count[g];
+  const double4 lo = g_lo[g], hi = g_hi[g];
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  uint64_t out = FILL ? tok_off[t] : 0;
+  uint32_t ne = 0, ns = 0, nl = 0;  // per lane
+  double sa = __builtin_inf(), so = __builtin_inf();
+  const uint32_t sys = seg[gb];
+  uint32_t c = croot[sys];
+  const uint32_t nc = croot[sys + 1];
+  while (c < nc) {
+    const uint32_t i = c + (uint32_t)lane;
+    const bool valid = i < nc;
+    uint4 m = make_uint4(0u, 0u, 0u, 0u);
+    bool open = false, stop = false, holds = false;
+    double d2 = 0.0, rc2 = 0.0;
+    if (valid) {
+      m = rec[i].meta;
+      const double4 cc = LEARN ? ctr[i] : rec[i].geo;
+      holds = m.x <= gb && m.y >= ge;
+      if (holds) {
+        open = true;
+      } else {
+        double dx = 0.0, dy = 0.0, dz = 0.0, u;
+        u = __dsub_rn(lo.x, cc.x);
+        if (u > dx) dx = u;
+        u = __dsub_rn(cc.x, hi.x);
+        if (u > dx) dx = u;
+        u = __dsub_rn(lo.y, cc.y);
+        if (u > dy) dy = u;
+        u = __dsub_rn(cc.y, hi.y);
+        if (u > dy) dy = u;
+        u = __dsub_rn(lo.z, cc.z);
+        if (u > dz) dz = u;
+        u = __dsub_rn(cc.z, hi.z);
+        if (u > dz) dz = u;
+        d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                       __dmul_rn(dz, dz));
+        rc2 = cc.w;
+        open = !(d2 > rc2);
+      }
+      stop = !open || ((m.w >> 8) & 1u);
+    }
+    // exclusive prefix maximum of the subtree ends of stopping cells
+    uint32_t incl = stop ? m.z : 0u;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(incl, d, 64);
+      if (lane >= d && v > incl) incl = v;
+    }
+    uint32_t excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = 0u;
+    const bool visited = valid && !(excl > i);
+    const bool acc = visited && !open;
+    const bool lf = visited && open && stop;
+    if (LEARN && !FILL && visited && !holds) {
+      const double dd = __dsqrt_rn(d2), rr = __dsqrt_rn(rc2);
+      if (open) {
+        const double v = __dsub_rn(rr, dd);
+        if (v < so) so = v;
+      } else {
+        const double v = __dsub_rn(dd, rr);
+        if (v < sa) sa = v;
+      }
+    }
+    if (FILL) {
+      const uint64_t me = __ballot(acc || lf);
+      if (acc || lf)
+        tok[out + __popcll(me & below)] = acc ? i : (i | kLeafTag);
+      out += __popcll(me);
+    } else {
+      ns += acc ? 1u : 0u;
+      nl += lf ? 1u : 0u;
+      ne += lf ? m.y - m.x : 0u;
+    }
+    const uint32_t far = __shfl(incl, 63, 64);
+    const uint32_t next = c + 64u;
+    c = far > next ? far : next;
+  }
+  if (!FILL) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      ne += __shfl_xor(ne, o, 64);
+      ns += __shfl_xor(ns, o, 64);
+      nl += __shfl_xor(nl, o, 64);
+      if (LEARN) {
+        sa = fmin(sa, __shfl_xor(sa, o, 64));
+        so = fmin(so, __shfl_xor(so, o, 64));
+      }
+    }
+    if (lane == 0) {
+      cnt_e[t] = ne;
+      cnt_s[t] = ns;
+      cnt_t[t] = ns + nl;
+      if (LEARN) {
+        g_sa[g] = sa;
+        g_so[g] = so;
+        g_tau0[g] = shift[g_cell[g]];
+      }
+    }
+  }
+}
+
 // One wave per group: the token stream -> SPJ ids and EPJ particle ids.
 // Tokens are read in chunks of 64; accepted cells are compacted with a
 // ballot, opened leaves are expanded using a wave scan of their sizes, so
@@ -259,10 +394,18 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
   if (n_walk <= 0) return NB_OK;
   const bool learn = c->learn;
   if (!learn && sel) return set_err(c, NB_ERR_STATE, "selected walk needs refresh mode");
-  const int64_t nblk = grid_for(n_walk, kWalkThreads);
+  // one thread per group fills the device only with many groups; below
+  // that, one wave per group
+  const bool wave = n_walk < kWaveWalkBelow;
+  const int64_t nblk = wave ? grid_for(n_walk, 4)
+                            : grid_for(n_walk, kWalkThreads);
   const int64_t launch = (nblk + 7) / 8 * 8;
-  auto k = fill ? (learn ? k_walk<true, true> : k_walk<true, false>)
-                : (learn ? k_walk<false, true> : k_walk<false, false>);
+  auto k = wave ? (fill ? (learn ? k_walk_wave<true, true>
+                                 : k_walk_wave<true, false>)
+                        : (learn ? k_walk_wave<false, true>
+                                 : k_walk_wave<false, false>))
+                : (fill ? (learn ? k_walk<true, true> : k_walk<true, false>)
+                        : (learn ? k_walk<false, true> : k_walk<false, false>));
   hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
                      c->stream, n_walk, nblk, sel,
                      (const uint32_t*)c->g_begin.p,

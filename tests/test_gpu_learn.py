@@ -342,3 +342,45 @@ def test_checked_refresh_matches_oracle():
             # after the step no kept list is stale at tau
             assert not ctx.group_stale(tau).any()
         assert ctx.get_info()["total_refreshed"] == total
+
+
+def test_learned_refresh_gains_over_fixed_interval():
+    """What the trained predictor gains over the method without it: with the
+    same construction schedule (every 16 steps), refreshing the lists the
+    predictor flags keeps far fewer stale lists in use and lowers the tail
+    of the force error against the direct sum, while walking far fewer lists
+    than a full refresh every step would."""
+    from paper_1907_02290_amd import learn
+    say("case learned gain")
+    n, tau, kt = 1 << 15, 0.1, 16
+    d0, p = workloads.make("disk_4m", n=n, replicate=0)
+    d1, _ = workloads.make("disk_4m", n=n, replicate=1)
+    common = dict(theta=p["theta"], eps=p["eps"], n_leaf=8, n_grp=64,
+                  order=1, tau=tau)
+    with learn.make_context(d0, k_max=kt, **common) as ctx:
+        ctx.mlp_set(learn.init_weights(0))
+        X, Y = learn.collect(ctx, 2 * kt, p["dt"], tau, kt)
+        cut = (2 * X.shape[0]) // 3
+        learn.train(ctx, X[:cut].contiguous(), Y[:cut].contiguous(),
+                    epochs=30, batch=4096, lr=2e-3)
+        pv = ctx.mlp_forward(X[cut:].contiguous()).cpu().numpy()
+        yv = Y[cut:].cpu().numpy()
+        p_star = learn.choose_threshold(pv, yv, 0.98)
+        w = ctx.mlp_get()
+    stats = learn.classify(pv, yv, p_star)
+    say("  p* %.4f validation %s" % (p_star, stats))
+    ref = learn.Reference(p["eps"])
+    res = {}
+    for policy in ("fixed", "learned"):
+        with learn.make_context(d1, k_max=kt, p_star=p_star, **common) as ctx:
+            ctx.mlp_set(w)
+            res[policy] = learn.run_policy(ctx, policy, 32, p["dt"], kt, tau,
+                                           ref=ref, m=d1["m"])
+        say("  %s: %s" % (policy, {k: (round(v, 5) if isinstance(v, float)
+                                       else v) for k, v in res[policy].items()}))
+    ref.close()
+    f, l = res["fixed"], res["learned"]
+    assert stats["recall"] >= 0.9
+    assert l["stale_mean"] < 0.3 * f["stale_mean"]
+    assert l["force_err_p99"] < f["force_err_p99"]
+    assert l["walk_fraction"] < 0.7
