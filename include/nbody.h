@@ -241,8 +241,12 @@ int nb_get_timing(nb_ctx* ctx, double* ms, int64_t* calls, int reset);
  * a fixed number of steps.  Cells keep their particle ranges between
  * construction steps; in every opening test of a refresh mode walk, the
  * geometric centre of a cell is moved by the displacement of its FP64
- * centre of mass since the construction step (zero at construction, so
- * construction lists are unchanged), so that a rigid motion stales no list.
+ * centre of mass since the construction step, so that a rigid motion stales
+ * no list, and the cell's side becomes twice the largest per-axis distance
+ * from that centre to the box of its current particles when that is larger
+ * (a cell whose particles spread is opened sooner).  At construction the
+ * shift is zero and the side the geometric one, so construction lists are
+ * unchanged.
  * A group's list is stale (at tolerance tau >= 0) when one of its
  * superparticles fails the opening test at the relaxed angle theta (1 + tau)
  * from the group's current tight box; particles are exact and cells that a
@@ -285,6 +289,9 @@ int nb_refresh_lists(nb_ctx* ctx, int64_t n_sel, const int64_t* sel);
  * so = smallest rcrit - |box - centre| over opened cells not holding the
  * group, of the walk that made the list. */
 int nb_get_group_state(nb_ctx* ctx, double* sa, double* so, int32_t* age);
+
+/* The side each cell has in the opening test now (info[1] values, FP64). */
+int nb_get_cell_sides(nb_ctx* ctx, double* side);
 
 /* Perceptron weights (host, NB_MLP_NPARAM floats).  Setting them clears the
  * Adam state.  A context starts with zero weights (p = 1/2). */

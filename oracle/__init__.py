@@ -79,6 +79,7 @@ def _load():
     lib.orc_group_margins.argtypes = [p, p, p]
     lib.orc_group_stale.argtypes = [p, d, d, p, p, p]
     lib.orc_refresh_lists.argtypes = [p, d, i64, p, p]
+    lib.orc_cell_sides.argtypes = [p, p]
     lib.orc_group_features.argtypes = [p, C.c_int, p, p]
     lib.orc_mlp_nparam.argtypes = []
     lib.orc_mlp_forward.argtypes = [p, i64, p, p]
@@ -89,7 +90,8 @@ def _load():
               "orc_make_lists", "orc_get_lists", "orc_refresh",
               "orc_force_lists", "orc_force_direct", "orc_kick_drift",
               "orc_num_threads", "orc_group_margins", "orc_group_stale",
-              "orc_refresh_lists", "orc_group_features", "orc_mlp_nparam", "orc_mlp_forward", "orc_mlp_loss_grad",
+              "orc_refresh_lists", "orc_group_features", "orc_cell_sides",
+              "orc_mlp_nparam", "orc_mlp_forward", "orc_mlp_loss_grad",
               "orc_adam"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -262,6 +264,13 @@ class Tree:
                "refresh_lists")
         self._sizes = sizes.copy()
         return int(sizes[0]), int(sizes[1]), int(sizes[2])
+
+    def cell_sides(self):
+        """Side of every cell in the opening test at the current positions
+        (the geometric side unless the cell's particles spread further)."""
+        out = np.zeros(self.n_cell)
+        _check(_load().orc_cell_sides(self._h, _ptr(out)), "cell_sides")
+        return out
 
     def features(self, kmax, age):
         """The 12 rebuild-predictor inputs per group (FP64, [G, 12])."""

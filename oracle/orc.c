@@ -66,6 +66,7 @@ struct orc_tree {
   double* mass;
   double* com;  /* 3 per cell */
   double* com0; /* 3 per cell: centres of mass at construction */
+  double *bmin, *bmax; /* 3 per cell: box of the cell's particles now */
   double* quad; /* 6 per cell: xx yy zz xy xz yz */
   /* groups; g_lo/g_hi is the box the group's current list was walked
    * with (the construction-time box until a list refresh) */
@@ -284,6 +285,16 @@ static void compute_moments(orc_tree* t) {
     t->mass[c] = M;
     memcpy(&t->com[3 * c], X, sizeof X);
     memcpy(&t->quad[6 * c], S, sizeof S);
+    const double* p[3] = {t->x, t->y, t->z};
+    for (int a = 0; a < 3; ++a) {
+      double mn = p[a][b], mx = p[a][b];
+      for (int64_t i = b + 1; i < e; ++i) {
+        if (p[a][i] < mn) mn = p[a][i];
+        if (p[a][i] > mx) mx = p[a][i];
+      }
+      t->bmin[3 * c + a] = mn;
+      t->bmax[3 * c + a] = mx;
+    }
   }
 }
 
@@ -366,6 +377,8 @@ void orc_free(orc_tree* t) {
   free(t->mass);
   free(t->com);
   free(t->com0);
+  free(t->bmin);
+  free(t->bmax);
   free(t->quad);
   free(t->g_cell);
   free(t->g_begin);
@@ -434,8 +447,11 @@ orc_tree* orc_build(int64_t n, const double* x, const double* y,
   t->mass = (double*)malloc((size_t)t->n_cell * sizeof(double));
   t->com = (double*)malloc((size_t)t->n_cell * 3 * sizeof(double));
   t->com0 = (double*)malloc((size_t)t->n_cell * 3 * sizeof(double));
+  t->bmin = (double*)malloc((size_t)t->n_cell * 3 * sizeof(double));
+  t->bmax = (double*)malloc((size_t)t->n_cell * 3 * sizeof(double));
   t->quad = (double*)malloc((size_t)t->n_cell * 6 * sizeof(double));
-  if (!t->mass || !t->com || !t->com0 || !t->quad) goto fail;
+  if (!t->mass || !t->com || !t->com0 || !t->bmin || !t->bmax || !t->quad)
+    goto fail;
   compute_moments(t);
   memcpy(t->com0, t->com, (size_t)t->n_cell * 3 * sizeof(double));
   if (make_groups(t)) goto fail;
@@ -523,12 +539,54 @@ static void cell_shift(const orc_tree* t, int64_t c, double tr[3]) {
   for (int a = 0; a < 3; ++a) tr[a] = t->com[3 * c + a] - t->com0[3 * c + a];
 }
 
+/* Moved centre of cell c (geometric centre + shift). */
+static void moved_centre(const orc_tree* t, int64_t c, double cc[3]) {
+  double tr[3];
+  cell_shift(t, c, tr);
+  for (int a = 0; a < 3; ++a) cc[a] = t->ctr[3 * c + a] + tr[a];
+}
+
+/* Side used in the opening test of cell c: the geometric side, or twice
+ * the largest per-axis distance from the moved centre cc to the box of the
+ * cell's current particles, whichever is larger.  Right after construction
+ * every particle lies in its cell's cube, so this is the geometric side;
+ * later it grows with a cell whose particles spread. */
+static double side_eff(const orc_tree* t, int64_t c, const double cc[3]) {
+  const double s = ldexp(1.0, t->k - t->level[c]);
+  double h = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double up = t->bmax[3 * c + a] - cc[a];
+    const double dn = cc[a] - t->bmin[3 * c + a];
+    if (up > h) h = up;
+    if (dn > h) h = dn;
+  }
+  const double w = 2.0 * h;
+  return w > s ? w : s;
+}
+
+/* (side_eff / theta)^2: the squared opening radius of cell c. */
+static double crit2(const orc_tree* t, int64_t c, const double cc[3],
+                    double theta) {
+  const double r = side_eff(t, c, cc) / theta;
+  return r * r;
+}
+
+int orc_cell_sides(const orc_tree* t, double* side) {
+  if (!t || !side) return -1;
+  for (int64_t c = 0; c < t->n_cell; ++c) {
+    double cc[3];
+    moved_centre(t, c, cc);
+    side[c] = side_eff(t, c, cc);
+  }
+  return 0;
+}
+
 /* Group tree walk (section 4.3 "construct the interaction lists"; indirect
  * addressing of section 4.1: the lists hold 32-bit indices).  Reading R6.
  * DFS from the root over the pre-order cell array; `skip` jumps over a
  * subtree.  When `fill` is zero only the list lengths are counted. */
 static void walk_box(const orc_tree* t, int64_t g, const double* glo,
-                     const double* ghi, const double* rcrit2, int fill,
+                     const double* ghi, double theta, int fill,
                      uint32_t* epj, uint32_t* spj, int64_t* n_epj,
                      int64_t* n_spj, orc_slack* mg) {
   const uint32_t gb = t->g_begin[g];
@@ -543,19 +601,18 @@ static void walk_box(const orc_tree* t, int64_t g, const double* glo,
     if (cb <= gb && ce >= ge) {
       open = 1; /* the cell holds the group */
     } else {
-      double tr[3], d[3];
-      cell_shift(t, c, tr);
+      double cc[3], d[3];
+      moved_centre(t, c, cc);
       for (int a = 0; a < 3; ++a) {
-        const double cc = t->ctr[3 * c + a] + tr[a];
         double v = 0.0;
-        const double below = glo[a] - cc;
-        const double above = cc - ghi[a];
+        const double below = glo[a] - cc[a];
+        const double above = cc[a] - ghi[a];
         if (below > v) v = below;
         if (above > v) v = above;
         d[a] = v;
       }
       const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-      const double rc = rcrit2[t->level[c]];
+      const double rc = crit2(t, c, cc, theta);
       open = !(d2 > rc);
       if (mg) {
         const double dd = sqrt(d2), rr = sqrt(rc);
@@ -588,13 +645,6 @@ static void walk_box(const orc_tree* t, int64_t g, const double* glo,
   }
 }
 
-static void crit_radii(const orc_tree* t, double theta, double* rcrit2) {
-  for (int l = 0; l <= MAX_LEVEL; ++l) {
-    const double r = ldexp(1.0, t->k - l) / theta;
-    rcrit2[l] = r * r;
-  }
-}
-
 /* Tight box of group g's particles at their current positions. */
 static void group_box(const orc_tree* t, int64_t g, double lo[3],
                       double hi[3]) {
@@ -610,11 +660,11 @@ static void group_box(const orc_tree* t, int64_t g, double lo[3],
 }
 
 /* Walk group g with box (lo, hi) and record what the features need. */
-static void walk_record(orc_tree* t, int64_t g, const double* rcrit2,
+static void walk_record(orc_tree* t, int64_t g, double theta,
                         int fill, uint32_t* epj, uint32_t* spj, int64_t* ne,
                         int64_t* ns) {
   orc_slack mg;
-  walk_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g], rcrit2, fill, epj, spj,
+  walk_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g], theta, fill, epj, spj,
            ne, ns, &mg);
   if (!fill) {
     t->g_sa[g] = mg.sa;
@@ -645,8 +695,6 @@ int orc_group_stale(const orc_tree* t, double theta, double tau,
                     uint8_t* stale, double* lo3, double* hi3) {
   if (!t || !stale || !full_lists(t) || !(tau >= 0.0)) return -1;
   const double th = theta * (1.0 + tau);
-  double rcrit2[MAX_LEVEL + 1];
-  crit_radii(t, th, rcrit2);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t g = 0; g < t->n_groups; ++g) {
     double lo[3], hi[3];
@@ -656,19 +704,18 @@ int orc_group_stale(const orc_tree* t, double theta, double tau,
     int bad = 0;
     for (int64_t j = t->spj_off[g]; j < t->spj_off[g + 1] && !bad; ++j) {
       const uint32_t c = t->spj[j];
-      double tr[3], d[3];
-      cell_shift(t, c, tr);
+      double cc[3], d[3];
+      moved_centre(t, c, cc);
       for (int a = 0; a < 3; ++a) {
-        const double cc = t->ctr[3 * c + a] + tr[a];
         double v = 0.0;
-        const double below = lo[a] - cc;
-        const double above = cc - hi[a];
+        const double below = lo[a] - cc[a];
+        const double above = cc[a] - hi[a];
         if (below > v) v = below;
         if (above > v) v = above;
         d[a] = v;
       }
       const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-      bad = !(d2 > rcrit2[t->level[c]]);
+      bad = !(d2 > crit2(t, c, cc, th));
     }
     stale[g] = (uint8_t)bad;
   }
@@ -695,13 +742,11 @@ int orc_refresh_lists(orc_tree* t, double theta, int64_t n_sel,
     if (sel[i] < 0 || sel[i] >= G || (i > 0 && sel[i] <= sel[i - 1])) goto out;
     pick[sel[i]] = 1;
   }
-  double rcrit2[MAX_LEVEL + 1];
-  crit_radii(t, theta, rcrit2);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t g = 0; g < G; ++g) {
     if (pick[g]) {
       group_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g]);
-      walk_record(t, g, rcrit2, 0, NULL, NULL, &ne[g], &ns[g]);
+      walk_record(t, g, theta, 0, NULL, NULL, &ne[g], &ns[g]);
     } else {
       ne[g] = t->epj_off[g + 1] - t->epj_off[g];
       ns[g] = t->spj_off[g + 1] - t->spj_off[g];
@@ -719,7 +764,7 @@ int orc_refresh_lists(orc_tree* t, double theta, int64_t n_sel,
   for (int64_t g = 0; g < G; ++g) {
     if (pick[g]) {
       int64_t a, b;
-      walk_record(t, g, rcrit2, 1, ee + eo[g], ss + so[g], &a, &b);
+      walk_record(t, g, theta, 1, ee + eo[g], ss + so[g], &a, &b);
     } else {
       memcpy(ee + eo[g], t->epj + t->epj_off[g], (size_t)ne[g] * 4);
       memcpy(ss + so[g], t->spj + t->spj_off[g], (size_t)ns[g] * 4);
@@ -828,9 +873,6 @@ int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
     if (g < 0 || g >= t->n_groups) return -1;
     t->sel[s] = g;
   }
-  /* critical radius per level: (s_l / theta)^2 with s_l = L 2^-l */
-  double rcrit2[MAX_LEVEL + 1];
-  crit_radii(t, theta, rcrit2);
   /* count pass */
   int64_t* ne = (int64_t*)malloc((size_t)(ns_all ? ns_all : 1) * sizeof(int64_t));
   int64_t* ns = (int64_t*)malloc((size_t)(ns_all ? ns_all : 1) * sizeof(int64_t));
@@ -841,7 +883,7 @@ int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
   }
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t s = 0; s < ns_all; ++s)
-    walk_record(t, t->sel[s], rcrit2, 0, NULL, NULL, &ne[s], &ns[s]);
+    walk_record(t, t->sel[s], theta, 0, NULL, NULL, &ne[s], &ns[s]);
   t->epj_off[0] = t->spj_off[0] = 0;
   for (int64_t s = 0; s < ns_all; ++s) {
     t->epj_off[s + 1] = t->epj_off[s] + ne[s];
@@ -856,7 +898,7 @@ int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t s = 0; s < ns_all; ++s) {
     int64_t a, b;
-    walk_record(t, t->sel[s], rcrit2, 1, t->epj + t->epj_off[s],
+    walk_record(t, t->sel[s], theta, 1, t->epj + t->epj_off[s],
                 t->spj + t->spj_off[s], &a, &b);
   }
   sizes[0] = ns_all;

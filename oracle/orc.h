@@ -62,8 +62,14 @@ int orc_get_lists(const orc_tree* t, int64_t* epj_off, uint32_t* epj,
 /* Reuse with per-group list refresh (an extension of section 4.2's list
  * reuse).  Cells keep their particle ranges; in every opening test the
  * geometric centre of a cell is moved by the displacement of its centre of
- * mass since construction (zero right after construction).  Positions come
- * from the last orc_build / orc_refresh.  All need lists of every group. */
+ * mass since construction (zero right after construction), and the cell's
+ * side is replaced by twice the largest per-axis distance from that centre
+ * to the box of its current particles when that is larger (never right
+ * after construction).  Positions come from the last orc_build /
+ * orc_refresh.  All but orc_cell_sides need lists of every group. */
+
+/* The side each cell has in the opening test now (n_cell values). */
+int orc_cell_sides(const orc_tree* t, double* side);
 
 /* Opening-test slacks of the walk that made each group's list: sa = the
  * smallest |box - centre| - rcrit over accepted cells, so = the smallest

@@ -342,6 +342,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->epj); release(c->spj); release(c->tok);
   release(c->scan_tmp); release(c->red);
   release(c->c_com); release(c->c_com0); release(c->c_shift); release(c->c_ctr);
+  release(c->c_bmin); release(c->c_bmax);
   release(c->g_clo); release(c->g_chi); release(c->g_tau0);
   release(c->g_sa); release(c->g_so); release(c->g_age);
   release(c->pick); release(c->pickpos); release(c->sel);

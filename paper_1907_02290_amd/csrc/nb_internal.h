@@ -134,8 +134,9 @@ struct nb_ctx {
   bool shift_fresh = false;  // centres of mass match the positions
   nb::DBuf<double4> c_com, c_com0;  // FP64 centre of mass (w = mass): now,
                                     // and at construction
-  nb::DBuf<double4> c_shift;        // com - com0
-  nb::DBuf<double4> c_ctr;          // geo + shift, w = rcrit^2
+  nb::DBuf<double4> c_bmin, c_bmax;  // box of each cell's particles now
+  nb::DBuf<double4> c_shift;        // com - com0, w = side in the test
+  nb::DBuf<double4> c_ctr;          // geo + shift, w = (side/theta)^2
   nb::DBuf<double4> g_clo, g_chi;   // current tight boxes
   nb::DBuf<double4> g_tau0;         // cell shift when the list was walked
   nb::DBuf<double> g_sa, g_so;      // opening-test slacks of that walk

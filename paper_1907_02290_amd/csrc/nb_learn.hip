@@ -5,10 +5,13 @@
 // their kept list has gone stale.
 //
 // Refresh mode (NB_FLAG_REFRESH) keeps per cell the FP64 centre of mass at
-// construction and at the current step; in every opening test the cell's
-// geometric centre is moved by their difference, so that a rigid motion
-// changes no list.  Right after construction the shift is exactly zero and
-// the walk is the plain one.  Per group it keeps the box, the cell shift and
+// construction and at the current step and the box of its current
+// particles; in every opening test the cell's geometric centre is moved by
+// the difference of the two centres of mass (a rigid motion changes no
+// list), and its side becomes twice the largest distance from that centre
+// to the particle box when that is larger (a cell whose particles spread is
+// opened sooner).  Right after construction the shift is exactly zero, the
+// side the geometric one, and the walk the plain one.  Per group it keeps the box, the cell shift and
 // the opening-test slacks of the walk that made its list, and the list's
 // age in reuse steps.  A kept list is stale at tolerance tau when one of its
 // superparticles fails the opening test at angle theta (1 + tau): that is
@@ -52,58 +55,100 @@ __device__ inline uint32_t next_sibling(const CellRec* __restrict__ rec,
 __global__ void __launch_bounds__(256)
 k_com_leaf(int64_t cnt, const uint32_t* __restrict__ list,
            const CellRec* __restrict__ rec, const double4* __restrict__ pos,
-           double4* __restrict__ com) {
+           double4* __restrict__ com, double4* __restrict__ bmin,
+           double4* __restrict__ bmax) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cnt) return;
   const uint32_t c = list[t];
   const uint4 m = rec[c].meta;
   const double4 g = rec[c].geo;
   double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+  double4 lo = pos[m.x], hi = lo;
   for (uint32_t p = m.x; p < m.y; ++p) {
     const double4 P = pos[p];
     M += P.w;
     sx += P.w * (P.x - g.x);
     sy += P.w * (P.y - g.y);
     sz += P.w * (P.z - g.z);
+    lo.x = fmin(lo.x, P.x);
+    lo.y = fmin(lo.y, P.y);
+    lo.z = fmin(lo.z, P.z);
+    hi.x = fmax(hi.x, P.x);
+    hi.y = fmax(hi.y, P.y);
+    hi.z = fmax(hi.z, P.z);
   }
+  bmin[c] = lo;
+  bmax[c] = hi;
   com[c] = M > 0.0 ? make_double4(g.x + sx / M, g.y + sy / M, g.z + sz / M, M)
                    : make_double4(g.x, g.y, g.z, 0.0);
 }
 
 __global__ void __launch_bounds__(256)
 k_com_internal(int64_t cnt, const uint32_t* __restrict__ list,
-               const CellRec* __restrict__ rec, double4* __restrict__ com) {
+               const CellRec* __restrict__ rec, double4* __restrict__ com,
+               double4* __restrict__ bmin, double4* __restrict__ bmax) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cnt) return;
   const uint32_t c = list[t];
   const uint32_t stop = rec[c].meta.z;
   const double4 g = rec[c].geo;
   double M = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+  double4 lo = bmin[c + 1], hi = bmax[c + 1];
   for (uint32_t k = c + 1; k < stop; k = next_sibling(rec, k, stop)) {
     const double4 ck = com[k];
     M += ck.w;
     sx += ck.w * (ck.x - g.x);
     sy += ck.w * (ck.y - g.y);
     sz += ck.w * (ck.z - g.z);
+    const double4 a = bmin[k], b = bmax[k];
+    lo.x = fmin(lo.x, a.x);
+    lo.y = fmin(lo.y, a.y);
+    lo.z = fmin(lo.z, a.z);
+    hi.x = fmax(hi.x, b.x);
+    hi.y = fmax(hi.y, b.y);
+    hi.z = fmax(hi.z, b.z);
   }
+  bmin[c] = lo;
+  bmax[c] = hi;
   com[c] = M > 0.0 ? make_double4(g.x + sx / M, g.y + sy / M, g.z + sz / M, M)
                    : make_double4(g.x, g.y, g.z, 0.0);
 }
 
-// shift = com - com0; centre for the opening test = geo + shift (rounded
-// once each, as the FP64 reference does), w = (side / theta)^2.
+// Per cell: shift = com - com0, moved centre c' = geo + shift (rounded once
+// each, as the FP64 reference does), and the side of the opening test:
+// the geometric side s, or twice the largest per-axis distance from c' to
+// the box of the cell's current particles when that is larger (never right
+// after construction, when every particle lies in its cube).  ctr.w =
+// (side / theta)^2 -- at construction exactly the record's value, since
+// s / theta = s (1 / theta) for a power of two s; shift.w = side.
 __global__ void __launch_bounds__(256)
 k_shift(int64_t nc, const CellRec* __restrict__ rec,
         const double4* __restrict__ com, const double4* __restrict__ com0,
-        double4* __restrict__ shift, double4* __restrict__ ctr) {
+        const double4* __restrict__ bmin, const double4* __restrict__ bmax,
+        const Root* __restrict__ root, const uint32_t* __restrict__ seg,
+        double theta, double4* __restrict__ shift, double4* __restrict__ ctr) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   const double4 a = com[c], b = com0[c], g = rec[c].geo;
+  const uint4 m = rec[c].meta;
   const double sx = __dsub_rn(a.x, b.x), sy = __dsub_rn(a.y, b.y),
                sz = __dsub_rn(a.z, b.z);
-  shift[c] = make_double4(sx, sy, sz, 0.0);
-  ctr[c] = make_double4(__dadd_rn(g.x, sx), __dadd_rn(g.y, sy),
-                        __dadd_rn(g.z, sz), g.w);
+  const double cx = __dadd_rn(g.x, sx), cy = __dadd_rn(g.y, sy),
+               cz = __dadd_rn(g.z, sz);
+  const double4 lo = bmin[c], hi = bmax[c];
+  double h = 0.0;
+  h = fmax(h, __dsub_rn(hi.x, cx));
+  h = fmax(h, __dsub_rn(cx, lo.x));
+  h = fmax(h, __dsub_rn(hi.y, cy));
+  h = fmax(h, __dsub_rn(cy, lo.y));
+  h = fmax(h, __dsub_rn(hi.z, cz));
+  h = fmax(h, __dsub_rn(cz, lo.z));
+  const double s = ldexp(1.0, root[seg[m.x]].k - (int)(m.w & 255u));
+  const double w = 2.0 * h;
+  const double side = w > s ? w : s;
+  const double r = __ddiv_rn(side, theta);
+  shift[c] = make_double4(sx, sy, sz, side);
+  ctr[c] = make_double4(cx, cy, cz, __dmul_rn(r, r));
 }
 
 __global__ void __launch_bounds__(256)
@@ -179,27 +224,22 @@ k_features(int64_t ng, const uint32_t* __restrict__ g_cell,
 
 // ---- staleness labels -------------------------------------------------------
 // A kept list is stale when one of its superparticles fails the opening
-// test at the relaxed angle theta (1 + tau) from the group's current box and
-// the cell's current centre.  (side / theta')^2 = 2^(2 (k - level)) rr with
-// rr = (1 / theta')^2 rounded as (side / theta')^2 would be (power-of-two
-// scaling is exact).
+// test at the relaxed angle theta' = theta (1 + tau) from the group's current
+// box and the cell's current centre and side: (side / theta')^2.
 // One wave per group: the lanes test 64 kept superparticles at a time and a
 // ballot ends the group at the first failing stretch.
 __global__ void __launch_bounds__(256)
-k_check_lists(int64_t ng, const uint32_t* __restrict__ g_begin,
-              const double4* __restrict__ clo,
+k_check_lists(int64_t ng, const double4* __restrict__ clo,
               const double4* __restrict__ chi,
-              const CellRec* __restrict__ rec,
-              const double4* __restrict__ ctr, const Root* __restrict__ root,
-              const uint32_t* __restrict__ seg,
+              const double4* __restrict__ ctr,
+              const double4* __restrict__ shift,
               const uint64_t* __restrict__ spj_off,
-              const uint32_t* __restrict__ spj, double rr,
+              const uint32_t* __restrict__ spj, double th,
               uint8_t* __restrict__ stale) {
   const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (g >= ng) return;
   const double4 lo = clo[g], hi = chi[g];
-  const int k = root[seg[g_begin[g]]].k;
   bool bad = false;
   for (uint64_t j0 = spj_off[g], e = spj_off[g + 1]; j0 < e; j0 += 64) {
     const uint64_t j = j0 + lane;
@@ -207,7 +247,7 @@ k_check_lists(int64_t ng, const uint32_t* __restrict__ g_begin,
     if (j < e) {
       const uint32_t c = spj[j];
       const double4 cc = ctr[c];
-      const int level = (int)(rec[c].meta.w & 255u);
+      const double r = __ddiv_rn(shift[c].w, th);
       double dx = 0.0, dy = 0.0, dz = 0.0, t;
       t = __dsub_rn(lo.x, cc.x);
       if (t > dx) dx = t;
@@ -223,7 +263,7 @@ k_check_lists(int64_t ng, const uint32_t* __restrict__ g_begin,
       if (t > dz) dz = t;
       const double d2 = __dadd_rn(
           __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-      b = !(d2 > ldexp(rr, 2 * (k - level)));
+      b = !(d2 > __dmul_rn(r, r));
     }
     if (__ballot(b)) {
       bad = true;
@@ -491,6 +531,8 @@ int learn_reserve_cells(nb_ctx* c) {
   const size_t nc = (size_t)c->n_cell;
   int rc = reserve(c, c->c_com, nc);
   if (!rc) rc = reserve(c, c->c_com0, nc);
+  if (!rc) rc = reserve(c, c->c_bmin, nc);
+  if (!rc) rc = reserve(c, c->c_bmax, nc);
   if (!rc) rc = reserve(c, c->c_shift, nc);
   if (!rc) rc = reserve(c, c->c_ctr, nc);
   return rc;
@@ -526,14 +568,15 @@ int launch_com(nb_ctx* c) {
                        dim3(256), 0, c->stream, c->n_leaves,
                        (const uint32_t*)c->lvl_cells.p + c->lvl_off[kLevels],
                        (const CellRec*)c->c_rec.p, (const double4*)c->pos.p,
-                       c->c_com.p);
+                       c->c_com.p, c->c_bmin.p, c->c_bmax.p);
   for (int l = kMaxLevel - 1; l >= 0; --l) {
     const int64_t cnt = c->lvl_count[l];
     if (cnt == 0) continue;
     hipLaunchKernelGGL(k_com_internal, dim3(grid_for(cnt, 256)), dim3(256), 0,
                        c->stream, cnt,
                        (const uint32_t*)c->lvl_cells.p + c->lvl_off[l],
-                       (const CellRec*)c->c_rec.p, c->c_com.p);
+                       (const CellRec*)c->c_rec.p, c->c_com.p, c->c_bmin.p,
+                       c->c_bmax.p);
   }
   rc = hip_check(c, hipGetLastError(), "centre-of-mass launch");
   if (rc) return rc;
@@ -547,7 +590,9 @@ int launch_com(nb_ctx* c) {
   hipLaunchKernelGGL(k_shift, dim3(grid_for(c->n_cell, 256)), dim3(256), 0,
                      c->stream, c->n_cell, (const CellRec*)c->c_rec.p,
                      (const double4*)c->c_com.p, (const double4*)c->c_com0.p,
-                     c->c_shift.p, c->c_ctr.p);
+                     (const double4*)c->c_bmin.p, (const double4*)c->c_bmax.p,
+                     (const Root*)c->root.p, (const uint32_t*)c->seg.p,
+                     c->cfg.theta, c->c_shift.p, c->c_ctr.p);
   return hip_check(c, hipGetLastError(), "shift launch");
 }
 
@@ -585,15 +630,12 @@ int launch_stale(nb_ctx* c, double tau) {
   int rc = launch_group_box(c, c->g_clo.p, c->g_chi.p);
   if (rc) return rc;
   const double th = c->cfg.theta * (1.0 + tau);
-  const double r1 = 1.0 / th;
-  const double rr = r1 * r1;
   hipLaunchKernelGGL(k_check_lists, dim3(grid_for(c->n_groups, 4)),
                      dim3(256), 0, c->stream, c->n_groups,
-                     (const uint32_t*)c->g_begin.p, (const double4*)c->g_clo.p,
-                     (const double4*)c->g_chi.p, (const CellRec*)c->c_rec.p,
-                     (const double4*)c->c_ctr.p, (const Root*)c->root.p,
-                     (const uint32_t*)c->seg.p, (const uint64_t*)c->spj_off.p,
-                     (const uint32_t*)c->spj.p, rr, c->stale.p);
+                     (const double4*)c->g_clo.p, (const double4*)c->g_chi.p,
+                     (const double4*)c->c_ctr.p, (const double4*)c->c_shift.p,
+                     (const uint64_t*)c->spj_off.p, (const uint32_t*)c->spj.p,
+                     th, c->stale.p);
   return hip_check(c, hipGetLastError(), "list check launch");
 }
 
@@ -917,6 +959,17 @@ int nb_get_group_state(nb_ctx* c, double* sa, double* so, int32_t* age) {
     for (size_t g = 0; !rc && g < ng; ++g)
       age[g] = (int32_t)(h[g] > 0x7FFFFFFFu ? 0x7FFFFFFFu : h[g]);
   }
+  return rc;
+}
+
+int nb_get_cell_sides(nb_ctx* c, double* side) {
+  if (!c || !side) return NB_ERR_INPUT;
+  if (!c->learn || !c->tree_valid || !c->shift_fresh)
+    return set_err(c, NB_ERR_STATE,
+                   "needs NB_FLAG_REFRESH and moments of the current positions");
+  std::vector<double4> h((size_t)c->n_cell);
+  int rc = copy_out(c, h.data(), c->c_shift.p, h.size() * sizeof(double4), 0);
+  for (size_t i = 0; !rc && i < h.size(); ++i) side[i] = h[i].w;
   return rc;
 }
 

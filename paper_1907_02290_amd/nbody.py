@@ -103,6 +103,7 @@ def load():
         "nb_group_stale": ([p, d, p, p, i32], i32),
         "nb_refresh_lists": ([p, i64, p], i32),
         "nb_get_group_state": ([p, p, p, p], i32),
+        "nb_get_cell_sides": ([p, p], i32),
         "nb_mlp_set": ([p, p, i64], i32),
         "nb_mlp_get": ([p, p, i64], i32),
         "nb_mlp_forward": ([p, i64, p, p, i32], i32),
@@ -370,6 +371,12 @@ class Context:
         self._chk(self._lib.nb_get_group_state(self._h, _ptr(sa), _ptr(so),
                                                _ptr(age)))
         return sa, so, age
+
+    def cell_sides(self):
+        nc = self.get_info()["n_cell"]
+        out = np.zeros(nc)
+        self._chk(self._lib.nb_get_cell_sides(self._h, _ptr(out)))
+        return out
 
     def mlp_set(self, w):
         w = np.ascontiguousarray(w, dtype=np.float32)

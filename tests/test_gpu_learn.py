@@ -110,6 +110,7 @@ def test_refresh_mode_keeps_construction_lists(kind, n):
         compare_slacks(ctx, t, cell_side(t, g, c))
         _, _, age = ctx.group_state()
         assert np.all(age == 0)
+        np.testing.assert_array_equal(ctx.cell_sides(), t.cell_sides())
 
 
 @pytest.mark.parametrize("n_grp,steps", [(64, 2), (16, 3)])
@@ -129,6 +130,11 @@ def test_stale_features_refresh_match_oracle(n_grp, steps):
         g, c = ctx.get_groups(), ctx.get_cells()
         side = cell_side(t, g, c)
         ng = t.n_groups
+        osides = t.cell_sides()
+        np.testing.assert_allclose(ctx.cell_sides(), osides, rtol=1e-12)
+        geo = 2.0 ** (t.k - c["level"].astype(float))
+        say("  cells wider than their cube: %d / %d" % ((osides > geo).sum(),
+                                                        t.n_cell))
         # stale flags
         for tau in (0.0, 0.05, 0.1):
             st = ctx.group_stale(tau)

@@ -120,7 +120,21 @@ def _children(c):
     return kids
 
 
-def _brute_walk(t, c, kids, shift, gb, gn, lo, hi, theta):
+def _sides(t, c, shift, pos):
+    """Brute-force opening-test sides: max(geometric side, twice the largest
+    per-axis distance from the moved centre to a member particle)."""
+    key, perm = t.keys()
+    p = np.stack([a[perm] for a in pos], axis=1)   # sorted order
+    out = np.empty(t.n_cell)
+    for cc in range(t.n_cell):
+        b, n = int(c["begin"][cc]), int(c["count"][cc])
+        ctr = c["ctr"][cc] + shift[cc]
+        h = np.abs(p[b:b + n] - ctr).max()
+        out[cc] = max(2.0 ** (t.k - int(c["level"][cc])), 2.0 * h)
+    return out
+
+
+def _brute_walk(t, c, kids, shift, gb, gn, lo, hi, theta, sides=None):
     """Recursive walk (an independent restatement of the stackless one):
     returns EPJ ids, SPJ ids and the two opening-test slacks."""
     epj, spj, sa, so = [], [], [np.inf], [np.inf]
@@ -128,7 +142,8 @@ def _brute_walk(t, c, kids, shift, gb, gn, lo, hi, theta):
     def visit(cc):
         cb, cn = int(c["begin"][cc]), int(c["count"][cc])
         if not (cb <= gb and cb + cn >= gb + gn):
-            side = 2.0 ** (t.k - int(c["level"][cc]))
+            side = (2.0 ** (t.k - int(c["level"][cc])) if sides is None
+                    else sides[cc])
             ctr = c["ctr"][cc] + shift[cc]
             d = np.maximum(0.0, np.maximum(lo - ctr, ctr - hi))
             dist = float(np.sqrt(d @ d))
@@ -176,6 +191,21 @@ def test_slacks_against_brute_force(orc):
         assert sa[gi] > 0.0 and so[gi] >= 0.0
 
 
+def test_cell_sides_are_geometric_until_particles_spread(orc):
+    _, (x, y, z, m), t = _setup(orc)
+    c = t.cells()
+    geo = 2.0 ** (t.k - c["level"].astype(float))
+    np.testing.assert_array_equal(t.cell_sides(), geo)
+    # a rigid shift keeps every cell's particles about its moved centre
+    t.refresh(x + 0.5, y - 0.25, z + 0.125, m)
+    np.testing.assert_allclose(t.cell_sides(), geo, rtol=1e-12)
+    # stretching by 3 along x: the top cell's particles reach 3x as far
+    t.refresh(3.0 * x, y, z, m)
+    s = t.cells()
+    sides = t.cell_sides()
+    assert sides[0] > geo[0]
+
+
 def test_unmoved_particles_are_not_stale(orc):
     _, (x, y, z, m), t = _setup(orc)
     t.refresh(x, y, z, m)
@@ -213,11 +243,11 @@ def test_rigid_motion_changes_no_list(orc):
                                rtol=1e-12)
 
 
-def _violations(t, kids_unused, shift, lo, hi, theta, tau, eo_so):
+def _violations(t, sides, shift, lo, hi, theta, tau, eo_so):
     """Direct check of every kept superparticle (vectorised restatement)."""
     c = t.cells()
     _, so, s = eo_so
-    side = 2.0 ** (t.k - c["level"].astype(float))
+    side = sides
     r2 = (side / (theta * (1.0 + tau))) ** 2
     ctr = c["ctr"] + shift
     out = np.zeros(t.n_groups, bool)
@@ -243,6 +273,10 @@ def test_stale_and_refresh_against_brute_force(orc):
     _, com, _ = t.moments()
     shift = com - com0
     key, perm = t.keys()
+    sides = _sides(t, c, shift, (xn, yn, zn))
+    np.testing.assert_allclose(t.cell_sides(), sides, rtol=1e-13)
+    geo = 2.0 ** (t.k - c["level"].astype(float))
+    assert np.all(sides >= geo) and np.any(sides > geo)
     st, lo, hi = t.stale(theta)
     st1, _, _ = t.stale(theta, 0.1)
     assert st.any() and not st.all()
@@ -250,9 +284,9 @@ def test_stale_and_refresh_against_brute_force(orc):
     assert not np.any(st1 & ~st)               # monotone in tau
     assert not t.stale(theta, 1e6)[0].any()
     np.testing.assert_array_equal(
-        st, _violations(t, kids, shift, lo, hi, theta, 0.0, (eo0, so0, s0)))
+        st, _violations(t, sides, shift, lo, hi, theta, 0.0, (eo0, so0, s0)))
     np.testing.assert_array_equal(
-        st1, _violations(t, kids, shift, lo, hi, theta, 0.1, (eo0, so0, s0)))
+        st1, _violations(t, sides, shift, lo, hi, theta, 0.1, (eo0, so0, s0)))
     walked = {}
     for gi in range(t.n_groups):
         b, cnt = int(g["begin"][gi]), int(g["count"][gi])
@@ -261,7 +295,7 @@ def test_stale_and_refresh_against_brute_force(orc):
                                                yn[members].min(),
                                                zn[members].min()])
         pe, ps, a, o = _brute_walk(t, c, kids, shift, b, cnt, lo[gi], hi[gi],
-                                   theta)
+                                   theta, sides)
         walked[gi] = (pe, ps, a, o)
         same = (pe == e0[eo0[gi]:eo0[gi + 1]].tolist() and
                 ps == s0[so0[gi]:so0[gi + 1]].tolist())
