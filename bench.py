@@ -109,7 +109,8 @@ def main():
         % (args.workload, n, p["theta"], p["eps"], n_leaf, n_grp, reuse))
 
     torch.cuda.set_device(0)
-    dev = {k: torch.from_numpy(v).cuda() for k, v in d.items()}
+    dev = {k: torch.from_numpy(d[k]).cuda()
+           for k in ("x", "y", "z", "vx", "vy", "vz", "m")}
     ctx = nb.Context(theta=p["theta"], eps=p["eps"], n_leaf=n_leaf,
                      n_grp=n_grp, order=p["order"],
                      ext_mass=p.get("ext_mass", 0.0), timing=True,

@@ -25,8 +25,12 @@ namespace nb {
 namespace {
 
 constexpr int kWalkThreads = 256;
-// launches with fewer groups than this walk one group per wavefront
-constexpr int64_t kWaveWalkBelow = 1 << 30;
+// launches with fewer groups than this walk one group per wavefront (on
+// MI355X the one-thread walk of a 2^22-particle disk, 56k groups, takes
+// 3.4 ms and the wave walk 27 ms; with 1.8k groups 4.4 ms against 0.85 ms:
+// the wave walk costs about 0.5 us per group, the thread walk a few ms
+// whatever the count)
+constexpr int64_t kWaveWalkBelow = 8192;
 
 __device__ inline int64_t xcd_block(int64_t nblk) {
   const int64_t per = (nblk + 7) / 8;
