@@ -233,31 +233,51 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
     return set_err(c, NB_ERR_STATE, "lists need a tree of the current positions");
   int rc;
   c->lists_valid = c->lists_reusable = false;
-  {
+  // one pass (counts and tokens into per-group slabs sized from the last
+  // construction) when the one-thread walk runs and the slabs fit in a
+  // bounded buffer; otherwise, or when a group overflows its slab, a count
+  // pass and an exact fill pass
+  const uint32_t slab = c->tok_slab;
+  const bool one_pass = slab > 0 && !walk_uses_waves(c->n_groups) &&
+                        (uint64_t)c->n_groups * slab < (1ull << 31);
+  if (one_pass) {
+    Timed t(c, NB_PH_WALK);
+    if ((rc = reserve(c, c->tok, (size_t)c->n_groups * slab))) return rc;
+    if ((rc = launch_walk(c, true, slab))) return rc;
+    if ((rc = launch_list_stats(c))) return rc;
+  } else {
     Timed t(c, NB_PH_WALK);
     if ((rc = launch_walk(c, false))) return rc;
     if ((rc = launch_list_stats(c))) return rc;
   }
-  // sync 3: list totals, interaction count, force work items
+  // sync 3: list totals, interaction count, force work items, largest
+  // token count
   if ((rc = stage_d2h(c, 0, c->epj_off.p + c->n_groups, 8))) return rc;
   if ((rc = stage_d2h(c, 8, c->spj_off.p + c->n_groups, 8))) return rc;
-  if ((rc = stage_d2h(c, 16, c->red.p, 8))) return rc;
-  if ((rc = stage_d2h(c, 24, c->tok_off.p + c->n_groups, 8))) return rc;
-  if ((rc = stage_d2h(c, 32, c->g_chunks.p + c->n_groups, 4))) return rc;
+  if ((rc = stage_d2h(c, 16, c->red.p, 16))) return rc;
+  if ((rc = stage_d2h(c, 32, c->tok_off.p + c->n_groups, 8))) return rc;
+  if ((rc = stage_d2h(c, 40, c->g_chunks.p + c->n_groups, 4))) return rc;
   if ((rc = sync(c))) return rc;
-  int64_t n_tok;
+  int64_t n_tok, max_tok;
   {
     const uint64_t* h = static_cast<const uint64_t*>(c->h_small);
     c->n_epj = (int64_t)h[0];
     c->n_spj = (int64_t)h[1];
     c->n_inter = (int64_t)h[2];
-    n_tok = (int64_t)h[3];
-    c->n_wi = static_cast<const uint32_t*>(c->h_small)[8];
+    max_tok = (int64_t)h[3];
+    n_tok = (int64_t)h[4];
+    c->n_wi = static_cast<const uint32_t*>(c->h_small)[10];
   }
+  // slab for the next construction: 1.25 x the largest list, 16-aligned
+  c->tok_slab = (uint32_t)std::min<int64_t>(
+      (max_tok + max_tok / 4 + 16 + 15) / 16 * 16, 1 << 24);
   if ((rc = reserve(c, c->epj, (size_t)c->n_epj + 1))) return rc;
   if ((rc = reserve(c, c->spj, (size_t)c->n_spj + 1))) return rc;
-  if ((rc = reserve(c, c->tok, (size_t)n_tok + 1))) return rc;
-  {
+  if (one_pass && max_tok <= (int64_t)slab) {
+    Timed t(c, NB_PH_WALK);
+    if ((rc = launch_expand_slab(c, slab))) return rc;
+  } else {
+    if ((rc = reserve(c, c->tok, (size_t)n_tok + 1))) return rc;
     Timed t(c, NB_PH_WALK);
     if ((rc = launch_walk(c, true))) return rc;
   }

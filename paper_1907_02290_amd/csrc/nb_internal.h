@@ -65,6 +65,9 @@ struct nb_ctx {
   std::vector<int64_t> h_sys_off;
   std::vector<int4> h_bbox_chunks;  // system, begin, end, first partial
   int64_t n_epj = 0, n_spj = 0, n_inter = 0;
+  // token slots per group of the one-pass walk (0: count pass first); set
+  // from the largest token count of the previous construction
+  uint32_t tok_slab = 0;
   int64_t force_evals = 0, total_inter = 0;
   int32_t k = 0;
   // internal cells per level and where each level starts in lvl_cells;
@@ -232,11 +235,13 @@ int launch_seg_fill(nb_ctx* c);
 int launch_group_fill(nb_ctx* c);
 int launch_group_box(nb_ctx* c, double4* lo, double4* hi);
 // nb_walk.hip
-int launch_walk(nb_ctx* c, bool fill);
+int launch_walk(nb_ctx* c, bool fill, uint32_t slab = 0);
 int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                     const double4* lo, const double4* hi,
                     const uint64_t* epj_off, const uint64_t* spj_off,
-                    uint32_t* epj, uint32_t* spj);
+                    uint32_t* epj, uint32_t* spj, uint32_t slab = 0);
+int launch_expand_slab(nb_ctx* c, uint32_t slab);
+bool walk_uses_waves(int64_t n_walk);
 int launch_list_stats(nb_ctx* c);
 int launch_interactions(nb_ctx* c, const uint32_t* ne, const uint32_t* ns);
 // nb_learn.hip

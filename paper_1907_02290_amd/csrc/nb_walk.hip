@@ -59,7 +59,7 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
        const uint32_t* __restrict__ seg, const uint32_t* __restrict__ croot,
        uint32_t* __restrict__ cnt_e, uint32_t* __restrict__ cnt_s,
        uint32_t* __restrict__ cnt_t, const uint64_t* __restrict__ tok_off,
-       uint32_t* __restrict__ tok) {
+       uint32_t* __restrict__ tok, uint32_t slab) {
   // per-lane staging of the token stream: a lane writes its tokens out one
   // aligned 64-byte segment at a time, so that partially written lines do
   // not pile up in L2 (one open line per group otherwise)
@@ -74,11 +74,17 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   const double4 lo = g_lo[g], hi = g_hi[g];
   uint32_t* dst = nullptr;
   uint64_t out = 0;   // next output slot of this lane
+  uint64_t end = 0;   // slab mode: end of this group's slab
   int sc = 0;         // staged tokens
   if (FILL) {
-    out = tok_off[t];
+    // slab mode (slab > 0): counts and tokens in one pass, the tokens into a
+    // fixed slab of `slab` slots per group (a multiple of 16); tokens past
+    // the slab are dropped and the caller sees the overflow in the counts
+    out = slab ? (uint64_t)t * slab : tok_off[t];
+    end = slab ? out + slab : ~0ull;
     dst = tok;
   }
+  const bool counts = !FILL || slab != 0;
   double sa = __builtin_inf(), so = __builtin_inf();
   uint32_t ne = 0, ns = 0, nl = 0;
   // the walk covers the cells of the group's own system
@@ -109,7 +115,7 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
           __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
                     __dmul_rn(dz, dz));
       open = !(d2 > cc.w);
-      if (LEARN && !FILL) {
+      if (LEARN && counts) {
         const double dd = __dsqrt_rn(d2), rr = __dsqrt_rn(cc.w);
         if (open) {
           const double v = __dsub_rn(rr, dd);
@@ -136,7 +142,9 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
         stage[sc][threadIdx.x] = open ? (c | kLeafTag) : c;
         ++sc;
         if (((out + sc) & (kSeg - 1)) == 0) {
-          if (sc == kSeg) {
+          if (out + sc > end) {
+            // past the slab: drop
+          } else if (sc == kSeg) {
             uint4* d4 = reinterpret_cast<uint4*>(dst + out);
 #pragma unroll
             for (int q = 0; q < kSeg / 4; ++q)
@@ -154,9 +162,10 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
     }
     c = next;
   }
-  if (FILL) {
+  if (FILL && out + sc <= end) {
     for (int q = 0; q < sc; ++q) dst[out + q] = stage[q][threadIdx.x];
-  } else {
+  }
+  if (counts) {
     cnt_e[t] = ne;
     cnt_s[t] = ns;
     cnt_t[t] = ns + nl;
@@ -309,7 +318,8 @@ k_walk_wave(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
 // (sel[t], or t when sel is NULL).
 __global__ void __launch_bounds__(256)
 k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
-         const uint64_t* __restrict__ tok_off,
+         const uint64_t* __restrict__ tok_off, uint32_t slab,
+         const uint32_t* __restrict__ cnt_t,
          const uint32_t* __restrict__ tok, const CellRec* __restrict__ rec,
          const uint64_t* __restrict__ epj_off,
          const uint64_t* __restrict__ spj_off, uint32_t* __restrict__ epj,
@@ -320,7 +330,8 @@ k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   const int lane = threadIdx.x & 63;
   if (t >= n_walk) return;
   const int64_t g = sel ? (int64_t)sel[t] : t;
-  const uint64_t t0 = tok_off[t], t1 = tok_off[t + 1];
+  const uint64_t t0 = slab ? (uint64_t)t * slab : tok_off[t];
+  const uint64_t t1 = slab ? t0 + cnt_t[t] : tok_off[t + 1];
   uint64_t oe = epj_off[g], os = spj_off[g];
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   for (uint64_t cb = t0; cb < t1; cb += 64) {
@@ -370,13 +381,29 @@ k_interactions(int64_t n_groups, const uint32_t* __restrict__ g_count,
   if (threadIdx.x == 0) atomicAdd(out, s[0] + s[1] + s[2] + s[3]);
 }
 
+// Largest per-group token count into *out (zeroed before).
+__global__ void __launch_bounds__(256)
+k_max_u32(int64_t n, const uint32_t* __restrict__ v,
+          unsigned long long* __restrict__ out) {
+  unsigned long long m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = v[i] > m ? v[i] : m;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long u = __shfl_xor(m, o, 64);
+    m = u > m ? u : m;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int n) {
   if (threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
 }  // namespace
 
-int launch_walk(nb_ctx* c, bool fill) {
+int launch_walk(nb_ctx* c, bool fill, uint32_t slab) {
   const size_t ng = (size_t)c->n_groups;
   int rc = reserve(c, c->cnt_e, ng);
   if (!rc) rc = reserve(c, c->cnt_s, ng);
@@ -386,13 +413,30 @@ int launch_walk(nb_ctx* c, bool fill) {
   if (!rc) rc = reserve(c, c->tok_off, ng + 1);
   if (rc) return rc;
   return launch_walk_sel(c, fill, c->n_groups, nullptr, c->g_lo.p, c->g_hi.p,
-                         c->epj_off.p, c->spj_off.p, c->epj.p, c->spj.p);
+                         c->epj_off.p, c->spj_off.p, c->epj.p, c->spj.p,
+                         slab);
 }
+
+// Expand of a slab-mode fill pass (tokens at group * slab, counts known).
+int launch_expand_slab(nb_ctx* c, uint32_t slab) {
+  const int64_t eblk = grid_for(c->n_groups, 4);
+  const int64_t elaunch = (eblk + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_expand, dim3((unsigned)elaunch), dim3(256), 0,
+                     c->stream, c->n_groups, eblk, (const uint32_t*)nullptr,
+                     (const uint64_t*)c->tok_off.p, slab,
+                     (const uint32_t*)c->cnt_t.p, (const uint32_t*)c->tok.p,
+                     (const CellRec*)c->c_rec.p,
+                     (const uint64_t*)c->epj_off.p,
+                     (const uint64_t*)c->spj_off.p, c->epj.p, c->spj.p);
+  return hip_check(c, hipGetLastError(), "expand launch");
+}
+
+bool walk_uses_waves(int64_t n_walk) { return n_walk < kWaveWalkBelow; }
 
 int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                     const double4* lo, const double4* hi,
                     const uint64_t* epj_off, const uint64_t* spj_off,
-                    uint32_t* epj, uint32_t* spj) {
+                    uint32_t* epj, uint32_t* spj, uint32_t slab) {
   if (c->n_cell >= (int64_t)kLeafTag)
     return set_err(c, NB_ERR_INPUT, "too many cells for 31-bit list tokens");
   if (n_walk <= 0) return NB_OK;
@@ -401,32 +445,48 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
   // one thread per group fills the device only with many groups; below
   // that, one wave per group
   const bool wave = n_walk < kWaveWalkBelow;
+  if (wave && slab)
+    return set_err(c, NB_ERR_STATE, "slab mode needs the one-thread walk");
   const int64_t nblk = wave ? grid_for(n_walk, 4)
                             : grid_for(n_walk, kWalkThreads);
   const int64_t launch = (nblk + 7) / 8 * 8;
-  auto k = wave ? (fill ? (learn ? k_walk_wave<true, true>
-                                 : k_walk_wave<true, false>)
-                        : (learn ? k_walk_wave<false, true>
-                                 : k_walk_wave<false, false>))
-                : (fill ? (learn ? k_walk<true, true> : k_walk<true, false>)
-                        : (learn ? k_walk<false, true> : k_walk<false, false>));
-  hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
-                     c->stream, n_walk, nblk, sel,
-                     (const uint32_t*)c->g_begin.p,
-                     (const uint32_t*)c->g_count.p, lo, hi,
-                     (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
-                     (const uint32_t*)c->g_cell.p,
-                     (const double4*)c->c_shift.p, c->g_sa.p, c->g_so.p,
-                     c->g_tau0.p, (const uint32_t*)c->seg.p,
-                     (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
-                     c->cnt_t.p, (const uint64_t*)c->tok_off.p, c->tok.p);
+  if (wave) {
+    auto k = fill ? (learn ? k_walk_wave<true, true> : k_walk_wave<true, false>)
+                  : (learn ? k_walk_wave<false, true>
+                           : k_walk_wave<false, false>);
+    hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
+                       c->stream, n_walk, nblk, sel,
+                       (const uint32_t*)c->g_begin.p,
+                       (const uint32_t*)c->g_count.p, lo, hi,
+                       (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
+                       (const uint32_t*)c->g_cell.p,
+                       (const double4*)c->c_shift.p, c->g_sa.p, c->g_so.p,
+                       c->g_tau0.p, (const uint32_t*)c->seg.p,
+                       (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
+                       c->cnt_t.p, (const uint64_t*)c->tok_off.p, c->tok.p);
+  } else {
+    auto k = fill ? (learn ? k_walk<true, true> : k_walk<true, false>)
+                  : (learn ? k_walk<false, true> : k_walk<false, false>);
+    hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
+                       c->stream, n_walk, nblk, sel,
+                       (const uint32_t*)c->g_begin.p,
+                       (const uint32_t*)c->g_count.p, lo, hi,
+                       (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
+                       (const uint32_t*)c->g_cell.p,
+                       (const double4*)c->c_shift.p, c->g_sa.p, c->g_so.p,
+                       c->g_tau0.p, (const uint32_t*)c->seg.p,
+                       (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
+                       c->cnt_t.p, (const uint64_t*)c->tok_off.p, c->tok.p,
+                       slab);
+  }
   int rc2 = hip_check(c, hipGetLastError(), "walk launch");
-  if (rc2 || !fill) return rc2;
+  if (rc2 || !fill || slab) return rc2;
   const int64_t eblk = grid_for(n_walk, 4);
   const int64_t elaunch = (eblk + 7) / 8 * 8;
   hipLaunchKernelGGL(k_expand, dim3((unsigned)elaunch), dim3(256), 0,
                      c->stream, n_walk, eblk, sel,
-                     (const uint64_t*)c->tok_off.p,
+                     (const uint64_t*)c->tok_off.p, 0u,
+                     (const uint32_t*)c->cnt_t.p,
                      (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
                      epj_off, spj_off, epj, spj);
   return hip_check(c, hipGetLastError(), "expand launch");
@@ -438,7 +498,13 @@ int launch_list_stats(nb_ctx* c) {
   if (!rc) rc = scan_u32_to_u64(c, c->cnt_s.p, c->spj_off.p, c->n_groups);
   if (!rc) rc = scan_u32_to_u64(c, c->cnt_t.p, c->tok_off.p, c->n_groups);
   if (!rc) rc = launch_interactions(c, c->cnt_e.p, c->cnt_s.p);
-  return rc;
+  if (rc) return rc;
+  unsigned nb = grid_for(c->n_groups, 256);
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(k_max_u32, dim3(nb), dim3(256), 0, c->stream,
+                     c->n_groups, (const uint32_t*)c->cnt_t.p,
+                     (unsigned long long*)c->red.p + 1);
+  return hip_check(c, hipGetLastError(), "list max launch");
 }
 
 // Interaction count of per-group list lengths ne, ns into red[0].
@@ -446,7 +512,7 @@ int launch_interactions(nb_ctx* c, const uint32_t* ne, const uint32_t* ns) {
   int rc = reserve(c, c->red, 16);
   if (rc) return rc;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream,
-                     (unsigned long long*)c->red.p, 8);
+                     (unsigned long long*)c->red.p, 2);
   unsigned nb = grid_for(c->n_groups, 256);
   if (nb > 1024) nb = 1024;
   hipLaunchKernelGGL(k_interactions, dim3(nb), dim3(256), 0, c->stream,

@@ -384,3 +384,34 @@ def test_full_size_sampled(name, order, sample):
         ref = t.force_lists(order, p["eps"], 1.0)
         mask = np.isfinite(ref[0])
         check_forces(ctx.get_forces(), ref, mask, what=name)
+
+
+def test_one_pass_walk_and_overflow_fallback():
+    """From the second construction on, lists come from one walk into
+    per-group slabs sized from the previous construction; a group that
+    outgrows its slab sends the step back to a count pass and an exact
+    fill.  Both give the oracle's lists."""
+    say("case one-pass walk")
+    d = system("plummer", 1 << 18, seed=3)
+    dt = 1 / 64
+    t0 = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 16)
+    _, perm0 = t0.keys()
+    with gpu_ctx(d, theta=0.6, n_grp=16) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        assert ctx.get_info()["n_groups"] >= 8192
+        ctx.kick_drift(0.0, dt)
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)  # one pass
+        xs = _drift(d, dt, 1)
+        x1 = [a[perm0] for a in xs]
+        t1 = oracle.Tree(*x1, d["m"][perm0], 8, 16)
+        t1.make_lists(0.6)
+        compare_tree(ctx, t1, prev_orig=perm0)
+        compare_lists(ctx, t1)
+        # longer lists than the slabs were sized for: fallback
+        _, perm1 = t1.keys()
+        ctx.set_config(theta=0.35)
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        x2 = [a[perm1] for a in x1]
+        t2 = oracle.Tree(*x2, d["m"][perm0][perm1], 8, 16)
+        t2.make_lists(0.35)
+        compare_lists(ctx, t2)
