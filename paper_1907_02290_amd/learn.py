@@ -244,7 +244,7 @@ def run_policy(ctx, policy, steps, dt, k, tau, measure=True, ref=None,
 
 def evaluate(workload="disk_4m", n=1 << 18, tau=0.1, k_tree=16,
              collect_cycles=3, recall=0.98, epochs=30, batch=8192, lr=2e-3,
-             steps=64, fixed=(1, 2, 4, 8, 16), log=print):
+             steps=64, fixed=(1, 2, 4, 8, 16), k_trees=None, log=print):
     """Train the predictor on one realisation of a workload (seed 0) and
     compare the reuse policies on another (seed 1).  Returns a list of
     result dicts: the training summary, then one per policy."""
@@ -283,8 +283,9 @@ def evaluate(workload="disk_4m", n=1 << 18, tau=0.1, k_tree=16,
                    train_s=t_train, validation=stats)
     log(summary)
     out.append(summary)
-    runs = [("fixed", k) for k in fixed] + [("checked", k_tree),
-                                            ("learned", k_tree)]
+    runs = [("fixed", k) for k in fixed]
+    for kt in (k_trees or (k_tree,)):
+        runs += [("checked", kt), ("learned", kt)]
     ref = Reference(p["eps"], ext_mass=p.get("ext_mass", 0.0),
                     offsets=d1.get("offsets"))
     for policy, k in runs:
@@ -318,9 +319,13 @@ def main(argv=None):
     ap.add_argument("--recall", type=float, default=0.98)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--k-trees", default=None,
+                    help="comma list of construction intervals for the "
+                         "refresh policies (default: --k-tree)")
     a = ap.parse_args(argv)
+    kts = tuple(int(v) for v in a.k_trees.split(",")) if a.k_trees else None
     res = evaluate(a.workload, a.n, a.tau, a.k_tree, a.cycles, a.recall,
-                   a.epochs, steps=a.steps,
+                   a.epochs, steps=a.steps, k_trees=kts,
                    log=lambda r: print(json.dumps(r), file=sys.stderr,
                                        flush=True))
     for r in res:
