@@ -244,7 +244,8 @@ def run_policy(ctx, policy, steps, dt, k, tau, measure=True, ref=None,
 
 def evaluate(workload="disk_4m", n=1 << 18, tau=0.1, k_tree=16,
              collect_cycles=3, recall=0.98, epochs=30, batch=8192, lr=2e-3,
-             steps=64, fixed=(1, 2, 4, 8, 16), k_trees=None, log=print):
+             steps=64, fixed=(1, 2, 4, 8, 16), k_trees=None,
+             fixed_thetas=(), log=print):
     """Train the predictor on one realisation of a workload (seed 0) and
     compare the reuse policies on another (seed 1).  Returns a list of
     result dicts: the training summary, then one per policy."""
@@ -283,19 +284,23 @@ def evaluate(workload="disk_4m", n=1 << 18, tau=0.1, k_tree=16,
                    train_s=t_train, validation=stats)
     log(summary)
     out.append(summary)
-    runs = [("fixed", k) for k in fixed]
+    # fixed intervals at the workload's theta and at smaller angles (the
+    # equal-error comparison), then the refresh policies
+    runs = [("fixed", k, p["theta"]) for k in fixed]
+    runs += [("fixed", k, th) for th in fixed_thetas for k in (2, 4, 8)]
     for kt in (k_trees or (k_tree,)):
-        runs += [("checked", kt), ("learned", kt)]
+        runs += [("checked", kt, p["theta"]), ("learned", kt, p["theta"])]
     ref = Reference(p["eps"], ext_mass=p.get("ext_mass", 0.0),
                     offsets=d1.get("offsets"))
-    for policy, k in runs:
+    for policy, k, th in runs:
+        cfg = dict(common, theta=th)
         with make_context(d1, k_max=k_tree, p_star=min(1.0, max(0.0, p_star)),
-                          offsets=d1.get("offsets"), **common) as ctx:
+                          offsets=d1.get("offsets"), **cfg) as ctx:
             ctx.mlp_set(w)
             r = run_policy(ctx, policy, steps, dt, k, tau, ref=ref,
                            m=d1["m"])
         r.update(kind="policy", workload=workload, n=int(d1["x"].size),
-                 tau=tau)
+                 tau=tau, theta=th)
         log(r)
         out.append(r)
     ref.close()
@@ -319,13 +324,17 @@ def main(argv=None):
     ap.add_argument("--recall", type=float, default=0.98)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--fixed-thetas", default="",
+                    help="comma list of smaller opening angles for extra "
+                         "fixed-interval runs (K = 2, 4, 8)")
     ap.add_argument("--k-trees", default=None,
                     help="comma list of construction intervals for the "
                          "refresh policies (default: --k-tree)")
     a = ap.parse_args(argv)
     kts = tuple(int(v) for v in a.k_trees.split(",")) if a.k_trees else None
+    fth = tuple(float(v) for v in a.fixed_thetas.split(",") if v)
     res = evaluate(a.workload, a.n, a.tau, a.k_tree, a.cycles, a.recall,
-                   a.epochs, steps=a.steps, k_trees=kts,
+                   a.epochs, steps=a.steps, k_trees=kts, fixed_thetas=fth,
                    log=lambda r: print(json.dumps(r), file=sys.stderr,
                                        flush=True))
     for r in res:
