@@ -647,7 +647,7 @@ int mlp_forward(nb_ctx* c, int64_t n, const float* x, float* p) {
 }
 
 // Gradient of the mean (weighted) cross-entropy over samples [0, n) of x, y
-// into c->mlp_g and the loss into c->mlp_loss (device).
+// into c->mlp_g[0, NP) and the loss into c->mlp_g[NP] (device).
 int mlp_grad(nb_ctx* c, int64_t n, const float* x, const float* y, float pw) {
   const int64_t nlp = grid_for(n, 256);
   const int64_t nch = (n + kChunk - 1) / kChunk;
