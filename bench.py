@@ -255,9 +255,10 @@ def main():
         cpu = {"value": ic / tc, "unit": "interactions/s",
                "cores": oracle.num_threads(), "kind": "oracle",
                "sample": "FP64 oracle walk + list-force sum over %d of %d "
-                         "groups (%d particles, %.3e interactions) of one "
-                         "construction step of the same workload; oracle "
-                         "tree build (%.1f s, all N) not counted"
+                         "groups (%d particles, %.3e interactions) of the "
+                         "construction step of the seeded initial state of "
+                         "the same workload; oracle tree build (%.1f s, all "
+                         "N) not counted"
                          % (sel.size, t.n_groups, int(gcount[sel].sum()),
                             ic, t_build),
                "seconds": tc}
