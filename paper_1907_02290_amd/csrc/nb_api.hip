@@ -234,11 +234,10 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
   int rc;
   c->lists_valid = c->lists_reusable = false;
   // one pass (counts and tokens into per-group slabs sized from the last
-  // construction) when the one-thread walk runs and the slabs fit in a
-  // bounded buffer; otherwise, or when a group overflows its slab, a count
-  // pass and an exact fill pass
+  // construction) when the slabs fit in a bounded buffer; otherwise, or when
+  // a group overflows its slab, a count pass and an exact fill pass
   const uint32_t slab = c->tok_slab;
-  const bool one_pass = slab > 0 && !walk_uses_waves(c->n_groups) &&
+  const bool one_pass = slab > 0 &&
                         (uint64_t)c->n_groups * slab < (1ull << 31);
   if (one_pass) {
     Timed t(c, NB_PH_WALK);

@@ -241,7 +241,7 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                     const uint64_t* epj_off, const uint64_t* spj_off,
                     uint32_t* epj, uint32_t* spj, uint32_t slab = 0);
 int launch_expand_slab(nb_ctx* c, uint32_t slab);
-bool walk_uses_waves(int64_t n_walk);
+int walk_tile(int64_t n_walk);  // lanes per group of the walk
 int launch_list_stats(nb_ctx* c);
 int launch_interactions(nb_ctx* c, const uint32_t* ne, const uint32_t* ns);
 // nb_learn.hip

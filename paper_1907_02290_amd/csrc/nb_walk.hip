@@ -25,12 +25,10 @@ namespace nb {
 namespace {
 
 constexpr int kWalkThreads = 256;
-// launches with fewer groups than this walk one group per wavefront (on
-// MI355X the one-thread walk of a 2^22-particle disk, 56k groups, takes
-// 3.4 ms and the wave walk 27 ms; with 1.8k groups 4.4 ms against 0.85 ms:
-// the wave walk costs about 0.5 us per group, the thread walk a few ms
-// whatever the count)
-constexpr int64_t kWaveWalkBelow = 8192;
+// Walk layout: kTileWalk = narrowest tile (1 = one thread per group), widened
+// until about kTileLanes lanes are in flight.
+constexpr int kTileWalk = 4;
+constexpr int64_t kTileLanes = 1 << 18;
 
 __device__ inline int64_t xcd_block(int64_t nblk) {
   const int64_t per = (nblk + 7) / 8;
@@ -177,19 +175,23 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   }
 }
 
-// Wave-cooperative walk: one wavefront per group, for launches with too
-// few groups to fill the device one thread per group.  The lanes take 64
+// Tile walk: W lanes per group (W = 4 .. 64, a power of two), for more
+// parallelism than one thread per group.  The lanes of a tile take W
 // consecutive cells of the pre-order array and evaluate the opening test of
 // each; a cell is one the stackless walk visits unless an earlier cell of
 // the window that ends the walk there (accepted, or an opened leaf) has a
 // subtree reaching past it -- an exclusive prefix maximum of those subtree
-// ends.  (Earlier windows cannot hide a cell: the window starts at a visited
-// cell, whose ancestors were all opened.)  The next window starts at the
-// later of the window's end and the farthest such subtree end.  Tokens come
-// out in pre-order, exactly as from the one-thread walk.
-template <bool FILL, bool LEARN>
+// ends over the tile.  (Earlier windows cannot hide a cell: the window
+// starts at a visited cell, whose ancestors were all opened.)  The next
+// window starts at the later of the window's end and the farthest such
+// subtree end.  Tokens come out in pre-order, exactly as from the
+// one-thread walk.  Small tiles waste little work on cells hidden inside a
+// window; large tiles give more lanes when there are few groups.
+// slab > 0 (fill pass only): counts and tokens in one pass, the tokens into
+// `slab` slots per group, as in the one-thread walk.
+template <int W, bool FILL, bool LEARN>
 __global__ void __launch_bounds__(256)
-k_walk_wave(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
+k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
             const uint32_t* __restrict__ g_begin,
             const uint32_t* __restrict__ g_count,
             const double4* __restrict__ g_lo, const double4* __restrict__ g_hi,
@@ -200,18 +202,28 @@ k_walk_wave(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
             const uint32_t* __restrict__ seg,
             const uint32_t* __restrict__ croot, uint32_t* __restrict__ cnt_e,
             uint32_t* __restrict__ cnt_s, uint32_t* __restrict__ cnt_t,
-            const uint64_t* __restrict__ tok_off, uint32_t* __restrict__ tok) {
+            const uint64_t* __restrict__ tok_off, uint32_t* __restrict__ tok,
+            uint32_t slab) {
+  static_assert(W >= 4 && W <= 64 && (W & (W - 1)) == 0, "tile width");
   const int64_t blk = xcd_block(nblk);
   if (blk >= nblk) return;
-  const int64_t t = blk * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (t >= n_walk) return;  // uniform over the wave
+  const int64_t t = blk * (256 / W) + (threadIdx.x / W);
+  const int lane = threadIdx.x & (W - 1);
+  if (t >= n_walk) return;  // uniform over the tile
   const int64_t g = (LEARN && sel) ? (int64_t)sel[t] : t;
   const uint32_t gb = g_begin[g];
   const uint32_t ge = gb + g_count[g];
   const double4 lo = g_lo[g], hi = g_hi[g];
-  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  uint64_t out = FILL ? tok_off[t] : 0;
+  // this tile's bits of a wave ballot, and the lanes below this one
+  const int base = (int)(threadIdx.x & 63) & ~(W - 1);
+  const uint64_t tmask = W == 64 ? ~0ull : ((1ull << W) - 1ull);
+  const uint64_t below = lane == 0 ? 0ull : ((1ull << lane) - 1ull);
+  uint64_t out = 0, end = ~0ull;
+  if (FILL) {
+    out = slab ? (uint64_t)t * slab : tok_off[t];
+    if (slab) end = out + slab;
+  }
+  const bool counts = !FILL || slab != 0;
   uint32_t ne = 0, ns = 0, nl = 0;  // per lane
   double sa = __builtin_inf(), so = __builtin_inf();
   const uint32_t sys = seg[gb];
@@ -253,16 +265,16 @@ k_walk_wave(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
     // exclusive prefix maximum of the subtree ends of stopping cells
     uint32_t incl = stop ? m.z : 0u;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t v = __shfl_up(incl, d, 64);
+    for (int d = 1; d < W; d <<= 1) {
+      const uint32_t v = __shfl_up(incl, d, W);
       if (lane >= d && v > incl) incl = v;
     }
-    uint32_t excl = __shfl_up(incl, 1, 64);
+    uint32_t excl = __shfl_up(incl, 1, W);
     if (lane == 0) excl = 0u;
     const bool visited = valid && !(excl > i);
     const bool acc = visited && !open;
     const bool lf = visited && open && stop;
-    if (LEARN && !FILL && visited && !holds) {
+    if (LEARN && counts && visited && !holds) {
       const double dd = __dsqrt_rn(d2), rr = __dsqrt_rn(rc2);
       if (open) {
         const double v = __dsub_rn(rr, dd);
@@ -272,29 +284,30 @@ k_walk_wave(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
         if (v < sa) sa = v;
       }
     }
-    if (FILL) {
-      const uint64_t me = __ballot(acc || lf);
-      if (acc || lf)
-        tok[out + __popcll(me & below)] = acc ? i : (i | kLeafTag);
-      out += __popcll(me);
-    } else {
+    if (counts) {
       ns += acc ? 1u : 0u;
       nl += lf ? 1u : 0u;
       ne += lf ? m.y - m.x : 0u;
     }
-    const uint32_t far = __shfl(incl, 63, 64);
-    const uint32_t next = c + 64u;
+    if (FILL) {
+      const uint64_t me = (__ballot(acc || lf) >> base) & tmask;
+      const uint64_t pos = out + (uint64_t)__popcll(me & below);
+      if ((acc || lf) && pos < end) tok[pos] = acc ? i : (i | kLeafTag);
+      out += (uint64_t)__popcll(me);
+    }
+    const uint32_t far = __shfl(incl, W - 1, W);
+    const uint32_t next = c + (uint32_t)W;
     c = far > next ? far : next;
   }
-  if (!FILL) {
+  if (counts) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      ne += __shfl_xor(ne, o, 64);
-      ns += __shfl_xor(ns, o, 64);
-      nl += __shfl_xor(nl, o, 64);
+    for (int o = W / 2; o > 0; o >>= 1) {
+      ne += __shfl_xor(ne, o, W);
+      ns += __shfl_xor(ns, o, W);
+      nl += __shfl_xor(nl, o, W);
       if (LEARN) {
-        sa = fmin(sa, __shfl_xor(sa, o, 64));
-        so = fmin(so, __shfl_xor(so, o, 64));
+        sa = fmin(sa, __shfl_xor(sa, o, W));
+        so = fmin(so, __shfl_xor(so, o, W));
       }
     }
     if (lane == 0) {
@@ -403,6 +416,50 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 
 }  // namespace
 
+// Lanes per group: enough lanes in flight to hide the cell-record loads
+// (about 2^18), from 4 (many groups) to 64 (few groups); 1 = the one-thread
+// walk with LDS-staged token writes.
+int walk_tile(int64_t n_walk) {
+  if (kTileWalk == 1) return 1;
+  int w = kTileWalk;
+  while (w < 64 && (int64_t)w * n_walk < kTileLanes) w <<= 1;
+  return w;
+}
+
+template <int W>
+static void tile_launch(nb_ctx* c, bool fill, bool learn, int64_t launch,
+                        int64_t n_walk, int64_t nblk, const uint32_t* sel,
+                        const double4* lo, const double4* hi, uint32_t slab) {
+  auto k = fill ? (learn ? k_walk_tile<W, true, true>
+                         : k_walk_tile<W, true, false>)
+                : (learn ? k_walk_tile<W, false, true>
+                         : k_walk_tile<W, false, false>);
+  hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(256), 0, c->stream,
+                     n_walk, nblk, sel, (const uint32_t*)c->g_begin.p,
+                     (const uint32_t*)c->g_count.p, lo, hi,
+                     (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
+                     (const uint32_t*)c->g_cell.p,
+                     (const double4*)c->c_shift.p, c->g_sa.p, c->g_so.p,
+                     c->g_tau0.p, (const uint32_t*)c->seg.p,
+                     (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
+                     c->cnt_t.p, (const uint64_t*)c->tok_off.p, c->tok.p,
+                     slab);
+}
+
+static int launch_tile(nb_ctx* c, int w, bool fill, bool learn,
+                       int64_t launch, int64_t n_walk, int64_t nblk,
+                       const uint32_t* sel, const double4* lo,
+                       const double4* hi, uint32_t slab) {
+  switch (w) {
+    case 4: tile_launch<4>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
+    case 8: tile_launch<8>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
+    case 16: tile_launch<16>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
+    case 32: tile_launch<32>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
+    default: tile_launch<64>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
+  }
+  return NB_OK;
+}
+
 int launch_walk(nb_ctx* c, bool fill, uint32_t slab) {
   const size_t ng = (size_t)c->n_groups;
   int rc = reserve(c, c->cnt_e, ng);
@@ -431,7 +488,7 @@ int launch_expand_slab(nb_ctx* c, uint32_t slab) {
   return hip_check(c, hipGetLastError(), "expand launch");
 }
 
-bool walk_uses_waves(int64_t n_walk) { return n_walk < kWaveWalkBelow; }
+
 
 int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                     const double4* lo, const double4* hi,
@@ -440,31 +497,19 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
   if (c->n_cell >= (int64_t)kLeafTag)
     return set_err(c, NB_ERR_INPUT, "too many cells for 31-bit list tokens");
   if (n_walk <= 0) return NB_OK;
+  int rc = NB_OK;
   const bool learn = c->learn;
   if (!learn && sel) return set_err(c, NB_ERR_STATE, "selected walk needs refresh mode");
-  // one thread per group fills the device only with many groups; below
-  // that, one wave per group
-  const bool wave = n_walk < kWaveWalkBelow;
-  if (wave && slab)
-    return set_err(c, NB_ERR_STATE, "slab mode needs the one-thread walk");
-  const int64_t nblk = wave ? grid_for(n_walk, 4)
-                            : grid_for(n_walk, kWalkThreads);
-  const int64_t launch = (nblk + 7) / 8 * 8;
-  if (wave) {
-    auto k = fill ? (learn ? k_walk_wave<true, true> : k_walk_wave<true, false>)
-                  : (learn ? k_walk_wave<false, true>
-                           : k_walk_wave<false, false>);
-    hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
-                       c->stream, n_walk, nblk, sel,
-                       (const uint32_t*)c->g_begin.p,
-                       (const uint32_t*)c->g_count.p, lo, hi,
-                       (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
-                       (const uint32_t*)c->g_cell.p,
-                       (const double4*)c->c_shift.p, c->g_sa.p, c->g_so.p,
-                       c->g_tau0.p, (const uint32_t*)c->seg.p,
-                       (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
-                       c->cnt_t.p, (const uint64_t*)c->tok_off.p, c->tok.p);
+  const int w = walk_tile(n_walk);
+  if (w > 1) {
+    const int64_t nblk = grid_for(n_walk, 256 / w);
+    const int64_t launch = (nblk + 7) / 8 * 8;
+    rc = launch_tile(c, w, fill, learn, launch, n_walk, nblk, sel, lo, hi,
+                     slab);
+    if (rc) return rc;
   } else {
+    const int64_t nblk = grid_for(n_walk, kWalkThreads);
+    const int64_t launch = (nblk + 7) / 8 * 8;
     auto k = fill ? (learn ? k_walk<true, true> : k_walk<true, false>)
                   : (learn ? k_walk<false, true> : k_walk<false, false>);
     hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
