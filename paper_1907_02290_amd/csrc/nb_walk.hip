@@ -25,8 +25,14 @@ namespace nb {
 namespace {
 
 constexpr int kWalkThreads = 256;
-// Walk layout: kTileWalk = narrowest tile (1 = one thread per group), widened
-// until about kTileLanes lanes are in flight.
+// Walk layout.  From kThreadWalkFrom groups on, one thread per group (its
+// LDS-staged token writes and lean loop win once the groups fill the
+// device: on MI355X, 58k groups of a 2^22-particle disk walk in 2.0 ms one
+// thread per group, 2.5 / 3.4 / 4.6 ms with tiles of 4 / 8 / 16 lanes);
+// below, tiles of at least kTileWalk lanes, widened until about kTileLanes
+// lanes are in flight (1.8k groups: 0.5 ms against 2.4 ms one thread per
+// group).
+constexpr int64_t kThreadWalkFrom = 8192;
 constexpr int kTileWalk = 4;
 constexpr int64_t kTileLanes = 1 << 18;
 
@@ -416,11 +422,9 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 
 }  // namespace
 
-// Lanes per group: enough lanes in flight to hide the cell-record loads
-// (about 2^18), from 4 (many groups) to 64 (few groups); 1 = the one-thread
-// walk with LDS-staged token writes.
+// Lanes per group of a walk over n_walk groups (see kThreadWalkFrom).
 int walk_tile(int64_t n_walk) {
-  if (kTileWalk == 1) return 1;
+  if (n_walk >= kThreadWalkFrom) return 1;
   int w = kTileWalk;
   while (w < 64 && (int64_t)w * n_walk < kTileLanes) w <<= 1;
   return w;
