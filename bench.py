@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--reuse", type=int, default=None)
     ap.add_argument("--graph", action="store_true",
                     help="replay reuse steps from a captured HIP graph")
+    ap.add_argument("--persistent", action="store_true",
+                    help="persistent work-queue force launch")
     ap.add_argument("--latency-steps", type=int, default=32,
                     help="steps timed one by one afterwards (p50/p99)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -114,7 +116,7 @@ def main():
     ctx = nb.Context(theta=p["theta"], eps=p["eps"], n_leaf=n_leaf,
                      n_grp=n_grp, order=p["order"],
                      ext_mass=p.get("ext_mass", 0.0), timing=True,
-                     graph=args.graph)
+                     graph=args.graph, persistent=args.persistent)
     ctx.set_particles(dev["x"], dev["y"], dev["z"], dev["vx"], dev["vy"],
                       dev["vz"], dev["m"])
     del dev
@@ -296,6 +298,7 @@ def main():
             "n_grp_autotuned": tuned is not None,
             "systems": n_sys,
             "graph": bool(args.graph),
+            "persistent_force": bool(args.persistent),
         },
         "step_latency": latency,
         "roofline": {

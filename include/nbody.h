@@ -72,7 +72,9 @@ typedef struct nb_config {
   int32_t order;   /* superparticle expansion: 1 monopole, 2 quadrupole */
   int32_t flags;   /* bit 0: record per-phase GPU timers (HIP events);
                       bit 1: run the reuse steps of nb_step from a captured
-                      HIP graph; bit 2: per-group list refresh (below) */
+                      HIP graph; bit 2: per-group list refresh (below);
+                      bit 3: persistent force launch (resident workgroups
+                      pull work items from per-XCD counters) */
   int32_t k_max;   /* refresh mode: a list this many reuse steps old is
                       walked again; 1..65535 */
   double p_star;   /* refresh mode: a list whose predicted staleness
@@ -99,7 +101,12 @@ enum {
   NB_PH_COUNT
 };
 
-enum { NB_FLAG_TIMING = 1, NB_FLAG_GRAPH = 2, NB_FLAG_REFRESH = 4 };
+enum {
+  NB_FLAG_TIMING = 1,
+  NB_FLAG_GRAPH = 2,
+  NB_FLAG_REFRESH = 4,
+  NB_FLAG_PERSISTENT = 8
+};
 
 /* Rebuild predictor: inputs per group and parameter count of the
  * 12-64-64-1 perceptron (tanh, tanh, logistic).  Parameter layout (floats):

@@ -355,7 +355,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->lvl_cells); release(c->bucket);
   release(c->gflag); release(c->g_cell); release(c->g_begin);
   release(c->g_count); release(c->g_lo); release(c->g_hi);
-  release(c->g_chunks); release(c->wi);
+  release(c->g_chunks); release(c->wi); release(c->queue);
   release(c->cnt_e); release(c->cnt_s); release(c->cnt_t);
   release(c->epj_off); release(c->spj_off); release(c->tok_off);
   release(c->epj); release(c->spj); release(c->tok);

@@ -108,24 +108,37 @@ constexpr int kBigTile = kTile * kMaxSlices;
 // a tile holds 64 r list entries and slice s sums entries [64 s, 64 s + 64):
 // every slice does the same unrolled work per tile as a full group does.
 // For r > 4 the 256-entry tile is cut into r near-equal blocks.
-template <int ORDER>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8)))
-k_force(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
-        const uint32_t* __restrict__ g_cell, const CellRec* __restrict__ rec,
-        const uint64_t* __restrict__ epj_off,
-        const uint32_t* __restrict__ epj,
-        const uint64_t* __restrict__ spj_off,
-        const uint32_t* __restrict__ spj, const double4* __restrict__ pos,
-        const double4* __restrict__ pm, const float4* __restrict__ quad,
-        float eps2, float G, float4* __restrict__ acc) {
-  __shared__ float4 tile[kBigTile];
-  __shared__ float4 tq[ORDER == 2 ? 2 * kBigTile : 1];
-  __shared__ float4 red[kTile];
+struct ForceArgs {
+  const uint32_t* __restrict__ g_cell;
+  const CellRec* __restrict__ rec;
+  const uint64_t* __restrict__ epj_off;
+  const uint32_t* __restrict__ epj;
+  const uint64_t* __restrict__ spj_off;
+  const uint32_t* __restrict__ spj;
+  const double4* __restrict__ pos;
+  const double4* __restrict__ pm;
+  const float4* __restrict__ quad;
+  float eps2, G;
+  float4* __restrict__ acc;
+};
 
-  const uint32_t bid = blockIdx.x;
-  const int64_t w = (int64_t)(bid & 7u) * per_xcd + (int64_t)(bid >> 3);
-  if (w >= n_wi) return;  // uniform over the workgroup
-  const uint4 it = wi[w];
+// The forces on one work item (wi = {group, first particle, count}); all 64
+// lanes of the workgroup call it.
+template <int ORDER>
+__device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
+                                           float4* tile, float4* tq,
+                                           float4* red) {
+  const uint32_t* __restrict__ g_cell = A.g_cell;
+  const CellRec* __restrict__ rec = A.rec;
+  const uint64_t* __restrict__ epj_off = A.epj_off;
+  const uint32_t* __restrict__ epj = A.epj;
+  const uint64_t* __restrict__ spj_off = A.spj_off;
+  const uint32_t* __restrict__ spj = A.spj;
+  const double4* __restrict__ pos = A.pos;
+  const double4* __restrict__ pm = A.pm;
+  const float4* __restrict__ quad = A.quad;
+  const float eps2 = A.eps2, G = A.G;
+  float4* __restrict__ acc = A.acc;
   const int lane = threadIdx.x;
   const int ni = (int)it.z;            // 1..64
   const int r = kTile / ni;            // lane slices
@@ -264,6 +277,49 @@ k_force(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
   }
 }
 
+// One launch, one workgroup (one wavefront) per work item; workgroup ids are
+// remapped so each XCD takes a contiguous stretch of work items.
+template <int ORDER>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8)))
+k_force(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
+        ForceArgs A) {
+  __shared__ float4 tile[kBigTile];
+  __shared__ float4 tq[ORDER == 2 ? 2 * kBigTile : 1];
+  __shared__ float4 red[kTile];
+  const uint32_t bid = blockIdx.x;
+  const int64_t w = (int64_t)(bid & 7u) * per_xcd + (int64_t)(bid >> 3);
+  if (w >= n_wi) return;  // uniform over the workgroup
+  force_item<ORDER>(wi[w], A, tile, tq, red);
+}
+
+// Persistent form: a fixed number of resident workgroups, each pulling the
+// next work item of its XCD's contiguous stretch from that XCD's counter
+// (queue[0..7], zeroed before the launch) until the stretch is used up.
+template <int ORDER>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_force_queue(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
+              unsigned int* __restrict__ queue, ForceArgs A) {
+  __shared__ float4 tile[kBigTile];
+  __shared__ float4 tq[ORDER == 2 ? 2 * kBigTile : 1];
+  __shared__ float4 red[kTile];
+  const uint32_t x = blockIdx.x & 7u;
+  const int64_t lo = (int64_t)x * per_xcd;
+  const int64_t hi = lo + per_xcd < n_wi ? lo + per_xcd : n_wi;
+  for (;;) {
+    unsigned int k = 0;
+    if (threadIdx.x == 0) k = atomicAdd(&queue[x], 1u);
+    k = __shfl(k, 0, 64);
+    const int64_t w = lo + (int64_t)k;
+    if (w >= hi) break;  // uniform over the workgroup
+    force_item<ORDER>(wi[w], A, tile, tq, red);
+    __syncthreads();  // the next item reuses the tile and reduction space
+  }
+}
+
+__global__ void k_zero_queue(unsigned int* q) {
+  if (threadIdx.x < 8) q[threadIdx.x] = 0u;
+}
+
 }  // namespace
 
 int launch_force(nb_ctx* c) {
@@ -274,16 +330,36 @@ int launch_force(nb_ctx* c) {
   const int64_t nblk = per_xcd * 8;
   if (nblk > 0x7FFFFFFFLL)
     return set_err(c, NB_ERR_INPUT, "too many force work items");
-  const float eps2 = (float)(c->cfg.eps * c->cfg.eps);
-  const float G = (float)c->cfg.G;
-  auto k = c->cfg.order == 2 ? k_force<2> : k_force<1>;
-  hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kTile), 0, c->stream,
-                     (const uint4*)c->wi.p, c->n_wi, per_xcd,
-                     (const uint32_t*)c->g_cell.p, (const CellRec*)c->c_rec.p,
-                     (const uint64_t*)c->epj_off.p, (const uint32_t*)c->epj.p,
-                     (const uint64_t*)c->spj_off.p, (const uint32_t*)c->spj.p,
-                     (const double4*)c->pos.p, (const double4*)c->c_pm.p,
-                     (const float4*)c->c_quad.p, eps2, G, c->acc.p);
+  ForceArgs A;
+  A.g_cell = c->g_cell.p;
+  A.rec = c->c_rec.p;
+  A.epj_off = c->epj_off.p;
+  A.epj = c->epj.p;
+  A.spj_off = c->spj_off.p;
+  A.spj = c->spj.p;
+  A.pos = c->pos.p;
+  A.pm = c->c_pm.p;
+  A.quad = c->c_quad.p;
+  A.eps2 = (float)(c->cfg.eps * c->cfg.eps);
+  A.G = (float)c->cfg.G;
+  A.acc = c->acc.p;
+  if (c->cfg.flags & NB_FLAG_PERSISTENT) {
+    if ((rc = reserve(c, c->queue, 8))) return rc;
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, c->stream,
+                       c->queue.p);
+    // resident workgroups: 256 CUs x 16 one-wave workgroups (4 per SIMD,
+    // the kernel's occupancy), dealt round-robin over the 8 XCDs
+    int64_t nq = 256 * 16;
+    if (nq > nblk) nq = nblk;
+    nq = (nq + 7) / 8 * 8;
+    auto k = c->cfg.order == 2 ? k_force_queue<2> : k_force_queue<1>;
+    hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(kTile), 0, c->stream,
+                       (const uint4*)c->wi.p, c->n_wi, per_xcd, c->queue.p, A);
+  } else {
+    auto k = c->cfg.order == 2 ? k_force<2> : k_force<1>;
+    hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kTile), 0, c->stream,
+                       (const uint4*)c->wi.p, c->n_wi, per_xcd, A);
+  }
   return hip_check(c, hipGetLastError(), "force launch");
 }
 

@@ -120,6 +120,7 @@ struct nb_ctx {
   nb::DBuf<double4> g_lo, g_hi;  // tight box of the members (w unused)
   nb::DBuf<uint32_t> g_chunks;  // n_groups + 1, scanned
   nb::DBuf<uint4> wi;           // force work items: group, first, count
+  nb::DBuf<unsigned int> queue;  // per-XCD counters of the persistent launch
 
   // lists
   nb::DBuf<uint32_t> cnt_e, cnt_s, cnt_t;

@@ -159,3 +159,25 @@ def test_set_systems_rejects_bad_offsets():
             with pytest.raises(nb.NbError) as err:
                 ctx.set_systems(bad)
             assert err.value.code == nb.NB_ERR_INPUT
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_persistent_force_launch_is_bit_identical(order):
+    """Resident workgroups pulling work items from per-XCD counters compute
+    each work item exactly as the one-workgroup-per-item launch does."""
+    say("case persistent force order=%d" % order)
+    d = _batch(seed=7, n_sys=6, lo=9, hi=14)
+    out = []
+    for persistent in (False, True):
+        ctx = nb.Context(theta=0.5, eps=0.01, n_leaf=8, n_grp=64, order=order,
+                         persistent=persistent)
+        ctx.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
+                          d["m"])
+        ctx.set_systems(d["offsets"])
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        ctx.kick_drift(1 / 128, 1 / 128)
+        ctx.compute_forces(nb.NB_REUSE_LIST)
+        out.append(ctx.get_forces())
+        ctx.close()
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)
