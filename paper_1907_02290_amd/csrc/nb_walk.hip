@@ -210,7 +210,7 @@ k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
             uint32_t* __restrict__ cnt_s, uint32_t* __restrict__ cnt_t,
             const uint64_t* __restrict__ tok_off, uint32_t* __restrict__ tok,
             uint32_t slab) {
-  static_assert(W >= 4 && W <= 64 && (W & (W - 1)) == 0, "tile width");
+  static_assert(W >= 2 && W <= 64 && (W & (W - 1)) == 0, "tile width");
   const int64_t blk = xcd_block(nblk);
   if (blk >= nblk) return;
   const int64_t t = blk * (256 / W) + (threadIdx.x / W);
@@ -455,6 +455,7 @@ static int launch_tile(nb_ctx* c, int w, bool fill, bool learn,
                        const uint32_t* sel, const double4* lo,
                        const double4* hi, uint32_t slab) {
   switch (w) {
+    case 2: tile_launch<2>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
     case 4: tile_launch<4>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
     case 8: tile_launch<8>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
     case 16: tile_launch<16>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
