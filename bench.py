@@ -165,6 +165,7 @@ def main():
     timing = ctx.get_timing(reset=True)
     elapsed = t1 - t0
     inter = info1["total_inter"] - info0["total_inter"]
+    inter_spj = info1["total_inter_spj"] - info0["total_inter_spj"]
     evals = info1["force_evals"] - info0["force_evals"]
     value = inter / elapsed
     ms_step = elapsed / args.steps * 1e3
@@ -321,6 +322,8 @@ def main():
         "phase_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
         "interactions_per_s_frac_of_fp32_peak": value * N_OP /
                                                 (FP32_PEAK_TFLOPS * 1e12),
+        "superparticle_interactions_per_s": inter_spj / elapsed,
+        "superparticle_share": inter_spj / max(inter, 1),
     }
     print(json.dumps(out), flush=True)
 

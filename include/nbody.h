@@ -202,7 +202,9 @@ int nb_get_state(nb_ctx* ctx, double* x, double* y, double* z, double* vx,
  * n_i * (n_epj + n_spj)), [6] force evaluations so far, [7] total
  * interactions evaluated so far, [8] root exponent k of system 0, [9] force
  * work items, [10] systems, [11] groups whose lists the last force call
- * refreshed, [12] refreshed groups so far.  info must hold 13 values. */
+ * refreshed, [12] refreshed groups so far, [13] superparticle interactions
+ * of the current lists (sum over groups of n_i * n_spj), [14] superparticle
+ * interactions evaluated so far.  info must hold 15 values. */
 int nb_get_info(nb_ctx* ctx, int64_t* info);
 
 /* Root corner lo[3] and exponent k of the last tree (side 2^k); with

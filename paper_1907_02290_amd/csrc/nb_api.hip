@@ -256,6 +256,7 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
   if ((rc = stage_d2h(c, 16, c->red.p, 16))) return rc;
   if ((rc = stage_d2h(c, 32, c->tok_off.p + c->n_groups, 8))) return rc;
   if ((rc = stage_d2h(c, 40, c->g_chunks.p + c->n_groups, 4))) return rc;
+  if ((rc = stage_d2h(c, 48, c->red.p + 2, 8))) return rc;
   if ((rc = sync(c))) return rc;
   int64_t n_tok, max_tok;
   {
@@ -265,6 +266,7 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
     c->n_inter = (int64_t)h[2];
     max_tok = (int64_t)h[3];
     n_tok = (int64_t)h[4];
+    c->n_inter_spj = (int64_t)h[6];
     c->n_wi = static_cast<const uint32_t*>(c->h_small)[10];
   }
   // slab for the next construction: 1.25 x the largest list, 16-aligned
@@ -526,6 +528,7 @@ int nb_compute_forces(nb_ctx* c, nb_mode mode) {
   c->forces_valid = true;
   c->force_evals += 1;
   c->total_inter += c->n_inter;
+  c->total_inter_spj += c->n_inter_spj;
   return NB_OK;
 }
 
@@ -614,6 +617,7 @@ int nb_step(nb_ctx* c, nb_mode mode, double dt_kick, double dt_drift) {
   c->forces_valid = true;
   c->force_evals += 1;
   c->total_inter += c->n_inter;
+  c->total_inter_spj += c->n_inter_spj;
   return NB_OK;
 }
 
@@ -692,6 +696,8 @@ int nb_get_info(nb_ctx* c, int64_t* info) {
   info[10] = c->n_sys;
   info[11] = c->last_refreshed;
   info[12] = c->total_refreshed;
+  info[13] = c->lists_valid ? c->n_inter_spj : 0;
+  info[14] = c->total_inter_spj;
   return NB_OK;
 }
 

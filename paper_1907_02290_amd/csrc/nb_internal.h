@@ -69,6 +69,7 @@ struct nb_ctx {
   // from the largest token count of the previous construction
   uint32_t tok_slab = 0;
   int64_t force_evals = 0, total_inter = 0;
+  int64_t n_inter_spj = 0, total_inter_spj = 0;  // superparticle share
   int32_t k = 0;
   // internal cells per level and where each level starts in lvl_cells;
   // index kLevels holds the leaves

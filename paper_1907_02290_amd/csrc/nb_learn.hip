@@ -733,10 +733,12 @@ int refresh_selected(nb_ctx* c, int64_t n_sel) {
   if ((rc = stage_d2h(c, 8, c->spj_off2.p + G, 8))) return rc;
   if ((rc = stage_d2h(c, 16, c->red.p, 8))) return rc;
   if ((rc = stage_d2h(c, 24, c->tok_off.p + n_sel, 8))) return rc;
+  if ((rc = stage_d2h(c, 32, c->red.p + 2, 8))) return rc;
   if ((rc = sync_stream(c))) return rc;
   const uint64_t* h = static_cast<const uint64_t*>(c->h_small);
   const int64_t ne = (int64_t)h[0], ns = (int64_t)h[1];
   const int64_t n_inter = (int64_t)h[2], n_tok = (int64_t)h[3];
+  c->n_inter_spj = (int64_t)h[4];
   if ((rc = reserve(c, c->epj2, (size_t)ne + 1))) return rc;
   if ((rc = reserve(c, c->spj2, (size_t)ns + 1))) return rc;
   if ((rc = reserve(c, c->tok, (size_t)n_tok + 1))) return rc;

@@ -381,23 +381,35 @@ k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   }
 }
 
-// Interactions of the lists: sum over groups of n_i * (n_epj + n_spj).
+// Interactions of the lists: sum over groups of n_i * (n_epj + n_spj) into
+// out[0], and of n_i * n_spj (superparticle interactions) into out[2].
 __global__ void __launch_bounds__(256)
 k_interactions(int64_t n_groups, const uint32_t* __restrict__ g_count,
                const uint32_t* __restrict__ cnt_e,
                const uint32_t* __restrict__ cnt_s,
                unsigned long long* __restrict__ out) {
-  __shared__ unsigned long long s[4];
-  unsigned long long v = 0;
+  __shared__ unsigned long long s[4], s2[4];
+  unsigned long long v = 0, v2 = 0;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-       g < n_groups; g += (int64_t)gridDim.x * blockDim.x)
+       g < n_groups; g += (int64_t)gridDim.x * blockDim.x) {
     v += (unsigned long long)g_count[g] *
          ((unsigned long long)cnt_e[g] + cnt_s[g]);
+    v2 += (unsigned long long)g_count[g] * cnt_s[g];
+  }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+  for (int o = 32; o > 0; o >>= 1) {
+    v += __shfl_xor(v, o, 64);
+    v2 += __shfl_xor(v2, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s[threadIdx.x >> 6] = v;
+    s2[threadIdx.x >> 6] = v2;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(out, s[0] + s[1] + s[2] + s[3]);
+  if (threadIdx.x == 0) {
+    atomicAdd(out, s[0] + s[1] + s[2] + s[3]);
+    atomicAdd(out + 2, s2[0] + s2[1] + s2[2] + s2[3]);
+  }
 }
 
 // Largest per-group token count into *out (zeroed before).
@@ -557,12 +569,13 @@ int launch_list_stats(nb_ctx* c) {
   return hip_check(c, hipGetLastError(), "list max launch");
 }
 
-// Interaction count of per-group list lengths ne, ns into red[0].
+// Interaction counts of per-group list lengths ne, ns into red[0] (all)
+// and red[2] (superparticles).
 int launch_interactions(nb_ctx* c, const uint32_t* ne, const uint32_t* ns) {
   int rc = reserve(c, c->red, 16);
   if (rc) return rc;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream,
-                     (unsigned long long*)c->red.p, 2);
+                     (unsigned long long*)c->red.p, 3);
   unsigned nb = grid_for(c->n_groups, 256);
   if (nb > 1024) nb = 1024;
   hipLaunchKernelGGL(k_interactions, dim3(nb), dim3(256), 0, c->stream,

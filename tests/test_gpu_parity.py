@@ -131,6 +131,7 @@ def test_tree_groups_lists_bit_exact(kind, n):
         gc = t.groups()["count"].astype(np.int64)
         inter = int((gc * (np.diff(eo) + np.diff(so))).sum())
         assert info["n_inter"] == inter
+        assert info["n_inter_spj"] == int((gc * np.diff(so)).sum())
 
 
 @pytest.mark.parametrize("theta", [0.0, 0.3, 0.7, 1.0])
