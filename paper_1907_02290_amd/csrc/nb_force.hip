@@ -10,11 +10,11 @@
 //  * a group of n_i < 33 particles is replicated over r = 64 / n_i lane
 //    slices; each slice sums its own block of every tile and the slices are
 //    added through LDS at the end;
-//  * the list is walked in tiles of 64 min(r, 4) entries: each lane gathers
-//    entries by index (particle by slot, superparticle by cell id -- the
-//    same {x, y, z, m} FP64 record), converts them to FP32 offsets and
-//    stores them in LDS; the lanes of a slice then read its block back as
-//    broadcasts;
+//  * the list is walked in tiles of 64 min(r, 4) entries, first its
+//    particles (by slot), then its superparticles (by cell id; the same
+//    {x, y, z, m} FP64 record): each lane gathers entries by index, converts
+//    them to FP32 offsets and stores them in LDS; the lanes of a slice then
+//    read its block back as broadcasts;
 //  * FP32 arithmetic with per-tile partial sums added into the totals;
 //    the potential of the particle on itself is removed at the end;
 //  * workgroup ids are remapped so that each XCD (workgroups are dealt out
@@ -28,6 +28,9 @@ namespace {
 
 constexpr int kTile = 64;
 
+// One monopole term; the first term of a block assigns the partial sums
+// instead of adding to them (no zero initialisation).
+template <bool FIRST>
 __device__ __forceinline__ void mono(const float4 j, float xi, float yi,
                                      float zi, float eps2, float& ax,
                                      float& ay, float& az, float& ph) {
@@ -36,10 +39,17 @@ __device__ __forceinline__ void mono(const float4 j, float xi, float yi,
   const float rinv = __builtin_amdgcn_rsqf(r2);
   const float mr = j.w * rinv;
   const float mr3 = mr * rinv * rinv;
-  ax = fmaf(mr3, dx, ax);
-  ay = fmaf(mr3, dy, ay);
-  az = fmaf(mr3, dz, az);
-  ph -= mr;
+  if (FIRST) {
+    ax = mr3 * dx;
+    ay = mr3 * dy;
+    az = mr3 * dz;
+    ph = -mr;
+  } else {
+    ax = fmaf(mr3, dx, ax);
+    ay = fmaf(mr3, dy, ay);
+    az = fmaf(mr3, dz, az);
+    ph -= mr;
+  }
 }
 
 // Second-order expansion of the softened kernel about the centre of mass X:
@@ -72,26 +82,30 @@ __device__ __forceinline__ void quadr(const float4 j, const float4 qa,
   ph -= fmaf(j.w, f, 0.5f * fmaf(3.0f * q, f2, -t) * f3);
 }
 
-// Sum of one slice's block of `cnt` tile entries (cnt <= 64).  Full blocks
-// take the unrolled path; LDS offsets are then immediates.
+// Adds the sum over one slice's block of `cnt` staged entries (cnt <= 64)
+// to the totals; the block's partial sums are kept apart and added once.
+// A full block is unrolled completely, so its LDS offsets are immediates.
 template <int ORDER>
 __device__ __forceinline__ void slice_sum(const float4* __restrict__ t,
                                           const float4* __restrict__ q,
                                           int cnt, float xi, float yi,
                                           float zi, float eps2, float& ax,
                                           float& ay, float& az, float& ph) {
-  float tx = 0.f, ty = 0.f, tz = 0.f, tp = 0.f;
+  if (cnt <= 0) return;
+  float tx, ty, tz, tp;
   if (ORDER == 1) {
+    mono<true>(t[0], xi, yi, zi, eps2, tx, ty, tz, tp);
     if (cnt == kTile) {
-#pragma unroll 8
-      for (int k = 0; k < kTile; ++k)
-        mono(t[k], xi, yi, zi, eps2, tx, ty, tz, tp);
+#pragma unroll
+      for (int k = 1; k < kTile; ++k)
+        mono<false>(t[k], xi, yi, zi, eps2, tx, ty, tz, tp);
     } else {
 #pragma unroll 4
-      for (int k = 0; k < cnt; ++k)
-        mono(t[k], xi, yi, zi, eps2, tx, ty, tz, tp);
+      for (int k = 1; k < cnt; ++k)
+        mono<false>(t[k], xi, yi, zi, eps2, tx, ty, tz, tp);
     }
   } else {
+    tx = ty = tz = tp = 0.f;
     for (int k = 0; k < cnt; ++k)
       quadr(t[k], q[2 * k], q[2 * k + 1], xi, yi, zi, eps2, tx, ty, tz, tp);
   }
@@ -122,20 +136,23 @@ struct ForceArgs {
   float4* __restrict__ acc;
 };
 
+// One slice's share of a tile of T entries of which `valid` are filled.
+__device__ __forceinline__ int block_count(int valid, int blk0, int blk1) {
+  const int hi = blk1 < valid ? blk1 : valid;
+  return hi - blk0;
+}
+
 // The forces on one work item (wi = {group, first particle, count}); all 64
-// lanes of the workgroup call it.
+// lanes of the workgroup call it.  The list is taken in two segments, its
+// particles (ids into the particle array) and its superparticles (ids into
+// the cell array), so every tile reads from one array.  Entries past the end
+// of a segment are staged as duplicates of its last entry and never summed.
 template <int ORDER>
 __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
                                            float4* tile, float4* tq,
                                            float4* red) {
   const uint32_t* __restrict__ g_cell = A.g_cell;
   const CellRec* __restrict__ rec = A.rec;
-  const uint64_t* __restrict__ epj_off = A.epj_off;
-  const uint32_t* __restrict__ epj = A.epj;
-  const uint64_t* __restrict__ spj_off = A.spj_off;
-  const uint32_t* __restrict__ spj = A.spj;
-  const double4* __restrict__ pos = A.pos;
-  const double4* __restrict__ pm = A.pm;
   const float4* __restrict__ quad = A.quad;
   const float eps2 = A.eps2, G = A.G;
   float4* __restrict__ acc = A.acc;
@@ -155,91 +172,88 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
 
   float xi = 0.f, yi = 0.f, zi = 0.f, mi = 0.f;
   if (act) {
-    const double4 p = pos[it.y + ii];
+    const double4 p = A.pos[it.y + ii];
     xi = (float)(p.x - cg.x);
     yi = (float)(p.y - cg.y);
     zi = (float)(p.z - cg.z);
     mi = (float)p.w;
   }
-  // list entries are addressed relative to the group's list: [0, ne) are
-  // particles, [ne, ne + ns) superparticles
-  const uint64_t e0 = epj_off[g];
-  const uint32_t ne = (uint32_t)(epj_off[g + 1] - e0);
-  const uint64_t s0 = spj_off[g];
-  const uint32_t ns = (uint32_t)(spj_off[g + 1] - s0);
-  const uint32_t* __restrict__ ida = epj + e0;
-  const uint32_t* __restrict__ idb = spj + s0;
-  const uint32_t nl = ORDER == 1 ? ne + ns : ne;
-
-  // ids of the tile starting at tb (slot u of this lane), kNone past the end
-  auto load_ids = [&](uint32_t tb, uint32_t* id) {
-#pragma unroll
-    for (int u = 0; u < kMaxSlices; ++u) {
-      id[u] = kNone;
-      const uint32_t e = tb + (uint32_t)(u * kTile + lane);
-      if (u < q && e < nl) id[u] = e < ne ? ida[e] : idb[e - ne];
-    }
-  };
+  const uint64_t e0 = A.epj_off[g];
+  const uint32_t ne = (uint32_t)(A.epj_off[g + 1] - e0);
+  const uint64_t s0 = A.spj_off[g];
+  const uint32_t ns = (uint32_t)(A.spj_off[g + 1] - s0);
 
   float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
-  uint32_t nid[kMaxSlices];
-  load_ids(0, nid);
-  for (uint32_t tb = 0; tb < nl; tb += (uint32_t)T) {
-    uint32_t cid[kMaxSlices];
-    double4 P[kMaxSlices];
-#pragma unroll
-    for (int u = 0; u < kMaxSlices; ++u) {
-      cid[u] = nid[u];
-      const uint32_t e = tb + (uint32_t)(u * kTile + lane);
-      if (cid[u] != kNone) P[u] = e < ne ? pos[cid[u]] : pm[cid[u]];
-    }
-    // the next tile's ids arrive while this tile is staged and summed
-    if (tb + (uint32_t)T < nl) load_ids(tb + (uint32_t)T, nid);
-    __syncthreads();
+  // monopole: both segments; quadrupole: the particle segment here, the
+  // superparticles with their second moments below
+  for (int seg = 0; seg < (ORDER == 1 ? 2 : 1); ++seg) {
+    const uint32_t* __restrict__ ids = seg ? A.spj + s0 : A.epj + e0;
+    const double4* __restrict__ src = seg ? A.pm : A.pos;
+    const uint32_t n = seg ? ns : ne;
+    if (n == 0) continue;
+    const uint32_t last = n - 1;
+    uint32_t nid[kMaxSlices];
 #pragma unroll
     for (int u = 0; u < kMaxSlices; ++u) {
       if (u < q) {
-        float4 jd = make_float4(0.f, 0.f, 0.f, 0.f);  // massless padding
-        if (cid[u] != kNone)
-          jd = make_float4((float)(P[u].x - cg.x), (float)(P[u].y - cg.y),
-                           (float)(P[u].z - cg.z), (float)P[u].w);
-        tile[u * kTile + lane] = jd;
+        const uint32_t e = (uint32_t)(u * kTile + lane);
+        nid[u] = ids[e < last ? e : last];
       }
     }
-    __syncthreads();
-    if (act) {
-      const int valid = nl - tb < (uint32_t)T ? (int)(nl - tb) : T;
-      const int hi = blk1 < valid ? blk1 : valid;
-      const int cnt = hi > blk0 ? hi - blk0 : 0;
-      slice_sum<1>(tile + blk0, nullptr, cnt, xi, yi, zi, eps2, ax, ay, az,
-                   ph);
+    for (uint32_t tb = 0; tb < n; tb += (uint32_t)T) {
+      double4 P[kMaxSlices];
+#pragma unroll
+      for (int u = 0; u < kMaxSlices; ++u)
+        if (u < q) P[u] = src[nid[u]];
+      // the next tile's ids arrive while this tile is staged and summed
+      const uint32_t nb = tb + (uint32_t)T;
+      if (nb < n) {
+#pragma unroll
+        for (int u = 0; u < kMaxSlices; ++u) {
+          if (u < q) {
+            const uint32_t e = nb + (uint32_t)(u * kTile + lane);
+            nid[u] = ids[e < last ? e : last];
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kMaxSlices; ++u)
+        if (u < q)
+          tile[u * kTile + lane] = make_float4(
+              (float)(P[u].x - cg.x), (float)(P[u].y - cg.y),
+              (float)(P[u].z - cg.z), (float)P[u].w);
+      __syncthreads();
+      if (act) {
+        const int valid = n - tb < (uint32_t)T ? (int)(n - tb) : T;
+        slice_sum<1>(tile + blk0, nullptr, block_count(valid, blk0, blk1),
+                     xi, yi, zi, eps2, ax, ay, az, ph);
+      }
     }
   }
-  if (ORDER == 2) {
+  if (ORDER == 2 && ns > 0) {
+    const uint32_t* __restrict__ ids = A.spj + s0;
+    const uint32_t last = ns - 1;
     for (uint32_t tb = 0; tb < ns; tb += (uint32_t)T) {
       uint32_t cid[kMaxSlices];
 #pragma unroll
       for (int u = 0; u < kMaxSlices; ++u) {
-        const uint32_t e = tb + (uint32_t)(u * kTile + lane);
-        cid[u] = (u < q && e < ns) ? idb[e] : kNone;
+        if (u < q) {
+          const uint32_t e = tb + (uint32_t)(u * kTile + lane);
+          cid[u] = ids[e < last ? e : last];
+        }
       }
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < kMaxSlices; ++u) {
         if (u < q) {
-          float4 jd = make_float4(0.f, 0.f, 0.f, 0.f);
-          float4 qa = make_float4(0.f, 0.f, 0.f, 0.f);
-          float4 qb = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (cid[u] != kNone) {
-            const double4 Q = pm[cid[u]];
-            jd = make_float4((float)(Q.x - cg.x), (float)(Q.y - cg.y),
-                             (float)(Q.z - cg.z), (float)Q.w);
-            qa = quad[2 * (int64_t)cid[u]];
-            qb = quad[2 * (int64_t)cid[u] + 1];
-            qb.z = qa.x + qa.y + qa.z;
-          }
+          const double4 Q = A.pm[cid[u]];
+          float4 qa = quad[2 * (int64_t)cid[u]];
+          float4 qb = quad[2 * (int64_t)cid[u] + 1];
+          qb.z = qa.x + qa.y + qa.z;
           const int slot = u * kTile + lane;
-          tile[slot] = jd;
+          tile[slot] = make_float4((float)(Q.x - cg.x), (float)(Q.y - cg.y),
+                                   (float)(Q.z - cg.z), (float)Q.w);
           tq[2 * slot] = qa;
           tq[2 * slot + 1] = qb;
         }
@@ -247,9 +261,8 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
       __syncthreads();
       if (act) {
         const int valid = ns - tb < (uint32_t)T ? (int)(ns - tb) : T;
-        const int hi = blk1 < valid ? blk1 : valid;
-        const int cnt = hi > blk0 ? hi - blk0 : 0;
-        slice_sum<2>(tile + blk0, tq + 2 * blk0, cnt, xi, yi, zi, eps2, ax,
+        slice_sum<2>(tile + blk0, tq + 2 * blk0,
+                     block_count(valid, blk0, blk1), xi, yi, zi, eps2, ax,
                      ay, az, ph);
       }
     }
