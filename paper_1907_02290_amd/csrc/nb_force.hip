@@ -193,29 +193,18 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
     if (n == 0) continue;
     const uint32_t last = n - 1;
     uint32_t nid[kMaxSlices];
+    double4 P[kMaxSlices];
+    // records of the first tile, ids of the second
 #pragma unroll
     for (int u = 0; u < kMaxSlices; ++u) {
       if (u < q) {
         const uint32_t e = (uint32_t)(u * kTile + lane);
-        nid[u] = ids[e < last ? e : last];
+        P[u] = src[ids[e < last ? e : last]];
+        const uint32_t e2 = (uint32_t)T + e;
+        nid[u] = ids[e2 < last ? e2 : last];
       }
     }
     for (uint32_t tb = 0; tb < n; tb += (uint32_t)T) {
-      double4 P[kMaxSlices];
-#pragma unroll
-      for (int u = 0; u < kMaxSlices; ++u)
-        if (u < q) P[u] = src[nid[u]];
-      // the next tile's ids arrive while this tile is staged and summed
-      const uint32_t nb = tb + (uint32_t)T;
-      if (nb < n) {
-#pragma unroll
-        for (int u = 0; u < kMaxSlices; ++u) {
-          if (u < q) {
-            const uint32_t e = nb + (uint32_t)(u * kTile + lane);
-            nid[u] = ids[e < last ? e : last];
-          }
-        }
-      }
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < kMaxSlices; ++u)
@@ -223,6 +212,19 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
           tile[u * kTile + lane] = make_float4(
               (float)(P[u].x - cg.x), (float)(P[u].y - cg.y),
               (float)(P[u].z - cg.z), (float)P[u].w);
+      // the next tile's records and the ids of the one after arrive while
+      // this tile is summed
+      const uint32_t nb = tb + (uint32_t)T;
+      if (nb < n) {
+#pragma unroll
+        for (int u = 0; u < kMaxSlices; ++u) {
+          if (u < q) {
+            P[u] = src[nid[u]];
+            const uint32_t e = nb + (uint32_t)T + (uint32_t)(u * kTile + lane);
+            nid[u] = ids[e < last ? e : last];
+          }
+        }
+      }
       __syncthreads();
       if (act) {
         const int valid = n - tb < (uint32_t)T ? (int)(n - tb) : T;
@@ -291,9 +293,11 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
 }
 
 // One launch, one workgroup (one wavefront) per work item; workgroup ids are
-// remapped so each XCD takes a contiguous stretch of work items.
+// remapped so each XCD takes a contiguous stretch of work items.  Five waves
+// per SIMD leave room for the next tile's records in registers (93 VGPRs);
+// at six the compiler spills them.
 template <int ORDER>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_force(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
         ForceArgs A) {
   __shared__ float4 tile[kBigTile];
