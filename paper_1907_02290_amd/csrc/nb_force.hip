@@ -115,13 +115,22 @@ __device__ __forceinline__ void slice_sum(const float4* __restrict__ t,
   ph += tp;
 }
 
-constexpr int kMaxSlices = 4;
-constexpr int kBigTile = kTile * kMaxSlices;
+// Largest tile: 64 x 4 entries.  The quadrupole kernel stages 2 x 16 bytes
+// of second moments per entry besides the record, so its tiles stop at
+// 64 x 2 entries, which keeps its LDS (and so its occupancy) in line with
+// its registers.
+template <int ORDER>
+struct Tiles {
+  static constexpr int kMaxSlices = ORDER == 2 ? 2 : 4;
+  static constexpr int kBig = kTile * kMaxSlices;
+};
 
-// One group chunk per wavefront.  With r = 64 / n_i lane slices (r <= 4),
-// a tile holds 64 r list entries and slice s sums entries [64 s, 64 s + 64):
-// every slice does the same unrolled work per tile as a full group does.
-// For r > 4 the 256-entry tile is cut into r near-equal blocks.
+// One group chunk per wavefront.  With r = 64 / n_i lane slices (r up to
+// the kernel's largest slice count, kMaxSlices), a tile holds 64 r list
+// entries and slice s sums entries [64 s, 64 s + 64): every slice does the
+// same unrolled work per tile as a full group does.  For larger r the
+// largest tile is cut into r near-equal blocks.  The slices' sums are added
+// through LDS at the end, in the tile's space.
 struct ForceArgs {
   const uint32_t* __restrict__ g_cell;
   const CellRec* __restrict__ rec;
@@ -162,6 +171,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
   const int sl = lane / ni;
   const int ii = lane - sl * ni;
   const bool act = sl < r;
+  constexpr int kMaxSlices = Tiles<ORDER>::kMaxSlices;
   const int q = r < kMaxSlices ? r : kMaxSlices;  // tile = 64 q entries
   const int T = kTile * q;
   // this slice's block of a full tile
@@ -300,13 +310,12 @@ template <int ORDER>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_force(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
         ForceArgs A) {
-  __shared__ float4 tile[kBigTile];
-  __shared__ float4 tq[ORDER == 2 ? 2 * kBigTile : 1];
-  __shared__ float4 red[kTile];
+  __shared__ float4 tile[Tiles<ORDER>::kBig];
+  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<ORDER>::kBig : 1];
   const uint32_t bid = blockIdx.x;
   const int64_t w = (int64_t)(bid & 7u) * per_xcd + (int64_t)(bid >> 3);
   if (w >= n_wi) return;  // uniform over the workgroup
-  force_item<ORDER>(wi[w], A, tile, tq, red);
+  force_item<ORDER>(wi[w], A, tile, tq, tile);
 }
 
 // Persistent form: a fixed number of resident workgroups, each pulling the
@@ -316,9 +325,8 @@ template <int ORDER>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_force_queue(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
               unsigned int* __restrict__ queue, ForceArgs A) {
-  __shared__ float4 tile[kBigTile];
-  __shared__ float4 tq[ORDER == 2 ? 2 * kBigTile : 1];
-  __shared__ float4 red[kTile];
+  __shared__ float4 tile[Tiles<ORDER>::kBig];
+  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<ORDER>::kBig : 1];
   const uint32_t x = blockIdx.x & 7u;
   const int64_t lo = (int64_t)x * per_xcd;
   const int64_t hi = lo + per_xcd < n_wi ? lo + per_xcd : n_wi;
@@ -328,7 +336,7 @@ k_force_queue(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
     k = __shfl(k, 0, 64);
     const int64_t w = lo + (int64_t)k;
     if (w >= hi) break;  // uniform over the workgroup
-    force_item<ORDER>(wi[w], A, tile, tq, red);
+    force_item<ORDER>(wi[w], A, tile, tq, tile);
     __syncthreads();  // the next item reuses the tile and reduction space
   }
 }
