@@ -70,6 +70,9 @@ def parse():
                     help="replay reuse steps from a captured HIP graph")
     ap.add_argument("--persistent", action="store_true",
                     help="persistent work-queue force launch")
+    ap.add_argument("--copied-lists", action="store_true",
+                    help="lists of copied j-data (the paper's G1) instead "
+                         "of indices, for comparison")
     ap.add_argument("--latency-steps", type=int, default=32,
                     help="steps timed one by one afterwards (p50/p99)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -116,7 +119,8 @@ def main():
     ctx = nb.Context(theta=p["theta"], eps=p["eps"], n_leaf=n_leaf,
                      n_grp=n_grp, order=p["order"],
                      ext_mass=p.get("ext_mass", 0.0), timing=True,
-                     graph=args.graph, persistent=args.persistent)
+                     graph=args.graph, persistent=args.persistent,
+                     copied_lists=args.copied_lists)
     ctx.set_particles(dev["x"], dev["y"], dev["z"], dev["vx"], dev["vy"],
                       dev["vz"], dev["m"])
     del dev
@@ -300,6 +304,7 @@ def main():
             "systems": n_sys,
             "graph": bool(args.graph),
             "persistent_force": bool(args.persistent),
+            "lists": "copied j-data" if args.copied_lists else "indices",
         },
         "step_latency": latency,
         "roofline": {

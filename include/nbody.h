@@ -105,7 +105,15 @@ enum {
   NB_FLAG_TIMING = 1,
   NB_FLAG_GRAPH = 2,
   NB_FLAG_REFRESH = 4,
-  NB_FLAG_PERSISTENT = 8
+  NB_FLAG_PERSISTENT = 8,
+  /* Lists that hold copies of the j-data instead of indices (the paper's
+   * method G1, section 4.1 and its table of methods; kept for comparison
+   * with the index lists, G2): every force evaluation first copies each list
+   * entry, as an FP32 offset from its group's centre and its mass, into a
+   * per-group contiguous array (16 bytes per entry), and the force kernel
+   * reads that.  Same forces bit for bit.  Order 1 only, not with
+   * NB_FLAG_REFRESH or NB_FLAG_PERSISTENT (NB_ERR_INPUT). */
+  NB_FLAG_COPIED_LISTS = 16
 };
 
 /* Rebuild predictor: inputs per group and parameter count of the

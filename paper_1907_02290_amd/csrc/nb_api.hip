@@ -102,6 +102,11 @@ static int check_cfg(nb_ctx* c, const nb_config* cfg) {
     return set_err(c, NB_ERR_INPUT, "n_grp must be in 1..65536");
   if (cfg->order != 1 && cfg->order != 2)
     return set_err(c, NB_ERR_INPUT, "order must be 1 or 2");
+  if ((cfg->flags & NB_FLAG_COPIED_LISTS) &&
+      (cfg->order != 1 || (cfg->flags & (NB_FLAG_REFRESH | NB_FLAG_PERSISTENT))))
+    return set_err(c, NB_ERR_INPUT,
+                   "copied lists need order 1, no refresh mode and no "
+                   "persistent launch");
   if (cfg->flags & NB_FLAG_REFRESH) {
     if (cfg->k_max < 1 || cfg->k_max > 65535)
       return set_err(c, NB_ERR_INPUT, "k_max must be in 1..65535");
@@ -347,6 +352,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->vx); release(c->vy); release(c->vz);
   release(c->vx2); release(c->vy2); release(c->vz2);
   release(c->orig); release(c->orig2); release(c->acc);
+  release(c->jcopy);
   release(c->key); release(c->key2); release(c->val); release(c->val2);
   release(c->hist); release(c->dtot); release(c->root); release(c->bbox_part);
   release(c->bbox_chunks); release(c->bbox_first); release(c->seg);

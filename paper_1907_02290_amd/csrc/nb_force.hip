@@ -141,6 +141,7 @@ struct ForceArgs {
   const double4* __restrict__ pos;
   const double4* __restrict__ pm;
   const float4* __restrict__ quad;
+  const float4* __restrict__ jcopy;  // copied lists (COPIED), else unused
   float eps2, G;
   float4* __restrict__ acc;
 };
@@ -156,7 +157,10 @@ __device__ __forceinline__ int block_count(int valid, int blk0, int blk1) {
 // particles (ids into the particle array) and its superparticles (ids into
 // the cell array), so every tile reads from one array.  Entries past the end
 // of a segment are staged as duplicates of its last entry and never summed.
-template <int ORDER>
+// COPIED (monopole only): the group's entries were copied beforehand, as
+// FP32 offsets from its centre, to jcopy[epj_off + spj_off ...] (k_copy_j),
+// and the tiles are read from there.
+template <int ORDER, bool COPIED>
 __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
                                            float4* tile, float4* tq,
                                            float4* red) {
@@ -197,6 +201,43 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
   // monopole: both segments; quadrupole: the particle segment here, the
   // superparticles with their second moments below
   for (int seg = 0; seg < (ORDER == 1 ? 2 : 1); ++seg) {
+    if (COPIED) {
+      const uint32_t n = seg ? ns : ne;
+      if (n == 0) continue;
+      const uint32_t last = n - 1;
+      const float4* __restrict__ jc = A.jcopy + (e0 + s0) + (seg ? ne : 0u);
+      float4 J[kMaxSlices];
+#pragma unroll
+      for (int u = 0; u < kMaxSlices; ++u) {
+        if (u < q) {
+          const uint32_t e = (uint32_t)(u * kTile + lane);
+          J[u] = jc[e < last ? e : last];
+        }
+      }
+      for (uint32_t tb = 0; tb < n; tb += (uint32_t)T) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kMaxSlices; ++u)
+          if (u < q) tile[u * kTile + lane] = J[u];
+        const uint32_t nb = tb + (uint32_t)T;
+        if (nb < n) {
+#pragma unroll
+          for (int u = 0; u < kMaxSlices; ++u) {
+            if (u < q) {
+              const uint32_t e = nb + (uint32_t)(u * kTile + lane);
+              J[u] = jc[e < last ? e : last];
+            }
+          }
+        }
+        __syncthreads();
+        if (act) {
+          const int valid = n - tb < (uint32_t)T ? (int)(n - tb) : T;
+          slice_sum<1>(tile + blk0, nullptr, block_count(valid, blk0, blk1),
+                       xi, yi, zi, eps2, ax, ay, az, ph);
+        }
+      }
+      continue;
+    }
     const uint32_t* __restrict__ ids = seg ? A.spj + s0 : A.epj + e0;
     const double4* __restrict__ src = seg ? A.pm : A.pos;
     const uint32_t n = seg ? ns : ne;
@@ -306,7 +347,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
 // remapped so each XCD takes a contiguous stretch of work items.  Five waves
 // per SIMD leave room for the next tile's records in registers (93 VGPRs);
 // at six the compiler spills them.
-template <int ORDER>
+template <int ORDER, bool COPIED>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_force(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
         ForceArgs A) {
@@ -315,7 +356,38 @@ k_force(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
   const uint32_t bid = blockIdx.x;
   const int64_t w = (int64_t)(bid & 7u) * per_xcd + (int64_t)(bid >> 3);
   if (w >= n_wi) return;  // uniform over the workgroup
-  force_item<ORDER>(wi[w], A, tile, tq, tile);
+  force_item<ORDER, COPIED>(wi[w], A, tile, tq, tile);
+}
+
+// Copied lists (the paper's method G1, for comparison with index lists):
+// one wave per group writes every entry of its list, particles then
+// superparticles, as an FP32 offset from the group's centre and the mass,
+// to jc[epj_off[g] + spj_off[g] ...].  Groups are dealt to XCDs in
+// contiguous stretches as in the force kernel.
+__global__ void __launch_bounds__(256)
+k_copy_j(int64_t n_groups, int64_t nblk, const uint32_t* __restrict__ g_cell,
+         const CellRec* __restrict__ rec,
+         const uint64_t* __restrict__ epj_off,
+         const uint32_t* __restrict__ epj,
+         const uint64_t* __restrict__ spj_off,
+         const uint32_t* __restrict__ spj, const double4* __restrict__ pos,
+         const double4* __restrict__ pm, float4* __restrict__ jc) {
+  const int64_t per = (nblk + 7) / 8;
+  const int64_t blk = (int64_t)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  if (blk >= nblk) return;
+  const int64_t g = blk * 4 + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63u;
+  if (g >= n_groups) return;
+  const double4 cg = rec[g_cell[g]].geo;
+  const uint64_t e0 = epj_off[g], s0 = spj_off[g];
+  const uint32_t ne = (uint32_t)(epj_off[g + 1] - e0);
+  const uint32_t ns = (uint32_t)(spj_off[g + 1] - s0);
+  float4* __restrict__ out = jc + (e0 + s0);
+  for (uint32_t e = lane; e < ne + ns; e += 64u) {
+    const double4 P = e < ne ? pos[epj[e0 + e]] : pm[spj[s0 + (e - ne)]];
+    out[e] = make_float4((float)(P.x - cg.x), (float)(P.y - cg.y),
+                         (float)(P.z - cg.z), (float)P.w);
+  }
 }
 
 // Persistent form: a fixed number of resident workgroups, each pulling the
@@ -336,7 +408,7 @@ k_force_queue(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
     k = __shfl(k, 0, 64);
     const int64_t w = lo + (int64_t)k;
     if (w >= hi) break;  // uniform over the workgroup
-    force_item<ORDER>(wi[w], A, tile, tq, tile);
+    force_item<ORDER, false>(wi[w], A, tile, tq, tile);
     __syncthreads();  // the next item reuses the tile and reduction space
   }
 }
@@ -365,6 +437,7 @@ int launch_force(nb_ctx* c) {
   A.pos = c->pos.p;
   A.pm = c->c_pm.p;
   A.quad = c->c_quad.p;
+  A.jcopy = nullptr;
   A.eps2 = (float)(c->cfg.eps * c->cfg.eps);
   A.G = (float)c->cfg.G;
   A.acc = c->acc.p;
@@ -380,8 +453,26 @@ int launch_force(nb_ctx* c) {
     auto k = c->cfg.order == 2 ? k_force_queue<2> : k_force_queue<1>;
     hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(kTile), 0, c->stream,
                        (const uint4*)c->wi.p, c->n_wi, per_xcd, c->queue.p, A);
+  } else if (c->cfg.flags & NB_FLAG_COPIED_LISTS) {
+    // monopole only (checked with the configuration)
+    if ((rc = reserve(c, c->jcopy, (size_t)(c->n_epj + c->n_spj) + 1)))
+      return rc;
+    const int64_t cblk = grid_for(c->n_groups, 4);
+    hipLaunchKernelGGL(k_copy_j, dim3((unsigned)((cblk + 7) / 8 * 8)),
+                       dim3(256), 0, c->stream, c->n_groups, cblk,
+                       (const uint32_t*)c->g_cell.p,
+                       (const CellRec*)c->c_rec.p,
+                       (const uint64_t*)c->epj_off.p,
+                       (const uint32_t*)c->epj.p,
+                       (const uint64_t*)c->spj_off.p,
+                       (const uint32_t*)c->spj.p, (const double4*)c->pos.p,
+                       (const double4*)c->c_pm.p, c->jcopy.p);
+    A.jcopy = c->jcopy.p;
+    hipLaunchKernelGGL((k_force<1, true>), dim3((unsigned)nblk), dim3(kTile),
+                       0, c->stream, (const uint4*)c->wi.p, c->n_wi, per_xcd,
+                       A);
   } else {
-    auto k = c->cfg.order == 2 ? k_force<2> : k_force<1>;
+    auto k = c->cfg.order == 2 ? k_force<2, false> : k_force<1, false>;
     hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kTile), 0, c->stream,
                        (const uint4*)c->wi.p, c->n_wi, per_xcd, A);
   }

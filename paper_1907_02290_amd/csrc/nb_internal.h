@@ -89,6 +89,7 @@ struct nb_ctx {
   nb::DBuf<double> vx, vy, vz, vx2, vy2, vz2;
   nb::DBuf<uint32_t> orig, orig2;  // original index per internal slot
   nb::DBuf<float4> acc;            // ax, ay, az, pot (G applied)
+  nb::DBuf<float4> jcopy;          // copied lists (NB_FLAG_COPIED_LISTS)
 
   // keys and sort
   nb::DBuf<uint64_t> key, key2;

@@ -33,6 +33,7 @@ NB_FLAG_TIMING = 1
 NB_FLAG_GRAPH = 2
 NB_FLAG_REFRESH = 4
 NB_FLAG_PERSISTENT = 8
+NB_FLAG_COPIED_LISTS = 16
 MLP_NIN = 12
 MLP_NPARAM = 5057
 
@@ -142,12 +143,13 @@ class Context:
     def __init__(self, theta=0.5, eps=0.01, G=1.0, n_leaf=8, n_grp=64,
                  order=1, ext_mass=0.0, timing=False, graph=False,
                  refresh=False, k_max=8, p_star=0.5, tau=0.0,
-                 persistent=False, stream=None):
+                 persistent=False, copied_lists=False, stream=None):
         self._lib = load()
         flags = (NB_FLAG_TIMING if timing else 0) | \
             (NB_FLAG_GRAPH if graph else 0) | \
             (NB_FLAG_REFRESH if refresh else 0) | \
-            (NB_FLAG_PERSISTENT if persistent else 0)
+            (NB_FLAG_PERSISTENT if persistent else 0) | \
+            (NB_FLAG_COPIED_LISTS if copied_lists else 0)
         self._cfg = nb_config(theta, eps, G, ext_mass, n_leaf, n_grp, order,
                               flags, k_max, p_star, tau, stream)
         h = C.c_void_p()
@@ -202,6 +204,9 @@ class Context:
             elif k == "persistent":
                 self._cfg.flags = (self._cfg.flags & ~NB_FLAG_PERSISTENT) | \
                     (NB_FLAG_PERSISTENT if v else 0)
+            elif k == "copied_lists":
+                self._cfg.flags = (self._cfg.flags & ~NB_FLAG_COPIED_LISTS) | \
+                    (NB_FLAG_COPIED_LISTS if v else 0)
             else:
                 setattr(self._cfg, k, v)
         self._chk(self._lib.nb_set_config(self._h, C.byref(self._cfg)))

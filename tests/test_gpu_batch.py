@@ -181,3 +181,33 @@ def test_persistent_force_launch_is_bit_identical(order):
         ctx.close()
     for a, b in zip(*out):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("n_grp", [8, 64, 256])
+def test_copied_lists_give_the_same_forces(n_grp):
+    """Lists of copied j-data (the paper's method G1) give the forces of
+    index lists (G2) bit for bit, on a construction and a reuse step."""
+    say("case copied lists n_grp=%d" % n_grp)
+    d = _batch(seed=9, n_sys=5, lo=9, hi=14)
+    out = []
+    for copied in (False, True):
+        ctx = nb.Context(theta=0.5, eps=0.01, n_leaf=8, n_grp=n_grp, order=1,
+                         copied_lists=copied)
+        ctx.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
+                          d["m"])
+        ctx.set_systems(d["offsets"])
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        f0 = ctx.get_forces()
+        ctx.kick_drift(1 / 128, 1 / 128)
+        ctx.compute_forces(nb.NB_REUSE_LIST)
+        out.append((f0, ctx.get_forces()))
+        ctx.close()
+    for step in (0, 1):
+        for a, b in zip(out[0][step], out[1][step]):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_copied_lists_config_errors():
+    for kw in (dict(order=2), dict(refresh=True), dict(persistent=True)):
+        with pytest.raises(nb.NbError):
+            nb.Context(copied_lists=True, **kw)
