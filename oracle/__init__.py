@@ -85,6 +85,12 @@ def _load():
     lib.orc_mlp_forward.argtypes = [p, i64, p, p]
     lib.orc_mlp_loss_grad.argtypes = [p, i64, p, p, d, p, p]
     lib.orc_adam.argtypes = [p, p, p, p, i64, d, d, d, d]
+    lib.orc_neighbour_lists.argtypes = [p, d, p]
+    lib.orc_get_neighbour_lists.argtypes = [p, p, p]
+    lib.orc_sph_w.argtypes = [d, d]
+    lib.orc_sph_w.restype = d
+    lib.orc_sph_density.argtypes = [p, d, p]
+    lib.orc_sph_density_direct.argtypes = [i64, p, p, p, p, d, p]
     for f in ("orc_root", "orc_keys", "orc_info", "orc_get_keys",
               "orc_get_cells", "orc_get_moments", "orc_get_groups",
               "orc_make_lists", "orc_get_lists", "orc_refresh",
@@ -92,7 +98,8 @@ def _load():
               "orc_num_threads", "orc_group_margins", "orc_group_stale",
               "orc_refresh_lists", "orc_group_features", "orc_cell_sides",
               "orc_mlp_nparam", "orc_mlp_forward", "orc_mlp_loss_grad",
-              "orc_adam"):
+              "orc_adam", "orc_neighbour_lists", "orc_get_neighbour_lists",
+              "orc_sph_density", "orc_sph_density_direct"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -281,6 +288,25 @@ class Tree:
                                           _ptr(f)), "features")
         return f
 
+    def neighbour_lists(self, h):
+        """Neighbour lists of every group for search radius h (short-range
+        walk, section 2); returns (offsets, sorted-order ids)."""
+        n = np.zeros(1, np.int64)
+        _check(_load().orc_neighbour_lists(self._h, float(h), _ptr(n)),
+               "neighbour_lists")
+        off = np.zeros(self.n_groups + 1, np.int64)
+        ids = np.zeros(int(n[0]), np.uint32)
+        _check(_load().orc_get_neighbour_lists(self._h, _ptr(off), _ptr(ids)),
+               "get_neighbour_lists")
+        return off, ids
+
+    def sph_density(self, h):
+        """FP64 SPH density over the neighbour lists, input order."""
+        rho = np.zeros(self.n)
+        _check(_load().orc_sph_density(self._h, float(h), _ptr(rho)),
+               "sph_density")
+        return rho
+
     def force_lists(self, order=1, eps=0.0, G=1.0):
         """FP64 sum over the saved lists; NaN for particles of groups that
         were not walked.  Input order."""
@@ -336,6 +362,21 @@ def force_direct(x, y, z, m, eps=0.0, G=1.0, targets=None):
                                     float(eps), float(G), tgt.size, _ptr(tgt),
                                     *(_ptr(a) for a in out)), "force_direct")
     return tuple(out)
+
+
+def sph_w(r, h):
+    """The SPH kernel W(r, h) (cubic spline of compact support h)."""
+    return float(_load().orc_sph_w(float(r), float(h)))
+
+
+def sph_density_direct(x, y, z, m, h):
+    """SPH density over all pairs, FP64."""
+    x, y, z, m = _f64(x), _f64(y), _f64(z), _f64(m)
+    rho = np.zeros(x.size)
+    _check(_load().orc_sph_density_direct(x.size, _ptr(x), _ptr(y), _ptr(z),
+                                          _ptr(m), float(h), _ptr(rho)),
+           "sph_density_direct")
+    return rho
 
 
 def kick_drift(pos, vel, acc, dt_kick, dt_drift, ext_mass=0.0, G=1.0):

@@ -75,6 +75,10 @@ struct orc_tree {
   double *g_lo, *g_hi, *g_ctr; /* 3 per group */
   double* g_tau0;              /* 3 per group: cell shift at that walk */
   double *g_sa, *g_so;         /* opening-test slacks of that walk */
+  /* neighbour lists (short-range walk), every group */
+  int have_nbr;
+  int64_t* nb_off;
+  uint32_t* nb;
   /* lists over the last walked selection */
   int have_lists;
   int64_t n_sel;
@@ -390,6 +394,8 @@ void orc_free(orc_tree* t) {
   free(t->g_sa);
   free(t->g_so);
   free_lists(t);
+  free(t->nb_off);
+  free(t->nb);
   free(t);
 }
 
@@ -1067,6 +1073,145 @@ int orc_kick_drift(int64_t n, double* x, double* y, double* z, double* vx,
     x[i] += vx[i] * dt_drift;
     y[i] += vy[i] * dt_drift;
     z[i] += vz[i] * dt_drift;
+  }
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Short-range interactions (section 2: the same group-wise walk with an
+ * opening criterion other than the opening angle; section 4.2: such lists
+ * are reused over several steps).  Reading R18: with one search radius h,
+ * a cell that holds the group is opened; any other cell is opened when its
+ * cube overlaps the group's tight box grown by h on every side, i.e. when
+ * on every axis the gap between the box and the cell's centre is at most
+ * half the side plus h, and is skipped with its subtree otherwise; an
+ * opened leaf puts its particles on the list.  Every particle within h of a
+ * member (max norm, hence also Euclidean) is on the group's list. */
+static void nbr_walk(const orc_tree* t, int64_t g, double h, uint32_t* out,
+                     int64_t* n_out) {
+  const uint32_t gb = t->g_begin[g];
+  const uint64_t ge = (uint64_t)gb + t->g_count[g];
+  const double* lo = &t->g_lo[3 * g];
+  const double* hi = &t->g_hi[3 * g];
+  int64_t ne = 0;
+  int64_t c = 0;
+  while (c < t->n_cell) {
+    const uint32_t cb = t->begin[c];
+    const uint64_t ce = (uint64_t)cb + t->count[c];
+    int open = 1;
+    if (!(cb <= gb && ce >= ge)) {
+      const double r = ldexp(1.0, t->k - t->level[c] - 1) + h;
+      for (int a = 0; a < 3; ++a) {
+        double v = 0.0;
+        const double below = lo[a] - t->ctr[3 * c + a];
+        const double above = t->ctr[3 * c + a] - hi[a];
+        if (below > v) v = below;
+        if (above > v) v = above;
+        if (v > r) open = 0;
+      }
+    }
+    if (!open) {
+      c = t->skip[c];
+    } else if (t->leaf[c]) {
+      for (uint64_t j = cb; j < ce; ++j) {
+        if (out) out[ne] = (uint32_t)j;
+        ne++;
+      }
+      c = t->skip[c];
+    } else {
+      c = c + 1;
+    }
+  }
+  *n_out = ne;
+}
+
+int orc_neighbour_lists(orc_tree* t, double h, int64_t* n_entries) {
+  if (!t || !(h >= 0.0) || !isfinite(h) || !n_entries) return -1;
+  free(t->nb_off);
+  free(t->nb);
+  t->nb = NULL;
+  t->have_nbr = 0;
+  const int64_t ng = t->n_groups;
+  t->nb_off = (int64_t*)malloc((size_t)(ng + 1) * sizeof(int64_t));
+  int64_t* cnt = (int64_t*)malloc((size_t)(ng ? ng : 1) * sizeof(int64_t));
+  if (!t->nb_off || !cnt) {
+    free(cnt);
+    return -1;
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t g = 0; g < ng; ++g) nbr_walk(t, g, h, NULL, &cnt[g]);
+  t->nb_off[0] = 0;
+  for (int64_t g = 0; g < ng; ++g) t->nb_off[g + 1] = t->nb_off[g] + cnt[g];
+  free(cnt);
+  t->nb = (uint32_t*)malloc((size_t)(t->nb_off[ng] + 1) * sizeof(uint32_t));
+  if (!t->nb) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t g = 0; g < ng; ++g) {
+    int64_t k;
+    nbr_walk(t, g, h, t->nb + t->nb_off[g], &k);
+  }
+  t->have_nbr = 1;
+  *n_entries = t->nb_off[ng];
+  return 0;
+}
+
+int orc_get_neighbour_lists(const orc_tree* t, int64_t* off, uint32_t* ids) {
+  if (!t || !t->have_nbr) return -1;
+  if (off) memcpy(off, t->nb_off, (size_t)(t->n_groups + 1) * sizeof(int64_t));
+  if (ids) memcpy(ids, t->nb, (size_t)t->nb_off[t->n_groups] * sizeof(uint32_t));
+  return 0;
+}
+
+/* The SPH kernel (reading R18): cubic spline of compact support h,
+ * W(r, h) = 8 / (pi h^3) w(r / h), w(q) = 1 - 6 q^2 + 6 q^3 on [0, 1/2],
+ * 2 (1 - q)^3 on (1/2, 1], 0 beyond. */
+double orc_sph_w(double r, double h) {
+  const double q = r / h;
+  double w = 0.0;
+  if (q <= 0.5) {
+    w = 1.0 - 6.0 * q * q + 6.0 * q * q * q;
+  } else if (q <= 1.0) {
+    const double u = 1.0 - q;
+    w = 2.0 * u * u * u;
+  }
+  return 8.0 / (3.14159265358979323846 * h * h * h) * w;
+}
+
+/* SPH density over the neighbour lists at the positions of the last
+ * orc_build / orc_refresh: rho_i = sum over the list of i's group of
+ * m_j W(|x_i - x_j|, h), the particle itself included.  Input order. */
+int orc_sph_density(const orc_tree* t, double h, double* rho) {
+  if (!t || !t->have_nbr || !rho || !(h > 0.0) || !isfinite(h)) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t g = 0; g < t->n_groups; ++g) {
+    const int64_t b = t->g_begin[g], e = b + t->g_count[g];
+    for (int64_t i = b; i < e; ++i) {
+      double sum = 0.0;
+      for (int64_t q = t->nb_off[g]; q < t->nb_off[g + 1]; ++q) {
+        const int64_t j = t->nb[q];
+        const double dx = t->x[j] - t->x[i], dy = t->y[j] - t->y[i],
+                     dz = t->z[j] - t->z[i];
+        sum += t->m[j] * orc_sph_w(sqrt(dx * dx + dy * dy + dz * dz), h);
+      }
+      rho[t->perm[i]] = sum;
+    }
+  }
+  return 0;
+}
+
+/* The same density over all pairs (the quantity the lists must reproduce). */
+int orc_sph_density_direct(int64_t n, const double* x, const double* y,
+                           const double* z, const double* m, double h,
+                           double* rho) {
+  if (n < 0 || !x || !y || !z || !m || !rho || !(h > 0.0)) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double sum = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      const double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+      sum += m[j] * orc_sph_w(sqrt(dx * dx + dy * dy + dz * dz), h);
+    }
+    rho[i] = sum;
   }
   return 0;
 }

@@ -135,6 +135,18 @@ int orc_kick_drift(int64_t n, double* x, double* y, double* z, double* vx,
 /* Threads the OpenMP runtime gives the per-group loops. */
 int orc_num_threads(void);
 
+/* Short-range interactions (section 2, section 4.2).  Neighbour lists for
+ * search radius h over every group (EPJ only, sorted-order ids); the SPH
+ * kernel W(r, h); densities over the lists (input order) and over all
+ * pairs. */
+int orc_neighbour_lists(orc_tree* t, double h, int64_t* n_entries);
+int orc_get_neighbour_lists(const orc_tree* t, int64_t* off, uint32_t* ids);
+double orc_sph_w(double r, double h);
+int orc_sph_density(const orc_tree* t, double h, double* rho);
+int orc_sph_density_direct(int64_t n, const double* x, const double* y,
+                           const double* z, const double* m, double h,
+                           double* rho);
+
 #ifdef __cplusplus
 }
 #endif
