@@ -253,6 +253,46 @@ int nb_get_lists(nb_ctx* ctx, int64_t* epj_off, uint32_t* epj,
  * needs cfg.flags bit 0.  reset != 0 clears the counters after reading. */
 int nb_get_timing(nb_ctx* ctx, double* ms, int64_t* calls, int reset);
 
+/* ---- short-range interactions ----------------------------------------
+ * Section 2: short-range interactions (SPH) use the same group-wise tree
+ * walk with a cell-opening criterion other than the opening angle;
+ * section 4.2: their lists are kept over several steps.
+ *
+ * Neighbour lists for the search radius h_list over every group of the
+ * current tree: a cell that holds the group is opened; any other cell when
+ * its cube overlaps the group's tight box grown by h_list on every side
+ * (on each axis the gap from the box to the cell's centre is at most half
+ * the side plus h_list, FP64), and is skipped with its subtree otherwise;
+ * an opened leaf adds its particles (internal slots, DFS order).  Every
+ * particle within h_list of a member is on the member's group list, the
+ * member included.  The lists stay valid through kick-drift steps (the
+ * particle order is kept) until the next tree build: built with
+ * h_list = h (1 + s), they hold every pair within h while no particle has
+ * moved more than s h / 2 since.  Timed as the walk phase.
+ * Errors: NB_ERR_INPUT (h_list negative or not finite), NB_ERR_STATE (no
+ * tree of the current positions), NB_ERR_OOM, NB_ERR_HIP. */
+int nb_neighbour_lists(nb_ctx* ctx, double h_list);
+
+/* SPH density on the neighbour lists at the current positions:
+ * rho_i = sum over the list of i's group of m_j W(|x_i - x_j|, h), W the
+ * cubic spline of compact support h, W(r, h) = 8 / (pi h^3) w(r / h),
+ * w(q) = 1 - 6 q^2 + 6 q^3 (q <= 1/2), 2 (1 - q)^3 (1/2 < q <= 1), 0
+ * beyond; FP32 offsets from the group centre and FP32 sums, as in the force
+ * kernel.  Timed as the force phase.
+ * Errors: NB_ERR_STATE (no neighbour lists), NB_ERR_INPUT (h <= 0 or
+ * h > h_list of the lists). */
+int nb_sph_density(nb_ctx* ctx, double h);
+
+/* The densities (n values; internal as for nb_get_forces); synchronises.
+ * Errors: NB_ERR_STATE (no density computed), NB_ERR_INPUT (NULL). */
+int nb_get_density(nb_ctx* ctx, double* rho, int internal);
+
+/* The neighbour lists: n_entries (may be NULL) gets the total entry
+ * count; off (n_groups + 1 values) and ids (n_entries values, internal
+ * slots) may be NULL.  Synchronises.  Errors: NB_ERR_STATE (no lists). */
+int nb_get_neighbour_lists(nb_ctx* ctx, int64_t* n_entries, int64_t* off,
+                           uint32_t* ids);
+
 /* ---- per-group list refresh (NB_FLAG_REFRESH) --------------------------
  * An extension of the list reuse of section 4.2, which keeps every list for
  * a fixed number of steps.  Cells keep their particle ranges between

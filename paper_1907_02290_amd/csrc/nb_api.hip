@@ -146,6 +146,7 @@ static int build_tree(nb_ctx* c) {
   drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = c->forces_valid = false;
+  c->nbr_valid = c->rho_valid = false;
   {
     Timed t(c, NB_PH_ROOT);
     if ((rc = launch_root(c))) return rc;
@@ -364,6 +365,8 @@ void nb_destroy(nb_ctx* c) {
   release(c->gflag); release(c->g_cell); release(c->g_begin);
   release(c->g_count); release(c->g_lo); release(c->g_hi);
   release(c->g_chunks); release(c->wi); release(c->queue);
+  release(c->nb_cnt); release(c->nb_tcnt); release(c->nb_ids);
+  release(c->nb_off); release(c->nb_toff); release(c->rho);
   release(c->cnt_e); release(c->cnt_s); release(c->cnt_t);
   release(c->epj_off); release(c->spj_off); release(c->tok_off);
   release(c->epj); release(c->spj); release(c->tok);
@@ -396,6 +399,7 @@ int nb_set_config(nb_ctx* c, const nb_config* cfg) {
   drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = false;
+  c->nbr_valid = c->rho_valid = false;
   return NB_OK;
 }
 
@@ -411,6 +415,7 @@ int nb_set_particles(nb_ctx* c, int64_t n, const double* x, const double* y,
   drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = c->forces_valid = false;
+  c->nbr_valid = c->rho_valid = false;
   const size_t un = (size_t)n;
   int rc = reserve(c, c->pos, un);
   if (!rc) rc = reserve(c, c->vx, un);
@@ -477,6 +482,7 @@ int nb_set_systems(nb_ctx* c, int64_t n_sys, const int64_t* off) {
   drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = false;
+  c->nbr_valid = c->rho_valid = false;
   c->n_sys = n_sys;
   c->h_sys_off.assign(off, off + n_sys + 1);
   return launch_seg_fill(c);
@@ -650,6 +656,90 @@ int nb_get_forces(nb_ctx* c, double* ax, double* ay, double* az, double* pot,
     pot[d] = a[i].w;
   }
   return NB_OK;
+}
+
+int nb_neighbour_lists(nb_ctx* c, double h_list) {
+  if (!c) return NB_ERR_INPUT;
+  if (!(h_list >= 0.0) || !std::isfinite(h_list))
+    return set_err(c, NB_ERR_INPUT, "search radius must be finite and >= 0");
+  if (!c->tree_valid || !c->positions_fresh)
+    return set_err(c, NB_ERR_STATE,
+                   "neighbour lists need a tree of the current positions");
+  c->nbr_valid = c->rho_valid = false;
+  int rc;
+  {
+    Timed t(c, NB_PH_WALK);
+    if ((rc = launch_nbr_count(c, h_list))) return rc;
+  }
+  // totals, and the work-item count of the tree's groups (the density
+  // kernel runs on the force kernel's work items)
+  if ((rc = stage_d2h(c, 0, c->nb_off.p + c->n_groups, 8))) return rc;
+  if ((rc = stage_d2h(c, 8, c->nb_toff.p + c->n_groups, 8))) return rc;
+  if ((rc = stage_d2h(c, 16, c->g_chunks.p + c->n_groups, 4))) return rc;
+  if ((rc = sync(c))) return rc;
+  const uint64_t* hs = static_cast<const uint64_t*>(c->h_small);
+  c->n_nbr = (int64_t)hs[0];
+  const int64_t n_tok = (int64_t)hs[1];
+  c->n_wi = static_cast<const uint32_t*>(c->h_small)[4];
+  if ((rc = reserve(c, c->nb_ids, (size_t)c->n_nbr + 1))) return rc;
+  if ((rc = reserve(c, c->tok, (size_t)n_tok + 1))) return rc;
+  {
+    Timed t(c, NB_PH_WALK);
+    if ((rc = launch_nbr_fill(c, h_list))) return rc;
+  }
+  c->nbr_h = h_list;
+  c->nbr_valid = true;
+  return NB_OK;
+}
+
+int nb_sph_density(nb_ctx* c, double h) {
+  if (!c) return NB_ERR_INPUT;
+  if (!c->nbr_valid) return set_err(c, NB_ERR_STATE, "no neighbour lists");
+  if (!(h > 0.0) || !(h <= c->nbr_h))
+    return set_err(c, NB_ERR_INPUT,
+                   "h must be > 0 and at most the lists' search radius");
+  c->rho_valid = false;
+  int rc;
+  {
+    Timed t(c, NB_PH_FORCE);
+    rc = launch_density(c, h);
+  }
+  if (rc) return rc;
+  c->rho_valid = true;
+  return NB_OK;
+}
+
+int nb_get_density(nb_ctx* c, double* rho, int internal) {
+  if (!c) return NB_ERR_INPUT;
+  if (!rho) return set_err(c, NB_ERR_INPUT, "NULL output array");
+  if (!c->rho_valid) return set_err(c, NB_ERR_STATE, "no density computed");
+  const size_t n = (size_t)c->n;
+  std::vector<float> a(n);
+  std::vector<uint32_t> o(n);
+  int rc = sync(c);
+  if (!rc) rc = hip_check(c, hipMemcpy(a.data(), c->rho.p, n * sizeof(float),
+                                       hipMemcpyDeviceToHost), "rho readback");
+  if (!rc) rc = hip_check(c, hipMemcpy(o.data(), c->orig.p, n * 4,
+                                       hipMemcpyDeviceToHost), "orig readback");
+  if (rc) return rc;
+  for (size_t i = 0; i < n; ++i) rho[internal ? i : o[i]] = a[i];
+  return NB_OK;
+}
+
+int nb_get_neighbour_lists(nb_ctx* c, int64_t* n_entries, int64_t* off,
+                           uint32_t* ids) {
+  if (!c) return NB_ERR_INPUT;
+  if (!c->nbr_valid) return set_err(c, NB_ERR_STATE, "no neighbour lists");
+  if (n_entries) *n_entries = c->n_nbr;
+  int rc = sync(c);
+  if (!rc && off)
+    rc = hip_check(c, hipMemcpy(off, c->nb_off.p,
+                                ((size_t)c->n_groups + 1) * 8,
+                                hipMemcpyDeviceToHost), "list readback");
+  if (!rc && ids && c->n_nbr > 0)
+    rc = hip_check(c, hipMemcpy(ids, c->nb_ids.p, (size_t)c->n_nbr * 4,
+                                hipMemcpyDeviceToHost), "list readback");
+  return rc;
 }
 
 int nb_get_state(nb_ctx* c, double* x, double* y, double* z, double* vx,

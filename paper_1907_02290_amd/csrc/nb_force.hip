@@ -413,6 +413,82 @@ k_force_queue(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
   }
 }
 
+// SPH density on the short-range neighbour lists (section 2's short-range
+// interaction): rho_i = norm * sum_j m_j w(|x_i - x_j| / h) over the list
+// of i's group, w the cubic spline of compact support (1 - 6 q^2 + 6 q^3 up
+// to q = 1/2, 2 (1 - q)^3 up to 1, 0 beyond), norm = 8 / (pi h^3).  The
+// work items, lane slices, FP32 offsets from the group centre and LDS tiles
+// are the force kernel's; a slice takes a block of every 64-entry tile.
+__global__ void __launch_bounds__(64)
+k_density(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
+          const uint32_t* __restrict__ g_cell,
+          const CellRec* __restrict__ rec,
+          const uint64_t* __restrict__ nb_off,
+          const uint32_t* __restrict__ nb_ids,
+          const double4* __restrict__ pos, float h2inv, float norm,
+          float* __restrict__ rho) {
+  __shared__ float4 tile[kTile];
+  __shared__ float red[kTile];
+  const uint32_t bid = blockIdx.x;
+  const int64_t w = (int64_t)(bid & 7u) * per_xcd + (int64_t)(bid >> 3);
+  if (w >= n_wi) return;  // uniform over the workgroup
+  const uint4 it = wi[w];
+  const int lane = threadIdx.x;
+  const int ni = (int)it.z;
+  const int r = kTile / ni;
+  const int sl = lane / ni;
+  const int ii = lane - sl * ni;
+  const bool act = sl < r;
+  const int blk0 = (sl * kTile) / r, blk1 = ((sl + 1) * kTile) / r;
+  const uint32_t g = it.x;
+  const double4 cg = rec[g_cell[g]].geo;
+  float xi = 0.f, yi = 0.f, zi = 0.f;
+  if (act) {
+    const double4 p = pos[it.y + ii];
+    xi = (float)(p.x - cg.x);
+    yi = (float)(p.y - cg.y);
+    zi = (float)(p.z - cg.z);
+  }
+  const uint64_t o0 = nb_off[g];
+  const uint32_t n = (uint32_t)(nb_off[g + 1] - o0);
+  const uint32_t last = n ? n - 1 : 0;
+  float sum = 0.f;
+  for (uint32_t tb = 0; tb < n; tb += (uint32_t)kTile) {
+    const uint32_t e = tb + (uint32_t)lane;
+    const double4 P = pos[nb_ids[o0 + (e < last ? e : last)]];
+    __syncthreads();
+    tile[lane] = make_float4((float)(P.x - cg.x), (float)(P.y - cg.y),
+                             (float)(P.z - cg.z), (float)P.w);
+    __syncthreads();
+    if (act) {
+      const int valid = n - tb < (uint32_t)kTile ? (int)(n - tb) : kTile;
+      const int hi = blk1 < valid ? blk1 : valid;
+      for (int k = blk0; k < hi; ++k) {
+        const float4 j = tile[k];
+        const float dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
+        const float q2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx)) * h2inv;
+        if (q2 < 1.f) {
+          const float q = __builtin_sqrtf(q2);
+          const float u = 1.f - q;
+          const float wq =
+              q <= 0.5f ? fmaf(6.f * q2, q - 1.f, 1.f) : 2.f * u * u * u;
+          sum = fmaf(j.w, wq, sum);
+        }
+      }
+    }
+  }
+  if (r > 1) {
+    __syncthreads();
+    red[lane] = sum;
+    __syncthreads();
+    if (lane < ni) {
+      sum = 0.f;
+      for (int s2 = 0; s2 < r; ++s2) sum += red[s2 * ni + lane];
+    }
+  }
+  if (lane < ni) rho[it.y + lane] = norm * sum;
+}
+
 __global__ void k_zero_queue(unsigned int* q) {
   if (threadIdx.x < 8) q[threadIdx.x] = 0u;
 }
@@ -477,6 +553,24 @@ int launch_force(nb_ctx* c) {
                        (const uint4*)c->wi.p, c->n_wi, per_xcd, A);
   }
   return hip_check(c, hipGetLastError(), "force launch");
+}
+
+
+// SPH density with smoothing length h on the neighbour lists.
+int launch_density(nb_ctx* c, double h) {
+  int rc = reserve(c, c->rho, (size_t)c->n);
+  if (rc) return rc;
+  if (c->n_wi <= 0) return NB_OK;
+  const int64_t per_xcd = (c->n_wi + 7) / 8;
+  const double pi = 3.14159265358979323846;
+  hipLaunchKernelGGL(k_density, dim3((unsigned)(per_xcd * 8)), dim3(kTile), 0,
+                     c->stream, (const uint4*)c->wi.p, c->n_wi, per_xcd,
+                     (const uint32_t*)c->g_cell.p, (const CellRec*)c->c_rec.p,
+                     (const uint64_t*)c->nb_off.p,
+                     (const uint32_t*)c->nb_ids.p, (const double4*)c->pos.p,
+                     (float)(1.0 / (h * h)), (float)(8.0 / (pi * h * h * h)),
+                     c->rho.p);
+  return hip_check(c, hipGetLastError(), "density launch");
 }
 
 }  // namespace nb

@@ -124,6 +124,16 @@ struct nb_ctx {
   nb::DBuf<uint4> wi;           // force work items: group, first, count
   nb::DBuf<unsigned int> queue;  // per-XCD counters of the persistent launch
 
+  // short-range neighbour lists (nb_neighbour_lists): per group the
+  // particle-slot candidates within the search radius nbr_h, and the SPH
+  // densities computed on them
+  bool nbr_valid = false, rho_valid = false;
+  double nbr_h = 0.0;
+  int64_t n_nbr = 0;
+  nb::DBuf<uint32_t> nb_cnt, nb_tcnt, nb_ids;
+  nb::DBuf<uint64_t> nb_off, nb_toff;
+  nb::DBuf<float> rho;
+
   // lists
   nb::DBuf<uint32_t> cnt_e, cnt_s, cnt_t;
   nb::DBuf<uint64_t> epj_off, spj_off, tok_off;
@@ -246,6 +256,12 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
 int launch_expand_slab(nb_ctx* c, uint32_t slab);
 int walk_tile(int64_t n_walk);  // lanes per group of the walk
 int launch_list_stats(nb_ctx* c);
+// short-range walk: count pass (nb_cnt, nb_tcnt and their scans) and, with
+// the totals known, the fill pass and expand into nb_ids
+int launch_nbr_count(nb_ctx* c, double h);
+int launch_nbr_fill(nb_ctx* c, double h);
+// SPH density on the neighbour lists into c->rho
+int launch_density(nb_ctx* c, double h);
 int launch_interactions(nb_ctx* c, const uint32_t* ne, const uint32_t* ns);
 // nb_learn.hip
 int learn_reserve_cells(nb_ctx* c);

@@ -428,6 +428,101 @@ k_max_u32(int64_t n, const uint32_t* __restrict__ v,
   if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
+// Short-range walk (section 2: the same group walk with another opening
+// rule; reuse as in section 4.2).  A cell that holds the group is opened;
+// any other cell when its cube overlaps the group's tight box grown by h on
+// every side: on each axis the gap between the box and the cell's centre
+// (zero inside) is at most half the cell's side plus h.  Cells that fail
+// are skipped with their subtree; an opened leaf becomes a token, expanded
+// into its particles as for the gravity lists.  FP64, explicit rounding.
+template <bool FILL>
+__global__ void __launch_bounds__(kWalkThreads)
+k_walk_nbr(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
+           const uint32_t* __restrict__ g_count,
+           const double4* __restrict__ g_lo, const double4* __restrict__ g_hi,
+           const CellRec* __restrict__ rec, const uint32_t* __restrict__ seg,
+           const uint32_t* __restrict__ croot, const Root* __restrict__ root,
+           double h, uint32_t* __restrict__ cnt_e,
+           uint32_t* __restrict__ cnt_t, const uint64_t* __restrict__ tok_off,
+           uint32_t* __restrict__ tok) {
+  __shared__ uint32_t stage[FILL ? kSeg : 1][kWalkThreads];
+  const int64_t blk = xcd_block(nblk);
+  if (blk >= nblk) return;
+  const int64_t g = blk * kWalkThreads + threadIdx.x;
+  if (g >= n_walk) return;
+  const uint32_t gb = g_begin[g];
+  const uint32_t ge = gb + g_count[g];
+  const double4 lo = g_lo[g], hi = g_hi[g];
+  const uint32_t sys = seg[gb];
+  const int k = root[sys].k;
+  uint32_t c = croot[sys];
+  const uint32_t nc = croot[sys + 1];
+  uint64_t out = FILL ? tok_off[g] : 0;
+  int sc = 0;
+  uint32_t ne = 0, nl = 0;
+  while (c < nc) {
+    const uint4 m = rec[c].meta;
+    bool open = true;
+    if (!(m.x <= gb && m.y >= ge)) {
+      const double4 cc = rec[c].geo;
+      const double r =
+          __dadd_rn(ldexp(1.0, k - (int)(m.w & 0xFFu) - 1), h);
+      double t, v;
+      v = 0.0;
+      t = __dsub_rn(lo.x, cc.x);
+      if (t > v) v = t;
+      t = __dsub_rn(cc.x, hi.x);
+      if (t > v) v = t;
+      if (v > r) open = false;
+      v = 0.0;
+      t = __dsub_rn(lo.y, cc.y);
+      if (t > v) v = t;
+      t = __dsub_rn(cc.y, hi.y);
+      if (t > v) v = t;
+      if (v > r) open = false;
+      v = 0.0;
+      t = __dsub_rn(lo.z, cc.z);
+      if (t > v) v = t;
+      t = __dsub_rn(cc.z, hi.z);
+      if (t > v) v = t;
+      if (v > r) open = false;
+    }
+    const bool leaf = (m.w >> 8) & 1u;
+    const uint32_t next = (!open || leaf) ? m.z : c + 1;
+    if (next <= c) break;
+    if (open && leaf) {
+      ++nl;
+      ne += m.y - m.x;
+      if (FILL) {
+        stage[sc][threadIdx.x] = c | kLeafTag;
+        ++sc;
+        if (((out + sc) & (kSeg - 1)) == 0) {
+          if (sc == kSeg) {
+            uint4* d4 = reinterpret_cast<uint4*>(tok + out);
+#pragma unroll
+            for (int q = 0; q < kSeg / 4; ++q)
+              d4[q] = make_uint4(stage[4 * q][threadIdx.x],
+                                 stage[4 * q + 1][threadIdx.x],
+                                 stage[4 * q + 2][threadIdx.x],
+                                 stage[4 * q + 3][threadIdx.x]);
+          } else {
+            for (int q = 0; q < sc; ++q) tok[out + q] = stage[q][threadIdx.x];
+          }
+          out += sc;
+          sc = 0;
+        }
+      }
+    }
+    c = next;
+  }
+  if (FILL) {
+    for (int q = 0; q < sc; ++q) tok[out + q] = stage[q][threadIdx.x];
+  } else {
+    cnt_e[g] = ne;
+    cnt_t[g] = nl;
+  }
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int n) {
   if (threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
@@ -582,6 +677,64 @@ int launch_interactions(nb_ctx* c, const uint32_t* ne, const uint32_t* ns) {
                      c->n_groups, (const uint32_t*)c->g_count.p, ne, ns,
                      (unsigned long long*)c->red.p);
   return hip_check(c, hipGetLastError(), "list stats launch");
+}
+
+
+// Short-range walk, count pass: per-group entries and tokens, their CSR
+// offsets (nb_off, nb_toff; totals at [n_groups]).
+int launch_nbr_count(nb_ctx* c, double h) {
+  if (c->n_cell >= (int64_t)kLeafTag)
+    return set_err(c, NB_ERR_INPUT, "too many cells for 31-bit list tokens");
+  const size_t ng = (size_t)c->n_groups;
+  int rc = reserve(c, c->nb_cnt, ng);
+  if (!rc) rc = reserve(c, c->nb_tcnt, ng);
+  if (!rc) rc = reserve(c, c->nb_off, ng + 1);
+  if (!rc) rc = reserve(c, c->nb_toff, ng + 1);
+  if (rc) return rc;
+  const int64_t nblk = grid_for(c->n_groups, kWalkThreads);
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_walk_nbr<false>, dim3((unsigned)((nblk + 7) / 8 * 8)),
+                       dim3(kWalkThreads), 0, c->stream, c->n_groups, nblk,
+                       (const uint32_t*)c->g_begin.p,
+                       (const uint32_t*)c->g_count.p,
+                       (const double4*)c->g_lo.p, (const double4*)c->g_hi.p,
+                       (const CellRec*)c->c_rec.p, (const uint32_t*)c->seg.p,
+                       (const uint32_t*)c->croot.p, (const Root*)c->root.p, h,
+                       c->nb_cnt.p, c->nb_tcnt.p, (const uint64_t*)nullptr,
+                       (uint32_t*)nullptr);
+  if ((rc = hip_check(c, hipGetLastError(), "neighbour walk launch")))
+    return rc;
+  rc = scan_u32_to_u64(c, c->nb_cnt.p, c->nb_off.p, c->n_groups);
+  if (!rc) rc = scan_u32_to_u64(c, c->nb_tcnt.p, c->nb_toff.p, c->n_groups);
+  return rc;
+}
+
+// Fill pass into c->tok (n tokens reserved) and expand into c->nb_ids.
+int launch_nbr_fill(nb_ctx* c, double h) {
+  const int64_t nblk = grid_for(c->n_groups, kWalkThreads);
+  if (nblk <= 0) return NB_OK;
+  hipLaunchKernelGGL(k_walk_nbr<true>, dim3((unsigned)((nblk + 7) / 8 * 8)),
+                     dim3(kWalkThreads), 0, c->stream, c->n_groups, nblk,
+                     (const uint32_t*)c->g_begin.p,
+                     (const uint32_t*)c->g_count.p,
+                     (const double4*)c->g_lo.p, (const double4*)c->g_hi.p,
+                     (const CellRec*)c->c_rec.p, (const uint32_t*)c->seg.p,
+                     (const uint32_t*)c->croot.p, (const Root*)c->root.p, h,
+                     (uint32_t*)nullptr, (uint32_t*)nullptr,
+                     (const uint64_t*)c->nb_toff.p, c->tok.p);
+  int rc = hip_check(c, hipGetLastError(), "neighbour fill launch");
+  if (rc) return rc;
+  // only leaf tokens: the superparticle side of the expand is never written
+  const int64_t eblk = grid_for(c->n_groups, 4);
+  hipLaunchKernelGGL(k_expand, dim3((unsigned)((eblk + 7) / 8 * 8)),
+                     dim3(256), 0, c->stream, c->n_groups, eblk,
+                     (const uint32_t*)nullptr, (const uint64_t*)c->nb_toff.p,
+                     0u, (const uint32_t*)c->nb_tcnt.p,
+                     (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
+                     (const uint64_t*)c->nb_off.p,
+                     (const uint64_t*)c->nb_off.p, c->nb_ids.p,
+                     (uint32_t*)nullptr);
+  return hip_check(c, hipGetLastError(), "neighbour expand launch");
 }
 
 }  // namespace nb

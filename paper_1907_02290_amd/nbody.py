@@ -95,6 +95,10 @@ def load():
         "nb_get_root": ([p, p, p], i32),
         "nb_get_roots": ([p, p, p], i32),
         "nb_set_systems": ([p, i64, p], i32),
+        "nb_neighbour_lists": ([p, d], i32),
+        "nb_sph_density": ([p, d], i32),
+        "nb_get_density": ([p, p, i32], i32),
+        "nb_get_neighbour_lists": ([p, p, p, p], i32),
         "nb_get_keys": ([p, p, p], i32),
         "nb_get_cells": ([p] + [p] * 7, i32),
         "nb_get_moments": ([p, p, p, p], i32),
@@ -337,6 +341,31 @@ class Context:
         self._chk(self._lib.nb_get_lists(self._h, _ptr(eo), _ptr(e), _ptr(so),
                                          _ptr(s)))
         return eo, e, so, s
+
+    # ---- short-range interactions ----
+    def neighbour_lists(self, h_list):
+        """Neighbour lists of every group for search radius h_list."""
+        self._chk(self._lib.nb_neighbour_lists(self._h, float(h_list)))
+
+    def sph_density(self, h):
+        self._chk(self._lib.nb_sph_density(self._h, float(h)))
+
+    def get_density(self, internal=False):
+        rho = np.zeros(self.n)
+        self._chk(self._lib.nb_get_density(self._h, _ptr(rho),
+                                           1 if internal else 0))
+        return rho
+
+    def get_neighbour_lists(self):
+        ne = np.zeros(1, np.int64)
+        self._chk(self._lib.nb_get_neighbour_lists(self._h, _ptr(ne), None,
+                                                   None))
+        ng = self.get_info()["n_groups"]
+        off = np.zeros(ng + 1, np.int64)
+        ids = np.zeros(int(ne[0]), np.uint32)
+        self._chk(self._lib.nb_get_neighbour_lists(self._h, None, _ptr(off),
+                                                   _ptr(ids)))
+        return off, ids
 
     def get_timing(self, reset=False):
         ms = np.zeros(len(PHASES))
