@@ -359,7 +359,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->bbox_chunks); release(c->bbox_first); release(c->seg);
   release(c->sys_off); release(c->croot);
   release(c->lam); release(c->lmin); release(c->cstart);
-  release(c->c_rec);
+  release(c->c_rec); release(c->c_wrec);
   release(c->c_mom); release(c->c_quad); release(c->c_pm);
   release(c->lvl_cells); release(c->bucket);
   release(c->gflag); release(c->g_cell); release(c->g_begin);

@@ -21,6 +21,7 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 struct Root {
   double lo[3];
   double rcrit2[kLevels];  // (side_l / theta)^2 per level
+  double rr;               // (1/theta)^2: rcrit2[l] = ldexp(rr, 2 (k - l))
   int32_t k;               // side of the root cube = 2^k
   int32_t bad;             // non-zero: a non-finite coordinate was seen
 };
@@ -35,6 +36,17 @@ struct __attribute__((aligned(64))) CellRec {
   uint4 meta;
   uint4 aux;
 };
+
+// The walk's view of a cell in 16 bytes (one load per visit):
+//   x, y = integer coordinates of the cell at its level, packed as
+//          qx | qy << 21 | qz << 42 over the 64 bits x | y << 32, and the
+//          leaf flag in bit 31 of y
+//   z    = id after the subtree
+//   w    = level | particle count << 5 for leaves (saturated at
+//          kWalkCountSat; the exact count is in CellRec), 0 otherwise
+// The walk rebuilds the centre and (side / theta)^2 from these with the same
+// FP64 operations as the tree build, so the opening test is unchanged.
+constexpr uint32_t kWalkCountSat = (1u << 27) - 1u;
 
 // A device buffer that only grows.
 template <class T>
@@ -110,6 +122,7 @@ struct nb_ctx {
 
   // cells (DFS pre-order)
   nb::DBuf<nb::CellRec> c_rec;
+  nb::DBuf<uint4> c_wrec;    // 16-byte walk records, same ids
   nb::DBuf<float4> c_mom;    // COM offset from the centre (FP32), mass
   nb::DBuf<float4> c_quad;   // 2 per cell: xx yy zz xy | xz yz 0 0
   nb::DBuf<double4> c_pm;    // absolute COM (FP64) and mass: SPJ record

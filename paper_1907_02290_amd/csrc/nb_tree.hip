@@ -163,6 +163,7 @@ k_bbox_final(const double* __restrict__ part,
     while (ldexp(1.0, k - 1) > ext) k--;
   }
   root->k = k;
+  root->rr = rr;
   root->bad = (s[0][6] != 0.0 || !isfinite(ext)) ? 1 : 0;
   for (int l = 0; l < kLevels; ++l) root->rcrit2[l] = ldexp(rr, 2 * (k - l));
 }
@@ -313,7 +314,7 @@ k_link_fill(const uint64_t* __restrict__ key, int64_t n,
             const uint32_t* __restrict__ sys_off,
             const uint8_t* __restrict__ lam, const uint8_t* __restrict__ lmin,
             const uint32_t* __restrict__ S, const Root* __restrict__ roots,
-            CellRec* __restrict__ rec) {
+            CellRec* __restrict__ rec, uint4* __restrict__ wrec) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int la = lam[i], lm = lmin[i];
@@ -354,6 +355,14 @@ k_link_fill(const uint64_t* __restrict__ key, int64_t n,
                         (uint32_t)l | (l == la ? 256u : 0u));
     r.aux = make_uint4(par, 0u, 0u, 0u);
     rec[id] = r;
+    const uint64_t q = (uint64_t)qx | ((uint64_t)qy << 21) |
+                       ((uint64_t)qz << 42);
+    const bool leaf = l == la;
+    uint64_t cnt = leaf ? (uint64_t)(end - i) : 0;
+    if (cnt > kWalkCountSat) cnt = kWalkCountSat;
+    wrec[id] = make_uint4((uint32_t)q,
+                          (uint32_t)(q >> 32) | (leaf ? 0x80000000u : 0u),
+                          skip, (uint32_t)l | ((uint32_t)cnt << 5));
   }
 }
 
@@ -754,13 +763,14 @@ int launch_link_count(nb_ctx* c) {
 
 int launch_link_fill(nb_ctx* c) {
   int rc = reserve(c, c->c_rec, (size_t)c->n_cell);
+  if (!rc) rc = reserve(c, c->c_wrec, (size_t)c->n_cell);
   if (rc) return rc;
   hipLaunchKernelGGL(k_link_fill, dim3(grid_for(c->n, 256)), dim3(256), 0,
                      c->stream, (const uint64_t*)c->key.p, c->n,
                      (const uint32_t*)c->seg.p, (const uint32_t*)c->sys_off.p,
                      (const uint8_t*)c->lam.p, (const uint8_t*)c->lmin.p,
                      (const uint32_t*)c->cstart.p, (const Root*)c->root.p,
-                     c->c_rec.p);
+                     c->c_rec.p, c->c_wrec.p);
   hipLaunchKernelGGL(k_sys_roots, dim3(grid_for(c->n_sys + 1, 256)),
                      dim3(256), 0, c->stream, (const uint32_t*)c->cstart.p,
                      (const uint32_t*)c->sys_off.p, c->n_sys, c->croot.p);

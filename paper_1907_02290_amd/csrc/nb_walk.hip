@@ -181,6 +181,158 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   }
 }
 
+// The one-thread walk over the 16-byte walk records (one load per visit
+// instead of the 64-byte cell record's three).  The centre and
+// (side / theta)^2 of a cell come from its integer coordinates and level by
+// the tree build's own FP64 operations, so every opening decision, and the
+// token stream, is the same as from the cell records.  A cell holds the
+// group's particle range exactly when it is an ancestor of, or is, the
+// deepest cell with that range (cell ranges are nested or disjoint and never
+// empty), i.e. when c <= gd < skip(c) in pre-order.
+template <bool FILL>
+__global__ void __launch_bounds__(kWalkThreads)
+k_walk_c(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
+         const uint32_t* __restrict__ g_count,
+         const double4* __restrict__ g_lo, const double4* __restrict__ g_hi,
+         const uint32_t* __restrict__ g_cell, const CellRec* __restrict__ rec,
+         const uint4* __restrict__ wrec, const Root* __restrict__ roots,
+         const uint32_t* __restrict__ seg, const uint32_t* __restrict__ croot,
+         uint32_t* __restrict__ cnt_e, uint32_t* __restrict__ cnt_s,
+         uint32_t* __restrict__ cnt_t, const uint64_t* __restrict__ tok_off,
+         uint32_t* __restrict__ tok, uint32_t slab) {
+  __shared__ uint32_t stage[FILL ? kSeg : 1][kWalkThreads];
+  const int64_t blk = xcd_block(nblk);
+  if (blk >= nblk) return;
+  const int64_t g = blk * kWalkThreads + threadIdx.x;
+  if (g >= n_walk) return;
+  const uint32_t gb = g_begin[g];
+  const uint32_t ge = gb + g_count[g];
+  const double4 lo = g_lo[g], hi = g_hi[g];
+  // deepest cell whose range is the group's: down the chain of only children
+  uint32_t gd = g_cell[g];
+  for (;;) {
+    if ((rec[gd].meta.w >> 8) & 1u) break;
+    const uint4 m1 = rec[gd + 1].meta;
+    if (m1.x != gb || m1.y != ge) break;
+    ++gd;
+  }
+  uint32_t* dst = nullptr;
+  uint64_t out = 0;
+  uint64_t end = 0;
+  int sc = 0;
+  if (FILL) {
+    out = slab ? (uint64_t)g * slab : tok_off[g];
+    end = slab ? out + slab : ~0ull;
+    dst = tok;
+  }
+  const bool counts = !FILL || slab != 0;
+  uint32_t ne = 0, ns = 0, nl = 0;
+  const uint32_t sys = seg[gb];
+  const Root* root = roots + sys;
+  const double rx = root->lo[0], ry = root->lo[1], rz = root->lo[2];
+  const double rr = root->rr;
+  const int k = root->k;
+  uint32_t c = croot[sys];
+  const uint32_t nc = croot[sys + 1];
+  // Loads and stores share one completion counter, so the wait for a
+  // visit's record also waits for every store issued before it.  A full
+  // segment read from the stage is therefore stored in the next visit, right
+  // after that visit's record has arrived: the stores then have a whole
+  // visit to complete before the following wait.  The loop-invariant loads
+  // are completed before the loop, so that its head needs no wait.
+  asm volatile("" ::"v"(c), "v"(nc), "v"(gd), "v"(k), "v"(rr), "v"(rx),
+               "v"(ry), "v"(rz));
+  asm volatile("" ::"v"(lo.x), "v"(lo.y), "v"(lo.z), "v"(hi.x), "v"(hi.y),
+               "v"(hi.z), "v"(gb));
+  uint4 seg0, seg1, seg2, seg3;
+  uint32_t* pend = nullptr;
+  while (c < nc) {
+    const uint4 w = wrec[c];
+    // all four words in registers here: otherwise the compiler loads the
+    // coordinates separately inside the opening test, a second round trip
+    // to memory after the first
+    asm volatile("" ::"v"(w.x), "v"(w.y), "v"(w.z), "v"(w.w));
+    if (FILL && pend) {
+      uint4* d4 = reinterpret_cast<uint4*>(pend);
+      d4[0] = seg0;
+      d4[1] = seg1;
+      d4[2] = seg2;
+      d4[3] = seg3;
+      pend = nullptr;
+    }
+    const uint32_t skip = w.z;
+    const bool leaf = (w.y >> 31) != 0u;
+    // the opening test for every cell (branch-free: with about one wave per
+    // SIMD each divergent branch costs its full latency)
+    const int l = (int)(w.w & 31u);
+    const uint64_t q = (uint64_t)w.x | ((uint64_t)(w.y & 0x7FFFFFFFu) << 32);
+    const uint32_t qx = (uint32_t)q & 0x1FFFFFu;
+    const uint32_t qy = (uint32_t)(q >> 21) & 0x1FFFFFu;
+    const uint32_t qz = (uint32_t)(q >> 42);
+    const double half = ldexp(1.0, k - l - 1);
+    const double cx = __dadd_rn(rx, __dmul_rn((double)(2u * qx + 1u), half));
+    const double cy = __dadd_rn(ry, __dmul_rn((double)(2u * qy + 1u), half));
+    const double cz = __dadd_rn(rz, __dmul_rn((double)(2u * qz + 1u), half));
+    const double dx = fmax(fmax(__dsub_rn(lo.x, cx), __dsub_rn(cx, hi.x)), 0.0);
+    const double dy = fmax(fmax(__dsub_rn(lo.y, cy), __dsub_rn(cy, hi.y)), 0.0);
+    const double dz = fmax(fmax(__dsub_rn(lo.z, cz), __dsub_rn(cz, hi.z)), 0.0);
+    const double d2 =
+        __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                  __dmul_rn(dz, dz));
+    // a cell holding the group is opened whatever its distance
+    const bool open = (c <= gd && gd < skip) || !(d2 > ldexp(rr, 2 * (k - l)));
+    const bool term = !open || leaf;   // accepted, or an opened leaf
+    const uint32_t next = term ? skip : c + 1;
+    if (next <= c) break;
+    ns += open ? 0u : 1u;
+    uint32_t cnt = w.w >> 5;
+    if (cnt == kWalkCountSat) cnt = rec[c].meta.y - rec[c].meta.x;
+    const bool opened_leaf = open && leaf;
+    nl += opened_leaf ? 1u : 0u;
+    ne += opened_leaf ? cnt : 0u;
+    if (FILL) {
+      // slot sc is free: write it every visit, keep it only for a token
+      stage[sc][threadIdx.x] = open ? (c | kLeafTag) : c;
+      sc += term ? 1 : 0;
+      if (term && ((out + sc) & (kSeg - 1)) == 0) {
+        if (out + sc > end) {
+          // past the slab: drop
+        } else if (sc == kSeg) {
+          seg0 = make_uint4(stage[0][threadIdx.x], stage[1][threadIdx.x],
+                            stage[2][threadIdx.x], stage[3][threadIdx.x]);
+          seg1 = make_uint4(stage[4][threadIdx.x], stage[5][threadIdx.x],
+                            stage[6][threadIdx.x], stage[7][threadIdx.x]);
+          seg2 = make_uint4(stage[8][threadIdx.x], stage[9][threadIdx.x],
+                            stage[10][threadIdx.x], stage[11][threadIdx.x]);
+          seg3 = make_uint4(stage[12][threadIdx.x], stage[13][threadIdx.x],
+                            stage[14][threadIdx.x], stage[15][threadIdx.x]);
+          pend = dst + out;
+        } else {
+          for (int r = 0; r < sc; ++r) dst[out + r] = stage[r][threadIdx.x];
+        }
+        out += sc;
+        sc = 0;
+      }
+    }
+    c = next;
+  }
+  if (FILL && pend) {
+    uint4* d4 = reinterpret_cast<uint4*>(pend);
+    d4[0] = seg0;
+    d4[1] = seg1;
+    d4[2] = seg2;
+    d4[3] = seg3;
+  }
+  if (FILL && out + sc <= end) {
+    for (int q = 0; q < sc; ++q) dst[out + q] = stage[q][threadIdx.x];
+  }
+  if (counts) {
+    cnt_e[g] = ne;
+    cnt_s[g] = ns;
+    cnt_t[g] = ns + nl;
+  }
+}
+
 // Tile walk: W lanes per group (W = 4 .. 64, a power of two), for more
 // parallelism than one thread per group.  The lanes of a tile take W
 // consecutive cells of the pre-order array and evaluate the opening test of
@@ -619,11 +771,23 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
     rc = launch_tile(c, w, fill, learn, launch, n_walk, nblk, sel, lo, hi,
                      slab);
     if (rc) return rc;
+  } else if (!learn) {
+    const int64_t nblk = grid_for(n_walk, kWalkThreads);
+    const int64_t launch = (nblk + 7) / 8 * 8;
+    hipLaunchKernelGGL(fill ? k_walk_c<true> : k_walk_c<false>,
+                       dim3((unsigned)launch), dim3(kWalkThreads), 0,
+                       c->stream, n_walk, nblk, (const uint32_t*)c->g_begin.p,
+                       (const uint32_t*)c->g_count.p, lo, hi,
+                       (const uint32_t*)c->g_cell.p,
+                       (const CellRec*)c->c_rec.p, (const uint4*)c->c_wrec.p,
+                       (const Root*)c->root.p, (const uint32_t*)c->seg.p,
+                       (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
+                       c->cnt_t.p, (const uint64_t*)c->tok_off.p, c->tok.p,
+                       slab);
   } else {
     const int64_t nblk = grid_for(n_walk, kWalkThreads);
     const int64_t launch = (nblk + 7) / 8 * 8;
-    auto k = fill ? (learn ? k_walk<true, true> : k_walk<true, false>)
-                  : (learn ? k_walk<false, true> : k_walk<false, false>);
+    auto k = fill ? k_walk<true, true> : k_walk<false, true>;
     hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
                        c->stream, n_walk, nblk, sel,
                        (const uint32_t*)c->g_begin.p,

@@ -149,6 +149,26 @@ def test_lists_bit_exact_theta_and_sizes(theta, n_leaf, n_grp):
         compare_lists(ctx, t)
 
 
+@pytest.mark.parametrize("kind,n,n_leaf,n_grp,theta", [
+    ("plummer", 20000, 1, 1, 1.0), ("plummer", 40000, 2, 4, 0.3),
+    ("clustered", 60000, 1, 2, 0.5), ("disk", 60000, 4, 4, 0.7),
+    ("ring", 50000, 8, 4, 0.5)])
+def test_lists_bit_exact_one_thread_walk(kind, n, n_leaf, n_grp, theta):
+    """Enough groups for the one-thread-per-group walk (over the 16-byte
+    walk records), whole lists against the oracle."""
+    say("case one-thread walk %s n=%d n_leaf=%d n_grp=%d theta=%g"
+        % (kind, n, n_leaf, n_grp, theta))
+    d = system(kind, n)
+    with gpu_ctx(d, theta=theta, n_leaf=n_leaf, n_grp=n_grp) as ctx:
+        ctx.build_tree()
+        ctx.make_lists(nb.NB_MAKE_LIST)
+        assert ctx.get_info()["n_groups"] >= 8192
+        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], n_leaf, n_grp)
+        t.make_lists(theta)
+        compare_tree(ctx, t)
+        compare_lists(ctx, t)
+
+
 @pytest.mark.parametrize("order", [1, 2])
 def test_moments_within_fp32_tolerance(order):
     say("case moments order=%d" % order)
