@@ -255,8 +255,13 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
     if ((rc = launch_walk(c, false))) return rc;
     if ((rc = launch_list_stats(c))) return rc;
   }
+  {
+    Timed t(c, NB_PH_WALK);
+    if ((rc = launch_xcd_plan(c))) return rc;
+  }
   // sync 3: list totals, interaction count, force work items, largest
-  // token count
+  // token count, force launch plan
+  if ((rc = stage_d2h(c, 64, c->xcd_plan.p, 9 * 8))) return rc;
   if ((rc = stage_d2h(c, 0, c->epj_off.p + c->n_groups, 8))) return rc;
   if ((rc = stage_d2h(c, 8, c->spj_off.p + c->n_groups, 8))) return rc;
   if ((rc = stage_d2h(c, 16, c->red.p, 16))) return rc;
@@ -274,6 +279,7 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
     n_tok = (int64_t)h[4];
     c->n_inter_spj = (int64_t)h[6];
     c->n_wi = static_cast<const uint32_t*>(c->h_small)[10];
+    for (int x = 0; x <= 8; ++x) c->xcd_b[x] = (int64_t)h[8 + x];
   }
   // slab for the next construction: 1.25 x the largest list, 16-aligned
   c->tok_slab = (uint32_t)std::min<int64_t>(
@@ -365,6 +371,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->gflag); release(c->g_cell); release(c->g_begin);
   release(c->g_count); release(c->g_lo); release(c->g_hi);
   release(c->g_chunks); release(c->wi); release(c->queue);
+  release(c->g_cost); release(c->g_cost_off); release(c->xcd_plan);
   release(c->nb_cnt); release(c->nb_tcnt); release(c->nb_ids);
   release(c->nb_off); release(c->nb_toff); release(c->rho);
   release(c->cnt_e); release(c->cnt_s); release(c->cnt_t);

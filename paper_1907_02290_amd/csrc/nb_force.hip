@@ -343,20 +343,88 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
   }
 }
 
-// One launch, one workgroup (one wavefront) per work item; workgroup ids are
-// remapped so each XCD takes a contiguous stretch of work items.  Five waves
-// per SIMD leave room for the next tile's records in registers (93 VGPRs);
-// at six the compiler spills them.
+// Launch plan: XCD x takes the work items [b[x], b[x + 1]), a contiguous
+// stretch (its groups' tree neighbourhoods share that XCD's L2), and the
+// stretches are cut where the estimated cost is balanced.  Workgroups are
+// dealt to the XCDs round-robin, so workgroup bid runs item
+// b[bid & 7] + (bid >> 3).
+struct XcdPlan {
+  int64_t b[9];
+};
+
+// One launch, one workgroup (one wavefront) per work item.  Five waves per
+// SIMD leave room for the next tile's records in registers (93 VGPRs); at
+// six the compiler spills them.
 template <int ORDER, bool COPIED>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8)))
-k_force(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
-        ForceArgs A) {
+k_force(const uint4* __restrict__ wi, XcdPlan plan, ForceArgs A) {
   __shared__ float4 tile[Tiles<ORDER>::kBig];
   __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<ORDER>::kBig : 1];
   const uint32_t bid = blockIdx.x;
-  const int64_t w = (int64_t)(bid & 7u) * per_xcd + (int64_t)(bid >> 3);
-  if (w >= n_wi) return;  // uniform over the workgroup
+  const uint32_t x = bid & 7u;
+  const int64_t w = plan.b[x] + (int64_t)(bid >> 3);
+  if (w >= plan.b[x + 1]) return;  // uniform over the workgroup
   force_item<ORDER, COPIED>(wi[w], A, tile, tq, tile);
+}
+
+// Estimated cost of a group's work items, in list entries per lane slice:
+// a chunk of n_i particles runs on r = 64 / n_i slices over tiles of 64 q
+// entries (q = min(r, largest slice count)), every slice taking 64 q / r
+// entries of each tile, for the particle and the superparticle segment
+// separately; plus about one tile for loading the chunk and the final sums.
+// Quadrupole superparticles count twice.
+template <int ORDER>
+__device__ inline uint64_t item_cost(uint64_t ne, uint64_t ns, int ni) {
+  constexpr int kMax = Tiles<ORDER>::kMaxSlices;
+  const int r = kTile / ni;
+  const int q = r < kMax ? r : kMax;
+  const uint64_t T = (uint64_t)kTile * (uint64_t)q;
+  const uint64_t tiles =
+      (ne + T - 1) / T + (ORDER == 2 ? 2u : 1u) * ((ns + T - 1) / T);
+  return tiles * T / (uint64_t)r + (uint64_t)kTile;
+}
+
+template <int ORDER>
+__global__ void __launch_bounds__(256)
+k_group_cost(int64_t n_groups, const uint32_t* __restrict__ g_chunks,
+             const uint4* __restrict__ wi,
+             const uint64_t* __restrict__ epj_off,
+             const uint64_t* __restrict__ spj_off,
+             uint32_t* __restrict__ cost) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_groups) return;
+  const uint64_t ne = epj_off[g + 1] - epj_off[g];
+  const uint64_t ns = spj_off[g + 1] - spj_off[g];
+  uint64_t sum = 0;
+  for (uint32_t w = g_chunks[g]; w < g_chunks[g + 1]; ++w)
+    sum += item_cost<ORDER>(ne, ns, (int)wi[w].z);
+  cost[g] = sum < 0xFFFFFFFFull ? (uint32_t)sum : 0xFFFFFFFFu;
+}
+
+// The plan from the scanned group costs (off[n_groups] = total): the cut
+// before XCD x is at the first group whose cost prefix reaches x / 8 of the
+// total, turned into a work-item index by the groups' chunk offsets.
+__global__ void k_xcd_split(int64_t n_groups, const uint64_t* __restrict__ off,
+                            const uint32_t* __restrict__ g_chunks,
+                            uint64_t* __restrict__ plan) {
+  const int x = (int)threadIdx.x;
+  if (x > 8) return;
+  const uint64_t total = off[n_groups];
+  int64_t g = x == 8 ? n_groups : 0;
+  if (x > 0 && x < 8) {
+    const uint64_t target = (total / 8) * (uint64_t)x +
+                            ((total % 8) * (uint64_t)x) / 8;
+    int64_t lo = 0, hi = n_groups;  // smallest g with off[g] >= target
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (off[mid] >= target)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    g = lo;
+  }
+  plan[x] = g_chunks[g];
 }
 
 // Copied lists (the paper's method G1, for comparison with index lists):
@@ -500,7 +568,17 @@ int launch_force(nb_ctx* c) {
   if (rc) return rc;
   if (c->n_wi <= 0) return NB_OK;
   const int64_t per_xcd = (c->n_wi + 7) / 8;
-  const int64_t nblk = per_xcd * 8;
+  if (per_xcd * 8 > 0x7FFFFFFFLL)
+    return set_err(c, NB_ERR_INPUT, "too many force work items");
+  // the plan of the last list construction, checked against the items
+  XcdPlan plan;
+  bool ok = c->xcd_b[0] == 0 && c->xcd_b[8] == c->n_wi;
+  for (int x = 0; x < 8; ++x) ok = ok && c->xcd_b[x] <= c->xcd_b[x + 1];
+  if (!ok) equal_xcd_plan(c);
+  int64_t most = 0;
+  for (int x = 0; x < 9; ++x) plan.b[x] = c->xcd_b[x];
+  for (int x = 0; x < 8; ++x) most = std::max(most, plan.b[x + 1] - plan.b[x]);
+  const int64_t nblk = most * 8;
   if (nblk > 0x7FFFFFFFLL)
     return set_err(c, NB_ERR_INPUT, "too many force work items");
   ForceArgs A;
@@ -545,14 +623,40 @@ int launch_force(nb_ctx* c) {
                        (const double4*)c->c_pm.p, c->jcopy.p);
     A.jcopy = c->jcopy.p;
     hipLaunchKernelGGL((k_force<1, true>), dim3((unsigned)nblk), dim3(kTile),
-                       0, c->stream, (const uint4*)c->wi.p, c->n_wi, per_xcd,
-                       A);
+                       0, c->stream, (const uint4*)c->wi.p, plan, A);
   } else {
     auto k = c->cfg.order == 2 ? k_force<2, false> : k_force<1, false>;
     hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kTile), 0, c->stream,
-                       (const uint4*)c->wi.p, c->n_wi, per_xcd, A);
+                       (const uint4*)c->wi.p, plan, A);
   }
   return hip_check(c, hipGetLastError(), "force launch");
+}
+
+void equal_xcd_plan(nb_ctx* c) {
+  const int64_t per = (c->n_wi + 7) / 8;
+  for (int x = 0; x <= 8; ++x) c->xcd_b[x] = std::min<int64_t>(x * per, c->n_wi);
+}
+
+// Plan of the force launch from the lists just made (before their totals
+// are read back: the nine item indices come back with them).
+int launch_xcd_plan(nb_ctx* c) {
+  const size_t ng = (size_t)c->n_groups;
+  int rc = reserve(c, c->g_cost, ng);
+  if (!rc) rc = reserve(c, c->g_cost_off, ng + 1);
+  if (!rc) rc = reserve(c, c->xcd_plan, 9);
+  if (rc) return rc;
+  auto k = c->cfg.order == 2 ? k_group_cost<2> : k_group_cost<1>;
+  hipLaunchKernelGGL(k, dim3(grid_for(c->n_groups, 256)), dim3(256), 0,
+                     c->stream, c->n_groups, (const uint32_t*)c->g_chunks.p,
+                     (const uint4*)c->wi.p, (const uint64_t*)c->epj_off.p,
+                     (const uint64_t*)c->spj_off.p, c->g_cost.p);
+  rc = hip_check(c, hipGetLastError(), "group cost launch");
+  if (!rc) rc = scan_u32_to_u64(c, c->g_cost.p, c->g_cost_off.p, c->n_groups);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_xcd_split, dim3(1), dim3(64), 0, c->stream,
+                     c->n_groups, (const uint64_t*)c->g_cost_off.p,
+                     (const uint32_t*)c->g_chunks.p, c->xcd_plan.p);
+  return hip_check(c, hipGetLastError(), "plan launch");
 }
 
 

@@ -135,6 +135,12 @@ struct nb_ctx {
   nb::DBuf<double4> g_lo, g_hi;  // tight box of the members (w unused)
   nb::DBuf<uint32_t> g_chunks;  // n_groups + 1, scanned
   nb::DBuf<uint4> wi;           // force work items: group, first, count
+  // force launch plan: XCD x takes work items [xcd_b[x], xcd_b[x + 1]),
+  // split where the estimated cost of the items is balanced
+  nb::DBuf<uint32_t> g_cost;     // n_groups: estimated cost of each group
+  nb::DBuf<uint64_t> g_cost_off; // n_groups + 1, scanned
+  nb::DBuf<uint64_t> xcd_plan;   // 9 item indices
+  int64_t xcd_b[9] = {};
   nb::DBuf<unsigned int> queue;  // per-XCD counters of the persistent launch
 
   // short-range neighbour lists (nb_neighbour_lists): per group the
@@ -296,6 +302,8 @@ int refresh_checked(nb_ctx* c);
 int labels_to_float(nb_ctx* c, float* out);
 // nb_force.hip
 int launch_force(nb_ctx* c);
+int launch_xcd_plan(nb_ctx* c);   // device plan; read back with the lists
+void equal_xcd_plan(nb_ctx* c);   // host fallback: equal item counts
 // nb_step.hip
 int launch_kick_drift(nb_ctx* c, double dt_kick, double dt_drift);
 int launch_pack(nb_ctx* c, const double* x, const double* y, const double* z,
