@@ -257,7 +257,7 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
   }
   {
     Timed t(c, NB_PH_WALK);
-    if ((rc = launch_xcd_plan(c))) return rc;
+    if ((rc = launch_xcd_plan(c, false))) return rc;
   }
   // sync 3: list totals, interaction count, force work items, largest
   // token count, force launch plan
@@ -677,9 +677,11 @@ int nb_neighbour_lists(nb_ctx* c, double h_list) {
   {
     Timed t(c, NB_PH_WALK);
     if ((rc = launch_nbr_count(c, h_list))) return rc;
+    if ((rc = launch_xcd_plan(c, true))) return rc;
   }
-  // totals, and the work-item count of the tree's groups (the density
-  // kernel runs on the force kernel's work items)
+  // totals, the work-item count of the tree's groups (the density kernel
+  // runs on the force kernel's work items) and the density launch plan
+  if ((rc = stage_d2h(c, 64, c->xcd_plan.p, 9 * 8))) return rc;
   if ((rc = stage_d2h(c, 0, c->nb_off.p + c->n_groups, 8))) return rc;
   if ((rc = stage_d2h(c, 8, c->nb_toff.p + c->n_groups, 8))) return rc;
   if ((rc = stage_d2h(c, 16, c->g_chunks.p + c->n_groups, 4))) return rc;
@@ -688,6 +690,7 @@ int nb_neighbour_lists(nb_ctx* c, double h_list) {
   c->n_nbr = (int64_t)hs[0];
   const int64_t n_tok = (int64_t)hs[1];
   c->n_wi = static_cast<const uint32_t*>(c->h_small)[4];
+  for (int x = 0; x <= 8; ++x) c->nbr_b[x] = (int64_t)hs[8 + x];
   if ((rc = reserve(c, c->nb_ids, (size_t)c->n_nbr + 1))) return rc;
   if ((rc = reserve(c, c->tok, (size_t)n_tok + 1))) return rc;
   {

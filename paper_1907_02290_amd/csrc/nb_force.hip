@@ -352,6 +352,22 @@ struct XcdPlan {
   int64_t b[9];
 };
 
+// The plan b as a kernel argument; a plan that does not cover the n_wi
+// items (none computed for them) is replaced by equal stretches.  Returns
+// the grid size: 8 x the longest stretch.
+int64_t checked_plan(int64_t n_wi, int64_t* b, XcdPlan& plan) {
+  bool ok = b[0] == 0 && b[8] == n_wi;
+  for (int x = 0; x < 8; ++x) ok = ok && b[x] <= b[x + 1];
+  if (!ok) {
+    const int64_t per = (n_wi + 7) / 8;
+    for (int x = 0; x <= 8; ++x) b[x] = std::min<int64_t>(x * per, n_wi);
+  }
+  int64_t most = 0;
+  for (int x = 0; x < 9; ++x) plan.b[x] = b[x];
+  for (int x = 0; x < 8; ++x) most = std::max(most, b[x + 1] - b[x]);
+  return most * 8;
+}
+
 // One launch, one workgroup (one wavefront) per work item.  Five waves per
 // SIMD leave room for the next tile's records in registers (93 VGPRs); at
 // six the compiler spills them.
@@ -373,18 +389,19 @@ k_force(const uint4* __restrict__ wi, XcdPlan plan, ForceArgs A) {
 // entries of each tile, for the particle and the superparticle segment
 // separately; plus about one tile for loading the chunk and the final sums.
 // Quadrupole superparticles count twice.
-template <int ORDER>
+// KMAX: the kernel's largest slice count (tiles of 64 q entries,
+// q = min(r, KMAX)); WS: weight of a superparticle entry.  The SPH density
+// kernel takes tiles of 64 entries (KMAX 1) and has no superparticles.
+template <int KMAX, int WS>
 __device__ inline uint64_t item_cost(uint64_t ne, uint64_t ns, int ni) {
-  constexpr int kMax = Tiles<ORDER>::kMaxSlices;
   const int r = kTile / ni;
-  const int q = r < kMax ? r : kMax;
+  const int q = r < KMAX ? r : KMAX;
   const uint64_t T = (uint64_t)kTile * (uint64_t)q;
-  const uint64_t tiles =
-      (ne + T - 1) / T + (ORDER == 2 ? 2u : 1u) * ((ns + T - 1) / T);
+  const uint64_t tiles = (ne + T - 1) / T + (uint64_t)WS * ((ns + T - 1) / T);
   return tiles * T / (uint64_t)r + (uint64_t)kTile;
 }
 
-template <int ORDER>
+template <int KMAX, int WS>
 __global__ void __launch_bounds__(256)
 k_group_cost(int64_t n_groups, const uint32_t* __restrict__ g_chunks,
              const uint4* __restrict__ wi,
@@ -394,10 +411,10 @@ k_group_cost(int64_t n_groups, const uint32_t* __restrict__ g_chunks,
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_groups) return;
   const uint64_t ne = epj_off[g + 1] - epj_off[g];
-  const uint64_t ns = spj_off[g + 1] - spj_off[g];
+  const uint64_t ns = spj_off ? spj_off[g + 1] - spj_off[g] : 0;
   uint64_t sum = 0;
   for (uint32_t w = g_chunks[g]; w < g_chunks[g + 1]; ++w)
-    sum += item_cost<ORDER>(ne, ns, (int)wi[w].z);
+    sum += item_cost<KMAX, WS>(ne, ns, (int)wi[w].z);
   cost[g] = sum < 0xFFFFFFFFull ? (uint32_t)sum : 0xFFFFFFFFu;
 }
 
@@ -463,13 +480,13 @@ k_copy_j(int64_t n_groups, int64_t nblk, const uint32_t* __restrict__ g_cell,
 // (queue[0..7], zeroed before the launch) until the stretch is used up.
 template <int ORDER>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
-k_force_queue(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
+k_force_queue(const uint4* __restrict__ wi, XcdPlan plan,
               unsigned int* __restrict__ queue, ForceArgs A) {
   __shared__ float4 tile[Tiles<ORDER>::kBig];
   __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<ORDER>::kBig : 1];
   const uint32_t x = blockIdx.x & 7u;
-  const int64_t lo = (int64_t)x * per_xcd;
-  const int64_t hi = lo + per_xcd < n_wi ? lo + per_xcd : n_wi;
+  const int64_t lo = plan.b[x];
+  const int64_t hi = plan.b[x + 1];
   for (;;) {
     unsigned int k = 0;
     if (threadIdx.x == 0) k = atomicAdd(&queue[x], 1u);
@@ -488,7 +505,7 @@ k_force_queue(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
 // work items, lane slices, FP32 offsets from the group centre and LDS tiles
 // are the force kernel's; a slice takes a block of every 64-entry tile.
 __global__ void __launch_bounds__(64)
-k_density(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
+k_density(const uint4* __restrict__ wi, XcdPlan plan,
           const uint32_t* __restrict__ g_cell,
           const CellRec* __restrict__ rec,
           const uint64_t* __restrict__ nb_off,
@@ -498,8 +515,9 @@ k_density(const uint4* __restrict__ wi, int64_t n_wi, int64_t per_xcd,
   __shared__ float4 tile[kTile];
   __shared__ float red[kTile];
   const uint32_t bid = blockIdx.x;
-  const int64_t w = (int64_t)(bid & 7u) * per_xcd + (int64_t)(bid >> 3);
-  if (w >= n_wi) return;  // uniform over the workgroup
+  const uint32_t x = bid & 7u;
+  const int64_t w = plan.b[x] + (int64_t)(bid >> 3);
+  if (w >= plan.b[x + 1]) return;  // uniform over the workgroup
   const uint4 it = wi[w];
   const int lane = threadIdx.x;
   const int ni = (int)it.z;
@@ -570,15 +588,9 @@ int launch_force(nb_ctx* c) {
   const int64_t per_xcd = (c->n_wi + 7) / 8;
   if (per_xcd * 8 > 0x7FFFFFFFLL)
     return set_err(c, NB_ERR_INPUT, "too many force work items");
-  // the plan of the last list construction, checked against the items
+  // the plan of the last list construction
   XcdPlan plan;
-  bool ok = c->xcd_b[0] == 0 && c->xcd_b[8] == c->n_wi;
-  for (int x = 0; x < 8; ++x) ok = ok && c->xcd_b[x] <= c->xcd_b[x + 1];
-  if (!ok) equal_xcd_plan(c);
-  int64_t most = 0;
-  for (int x = 0; x < 9; ++x) plan.b[x] = c->xcd_b[x];
-  for (int x = 0; x < 8; ++x) most = std::max(most, plan.b[x + 1] - plan.b[x]);
-  const int64_t nblk = most * 8;
+  const int64_t nblk = checked_plan(c->n_wi, c->xcd_b, plan);
   if (nblk > 0x7FFFFFFFLL)
     return set_err(c, NB_ERR_INPUT, "too many force work items");
   ForceArgs A;
@@ -606,7 +618,7 @@ int launch_force(nb_ctx* c) {
     nq = (nq + 7) / 8 * 8;
     auto k = c->cfg.order == 2 ? k_force_queue<2> : k_force_queue<1>;
     hipLaunchKernelGGL(k, dim3((unsigned)nq), dim3(kTile), 0, c->stream,
-                       (const uint4*)c->wi.p, c->n_wi, per_xcd, c->queue.p, A);
+                       (const uint4*)c->wi.p, plan, c->queue.p, A);
   } else if (c->cfg.flags & NB_FLAG_COPIED_LISTS) {
     // monopole only (checked with the configuration)
     if ((rc = reserve(c, c->jcopy, (size_t)(c->n_epj + c->n_spj) + 1)))
@@ -632,24 +644,25 @@ int launch_force(nb_ctx* c) {
   return hip_check(c, hipGetLastError(), "force launch");
 }
 
-void equal_xcd_plan(nb_ctx* c) {
-  const int64_t per = (c->n_wi + 7) / 8;
-  for (int x = 0; x <= 8; ++x) c->xcd_b[x] = std::min<int64_t>(x * per, c->n_wi);
-}
-
-// Plan of the force launch from the lists just made (before their totals
-// are read back: the nine item indices come back with them).
-int launch_xcd_plan(nb_ctx* c) {
+// Plan of the force launch (or, `neighbours`, of the SPH density launch)
+// from the lists just made, before their totals are read back: the nine
+// item indices come back with them.
+int launch_xcd_plan(nb_ctx* c, bool neighbours) {
   const size_t ng = (size_t)c->n_groups;
   int rc = reserve(c, c->g_cost, ng);
   if (!rc) rc = reserve(c, c->g_cost_off, ng + 1);
   if (!rc) rc = reserve(c, c->xcd_plan, 9);
   if (rc) return rc;
-  auto k = c->cfg.order == 2 ? k_group_cost<2> : k_group_cost<1>;
+  auto k = neighbours ? k_group_cost<1, 1>
+                      : (c->cfg.order == 2 ? k_group_cost<2, 2>
+                                           : k_group_cost<4, 1>);
   hipLaunchKernelGGL(k, dim3(grid_for(c->n_groups, 256)), dim3(256), 0,
                      c->stream, c->n_groups, (const uint32_t*)c->g_chunks.p,
-                     (const uint4*)c->wi.p, (const uint64_t*)c->epj_off.p,
-                     (const uint64_t*)c->spj_off.p, c->g_cost.p);
+                     (const uint4*)c->wi.p,
+                     (const uint64_t*)(neighbours ? c->nb_off.p
+                                                  : c->epj_off.p),
+                     (const uint64_t*)(neighbours ? nullptr : c->spj_off.p),
+                     c->g_cost.p);
   rc = hip_check(c, hipGetLastError(), "group cost launch");
   if (!rc) rc = scan_u32_to_u64(c, c->g_cost.p, c->g_cost_off.p, c->n_groups);
   if (rc) return rc;
@@ -665,10 +678,13 @@ int launch_density(nb_ctx* c, double h) {
   int rc = reserve(c, c->rho, (size_t)c->n);
   if (rc) return rc;
   if (c->n_wi <= 0) return NB_OK;
-  const int64_t per_xcd = (c->n_wi + 7) / 8;
+  XcdPlan plan;
+  const int64_t nblk = checked_plan(c->n_wi, c->nbr_b, plan);
+  if (nblk > 0x7FFFFFFFLL)
+    return set_err(c, NB_ERR_INPUT, "too many work items");
   const double pi = 3.14159265358979323846;
-  hipLaunchKernelGGL(k_density, dim3((unsigned)(per_xcd * 8)), dim3(kTile), 0,
-                     c->stream, (const uint4*)c->wi.p, c->n_wi, per_xcd,
+  hipLaunchKernelGGL(k_density, dim3((unsigned)nblk), dim3(kTile), 0,
+                     c->stream, (const uint4*)c->wi.p, plan,
                      (const uint32_t*)c->g_cell.p, (const CellRec*)c->c_rec.p,
                      (const uint64_t*)c->nb_off.p,
                      (const uint32_t*)c->nb_ids.p, (const double4*)c->pos.p,

@@ -141,6 +141,7 @@ struct nb_ctx {
   nb::DBuf<uint64_t> g_cost_off; // n_groups + 1, scanned
   nb::DBuf<uint64_t> xcd_plan;   // 9 item indices
   int64_t xcd_b[9] = {};
+  int64_t nbr_b[9] = {};         // the same for the SPH density launch
   nb::DBuf<unsigned int> queue;  // per-XCD counters of the persistent launch
 
   // short-range neighbour lists (nb_neighbour_lists): per group the
@@ -302,8 +303,9 @@ int refresh_checked(nb_ctx* c);
 int labels_to_float(nb_ctx* c, float* out);
 // nb_force.hip
 int launch_force(nb_ctx* c);
-int launch_xcd_plan(nb_ctx* c);   // device plan; read back with the lists
-void equal_xcd_plan(nb_ctx* c);   // host fallback: equal item counts
+// device plan of the force (or SPH density) launch, read back with the
+// lists' totals into xcd_b (nbr_b)
+int launch_xcd_plan(nb_ctx* c, bool neighbours);
 // nb_step.hip
 int launch_kick_drift(nb_ctx* c, double dt_kick, double dt_drift);
 int launch_pack(nb_ctx* c, const double* x, const double* y, const double* z,
