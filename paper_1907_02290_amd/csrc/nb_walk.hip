@@ -592,7 +592,9 @@ __global__ void __launch_bounds__(kWalkThreads)
 k_walk_nbr(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
            const uint32_t* __restrict__ g_count,
            const double4* __restrict__ g_lo, const double4* __restrict__ g_hi,
-           const CellRec* __restrict__ rec, const uint32_t* __restrict__ seg,
+           const uint32_t* __restrict__ g_cell,
+           const CellRec* __restrict__ rec, const uint4* __restrict__ wrec,
+           const uint32_t* __restrict__ seg,
            const uint32_t* __restrict__ croot, const Root* __restrict__ root,
            double h, uint32_t* __restrict__ cnt_e,
            uint32_t* __restrict__ cnt_t, const uint64_t* __restrict__ tok_off,
@@ -605,70 +607,99 @@ k_walk_nbr(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
   const uint32_t gb = g_begin[g];
   const uint32_t ge = gb + g_count[g];
   const double4 lo = g_lo[g], hi = g_hi[g];
+  // deepest cell whose range is the group's (as in the gravity walk)
+  uint32_t gd = g_cell[g];
+  for (;;) {
+    if ((rec[gd].meta.w >> 8) & 1u) break;
+    const uint4 m1 = rec[gd + 1].meta;
+    if (m1.x != gb || m1.y != ge) break;
+    ++gd;
+  }
   const uint32_t sys = seg[gb];
-  const int k = root[sys].k;
+  const Root* rt = root + sys;
+  const double rx = rt->lo[0], ry = rt->lo[1], rz = rt->lo[2];
+  const int k = rt->k;
   uint32_t c = croot[sys];
   const uint32_t nc = croot[sys + 1];
   uint64_t out = FILL ? tok_off[g] : 0;
   int sc = 0;
   uint32_t ne = 0, nl = 0;
+  // the gravity walk's visit: one record load, no divergent branch, full
+  // token segments stored one visit late
+  asm volatile("" ::"v"(c), "v"(nc), "v"(gd), "v"(k), "v"(rx), "v"(ry),
+               "v"(rz));
+  asm volatile("" ::"v"(lo.x), "v"(lo.y), "v"(lo.z), "v"(hi.x), "v"(hi.y),
+               "v"(hi.z), "v"(gb));
+  uint4 seg0, seg1, seg2, seg3;
+  uint32_t* pend = nullptr;
   while (c < nc) {
-    const uint4 m = rec[c].meta;
-    bool open = true;
-    if (!(m.x <= gb && m.y >= ge)) {
-      const double4 cc = rec[c].geo;
-      const double r =
-          __dadd_rn(ldexp(1.0, k - (int)(m.w & 0xFFu) - 1), h);
-      double t, v;
-      v = 0.0;
-      t = __dsub_rn(lo.x, cc.x);
-      if (t > v) v = t;
-      t = __dsub_rn(cc.x, hi.x);
-      if (t > v) v = t;
-      if (v > r) open = false;
-      v = 0.0;
-      t = __dsub_rn(lo.y, cc.y);
-      if (t > v) v = t;
-      t = __dsub_rn(cc.y, hi.y);
-      if (t > v) v = t;
-      if (v > r) open = false;
-      v = 0.0;
-      t = __dsub_rn(lo.z, cc.z);
-      if (t > v) v = t;
-      t = __dsub_rn(cc.z, hi.z);
-      if (t > v) v = t;
-      if (v > r) open = false;
+    const uint4 w = wrec[c];
+    asm volatile("" ::"v"(w.x), "v"(w.y), "v"(w.z), "v"(w.w));
+    if (FILL && pend) {
+      uint4* d4 = reinterpret_cast<uint4*>(pend);
+      d4[0] = seg0;
+      d4[1] = seg1;
+      d4[2] = seg2;
+      d4[3] = seg3;
+      pend = nullptr;
     }
-    const bool leaf = (m.w >> 8) & 1u;
-    const uint32_t next = (!open || leaf) ? m.z : c + 1;
+    const uint32_t skip = w.z;
+    const bool leaf = (w.y >> 31) != 0u;
+    const int l = (int)(w.w & 31u);
+    const uint64_t q = (uint64_t)w.x | ((uint64_t)(w.y & 0x7FFFFFFFu) << 32);
+    const uint32_t qx = (uint32_t)q & 0x1FFFFFu;
+    const uint32_t qy = (uint32_t)(q >> 21) & 0x1FFFFFu;
+    const uint32_t qz = (uint32_t)(q >> 42);
+    const double half = ldexp(1.0, k - l - 1);
+    const double cx = __dadd_rn(rx, __dmul_rn((double)(2u * qx + 1u), half));
+    const double cy = __dadd_rn(ry, __dmul_rn((double)(2u * qy + 1u), half));
+    const double cz = __dadd_rn(rz, __dmul_rn((double)(2u * qz + 1u), half));
+    // the cube grown by h overlaps the group's box on every axis
+    const double r = __dadd_rn(half, h);
+    const double vx = fmax(fmax(__dsub_rn(lo.x, cx), __dsub_rn(cx, hi.x)), 0.0);
+    const double vy = fmax(fmax(__dsub_rn(lo.y, cy), __dsub_rn(cy, hi.y)), 0.0);
+    const double vz = fmax(fmax(__dsub_rn(lo.z, cz), __dsub_rn(cz, hi.z)), 0.0);
+    const bool open = (c <= gd && gd < skip) ||
+                      (!(vx > r) && !(vy > r) && !(vz > r));
+    const uint32_t next = (!open || leaf) ? skip : c + 1;
     if (next <= c) break;
-    if (open && leaf) {
-      ++nl;
-      ne += m.y - m.x;
-      if (FILL) {
-        stage[sc][threadIdx.x] = c | kLeafTag;
-        ++sc;
-        if (((out + sc) & (kSeg - 1)) == 0) {
-          if (sc == kSeg) {
-            uint4* d4 = reinterpret_cast<uint4*>(tok + out);
-#pragma unroll
-            for (int q = 0; q < kSeg / 4; ++q)
-              d4[q] = make_uint4(stage[4 * q][threadIdx.x],
-                                 stage[4 * q + 1][threadIdx.x],
-                                 stage[4 * q + 2][threadIdx.x],
-                                 stage[4 * q + 3][threadIdx.x]);
-          } else {
-            for (int q = 0; q < sc; ++q) tok[out + q] = stage[q][threadIdx.x];
-          }
-          out += sc;
-          sc = 0;
+    const bool opened_leaf = open && leaf;
+    uint32_t cnt = w.w >> 5;
+    if (cnt == kWalkCountSat) cnt = rec[c].meta.y - rec[c].meta.x;
+    nl += opened_leaf ? 1u : 0u;
+    ne += opened_leaf ? cnt : 0u;
+    if (FILL) {
+      stage[sc][threadIdx.x] = c | kLeafTag;
+      sc += opened_leaf ? 1 : 0;
+      if (opened_leaf && ((out + sc) & (kSeg - 1)) == 0) {
+        if (sc == kSeg) {
+          seg0 = make_uint4(stage[0][threadIdx.x], stage[1][threadIdx.x],
+                            stage[2][threadIdx.x], stage[3][threadIdx.x]);
+          seg1 = make_uint4(stage[4][threadIdx.x], stage[5][threadIdx.x],
+                            stage[6][threadIdx.x], stage[7][threadIdx.x]);
+          seg2 = make_uint4(stage[8][threadIdx.x], stage[9][threadIdx.x],
+                            stage[10][threadIdx.x], stage[11][threadIdx.x]);
+          seg3 = make_uint4(stage[12][threadIdx.x], stage[13][threadIdx.x],
+                            stage[14][threadIdx.x], stage[15][threadIdx.x]);
+          pend = tok + out;
+        } else {
+          for (int t = 0; t < sc; ++t) tok[out + t] = stage[t][threadIdx.x];
         }
+        out += sc;
+        sc = 0;
       }
     }
     c = next;
   }
   if (FILL) {
-    for (int q = 0; q < sc; ++q) tok[out + q] = stage[q][threadIdx.x];
+    if (pend) {
+      uint4* d4 = reinterpret_cast<uint4*>(pend);
+      d4[0] = seg0;
+      d4[1] = seg1;
+      d4[2] = seg2;
+      d4[3] = seg3;
+    }
+    for (int t = 0; t < sc; ++t) tok[out + t] = stage[t][threadIdx.x];
   } else {
     cnt_e[g] = ne;
     cnt_t[g] = nl;
@@ -862,7 +893,9 @@ int launch_nbr_count(nb_ctx* c, double h) {
                        (const uint32_t*)c->g_begin.p,
                        (const uint32_t*)c->g_count.p,
                        (const double4*)c->g_lo.p, (const double4*)c->g_hi.p,
-                       (const CellRec*)c->c_rec.p, (const uint32_t*)c->seg.p,
+                       (const uint32_t*)c->g_cell.p,
+                       (const CellRec*)c->c_rec.p, (const uint4*)c->c_wrec.p,
+                       (const uint32_t*)c->seg.p,
                        (const uint32_t*)c->croot.p, (const Root*)c->root.p, h,
                        c->nb_cnt.p, c->nb_tcnt.p, (const uint64_t*)nullptr,
                        (uint32_t*)nullptr);
@@ -882,7 +915,9 @@ int launch_nbr_fill(nb_ctx* c, double h) {
                      (const uint32_t*)c->g_begin.p,
                      (const uint32_t*)c->g_count.p,
                      (const double4*)c->g_lo.p, (const double4*)c->g_hi.p,
-                     (const CellRec*)c->c_rec.p, (const uint32_t*)c->seg.p,
+                     (const uint32_t*)c->g_cell.p,
+                     (const CellRec*)c->c_rec.p, (const uint4*)c->c_wrec.p,
+                     (const uint32_t*)c->seg.p,
                      (const uint32_t*)c->croot.p, (const Root*)c->root.p, h,
                      (uint32_t*)nullptr, (uint32_t*)nullptr,
                      (const uint64_t*)c->nb_toff.p, c->tok.p);
