@@ -243,11 +243,13 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
   // construction) when the slabs fit in a bounded buffer; otherwise, or when
   // a group overflows its slab, a count pass and an exact fill pass
   const uint32_t slab = c->tok_slab;
+  const uint64_t slabs = split_walk(c, c->n_groups) ? 2u : 1u;  // per group
   const bool one_pass = slab > 0 &&
-                        (uint64_t)c->n_groups * slab < (1ull << 31);
+                        (uint64_t)c->n_groups * slabs * slab < (1ull << 31);
   if (one_pass) {
     Timed t(c, NB_PH_WALK);
-    if ((rc = reserve(c, c->tok, (size_t)c->n_groups * slab))) return rc;
+    if ((rc = reserve(c, c->tok, (size_t)(c->n_groups * slabs * slab))))
+      return rc;
     if ((rc = launch_walk(c, true, slab))) return rc;
     if ((rc = launch_list_stats(c))) return rc;
   } else {
@@ -372,6 +374,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->g_count); release(c->g_lo); release(c->g_hi);
   release(c->g_chunks); release(c->wi); release(c->queue);
   release(c->g_cost); release(c->g_cost_off); release(c->xcd_plan);
+  release(c->cnt_ta);
   release(c->nb_cnt); release(c->nb_tcnt); release(c->nb_ids);
   release(c->nb_off); release(c->nb_toff); release(c->rho);
   release(c->cnt_e); release(c->cnt_s); release(c->cnt_t);

@@ -156,6 +156,8 @@ struct nb_ctx {
 
   // lists
   nb::DBuf<uint32_t> cnt_e, cnt_s, cnt_t;
+  nb::DBuf<uint32_t> cnt_ta;  // tokens of the first half of a two-lane walk
+  bool walk_split = false;    // the last walk ran two lanes per group
   nb::DBuf<uint64_t> epj_off, spj_off, tok_off;
   nb::DBuf<uint32_t> epj, spj, tok;  // tok: walk tokens per group
 
@@ -275,6 +277,7 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                     uint32_t* epj, uint32_t* spj, uint32_t slab = 0);
 int launch_expand_slab(nb_ctx* c, uint32_t slab);
 int walk_tile(int64_t n_walk);  // lanes per group of the walk
+bool split_walk(const nb_ctx* c, int64_t n_walk);  // two slabs per group
 int launch_list_stats(nb_ctx* c);
 // short-range walk: count pass (nb_cnt, nb_tcnt and their scans) and, with
 // the totals known, the fill pass and expand into nb_ids
