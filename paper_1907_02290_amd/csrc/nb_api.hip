@@ -239,13 +239,14 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
     return set_err(c, NB_ERR_STATE, "lists need a tree of the current positions");
   int rc;
   c->lists_valid = c->lists_reusable = false;
+  c->tail_valid = false;
   // one pass (counts and tokens into per-group slabs sized from the last
   // construction) when the slabs fit in a bounded buffer; otherwise, or when
   // a group overflows its slab, a count pass and an exact fill pass
   const uint32_t slab = c->tok_slab;
   const uint64_t slabs = split_walk(c, c->n_groups) ? 2u : 1u;  // per group
   const bool one_pass = slab > 0 &&
-                        (uint64_t)c->n_groups * slabs * slab < (1ull << 31);
+                        (uint64_t)c->n_groups * slabs * slab < (1ull << 32);
   if (one_pass) {
     Timed t(c, NB_PH_WALK);
     if ((rc = reserve(c, c->tok, (size_t)(c->n_groups * slabs * slab))))
@@ -286,6 +287,10 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
   // slab for the next construction: 1.25 x the largest list, 16-aligned
   c->tok_slab = (uint32_t)std::min<int64_t>(
       (max_tok + max_tok / 4 + 16 + 15) / 16 * 16, 1 << 24);
+  {
+    Timed t(c, NB_PH_WALK);
+    if ((rc = launch_tail_order(c))) return rc;
+  }
   if ((rc = reserve(c, c->epj, (size_t)c->n_epj + 1))) return rc;
   if ((rc = reserve(c, c->spj, (size_t)c->n_spj + 1))) return rc;
   if (one_pass && max_tok <= (int64_t)slab) {
@@ -374,7 +379,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->g_count); release(c->g_lo); release(c->g_hi);
   release(c->g_chunks); release(c->wi); release(c->queue);
   release(c->g_cost); release(c->g_cost_off); release(c->xcd_plan);
-  release(c->cnt_ta);
+  release(c->cnt_ta); release(c->tail_order);
   release(c->nb_cnt); release(c->nb_tcnt); release(c->nb_ids);
   release(c->nb_off); release(c->nb_toff); release(c->rho);
   release(c->cnt_e); release(c->cnt_s); release(c->cnt_t);
@@ -409,6 +414,7 @@ int nb_set_config(nb_ctx* c, const nb_config* cfg) {
   drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = false;
+  c->tail_valid = false;
   c->nbr_valid = c->rho_valid = false;
   return NB_OK;
 }
@@ -492,6 +498,7 @@ int nb_set_systems(nb_ctx* c, int64_t n_sys, const int64_t* off) {
   drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = false;
+  c->tail_valid = false;
   c->nbr_valid = c->rho_valid = false;
   c->n_sys = n_sys;
   c->h_sys_off.assign(off, off + n_sys + 1);

@@ -21,6 +21,8 @@
 //    round-robin over the 8 XCDs) walks a contiguous stretch of groups,
 //    which share most of their list entries in that XCD's L2.
 // No MFMA: the pairwise sum is not a dense contraction.
+#include <algorithm>
+
 #include "nb_internal.h"
 
 namespace nb {
@@ -348,9 +350,24 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
 // stretches are cut where the estimated cost is balanced.  Workgroups are
 // dealt to the XCDs round-robin, so workgroup bid runs item
 // b[bid & 7] + (bid >> 3).
+// The last kTailItems items of each stretch (the launch's tail) are taken
+// longest first: item tail[x kTailItems + k] for position ws[x] + k (order
+// NULL, or ws[x] = b[x + 1]: no reordering).  Only the tail leaves Morton
+// order, so the L2 sharing between neighbouring groups is kept for the rest.
+constexpr int kTailItems = 2048;
+
 struct XcdPlan {
   int64_t b[9];
+  int64_t ws[8];
+  const uint32_t* tail;
 };
+
+__device__ __forceinline__ int64_t plan_item(const XcdPlan& plan, uint32_t x,
+                                             int64_t j) {
+  return (plan.tail && j >= plan.ws[x])
+             ? (int64_t)plan.tail[x * kTailItems + (j - plan.ws[x])]
+             : j;
+}
 
 // The plan b as a kernel argument; a plan that does not cover the n_wi
 // items (none computed for them) is replaced by equal stretches.  Returns
@@ -364,7 +381,11 @@ int64_t checked_plan(int64_t n_wi, int64_t* b, XcdPlan& plan) {
   }
   int64_t most = 0;
   for (int x = 0; x < 9; ++x) plan.b[x] = b[x];
-  for (int x = 0; x < 8; ++x) most = std::max(most, b[x + 1] - b[x]);
+  for (int x = 0; x < 8; ++x) {
+    plan.ws[x] = b[x + 1];
+    most = std::max(most, b[x + 1] - b[x]);
+  }
+  plan.tail = nullptr;
   return most * 8;
 }
 
@@ -378,9 +399,9 @@ k_force(const uint4* __restrict__ wi, XcdPlan plan, ForceArgs A) {
   __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<ORDER>::kBig : 1];
   const uint32_t bid = blockIdx.x;
   const uint32_t x = bid & 7u;
-  const int64_t w = plan.b[x] + (int64_t)(bid >> 3);
-  if (w >= plan.b[x + 1]) return;  // uniform over the workgroup
-  force_item<ORDER, COPIED>(wi[w], A, tile, tq, tile);
+  const int64_t j = plan.b[x] + (int64_t)(bid >> 3);
+  if (j >= plan.b[x + 1]) return;  // uniform over the workgroup
+  force_item<ORDER, COPIED>(wi[plan_item(plan, x, j)], A, tile, tq, tile);
 }
 
 // Estimated cost of a group's work items, in list entries per lane slice:
@@ -444,6 +465,53 @@ __global__ void k_xcd_split(int64_t n_groups, const uint64_t* __restrict__ off,
   plan[x] = g_chunks[g];
 }
 
+// The tail of XCD x's stretch (its last kTailItems items, fewer if the
+// stretch is shorter) sorted by estimated cost, longest first, ties in item
+// order: a bitonic sort in LDS by one workgroup per XCD.
+template <int KMAX, int WS>
+__global__ void __launch_bounds__(1024)
+k_tail_order(const uint4* __restrict__ wi,
+             const uint64_t* __restrict__ epj_off,
+             const uint64_t* __restrict__ spj_off, XcdPlan plan,
+             uint32_t* __restrict__ tail) {
+  __shared__ uint64_t key[kTailItems];
+  const uint32_t x = blockIdx.x;
+  const int64_t s0 = plan.ws[x];
+  const int n = (int)(plan.b[x + 1] - s0);
+  for (int i = threadIdx.x; i < kTailItems; i += blockDim.x) {
+    uint64_t k = ~0ull;
+    if (i < n) {
+      const uint4 it = wi[s0 + i];
+      const uint32_t g = it.x;
+      uint64_t c = item_cost<KMAX, WS>(epj_off[g + 1] - epj_off[g],
+                                       spj_off[g + 1] - spj_off[g],
+                                       (int)it.z);
+      if (c > 0xFFFFFFFEull) c = 0xFFFFFFFEull;
+      k = ((uint64_t)(0xFFFFFFFFu - (uint32_t)c) << 32) | (uint32_t)i;
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  for (int size = 2; size <= kTailItems; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < kTailItems; i += blockDim.x) {
+        const int jx = i ^ stride;
+        if (jx > i) {
+          const bool up = (i & size) == 0;
+          const uint64_t a = key[i], b = key[jx];
+          if ((a > b) == up) {
+            key[i] = b;
+            key[jx] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    tail[x * kTailItems + i] = (uint32_t)(s0 + (int64_t)(key[i] & 0xFFFFFFFFu));
+}
+
 // Copied lists (the paper's method G1, for comparison with index lists):
 // one wave per group writes every entry of its list, particles then
 // superparticles, as an FP32 offset from the group's centre and the mass,
@@ -491,9 +559,9 @@ k_force_queue(const uint4* __restrict__ wi, XcdPlan plan,
     unsigned int k = 0;
     if (threadIdx.x == 0) k = atomicAdd(&queue[x], 1u);
     k = __shfl(k, 0, 64);
-    const int64_t w = lo + (int64_t)k;
-    if (w >= hi) break;  // uniform over the workgroup
-    force_item<ORDER, false>(wi[w], A, tile, tq, tile);
+    const int64_t j = lo + (int64_t)k;
+    if (j >= hi) break;  // uniform over the workgroup
+    force_item<ORDER, false>(wi[plan_item(plan, x, j)], A, tile, tq, tile);
     __syncthreads();  // the next item reuses the tile and reduction space
   }
 }
@@ -588,9 +656,16 @@ int launch_force(nb_ctx* c) {
   const int64_t per_xcd = (c->n_wi + 7) / 8;
   if (per_xcd * 8 > 0x7FFFFFFFLL)
     return set_err(c, NB_ERR_INPUT, "too many force work items");
-  // the plan of the last list construction
+  // the plan of the last list construction, with its tail order when that
+  // was made for the same plan
   XcdPlan plan;
   const int64_t nblk = checked_plan(c->n_wi, c->xcd_b, plan);
+  if (c->tail_valid &&
+      std::equal(c->tail_b, c->tail_b + 9, plan.b)) {
+    for (int x = 0; x < 8; ++x)
+      plan.ws[x] = std::max(plan.b[x], plan.b[x + 1] - (int64_t)kTailItems);
+    plan.tail = c->tail_order.p;
+  }
   if (nblk > 0x7FFFFFFFLL)
     return set_err(c, NB_ERR_INPUT, "too many force work items");
   ForceArgs A;
@@ -642,6 +717,28 @@ int launch_force(nb_ctx* c) {
                        (const uint4*)c->wi.p, plan, A);
   }
   return hip_check(c, hipGetLastError(), "force launch");
+}
+
+// Longest-first order of the tail of every XCD's stretch of the force
+// launch, from the plan read back with the list totals.
+int launch_tail_order(nb_ctx* c) {
+  c->tail_valid = false;
+  if (c->n_wi <= 0) return NB_OK;
+  XcdPlan plan;
+  (void)checked_plan(c->n_wi, c->xcd_b, plan);
+  for (int x = 0; x < 8; ++x)
+    plan.ws[x] = std::max(plan.b[x], plan.b[x + 1] - (int64_t)kTailItems);
+  int rc = reserve(c, c->tail_order, 8 * (size_t)kTailItems);
+  if (rc) return rc;
+  auto k = c->cfg.order == 2 ? k_tail_order<2, 2> : k_tail_order<4, 1>;
+  hipLaunchKernelGGL(k, dim3(8), dim3(1024), 0, c->stream,
+                     (const uint4*)c->wi.p, (const uint64_t*)c->epj_off.p,
+                     (const uint64_t*)c->spj_off.p, plan, c->tail_order.p);
+  rc = hip_check(c, hipGetLastError(), "tail order launch");
+  if (rc) return rc;
+  std::copy(plan.b, plan.b + 9, c->tail_b);
+  c->tail_valid = true;
+  return NB_OK;
 }
 
 // Plan of the force launch (or, `neighbours`, of the SPH density launch)

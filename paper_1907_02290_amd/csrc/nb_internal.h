@@ -142,6 +142,10 @@ struct nb_ctx {
   nb::DBuf<uint64_t> xcd_plan;   // 9 item indices
   int64_t xcd_b[9] = {};
   int64_t nbr_b[9] = {};         // the same for the SPH density launch
+  // longest-first order of the last items of each XCD's stretch
+  nb::DBuf<uint32_t> tail_order;
+  int64_t tail_b[9] = {};        // the plan it was made for
+  bool tail_valid = false;
   nb::DBuf<unsigned int> queue;  // per-XCD counters of the persistent launch
 
   // short-range neighbour lists (nb_neighbour_lists): per group the
@@ -309,6 +313,7 @@ int launch_force(nb_ctx* c);
 // device plan of the force (or SPH density) launch, read back with the
 // lists' totals into xcd_b (nbr_b)
 int launch_xcd_plan(nb_ctx* c, bool neighbours);
+int launch_tail_order(nb_ctx* c);  // after the plan is read back
 // nb_step.hip
 int launch_kick_drift(nb_ctx* c, double dt_kick, double dt_drift);
 int launch_pack(nb_ctx* c, const double* x, const double* y, const double* z,
