@@ -239,7 +239,7 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
     return set_err(c, NB_ERR_STATE, "lists need a tree of the current positions");
   int rc;
   c->lists_valid = c->lists_reusable = false;
-  c->tail_valid = false;
+  c->tail.valid = false;
   // one pass (counts and tokens into per-group slabs sized from the last
   // construction) when the slabs fit in a bounded buffer; otherwise, or when
   // a group overflows its slab, a count pass and an exact fill pass
@@ -379,7 +379,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->g_count); release(c->g_lo); release(c->g_hi);
   release(c->g_chunks); release(c->wi); release(c->queue);
   release(c->g_cost); release(c->g_cost_off); release(c->xcd_plan);
-  release(c->cnt_ta); release(c->tail_order);
+  release(c->cnt_ta); release(c->tail.order);
   release(c->nb_cnt); release(c->nb_tcnt); release(c->nb_ids);
   release(c->nb_off); release(c->nb_toff); release(c->rho);
   release(c->cnt_e); release(c->cnt_s); release(c->cnt_t);
@@ -414,7 +414,7 @@ int nb_set_config(nb_ctx* c, const nb_config* cfg) {
   drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = false;
-  c->tail_valid = false;
+  c->tail.valid = false;
   c->nbr_valid = c->rho_valid = false;
   return NB_OK;
 }
@@ -498,7 +498,7 @@ int nb_set_systems(nb_ctx* c, int64_t n_sys, const int64_t* off) {
   drop_graph(c);
   c->tree_valid = c->positions_fresh = false;
   c->lists_valid = c->lists_reusable = false;
-  c->tail_valid = false;
+  c->tail.valid = false;
   c->nbr_valid = c->rho_valid = false;
   c->n_sys = n_sys;
   c->h_sys_off.assign(off, off + n_sys + 1);

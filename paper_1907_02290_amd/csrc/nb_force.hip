@@ -369,6 +369,14 @@ __device__ __forceinline__ int64_t plan_item(const XcdPlan& plan, uint32_t x,
              : j;
 }
 
+// The tail order t in the plan, when it was made for the same stretches.
+void use_tail(const TailOrder& t, XcdPlan& plan) {
+  if (!t.valid || !std::equal(t.b, t.b + 9, plan.b)) return;
+  for (int x = 0; x < 8; ++x)
+    plan.ws[x] = std::max(plan.b[x], plan.b[x + 1] - (int64_t)kTailItems);
+  plan.tail = t.order.p;
+}
+
 // The plan b as a kernel argument; a plan that does not cover the n_wi
 // items (none computed for them) is replaced by equal stretches.  Returns
 // the grid size: 8 x the longest stretch.
@@ -660,12 +668,7 @@ int launch_force(nb_ctx* c) {
   // was made for the same plan
   XcdPlan plan;
   const int64_t nblk = checked_plan(c->n_wi, c->xcd_b, plan);
-  if (c->tail_valid &&
-      std::equal(c->tail_b, c->tail_b + 9, plan.b)) {
-    for (int x = 0; x < 8; ++x)
-      plan.ws[x] = std::max(plan.b[x], plan.b[x + 1] - (int64_t)kTailItems);
-    plan.tail = c->tail_order.p;
-  }
+  use_tail(c->tail, plan);
   if (nblk > 0x7FFFFFFFLL)
     return set_err(c, NB_ERR_INPUT, "too many force work items");
   ForceArgs A;
@@ -722,22 +725,23 @@ int launch_force(nb_ctx* c) {
 // Longest-first order of the tail of every XCD's stretch of the force
 // launch, from the plan read back with the list totals.
 int launch_tail_order(nb_ctx* c) {
-  c->tail_valid = false;
+  TailOrder& t = c->tail;
+  t.valid = false;
   if (c->n_wi <= 0) return NB_OK;
   XcdPlan plan;
   (void)checked_plan(c->n_wi, c->xcd_b, plan);
   for (int x = 0; x < 8; ++x)
     plan.ws[x] = std::max(plan.b[x], plan.b[x + 1] - (int64_t)kTailItems);
-  int rc = reserve(c, c->tail_order, 8 * (size_t)kTailItems);
+  int rc = reserve(c, t.order, 8 * (size_t)kTailItems);
   if (rc) return rc;
   auto k = c->cfg.order == 2 ? k_tail_order<2, 2> : k_tail_order<4, 1>;
   hipLaunchKernelGGL(k, dim3(8), dim3(1024), 0, c->stream,
                      (const uint4*)c->wi.p, (const uint64_t*)c->epj_off.p,
-                     (const uint64_t*)c->spj_off.p, plan, c->tail_order.p);
+                     (const uint64_t*)c->spj_off.p, plan, t.order.p);
   rc = hip_check(c, hipGetLastError(), "tail order launch");
   if (rc) return rc;
-  std::copy(plan.b, plan.b + 9, c->tail_b);
-  c->tail_valid = true;
+  std::copy(plan.b, plan.b + 9, t.b);
+  t.valid = true;
   return NB_OK;
 }
 

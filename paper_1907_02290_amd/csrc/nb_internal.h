@@ -55,6 +55,14 @@ struct DBuf {
   size_t cap = 0;
 };
 
+// Longest-first order of the last items of each XCD's stretch of the force
+// launch, and the stretches (item indices b[0..8]) it was made for.
+struct TailOrder {
+  DBuf<uint32_t> order;
+  int64_t b[9] = {};
+  bool valid = false;
+};
+
 struct TimerRec {
   int phase;
   hipEvent_t a, b;
@@ -143,9 +151,7 @@ struct nb_ctx {
   int64_t xcd_b[9] = {};
   int64_t nbr_b[9] = {};         // the same for the SPH density launch
   // longest-first order of the last items of each XCD's stretch
-  nb::DBuf<uint32_t> tail_order;
-  int64_t tail_b[9] = {};        // the plan it was made for
-  bool tail_valid = false;
+  nb::TailOrder tail;
   nb::DBuf<unsigned int> queue;  // per-XCD counters of the persistent launch
 
   // short-range neighbour lists (nb_neighbour_lists): per group the
