@@ -45,6 +45,7 @@ __device__ inline int64_t xcd_block(int64_t nblk) {
 // leaf is its id with the top bit set.
 constexpr uint32_t kLeafTag = 0x80000000u;
 constexpr int kSeg = 16;  // tokens per 64-byte output segment
+constexpr int kExpandBatch = 4;  // 64-token chunks per round of k_expand
 
 // LEARN: the variant used with per-group list refresh.  Threads take the
 // groups listed in `sel` (all groups when sel is NULL), the centres come
@@ -545,34 +546,49 @@ k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   }
   uint64_t oe = epj_off[g], os = spj_off[g];
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  // kExpandBatch chunks of 64 tokens per round: their token loads, then
+  // their leaves' record loads, are issued together, so a round waits for
+  // two memory latencies instead of two per chunk
   for (int ri = 0; ri < nr; ++ri) {
-  const uint64_t t0 = r0[ri], t1 = r1[ri];
-  for (uint64_t cb = t0; cb < t1; cb += 64) {
-    const uint64_t q = cb + lane;
-    const bool ok = q < t1;
-    const uint32_t tk = ok ? tok[q] : 0u;
-    const bool is_leaf = ok && (tk & kLeafTag);
-    const bool is_spj = ok && !(tk & kLeafTag);
-    const uint64_t sm = __ballot(is_spj);
-    if (is_spj) spj[os + __popcll(sm & lt)] = tk;
-    os += __popcll(sm);
-    uint32_t b = 0, n = 0;
-    if (is_leaf) {
-      const uint4 m = rec[tk & ~kLeafTag].meta;
-      b = m.x;
-      n = m.y - m.x;
-    }
-    uint32_t inc = n;
+    const uint64_t t0 = r0[ri], t1 = r1[ri];
+    for (uint64_t cb = t0; cb < t1; cb += 64 * kExpandBatch) {
+      uint32_t tk[kExpandBatch], bb[kExpandBatch], nn[kExpandBatch];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t t = __shfl_up(inc, d, 64);
-      if (lane >= d) inc += t;
+      for (int u = 0; u < kExpandBatch; ++u) {
+        const uint64_t q = cb + 64 * u + lane;
+        tk[u] = q < t1 ? tok[q] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < kExpandBatch; ++u) {
+        const uint64_t q = cb + 64 * u + lane;
+        bb[u] = 0;
+        nn[u] = 0;
+        if (q < t1 && (tk[u] & kLeafTag)) {
+          const uint4 m = rec[tk[u] & ~kLeafTag].meta;
+          bb[u] = m.x;
+          nn[u] = m.y - m.x;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kExpandBatch; ++u) {
+        const bool ok = cb + 64 * u + lane < t1;
+        const bool is_spj = ok && !(tk[u] & kLeafTag);
+        const uint64_t sm = __ballot(is_spj);
+        if (is_spj) spj[os + __popcll(sm & lt)] = tk[u];
+        os += __popcll(sm);
+        const uint32_t n = nn[u], b = bb[u];
+        uint32_t inc = n;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t v = __shfl_up(inc, d, 64);
+          if (lane >= d) inc += v;
+        }
+        const uint32_t total = __shfl(inc, 63, 64);
+        uint32_t* dst = epj + oe + (inc - n);
+        for (uint32_t j = 0; j < n; ++j) dst[j] = b + j;
+        oe += total;
+      }
     }
-    const uint32_t total = __shfl(inc, 63, 64);
-    uint32_t* dst = epj + oe + (inc - n);
-    for (uint32_t j = 0; j < n; ++j) dst[j] = b + j;
-    oe += total;
-  }
   }
 }
 
