@@ -559,15 +559,24 @@ k_mom_leaf(int64_t cnt, const uint32_t* __restrict__ list,
   const uint4 m = rec[c].meta;
   const double4 g = rec[c].geo;
   float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-  for (uint32_t p = m.x; p < m.y; ++p) {
-    const double4 P = pos[p];
-    const float w = (float)P.w;
-    const float dx = (float)(P.x - g.x), dy = (float)(P.y - g.y),
-                dz = (float)(P.z - g.z);
-    M += w;
-    sx = fmaf(w, dx, sx);
-    sy = fmaf(w, dy, sy);
-    sz = fmaf(w, dz, sz);
+  // particles in batches of four, loaded together, summed in order
+  for (uint32_t p0 = m.x; p0 < m.y; p0 += 4) {
+    double4 P[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (p0 + u < m.y) P[u] = pos[p0 + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (p0 + u < m.y) {
+        const float w = (float)P[u].w;
+        const float dx = (float)(P[u].x - g.x), dy = (float)(P[u].y - g.y),
+                    dz = (float)(P[u].z - g.z);
+        M += w;
+        sx = fmaf(w, dx, sx);
+        sy = fmaf(w, dy, sy);
+        sz = fmaf(w, dz, sz);
+      }
+    }
   }
   const float inv = M > 0.f ? 1.0f / M : 0.f;
   const float ox = sx * inv, oy = sy * inv, oz = sz * inv;
