@@ -126,6 +126,40 @@ def test_batch_matches_oracle_per_system():
         assert np.median(num / den) < 1e-5
 
 
+def test_batch_many_groups_two_lane_walk_and_slabs():
+    """Enough groups for the walk on two lanes per group; the second
+    construction (same positions) writes its tokens into per-group slabs in
+    one pass.  Both give every system the oracle's lists."""
+    say("case batch many groups")
+    d = _batch(seed=13, n_sys=4, lo=13, hi=15)
+    off = d["offsets"]
+    with _ctx(d, n_grp=4) as ctx:
+        ctx.set_systems(off)
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        assert ctx.get_info()["n_groups"] >= 8192
+        first = ctx.get_lists()
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)  # one pass, slabs
+        eo, e, so, s = ctx.get_lists()
+        for a, b in zip(first, (eo, e, so, s)):
+            np.testing.assert_array_equal(a, b)
+        g = ctx.get_groups()
+        c = ctx.get_cells()
+    roots = np.nonzero(c["level"] == 0)[0]
+    for si in range(off.size - 1):
+        b, en = int(off[si]), int(off[si + 1])
+        sub = _sub(d, b, en)
+        t = oracle.Tree(sub["x"], sub["y"], sub["z"], sub["m"], 8, 4)
+        t.make_lists(0.5)
+        oeo, oe, oso, os_ = t.lists()
+        gs = np.nonzero((g["begin"] >= b) & (g["begin"] < en))[0]
+        assert gs.size == t.n_groups
+        for j, gi in enumerate(gs):
+            np.testing.assert_array_equal(e[eo[gi]:eo[gi + 1]],
+                                          oe[oeo[j]:oeo[j + 1]] + b)
+            np.testing.assert_array_equal(s[so[gi]:so[gi + 1]],
+                                          os_[oso[j]:oso[j + 1]] + roots[si])
+
+
 def test_batch_reuse_steps_stay_independent():
     say("case batch reuse")
     d = _batch(seed=3, n_sys=4, lo=8, hi=11)
