@@ -378,7 +378,8 @@ def test_device_resident_input_matches_host_input():
 
 
 @pytest.mark.parametrize("name,order,sample", [("plummer_1m", 2, 256),
-                                               ("disk_4m", 1, 256)])
+                                               ("disk_4m", 1, 256),
+                                               ("sphere_4m", 1, 256)])
 def test_full_size_sampled(name, order, sample):
     """Full-size systems in the benchmark's launch configuration: keys, tree
     and groups compared whole; lists and forces on sampled groups."""

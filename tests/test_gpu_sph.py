@@ -170,11 +170,13 @@ def test_errors():
             ctx.sph_density(0.1)
 
 
-def test_full_size_sampled():
-    """N = 2^22 (the cold sphere, leaf 16, n_grp 64) with h for about 64
-    neighbours: lists of sampled groups and their densities."""
-    say("case neighbour lists full size")
-    d, p = workloads.make("sphere_4m")
+@pytest.mark.parametrize("name", ["sphere_4m", "disk_4m"])
+def test_full_size_sampled(name):
+    """N = 2^22 (the cold sphere, leaf 16, n_grp 64; the disk, leaf 8,
+    n_grp 256) with h for about 64 neighbours in a unit ball: lists of
+    sampled groups and every density."""
+    say("case neighbour lists full size %s" % name)
+    d, p = workloads.make(name)
     n = d["x"].size
     h = (64 / n) ** (1 / 3)   # unit ball of n particles: 64 within h
     t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], p["n_leaf"], p["n_grp"])
@@ -191,4 +193,4 @@ def test_full_size_sampled():
     for g in rng.choice(off.size - 1, 256, replace=False):
         np.testing.assert_array_equal(gids[goff[g]:goff[g + 1]],
                                       ids[off[g]:off[g + 1]])
-    _check_rho(rho, rho_o, "sphere_4m")
+    _check_rho(rho, rho_o, name)
