@@ -117,13 +117,15 @@ __device__ __forceinline__ void slice_sum(const float4* __restrict__ t,
   ph += tp;
 }
 
-// Largest tile: 64 x 4 entries.  The quadrupole kernel stages 2 x 16 bytes
-// of second moments per entry besides the record, so its tiles stop at
-// 64 x 2 entries, which keeps its LDS (and so its occupancy) in line with
-// its registers.
+// Largest tile: 64 x 3 entries for the monopole kernel, whose prefetched
+// records (one FP64 record per slice and lane) then fit six waves per SIMD
+// (77 VGPRs; with 64 x 4 entries it needed 93, five waves).  The quadrupole
+// kernel stages 2 x 16 bytes of second moments per entry besides the
+// record, so its tiles stop at 64 x 2 entries, which keeps its LDS (and so
+// its occupancy) in line with its registers.
 template <int ORDER>
 struct Tiles {
-  static constexpr int kMaxSlices = ORDER == 2 ? 2 : 4;
+  static constexpr int kMaxSlices = ORDER == 2 ? 2 : 3;
   static constexpr int kBig = kTile * kMaxSlices;
 };
 
@@ -397,11 +399,10 @@ int64_t checked_plan(int64_t n_wi, int64_t* b, XcdPlan& plan) {
   return most * 8;
 }
 
-// One launch, one workgroup (one wavefront) per work item.  Five waves per
-// SIMD leave room for the next tile's records in registers (93 VGPRs); at
-// six the compiler spills them.
+// One launch, one workgroup (one wavefront) per work item, six waves per
+// SIMD with the next tile's records in registers.
 template <int ORDER, bool COPIED>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_force(const uint4* __restrict__ wi, XcdPlan plan, ForceArgs A) {
   __shared__ float4 tile[Tiles<ORDER>::kBig];
   __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<ORDER>::kBig : 1];
@@ -734,7 +735,8 @@ int launch_tail_order(nb_ctx* c) {
     plan.ws[x] = std::max(plan.b[x], plan.b[x + 1] - (int64_t)kTailItems);
   int rc = reserve(c, t.order, 8 * (size_t)kTailItems);
   if (rc) return rc;
-  auto k = c->cfg.order == 2 ? k_tail_order<2, 2> : k_tail_order<4, 1>;
+  auto k = c->cfg.order == 2 ? k_tail_order<Tiles<2>::kMaxSlices, 2>
+                              : k_tail_order<Tiles<1>::kMaxSlices, 1>;
   hipLaunchKernelGGL(k, dim3(8), dim3(1024), 0, c->stream,
                      (const uint4*)c->wi.p, (const uint64_t*)c->epj_off.p,
                      (const uint64_t*)c->spj_off.p, plan, t.order.p);
@@ -755,8 +757,9 @@ int launch_xcd_plan(nb_ctx* c, bool neighbours) {
   if (!rc) rc = reserve(c, c->xcd_plan, 9);
   if (rc) return rc;
   auto k = neighbours ? k_group_cost<1, 1>
-                      : (c->cfg.order == 2 ? k_group_cost<2, 2>
-                                           : k_group_cost<4, 1>);
+                      : (c->cfg.order == 2
+                             ? k_group_cost<Tiles<2>::kMaxSlices, 2>
+                             : k_group_cost<Tiles<1>::kMaxSlices, 1>);
   hipLaunchKernelGGL(k, dim3(grid_for(c->n_groups, 256)), dim3(256), 0,
                      c->stream, c->n_groups, (const uint32_t*)c->g_chunks.p,
                      (const uint4*)c->wi.p,
