@@ -616,12 +616,26 @@ k_density(const uint4* __restrict__ wi, XcdPlan plan,
   const uint32_t n = (uint32_t)(nb_off[g + 1] - o0);
   const uint32_t last = n ? n - 1 : 0;
   float sum = 0.f;
+  // the next tile's record and the id of the one after are loaded while a
+  // tile is summed (as in the force kernel)
+  double4 P = make_double4(0.0, 0.0, 0.0, 0.0);
+  uint32_t nid = 0;
+  if (n > 0) {
+    const uint32_t e = (uint32_t)lane;
+    P = pos[nb_ids[o0 + (e < last ? e : last)]];
+    const uint32_t e2 = (uint32_t)kTile + e;
+    nid = nb_ids[o0 + (e2 < last ? e2 : last)];
+  }
   for (uint32_t tb = 0; tb < n; tb += (uint32_t)kTile) {
-    const uint32_t e = tb + (uint32_t)lane;
-    const double4 P = pos[nb_ids[o0 + (e < last ? e : last)]];
     __syncthreads();
     tile[lane] = make_float4((float)(P.x - cg.x), (float)(P.y - cg.y),
                              (float)(P.z - cg.z), (float)P.w);
+    const uint32_t nb = tb + (uint32_t)kTile;
+    if (nb < n) {
+      P = pos[nid];
+      const uint32_t e = nb + (uint32_t)kTile + (uint32_t)lane;
+      nid = nb_ids[o0 + (e < last ? e : last)];
+    }
     __syncthreads();
     if (act) {
       const int valid = n - tb < (uint32_t)kTile ? (int)(n - tb) : kTile;
