@@ -640,6 +640,7 @@ k_density(const uint4* __restrict__ wi, XcdPlan plan,
     if (act) {
       const int valid = n - tb < (uint32_t)kTile ? (int)(n - tb) : kTile;
       const int hi = blk1 < valid ? blk1 : valid;
+#pragma unroll 8
       for (int k = blk0; k < hi; ++k) {
         const float4 j = tile[k];
         const float dx = j.x - xi, dy = j.y - yi, dz = j.z - zi;
