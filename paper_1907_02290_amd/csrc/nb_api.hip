@@ -381,6 +381,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->g_cost); release(c->g_cost_off); release(c->xcd_plan);
   release(c->cnt_ta); release(c->tail.order);
   release(c->nb_cnt); release(c->nb_tcnt); release(c->nb_ids);
+  release(c->nb_tcnt_a);
   release(c->nb_off); release(c->nb_toff); release(c->rho);
   release(c->cnt_e); release(c->cnt_s); release(c->cnt_t);
   release(c->epj_off); release(c->spj_off); release(c->tok_off);

@@ -161,6 +161,7 @@ struct nb_ctx {
   double nbr_h = 0.0;
   int64_t n_nbr = 0;
   nb::DBuf<uint32_t> nb_cnt, nb_tcnt, nb_ids;
+  nb::DBuf<uint32_t> nb_tcnt_a;  // tokens of the first half of each walk
   nb::DBuf<uint64_t> nb_off, nb_toff;
   nb::DBuf<float> rho;
 

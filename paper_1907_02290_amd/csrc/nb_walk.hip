@@ -646,6 +646,9 @@ k_max_u32(int64_t n, const uint32_t* __restrict__ v,
 // (zero inside) is at most half the cell's side plus h.  Cells that fail
 // are skipped with their subtree; an opened leaf becomes a token, expanded
 // into its particles as for the gravity lists.  FP64, explicit rounding.
+// Two lanes per group, split at gd as in the gravity walk; the count pass
+// records the first half's tokens (cnt_ta) so the fill's second half writes
+// after them.
 template <bool FILL>
 __global__ void __launch_bounds__(kWalkThreads)
 k_walk_nbr(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
@@ -656,13 +659,18 @@ k_walk_nbr(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
            const uint32_t* __restrict__ seg,
            const uint32_t* __restrict__ croot, const Root* __restrict__ root,
            double h, uint32_t* __restrict__ cnt_e,
-           uint32_t* __restrict__ cnt_t, const uint64_t* __restrict__ tok_off,
+           uint32_t* __restrict__ cnt_t, uint32_t* __restrict__ cnt_ta,
+           const uint64_t* __restrict__ tok_off,
            uint32_t* __restrict__ tok) {
   __shared__ uint32_t stage[FILL ? kSeg : 1][kWalkThreads];
   const int64_t blk = xcd_block(nblk);
   if (blk >= nblk) return;
-  const int64_t g = blk * kWalkThreads + threadIdx.x;
-  if (g >= n_walk) return;
+  // two lanes per group, split at gd as in the gravity walk (n_walk = 2 x
+  // groups: the lanes of a group leave together)
+  const int64_t tt = blk * kWalkThreads + threadIdx.x;
+  if (tt >= n_walk) return;
+  const int64_t g = tt >> 1;
+  const int half = (int)(tt & 1);
   const uint32_t gb = g_begin[g];
   const uint32_t ge = gb + g_count[g];
   const double4 lo = g_lo[g], hi = g_hi[g];
@@ -678,9 +686,9 @@ k_walk_nbr(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
   const Root* rt = root + sys;
   const double rx = rt->lo[0], ry = rt->lo[1], rz = rt->lo[2];
   const int k = rt->k;
-  uint32_t c = croot[sys];
-  const uint32_t nc = croot[sys + 1];
-  uint64_t out = FILL ? tok_off[g] : 0;
+  uint32_t c = half ? gd : croot[sys];
+  const uint32_t nc = half ? croot[sys + 1] : gd;
+  uint64_t out = FILL ? tok_off[g] + (half ? cnt_ta[g] : 0u) : 0;
   int sc = 0;
   uint32_t ne = 0, nl = 0;
   // the gravity walk's visit: one record load, no divergent branch, full
@@ -760,8 +768,13 @@ k_walk_nbr(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
     }
     for (int t = 0; t < sc; ++t) tok[out + t] = stage[t][threadIdx.x];
   } else {
-    cnt_e[g] = ne;
-    cnt_t[g] = nl;
+    const uint32_t e2 = ne + __shfl_xor(ne, 1, 64);
+    const uint32_t t2 = nl + __shfl_xor(nl, 1, 64);
+    if (half == 0) {
+      cnt_e[g] = e2;
+      cnt_t[g] = t2;
+      cnt_ta[g] = nl;
+    }
   }
 }
 
@@ -954,13 +967,16 @@ int launch_nbr_count(nb_ctx* c, double h) {
   const size_t ng = (size_t)c->n_groups;
   int rc = reserve(c, c->nb_cnt, ng);
   if (!rc) rc = reserve(c, c->nb_tcnt, ng);
+  if (!rc) rc = reserve(c, c->nb_tcnt_a, ng);
   if (!rc) rc = reserve(c, c->nb_off, ng + 1);
   if (!rc) rc = reserve(c, c->nb_toff, ng + 1);
   if (rc) return rc;
-  const int64_t nblk = grid_for(c->n_groups, kWalkThreads);
+  // two lanes per group
+  const int64_t nblk = grid_for(2 * c->n_groups, kWalkThreads);
   if (nblk > 0)
     hipLaunchKernelGGL(k_walk_nbr<false>, dim3((unsigned)((nblk + 7) / 8 * 8)),
-                       dim3(kWalkThreads), 0, c->stream, c->n_groups, nblk,
+                       dim3(kWalkThreads), 0, c->stream, 2 * c->n_groups,
+                       nblk,
                        (const uint32_t*)c->g_begin.p,
                        (const uint32_t*)c->g_count.p,
                        (const double4*)c->g_lo.p, (const double4*)c->g_hi.p,
@@ -968,8 +984,8 @@ int launch_nbr_count(nb_ctx* c, double h) {
                        (const CellRec*)c->c_rec.p, (const uint4*)c->c_wrec.p,
                        (const uint32_t*)c->seg.p,
                        (const uint32_t*)c->croot.p, (const Root*)c->root.p, h,
-                       c->nb_cnt.p, c->nb_tcnt.p, (const uint64_t*)nullptr,
-                       (uint32_t*)nullptr);
+                       c->nb_cnt.p, c->nb_tcnt.p, c->nb_tcnt_a.p,
+                       (const uint64_t*)nullptr, (uint32_t*)nullptr);
   if ((rc = hip_check(c, hipGetLastError(), "neighbour walk launch")))
     return rc;
   rc = scan_u32_to_u64(c, c->nb_cnt.p, c->nb_off.p, c->n_groups);
@@ -979,10 +995,10 @@ int launch_nbr_count(nb_ctx* c, double h) {
 
 // Fill pass into c->tok (n tokens reserved) and expand into c->nb_ids.
 int launch_nbr_fill(nb_ctx* c, double h) {
-  const int64_t nblk = grid_for(c->n_groups, kWalkThreads);
+  const int64_t nblk = grid_for(2 * c->n_groups, kWalkThreads);
   if (nblk <= 0) return NB_OK;
   hipLaunchKernelGGL(k_walk_nbr<true>, dim3((unsigned)((nblk + 7) / 8 * 8)),
-                     dim3(kWalkThreads), 0, c->stream, c->n_groups, nblk,
+                     dim3(kWalkThreads), 0, c->stream, 2 * c->n_groups, nblk,
                      (const uint32_t*)c->g_begin.p,
                      (const uint32_t*)c->g_count.p,
                      (const double4*)c->g_lo.p, (const double4*)c->g_hi.p,
@@ -991,7 +1007,7 @@ int launch_nbr_fill(nb_ctx* c, double h) {
                      (const uint32_t*)c->seg.p,
                      (const uint32_t*)c->croot.p, (const Root*)c->root.p, h,
                      (uint32_t*)nullptr, (uint32_t*)nullptr,
-                     (const uint64_t*)c->nb_toff.p, c->tok.p);
+                     c->nb_tcnt_a.p, (const uint64_t*)c->nb_toff.p, c->tok.p);
   int rc = hip_check(c, hipGetLastError(), "neighbour fill launch");
   if (rc) return rc;
   // only leaf tokens: the superparticle side of the expand is never written
