@@ -547,45 +547,57 @@ k_make_wi(int64_t n_groups, const uint32_t* __restrict__ g_begin,
 // Offsets from the cell's geometric centre are formed in FP64 and kept in
 // FP32; parents combine their children with the parallel-axis rule in FP32
 // (the child-to-parent centre shift is an exact power of two).
+// Leaves: four lanes per leaf, lane s taking particles s, s + 4, ... of it,
+// so that the lanes of a wave read consecutive particles; the four partial
+// sums are combined pairwise across the lanes.
+constexpr int kLeafLanes = 4;
+
+__device__ inline float sum_leaf_lanes(float v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  return v;
+}
+
 template <bool QUAD>
 __global__ void __launch_bounds__(256)
 k_mom_leaf(int64_t cnt, const uint32_t* __restrict__ list,
            const CellRec* __restrict__ rec, const double4* __restrict__ pos,
            float4* __restrict__ mom, float4* __restrict__ quad,
            double4* __restrict__ pm) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = gt / kLeafLanes;
+  const uint32_t s = (uint32_t)(gt % kLeafLanes);
+  // the lanes of one leaf leave together, so the exchanges below only
+  // involve lanes that are still running
   if (t >= cnt) return;
   const uint32_t c = list[t];
   const uint4 m = rec[c].meta;
   const double4 g = rec[c].geo;
   float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
-  // particles in batches of four, loaded together, summed in order
-  for (uint32_t p0 = m.x; p0 < m.y; p0 += 4) {
-    double4 P[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (p0 + u < m.y) P[u] = pos[p0 + u];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (p0 + u < m.y) {
-        const float w = (float)P[u].w;
-        const float dx = (float)(P[u].x - g.x), dy = (float)(P[u].y - g.y),
-                    dz = (float)(P[u].z - g.z);
-        M += w;
-        sx = fmaf(w, dx, sx);
-        sy = fmaf(w, dy, sy);
-        sz = fmaf(w, dz, sz);
-      }
-    }
+  for (uint32_t p = m.x + s; p < m.y; p += kLeafLanes) {
+    const double4 P = pos[p];
+    const float w = (float)P.w;
+    const float dx = (float)(P.x - g.x), dy = (float)(P.y - g.y),
+                dz = (float)(P.z - g.z);
+    M += w;
+    sx = fmaf(w, dx, sx);
+    sy = fmaf(w, dy, sy);
+    sz = fmaf(w, dz, sz);
   }
+  M = sum_leaf_lanes(M);
+  sx = sum_leaf_lanes(sx);
+  sy = sum_leaf_lanes(sy);
+  sz = sum_leaf_lanes(sz);
   const float inv = M > 0.f ? 1.0f / M : 0.f;
   const float ox = sx * inv, oy = sy * inv, oz = sz * inv;
-  mom[c] = make_float4(ox, oy, oz, M);
-  pm[c] = make_double4(g.x + (double)ox, g.y + (double)oy, g.z + (double)oz,
-                       (double)M);
+  if (s == 0) {
+    mom[c] = make_float4(ox, oy, oz, M);
+    pm[c] = make_double4(g.x + (double)ox, g.y + (double)oy,
+                         g.z + (double)oz, (double)M);
+  }
   if (QUAD) {
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
-    for (uint32_t p = m.x; p < m.y; ++p) {
+    for (uint32_t p = m.x + s; p < m.y; p += kLeafLanes) {
       const double4 P = pos[p];
       const float w = (float)P.w;
       const float dx = (float)(P.x - g.x) - ox, dy = (float)(P.y - g.y) - oy,
@@ -597,8 +609,16 @@ k_mom_leaf(int64_t cnt, const uint32_t* __restrict__ list,
       s4 = fmaf(w * dx, dz, s4);
       s5 = fmaf(w * dy, dz, s5);
     }
-    quad[2 * (int64_t)c] = make_float4(s0, s1, s2, s3);
-    quad[2 * (int64_t)c + 1] = make_float4(s4, s5, 0.f, 0.f);
+    s0 = sum_leaf_lanes(s0);
+    s1 = sum_leaf_lanes(s1);
+    s2 = sum_leaf_lanes(s2);
+    s3 = sum_leaf_lanes(s3);
+    s4 = sum_leaf_lanes(s4);
+    s5 = sum_leaf_lanes(s5);
+    if (s == 0) {
+      quad[2 * (int64_t)c] = make_float4(s0, s1, s2, s3);
+      quad[2 * (int64_t)c + 1] = make_float4(s4, s5, 0.f, 0.f);
+    }
   }
 }
 
@@ -833,7 +853,8 @@ int launch_moments(nb_ctx* c) {
   auto leaf = quad ? k_mom_leaf<true> : k_mom_leaf<false>;
   auto inner = quad ? k_mom_internal<true> : k_mom_internal<false>;
   if (c->n_leaves > 0)
-    hipLaunchKernelGGL(leaf, dim3(grid_for(c->n_leaves, 256)), dim3(256), 0,
+    hipLaunchKernelGGL(leaf, dim3(grid_for(kLeafLanes * c->n_leaves, 256)),
+                       dim3(256), 0,
                        c->stream, c->n_leaves,
                        (const uint32_t*)c->lvl_cells.p + c->lvl_off[kLevels],
                        (const CellRec*)c->c_rec.p, (const double4*)c->pos.p,

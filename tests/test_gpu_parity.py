@@ -169,13 +169,17 @@ def test_lists_bit_exact_one_thread_walk(kind, n, n_leaf, n_grp, theta):
         compare_lists(ctx, t)
 
 
+@pytest.mark.parametrize("n,n_leaf", [(20000, 8), (20011, 1), (20011, 3),
+                                      (20011, 13), (20011, 32)])
 @pytest.mark.parametrize("order", [1, 2])
-def test_moments_within_fp32_tolerance(order):
-    say("case moments order=%d" % order)
-    d = system("plummer", 20000, seed=3)
-    with gpu_ctx(d, order=order) as ctx:
+def test_moments_within_fp32_tolerance(order, n, n_leaf):
+    """Leaves of 1 to 32 particles: several particles per lane of a leaf,
+    one, or idle lanes."""
+    say("case moments order=%d n=%d n_leaf=%d" % (order, n, n_leaf))
+    d = system("plummer", n, seed=3)
+    with gpu_ctx(d, order=order, n_leaf=n_leaf) as ctx:
         ctx.build_tree()
-        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 64)
+        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], n_leaf, 64)
         M, X, S = ctx.get_moments()
         oM, oX, oS = t.moments()
         lev = t.cells()["level"].astype(np.int64)
