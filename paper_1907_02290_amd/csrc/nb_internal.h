@@ -287,7 +287,7 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                     const uint64_t* epj_off, const uint64_t* spj_off,
                     uint32_t* epj, uint32_t* spj, uint32_t slab = 0);
 int launch_expand_slab(nb_ctx* c, uint32_t slab);
-int walk_tile(int64_t n_walk);  // lanes per group of the walk
+int walk_tile(int64_t n_walk, bool refresh = false);  // lanes per group of the walk
 bool split_walk(const nb_ctx* c, int64_t n_walk);  // two slabs per group
 int launch_list_stats(nb_ctx* c);
 // short-range walk: count pass (nb_cnt, nb_tcnt and their scans) and, with
