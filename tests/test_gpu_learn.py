@@ -113,6 +113,33 @@ def test_refresh_mode_keeps_construction_lists(kind, n):
         np.testing.assert_array_equal(ctx.cell_sides(), t.cell_sides())
 
 
+def test_refresh_mode_tile_walk_many_groups():
+    """Refresh-mode walks over 8192 or more groups (the construction walk
+    and a large refresh selection) run in lane tiles; their lists must be
+    the oracle's."""
+    say("case refresh mode, tile walk over many groups")
+    d = sheared(200000, 4)
+    dt = 1 / 64
+    n_grp = 16
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, n_grp)
+    t.make_lists(THETA)
+    assert t.n_groups >= 8192
+    with ctx_for(d, n_grp=n_grp, k_max=8) as ctx:
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        compare_lists(ctx, t)
+        ctx.kick_drift(0.0, dt)
+        ctx.compute_forces(nb.NB_REUSE_LIST)
+        x, y, z = drift(d, dt, 1)
+        t.refresh(x, y, z, d["m"])
+        ng = t.n_groups
+        sel = np.arange(0, ng, 1, dtype=np.int64)[(np.arange(ng) % 5) != 0]
+        assert sel.size >= 8192
+        ctx.refresh_lists(sel)
+        t.refresh_lists(THETA, sel)
+        compare_lists(ctx, t)
+        assert ctx.get_info()["last_refreshed"] == sel.size
+
+
 @pytest.mark.parametrize("n_grp,steps", [(64, 2), (16, 3)])
 def test_stale_features_refresh_match_oracle(n_grp, steps):
     say("case stale/features/refresh n_grp=%d steps=%d" % (n_grp, steps))
