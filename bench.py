@@ -11,6 +11,12 @@ Inputs are resident in HBM before timing starts.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--n-grp G]
                   [--no-cpu-baseline] [--copy-probe MiB]
+
+``--sph`` times the short-range path instead (neighbour lists and SPH
+densities on them, ``paper_1907_02290_amd.sph``) with the FP64 oracle's
+lists and densities on the same workload as its CPU baseline:
+
+  python bench.py --sph --workload sphere_4m [--neighbours 64] [--skin 0.3]
 """
 from __future__ import annotations
 
@@ -77,10 +83,47 @@ def parse():
                     help="steps timed one by one afterwards (p50/p99)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--sph", action="store_true",
+                    help="time the short-range path (neighbour lists and "
+                         "SPH densities) instead of the gravity step")
+    ap.add_argument("--neighbours", type=float, default=64)
+    ap.add_argument("--skin", type=float, default=0.3)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB "
                          "(reference kernel for HBM counters)")
     return ap.parse_args()
+
+
+def sph_main(args):
+    """Short-range path: the library's neighbour lists and densities, and
+    the FP64 oracle's on the same workload (CPU baseline)."""
+    import torch
+    from paper_1907_02290_amd import sph
+    torch.cuda.set_device(0)
+    workload = args.workload if args.workload != WORKLOAD else "sphere_4m"
+    res = sph.measure(workload, args.n, args.neighbours, args.skin,
+                      max(args.steps, 1),
+                      int(args.n_grp) if args.n_grp else None, args.n_leaf)
+    if not args.no_cpu_baseline:
+        import oracle
+        import workloads
+        d, p = workloads.make(workload, n=args.n)
+        h = res["h"]
+        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], res["n_leaf"],
+                        res["n_grp"])
+        t0 = time.perf_counter()
+        t.neighbour_lists(h * (1 + args.skin))
+        t1 = time.perf_counter()
+        t.sph_density(h)
+        t2 = time.perf_counter()
+        res["cpu_baseline"] = {
+            "kind": "oracle", "cores": oracle.num_threads(),
+            "list_s": t1 - t0, "density_s": t2 - t1,
+            "value": res["pairs_per_eval"] / (t2 - t1),
+            "unit": "candidate pairs/s",
+            "sample": "FP64 oracle neighbour lists and densities of every "
+                      "group of the same tree"}
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -91,6 +134,9 @@ def main():
               "path (requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world),
               file=sys.stderr)
         sys.exit(2)
+    if args.sph:
+        sph_main(args)
+        return
 
     import torch
     import workloads

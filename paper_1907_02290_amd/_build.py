@@ -17,8 +17,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnbody_hip.so")
-# standalone measurement program (not linked into the library)
-VALU_COST = os.path.join(HERE, "valu_cost")
 ARCH = "gfx950"
 
 SOURCES = ["nb_scan.hip", "nb_tree.hip", "nb_walk.hip", "nb_force.hip",
@@ -57,23 +55,7 @@ def build(jobs: int = 6, verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)
-    build_valu_cost(verbose)
     return LIB
-
-
-def build_valu_cost(verbose: bool = False) -> str:
-    """Compile the instruction-cost measurement program."""
-    tmp = VALU_COST + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", *[f for f in COMMON if f != "-fPIC"],
-           os.path.join(CSRC, "valu_cost.hip"), "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed for valu_cost.hip:\n%s\n%s"
-                           % (r.stdout, r.stderr))
-    os.replace(tmp, VALU_COST)
-    if verbose:
-        print("built", VALU_COST)
-    return VALU_COST
 
 
 if __name__ == "__main__":

@@ -7,12 +7,13 @@ uniform ball of unit radius would hold ``--neighbours`` particles within h;
 the lists are built for h (1 + skin).  The tool builds the tree and the
 lists once, evaluates the density ``--evals`` times, and reports the list
 and density times from the library's HIP-event timers and the candidate
-pairs per evaluation (sum over groups of members x list length).  ``--cpu``
-also times the FP64 oracle's lists and densities on the same workload, for
-reference.
+pairs per evaluation (sum over groups of members x list length).  The
+FP64 CPU timing of the same lists and densities is a leg of the repository's
+benchmark script (``bench.py --sph``), which is allowed to run the oracle;
+this module never loads it.
 
   python -m paper_1907_02290_amd.sph --workload sphere_4m [--neighbours 64]
-         [--skin 0.3] [--evals 20] [--cpu]
+         [--skin 0.3] [--evals 20]
 """
 from __future__ import annotations
 
@@ -73,23 +74,6 @@ def measure(workload, n=None, neighbours=64, skin=0.3, evals=20, n_grp=None,
                 mean_rho=float(rho.mean()))
 
 
-def cpu_reference(workload, n=None, neighbours=64, skin=0.3):
-    """The oracle's lists and densities for the whole tree, timed."""
-    import oracle
-    import workloads
-    d, p = workloads.make(workload, n=n)
-    n = int(d["x"].size)
-    h = smoothing_length(n, neighbours)
-    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], p["n_leaf"], p["n_grp"])
-    t0 = time.perf_counter()
-    t.neighbour_lists(h * (1 + skin))
-    t1 = time.perf_counter()
-    t.sph_density(h)
-    t2 = time.perf_counter()
-    return dict(n=n, list_s=t1 - t0, density_s=t2 - t1,
-                threads=oracle.num_threads())
-
-
 def main(argv=None):
     import argparse
     import os
@@ -108,8 +92,6 @@ def main(argv=None):
                          "workload's)")
     ap.add_argument("--n-leaf", default=None,
                     help="leaf sizes to try, comma-separated")
-    ap.add_argument("--cpu", action="store_true",
-                    help="also time the FP64 oracle on the same workload")
     a = ap.parse_args(argv)
     grps = [int(v) for v in a.n_grp.split(",")] if a.n_grp else [None]
     leafs = [int(v) for v in a.n_leaf.split(",")] if a.n_leaf else [None]
@@ -117,9 +99,6 @@ def main(argv=None):
         for ng in grps:
             res = measure(a.workload, a.n, a.neighbours, a.skin, a.evals, ng,
                           nl)
-            if a.cpu:
-                res["cpu_oracle"] = cpu_reference(a.workload, a.n,
-                                                  a.neighbours, a.skin)
             print(json.dumps(res), flush=True)
 
 
