@@ -67,6 +67,7 @@ struct orc_tree {
   double* com;  /* 3 per cell */
   double* com0; /* 3 per cell: centres of mass at construction */
   double *bmin, *bmax; /* 3 per cell: box of the cell's particles now */
+  int moved; /* 0 from construction until the first reuse step */
   double* quad; /* 6 per cell: xx yy zz xy xz yz */
   /* groups; g_lo/g_hi is the box the group's current list was walked
    * with (the construction-time box until a list refresh) */
@@ -552,13 +553,17 @@ static void moved_centre(const orc_tree* t, int64_t c, double cc[3]) {
   for (int a = 0; a < 3; ++a) cc[a] = t->ctr[3 * c + a] + tr[a];
 }
 
-/* Side used in the opening test of cell c: the geometric side, or twice
- * the largest per-axis distance from the moved centre cc to the box of the
- * cell's current particles, whichever is larger.  Right after construction
- * every particle lies in its cell's cube, so this is the geometric side;
- * later it grows with a cell whose particles spread. */
+/* Side used in the opening test of a refresh walk for cell c: until the
+ * first reuse step the geometric side (construction walks are the plain
+ * test R6); after it the geometric side or twice the largest per-axis
+ * distance from the moved centre cc to the box of the cell's current
+ * particles, whichever is larger, so that a cell whose particles spread is
+ * opened sooner.  (A particle can sit just outside its cube even at
+ * construction, by the rounding of x - lo in the key, so the box rule is
+ * not applied before anything has moved.) */
 static double side_eff(const orc_tree* t, int64_t c, const double cc[3]) {
   const double s = ldexp(1.0, t->k - t->level[c]);
+  if (!t->moved) return s;
   double h = 0.0;
   for (int a = 0; a < 3; ++a) {
     const double up = t->bmax[3 * c + a] - cc[a];
@@ -590,9 +595,13 @@ int orc_cell_sides(const orc_tree* t, double* side) {
 /* Group tree walk (section 4.3 "construct the interaction lists"; indirect
  * addressing of section 4.1: the lists hold 32-bit indices).  Reading R6.
  * DFS from the root over the pre-order cell array; `skip` jumps over a
- * subtree.  When `fill` is zero only the list lengths are counted. */
+ * subtree.  When `fill` is zero only the list lengths are counted.
+ * `plain` = 1 is the construction walk: the geometric centre of every cell
+ * and its squared opening radius (s/theta)^2.  `plain` = 0 is a refresh
+ * walk between construction steps (an extension of section 4.2): moved
+ * centres and effective sides. */
 static void walk_box(const orc_tree* t, int64_t g, const double* glo,
-                     const double* ghi, double theta, int fill,
+                     const double* ghi, double theta, int plain, int fill,
                      uint32_t* epj, uint32_t* spj, int64_t* n_epj,
                      int64_t* n_spj, orc_slack* mg) {
   const uint32_t gb = t->g_begin[g];
@@ -607,8 +616,15 @@ static void walk_box(const orc_tree* t, int64_t g, const double* glo,
     if (cb <= gb && ce >= ge) {
       open = 1; /* the cell holds the group */
     } else {
-      double cc[3], d[3];
-      moved_centre(t, c, cc);
+      double cc[3], d[3], rc;
+      if (plain) {
+        const double r = ldexp(1.0, t->k - t->level[c]) / theta;
+        for (int a = 0; a < 3; ++a) cc[a] = t->ctr[3 * c + a];
+        rc = r * r;
+      } else {
+        moved_centre(t, c, cc);
+        rc = crit2(t, c, cc, theta);
+      }
       for (int a = 0; a < 3; ++a) {
         double v = 0.0;
         const double below = glo[a] - cc[a];
@@ -618,7 +634,6 @@ static void walk_box(const orc_tree* t, int64_t g, const double* glo,
         d[a] = v;
       }
       const double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-      const double rc = crit2(t, c, cc, theta);
       open = !(d2 > rc);
       if (mg) {
         const double dd = sqrt(d2), rr = sqrt(rc);
@@ -666,12 +681,12 @@ static void group_box(const orc_tree* t, int64_t g, double lo[3],
 }
 
 /* Walk group g with box (lo, hi) and record what the features need. */
-static void walk_record(orc_tree* t, int64_t g, double theta,
+static void walk_record(orc_tree* t, int64_t g, double theta, int plain,
                         int fill, uint32_t* epj, uint32_t* spj, int64_t* ne,
                         int64_t* ns) {
   orc_slack mg;
-  walk_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g], theta, fill, epj, spj,
-           ne, ns, &mg);
+  walk_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g], theta, plain, fill, epj,
+           spj, ne, ns, &mg);
   if (!fill) {
     t->g_sa[g] = mg.sa;
     t->g_so[g] = mg.so;
@@ -752,7 +767,7 @@ int orc_refresh_lists(orc_tree* t, double theta, int64_t n_sel,
   for (int64_t g = 0; g < G; ++g) {
     if (pick[g]) {
       group_box(t, g, &t->g_lo[3 * g], &t->g_hi[3 * g]);
-      walk_record(t, g, theta, 0, NULL, NULL, &ne[g], &ns[g]);
+      walk_record(t, g, theta, 0, 0, NULL, NULL, &ne[g], &ns[g]);
     } else {
       ne[g] = t->epj_off[g + 1] - t->epj_off[g];
       ns[g] = t->spj_off[g + 1] - t->spj_off[g];
@@ -770,7 +785,7 @@ int orc_refresh_lists(orc_tree* t, double theta, int64_t n_sel,
   for (int64_t g = 0; g < G; ++g) {
     if (pick[g]) {
       int64_t a, b;
-      walk_record(t, g, theta, 1, ee + eo[g], ss + so[g], &a, &b);
+      walk_record(t, g, theta, 0, 1, ee + eo[g], ss + so[g], &a, &b);
     } else {
       memcpy(ee + eo[g], t->epj + t->epj_off[g], (size_t)ne[g] * 4);
       memcpy(ss + so[g], t->spj + t->spj_off[g], (size_t)ns[g] * 4);
@@ -889,7 +904,7 @@ int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
   }
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t s = 0; s < ns_all; ++s)
-    walk_record(t, t->sel[s], theta, 0, NULL, NULL, &ne[s], &ns[s]);
+    walk_record(t, t->sel[s], theta, 1, 0, NULL, NULL, &ne[s], &ns[s]);
   t->epj_off[0] = t->spj_off[0] = 0;
   for (int64_t s = 0; s < ns_all; ++s) {
     t->epj_off[s + 1] = t->epj_off[s] + ne[s];
@@ -904,7 +919,7 @@ int orc_make_lists(orc_tree* t, double theta, int64_t n_sel,
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t s = 0; s < ns_all; ++s) {
     int64_t a, b;
-    walk_record(t, t->sel[s], theta, 1, t->epj + t->epj_off[s],
+    walk_record(t, t->sel[s], theta, 1, 1, t->epj + t->epj_off[s],
                 t->spj + t->spj_off[s], &a, &b);
   }
   sizes[0] = ns_all;
@@ -938,6 +953,7 @@ int orc_refresh(orc_tree* t, const double* x, const double* y,
     t->m[i] = m[s];
   }
   compute_moments(t);
+  t->moved = 1;
   return 0;
 }
 

@@ -115,18 +115,21 @@ k_com_internal(int64_t cnt, const uint32_t* __restrict__ list,
 }
 
 // Per cell: shift = com - com0, moved centre c' = geo + shift (rounded once
-// each, as the FP64 reference does), and the side of the opening test:
-// the geometric side s, or twice the largest per-axis distance from c' to
-// the box of the cell's current particles when that is larger (never right
-// after construction, when every particle lies in its cube).  ctr.w =
-// (side / theta)^2 -- at construction exactly the record's value, since
-// s / theta = s (1 / theta) for a power of two s; shift.w = side.
+// each, as the FP64 reference does), and the side of the opening test: at a
+// construction step (`fresh`) the geometric side s, so that construction
+// walks are the plain opening test; later s, or twice the largest per-axis
+// distance from c' to the box of the cell's current particles when that is
+// larger.  (A particle can lie just outside its cube at construction: its
+// key comes from the rounded x - lo.)  ctr.w = (side / theta)^2 -- at
+// construction exactly the walk record's value, since s / theta =
+// s (1 / theta) for a power of two s; shift.w = side.
 __global__ void __launch_bounds__(256)
 k_shift(int64_t nc, const CellRec* __restrict__ rec,
         const double4* __restrict__ com, const double4* __restrict__ com0,
         const double4* __restrict__ bmin, const double4* __restrict__ bmax,
         const Root* __restrict__ root, const uint32_t* __restrict__ seg,
-        double theta, double4* __restrict__ shift, double4* __restrict__ ctr) {
+        double theta, int fresh, double4* __restrict__ shift,
+        double4* __restrict__ ctr) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
   const double4 a = com[c], b = com0[c], g = rec[c].geo;
@@ -145,7 +148,7 @@ k_shift(int64_t nc, const CellRec* __restrict__ rec,
   h = fmax(h, __dsub_rn(cz, lo.z));
   const double s = ldexp(1.0, root[seg[m.x]].k - (int)(m.w & 255u));
   const double w = 2.0 * h;
-  const double side = w > s ? w : s;
+  const double side = (!fresh && w > s) ? w : s;
   const double r = __ddiv_rn(side, theta);
   shift[c] = make_double4(sx, sy, sz, side);
   ctr[c] = make_double4(cx, cy, cz, __dmul_rn(r, r));
@@ -592,7 +595,8 @@ int launch_com(nb_ctx* c) {
                      (const double4*)c->c_com.p, (const double4*)c->c_com0.p,
                      (const double4*)c->c_bmin.p, (const double4*)c->c_bmax.p,
                      (const Root*)c->root.p, (const uint32_t*)c->seg.p,
-                     c->cfg.theta, c->c_shift.p, c->c_ctr.p);
+                     c->cfg.theta, c->in_build ? 1 : 0, c->c_shift.p,
+                     c->c_ctr.p);
   return hip_check(c, hipGetLastError(), "shift launch");
 }
 

@@ -441,3 +441,41 @@ def test_one_pass_walk_and_overflow_fallback():
         t2 = oracle.Tree(*x2, d["m"][perm0][perm1], 8, 16)
         t2.make_lists(0.35)
         compare_lists(ctx, t2)
+
+
+def test_particles_outside_their_cube_lists_bit_exact():
+    """A particle can sit just outside the cube of its cell (its key comes
+    from the rounded x - lo).  Construction lists stay the plain opening
+    test, in the ordinary walk and in the refresh-mode walk, at opening
+    angles where a grown side would flip a decision."""
+    from test_oracle_lists import _box_sides, threshold_thetas
+    done = 0
+    for seed in range(900):
+        if done >= 8:
+            break
+        d = workloads.near_faces(4 + seed % 3, seed)
+        t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 1, 1)
+        c, g = t.cells(), t.groups()
+        grown = _box_sides(t, c, (d["x"], d["y"], d["z"]))
+        geo = 2.0 ** (t.k - c["level"].astype(float))
+        out = np.flatnonzero(grown > geo)
+        if out.size == 0:
+            continue
+        done += 1
+        thetas = sorted(threshold_thetas(t, c, g, out[:2]))[:12] + [0.6]
+        say("case outside-cube seed %d n %d thetas %d"
+            % (seed, d["x"].size, len(thetas)))
+        for refresh in (False, True):
+            with nb.Context(theta=0.5, eps=1 / 64, n_leaf=1, n_grp=1,
+                            refresh=refresh) as ctx:
+                ctx.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"],
+                                  d["vz"], d["m"])
+                for theta in thetas:
+                    ctx.set_config(theta=theta)
+                    ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+                    t.make_lists(theta)
+                    compare_tree(ctx, t)
+                    compare_lists(ctx, t)
+                    if refresh:
+                        np.testing.assert_array_equal(ctx.cell_sides(), geo)
+    assert done == 8

@@ -345,3 +345,45 @@ def test_feature_counts_and_caps(orc):
     assert np.all(f[np.isinf(sa), 7] == cap)
     assert np.all(f[np.isinf(so_), 8] == cap)
     assert np.all(f[:, 7:9] <= cap)
+
+
+def test_slack_and_shift_features_by_hand(orc):
+    """f3, f4, f7, f8 at non-trivial values: a rigid translation v of a
+    tree on a 2^-30 grid gives every cell the shift v (B = |v|, E = 0);
+    the slacks come from the brute-force walk above, not from the oracle.
+    Rows with finite, distinct sa and so tell the four inputs apart (a swap
+    of sa and so, or of B and E, fails)."""
+    rng = np.random.default_rng(21)
+    n = 400
+    q = lambda a: np.round(a * 2.0**30) / 2.0**30
+    x, y, z = q(rng.standard_normal((3, n)))
+    m = np.full(n, 2.0**-9)
+    theta = 0.55
+    t = orc.Tree(x, y, z, m, n_leaf=4, n_grp=8)
+    t.make_lists(theta)
+    c, g = t.cells(), t.groups()
+    kids = _children(c)
+    zero = np.zeros((t.n_cell, 3))
+    v = np.array([0.0625, -0.09375, 0.03125])
+    t.refresh(x + v[0], y + v[1], z + v[2], m)
+    f = t.features(4, np.full(t.n_groups, 2, np.int32))
+    B = float(np.linalg.norm(v))
+    cap = 1e6
+    rows = 0
+    for gi in range(t.n_groups):
+        b, cnt = int(g["begin"][gi]), int(g["count"][gi])
+        _, _, sa, so = _brute_walk(t, c, kids, zero, b, cnt, g["lo"][gi],
+                                   g["hi"][gi], theta)
+        if not (np.isfinite(sa) and np.isfinite(so) and sa > 0 and so > 0
+                and abs(sa - so) > 0.1 * max(sa, so)):
+            continue
+        rows += 1
+        s = 2.0 ** (t.k - int(c["level"][int(g["cell"][gi])]))
+        want = {3: np.log1p(min(B / sa, cap)), 4: np.log1p(min(B / so, cap)),
+                7: np.log1p(min(sa / s, cap)), 8: np.log1p(min(so / s, cap))}
+        for k, w in want.items():
+            assert f[gi, k] == pytest.approx(w, rel=1e-9), (gi, k)
+        # no deformation: E = 0, so the box-motion inputs vanish
+        assert f[gi, 1] < 1e-12 and f[gi, 2] < 1e-12
+        assert f[gi, 0] == 0.5
+    assert rows >= 10, rows

@@ -77,8 +77,9 @@ def test_accepted_cells_far_from_every_member(orc, theta):
                 assert (bx ** 2).sum() <= (pside / theta) ** 2 or dp <= pside / theta
 
 
-def _brute_walk(t, c, g, gi, theta):
-    """Recursive walk over explicit children, emitting in visiting order."""
+def _brute_walk(t, c, g, gi, theta, sides=None):
+    """Recursive walk over explicit children, emitting in visiting order
+    (``sides`` replaces the geometric side of each cell when given)."""
     kids = _children(c)
     gb, gn = int(g["begin"][gi]), int(g["count"][gi])
     lo, hi = g["lo"][gi], g["hi"][gi]
@@ -88,9 +89,11 @@ def _brute_walk(t, c, g, gi, theta):
         cb, cn = int(c["begin"][cc]), int(c["count"][cc])
         holds = cb <= gb and cb + cn >= gb + gn
         if not holds:
-            side = 2.0 ** (t.k - int(c["level"][cc]))
+            side = (2.0 ** (t.k - int(c["level"][cc])) if sides is None
+                    else sides[cc])
             d = np.maximum(0.0, np.maximum(lo - c["ctr"][cc], c["ctr"][cc] - hi))
-            if float((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) > (side / theta) ** 2:
+            r = side / theta     # (s/theta)^2 as one FP64 product, not pow
+            if float((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) > r * r:
                 spj.append(cc)
                 return
         if c["leaf"][cc]:
@@ -157,3 +160,72 @@ def test_mean_list_length_order_of_paper_model(orc):
              * np.log2(theta / pc["c4"] * (n ** (1 / 3) - n_i ** (1 / 3))))
     mean = (ne + ns) / ng
     assert model / 3 < mean < model * 3, (mean, model)
+
+
+def _box_sides(t, c, pos):
+    """Per cell: max(geometric side, twice the largest per-axis distance from
+    the geometric centre to a member particle), FP64."""
+    key, perm = t.keys()
+    P = np.stack([a[perm] for a in pos], 1)
+    out = np.empty(t.n_cell)
+    for cc in range(t.n_cell):
+        b, cn = int(c["begin"][cc]), int(c["count"][cc])
+        h = max(0.0, float((P[b:b + cn] - c["ctr"][cc]).max()),
+                float((c["ctr"][cc] - P[b:b + cn]).max()))
+        out[cc] = max(2.0 ** (t.k - int(c["level"][cc])), 2.0 * h)
+    return out
+
+
+def threshold_thetas(t, c, g, cells):
+    """Opening angles at which one of `cells` sits on the opening threshold
+    of some group: s / dist and the next two doubles above it."""
+    out = set()
+    for cc in cells:
+        s = 2.0 ** (t.k - int(c["level"][cc]))
+        for gi in range(t.n_groups):
+            dd = np.maximum(0.0, np.maximum(g["lo"][gi] - c["ctr"][cc],
+                                            c["ctr"][cc] - g["hi"][gi]))
+            dist = float(np.sqrt((dd[0] * dd[0] + dd[1] * dd[1]) +
+                                 dd[2] * dd[2]))
+            if dist > 0:
+                th = s / dist
+                for _ in range(3):
+                    out.add(float(th))
+                    th = np.nextafter(th, np.inf)
+    return out
+
+
+def test_construction_walk_is_plain_test_for_particles_outside_their_cube(orc):
+    """Keys come from the rounded x - lo, so a particle can sit just outside
+    the cube of its cell.  The construction walk is still the plain opening
+    test of reading R6 (geometric centre and side): over the seeded
+    near-face inputs where that happens, at opening angles chosen so that a
+    side grown to hold the cell's particles would flip a decision, the lists
+    equal the brute-force walk with geometric sides (and differ from the one
+    with grown sides), and the sides the walk reports are geometric."""
+    import workloads
+    hit = flips = 0
+    for seed in range(900):
+        d = workloads.near_faces(4 + seed % 3, seed)
+        pos = (d["x"], d["y"], d["z"])
+        t = orc.Tree(d["x"], d["y"], d["z"], d["m"], n_leaf=1, n_grp=1)
+        c, g = t.cells(), t.groups()
+        grown = _box_sides(t, c, pos)
+        geo = 2.0 ** (t.k - c["level"].astype(float))
+        out = np.flatnonzero(grown > geo)
+        if out.size == 0:
+            continue
+        hit += 1
+        np.testing.assert_array_equal(t.cell_sides(), geo)
+        thetas = threshold_thetas(t, c, g, out[:2]) | {0.6, 1.4}
+        for theta in sorted(thetas):
+            t.make_lists(theta)
+            eo, e, so, s = t.lists()
+            for gi in range(t.n_groups):
+                be, bs = _brute_walk(t, c, g, gi, theta)
+                assert e[eo[gi]:eo[gi + 1]].tolist() == be, (seed, theta, gi)
+                assert s[so[gi]:so[gi + 1]].tolist() == bs, (seed, theta, gi)
+                we, ws = _brute_walk(t, c, g, gi, theta, grown)
+                flips += (we, ws) != (be, bs)
+    assert hit >= 15, hit
+    assert flips >= 5, flips

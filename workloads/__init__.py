@@ -295,6 +295,29 @@ def clusters(n_sys, seed, lo_exp=10, hi_exp=18):
     return out
 
 
+def near_faces(n, seed):
+    """Tiny adversarial input for the key quantisation: a corner particle at
+    a non-dyadic lo (about 0.1 per axis), one at lo + 0.9 (so the root side
+    is 1), and n - 2 particles at lo + j/16 (j = 1..15 per axis) moved by
+    -2..2 units in the last place.  The subtraction x - lo that gives a key
+    rounds, so some of them land in a cell whose cube they lie just outside
+    of.  Equal masses 1/n, zero velocities."""
+    rng = _rng(seed)
+    lo = 0.1 + rng.uniform(0.0, 1e-3, 3)
+    pos = np.empty((3, n))
+    pos[:, 0] = lo
+    pos[:, 1] = lo + 0.9
+    for a in range(3):
+        v = lo[a] + rng.integers(1, 16, n - 2) / 16.0
+        for i, k in enumerate(rng.integers(-2, 3, n - 2)):
+            for _ in range(abs(int(k))):
+                v[i] = np.nextafter(v[i], np.inf if k > 0 else -np.inf)
+        pos[a, 2:] = v
+    z = np.zeros(n)
+    return dict(x=pos[0].copy(), y=pos[1].copy(), z=pos[2].copy(), vx=z,
+                vy=z.copy(), vz=z.copy(), m=np.full(n, 1.0 / n))
+
+
 # Named workloads: (generator, kwargs) plus run parameters.
 def make(name, n=None, seed=None, replicate=0):
     """Build one of the named workloads.
