@@ -123,26 +123,38 @@ enum { NB_MLP_NIN = 12, NB_MLP_NPARAM = 5057 };
 
 /* ---- lifetime --------------------------------------------------------- */
 
-/* Create a context on the current HIP device.  cfg is copied.
+/* Create a context on the current HIP device.  cfg is copied.  One context
+ * is one particle system with its tree and lists, the state the paper's
+ * top-level force call works on (section 5); the opening angle, softening,
+ * leaf and group sizes are those of its measurements (section 6.1).
  * Errors: NB_ERR_INPUT (cfg out of range), NB_ERR_HIP, NB_ERR_OOM. */
 int nb_create(const nb_config* cfg, nb_ctx** out);
 
-/* Destroy a context and free its device memory (NULL is a no-op). */
+/* Destroy a context and free its device memory (NULL is a no-op).  Section
+ * 5: the library owns the tree and the saved lists; they die with it. */
 void nb_destroy(nb_ctx* ctx);
 
 /* Replace the configuration (theta, eps, n_leaf, n_grp, order, ...).
- * Invalidates the tree and the lists; particles are kept. */
+ * Invalidates the tree and the lists; particles are kept (a new opening
+ * angle or group size needs a construction step, section 4.2).
+ * Errors: NB_ERR_INPUT (cfg out of range). */
 int nb_set_config(nb_ctx* ctx, const nb_config* cfg);
 
 /* Copy in n particles: positions, velocities and masses (FP64, original
- * order, 7 arrays of n doubles).  1 <= n < 2^31.  Invalidates the tree and
- * the lists.  Errors: NB_ERR_INPUT (NULL, n out of range), NB_ERR_OOM. */
+ * order, 7 arrays of n doubles).  1 <= n < 2^31.  These are the full
+ * particle records of section 4.3 (FP), from which the interaction records
+ * (EPI, EPJ) are derived on the device; the caller keeps ownership of the
+ * arrays.  Invalidates the tree and the lists (section 5: particles may not
+ * change while a list is reused).
+ * Errors: NB_ERR_INPUT (NULL, n out of range), NB_ERR_OOM. */
 int nb_set_particles(nb_ctx* ctx, int64_t n, const double* x,
                      const double* y, const double* z, const double* vx,
                      const double* vy, const double* vz, const double* m,
                      int on_device);
 
-/* Split the particles into independent systems: system s is particles
+/* Not in the paper (batching of independent systems, an extension; each
+ * system is the paper's single system of section 4.3).
+ * Split the particles into independent systems: system s is particles
  * [off[s], off[s + 1]) of the original order (off holds n_sys + 1 values,
  * off[0] = 0, off[n_sys] = n, every system non-empty).  Each system gets its
  * own root cell, tree, groups and lists and feels only its own particles;
@@ -185,11 +197,15 @@ int nb_compute_forces(nb_ctx* ctx, nb_mode mode);
 
 /* Kick-drift of the KDK leapfrog in FP64: v += (a + a_ext) * dt_kick, then
  * x += v * dt_drift, with a the last computed forces and a_ext the pull of
- * cfg.ext_mass at the origin.  Requires computed forces (NB_ERR_STATE).
- * Invalidates the tree for new lists; kept lists stay reusable. */
+ * cfg.ext_mass at the origin.  Section 4.3: after the forces are written
+ * back, the orbits of the particles are integrated (the paper does not name
+ * the integrator; leapfrog is the reading used).  Requires computed forces
+ * (NB_ERR_STATE).  Invalidates the tree for new lists; kept lists stay
+ * reusable (section 4.2).  Errors: NB_ERR_INPUT (non-finite step). */
 int nb_kick_drift(nb_ctx* ctx, double dt_kick, double dt_drift);
 
-/* One leapfrog step: nb_kick_drift(dt_kick, dt_drift) then
+/* One leapfrog step (section 4.3: integrate, then the next force call with
+ * its reuse mode, section 5): nb_kick_drift(dt_kick, dt_drift) then
  * nb_compute_forces(mode).  With NB_FLAG_GRAPH, the first NB_REUSE_LIST step
  * after a construction step captures kick-drift, moments and force kernel
  * into a HIP graph on the context's stream, and later reuse steps with the
@@ -199,13 +215,17 @@ int nb_kick_drift(nb_ctx* ctx, double dt_kick, double dt_drift);
 int nb_step(nb_ctx* ctx, nb_mode mode, double dt_kick, double dt_drift);
 
 /* ---- readback (synchronises the stream) --------------------------------
- * internal = 0: original order; 1: internal (Morton) order. */
+ * Section 5: the retrieve step copies the results back to the caller's
+ * particles.  internal = 0: original order; 1: internal (Morton) order.
+ * Errors: NB_ERR_STATE (nothing computed), NB_ERR_INPUT (NULL). */
 int nb_get_forces(nb_ctx* ctx, double* ax, double* ay, double* az,
                   double* pot, int internal);
 int nb_get_state(nb_ctx* ctx, double* x, double* y, double* z, double* vx,
                  double* vy, double* vz, int internal);
 
-/* info[0] n, [1] cells, [2] groups, [3] EPJ entries, [4] SPJ entries,
+/* Sizes and counters of the tree and lists (the quantities of section 6.1:
+ * <n_i> = n / groups, <n_list> = (EPJ + SPJ entries) / groups).
+ * info[0] n, [1] cells, [2] groups, [3] EPJ entries, [4] SPJ entries,
  * [5] interactions of the current lists (sum over groups of
  * n_i * (n_epj + n_spj)), [6] force evaluations so far, [7] total
  * interactions evaluated so far, [8] root exponent k of system 0, [9] force
@@ -216,39 +236,72 @@ int nb_get_state(nb_ctx* ctx, double* x, double* y, double* z, double* vx,
 int nb_get_info(nb_ctx* ctx, int64_t* info);
 
 /* Root corner lo[3] and exponent k of the last tree (side 2^k); with
- * several systems, those of system 0. */
+ * several systems, those of system 0.  Section 4.3: the root cell is set
+ * from the particle positions. */
 int nb_get_root(nb_ctx* ctx, double* lo, int32_t* k);
 
-/* Root corners (3 per system) and exponents (1 per system). */
+/* Root corners (3 per system) and exponents (1 per system); section 4.3
+ * root cell, one per independent system. */
 int nb_get_roots(nb_ctx* ctx, double* lo3, int32_t* k);
 
 /* Sorted keys (n) and, for each sorted position, the ORIGINAL index of the
- * particle there (n). */
+ * particle there (n).  Section 4.3 steps 1-3: Morton keys, their sort and
+ * the reorder of the particles. */
 int nb_get_keys(nb_ctx* ctx, uint64_t* key, uint32_t* orig);
 
-/* Cell arrays in DFS pre-order (system after system), each of length
+/* Section 4.3 step 4 (link): the tree cells.
+ * Cell arrays in DFS pre-order (system after system), each of length
  * info[1]; any may be NULL.  The parent of a root is 0xFFFFFFFF; skip = id
  * after the subtree; ctr3 = geometric centres (3 per cell). */
 int nb_get_cells(nb_ctx* ctx, uint8_t* level, uint32_t* begin,
                  uint32_t* count, uint32_t* parent, uint32_t* skip,
                  uint8_t* leaf, double* ctr3);
 
-/* Moments per cell: mass, centre of mass (3), second moments about the
- * centre of mass (6: xx yy zz xy xz yz).  Any may be NULL. */
+/* Moments per cell (section 4.3: multipole moments, recomputed every step):
+ * mass, centre of mass (3), second moments about the centre of mass (6: xx
+ * yy zz xy xz yz).  Any may be NULL. */
 int nb_get_moments(nb_ctx* ctx, double* mass, double* com3, double* quad6);
 
-/* Groups (length info[2]): cell id, first particle, count, tight box
- * lo3/hi3 and centre ctr3 (3 per group).  Any may be NULL. */
+/* Groups (length info[2]; section 2, Barnes' grouping of particles that
+ * share one list): cell id, first particle, count, tight box lo3/hi3 and
+ * centre ctr3 (3 per group).  Any may be NULL. */
 int nb_get_groups(nb_ctx* ctx, uint32_t* cell, uint32_t* begin,
                   uint32_t* count, double* lo3, double* hi3, double* ctr3);
 
-/* Lists in CSR form: epj_off/spj_off hold info[2]+1 offsets, epj/spj hold
+/* Lists in CSR form (section 4.1: indices of EPJ and SPJ instead of their
+ * copies): epj_off/spj_off hold info[2]+1 offsets, epj/spj hold
  * info[3]/info[4] ids (EPJ = internal particle positions, SPJ = cell ids),
  * ascending within each group.  Any may be NULL. */
 int nb_get_lists(nb_ctx* ctx, int64_t* epj_off, uint32_t* epj,
                  int64_t* spj_off, uint32_t* spj);
 
-/* Accumulated GPU milliseconds per phase (NB_PH_COUNT values) and the
+/* Install caller-made index lists for the current tree: the dispatch step
+ * with indirect addressing of section 5 (at a construction step the index
+ * lists are sent to the accelerator and saved there; reuse steps use the
+ * saved lists) and the index lists of section 4.1.  Same CSR layout as
+ * nb_get_lists: epj_off and spj_off hold n_groups + 1 offsets (from 0,
+ * non-decreasing, ending at n_epj and n_spj), epj holds n_epj internal
+ * particle slots, spj holds n_spj cell ids; any order within a group.
+ * Host arrays, or device arrays on the context's GPU when on_device != 0;
+ * the caller keeps ownership (they are copied).  Before any kernel indexes
+ * with them, one device pass reads the offsets and one the ids and checks
+ * them against n and the cell count; a failure returns NB_ERR_LIST and
+ * leaves no lists installed.  On success the lists are reusable: the next
+ * nb_compute_forces(NB_REUSE_LIST) evaluates them (moments refreshed, as at
+ * any reuse step).  They stay until the next tree build or list walk.
+ * Synchronises the stream twice.
+ * Errors: NB_ERR_STATE (no tree, or refresh mode, whose per-list walk state
+ * uploaded lists do not carry), NB_ERR_INPUT (n_groups differs from the
+ * tree's, NULL arrays, negative totals), NB_ERR_LIST, NB_ERR_OOM,
+ * NB_ERR_HIP. */
+int nb_upload_lists(nb_ctx* ctx, int64_t n_groups, const int64_t* epj_off,
+                    int64_t n_epj, const uint32_t* epj,
+                    const int64_t* spj_off, int64_t n_spj,
+                    const uint32_t* spj, int on_device);
+
+/* Per-phase time, in the phases of the paper's breakdown of a step (table
+ * of section 6.1).
+ * Accumulated GPU milliseconds per phase (NB_PH_COUNT values) and the
  * number of timed intervals per phase (may be NULL), since the last reset;
  * needs cfg.flags bit 0.  reset != 0 clears the counters after reading. */
 int nb_get_timing(nb_ctx* ctx, double* ms, int64_t* calls, int reset);
@@ -350,7 +403,9 @@ int nb_get_group_state(nb_ctx* ctx, double* sa, double* so, int32_t* age);
 /* The side each cell has in the opening test now (info[1] values, FP64). */
 int nb_get_cell_sides(nb_ctx* ctx, double* side);
 
-/* Perceptron weights (host, NB_MLP_NPARAM floats).  Setting them clears the
+/* Not in the paper (the learned predictor of list staleness, an extension
+ * of the fixed reuse interval of section 4.2).
+ * Perceptron weights (host, NB_MLP_NPARAM floats).  Setting them clears the
  * Adam state.  A context starts with zero weights (p = 1/2). */
 int nb_mlp_set(nb_ctx* ctx, const float* w, int64_t nw);
 int nb_mlp_get(nb_ctx* ctx, float* w, int64_t nw);
@@ -378,10 +433,12 @@ int nb_mlp_train(nb_ctx* ctx, int64_t n, const float* x, const float* y,
                  int on_device, int epochs, int64_t batch, float lr,
                  float pos_weight, float* loss);
 
-/* Description of the last error on this context ("" if none). */
+/* Description of the last error on this context ("" if none).  The paper
+ * specifies no error handling (its library is C++ templates); every entry
+ * point here returns a status instead. */
 const char* nb_last_error(const nb_ctx* ctx);
 
-/* Library version string. */
+/* Library version string (no paper counterpart). */
 const char* nb_version(void);
 
 #ifdef __cplusplus

@@ -385,7 +385,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->nb_off); release(c->nb_toff); release(c->rho);
   release(c->cnt_e); release(c->cnt_s); release(c->cnt_t);
   release(c->epj_off); release(c->spj_off); release(c->tok_off);
-  release(c->epj); release(c->spj); release(c->tok);
+  release(c->epj); release(c->spj); release(c->tok); release(c->lflag);
   release(c->scan_tmp); release(c->red);
   release(c->c_com); release(c->c_com0); release(c->c_shift); release(c->c_ctr);
   release(c->c_bmin); release(c->c_bmax);
@@ -967,6 +967,87 @@ int nb_get_groups(nb_ctx* c, uint32_t* cell, uint32_t* begin, uint32_t* count,
       ctr3[3 * g + 2] = rec[gc[g]].geo.z;
     }
   }
+  return NB_OK;
+}
+
+int nb_upload_lists(nb_ctx* c, int64_t n_groups, const int64_t* epj_off,
+                    int64_t n_epj, const uint32_t* epj,
+                    const int64_t* spj_off, int64_t n_spj,
+                    const uint32_t* spj, int on_device) {
+  if (!c) return NB_ERR_INPUT;
+  if (!c->tree_valid)
+    return set_err(c, NB_ERR_STATE, "uploaded lists need a built tree");
+  if (c->learn)
+    return set_err(c, NB_ERR_STATE,
+                   "uploaded lists carry no walk state for refresh mode");
+  if (n_groups != c->n_groups)
+    return set_err(c, NB_ERR_INPUT, "group count %lld, the tree has %lld",
+                   (long long)n_groups, (long long)c->n_groups);
+  if (!epj_off || !spj_off || (n_epj > 0 && !epj) || (n_spj > 0 && !spj))
+    return set_err(c, NB_ERR_INPUT, "NULL list array");
+  if (n_epj < 0 || n_spj < 0 || n_epj >= (int64_t)1 << 40 ||
+      n_spj >= (int64_t)1 << 40)
+    return set_err(c, NB_ERR_INPUT, "list totals out of range");
+  drop_graph(c);
+  c->lists_valid = c->lists_reusable = false;
+  c->tail.valid = false;
+  const size_t ng = (size_t)c->n_groups;
+  int rc = reserve(c, c->epj_off, ng + 1);
+  if (!rc) rc = reserve(c, c->spj_off, ng + 1);
+  if (!rc) rc = reserve(c, c->epj, (size_t)n_epj + 1);
+  if (!rc) rc = reserve(c, c->spj, (size_t)n_spj + 1);
+  if (!rc) rc = reserve(c, c->cnt_e, ng);
+  if (!rc) rc = reserve(c, c->cnt_s, ng);
+  if (!rc) rc = reserve(c, c->lflag, 1);
+  if (rc) return rc;
+  const hipMemcpyKind kind =
+      on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  rc = hip_check(c, hipMemcpyAsync(c->epj_off.p, epj_off, (ng + 1) * 8, kind,
+                                   c->stream), "list upload");
+  if (!rc)
+    rc = hip_check(c, hipMemcpyAsync(c->spj_off.p, spj_off, (ng + 1) * 8,
+                                     kind, c->stream), "list upload");
+  if (!rc && n_epj)
+    rc = hip_check(c, hipMemcpyAsync(c->epj.p, epj, (size_t)n_epj * 4, kind,
+                                     c->stream), "list upload");
+  if (!rc && n_spj)
+    rc = hip_check(c, hipMemcpyAsync(c->spj.p, spj, (size_t)n_spj * 4, kind,
+                                     c->stream), "list upload");
+  if (!rc) rc = fill_u32(c, c->lflag.p, 1, 0u);
+  if (rc) return rc;
+  c->n_epj = n_epj;
+  c->n_spj = n_spj;
+  // validate before anything indexes with the ids
+  if ((rc = launch_check_lists(c, c->lflag.p))) return rc;
+  if ((rc = stage_d2h(c, 0, c->lflag.p, 4))) return rc;
+  if ((rc = sync(c))) return rc;
+  const unsigned bad = *static_cast<const unsigned*>(c->h_small);
+  if (bad) {
+    c->n_epj = c->n_spj = 0;
+    return set_err(c, NB_ERR_LIST,
+                   "uploaded lists rejected:%s%s%s%s",
+                   (bad & 1) ? " bad EPJ offsets" : "",
+                   (bad & 2) ? " bad SPJ offsets" : "",
+                   (bad & 4) ? " EPJ id >= n" : "",
+                   (bad & 8) ? " SPJ id >= cells" : "");
+  }
+  if ((rc = launch_interactions(c, c->cnt_e.p, c->cnt_s.p))) return rc;
+  if ((rc = launch_xcd_plan(c, false))) return rc;
+  if ((rc = stage_d2h(c, 64, c->xcd_plan.p, 9 * 8))) return rc;
+  if ((rc = stage_d2h(c, 16, c->red.p, 8))) return rc;
+  if ((rc = stage_d2h(c, 40, c->g_chunks.p + c->n_groups, 4))) return rc;
+  if ((rc = stage_d2h(c, 48, c->red.p + 2, 8))) return rc;
+  if ((rc = sync(c))) return rc;
+  {
+    const uint64_t* h = static_cast<const uint64_t*>(c->h_small);
+    c->n_inter = (int64_t)h[2];
+    c->n_inter_spj = (int64_t)h[6];
+    c->n_wi = static_cast<const uint32_t*>(c->h_small)[10];
+    for (int x = 0; x <= 8; ++x) c->xcd_b[x] = (int64_t)h[8 + x];
+  }
+  if ((rc = launch_tail_order(c))) return rc;
+  c->lists_valid = true;
+  c->lists_reusable = true;
   return NB_OK;
 }
 

@@ -171,6 +171,7 @@ struct nb_ctx {
   bool walk_split = false;    // the last walk ran two lanes per group
   nb::DBuf<uint64_t> epj_off, spj_off, tok_off;
   nb::DBuf<uint32_t> epj, spj, tok;  // tok: walk tokens per group
+  nb::DBuf<unsigned> lflag;          // check of uploaded lists
 
   // scan / reduction scratch
   nb::DBuf<uint64_t> scan_tmp;
@@ -297,6 +298,7 @@ int launch_nbr_fill(nb_ctx* c, double h);
 // SPH density on the neighbour lists into c->rho
 int launch_density(nb_ctx* c, double h);
 int launch_interactions(nb_ctx* c, const uint32_t* ne, const uint32_t* ns);
+int launch_check_lists(nb_ctx* c, unsigned* flag);  // uploaded lists
 // nb_learn.hip
 int learn_reserve_cells(nb_ctx* c);
 int learn_reserve_groups(nb_ctx* c);

@@ -787,7 +787,66 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   if (threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
+// Caller-supplied CSR offsets (n_groups + 1 values): they must start at 0,
+// never decrease, end at the declared total, and give no group 2^32 or more
+// entries.  Sets `bit` in *flag otherwise; writes each group's length to
+// cnt (0 where the offsets are bad).  Reads only the offsets.
+__global__ void __launch_bounds__(256)
+k_check_offsets(int64_t ng, const uint64_t* __restrict__ off, uint64_t total,
+                uint32_t* __restrict__ cnt, unsigned bit,
+                unsigned* __restrict__ flag) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g > ng) return;
+  bool bad = false;
+  if (g == 0 && off[0] != 0ull) bad = true;
+  if (g == ng) {
+    if (off[ng] != total) bad = true;
+  } else {
+    const uint64_t a = off[g], b = off[g + 1];
+    const bool ok = b >= a && b - a < 0xFFFFFFFFull;
+    cnt[g] = ok ? (uint32_t)(b - a) : 0u;
+    if (!ok) bad = true;
+  }
+  if (bad) atomicOr(flag, bit);
+}
+
+// Ids of caller-supplied lists against their bound (particle slots < n,
+// cell ids < n_cell).  Sets `bit` in *flag if any is out of range; reads
+// only the n ids.
+__global__ void __launch_bounds__(256)
+k_check_ids(int64_t n, const uint32_t* __restrict__ id, uint32_t limit,
+            unsigned bit, unsigned* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad |= id[i] >= limit;
+  if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, bit);
+}
+
 }  // namespace
+
+// Check caller-supplied lists already copied into epj_off/epj/spj_off/spj
+// (totals n_epj, n_spj): flag bits 1 / 2 = bad EPJ / SPJ offsets, 4 / 8 =
+// EPJ / SPJ id out of range; per-group lengths into cnt_e, cnt_s.
+int launch_check_lists(nb_ctx* c, unsigned* flag) {
+  const unsigned nb = grid_for(c->n_groups + 1, 256);
+  hipLaunchKernelGGL(k_check_offsets, dim3(nb), dim3(256), 0, c->stream,
+                     c->n_groups, (const uint64_t*)c->epj_off.p,
+                     (uint64_t)c->n_epj, c->cnt_e.p, 1u, flag);
+  hipLaunchKernelGGL(k_check_offsets, dim3(nb), dim3(256), 0, c->stream,
+                     c->n_groups, (const uint64_t*)c->spj_off.p,
+                     (uint64_t)c->n_spj, c->cnt_s.p, 2u, flag);
+  unsigned ne = grid_for(c->n_epj, 256), ns = grid_for(c->n_spj, 256);
+  if (ne > 2048) ne = 2048;
+  if (ns > 2048) ns = 2048;
+  hipLaunchKernelGGL(k_check_ids, dim3(ne), dim3(256), 0, c->stream,
+                     c->n_epj, (const uint32_t*)c->epj.p, (uint32_t)c->n, 4u,
+                     flag);
+  hipLaunchKernelGGL(k_check_ids, dim3(ns), dim3(256), 0, c->stream,
+                     c->n_spj, (const uint32_t*)c->spj.p,
+                     (uint32_t)c->n_cell, 8u, flag);
+  return hip_check(c, hipGetLastError(), "list check launch");
+}
 
 // Whether a walk over n_walk groups runs two lanes per group (k_walk_c),
 // whose slab mode takes two slabs per group.

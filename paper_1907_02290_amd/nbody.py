@@ -104,6 +104,7 @@ def load():
         "nb_get_moments": ([p, p, p, p], i32),
         "nb_get_groups": ([p] + [p] * 6, i32),
         "nb_get_lists": ([p, p, p, p, p], i32),
+        "nb_upload_lists": ([p, i64, p, i64, p, p, i64, p, i32], i32),
         "nb_get_timing": ([p, p, p, i32], i32),
         "nb_group_features": ([p, p, i32], i32),
         "nb_group_stale": ([p, d, p, p, i32], i32),
@@ -341,6 +342,30 @@ class Context:
         self._chk(self._lib.nb_get_lists(self._h, _ptr(eo), _ptr(e), _ptr(so),
                                          _ptr(s)))
         return eo, e, so, s
+
+    def upload_lists(self, epj_off, epj, spj_off, spj):
+        """Install caller-made CSR index lists for the current tree (see
+        nb_upload_lists); numpy arrays or CUDA tensors (int64 offsets,
+        uint32/int32 ids), all on the same side."""
+        dev = _is_torch(epj_off)
+        if dev:
+            for a in (epj_off, epj, spj_off, spj):
+                assert a.is_cuda and a.is_contiguous()
+            ng = epj_off.numel() - 1
+            ne, ns = epj.numel(), spj.numel()
+            ptrs = [a.data_ptr() if a.numel() else None
+                    for a in (epj_off, epj, spj_off, spj)]
+        else:
+            eo = np.ascontiguousarray(epj_off, np.int64)
+            so = np.ascontiguousarray(spj_off, np.int64)
+            e = np.ascontiguousarray(epj, np.uint32)
+            s = np.ascontiguousarray(spj, np.uint32)
+            ng, ne, ns = eo.size - 1, e.size, s.size
+            keep = (eo, e, so, s)
+            ptrs = [_ptr(a) if a.size else None for a in keep]
+        self._chk(self._lib.nb_upload_lists(self._h, ng, ptrs[0], ne, ptrs[1],
+                                            ptrs[2], ns, ptrs[3],
+                                            1 if dev else 0))
 
     # ---- short-range interactions ----
     def neighbour_lists(self, h_list):

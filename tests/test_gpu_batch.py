@@ -8,6 +8,8 @@ import pytest
 import oracle
 import workloads
 import paper_1907_02290_amd as nb
+from test_gpu_graph import OracleRun
+from test_gpu_parity import check_forces
 
 pytestmark = pytest.mark.gpu
 
@@ -198,33 +200,44 @@ def test_set_systems_rejects_bad_offsets():
 @pytest.mark.parametrize("order", [1, 2])
 def test_persistent_force_launch_is_bit_identical(order):
     """Resident workgroups pulling work items from per-XCD counters compute
-    each work item exactly as the one-workgroup-per-item launch does."""
+    each work item exactly as the one-workgroup-per-item launch does, and
+    both match the oracle on the construction and the reuse step."""
     say("case persistent force order=%d" % order)
     d = _batch(seed=7, n_sys=6, lo=9, hi=14)
     out = []
     for persistent in (False, True):
+        orc = OracleRun(d["m"], d["offsets"], 64, order)
         ctx = nb.Context(theta=0.5, eps=0.01, n_leaf=8, n_grp=64, order=order,
                          persistent=persistent)
         ctx.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
                           d["m"])
         ctx.set_systems(d["offsets"])
         ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        f0 = ctx.get_forces()
+        check_forces(f0, orc.step(ctx.get_state(), True),
+                     what="persistent=%d construction" % persistent)
         ctx.kick_drift(1 / 128, 1 / 128)
         ctx.compute_forces(nb.NB_REUSE_LIST)
-        out.append(ctx.get_forces())
+        f1 = ctx.get_forces()
+        check_forces(f1, orc.step(ctx.get_state(), False),
+                     what="persistent=%d reuse" % persistent)
+        out.append((f0, f1))
         ctx.close()
-    for a, b in zip(*out):
-        np.testing.assert_array_equal(a, b)
+    for step in (0, 1):
+        for a, b in zip(out[0][step], out[1][step]):
+            np.testing.assert_array_equal(a, b)
 
 
 @pytest.mark.parametrize("n_grp", [8, 64, 256])
 def test_copied_lists_give_the_same_forces(n_grp):
     """Lists of copied j-data (the paper's method G1) give the forces of
-    index lists (G2) bit for bit, on a construction and a reuse step."""
+    index lists (G2) bit for bit, on a construction and a reuse step, and
+    both match the oracle's FP64 sums over the same lists."""
     say("case copied lists n_grp=%d" % n_grp)
     d = _batch(seed=9, n_sys=5, lo=9, hi=14)
     out = []
     for copied in (False, True):
+        orc = OracleRun(d["m"], d["offsets"], n_grp, 1)
         ctx = nb.Context(theta=0.5, eps=0.01, n_leaf=8, n_grp=n_grp, order=1,
                          copied_lists=copied)
         ctx.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
@@ -232,9 +245,14 @@ def test_copied_lists_give_the_same_forces(n_grp):
         ctx.set_systems(d["offsets"])
         ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
         f0 = ctx.get_forces()
+        check_forces(f0, orc.step(ctx.get_state(), True),
+                     what="copied=%d construction" % copied)
         ctx.kick_drift(1 / 128, 1 / 128)
         ctx.compute_forces(nb.NB_REUSE_LIST)
-        out.append((f0, ctx.get_forces()))
+        f1 = ctx.get_forces()
+        check_forces(f1, orc.step(ctx.get_state(), False),
+                     what="copied=%d reuse" % copied)
+        out.append((f0, f1))
         ctx.close()
     for step in (0, 1):
         for a, b in zip(out[0][step], out[1][step]):

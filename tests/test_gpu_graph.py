@@ -1,12 +1,17 @@
 """Reuse steps replayed from a captured HIP graph give exactly the results of
 the same steps launched one by one: every replay is checked, with readbacks
 (eager work and synchronisation) between replays, across construction steps
-and a change of time step."""
+and a change of time step.  Every step's forces are also checked against the
+FP64 oracle: its tree is built on the GPU's own positions at each
+construction step and refreshed with them at each reuse step (section 4.2:
+moments over the frozen tree), then summed over the same lists."""
 import numpy as np
 import pytest
 
+import oracle
 import workloads
 import paper_1907_02290_amd as nb
+from test_gpu_parity import check_forces
 
 pytestmark = pytest.mark.gpu
 
@@ -21,14 +26,45 @@ def _pair(d, **kw):
     return out
 
 
+class OracleRun:
+    """The oracle following a run of one system (or a batch of independent
+    systems, offsets `off`) on the GPU's positions."""
+
+    def __init__(self, m, off, n_grp, order, eps=0.01):
+        self.m, self.off, self.n_grp = m, off, n_grp
+        self.order, self.eps = order, eps
+        self.trees = None
+
+    def step(self, state, construct):
+        x, y, z = state[:3]
+        parts = range(self.off.size - 1)
+        if construct or self.trees is None:
+            self.trees = []
+            for s in parts:
+                b, e = int(self.off[s]), int(self.off[s + 1])
+                t = oracle.Tree(x[b:e], y[b:e], z[b:e], self.m[b:e], 8,
+                                self.n_grp)
+                t.make_lists(0.5)
+                self.trees.append(t)
+        else:
+            for s, t in zip(parts, self.trees):
+                b, e = int(self.off[s]), int(self.off[s + 1])
+                t.refresh(x[b:e], y[b:e], z[b:e], self.m[b:e])
+        refs = [t.force_lists(self.order, self.eps, 1.0) for t in self.trees]
+        return tuple(np.concatenate([r[k] for r in refs]) for k in range(4))
+
+
 @pytest.mark.parametrize("order,n_grp", [(1, 64), (2, 256)])
 def test_graph_replays_match_eager_steps(order, n_grp):
     print("case graph order=%d n_grp=%d" % (order, n_grp), flush=True)
     d = workloads.plummer(20000, workloads.seed_for(1, 9))
+    orc = OracleRun(d["m"], np.array([0, d["x"].size]), n_grp, order)
     g, e = _pair(d, order=order, n_grp=n_grp)
     with g, e:
         for c in (g, e):
             c.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        check_forces(g.get_forces(), orc.step(g.get_state(), True),
+                     what="step 0")
         dt = 1 / 128
         for step in range(1, 14):
             if step == 9:
@@ -43,6 +79,10 @@ def test_graph_replays_match_eager_steps(order, n_grp):
             sg, se = g.get_state(internal=True), e.get_state(internal=True)
             for a, b in zip(sg, se):
                 np.testing.assert_array_equal(a, b, err_msg="step %d" % step)
+            check_forces(g.get_forces(),
+                         orc.step(g.get_state(),
+                                  mode == nb.NB_MAKE_LIST_FOR_REUSE),
+                         what="step %d" % step)
         ig, ie = g.get_info(), e.get_info()
         assert ig["force_evals"] == ie["force_evals"] == 14
         assert ig["total_inter"] == ie["total_inter"]
@@ -51,11 +91,13 @@ def test_graph_replays_match_eager_steps(order, n_grp):
 def test_graph_with_batched_systems():
     print("case graph batch", flush=True)
     d = workloads.clusters(6, 5, lo_exp=8, hi_exp=12)
+    orc = OracleRun(d["m"], d["offsets"], 64, 1)
     g, e = _pair(d)
     with g, e:
         for c in (g, e):
             c.set_systems(d["offsets"])
             c.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        orc.step(g.get_state(), True)
         for step in range(1, 9):
             mode = nb.NB_MAKE_LIST_FOR_REUSE if step % 4 == 0 else \
                 nb.NB_REUSE_LIST
@@ -63,3 +105,7 @@ def test_graph_with_batched_systems():
                 c.step(mode, 1 / 128, 1 / 128)
             for a, b in zip(g.get_state(), e.get_state()):
                 np.testing.assert_array_equal(a, b)
+            check_forces(g.get_forces(),
+                         orc.step(g.get_state(),
+                                  mode == nb.NB_MAKE_LIST_FOR_REUSE),
+                         what="batch step %d" % step)

@@ -113,31 +113,45 @@ def test_refresh_mode_keeps_construction_lists(kind, n):
         np.testing.assert_array_equal(ctx.cell_sides(), t.cell_sides())
 
 
-def test_refresh_mode_tile_walk_many_groups():
-    """Refresh-mode walks over 8192 or more groups (the construction walk
-    and a large refresh selection) run in lane tiles; their lists must be
-    the oracle's."""
-    say("case refresh mode, tile walk over many groups")
-    d = sheared(200000, 4)
+def _refresh_many(d, n_grp, min_groups, min_sel):
     dt = 1 / 64
-    n_grp = 16
     t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, n_grp)
     t.make_lists(THETA)
-    assert t.n_groups >= 8192
+    assert t.n_groups >= min_groups
     with ctx_for(d, n_grp=n_grp, k_max=8) as ctx:
         ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
         compare_lists(ctx, t)
+        g, c = ctx.get_groups(), ctx.get_cells()
+        side = cell_side(t, g, c)
+        compare_slacks(ctx, t, side)
         ctx.kick_drift(0.0, dt)
         ctx.compute_forces(nb.NB_REUSE_LIST)
         x, y, z = drift(d, dt, 1)
         t.refresh(x, y, z, d["m"])
         ng = t.n_groups
         sel = np.arange(0, ng, 1, dtype=np.int64)[(np.arange(ng) % 5) != 0]
-        assert sel.size >= 8192
+        assert sel.size >= min_sel
         ctx.refresh_lists(sel)
         t.refresh_lists(THETA, sel)
         compare_lists(ctx, t)
+        compare_slacks(ctx, t, side)
         assert ctx.get_info()["last_refreshed"] == sel.size
+
+
+def test_refresh_mode_tile_walk_many_groups():
+    """Refresh-mode walks over 8192 or more groups (the construction walk
+    and a large refresh selection) run in lane tiles; their lists and the
+    opening-test slacks they record must be the oracle's."""
+    say("case refresh mode, tile walk over many groups")
+    _refresh_many(sheared(200000, 4), 16, 8192, 8192)
+
+
+def test_refresh_mode_thread_walk_over_65536_groups():
+    """From 65536 groups on, refresh-mode walks run one thread per group:
+    the construction walk and a selection of more than 65536 groups, with
+    their slacks, against the oracle."""
+    say("case refresh mode, one-thread walk over 65536+ groups")
+    _refresh_many(sheared(500000, 6), 8, 1 << 16, 1 << 16)
 
 
 @pytest.mark.parametrize("n_grp,steps", [(64, 2), (16, 3)])

@@ -383,14 +383,16 @@ def test_device_resident_input_matches_host_input():
 
 @pytest.mark.parametrize("name,order,sample", [("plummer_1m", 2, 256),
                                                ("disk_4m", 1, 256),
-                                               ("sphere_4m", 1, 256)])
+                                               ("sphere_4m", 1, 256),
+                                               ("ring_8m", 1, 256)])
 def test_full_size_sampled(name, order, sample):
     """Full-size systems in the benchmark's launch configuration: keys, tree
     and groups compared whole; lists and forces on sampled groups."""
     say("case full size %s" % name)
     d, p = workloads.make(name)
     with gpu_ctx(d, theta=p["theta"], eps=p["eps"], n_leaf=p["n_leaf"],
-                 n_grp=p["n_grp"], order=order) as ctx:
+                 n_grp=p["n_grp"], order=order,
+                 ext_mass=p.get("ext_mass", 0.0)) as ctx:
         ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
         say("  gpu done", ctx.get_info())
         t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], p["n_leaf"],
@@ -410,6 +412,51 @@ def test_full_size_sampled(name, order, sample):
         ref = t.force_lists(order, p["eps"], 1.0)
         mask = np.isfinite(ref[0])
         check_forces(ctx.get_forces(), ref, mask, what=name)
+
+
+def test_full_size_clusters_64_sampled_per_system():
+    """The 64-system batch at full size (about 3e6 particles in one set of
+    launches): every system's keys and permutation against the oracle run
+    on that system alone, and its lists and forces on sampled groups."""
+    say("case full size clusters_64")
+    d, p = workloads.make("clusters_64")
+    off = d["offsets"]
+    assert off.size == 65
+    with gpu_ctx(d, theta=p["theta"], eps=p["eps"], n_leaf=p["n_leaf"],
+                 n_grp=p["n_grp"]) as ctx:
+        ctx.set_systems(off)
+        ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        say("  gpu done", ctx.get_info())
+        key, orig = ctx.get_keys()
+        eo, e, so, s = ctx.get_lists()
+        g, c = ctx.get_groups(), ctx.get_cells()
+        f = ctx.get_forces()
+    roots = np.nonzero(c["level"] == 0)[0]
+    assert roots.size == 64
+    rng = np.random.default_rng(5)
+    for si in range(64):
+        b, en = int(off[si]), int(off[si + 1])
+        t = oracle.Tree(d["x"][b:en], d["y"][b:en], d["z"][b:en],
+                        d["m"][b:en], p["n_leaf"], p["n_grp"])
+        ok, op = t.keys()
+        np.testing.assert_array_equal(key[b:en], ok)
+        np.testing.assert_array_equal(orig[b:en], op + b)
+        gs = np.nonzero((g["begin"] >= b) & (g["begin"] < en))[0]
+        assert gs.size == t.n_groups
+        sel = np.sort(rng.choice(t.n_groups, size=min(6, t.n_groups),
+                                 replace=False))
+        t.make_lists(p["theta"], sel)
+        oeo, oe, oso, os_ = t.lists()
+        for k, j in enumerate(sel):
+            gi = gs[j]
+            np.testing.assert_array_equal(e[eo[gi]:eo[gi + 1]],
+                                          oe[oeo[k]:oeo[k + 1]] + b)
+            np.testing.assert_array_equal(s[so[gi]:so[gi + 1]],
+                                          os_[oso[k]:oso[k + 1]] + roots[si])
+        ref = t.force_lists(1, p["eps"], 1.0)
+        mask = np.isfinite(ref[0])
+        check_forces(tuple(a[b:en] for a in f), ref, mask,
+                     what="system %d" % si)
 
 
 def test_one_pass_walk_and_overflow_fallback():
@@ -479,3 +526,94 @@ def test_particles_outside_their_cube_lists_bit_exact():
                     if refresh:
                         np.testing.assert_array_equal(ctx.cell_sides(), geo)
     assert done == 8
+
+
+@pytest.mark.parametrize("order,theta_list", [(1, 0.3), (1, 0.8), (2, 0.45)])
+def test_uploaded_oracle_lists_give_oracle_forces(order, theta_list):
+    """Index lists made by the oracle (at an opening angle other than the
+    context's) go through nb_upload_lists into the force kernel; forces
+    match the oracle's FP64 sum over the same lists."""
+    say("case uploaded lists order %d theta %g" % (order, theta_list))
+    d = system("disk", 20000)
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 64)
+    t.make_lists(theta_list)
+    eo, e, so, s = t.lists()
+    with gpu_ctx(d, theta=0.5, order=order) as ctx:
+        ctx.build_tree()
+        compare_tree(ctx, t)
+        ctx.upload_lists(eo, e, so, s)
+        geo, ge, gso, gs = ctx.get_lists()
+        for a, b in ((geo, eo), (ge, e), (gso, so), (gs, s)):
+            np.testing.assert_array_equal(a, b)
+        info = ctx.get_info()
+        cnt = t.groups()["count"].astype(np.int64)
+        assert info["n_inter"] == int((cnt * (np.diff(eo) + np.diff(so))).sum())
+        ctx.compute_forces(nb.NB_REUSE_LIST)
+        got = ctx.get_forces()
+    ref = t.force_lists(order, 1 / 64, 1.0)
+    check_forces(got, ref, what="uploaded")
+
+
+def test_uploaded_lists_from_device_in_any_order():
+    """Device-resident lists with every group's entries shuffled: the same
+    forces as the oracle's sum (order inside a list only changes rounding)."""
+    import torch
+    say("case uploaded device lists, shuffled")
+    d = system("plummer", 30000)
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 64)
+    t.make_lists(0.5)
+    eo, e, so, s = t.lists()
+    rng = np.random.default_rng(3)
+    e2, s2 = e.copy(), s.copy()
+    for g in range(eo.size - 1):
+        rng.shuffle(e2[eo[g]:eo[g + 1]])
+        rng.shuffle(s2[so[g]:so[g + 1]])
+    dev = [torch.from_numpy(a.astype(np.int64) if a.dtype == np.int64 else
+                            a.view(np.int32)).cuda() for a in (eo, e2, so, s2)]
+    with gpu_ctx(d) as ctx:
+        ctx.build_tree()
+        ctx.upload_lists(*dev)
+        ctx.compute_forces(nb.NB_REUSE_LIST)
+        got = ctx.get_forces()
+    check_forces(got, t.force_lists(1, 1 / 64, 1.0), what="shuffled")
+
+
+def test_uploaded_lists_out_of_range_are_rejected():
+    """An EPJ id >= n, an SPJ id >= the cell count or bad offsets give
+    NB_ERR_LIST from the device check, before any force launch: no lists
+    are installed afterwards."""
+    say("case uploaded lists rejected")
+    d = system("plummer", 5000)
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 64)
+    t.make_lists(0.5)
+    eo, e, so, s = t.lists()
+    n, ncell = d["x"].size, t.n_cell
+    bad = []
+    e1 = e.copy(); e1[len(e1) // 2] = n
+    bad.append((eo, e1, so, s))
+    s1 = s.copy(); s1[-1] = ncell
+    bad.append((eo, e, so, s1))
+    s2 = s.copy(); s2[0] = 0xFFFFFFFF
+    bad.append((eo, e, so, s2))
+    eo1 = eo.copy(); eo1[3], eo1[4] = eo1[4], eo1[3] - 1
+    bad.append((eo1, e, so, s))
+    so1 = so.copy(); so1[0] = 1
+    bad.append((eo, e, so1, s[:-1] if s.size else s))
+    with gpu_ctx(d) as ctx:
+        ctx.build_tree()
+        for k, lists in enumerate(bad):
+            with pytest.raises(nb.NbError) as ex:
+                ctx.upload_lists(*lists)
+            assert ex.value.code == nb.NB_ERR_LIST, k
+            with pytest.raises(nb.NbError) as ex:
+                ctx.compute_forces(nb.NB_REUSE_LIST)
+            assert ex.value.code == nb.NB_ERR_STATE, k
+        # wrong group count: an argument error
+        with pytest.raises(nb.NbError) as ex:
+            ctx.upload_lists(eo[:-1], e, so[:-1], s)
+        assert ex.value.code == nb.NB_ERR_INPUT
+        # the good lists are then accepted
+        ctx.upload_lists(eo, e, so, s)
+        ctx.compute_forces(nb.NB_REUSE_LIST)
+        got = ctx.get_forces()
+    check_forces(got, t.force_lists(1, 1 / 64, 1.0), what="after rejects")
