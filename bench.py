@@ -33,6 +33,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 N_OP = 23              # flops per interaction (the paper's convention)
+# flops of one quadrupole superparticle interaction counted the same way
+# (FMA = 2, rsqrt = 4): 3 sub, r^2 6, rsqrt 4, f^2..f^7 4, S d 15, d.S.d 5,
+# coefficient 7, 3 f^5 1, acceleration 12, potential 8
+N_OP_QUAD = 65
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector peak
 WORKLOAD = "disk_4m"
 
@@ -51,6 +55,24 @@ def recorded_traffic():
         return None
     m = re.search(r"traffic_bytes_per_launch=([0-9.eE+-]+) source_sha256=(\w+)",
                   text)
+    if not m or m.group(2) != sha:
+        return None
+    return float(m.group(1))
+
+
+def recorded_valu_busy():
+    """VALU-busy fraction of the force kernel from the committed counter
+    summary, or None when the kernel source changed since."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1907_02290_amd", "csrc", "nb_force.hip")
+    prof = os.path.join(ROOT, "profiles", "force_disk_4m_valu_counters.md")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"valu_busy=([0-9.eE+-]+) source_sha256=(\w+)", text)
     if not m or m.group(2) != sha:
         return None
     return float(m.group(1))
@@ -83,6 +105,9 @@ def parse():
                     help="steps timed one by one afterwards (p50/p99)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--direct-targets", type=int, default=4096,
+                    help="sampled targets of the FP64 direct-sum error "
+                         "check (0: skip)")
     ap.add_argument("--sph", action="store_true",
                     help="time the short-range path (neighbour lists and "
                          "SPH densities) instead of the gravity step")
@@ -222,7 +247,11 @@ def main():
     f_ms, f_calls = timing["force"]
     f_avg_s = f_ms / max(f_calls, 1) * 1e-3
     inter_per_launch = inter / max(evals, 1)
-    achieved = N_OP * inter_per_launch / f_avg_s / 1e12 if f_avg_s > 0 else 0
+    # quadrupole superparticle interactions carry their own flop count
+    quad_share = inter_spj / max(inter, 1) if p["order"] == 2 else 0.0
+    flops_per_inter = N_OP * (1 - quad_share) + N_OP_QUAD * quad_share
+    flops_per_launch = flops_per_inter * inter_per_launch
+    achieved = flops_per_launch / f_avg_s / 1e12 if f_avg_s > 0 else 0
     log("timed %d steps in %.3f s: %.3f ms/step, %.3e interactions/s"
         % (args.steps, elapsed, ms_step, value))
     log("phase ms: " + ", ".join("%s %.2f/%d" % (k, v[0], v[1])
@@ -319,6 +348,36 @@ def main():
             "force err median %.2e" % (cpu["value"], cpu["cores"], tc,
                                        force_err["median"]))
 
+    # Barnes-Hut error: the same initial forces against the oracle's FP64
+    # direct sum over all N on sampled targets
+    force_err_direct = None
+    if args.direct_targets > 0 and n_sys == 1:
+        import oracle
+        rng = np.random.default_rng(4242)
+        tgt = np.sort(rng.choice(n, size=min(args.direct_targets, n),
+                                 replace=False))
+        td = time.perf_counter()
+        ref = oracle.force_direct(d["x"], d["y"], d["z"], d["m"], p["eps"],
+                                  1.0, tgt)
+        td = time.perf_counter() - td
+        num = np.sqrt((gx[tgt] - ref[0]) ** 2 + (gy[tgt] - ref[1]) ** 2 +
+                      (gz[tgt] - ref[2]) ** 2)
+        den = np.sqrt(ref[0] ** 2 + ref[1] ** 2 + ref[2] ** 2)
+        ea = num / den
+        ep = np.abs(gp[tgt] - ref[3]) / np.abs(ref[3])
+        force_err_direct = {
+            "median": float(np.median(ea)), "p99": float(np.percentile(ea, 99)),
+            "max": float(ea.max()), "pot_median": float(np.median(ep)),
+            "targets": int(tgt.size),
+            "reference": "FP64 oracle direct sum over all N particles "
+                         "(softened, self term excluded) on sampled targets; "
+                         "the error of the Barnes-Hut lists at this theta "
+                         "plus the FP32 kernel's",
+            "oracle_seconds": td}
+        log("force err vs direct sum: median %.2e p99 %.2e (%d targets, "
+            "%.1f s)" % (force_err_direct["median"], force_err_direct["p99"],
+                         tgt.size, td))
+
     out = {
         "metric": "interactions/s at N=2^22, theta=0.5 (lists reused every "
                   "4 steps); ms/step and rel force err vs FP64 oracle beside",
@@ -354,7 +413,9 @@ def main():
         },
         "step_latency": latency,
         "roofline": {
-            "kernel": "k_force (multiwalk force, monopole)",
+            "kernel": "k_force (multiwalk force, %s)" % (
+                "monopole" if p["order"] == 1 else
+                "monopole particles + quadrupole superparticles"),
             "bound": "alu",
             "achieved": achieved,
             "peak": FP32_PEAK_TFLOPS,
@@ -365,13 +426,18 @@ def main():
                         args.n is None else None),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + "
                             "WRITE_SIZE x 1.0, scaled on a 1 GiB copy)",
-            "flops_per_launch": N_OP * inter_per_launch,
+            "flops_per_launch": flops_per_launch,
+            "flops_per_interaction": flops_per_inter,
             "avg_launch_ms": f_avg_s * 1e3,
+            "valu_busy": (recorded_valu_busy()
+                          if args.workload == WORKLOAD and n_grp == 256 and
+                          args.n is None else None),
         },
         "cpu_baseline": cpu,
         "force_err": force_err,
+        "force_err_direct": force_err_direct,
         "phase_ms_per_step": {k: v[0] / args.steps for k, v in timing.items()},
-        "interactions_per_s_frac_of_fp32_peak": value * N_OP /
+        "interactions_per_s_frac_of_fp32_peak": value * flops_per_inter /
                                                 (FP32_PEAK_TFLOPS * 1e12),
         "superparticle_interactions_per_s": inter_spj / elapsed,
         "superparticle_share": inter_spj / max(inter, 1),
