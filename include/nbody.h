@@ -420,6 +420,26 @@ int nb_mlp_forward(nb_ctx* ctx, int64_t n, const float* x, float* p,
 int nb_mlp_grad(nb_ctx* ctx, int64_t n, const float* x, const float* y,
                 float pos_weight, float* loss, float* grad, int on_device);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc.  The same gradient and loss as nb_mlp_grad, from the same
+ * kernels, with no allocation and no host synchronisation: x (n rows of 12),
+ * y (n), grad (NB_MLP_NPARAM floats) and loss (1 float, may be NULL) are
+ * device arrays on the context's GPU, and the work is only enqueued on the
+ * context's stream (results are there once the stream reaches it).  The
+ * per-sample activations and partial sums live in one static array per GPU
+ * of about 8.2 MiB (1 <= n <= NB_MLP_STATIC_MAX_ROWS), held until the
+ * process ends and shared by every context on that GPU: calls whose work
+ * overlaps on one GPU (other streams, other contexts, other host threads)
+ * race on it; calls on one stream are ordered and do not.  Nothing in the
+ * array has to start at zero (each call writes what it reads).
+ * Errors: NB_ERR_INPUT (n out of range, NULL x, y or grad, pos_weight <= 0),
+ * NB_ERR_STATE (no weights: set them first with nb_mlp_set, which
+ * allocates), NB_ERR_HIP. */
+enum { NB_MLP_STATIC_MAX_ROWS = 8192 };
+int nb_mlp_grad_static(nb_ctx* ctx, int64_t n, const float* x, const float* y,
+                       float pos_weight, float* loss, float* grad);
+
 /* One Adam step (Kingma and Ba) on the weights with gradient grad (NULL =
  * the last nb_mlp_grad gradient); the step counter starts at 1 after
  * nb_mlp_set. */

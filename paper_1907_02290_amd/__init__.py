@@ -9,7 +9,7 @@ from .nbody import (Context, NbError, NB_MAKE_LIST, NB_MAKE_LIST_FOR_REUSE,
                     NB_ERR_INPUT, NB_ERR_OOM, NB_ERR_LIST, NB_ERR_STATE,
                     NB_ERR_HIP, NB_FLAG_TIMING, NB_FLAG_GRAPH,
                     NB_FLAG_REFRESH, NB_FLAG_PERSISTENT, NB_FLAG_COPIED_LISTS, MLP_NIN,
-                    MLP_NPARAM, PHASES, load,
+                    MLP_NPARAM, MLP_STATIC_MAX_ROWS, PHASES, load,
                     version, LIB_PATH)
 
 __all__ = ["Context", "NbError", "NB_MAKE_LIST", "NB_MAKE_LIST_FOR_REUSE",
@@ -17,4 +17,4 @@ __all__ = ["Context", "NbError", "NB_MAKE_LIST", "NB_MAKE_LIST_FOR_REUSE",
            "NB_ERR_INPUT", "NB_ERR_OOM", "NB_ERR_LIST", "NB_ERR_STATE",
            "NB_ERR_HIP", "NB_FLAG_TIMING", "NB_FLAG_GRAPH", "NB_FLAG_REFRESH",
            "NB_FLAG_PERSISTENT", "NB_FLAG_COPIED_LISTS",
-           "MLP_NIN", "MLP_NPARAM", "PHASES", "load", "version", "LIB_PATH"]
+           "MLP_NIN", "MLP_NPARAM", "MLP_STATIC_MAX_ROWS", "PHASES", "load", "version", "LIB_PATH"]

@@ -343,6 +343,11 @@ int nb_create(const nb_config* cfg, nb_ctx** out) {
     }
     c->own_stream = true;
   }
+  if (static_scratch_init(c)) {
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return NB_ERR_HIP;
+  }
   if (hipHostMalloc(&c->h_small, 4096, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     if (c->own_stream) (void)hipStreamDestroy(c->stream);

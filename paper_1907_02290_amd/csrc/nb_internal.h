@@ -308,6 +308,8 @@ int launch_age_inc(nb_ctx* c);
 int launch_features(nb_ctx* c);
 int launch_stale(nb_ctx* c, double tau);
 int mlp_ensure(nb_ctx* c);
+// device address of the static scratch of nb_mlp_grad_static, once per GPU
+int static_scratch_init(nb_ctx* c);
 int mlp_forward(nb_ctx* c, int64_t n, const float* x, float* p);
 int mlp_grad(nb_ctx* c, int64_t n, const float* x, const float* y, float pw);
 int mlp_adam(nb_ctx* c, const float* g, float lr, float b1, float b2,

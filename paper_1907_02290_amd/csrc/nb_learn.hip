@@ -26,6 +26,7 @@
 // for the operand staging; at 131k groups a forward pass is ~1.3 GFLOP.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <utility>
 
 #include "nb_internal.h"
@@ -651,7 +652,36 @@ int mlp_forward(nb_ctx* c, int64_t n, const float* x, float* p) {
 }
 
 // Gradient of the mean (weighted) cross-entropy over samples [0, n) of x, y
-// into c->mlp_g[0, NP) and the loss into c->mlp_g[NP] (device).
+// into grad[0, NP) and the loss into *loss (device), with the per-sample
+// activations and deltas in act (4 kNH n floats), the output deltas in dz
+// (n), the per-block loss terms in lossp (ceil(n / 256)) and the per-chunk
+// partial sums in part (ceil(n / kChunk) kNP).  Every scratch value read is
+// written earlier in the same call, so none needs clearing.
+static int mlp_grad_into(nb_ctx* c, int64_t n, const float* x, const float* y,
+                         float pw, float* act, float* dz, float* lossp,
+                         float* part, float* grad, float* loss) {
+  const int64_t nlp = grid_for(n, 256);
+  const int64_t nch = (n + kChunk - 1) / kChunk;
+  float* H1 = act;
+  float* H2 = H1 + (size_t)kNH * n;
+  float* D1 = H2 + (size_t)kNH * n;
+  float* D2 = D1 + (size_t)kNH * n;
+  const float inv_n = (float)(1.0 / (double)n);
+  hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)nlp), dim3(256), 0, c->stream,
+                     n, x, y, (const float*)c->mlp_w.p, pw, inv_n, H1, H2, D1,
+                     D2, dz, lossp);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(grid_for(kNP, 256), (unsigned)nch),
+                     dim3(256), 0, c->stream, n, x, (const float*)H1,
+                     (const float*)H2, (const float*)D1, (const float*)D2,
+                     (const float*)dz, part);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3(grid_for(kNP, 256)), dim3(256), 0,
+                     c->stream, (int)nch, (const float*)part, grad, (int)nlp,
+                     (const float*)lossp, inv_n, loss);
+  return hip_check(c, hipGetLastError(), "perceptron gradient launch");
+}
+
+// The same into c->mlp_g[0, NP) and the loss into c->mlp_g[NP], with scratch
+// the context allocates (and keeps) for n samples.
 int mlp_grad(nb_ctx* c, int64_t n, const float* x, const float* y, float pw) {
   const int64_t nlp = grid_for(n, 256);
   const int64_t nch = (n + kChunk - 1) / kChunk;
@@ -660,23 +690,53 @@ int mlp_grad(nb_ctx* c, int64_t n, const float* x, const float* y, float pw) {
   if (!rc) rc = reserve(c, c->mlp_lossp, (size_t)nlp);
   if (!rc) rc = reserve(c, c->mlp_part, (size_t)nch * kNP);
   if (rc) return rc;
-  float* H1 = c->mlp_act.p;
-  float* H2 = H1 + (size_t)kNH * n;
-  float* D1 = H2 + (size_t)kNH * n;
-  float* D2 = D1 + (size_t)kNH * n;
-  const float inv_n = (float)(1.0 / (double)n);
-  hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)nlp), dim3(256), 0, c->stream,
-                     n, x, y, (const float*)c->mlp_w.p, pw, inv_n, H1, H2, D1,
-                     D2, c->mlp_dz.p, c->mlp_lossp.p);
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3(grid_for(kNP, 256), (unsigned)nch),
-                     dim3(256), 0, c->stream, n, x, (const float*)H1,
-                     (const float*)H2, (const float*)D1, (const float*)D2,
-                     (const float*)c->mlp_dz.p, c->mlp_part.p);
-  hipLaunchKernelGGL(k_mlp_reduce, dim3(grid_for(kNP, 256)), dim3(256), 0,
-                     c->stream, (int)nch, (const float*)c->mlp_part.p,
-                     c->mlp_g.p, (int)nlp, (const float*)c->mlp_lossp.p,
-                     inv_n, c->mlp_g.p + kNP);
-  return hip_check(c, hipGetLastError(), "perceptron gradient launch");
+  return mlp_grad_into(c, n, x, y, pw, c->mlp_act.p, c->mlp_dz.p,
+                       c->mlp_lossp.p, c->mlp_part.p, c->mlp_g.p,
+                       c->mlp_g.p + kNP);
+}
+
+// ---- the allocation-free gradient (nb_mlp_grad_static) -----------------------
+// Its scratch is this file-scope array: one copy per GPU, held until the
+// process ends, shared by every context and call on that GPU.  Layout in
+// floats, each part starting on a 256-byte boundary: activations and deltas
+// (4 kNH rows), output deltas (rows), per-block loss terms (rows / 256),
+// per-chunk partial gradients (rows / kChunk x kNP), and a loss slot used
+// when the caller passes no loss pointer.
+constexpr int64_t kStaticRows = NB_MLP_STATIC_MAX_ROWS;
+static_assert(kStaticRows % kChunk == 0 && kStaticRows % 256 == 0,
+              "static scratch rows");
+constexpr size_t align64(size_t v) { return (v + 63) / 64 * 64; }
+constexpr size_t kSAct = 0;
+constexpr size_t kSDz = kSAct + align64((size_t)4 * kNH * kStaticRows);
+constexpr size_t kSLoss = kSDz + align64((size_t)kStaticRows);
+constexpr size_t kSPart = kSLoss + align64((size_t)kStaticRows / 256);
+constexpr size_t kSSink =
+    kSPart + align64((size_t)(kStaticRows / kChunk) * kNP);
+constexpr size_t kScratchFloats = kSSink + 64;
+
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+// Device address of `scratch` on each GPU (the host-side name is only a
+// stand-in: a kernel given it would fault).  Looked up once per device.
+constexpr int kMaxDevices = 64;
+static float* g_scratch_dev[kMaxDevices] = {};
+
+int static_scratch_init(nb_ctx* c) {
+  static std::mutex mu;
+  if (c->device < 0 || c->device >= kMaxDevices)
+    return set_err(c, NB_ERR_HIP, "device %d beyond the static scratch table",
+                   c->device);
+  std::lock_guard<std::mutex> lock(mu);
+  if (g_scratch_dev[c->device]) return NB_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return set_err(c, NB_ERR_HIP, "hipGetSymbolAddress(scratch): %s",
+                   hipGetErrorString(e));
+  }
+  g_scratch_dev[c->device] = static_cast<float*>(ptr);
+  return NB_OK;
 }
 
 int mlp_adam(nb_ctx* c, const float* g, float lr, float b1, float b2,
@@ -1040,6 +1100,23 @@ int nb_mlp_grad(nb_ctx* c, int64_t n, const float* x, const float* y,
   if (!rc && loss) rc = copy_out(c, loss, c->mlp_g.p + NB_MLP_NPARAM, 4, 0);
   if (!rc) rc = sync_stream(c);
   return rc;
+}
+
+int nb_mlp_grad_static(nb_ctx* c, int64_t n, const float* x, const float* y,
+                       float pos_weight, float* loss, float* grad) {
+  if (!c) return NB_ERR_INPUT;
+  if (n < 1 || n > NB_MLP_STATIC_MAX_ROWS || !x || !y || !grad ||
+      !(pos_weight > 0.f))
+    return set_err(c, NB_ERR_INPUT,
+                   "bad perceptron input (1 <= n <= %d device rows, x, y and "
+                   "grad required, pos_weight > 0)", NB_MLP_STATIC_MAX_ROWS);
+  if (!c->mlp_w.p)
+    return set_err(c, NB_ERR_STATE, "no perceptron weights (nb_mlp_set first)");
+  float* s = (c->device >= 0 && c->device < kMaxDevices)
+                 ? g_scratch_dev[c->device] : nullptr;
+  if (!s) return set_err(c, NB_ERR_STATE, "static scratch not set up");
+  return mlp_grad_into(c, n, x, y, pos_weight, s + kSAct, s + kSDz,
+                       s + kSLoss, s + kSPart, grad, loss ? loss : s + kSSink);
 }
 
 int nb_mlp_adam(nb_ctx* c, const float* grad, float lr, float beta1,

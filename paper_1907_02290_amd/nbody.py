@@ -36,6 +36,7 @@ NB_FLAG_PERSISTENT = 8
 NB_FLAG_COPIED_LISTS = 16
 MLP_NIN = 12
 MLP_NPARAM = 5057
+MLP_STATIC_MAX_ROWS = 8192
 
 STATUS = {NB_OK: "NB_OK", NB_ERR_INPUT: "NB_ERR_INPUT",
           NB_ERR_OOM: "NB_ERR_OOM", NB_ERR_LIST: "NB_ERR_LIST",
@@ -115,6 +116,7 @@ def load():
         "nb_mlp_get": ([p, p, i64], i32),
         "nb_mlp_forward": ([p, i64, p, p, i32], i32),
         "nb_mlp_grad": ([p, i64, p, p, C.c_float, p, p, i32], i32),
+        "nb_mlp_grad_static": ([p, i64, p, p, C.c_float, p, p], i32),
         "nb_mlp_adam": ([p, p, C.c_float, C.c_float, C.c_float, C.c_float,
                          i32], i32),
         "nb_mlp_train": ([p, i64, p, p, i32, i32, i64, C.c_float, C.c_float,
@@ -494,6 +496,25 @@ class Context:
         self._chk(self._lib.nb_mlp_grad(self._h, n, px, py, float(pos_weight),
                                         C.byref(loss), _ptr(g), 0))
         return float(loss.value), g
+
+    def mlp_grad_static(self, x, y, grad, loss=None, pos_weight=1.0):
+        """nb_mlp_grad_static: device tensors in and out (grad holds
+        MLP_NPARAM floats, loss one float or None); only enqueued on the
+        context's stream, no allocation, no synchronisation."""
+        px, n, dev, kx = self._in(x, MLP_NIN)
+        py, ny, dev2, ky = self._in(y)
+        pg, ng, dev3, kg = self._in(grad)
+        if not (dev and dev2 and dev3):
+            raise ValueError("x, y and grad must be device tensors")
+        if ny != n or ng != MLP_NPARAM:
+            raise ValueError("x, y and grad disagree")
+        pl = None
+        if loss is not None:
+            pl, nl, dev4, kl = self._in(loss)
+            if not dev4 or nl < 1:
+                raise ValueError("loss must be a device tensor")
+        self._chk(self._lib.nb_mlp_grad_static(self._h, n, px, py,
+                                               float(pos_weight), pl, pg))
 
     def mlp_adam(self, grad=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         if grad is None:

@@ -57,3 +57,13 @@ def test_null_context_is_rejected():
     assert lib.nb_compute_forces(None, 0) == nb.NB_ERR_INPUT
     assert lib.nb_kick_drift(None, 0.1, 0.1) == nb.NB_ERR_INPUT
     lib.nb_destroy(None)  # no-op
+
+
+def test_binding_constants_match_the_header():
+    import paper_1907_02290_amd as nb
+    src = open(HEADER).read()
+    for name, val in (("NB_MLP_NIN", nb.MLP_NIN),
+                      ("NB_MLP_NPARAM", nb.MLP_NPARAM),
+                      ("NB_MLP_STATIC_MAX_ROWS", nb.MLP_STATIC_MAX_ROWS)):
+        m = re.search(r"\b%s\s*=\s*(\d+)" % name, src)
+        assert m and int(m.group(1)) == val, name
