@@ -82,6 +82,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def direct_error(d, p, targets, seed=4242):
+    """Accuracy guard of the autotuner: a function of the forces (original
+    order) giving the 99th percentile of the relative acceleration error
+    against the FP64 oracle's direct sum on `targets` sampled particles of
+    the initial state (computed once here)."""
+    import oracle
+    n = d["x"].size
+    rng = np.random.default_rng(seed)
+    tgt = np.sort(rng.choice(n, size=min(targets, n), replace=False))
+    ref = oracle.force_direct(d["x"], d["y"], d["z"], d["m"], p["eps"], 1.0,
+                              tgt)
+    den = np.sqrt(ref[0] ** 2 + ref[1] ** 2 + ref[2] ** 2)
+
+    def err(forces):
+        num = np.sqrt((forces[0][tgt] - ref[0]) ** 2 +
+                      (forces[1][tgt] - ref[1]) ** 2 +
+                      (forces[2][tgt] - ref[2]) ** 2)
+        return float(np.percentile(num / den, 99))
+    return err
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +114,14 @@ def parse():
                     help="group size, or 'auto' to run the autotuner first "
                          "(untimed)")
     ap.add_argument("--n-leaf", type=int, default=None)
+    ap.add_argument("--theta", type=float, default=None,
+                    help="opening angle (default: the workload's)")
+    ap.add_argument("--tile-j", type=int, default=0,
+                    help="force kernel tile (list entries per LDS tile; 0: "
+                         "the library's default)")
+    ap.add_argument("--waves", type=int, default=0,
+                    help="force kernel occupancy target, waves per SIMD "
+                         "(0: the library's default)")
     ap.add_argument("--reuse", type=int, default=None)
     ap.add_argument("--graph", action="store_true",
                     help="replay reuse steps from a captured HIP graph")
@@ -113,6 +142,27 @@ def parse():
                          "SPH densities) instead of the gravity step")
     ap.add_argument("--neighbours", type=float, default=64)
     ap.add_argument("--skin", type=float, default=0.3)
+    ap.add_argument("--policies", action="store_true",
+                    help="compare list-reuse policies at equal error: fixed "
+                         "intervals against the learned per-group refresh "
+                         "(errors against the FP64 oracle's direct sum)")
+    ap.add_argument("--fixed", default="4,8,16",
+                    help="construction intervals of the fixed policies")
+    ap.add_argument("--fixed-thetas", default="0.45",
+                    help="smaller opening angles for more fixed policies")
+    ap.add_argument("--fixed-small", default="8,16",
+                    help="intervals used with --fixed-thetas")
+    ap.add_argument("--k-trees", default="16,32",
+                    help="construction intervals of the learned policy")
+    ap.add_argument("--tau", type=float, default=1.0,
+                    help="staleness tolerance of the predictor's labels")
+    ap.add_argument("--rebuild-frac", type=float, default=0.25,
+                    help="learned policy: a construction step replaces a "
+                         "refresh once this fraction of the groups is "
+                         "flagged")
+    ap.add_argument("--err-every", type=int, default=0,
+                    help="policy runs: steps between error checks (0: 8 "
+                         "checks per run)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run a plain device copy of this many MiB "
                          "(reference kernel for HBM counters)")
@@ -151,6 +201,218 @@ def sph_main(args):
     print(json.dumps(res), flush=True)
 
 
+class DirectCheck:
+    """Force errors against the FP64 oracle's direct sum (over each
+    particle's own system) on a fixed sample of target particles, and the
+    energy of a state from the run's own potentials."""
+
+    def __init__(self, d, p, targets, seed=4242):
+        n = d["x"].size
+        off = d.get("offsets")
+        self.off = off if off is not None else np.array([0, n])
+        self.m = d["m"]
+        self.eps = p["eps"]
+        self.ext = p.get("ext_mass", 0.0)
+        self.dt = p["dt"]
+        rng = np.random.default_rng(seed)
+        k = min(targets, n)
+        self.tgt = np.sort(rng.choice(n, size=k, replace=False))
+        self.seconds = 0.0
+
+    def errors(self, x, y, z, forces):
+        import oracle
+        t0 = time.perf_counter()
+        rel = []
+        for s in range(self.off.size - 1):
+            a, b = int(self.off[s]), int(self.off[s + 1])
+            sel = self.tgt[(self.tgt >= a) & (self.tgt < b)]
+            if sel.size == 0:
+                continue
+            r = oracle.force_direct(x[a:b], y[a:b], z[a:b], self.m[a:b],
+                                    self.eps, 1.0, sel - a)
+            num = np.sqrt((forces[0][sel] - r[0]) ** 2 +
+                          (forces[1][sel] - r[1]) ** 2 +
+                          (forces[2][sel] - r[2]) ** 2)
+            den = np.sqrt(r[0] ** 2 + r[1] ** 2 + r[2] ** 2)
+            rel.append(num[den > 0] / den[den > 0])
+        self.seconds += time.perf_counter() - t0
+        e = np.concatenate(rel)
+        return float(np.median(e)), float(np.percentile(e, 99))
+
+    def energy(self, state, forces):
+        """Total energy with the velocities brought to the positions' time
+        (the kick-drift leaves them half a step behind)."""
+        x, y, z, vx, vy, vz = state
+        ax, ay, az, pot = forces
+        if self.ext:
+            r3 = (x * x + y * y + z * z) ** 1.5
+            ax = ax - self.ext * x / r3
+            ay = ay - self.ext * y / r3
+            az = az - self.ext * z / r3
+        h = 0.5 * self.dt
+        ux, uy, uz = vx + h * ax, vy + h * ay, vz + h * az
+        m = self.m
+        e = 0.5 * np.sum(m * (ux * ux + uy * uy + uz * uz)) + \
+            0.5 * np.sum(m * pot)
+        if self.ext:
+            e -= self.ext * np.sum(m / np.sqrt(x * x + y * y + z * z))
+        return float(e)
+
+
+def run_policy(nb, ctx, policy, steps, dt, k, check, err_every,
+               rebuild_frac=1.0):
+    """Leapfrog steps under one reuse policy; returns ms/step (host clock
+    around each synchronised step), list walks per step, and the force
+    errors and energy change at every err_every-th step."""
+    import torch
+    times, errs, energies = [], [], []
+    walks = 0
+    constructions = 0
+    ng = 0
+
+    def measure(s):
+        if s % err_every and s != steps:
+            return
+        st = ctx.get_state()
+        f = ctx.get_forces()
+        errs.append(check.errors(st[0], st[1], st[2], f))
+        energies.append(check.energy(st, f))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+    torch.cuda.synchronize()
+    times.append(time.perf_counter() - t0)
+    ng = ctx.get_info()["n_groups"]
+    walks += ng
+    constructions += 1
+    measure(0)
+    since = 0
+    rebuild_next = False
+    for s in range(1, steps + 1):
+        dtk = dt / 2 if s == 1 else dt
+        since += 1
+        build = since >= k or rebuild_next
+        if build:
+            mode = nb.NB_MAKE_LIST_FOR_REUSE
+        elif policy == "fixed":
+            mode = nb.NB_REUSE_LIST
+        else:
+            mode = nb.NB_REUSE_REFRESH if policy == "learned" else \
+                nb.NB_REUSE_CHECK
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(mode, dtk, dt)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        info = ctx.get_info()
+        if build:
+            since = 0
+            rebuild_next = False
+            walks += info["n_groups"]
+            constructions += 1
+        elif policy != "fixed":
+            r = info["last_refreshed"]
+            walks += r
+            # the predictor flags so many lists that a construction step is
+            # cheaper than walking them again on the aging tree
+            rebuild_next = r > rebuild_frac * info["n_groups"]
+        measure(s)
+    e = np.array(errs)
+    return dict(policy=policy, k=k, steps=steps,
+                ms_per_step=1e3 * float(np.sum(times)) / len(times),
+                construction_steps=constructions,
+                walks_per_step=walks / len(times),
+                walk_fraction=walks / len(times) / max(1, ng),
+                force_err_median=float(e[:, 0].mean()),
+                force_err_p99=float(e[:, 1].mean()),
+                force_err_p99_max=float(e[:, 1].max()),
+                energy_rel_change=abs(energies[-1] - energies[0]) /
+                abs(energies[0]),
+                checks=len(errs))
+
+
+def policies_main(args):
+    """Equal-error comparison of list-reuse policies on one workload at full
+    size: the paper's fixed reuse interval (section 4.2) at the workload's
+    opening angle and at smaller ones, against the learned per-group
+    refresh (predictor trained on another realisation of the workload).
+    Errors are against the FP64 oracle's direct sum on sampled targets;
+    the energy uses each run's own potentials."""
+    import torch
+    import workloads
+    import paper_1907_02290_amd as nb
+    from paper_1907_02290_amd import learn
+    torch.cuda.set_device(0)
+    wl = args.workload
+    d0, p = workloads.make(wl, n=args.n, replicate=0)
+    d1, _ = workloads.make(wl, n=args.n, replicate=1)
+    theta, dt = p["theta"], p["dt"]
+    steps = args.steps
+    err_every = args.err_every or max(1, steps // 8)
+    n_grp = int(args.n_grp) if args.n_grp and args.n_grp != "auto" \
+        else p["n_grp"]
+    n_leaf = args.n_leaf or p["n_leaf"]
+    common = dict(eps=p["eps"], n_leaf=n_leaf, n_grp=n_grp, order=p["order"],
+                  ext_mass=p.get("ext_mass", 0.0))
+    ints = lambda v: [int(u) for u in v.split(",") if u]
+    k_trees = ints(args.k_trees)
+    tau = args.tau
+    # training on replicate 0: labels after every reuse step of fixed
+    # reuse with the first construction interval
+    kt0 = k_trees[0] if k_trees else 16
+    t0 = time.perf_counter()
+    with learn.make_context(d0, theta=theta, k_max=kt0, tau=tau,
+                            offsets=d0.get("offsets"), **common) as ctx:
+        ctx.mlp_set(learn.init_weights(0))
+        X, Y = learn.collect(ctx, 2 * kt0, dt, tau, kt0)
+        cut = (2 * X.shape[0]) // 3
+        loss = learn.train(ctx, X[:cut].contiguous(), Y[:cut].contiguous(),
+                           epochs=30)
+        pv = ctx.mlp_forward(X[cut:].contiguous()).cpu().numpy()
+        yv = Y[cut:].cpu().numpy()
+        p_star = learn.choose_threshold(pv, yv, 0.98)
+        w = ctx.mlp_get()
+    train = dict(rows=int(X.shape[0]), positives=float(Y.mean().item()),
+                 loss=loss, p_star=p_star,
+                 validation=learn.classify(pv, yv, p_star),
+                 seconds=time.perf_counter() - t0)
+    log("training: " + json.dumps(train))
+    del X, Y
+    check = DirectCheck(d1, p, args.direct_targets or 4096)
+    runs = [("fixed", k, theta) for k in ints(args.fixed)]
+    for th in (float(v) for v in args.fixed_thetas.split(",") if v):
+        runs += [("fixed", k, th) for k in ints(args.fixed_small)]
+    runs += [("learned", k, theta) for k in k_trees]
+    results = []
+    for policy, k, th in runs:
+        kw = dict(common, theta=th)
+        if policy == "fixed":
+            ctx = nb.Context(**kw)
+            ctx.set_particles(d1["x"], d1["y"], d1["z"], d1["vx"], d1["vy"],
+                              d1["vz"], d1["m"])
+            if "offsets" in d1:
+                ctx.set_systems(d1["offsets"])
+        else:
+            ctx = learn.make_context(d1, k_max=k, p_star=p_star, tau=tau,
+                                     offsets=d1.get("offsets"), **kw)
+            ctx.mlp_set(w)
+        with ctx:
+            r = run_policy(nb, ctx, policy, steps, dt, k, check, err_every,
+                           args.rebuild_frac)
+        r.update(theta=th)
+        log(json.dumps(r))
+        results.append(r)
+    out = dict(kind="policies", workload=wl, n=int(d1["x"].size),
+               steps=steps, dt=dt, tau=tau, rebuild_frac=args.rebuild_frac,
+               n_grp=n_grp, n_leaf=n_leaf, training=train,
+               error_reference="FP64 oracle direct sum over each particle's "
+                               "system, %d sampled targets"
+                               % check.tgt.size,
+               oracle_seconds=check.seconds, results=results)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -162,22 +424,34 @@ def main():
     if args.sph:
         sph_main(args)
         return
+    if args.policies:
+        policies_main(args)
+        return
 
     import torch
     import workloads
     import paper_1907_02290_amd as nb
 
     d, p = workloads.make(args.workload, n=args.n)
+    if args.theta is not None:
+        p = dict(p, theta=args.theta)
     tuned = None
+    tile_j, waves = args.tile_j, args.waves
+    n_leaf = args.n_leaf or p["n_leaf"]
     if args.n_grp == "auto":
         from paper_1907_02290_amd import tune
-        tuned = tune.tune(args.workload, args.n, log=log)
+        guard = None
+        if args.direct_targets > 0 and "offsets" not in d:
+            guard = direct_error(d, p, min(args.direct_targets, 1024))
+        tuned = tune.tune(args.workload, args.n, n_leafs=(n_leaf,),
+                          theta=p["theta"], error=guard, log=log)
         n_grp = tuned["best"]["n_grp"]
-        log("autotuner: n_grp %d (%.3f ms/step)" % (n_grp,
-                                                    tuned["best_ms_per_step"]))
+        tile_j = tuned["best"]["tile_j"]
+        waves = tuned["best"]["waves_per_simd"]
+        log("autotuner: n_grp %d tile_j %d waves %d (%.3f ms/step)"
+            % (n_grp, tile_j, waves, tuned["best_ms_per_step"]))
     else:
         n_grp = int(args.n_grp) if args.n_grp else p["n_grp"]
-    n_leaf = args.n_leaf or p["n_leaf"]
     reuse = args.reuse or p.get("reuse", 4)
     dt = p["dt"]
     n = d["x"].size
@@ -191,7 +465,8 @@ def main():
                      n_grp=n_grp, order=p["order"],
                      ext_mass=p.get("ext_mass", 0.0), timing=True,
                      graph=args.graph, persistent=args.persistent,
-                     copied_lists=args.copied_lists)
+                     copied_lists=args.copied_lists, tile_j=tile_j,
+                     waves_per_simd=waves)
     ctx.set_particles(dev["x"], dev["y"], dev["z"], dev["vx"], dev["vy"],
                       dev["vz"], dev["m"])
     del dev
@@ -406,6 +681,7 @@ def main():
             "force_evals": evals,
             "force_work_items": info_last["n_wi"],
             "n_grp_autotuned": tuned is not None,
+            "tile_j": tile_j, "waves_per_simd": waves,
             "systems": n_sys,
             "graph": bool(args.graph),
             "persistent_force": bool(args.persistent),

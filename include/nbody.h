@@ -81,6 +81,15 @@ typedef struct nb_config {
                       exceeds p_star is walked again; [0, 1] */
   double tau;      /* refresh mode: staleness tolerance of NB_REUSE_CHECK
                       (see nb_group_stale); >= 0 */
+  int32_t tile_j;  /* force kernel tile: list entries staged in LDS per
+                      round, 64, 128, 192 or 256 (a group chunk of n_i <= 32
+                      particles sums it on 64 / n_i lane slices); 0 = the
+                      default (192 monopole, 128 quadrupole).  Section 3's
+                      multiwalk kernel, tile shape of this GPU's instance */
+  int32_t waves_per_simd; /* force kernel occupancy the register allocation
+                      aims at: 4, 6 or 8 waves per SIMD; 0 = 6.  Neither
+                      changes which interactions are summed; the persistent
+                      launch (bit 3) keeps its own shape */
   void* stream;    /* hipStream_t to launch on; NULL = the library's own */
 } nb_config;
 

@@ -107,6 +107,12 @@ static int check_cfg(nb_ctx* c, const nb_config* cfg) {
     return set_err(c, NB_ERR_INPUT,
                    "copied lists need order 1, no refresh mode and no "
                    "persistent launch");
+  if (!(cfg->tile_j == 0 || cfg->tile_j == 64 || cfg->tile_j == 128 ||
+        cfg->tile_j == 192 || cfg->tile_j == 256))
+    return set_err(c, NB_ERR_INPUT, "tile_j must be 0, 64, 128, 192 or 256");
+  if (!(cfg->waves_per_simd == 0 || cfg->waves_per_simd == 4 ||
+        cfg->waves_per_simd == 6 || cfg->waves_per_simd == 8))
+    return set_err(c, NB_ERR_INPUT, "waves_per_simd must be 0, 4, 6 or 8");
   if (cfg->flags & NB_FLAG_REFRESH) {
     if (cfg->k_max < 1 || cfg->k_max > 65535)
       return set_err(c, NB_ERR_INPUT, "k_max must be in 1..65535");
@@ -244,7 +250,7 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
   // construction) when the slabs fit in a bounded buffer; otherwise, or when
   // a group overflows its slab, a count pass and an exact fill pass
   const uint32_t slab = c->tok_slab;
-  const uint64_t slabs = split_walk(c, c->n_groups) ? 2u : 1u;  // per group
+  const uint64_t slabs = split_walk(c, c->n_groups) ? kSplitLanes : 1u;
   const bool one_pass = slab > 0 &&
                         (uint64_t)c->n_groups * slabs * slab < (1ull << 32);
   if (one_pass) {
@@ -284,7 +290,8 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
     c->n_wi = static_cast<const uint32_t*>(c->h_small)[10];
     for (int x = 0; x <= 8; ++x) c->xcd_b[x] = (int64_t)h[8 + x];
   }
-  // slab for the next construction: 1.25 x the largest list, 16-aligned
+  // slab for the next construction: 1.25 x the largest token count of one
+  // slab (a group's, or one lane's of a split walk), 16-aligned
   c->tok_slab = (uint32_t)std::min<int64_t>(
       (max_tok + max_tok / 4 + 16 + 15) / 16 * 16, 1 << 24);
   {
@@ -384,7 +391,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->g_count); release(c->g_lo); release(c->g_hi);
   release(c->g_chunks); release(c->wi); release(c->queue);
   release(c->g_cost); release(c->g_cost_off); release(c->xcd_plan);
-  release(c->cnt_ta); release(c->tail.order);
+  release(c->cnt_tl); release(c->tail.order);
   release(c->nb_cnt); release(c->nb_tcnt); release(c->nb_ids);
   release(c->nb_tcnt_a);
   release(c->nb_off); release(c->nb_toff); release(c->rho);

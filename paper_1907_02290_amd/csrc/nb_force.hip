@@ -117,16 +117,22 @@ __device__ __forceinline__ void slice_sum(const float4* __restrict__ t,
   ph += tp;
 }
 
-// Largest tile: 64 x 3 entries for the monopole kernel, whose prefetched
-// records (one FP64 record per slice and lane) then fit six waves per SIMD
-// (77 VGPRs; with 64 x 4 entries it needed 93, five waves).  The quadrupole
-// kernel stages 2 x 16 bytes of second moments per entry besides the
-// record, so its tiles stop at 64 x 2 entries, which keeps its LDS (and so
-// its occupancy) in line with its registers.
-template <int ORDER>
+// Largest tile, in 64-entry blocks (KMAX): by default 3 for the monopole
+// kernel, whose prefetched records (one FP64 record per slice and lane) then
+// fit six waves per SIMD (77 VGPRs; with 4 blocks it needed 93, five
+// waves), and 2 for the quadrupole kernel, which stages 2 x 16 bytes of
+// second moments per entry besides the record, so that its LDS (and so its
+// occupancy) stays in line with its registers.  The configuration can pick
+// 1 to 4 blocks (nb_config.tile_j = 64 KMAX entries) and the occupancy the
+// register allocation aims at (nb_config.waves_per_simd: 4, 6 or 8); the
+// autotuner chooses among these instances.
+constexpr int kDefaultSlices[3] = {0, 3, 2};
+constexpr int kDefaultWaves = 6;
+
+template <int KMAX>
 struct Tiles {
-  static constexpr int kMaxSlices = ORDER == 2 ? 2 : 3;
-  static constexpr int kBig = kTile * kMaxSlices;
+  static constexpr int kMaxSlices = KMAX;
+  static constexpr int kBig = kTile * KMAX;
 };
 
 // One group chunk per wavefront.  With r = 64 / n_i lane slices (r up to
@@ -164,7 +170,7 @@ __device__ __forceinline__ int block_count(int valid, int blk0, int blk1) {
 // COPIED (monopole only): the group's entries were copied beforehand, as
 // FP32 offsets from its centre, to jcopy[epj_off + spj_off ...] (k_copy_j),
 // and the tiles are read from there.
-template <int ORDER, bool COPIED>
+template <int ORDER, bool COPIED, int KMAX>
 __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
                                            float4* tile, float4* tq,
                                            float4* red) {
@@ -179,7 +185,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
   const int sl = lane / ni;
   const int ii = lane - sl * ni;
   const bool act = sl < r;
-  constexpr int kMaxSlices = Tiles<ORDER>::kMaxSlices;
+  constexpr int kMaxSlices = Tiles<KMAX>::kMaxSlices;
   const int q = r < kMaxSlices ? r : kMaxSlices;  // tile = 64 q entries
   const int T = kTile * q;
   // this slice's block of a full tile
@@ -399,18 +405,21 @@ int64_t checked_plan(int64_t n_wi, int64_t* b, XcdPlan& plan) {
   return most * 8;
 }
 
-// One launch, one workgroup (one wavefront) per work item, six waves per
-// SIMD with the next tile's records in registers.
-template <int ORDER, bool COPIED>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8)))
+// One launch, one workgroup (one wavefront) per work item, with tiles of
+// KMAX 64-entry blocks and registers allotted for WAVES waves per SIMD (the
+// next tile's records are held in registers).
+template <int ORDER, bool COPIED, int KMAX, int WAVES>
+__global__ void __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_force(const uint4* __restrict__ wi, XcdPlan plan, ForceArgs A) {
-  __shared__ float4 tile[Tiles<ORDER>::kBig];
-  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<ORDER>::kBig : 1];
+  __shared__ float4 tile[Tiles<KMAX>::kBig];
+  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<KMAX>::kBig : 1];
   const uint32_t bid = blockIdx.x;
   const uint32_t x = bid & 7u;
   const int64_t j = plan.b[x] + (int64_t)(bid >> 3);
   if (j >= plan.b[x + 1]) return;  // uniform over the workgroup
-  force_item<ORDER, COPIED>(wi[plan_item(plan, x, j)], A, tile, tq, tile);
+  force_item<ORDER, COPIED, KMAX>(wi[plan_item(plan, x, j)], A, tile, tq,
+                                  tile);
 }
 
 // Estimated cost of a group's work items, in list entries per lane slice:
@@ -559,8 +568,9 @@ template <int ORDER>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_force_queue(const uint4* __restrict__ wi, XcdPlan plan,
               unsigned int* __restrict__ queue, ForceArgs A) {
-  __shared__ float4 tile[Tiles<ORDER>::kBig];
-  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<ORDER>::kBig : 1];
+  constexpr int K = kDefaultSlices[ORDER];
+  __shared__ float4 tile[Tiles<K>::kBig];
+  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<K>::kBig : 1];
   const uint32_t x = blockIdx.x & 7u;
   const int64_t lo = plan.b[x];
   const int64_t hi = plan.b[x + 1];
@@ -570,7 +580,8 @@ k_force_queue(const uint4* __restrict__ wi, XcdPlan plan,
     k = __shfl(k, 0, 64);
     const int64_t j = lo + (int64_t)k;
     if (j >= hi) break;  // uniform over the workgroup
-    force_item<ORDER, false>(wi[plan_item(plan, x, j)], A, tile, tq, tile);
+    force_item<ORDER, false, K>(wi[plan_item(plan, x, j)], A, tile, tq,
+                                tile);
     __syncthreads();  // the next item reuses the tile and reduction space
   }
 }
@@ -671,6 +682,66 @@ __global__ void k_zero_queue(unsigned int* q) {
   if (threadIdx.x < 8) q[threadIdx.x] = 0u;
 }
 
+// Instance selection: the largest tile (64-entry blocks) and the occupancy
+// target the configuration asks for (0 = the defaults above).  The
+// persistent launch keeps its own shape.
+int force_slices(const nb_ctx* c) {
+  const int o = c->cfg.order == 2 ? 2 : 1;
+  if ((c->cfg.flags & NB_FLAG_PERSISTENT) || c->cfg.tile_j <= 0)
+    return kDefaultSlices[o];
+  return c->cfg.tile_j / kTile;
+}
+
+int force_waves(const nb_ctx* c) {
+  return c->cfg.waves_per_simd > 0 ? c->cfg.waves_per_simd : kDefaultWaves;
+}
+
+using ForceFn = void (*)(const uint4*, XcdPlan, ForceArgs);
+
+template <int O, bool C, int K>
+ForceFn pick_waves(int waves) {
+  switch (waves) {
+    case 4: return k_force<O, C, K, 4>;
+    case 8: return k_force<O, C, K, 8>;
+    default: return k_force<O, C, K, kDefaultWaves>;
+  }
+}
+
+template <int O, bool C>
+ForceFn pick_force(int slices, int waves) {
+  switch (slices) {
+    case 1: return pick_waves<O, C, 1>(waves);
+    case 2: return pick_waves<O, C, 2>(waves);
+    case 4: return pick_waves<O, C, 4>(waves);
+    default: return pick_waves<O, C, 3>(waves);
+  }
+}
+
+using CostFn = void (*)(int64_t, const uint32_t*, const uint4*,
+                        const uint64_t*, const uint64_t*, uint32_t*);
+using TailFn = void (*)(const uint4*, const uint64_t*, const uint64_t*,
+                        XcdPlan, uint32_t*);
+
+template <int WS>
+CostFn pick_cost(int slices) {
+  switch (slices) {
+    case 1: return k_group_cost<1, WS>;
+    case 2: return k_group_cost<2, WS>;
+    case 4: return k_group_cost<4, WS>;
+    default: return k_group_cost<3, WS>;
+  }
+}
+
+template <int WS>
+TailFn pick_tail(int slices) {
+  switch (slices) {
+    case 1: return k_tail_order<1, WS>;
+    case 2: return k_tail_order<2, WS>;
+    case 4: return k_tail_order<4, WS>;
+    default: return k_tail_order<3, WS>;
+  }
+}
+
 }  // namespace
 
 int launch_force(nb_ctx* c) {
@@ -728,10 +799,13 @@ int launch_force(nb_ctx* c) {
                        (const uint32_t*)c->spj.p, (const double4*)c->pos.p,
                        (const double4*)c->c_pm.p, c->jcopy.p);
     A.jcopy = c->jcopy.p;
-    hipLaunchKernelGGL((k_force<1, true>), dim3((unsigned)nblk), dim3(kTile),
-                       0, c->stream, (const uint4*)c->wi.p, plan, A);
+    const ForceFn kc = pick_force<1, true>(force_slices(c), force_waves(c));
+    hipLaunchKernelGGL(kc, dim3((unsigned)nblk), dim3(kTile), 0, c->stream,
+                       (const uint4*)c->wi.p, plan, A);
   } else {
-    auto k = c->cfg.order == 2 ? k_force<2, false> : k_force<1, false>;
+    const int ks = force_slices(c), kw = force_waves(c);
+    ForceFn k = c->cfg.order == 2 ? pick_force<2, false>(ks, kw)
+                                  : pick_force<1, false>(ks, kw);
     hipLaunchKernelGGL(k, dim3((unsigned)nblk), dim3(kTile), 0, c->stream,
                        (const uint4*)c->wi.p, plan, A);
   }
@@ -750,8 +824,8 @@ int launch_tail_order(nb_ctx* c) {
     plan.ws[x] = std::max(plan.b[x], plan.b[x + 1] - (int64_t)kTailItems);
   int rc = reserve(c, t.order, 8 * (size_t)kTailItems);
   if (rc) return rc;
-  auto k = c->cfg.order == 2 ? k_tail_order<Tiles<2>::kMaxSlices, 2>
-                              : k_tail_order<Tiles<1>::kMaxSlices, 1>;
+  TailFn k = c->cfg.order == 2 ? pick_tail<2>(force_slices(c))
+                                : pick_tail<1>(force_slices(c));
   hipLaunchKernelGGL(k, dim3(8), dim3(1024), 0, c->stream,
                      (const uint4*)c->wi.p, (const uint64_t*)c->epj_off.p,
                      (const uint64_t*)c->spj_off.p, plan, t.order.p);
@@ -771,10 +845,9 @@ int launch_xcd_plan(nb_ctx* c, bool neighbours) {
   if (!rc) rc = reserve(c, c->g_cost_off, ng + 1);
   if (!rc) rc = reserve(c, c->xcd_plan, 9);
   if (rc) return rc;
-  auto k = neighbours ? k_group_cost<1, 1>
-                      : (c->cfg.order == 2
-                             ? k_group_cost<Tiles<2>::kMaxSlices, 2>
-                             : k_group_cost<Tiles<1>::kMaxSlices, 1>);
+  CostFn k = neighbours ? k_group_cost<1, 1>
+                        : (c->cfg.order == 2 ? pick_cost<2>(force_slices(c))
+                                             : pick_cost<1>(force_slices(c)));
   hipLaunchKernelGGL(k, dim3(grid_for(c->n_groups, 256)), dim3(256), 0,
                      c->stream, c->n_groups, (const uint32_t*)c->g_chunks.p,
                      (const uint4*)c->wi.p,

@@ -16,6 +16,8 @@ constexpr int kKeyBits = 21;   // bits per axis in a Morton key
 constexpr int kMaxLevel = 21;  // deepest tree level
 constexpr int kLevels = kMaxLevel + 1;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+// lanes per group of the gravity walk over many groups (2, 4 or 8)
+constexpr int kSplitLanes = 4;
 
 // Root cell of the last construction step, resident on the device.
 struct Root {
@@ -167,8 +169,9 @@ struct nb_ctx {
 
   // lists
   nb::DBuf<uint32_t> cnt_e, cnt_s, cnt_t;
-  nb::DBuf<uint32_t> cnt_ta;  // tokens of the first half of a two-lane walk
-  bool walk_split = false;    // the last walk ran two lanes per group
+  nb::DBuf<uint32_t> cnt_tl;  // tokens of each lane of a split walk
+                              // (nb::kSplitLanes per group)
+  bool walk_split = false;    // the last walk ran kSplitLanes lanes per group
   nb::DBuf<uint64_t> epj_off, spj_off, tok_off;
   nb::DBuf<uint32_t> epj, spj, tok;  // tok: walk tokens per group
   nb::DBuf<unsigned> lflag;          // check of uploaded lists
@@ -289,7 +292,7 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                     uint32_t* epj, uint32_t* spj, uint32_t slab = 0);
 int launch_expand_slab(nb_ctx* c, uint32_t slab);
 int walk_tile(int64_t n_walk, bool refresh = false);  // lanes per group of the walk
-bool split_walk(const nb_ctx* c, int64_t n_walk);  // two slabs per group
+bool split_walk(const nb_ctx* c, int64_t n_walk);  // kSplitLanes slabs per group
 int launch_list_stats(nb_ctx* c);
 // short-range walk: count pass (nb_cnt, nb_tcnt and their scans) and, with
 // the totals known, the fill pass and expand into nb_ids

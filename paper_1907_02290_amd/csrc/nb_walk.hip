@@ -188,21 +188,30 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
 }
 
 // The walk over the 16-byte walk records (one load per visit instead of the
-// 64-byte cell record's three), two lanes per group: the stackless walk
-// reaches the deepest cell gd holding the group (its ancestors all hold the
-// group and are opened), so lane 0 walks the cells before gd in pre-order
-// and lane 1 the cells from gd on, and lane 0's tokens followed by lane 1's
-// are the one-thread walk's.  That shortens the longest chain of dependent
-// visits (4.6k on the 2^22 disk) by about a third.  In slab mode each half
-// has a slab of its own (group g: slabs 2g and 2g + 1); in the exact fill
-// lane 1 writes after lane 0's count from the count pass (cnt_ta).  The centre and
+// 64-byte cell record's three), S lanes per group (S = 2, 4 or 8).  The
+// stackless walk reaches the deepest cell gd holding the group, and every
+// ancestor a of gd holds the group and is opened, so the walk visits a and
+// skip(a) (the first cell after a's subtree, whose ancestors are ancestors of
+// a).  Those cells cut the pre-order walk into S independent stretches: with
+// a_1 .. a_{S/2-1} the ancestors of gd at depths D q / (S / 2) (D = depth of
+// gd), lane h < S/2 walks the cells from a_h to a_{h+1} (a_0 = the system's
+// root, a_{S/2} = gd) and lane S/2 + h the cells from skip(a_{S/2-h}) to
+// skip(a_{S/2-h-1}) (skip(a_{S/2}) read as gd, skip(a_0) as the system's
+// end), and the lanes' tokens in lane order are the one-thread walk's.  A
+// terminal cell inside a stretch never reaches past its end: a subtree that
+// held the stretch's end would hold an ancestor of the group and be opened.
+// On the 2^20 disk (seeded sample of groups) the longest stretch of a group
+// averages 1678 visits with two lanes and 843 with eight.  In slab mode each
+// lane has a slab of its own (group g: slabs S g .. S g + S - 1); in the
+// exact fill lane h writes after the tokens that the count pass recorded
+// for lanes 0 .. h - 1 (cnt_tl, S per group).  The centre and
 // (side / theta)^2 of a cell come from its integer coordinates and level by
 // the tree build's own FP64 operations, so every opening decision, and the
 // token stream, is the same as from the cell records.  A cell holds the
 // group's particle range exactly when it is an ancestor of, or is, the
 // deepest cell with that range (cell ranges are nested or disjoint and never
 // empty), i.e. when c <= gd < skip(c) in pre-order.
-template <bool FILL>
+template <bool FILL, int S>
 __global__ void __launch_bounds__(kWalkThreads)
 k_walk_c(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
          const uint32_t* __restrict__ g_count,
@@ -211,17 +220,19 @@ k_walk_c(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
          const uint4* __restrict__ wrec, const Root* __restrict__ roots,
          const uint32_t* __restrict__ seg, const uint32_t* __restrict__ croot,
          uint32_t* __restrict__ cnt_e, uint32_t* __restrict__ cnt_s,
-         uint32_t* __restrict__ cnt_t, uint32_t* __restrict__ cnt_ta,
+         uint32_t* __restrict__ cnt_t, uint32_t* __restrict__ cnt_tl,
          const uint64_t* __restrict__ tok_off,
          uint32_t* __restrict__ tok, uint32_t slab) {
+  static_assert(S == 2 || S == 4 || S == 8, "lanes per group");
+  constexpr int H = S / 2;
   __shared__ uint32_t stage[FILL ? kSeg : 1][kWalkThreads];
   const int64_t blk = xcd_block(nblk);
   if (blk >= nblk) return;
-  // n_walk = 2 x groups: the two lanes of a group leave together
+  // n_walk = S x groups: the S lanes of a group leave together
   const int64_t tt = blk * kWalkThreads + threadIdx.x;
   if (tt >= n_walk) return;
-  const int64_t g = tt >> 1;
-  const int half = (int)(tt & 1);
+  const int64_t g = tt / S;
+  const int h = (int)(tt % S);
   const uint32_t gb = g_begin[g];
   const uint32_t ge = gb + g_count[g];
   const double4 lo = g_lo[g], hi = g_hi[g];
@@ -233,29 +244,61 @@ k_walk_c(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
     if (m1.x != gb || m1.y != ge) break;
     ++gd;
   }
+  const uint32_t sys = seg[gb];
+  const uint32_t r0 = croot[sys], r1 = croot[sys + 1];
+  // this lane's stretch [c, nc)
+  uint32_t c, nc;
+  if (S == 2) {
+    c = h ? gd : r0;
+    nc = h ? r1 : gd;
+  } else {
+    // ancestors of gd at depths D q / H, q = 1 .. H - 1 (one cell per level
+    // on the path: the parent of a level-l cell is at level l - 1)
+    const int D = (int)(rec[gd].meta.w & 255u);
+    uint32_t a[H + 1];
+    a[0] = r0;
+    a[H] = gd;
+    uint32_t x = gd;
+    int lx = D;
+#pragma unroll
+    for (int q = H - 1; q >= 1; --q) {
+      const int want = (D * q) / H;
+      while (lx > want) {
+        x = rec[x].aux.x;
+        --lx;
+      }
+      a[q] = x;
+    }
+    if (h < H) {
+      c = a[h];
+      nc = a[h + 1];
+    } else {
+      const int k2 = h - H;  // 0 .. H - 1
+      c = k2 == 0 ? gd : wrec[a[H - k2]].z;
+      nc = k2 == H - 1 ? r1 : wrec[a[H - 1 - k2]].z;
+    }
+  }
   uint32_t* dst = nullptr;
   uint64_t out = 0;
   uint64_t end = 0;
   int sc = 0;
   if (FILL) {
     if (slab) {
-      out = ((uint64_t)g * 2u + (uint64_t)half) * slab;
+      out = ((uint64_t)g * S + (uint64_t)h) * slab;
       end = out + slab;
     } else {
-      out = tok_off[g] + (half ? cnt_ta[g] : 0u);
+      out = tok_off[g];
+      for (int q = 0; q < h; ++q) out += cnt_tl[(uint64_t)g * S + q];
       end = ~0ull;
     }
     dst = tok;
   }
   const bool counts = !FILL || slab != 0;
   uint32_t ne = 0, ns = 0, nl = 0;
-  const uint32_t sys = seg[gb];
   const Root* root = roots + sys;
   const double rx = root->lo[0], ry = root->lo[1], rz = root->lo[2];
   const double rr = root->rr;
   const int k = root->k;
-  uint32_t c = half ? gd : croot[sys];
-  const uint32_t nc = half ? croot[sys + 1] : gd;
   // Loads and stores share one completion counter, so the wait for a
   // visit's record also waits for every store issued before it.  A full
   // segment read from the stage is therefore stored in the next visit, right
@@ -350,14 +393,18 @@ k_walk_c(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
   }
   if (counts) {
     const uint32_t ta = ns + nl;
-    const uint32_t e2 = ne + __shfl_xor(ne, 1, 64);
-    const uint32_t s2 = ns + __shfl_xor(ns, 1, 64);
-    const uint32_t t2 = ta + __shfl_xor(ta, 1, 64);
-    if (half == 0) {
+    uint32_t e2 = ne, s2 = ns, t2 = ta;
+#pragma unroll
+    for (int o = S / 2; o > 0; o >>= 1) {
+      e2 += __shfl_xor(e2, o, 64);
+      s2 += __shfl_xor(s2, o, 64);
+      t2 += __shfl_xor(t2, o, 64);
+    }
+    cnt_tl[(uint64_t)g * S + h] = ta;
+    if (h == 0) {
       cnt_e[g] = e2;
       cnt_s[g] = s2;
       cnt_t[g] = t2;
-      cnt_ta[g] = ta;
     }
   }
 }
@@ -520,7 +567,7 @@ __global__ void __launch_bounds__(256)
 k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
          const uint64_t* __restrict__ tok_off, uint32_t slab,
          const uint32_t* __restrict__ cnt_t,
-         const uint32_t* __restrict__ cnt_ta,
+         const uint32_t* __restrict__ cnt_tl, int lanes,
          const uint32_t* __restrict__ tok, const CellRec* __restrict__ rec,
          const uint64_t* __restrict__ epj_off,
          const uint64_t* __restrict__ spj_off, uint32_t* __restrict__ epj,
@@ -531,31 +578,26 @@ k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   const int lane = threadIdx.x & 63;
   if (t >= n_walk) return;
   const int64_t g = sel ? (int64_t)sel[t] : t;
-  // the token stream: one range, or (slab mode of the two-lane walk, cnt_ta
-  // given) the two halves' slabs one after the other
-  uint64_t r0[2], r1[2];
-  int nr = 1;
-  if (!slab) {
-    r0[0] = tok_off[t];
-    r1[0] = tok_off[t + 1];
-  } else if (!cnt_ta) {
-    r0[0] = (uint64_t)t * slab;
-    r1[0] = r0[0] + cnt_t[t];
-  } else {
-    const uint32_t ta = cnt_ta[t];
-    r0[0] = (uint64_t)t * 2u * slab;
-    r1[0] = r0[0] + ta;
-    r0[1] = r0[0] + slab;
-    r1[1] = r0[1] + (cnt_t[t] - ta);
-    nr = 2;
-  }
+  // the token stream: one range, or (slab mode of the walk with `lanes`
+  // lanes per group, cnt_tl given) the lanes' slabs one after the other
+  const int nr = (slab && cnt_tl) ? lanes : 1;
   uint64_t oe = epj_off[g], os = spj_off[g];
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   // kExpandBatch chunks of 64 tokens per round: their token loads, then
   // their leaves' record loads, are issued together, so a round waits for
   // two memory latencies instead of two per chunk
   for (int ri = 0; ri < nr; ++ri) {
-    const uint64_t t0 = r0[ri], t1 = r1[ri];
+    uint64_t t0, t1;
+    if (!slab) {
+      t0 = tok_off[t];
+      t1 = tok_off[t + 1];
+    } else if (!cnt_tl) {
+      t0 = (uint64_t)t * slab;
+      t1 = t0 + cnt_t[t];
+    } else {
+      t0 = ((uint64_t)t * (uint64_t)lanes + (uint64_t)ri) * slab;
+      t1 = t0 + cnt_tl[(uint64_t)t * (uint64_t)lanes + (uint64_t)ri];
+    }
     for (uint64_t cb = t0; cb < t1; cb += 64 * kExpandBatch) {
       uint32_t tk[kExpandBatch], bb[kExpandBatch], nn[kExpandBatch];
 #pragma unroll
@@ -902,7 +944,6 @@ int launch_walk(nb_ctx* c, bool fill, uint32_t slab) {
   int rc = reserve(c, c->cnt_e, ng);
   if (!rc) rc = reserve(c, c->cnt_s, ng);
   if (!rc) rc = reserve(c, c->cnt_t, ng);
-  if (!rc) rc = reserve(c, c->cnt_ta, ng);
   if (!rc) rc = reserve(c, c->epj_off, ng + 1);
   if (!rc) rc = reserve(c, c->spj_off, ng + 1);
   if (!rc) rc = reserve(c, c->tok_off, ng + 1);
@@ -920,8 +961,8 @@ int launch_expand_slab(nb_ctx* c, uint32_t slab) {
                      c->stream, c->n_groups, eblk, (const uint32_t*)nullptr,
                      (const uint64_t*)c->tok_off.p, slab,
                      (const uint32_t*)c->cnt_t.p,
-                     (const uint32_t*)(c->walk_split ? c->cnt_ta.p : nullptr),
-                     (const uint32_t*)c->tok.p,
+                     (const uint32_t*)(c->walk_split ? c->cnt_tl.p : nullptr),
+                     kSplitLanes, (const uint32_t*)c->tok.p,
                      (const CellRec*)c->c_rec.p,
                      (const uint64_t*)c->epj_off.p,
                      (const uint64_t*)c->spj_off.p, c->epj.p, c->spj.p);
@@ -949,19 +990,21 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                      slab);
     if (rc) return rc;
   } else if (!learn) {
-    // two lanes per group
-    const int64_t nblk = grid_for(2 * n_walk, kWalkThreads);
+    // kSplitLanes lanes per group
+    if ((rc = reserve(c, c->cnt_tl, (size_t)kSplitLanes * n_walk))) return rc;
+    const int64_t nblk = grid_for(kSplitLanes * n_walk, kWalkThreads);
     const int64_t launch = (nblk + 7) / 8 * 8;
-    hipLaunchKernelGGL(fill ? k_walk_c<true> : k_walk_c<false>,
-                       dim3((unsigned)launch), dim3(kWalkThreads), 0,
-                       c->stream, 2 * n_walk, nblk,
+    auto kw = fill ? k_walk_c<true, kSplitLanes>
+                   : k_walk_c<false, kSplitLanes>;
+    hipLaunchKernelGGL(kw, dim3((unsigned)launch), dim3(kWalkThreads), 0,
+                       c->stream, kSplitLanes * n_walk, nblk,
                        (const uint32_t*)c->g_begin.p,
                        (const uint32_t*)c->g_count.p, lo, hi,
                        (const uint32_t*)c->g_cell.p,
                        (const CellRec*)c->c_rec.p, (const uint4*)c->c_wrec.p,
                        (const Root*)c->root.p, (const uint32_t*)c->seg.p,
                        (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
-                       c->cnt_t.p, c->cnt_ta.p, (const uint64_t*)c->tok_off.p,
+                       c->cnt_t.p, c->cnt_tl.p, (const uint64_t*)c->tok_off.p,
                        c->tok.p, slab);
   } else {
     const int64_t nblk = grid_for(n_walk, kWalkThreads);
@@ -986,7 +1029,7 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
   hipLaunchKernelGGL(k_expand, dim3((unsigned)elaunch), dim3(256), 0,
                      c->stream, n_walk, eblk, sel,
                      (const uint64_t*)c->tok_off.p, 0u,
-                     (const uint32_t*)c->cnt_t.p, (const uint32_t*)nullptr,
+                     (const uint32_t*)c->cnt_t.p, (const uint32_t*)nullptr, 1,
                      (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
                      epj_off, spj_off, epj, spj);
   return hip_check(c, hipGetLastError(), "expand launch");
@@ -1001,8 +1044,11 @@ int launch_list_stats(nb_ctx* c) {
   if (rc) return rc;
   unsigned nb = grid_for(c->n_groups, 256);
   if (nb > 1024) nb = 1024;
+  // largest token count of one slab: per lane when the walk ran split
+  const bool lanes = c->walk_split;
   hipLaunchKernelGGL(k_max_u32, dim3(nb), dim3(256), 0, c->stream,
-                     c->n_groups, (const uint32_t*)c->cnt_t.p,
+                     lanes ? kSplitLanes * c->n_groups : c->n_groups,
+                     (const uint32_t*)(lanes ? c->cnt_tl.p : c->cnt_t.p),
                      (unsigned long long*)c->red.p + 1);
   return hip_check(c, hipGetLastError(), "list max launch");
 }
@@ -1080,7 +1126,7 @@ int launch_nbr_fill(nb_ctx* c, double h) {
                      dim3(256), 0, c->stream, c->n_groups, eblk,
                      (const uint32_t*)nullptr, (const uint64_t*)c->nb_toff.p,
                      0u, (const uint32_t*)c->nb_tcnt.p, (const uint32_t*)nullptr,
-                     (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
+                     1, (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
                      (const uint64_t*)c->nb_off.p,
                      (const uint64_t*)c->nb_off.p, c->nb_ids.p,
                      (uint32_t*)nullptr);

@@ -55,6 +55,7 @@ class nb_config(C.Structure):
                 ("n_grp", C.c_int32), ("order", C.c_int32),
                 ("flags", C.c_int32), ("k_max", C.c_int32),
                 ("p_star", C.c_double), ("tau", C.c_double),
+                ("tile_j", C.c_int32), ("waves_per_simd", C.c_int32),
                 ("stream", C.c_void_p)]
 
 
@@ -150,7 +151,8 @@ class Context:
     def __init__(self, theta=0.5, eps=0.01, G=1.0, n_leaf=8, n_grp=64,
                  order=1, ext_mass=0.0, timing=False, graph=False,
                  refresh=False, k_max=8, p_star=0.5, tau=0.0,
-                 persistent=False, copied_lists=False, stream=None):
+                 persistent=False, copied_lists=False, tile_j=0,
+                 waves_per_simd=0, stream=None):
         self._lib = load()
         flags = (NB_FLAG_TIMING if timing else 0) | \
             (NB_FLAG_GRAPH if graph else 0) | \
@@ -158,7 +160,8 @@ class Context:
             (NB_FLAG_PERSISTENT if persistent else 0) | \
             (NB_FLAG_COPIED_LISTS if copied_lists else 0)
         self._cfg = nb_config(theta, eps, G, ext_mass, n_leaf, n_grp, order,
-                              flags, k_max, p_star, tau, stream)
+                              flags, k_max, p_star, tau, tile_j,
+                              waves_per_simd, stream)
         h = C.c_void_p()
         rc = self._lib.nb_create(C.byref(self._cfg), C.byref(h))
         if rc != NB_OK:
@@ -195,6 +198,7 @@ class Context:
         return dict(theta=c.theta, eps=c.eps, G=c.G, ext_mass=c.ext_mass,
                     n_leaf=c.n_leaf, n_grp=c.n_grp, order=c.order,
                     k_max=c.k_max, p_star=c.p_star, tau=c.tau,
+                    tile_j=c.tile_j, waves_per_simd=c.waves_per_simd,
                     refresh=bool(c.flags & NB_FLAG_REFRESH))
 
     def set_config(self, **kw):

@@ -617,3 +617,46 @@ def test_uploaded_lists_out_of_range_are_rejected():
         ctx.compute_forces(nb.NB_REUSE_LIST)
         got = ctx.get_forces()
     check_forces(got, t.force_lists(1, 1 / 64, 1.0), what="after rejects")
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_every_force_kernel_instance_matches_oracle(order):
+    """Each tile length (64..256 list entries per LDS tile) and occupancy
+    target (4, 6, 8 waves per SIMD) of the force kernel sums the same lists:
+    forces within the FP32 tolerance of the oracle's FP64 list sum, on a
+    clustered set whose groups run full chunks and lane slices (n_grp 48:
+    remainders of 1..47 particles)."""
+    d = _clustered(30000, 5)
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 48)
+    t.make_lists(0.6)
+    ref = t.force_lists(order, 1 / 64, 1.0)
+    first = None
+    for tile_j in (64, 128, 192, 256):
+        for waves in (4, 6, 8):
+            say("case force instance order=%d tile_j=%d waves=%d"
+                % (order, tile_j, waves))
+            ctx = nb.Context(theta=0.6, eps=1 / 64, n_leaf=8, n_grp=48,
+                             order=order, tile_j=tile_j,
+                             waves_per_simd=waves)
+            with ctx:
+                ctx.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"],
+                                  d["vz"], d["m"])
+                ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+                if first is None:
+                    compare_lists(ctx, t)
+                got = ctx.get_forces()
+                check_forces(got, ref, what="tile %d waves %d" % (tile_j,
+                                                                   waves))
+                # the same tile gives the same sums whatever the occupancy
+                if waves == 4:
+                    first = got
+                else:
+                    for a, b in zip(got, first):
+                        np.testing.assert_array_equal(a, b)
+
+
+def test_tile_config_is_checked():
+    for bad in (dict(tile_j=96), dict(tile_j=512), dict(waves_per_simd=5)):
+        with pytest.raises(nb.NbError) as e:
+            nb.Context(**bad)
+        assert e.value.code == nb.NB_ERR_INPUT
