@@ -327,7 +327,9 @@ def make(name, n=None, seed=None, replicate=0):
     disk_4m      disk 2^21 + halo 2^21 (eps 0.01, theta 0.5, lists reused
                  every 4 steps, dt 1/128; n_grp 256, the fastest step of a
                  sweep over 32..1024 on MI355X)
-    ring_8m      ring N=2^23 (eps 1e-4, dt 2 pi/256, central mass 1)
+    ring_8m      ring N=2^23 (eps 1e-4, dt 2 pi/256, central mass 1; n_grp
+                 256, the autotuner's pick on MI355X: the thin ring's cells
+                 of <= 64 particles hold 11 on average)
     clusters_64  64 independent Plummer / King(W0 = 6) clusters, N log-uniform
                  in [2^10, 2^18] (eps 0.01, dt 1/128)
     sphere_4m    cold uniform sphere N=2^22 (leaf 16)
@@ -353,7 +355,7 @@ def make(name, n=None, seed=None, replicate=0):
         nn = n or (1 << 23)
         s = seed if seed is not None else seed_for(4, replicate)
         return ring(nn, s), dict(eps=1e-4, theta=0.5, order=1, n_leaf=8,
-                                 n_grp=64, dt=2.0 * np.pi / 256,
+                                 n_grp=256, dt=2.0 * np.pi / 256,
                                  ext_mass=1.0)
     if name == "clusters_64":
         s = seed if seed is not None else seed_for(5, replicate)
