@@ -239,6 +239,13 @@ class DirectCheck:
         e = np.concatenate(rel)
         return float(np.median(e)), float(np.percentile(e, 99))
 
+    def __call__(self, ctx):
+        """Errors and energy of a context's current state and forces."""
+        st = ctx.get_state()
+        f = ctx.get_forces()
+        med, p99 = self.errors(st[0], st[1], st[2], f)
+        return dict(err_median=med, err_p99=p99, energy=self.energy(st, f))
+
     def energy(self, state, forces):
         """Total energy with the velocities brought to the positions' time
         (the kick-drift leaves them half a step behind)."""
@@ -257,79 +264,6 @@ class DirectCheck:
         if self.ext:
             e -= self.ext * np.sum(m / np.sqrt(x * x + y * y + z * z))
         return float(e)
-
-
-def run_policy(nb, ctx, policy, steps, dt, k, check, err_every,
-               rebuild_frac=1.0):
-    """Leapfrog steps under one reuse policy; returns ms/step (host clock
-    around each synchronised step), list walks per step, and the force
-    errors and energy change at every err_every-th step."""
-    import torch
-    times, errs, energies = [], [], []
-    walks = 0
-    constructions = 0
-    ng = 0
-
-    def measure(s):
-        if s % err_every and s != steps:
-            return
-        st = ctx.get_state()
-        f = ctx.get_forces()
-        errs.append(check.errors(st[0], st[1], st[2], f))
-        energies.append(check.energy(st, f))
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
-    torch.cuda.synchronize()
-    times.append(time.perf_counter() - t0)
-    ng = ctx.get_info()["n_groups"]
-    walks += ng
-    constructions += 1
-    measure(0)
-    since = 0
-    rebuild_next = False
-    for s in range(1, steps + 1):
-        dtk = dt / 2 if s == 1 else dt
-        since += 1
-        build = since >= k or rebuild_next
-        if build:
-            mode = nb.NB_MAKE_LIST_FOR_REUSE
-        elif policy == "fixed":
-            mode = nb.NB_REUSE_LIST
-        else:
-            mode = nb.NB_REUSE_REFRESH if policy == "learned" else \
-                nb.NB_REUSE_CHECK
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.step(mode, dtk, dt)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        info = ctx.get_info()
-        if build:
-            since = 0
-            rebuild_next = False
-            walks += info["n_groups"]
-            constructions += 1
-        elif policy != "fixed":
-            r = info["last_refreshed"]
-            walks += r
-            # the predictor flags so many lists that a construction step is
-            # cheaper than walking them again on the aging tree
-            rebuild_next = r > rebuild_frac * info["n_groups"]
-        measure(s)
-    e = np.array(errs)
-    return dict(policy=policy, k=k, steps=steps,
-                ms_per_step=1e3 * float(np.sum(times)) / len(times),
-                construction_steps=constructions,
-                walks_per_step=walks / len(times),
-                walk_fraction=walks / len(times) / max(1, ng),
-                force_err_median=float(e[:, 0].mean()),
-                force_err_p99=float(e[:, 1].mean()),
-                force_err_p99_max=float(e[:, 1].max()),
-                energy_rel_change=abs(energies[-1] - energies[0]) /
-                abs(energies[0]),
-                checks=len(errs))
 
 
 def policies_main(args):
@@ -398,9 +332,17 @@ def policies_main(args):
                                      offsets=d1.get("offsets"), **kw)
             ctx.mlp_set(w)
         with ctx:
-            r = run_policy(nb, ctx, policy, steps, dt, k, check, err_every,
-                           args.rebuild_frac)
-        r.update(theta=th)
+            r = learn.run_policy(ctx, policy, steps, dt, k, check=check,
+                                 check_every=err_every,
+                                 rebuild_frac=(args.rebuild_frac
+                                               if policy != "fixed" else None))
+        c = r.pop("checks")
+        e0, e1 = c[0]["energy"], c[-1]["energy"]
+        r.update(theta=th,
+                 force_err_median=float(np.mean([q["err_median"] for q in c])),
+                 force_err_p99=float(np.mean([q["err_p99"] for q in c])),
+                 force_err_p99_max=float(np.max([q["err_p99"] for q in c])),
+                 energy_rel_change=abs(e1 - e0) / abs(e0), checks=len(c))
         log(json.dumps(r))
         results.append(r)
     out = dict(kind="policies", workload=wl, n=int(d1["x"].size),

@@ -4,7 +4,9 @@ policies that the predictor is compared with.
 
 Every computation goes through the library's C ABI (``nbody.Context``); this
 module only sequences the calls and keeps the training rows in device
-tensors.
+tensors.  It measures no accuracy itself: callers pass a check function
+(``bench.py --policies`` passes errors against the FP64 oracle's direct sum
+on sampled particles).
 
 Policies (``run_policy``):
   * ``fixed``   -- the paper's reuse (section 4.2): a construction step every
@@ -123,39 +125,8 @@ def classify(p, y, p_star):
                 precision=tp / max(1, int(flag.sum())))
 
 
-class Reference:
-    """Direct-sum forces (theta = 0: every list holds every particle of the
-    system) through the same library, for the error of a policy's forces at
-    the positions it reached."""
-
-    def __init__(self, eps, G=1.0, ext_mass=0.0, n_grp=256, offsets=None):
-        self.ctx = nb.Context(theta=0.0, eps=eps, G=G, n_leaf=8, n_grp=n_grp,
-                              order=1, ext_mass=ext_mass)
-        self.offsets = offsets
-        self.ext_mass = ext_mass
-        self.G = G
-
-    def close(self):
-        self.ctx.close()
-
-    def forces(self, x, y, z, m):
-        zero = np.zeros_like(x)
-        self.ctx.set_particles(x, y, z, zero, zero, zero, m)
-        if self.offsets is not None:
-            self.ctx.set_systems(self.offsets)
-        self.ctx.compute_forces(nb.NB_MAKE_LIST)
-        return self.ctx.get_forces()
-
-    def energy(self, x, y, z, vx, vy, vz, m, pot):
-        kin = 0.5 * np.sum(m * (vx * vx + vy * vy + vz * vz))
-        e = kin + 0.5 * np.sum(m * pot)
-        if self.ext_mass:
-            e -= self.G * self.ext_mass * np.sum(m / np.sqrt(x * x + y * y +
-                                                             z * z))
-        return float(e)
-
-
 def force_error(got, ref):
+    """Per-particle |a - a_ref| / |a_ref| of two (ax, ay, az, ...) tuples."""
     ax, ay, az = got[:3]
     rx, ry, rz = ref[:3]
     num = np.sqrt((ax - rx) ** 2 + (ay - ry) ** 2 + (az - rz) ** 2)
@@ -164,182 +135,74 @@ def force_error(got, ref):
     return num[ok] / den[ok]
 
 
-def run_policy(ctx, policy, steps, dt, k, tau, measure=True, ref=None,
-               m=None, err_every=4):
-    """Run ``steps`` leapfrog steps under a policy (see module doc).  With
-    ``measure`` the staleness of the lists the force kernel used is checked
-    after every reuse step, and with ``ref`` (a Reference) the forces are
-    compared with the direct sum every ``err_every`` steps and the energy
-    is evaluated; all of that outside the timed region.  Returns a dict with
-    the wall time of the steps, list walks per step (all groups at a
-    construction step, refreshed groups otherwise), stale fractions, force
-    errors and the relative energy change."""
+def run_policy(ctx, policy, steps, dt, k, tau=None, check=None,
+               check_every=4, rebuild_frac=None):
+    """Run ``steps`` leapfrog steps under a policy (see the module doc) from
+    a construction step at the initial state.  The wall time of every step
+    is taken around device synchronisations.  With ``tau`` the fraction of
+    groups whose list fails the relaxed test at tolerance tau is recorded
+    after every reuse step; with ``check`` (a function of the context that
+    returns a dict of numbers, for example errors against a reference) it is
+    called at step 0, at every ``check_every``-th step and at the last one.
+    Both happen outside the timed steps.  ``rebuild_frac`` (refresh
+    policies): when a step walks more than that fraction of the groups
+    again, the next step is a construction step.  Returns ms/step, list walks
+    per step (all groups at a construction step, refreshed groups
+    otherwise), construction steps, stale fractions and the check results
+    (a list of dicts)."""
     import torch
-    walks = 0
+    times = []
     stale = []
-    errs = []
-    energies = []
-    t_run = 0.0
-    refreshed = 0
+    checks = []
+    walks = refreshed = constructions = 0
 
-    def check(s):
-        if ref is None or s % err_every:
-            return
-        x, y, z, vx, vy, vz = ctx.get_state()
-        got = ctx.get_forces()
-        r = ref.forces(x, y, z, m)
-        e = force_error(got, r)
-        errs.append((float(np.median(e)), float(np.percentile(e, 99))))
-        energies.append(ref.energy(x, y, z, vx, vy, vz, m, r[3]))
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
-    walks += ctx.get_info()["n_groups"]
-    torch.cuda.synchronize()
-    t_run += time.perf_counter() - t0
-    check(0)
+    timed(lambda: ctx.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE))
+    ng = ctx.get_info()["n_groups"]
+    walks += ng
+    constructions += 1
+    if check is not None:
+        checks.append(dict(step=0, **check(ctx)))
+    since = 0
+    rebuild_next = False
+    reuse_mode = {"fixed": nb.NB_REUSE_LIST, "learned": nb.NB_REUSE_REFRESH,
+                  "checked": nb.NB_REUSE_CHECK}[policy]
     for s in range(1, steps + 1):
         dtk = dt / 2 if s == 1 else dt
-        t0 = time.perf_counter()
-        if s % k == 0:
-            ctx.step(nb.NB_MAKE_LIST_FOR_REUSE, dtk, dt)
-            walks += ctx.get_info()["n_groups"]
-        elif policy == "fixed":
-            ctx.step(nb.NB_REUSE_LIST, dtk, dt)
-        elif policy == "learned":
-            ctx.step(nb.NB_REUSE_REFRESH, dtk, dt)
-            r = ctx.get_info()["last_refreshed"]
+        since += 1
+        build = since >= k or rebuild_next
+        mode = nb.NB_MAKE_LIST_FOR_REUSE if build else reuse_mode
+        timed(lambda: ctx.step(mode, dtk, dt))
+        info = ctx.get_info()
+        if build:
+            since = 0
+            rebuild_next = False
+            walks += info["n_groups"]
+            constructions += 1
+        elif policy != "fixed":
+            r = info["last_refreshed"]
             walks += r
             refreshed += r
-        elif policy == "checked":
-            ctx.step(nb.NB_REUSE_CHECK, dtk, dt)
-            r = ctx.get_info()["last_refreshed"]
-            walks += r
-            refreshed += r
-        else:
-            raise ValueError(policy)
-        torch.cuda.synchronize()
-        t_run += time.perf_counter() - t0
-        if measure and s % k != 0:
+            if rebuild_frac is not None:
+                rebuild_next = r > rebuild_frac * info["n_groups"]
+            if tau is not None:
+                stale.append(float(np.mean(ctx.group_stale(tau))))
+        elif tau is not None:
             stale.append(float(np.mean(ctx.group_stale(tau))))
-        check(s)
-    ng = ctx.get_info()["n_groups"]
-    out = dict(policy=policy, k=k, steps=steps, seconds=t_run,
-               ms_per_step=1e3 * t_run / (steps + 1),
-               walks_per_step=walks / (steps + 1),
-               walk_fraction=walks / (steps + 1) / max(1, ng),
-               refreshed=refreshed,
-               stale_mean=float(np.mean(stale)) if stale else 0.0,
-               stale_max=float(np.max(stale)) if stale else 0.0)
-    if errs:
-        e = np.array(errs)
-        out.update(force_err_median=float(e[:, 0].mean()),
-                   force_err_p99=float(e[:, 1].mean()),
-                   force_err_p99_max=float(e[:, 1].max()),
-                   energy_rel_change=abs(energies[-1] - energies[0]) /
-                   abs(energies[0]))
-    return out
-
-
-def evaluate(workload="disk_4m", n=1 << 18, tau=0.1, k_tree=16,
-             collect_cycles=3, recall=0.98, epochs=30, batch=8192, lr=2e-3,
-             steps=64, fixed=(1, 2, 4, 8, 16), k_trees=None,
-             fixed_thetas=(), log=print):
-    """Train the predictor on one realisation of a workload (seed 0) and
-    compare the reuse policies on another (seed 1).  Returns a list of
-    result dicts: the training summary, then one per policy."""
-    import torch
-    import workloads
-    d0, p = workloads.make(workload, n=n, replicate=0)
-    d1, _ = workloads.make(workload, n=n, replicate=1)
-    common = dict(theta=p["theta"], eps=p["eps"], n_leaf=p["n_leaf"],
-                  n_grp=p["n_grp"], order=p["order"],
-                  ext_mass=p.get("ext_mass", 0.0), tau=tau)
-    dt = p["dt"]
-    out = []
-    with make_context(d0, k_max=k_tree, offsets=d0.get("offsets"),
-                      **common) as ctx:
-        ctx.mlp_set(init_weights(0))
-        t0 = time.perf_counter()
-        X, Y = collect(ctx, collect_cycles * k_tree, dt, tau, k_tree)
-        torch.cuda.synchronize()
-        t_collect = time.perf_counter() - t0
-        n_rows = X.shape[0]
-        cut = (2 * n_rows) // 3
-        t0 = time.perf_counter()
-        loss = train(ctx, X[:cut].contiguous(), Y[:cut].contiguous(),
-                     epochs=epochs, batch=batch, lr=lr)
-        torch.cuda.synchronize()
-        t_train = time.perf_counter() - t0
-        pv = ctx.mlp_forward(X[cut:].contiguous()).cpu().numpy()
-        yv = Y[cut:].cpu().numpy()
-        p_star = choose_threshold(pv, yv, recall)
-        w = ctx.mlp_get()
-    stats = classify(pv, yv, p_star)
-    summary = dict(kind="training", workload=workload, n=int(d0["x"].size),
-                   tau=tau, k_tree=k_tree, rows=int(n_rows),
-                   train_rows=int(cut), positives=float(Y.mean().item()),
-                   loss=loss, p_star=p_star, collect_s=t_collect,
-                   train_s=t_train, validation=stats)
-    log(summary)
-    out.append(summary)
-    # fixed intervals at the workload's theta and at smaller angles (the
-    # equal-error comparison), then the refresh policies
-    runs = [("fixed", k, p["theta"]) for k in fixed]
-    runs += [("fixed", k, th) for th in fixed_thetas for k in (2, 4, 8)]
-    for kt in (k_trees or (k_tree,)):
-        runs += [("checked", kt, p["theta"]), ("learned", kt, p["theta"])]
-    ref = Reference(p["eps"], ext_mass=p.get("ext_mass", 0.0),
-                    offsets=d1.get("offsets"))
-    for policy, k, th in runs:
-        cfg = dict(common, theta=th)
-        with make_context(d1, k_max=k_tree, p_star=min(1.0, max(0.0, p_star)),
-                          offsets=d1.get("offsets"), **cfg) as ctx:
-            ctx.mlp_set(w)
-            r = run_policy(ctx, policy, steps, dt, k, tau, ref=ref,
-                           m=d1["m"])
-        r.update(kind="policy", workload=workload, n=int(d1["x"].size),
-                 tau=tau, theta=th)
-        log(r)
-        out.append(r)
-    ref.close()
-    return out
-
-
-def main(argv=None):
-    import argparse
-    import json
-    import os
-    import sys
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    if root not in sys.path:
-        sys.path.insert(0, root)
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--workload", default="disk_4m")
-    ap.add_argument("--n", type=int, default=1 << 18)
-    ap.add_argument("--tau", type=float, default=0.1)
-    ap.add_argument("--k-tree", type=int, default=16)
-    ap.add_argument("--cycles", type=int, default=3)
-    ap.add_argument("--recall", type=float, default=0.98)
-    ap.add_argument("--epochs", type=int, default=30)
-    ap.add_argument("--steps", type=int, default=64)
-    ap.add_argument("--fixed-thetas", default="",
-                    help="comma list of smaller opening angles for extra "
-                         "fixed-interval runs (K = 2, 4, 8)")
-    ap.add_argument("--k-trees", default=None,
-                    help="comma list of construction intervals for the "
-                         "refresh policies (default: --k-tree)")
-    a = ap.parse_args(argv)
-    kts = tuple(int(v) for v in a.k_trees.split(",")) if a.k_trees else None
-    fth = tuple(float(v) for v in a.fixed_thetas.split(",") if v)
-    res = evaluate(a.workload, a.n, a.tau, a.k_tree, a.cycles, a.recall,
-                   a.epochs, steps=a.steps, k_trees=kts, fixed_thetas=fth,
-                   log=lambda r: print(json.dumps(r), file=sys.stderr,
-                                       flush=True))
-    for r in res:
-        print(json.dumps(r), flush=True)
-
-
-if __name__ == "__main__":
-    main()
+        if check is not None and (s % check_every == 0 or s == steps):
+            checks.append(dict(step=s, **check(ctx)))
+    return dict(policy=policy, k=k, steps=steps,
+                ms_per_step=1e3 * float(np.sum(times)) / len(times),
+                construction_steps=constructions,
+                walks_per_step=walks / len(times),
+                walk_fraction=walks / len(times) / max(1, ng),
+                refreshed=refreshed,
+                stale_mean=float(np.mean(stale)) if stale else 0.0,
+                stale_max=float(np.max(stale)) if stale else 0.0,
+                checks=checks)

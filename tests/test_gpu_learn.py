@@ -416,18 +416,30 @@ def test_learned_refresh_gains_over_fixed_interval():
         w = ctx.mlp_get()
     stats = learn.classify(pv, yv, p_star)
     say("  p* %.4f validation %s" % (p_star, stats))
-    ref = learn.Reference(p["eps"])
+
+    def check(ctx):
+        # errors against the FP64 oracle's direct sum over all particles
+        x, y, z = ctx.get_state()[:3]
+        ref = oracle.force_direct(x, y, z, d1["m"], p["eps"], 1.0)
+        e = learn.force_error(ctx.get_forces(), ref)
+        return dict(median=float(np.median(e)),
+                    p99=float(np.percentile(e, 99)))
+
     res = {}
     for policy in ("fixed", "learned"):
         with learn.make_context(d1, k_max=kt, p_star=p_star, **common) as ctx:
             ctx.mlp_set(w)
-            res[policy] = learn.run_policy(ctx, policy, 32, p["dt"], kt, tau,
-                                           ref=ref, m=d1["m"])
-        say("  %s: %s" % (policy, {k: (round(v, 5) if isinstance(v, float)
-                                       else v) for k, v in res[policy].items()}))
-    ref.close()
+            r = learn.run_policy(ctx, policy, 32, p["dt"], kt, tau=tau,
+                                 check=check, check_every=4)
+        r["p99"] = float(np.mean([c["p99"] for c in r["checks"]]))
+        res[policy] = r
+        # ms/step is recorded, not asserted: the learned refresh is slower
+        # per step than this fixed interval (its target is missed)
+        say("  %s: ms/step %.3f walks/step %.0f stale %.3f p99 %.5f"
+            % (policy, r["ms_per_step"], r["walks_per_step"],
+               r["stale_mean"], r["p99"]))
     f, l = res["fixed"], res["learned"]
     assert stats["recall"] >= 0.9
     assert l["stale_mean"] < 0.3 * f["stale_mean"]
-    assert l["force_err_p99"] < f["force_err_p99"]
+    assert l["p99"] < f["p99"]
     assert l["walk_fraction"] < 0.7
