@@ -194,11 +194,14 @@ int nb_make_lists(nb_ctx* ctx, nb_mode mode);
  * G, and potential excluding the self term) stay on the device until read.
  * NB_REUSE_REFRESH does the same, and between moments and force kernel
  * computes the predictor inputs of every group (nb_group_features), runs
- * the perceptron and walks again (nb_refresh_lists) every group with
- * p > cfg.p_star or age >= cfg.k_max; this synchronises with the host once,
- * twice when a group is refreshed.  NB_REUSE_CHECK does the same with the
- * exact staleness check at tolerance cfg.tau (nb_group_stale) in place of
- * the predictor.
+ * the perceptron and walks again every group with p > cfg.p_star or
+ * age >= cfg.k_max, without synchronising with the host.  In refresh mode
+ * each group's lists sit in a slot with room for twice the constructed
+ * length plus 32 entries; a walked-again list replaces the kept one in
+ * place when it fits its slot (and its token slab), otherwise the group
+ * keeps its list and age, and is counted in info[15] (nb_get_info).
+ * NB_REUSE_CHECK does the same with the exact staleness check at tolerance
+ * cfg.tau (nb_group_stale) in place of the predictor.
  * Errors: NB_ERR_STATE (REUSE_LIST without reusable lists or after
  * nb_set_particles; REUSE_REFRESH or REUSE_CHECK without NB_FLAG_REFRESH),
  * plus those of the stages. */
@@ -219,7 +222,10 @@ int nb_kick_drift(nb_ctx* ctx, double dt_kick, double dt_drift);
  * after a construction step captures kick-drift, moments and force kernel
  * into a HIP graph on the context's stream, and later reuse steps with the
  * same time steps replay it (one launch per step); a construction step, a
- * new configuration or other time steps drop the graph.  Results are the
+ * new configuration, another reuse mode or other time steps drop the graph.
+ * In refresh mode (NB_FLAG_REFRESH) NB_REUSE_REFRESH and NB_REUSE_CHECK
+ * steps are captured and replayed the same way (predictor or check,
+ * selection, walk and list refresh all run on the device).  Results are the
  * same as without the flag.  Errors: those of the two calls. */
 int nb_step(nb_ctx* ctx, nb_mode mode, double dt_kick, double dt_drift);
 
@@ -241,7 +247,12 @@ int nb_get_state(nb_ctx* ctx, double* x, double* y, double* z, double* vx,
  * work items, [10] systems, [11] groups whose lists the last force call
  * refreshed, [12] refreshed groups so far, [13] superparticle interactions
  * of the current lists (sum over groups of n_i * n_spj), [14] superparticle
- * interactions evaluated so far.  info must hold 15 values. */
+ * interactions evaluated so far, [15] groups whose walked-again list did not
+ * fit its slot in the last force call (they kept their lists), [16] the same
+ * summed over force calls.  info must hold 17 values.  In refresh mode the
+ * list sizes and these counts are kept on the device (a refresh changes the
+ * lists without the host) and this call synchronises the stream to read
+ * them. */
 int nb_get_info(nb_ctx* ctx, int64_t* info);
 
 /* Root corner lo[3] and exponent k of the last tree (side 2^k); with
@@ -280,7 +291,8 @@ int nb_get_groups(nb_ctx* ctx, uint32_t* cell, uint32_t* begin,
 /* Lists in CSR form (section 4.1: indices of EPJ and SPJ instead of their
  * copies): epj_off/spj_off hold info[2]+1 offsets, epj/spj hold
  * info[3]/info[4] ids (EPJ = internal particle positions, SPJ = cell ids),
- * ascending within each group.  Any may be NULL. */
+ * ascending within each group.  Any may be NULL.  (In refresh mode the
+ * lists sit in per-group slots on the device and are packed here.) */
 int nb_get_lists(nb_ctx* ctx, int64_t* epj_off, uint32_t* epj,
                  int64_t* spj_off, uint32_t* spj);
 
@@ -399,8 +411,11 @@ int nb_group_stale(nb_ctx* ctx, double tau, uint8_t* stale, float* label,
 
 /* Walk again the lists of the n_sel groups listed in sel (host array of
  * ascending group ids) with their current boxes and centres; other lists
- * are kept.  Sets those groups' box, shift, slacks and age (0).
- * Errors: NB_ERR_INPUT (ids not ascending or out of range). */
+ * are kept.  Sets those groups' box, shift, slacks and age (0).  A new list
+ * that does not fit its group's list slot (see nb_compute_forces) is not
+ * installed: that group keeps its list and state, and the call returns
+ * NB_ERR_LIST after installing the others.  Synchronises the stream.
+ * Errors: NB_ERR_INPUT (ids not ascending or out of range), NB_ERR_LIST. */
 int nb_refresh_lists(nb_ctx* ctx, int64_t n_sel, const int64_t* sel);
 
 /* Slacks sa, so (FP64, +inf when no such cell) and ages per group; any may

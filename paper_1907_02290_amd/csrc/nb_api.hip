@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "nb_internal.h"
 
@@ -199,7 +200,7 @@ static int build_tree(nb_ctx* c) {
   }
   // sync 2: where each level starts in the level lists (the leaves are
   // bucket kLevels) and the group count
-  if ((rc = stage_d2h(c, 0, c->red.p, (kLevels + 2) * sizeof(uint32_t))))
+  if ((rc = stage_d2h(c, 0, c->lvl_stage.p, (kLevels + 2) * sizeof(uint32_t))))
     return rc;
   if ((rc = sync(c))) return rc;
   {
@@ -277,12 +278,16 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
   if ((rc = stage_d2h(c, 32, c->tok_off.p + c->n_groups, 8))) return rc;
   if ((rc = stage_d2h(c, 40, c->g_chunks.p + c->n_groups, 4))) return rc;
   if ((rc = stage_d2h(c, 48, c->red.p + 2, 8))) return rc;
+  if ((rc = stage_d2h(c, 144, c->red.p + kRedEpj, 16))) return rc;
   if ((rc = sync(c))) return rc;
   int64_t n_tok, max_tok;
   {
     const uint64_t* h = static_cast<const uint64_t*>(c->h_small);
-    c->n_epj = (int64_t)h[0];
-    c->n_spj = (int64_t)h[1];
+    // list entries; in refresh mode the offsets' totals are the slots'
+    c->cap_e = (int64_t)h[0];
+    c->cap_s = (int64_t)h[1];
+    c->n_epj = (int64_t)h[18];
+    c->n_spj = (int64_t)h[19];
     c->n_inter = (int64_t)h[2];
     max_tok = (int64_t)h[3];
     n_tok = (int64_t)h[4];
@@ -298,8 +303,8 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
     Timed t(c, NB_PH_WALK);
     if ((rc = launch_tail_order(c))) return rc;
   }
-  if ((rc = reserve(c, c->epj, (size_t)c->n_epj + 1))) return rc;
-  if ((rc = reserve(c, c->spj, (size_t)c->n_spj + 1))) return rc;
+  if ((rc = reserve(c, c->epj, (size_t)c->cap_e + 1))) return rc;
+  if ((rc = reserve(c, c->spj, (size_t)c->cap_s + 1))) return rc;
   if (one_pass && max_tok <= (int64_t)slab) {
     Timed t(c, NB_PH_WALK);
     if ((rc = launch_expand_slab(c, slab))) return rc;
@@ -307,6 +312,18 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
     if ((rc = reserve(c, c->tok, (size_t)n_tok + 1))) return rc;
     Timed t(c, NB_PH_WALK);
     if ((rc = launch_walk(c, true))) return rc;
+  }
+  if (c->learn) {
+    // token slabs of the refresh walks (a refreshed list may have twice the
+    // tokens of the largest constructed one), sized here, after the
+    // construction's own tokens have been expanded, so that a refresh step
+    // allocates nothing
+    const int64_t most = ((int64_t)1 << 32) / c->n_groups / 16 * 16;
+    c->refresh_slab = (uint32_t)std::max<int64_t>(
+        16, std::min<int64_t>((2 * max_tok + 64 + 15) / 16 * 16, most));
+    if (c->sel_hint <= 0) c->sel_hint = std::max<int64_t>(1, c->n_groups / 8);
+    if ((rc = reserve(c, c->tok, (size_t)c->n_groups * c->refresh_slab)))
+      return rc;
   }
   c->lists_valid = true;
   c->lists_reusable = mode == NB_MAKE_LIST_FOR_REUSE;
@@ -398,14 +415,17 @@ void nb_destroy(nb_ctx* c) {
   release(c->cnt_e); release(c->cnt_s); release(c->cnt_t);
   release(c->epj_off); release(c->spj_off); release(c->tok_off);
   release(c->epj); release(c->spj); release(c->tok); release(c->lflag);
-  release(c->scan_tmp); release(c->red);
+  release(c->scan_tmp); release(c->red); release(c->lvl_stage);
   release(c->c_com); release(c->c_com0); release(c->c_shift); release(c->c_ctr);
   release(c->c_bmin); release(c->c_bmax);
   release(c->g_clo); release(c->g_chi); release(c->g_tau0);
   release(c->g_sa); release(c->g_so); release(c->g_age);
   release(c->pick); release(c->pickpos); release(c->sel);
-  release(c->ne2); release(c->ns2); release(c->epj_off2); release(c->spj_off2);
-  release(c->epj2); release(c->spj2); release(c->feat); release(c->prob);
+  release(c->ne2); release(c->ns2); release(c->sel_e); release(c->sel_s);
+  release(c->sel_t); release(c->sel_sa); release(c->sel_so);
+  release(c->sel_tau0); release(c->sel_ok); release(c->feat); release(c->prob);
+  release(c->epj_off2); release(c->spj_off2); release(c->epj2);
+  release(c->spj2);
   release(c->stale);
   release(c->mlp_w); release(c->mlp_m); release(c->mlp_v); release(c->mlp_g);
   release(c->mlp_act); release(c->mlp_dz); release(c->mlp_lossp);
@@ -531,7 +551,6 @@ int nb_make_lists(nb_ctx* c, nb_mode mode) {
 int nb_compute_forces(nb_ctx* c, nb_mode mode) {
   if (!c) return NB_ERR_INPUT;
   int rc;
-  c->last_refreshed = 0;
   if (mode == NB_REUSE_LIST || mode == NB_REUSE_REFRESH ||
       mode == NB_REUSE_CHECK) {
     if (!c->have_particles || !c->tree_valid || !c->lists_reusable)
@@ -567,6 +586,10 @@ int nb_compute_forces(nb_ctx* c, nb_mode mode) {
     Timed t(c, NB_PH_FORCE);
     if ((rc = launch_force(c))) return rc;
   }
+  // refresh mode counts on the device (the lists change without the host)
+  if (c->learn &&
+      (rc = launch_accum(c, mode == NB_REUSE_REFRESH || mode == NB_REUSE_CHECK)))
+    return rc;
   c->forces_valid = true;
   c->force_evals += 1;
   c->total_inter += c->n_inter;
@@ -594,19 +617,27 @@ int nb_kick_drift(nb_ctx* c, double dt_kick, double dt_drift) {
 }
 
 // The kernels of one reuse step: kick-drift, moments of the frozen tree,
-// force on the kept lists.
-static int enqueue_reuse_step(nb_ctx* c, double dtk, double dtd) {
+// (refresh mode) the predictor or the exact check and the refresh of the
+// lists it selects, force on the kept lists.  No host synchronisation.
+static int enqueue_reuse_step(nb_ctx* c, nb_mode mode, double dtk,
+                              double dtd) {
   int rc = launch_kick_drift(c, dtk, dtd);
   if (!rc) rc = launch_moments(c);
   if (!rc && c->learn) rc = launch_age_inc(c);
+  if (!rc && mode == NB_REUSE_REFRESH) rc = refresh_predicted(c);
+  if (!rc && mode == NB_REUSE_CHECK) rc = refresh_checked(c);
   if (!rc) rc = launch_force(c);
+  if (!rc && c->learn) rc = launch_accum(c, mode != NB_REUSE_LIST);
   return rc;
 }
 
 int nb_step(nb_ctx* c, nb_mode mode, double dt_kick, double dt_drift) {
   if (!c) return NB_ERR_INPUT;
   const bool graph = (c->cfg.flags & NB_FLAG_GRAPH) != 0;
-  if (!(graph && mode == NB_REUSE_LIST)) {
+  const bool reuse = mode == NB_REUSE_LIST ||
+                     (c->learn && (mode == NB_REUSE_REFRESH ||
+                                   mode == NB_REUSE_CHECK));
+  if (!(graph && reuse)) {
     int rc = nb_kick_drift(c, dt_kick, dt_drift);
     if (!rc) rc = nb_compute_forces(c, mode);
     return rc;
@@ -618,10 +649,16 @@ int nb_step(nb_ctx* c, nb_mode mode, double dt_kick, double dt_drift) {
   if (!c->have_particles || !c->tree_valid || !c->lists_reusable)
     return set_err(c, NB_ERR_STATE,
                    "REUSE_LIST needs lists made with MAKE_LIST_FOR_REUSE");
+  if (mode == NB_REUSE_CHECK && !(c->cfg.theta > 0.0))
+    return set_err(c, NB_ERR_INPUT, "REUSE_CHECK needs theta > 0");
   int rc;
   if (c->graph_exec &&
-      (c->graph_dtk != dt_kick || c->graph_dtd != dt_drift))
+      (c->graph_dtk != dt_kick || c->graph_dtd != dt_drift ||
+       c->graph_mode != (int)mode))
     drop_graph(c);
+  // the perceptron's weights exist before the capture (nothing is allocated
+  // while the stream is captured)
+  if (mode == NB_REUSE_REFRESH && (rc = mlp_ensure(c))) return rc;
   if (!c->graph_exec) {
     // buffers are already sized by the construction step, so nothing is
     // allocated while the stream is being captured
@@ -629,7 +666,7 @@ int nb_step(nb_ctx* c, nb_mode mode, double dt_kick, double dt_drift) {
                                             hipStreamCaptureModeRelaxed),
                    "graph capture");
     if (rc) return rc;
-    const int rq = enqueue_reuse_step(c, dt_kick, dt_drift);
+    const int rq = enqueue_reuse_step(c, mode, dt_kick, dt_drift);
     hipGraph_t gr = nullptr;
     const hipError_t ee = hipStreamEndCapture(c->stream, &gr);
     if (rq) {
@@ -647,6 +684,7 @@ int nb_step(nb_ctx* c, nb_mode mode, double dt_kick, double dt_drift) {
     }
     c->graph_dtk = dt_kick;
     c->graph_dtd = dt_drift;
+    c->graph_mode = (int)mode;
   }
   {
     Timed t(c, NB_PH_GRAPH);
@@ -655,7 +693,6 @@ int nb_step(nb_ctx* c, nb_mode mode, double dt_kick, double dt_drift) {
   }
   if (dt_drift != 0.0) c->positions_fresh = false;
   c->shift_fresh = c->learn;
-  c->last_refreshed = 0;
   c->forces_valid = true;
   c->force_evals += 1;
   c->total_inter += c->n_inter;
@@ -812,21 +849,37 @@ int nb_get_state(nb_ctx* c, double* x, double* y, double* z, double* vx,
 
 int nb_get_info(nb_ctx* c, int64_t* info) {
   if (!c || !info) return NB_ERR_INPUT;
+  // refresh mode: list sizes and the evaluated interactions are counted on
+  // the device (a refresh changes the lists without the host)
+  uint64_t d[kRedCount] = {0};
+  if (c->learn && c->red.p) {
+    int rc = stage_d2h(c, 0, c->red.p, sizeof d);
+    if (!rc) rc = sync(c);
+    if (rc) return rc;
+    std::memcpy(d, c->h_small, sizeof d);
+  }
+  const bool dev = c->learn && c->red.p;
+  // the next refresh walks' lane tiles are sized for the last selection
+  if (dev && d[kRedRefreshed] + d[kRedOverflow] > 0)
+    c->sel_hint = (int64_t)(d[kRedRefreshed] + d[kRedOverflow]);
   info[0] = c->n;
   info[1] = c->tree_valid ? c->n_cell : 0;
   info[2] = c->tree_valid ? c->n_groups : 0;
-  info[3] = c->lists_valid ? c->n_epj : 0;
-  info[4] = c->lists_valid ? c->n_spj : 0;
-  info[5] = c->lists_valid ? c->n_inter : 0;
+  info[3] = c->lists_valid ? (dev ? (int64_t)d[kRedEpj] : c->n_epj) : 0;
+  info[4] = c->lists_valid ? (dev ? (int64_t)d[kRedSpj] : c->n_spj) : 0;
+  info[5] = c->lists_valid ? (dev ? (int64_t)d[kRedInter] : c->n_inter) : 0;
   info[6] = c->force_evals;
-  info[7] = c->total_inter;
+  info[7] = dev ? (int64_t)d[kRedTotInter] : c->total_inter;
   info[8] = c->k;
   info[9] = c->n_wi;
   info[10] = c->n_sys;
-  info[11] = c->last_refreshed;
-  info[12] = c->total_refreshed;
-  info[13] = c->lists_valid ? c->n_inter_spj : 0;
-  info[14] = c->total_inter_spj;
+  info[11] = dev ? (int64_t)d[kRedRefreshed] : 0;
+  info[12] = dev ? (int64_t)d[kRedTotRefreshed] + c->host_refreshed : 0;
+  info[13] = c->lists_valid
+                 ? (dev ? (int64_t)d[kRedInterSpj] : c->n_inter_spj) : 0;
+  info[14] = dev ? (int64_t)d[kRedTotInterSpj] : c->total_inter_spj;
+  info[15] = dev ? (int64_t)d[kRedOverflow] : 0;
+  info[16] = dev ? (int64_t)d[kRedTotOverflow] : 0;
   return NB_OK;
 }
 
@@ -1069,6 +1122,42 @@ int nb_get_lists(nb_ctx* c, int64_t* epj_off, uint32_t* epj,
   if (!c->lists_valid) return set_err(c, NB_ERR_STATE, "no lists");
   const size_t ng = (size_t)c->n_groups;
   int rc = sync(c);
+  if (!rc && c->learn) {
+    // refresh mode: each list sits at the start of a slot with room to grow;
+    // read slots and lengths and pack the lists into CSR
+    std::vector<uint64_t> eo(ng + 1), so(ng + 1);
+    std::vector<uint32_t> ne(ng), ns(ng), e((size_t)c->cap_e + 1),
+        s((size_t)c->cap_s + 1);
+    rc = hip_check(c, hipMemcpy(eo.data(), c->epj_off.p, (ng + 1) * 8,
+                                hipMemcpyDeviceToHost), "list readback");
+    if (!rc) rc = hip_check(c, hipMemcpy(so.data(), c->spj_off.p, (ng + 1) * 8,
+                                         hipMemcpyDeviceToHost), "list readback");
+    if (!rc) rc = hip_check(c, hipMemcpy(ne.data(), c->cnt_e.p, ng * 4,
+                                         hipMemcpyDeviceToHost), "list readback");
+    if (!rc) rc = hip_check(c, hipMemcpy(ns.data(), c->cnt_s.p, ng * 4,
+                                         hipMemcpyDeviceToHost), "list readback");
+    if (!rc && epj) rc = hip_check(c, hipMemcpy(e.data(), c->epj.p,
+                                                (size_t)c->cap_e * 4,
+                                                hipMemcpyDeviceToHost),
+                                   "list readback");
+    if (!rc && spj) rc = hip_check(c, hipMemcpy(s.data(), c->spj.p,
+                                                (size_t)c->cap_s * 4,
+                                                hipMemcpyDeviceToHost),
+                                   "list readback");
+    if (rc) return rc;
+    int64_t oe = 0, os = 0;
+    for (size_t g = 0; g < ng; ++g) {
+      if (epj_off) epj_off[g] = oe;
+      if (spj_off) spj_off[g] = os;
+      if (epj) std::copy(e.begin() + eo[g], e.begin() + eo[g] + ne[g], epj + oe);
+      if (spj) std::copy(s.begin() + so[g], s.begin() + so[g] + ns[g], spj + os);
+      oe += ne[g];
+      os += ns[g];
+    }
+    if (epj_off) epj_off[ng] = oe;
+    if (spj_off) spj_off[ng] = os;
+    return NB_OK;
+  }
   if (!rc && epj_off)
     rc = hip_check(c, hipMemcpy(epj_off, c->epj_off.p, (ng + 1) * 8,
                                 hipMemcpyDeviceToHost), "list readback");

@@ -141,6 +141,10 @@ struct Tiles {
 // same unrolled work per tile as a full group does.  For larger r the
 // largest tile is cut into r near-equal blocks.  The slices' sums are added
 // through LDS at the end, in the tile's space.
+// Lists: group g's particle ids start at epj[epj_off[g]] and number
+// cnt_e[g], its superparticle ids at spj[spj_off[g]], cnt_s[g] of them (the
+// offsets are where the lists start; in refresh mode each group's list has
+// room to grow past its length).
 struct ForceArgs {
   const uint32_t* __restrict__ g_cell;
   const CellRec* __restrict__ rec;
@@ -148,6 +152,8 @@ struct ForceArgs {
   const uint32_t* __restrict__ epj;
   const uint64_t* __restrict__ spj_off;
   const uint32_t* __restrict__ spj;
+  const uint32_t* __restrict__ cnt_e;
+  const uint32_t* __restrict__ cnt_s;
   const double4* __restrict__ pos;
   const double4* __restrict__ pm;
   const float4* __restrict__ quad;
@@ -203,9 +209,9 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
     mi = (float)p.w;
   }
   const uint64_t e0 = A.epj_off[g];
-  const uint32_t ne = (uint32_t)(A.epj_off[g + 1] - e0);
+  const uint32_t ne = A.cnt_e[g];
   const uint64_t s0 = A.spj_off[g];
-  const uint32_t ns = (uint32_t)(A.spj_off[g + 1] - s0);
+  const uint32_t ns = A.cnt_s[g];
 
   float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
   // monopole: both segments; quadrupole: the particle segment here, the
@@ -443,14 +449,13 @@ __device__ inline uint64_t item_cost(uint64_t ne, uint64_t ns, int ni) {
 template <int KMAX, int WS>
 __global__ void __launch_bounds__(256)
 k_group_cost(int64_t n_groups, const uint32_t* __restrict__ g_chunks,
-             const uint4* __restrict__ wi,
-             const uint64_t* __restrict__ epj_off,
-             const uint64_t* __restrict__ spj_off,
+             const uint4* __restrict__ wi, const uint32_t* __restrict__ cnt_e,
+             const uint32_t* __restrict__ cnt_s,
              uint32_t* __restrict__ cost) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_groups) return;
-  const uint64_t ne = epj_off[g + 1] - epj_off[g];
-  const uint64_t ns = spj_off ? spj_off[g + 1] - spj_off[g] : 0;
+  const uint64_t ne = cnt_e[g];
+  const uint64_t ns = cnt_s ? cnt_s[g] : 0u;
   uint64_t sum = 0;
   for (uint32_t w = g_chunks[g]; w < g_chunks[g + 1]; ++w)
     sum += item_cost<KMAX, WS>(ne, ns, (int)wi[w].z);
@@ -489,8 +494,8 @@ __global__ void k_xcd_split(int64_t n_groups, const uint64_t* __restrict__ off,
 template <int KMAX, int WS>
 __global__ void __launch_bounds__(1024)
 k_tail_order(const uint4* __restrict__ wi,
-             const uint64_t* __restrict__ epj_off,
-             const uint64_t* __restrict__ spj_off, XcdPlan plan,
+             const uint32_t* __restrict__ cnt_e,
+             const uint32_t* __restrict__ cnt_s, XcdPlan plan,
              uint32_t* __restrict__ tail) {
   __shared__ uint64_t key[kTailItems];
   const uint32_t x = blockIdx.x;
@@ -501,9 +506,7 @@ k_tail_order(const uint4* __restrict__ wi,
     if (i < n) {
       const uint4 it = wi[s0 + i];
       const uint32_t g = it.x;
-      uint64_t c = item_cost<KMAX, WS>(epj_off[g + 1] - epj_off[g],
-                                       spj_off[g + 1] - spj_off[g],
-                                       (int)it.z);
+      uint64_t c = item_cost<KMAX, WS>(cnt_e[g], cnt_s[g], (int)it.z);
       if (c > 0xFFFFFFFEull) c = 0xFFFFFFFEull;
       k = ((uint64_t)(0xFFFFFFFFu - (uint32_t)c) << 32) | (uint32_t)i;
     }
@@ -718,8 +721,8 @@ ForceFn pick_force(int slices, int waves) {
 }
 
 using CostFn = void (*)(int64_t, const uint32_t*, const uint4*,
-                        const uint64_t*, const uint64_t*, uint32_t*);
-using TailFn = void (*)(const uint4*, const uint64_t*, const uint64_t*,
+                        const uint32_t*, const uint32_t*, uint32_t*);
+using TailFn = void (*)(const uint4*, const uint32_t*, const uint32_t*,
                         XcdPlan, uint32_t*);
 
 template <int WS>
@@ -765,6 +768,8 @@ int launch_force(nb_ctx* c) {
   A.epj = c->epj.p;
   A.spj_off = c->spj_off.p;
   A.spj = c->spj.p;
+  A.cnt_e = c->cnt_e.p;
+  A.cnt_s = c->cnt_s.p;
   A.pos = c->pos.p;
   A.pm = c->c_pm.p;
   A.quad = c->c_quad.p;
@@ -827,8 +832,8 @@ int launch_tail_order(nb_ctx* c) {
   TailFn k = c->cfg.order == 2 ? pick_tail<2>(force_slices(c))
                                 : pick_tail<1>(force_slices(c));
   hipLaunchKernelGGL(k, dim3(8), dim3(1024), 0, c->stream,
-                     (const uint4*)c->wi.p, (const uint64_t*)c->epj_off.p,
-                     (const uint64_t*)c->spj_off.p, plan, t.order.p);
+                     (const uint4*)c->wi.p, (const uint32_t*)c->cnt_e.p,
+                     (const uint32_t*)c->cnt_s.p, plan, t.order.p);
   rc = hip_check(c, hipGetLastError(), "tail order launch");
   if (rc) return rc;
   std::copy(plan.b, plan.b + 9, t.b);
@@ -851,9 +856,8 @@ int launch_xcd_plan(nb_ctx* c, bool neighbours) {
   hipLaunchKernelGGL(k, dim3(grid_for(c->n_groups, 256)), dim3(256), 0,
                      c->stream, c->n_groups, (const uint32_t*)c->g_chunks.p,
                      (const uint4*)c->wi.p,
-                     (const uint64_t*)(neighbours ? c->nb_off.p
-                                                  : c->epj_off.p),
-                     (const uint64_t*)(neighbours ? nullptr : c->spj_off.p),
+                     (const uint32_t*)(neighbours ? c->nb_cnt.p : c->cnt_e.p),
+                     (const uint32_t*)(neighbours ? nullptr : c->cnt_s.p),
                      c->g_cost.p);
   rc = hip_check(c, hipGetLastError(), "group cost launch");
   if (!rc) rc = scan_u32_to_u64(c, c->g_cost.p, c->g_cost_off.p, c->n_groups);

@@ -50,6 +50,35 @@ struct __attribute__((aligned(64))) CellRec {
 // FP64 operations as the tree build, so the opening test is unchanged.
 constexpr uint32_t kWalkCountSat = (1u << 27) - 1u;
 
+// Where a walk writes its per-group counts and, in refresh mode, the state
+// of the walk (opening-test slacks, cell shift): at the group's index, or
+// with slot_state at the walk's slot.  With n_dev the number of groups walked
+// is read on the device (at most the launch's n_walk).
+struct WalkOut {
+  uint32_t* cnt_e;
+  uint32_t* cnt_s;
+  uint32_t* cnt_t;
+  double* sa;
+  double* so;
+  double4* tau0;
+  const uint32_t* n_dev;
+  int slot_state;
+};
+
+// Device counters kept in nb_ctx::red (u64):
+//   0 interactions of the current lists, 1 largest token count of one slab,
+//   2 superparticle interactions of the current lists, 4 / 5 particle and
+//   superparticle entries of the current lists, 6 / 7 groups refreshed and
+//   groups whose refreshed list did not fit, in the last force call,
+//   8 / 9 interactions and superparticle interactions evaluated, 10 / 11
+//   groups refreshed and refreshes that did not fit, summed over force calls
+//   (8-11: refresh mode, where every force call adds to them on the device).
+enum {
+  kRedInter = 0, kRedMaxTok = 1, kRedInterSpj = 2, kRedEpj = 4, kRedSpj = 5,
+  kRedRefreshed = 6, kRedOverflow = 7, kRedTotInter = 8, kRedTotInterSpj = 9,
+  kRedTotRefreshed = 10, kRedTotOverflow = 11, kRedCount = 16
+};
+
 // A device buffer that only grows.
 template <class T>
 struct DBuf {
@@ -138,6 +167,7 @@ struct nb_ctx {
   nb::DBuf<double4> c_pm;    // absolute COM (FP64) and mass: SPJ record
   nb::DBuf<uint32_t> lvl_cells;  // cell ids grouped by level, leaves last
   nb::DBuf<uint32_t> bucket;     // per-block level histograms, scanned
+  nb::DBuf<uint32_t> lvl_stage;  // level starts and group count, for the host
 
   // groups
   nb::DBuf<uint32_t> gflag;  // n_cell + 1, scanned
@@ -178,7 +208,9 @@ struct nb_ctx {
 
   // scan / reduction scratch
   nb::DBuf<uint64_t> scan_tmp;
-  nb::DBuf<uint64_t> red;  // small reductions (interaction count, ...)
+  nb::DBuf<uint64_t> red;  // small reductions and counters (kRed*)
+  const uint64_t* red_zeroed = nullptr;  // red's allocation whose counters
+                                         // were set to zero
   void* h_small = nullptr; // pinned host staging (4 KiB)
 
   // per-group list refresh (NB_FLAG_REFRESH)
@@ -195,12 +227,26 @@ struct nb_ctx {
   nb::DBuf<double> g_sa, g_so;      // opening-test slacks of that walk
   nb::DBuf<uint32_t> g_age;         // reuse steps since that walk
   nb::DBuf<uint32_t> pick, pickpos, sel;  // refresh selection
-  nb::DBuf<uint32_t> ne2, ns2;
+  nb::DBuf<uint32_t> ne2, ns2;              // list slot capacities
+  // a refresh walk's output per selection slot: counts, walk state, and
+  // whether the new list fits the group's slot
+  nb::DBuf<uint32_t> sel_e, sel_s, sel_t;
+  nb::DBuf<double> sel_sa, sel_so;
+  nb::DBuf<double4> sel_tau0;
+  nb::DBuf<uint8_t> sel_ok;
+  // larger list slots, when an explicit refresh outgrows them
   nb::DBuf<uint64_t> epj_off2, spj_off2;
   nb::DBuf<uint32_t> epj2, spj2;
+  // refresh mode: each group's lists sit in a slot with room to grow (the
+  // offsets are the slots' starts, cnt_e / cnt_s the lengths); the totals of
+  // the slots, the token slab of a refresh walk, and the selection size the
+  // walk's lane tiles were last sized for
+  int64_t cap_e = 0, cap_s = 0;
+  uint32_t refresh_slab = 0;
+  int64_t sel_hint = 0;
+  int64_t host_refreshed = 0;  // groups refreshed by nb_refresh_lists
   nb::DBuf<float> feat, prob;       // predictor inputs [G x 12], outputs
   nb::DBuf<uint8_t> stale;          // labels of the last stale walk
-  int64_t last_refreshed = 0, total_refreshed = 0;
   // perceptron: weights, Adam moments, gradient (+ loss), scratch
   nb::DBuf<float> mlp_w, mlp_m, mlp_v, mlp_g;
   nb::DBuf<float> mlp_act, mlp_dz, mlp_lossp, mlp_part, mlp_x, mlp_y;
@@ -210,6 +256,7 @@ struct nb_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   double graph_dtk = 0.0, graph_dtd = 0.0;
+  int graph_mode = -1;
 
   // timing
   std::vector<nb::TimerRec> timers;
@@ -290,6 +337,18 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                     const double4* lo, const double4* hi,
                     const uint64_t* epj_off, const uint64_t* spj_off,
                     uint32_t* epj, uint32_t* spj, uint32_t slab = 0);
+// Refresh walk over up to n_max selected groups (count *o.n_dev on the
+// device): one pass, tokens in slabs of `slab` per slot, lanes per group
+// sized for about `hint` groups; then the expand of the slots with ok[t].
+int launch_walk_refresh(nb_ctx* c, int64_t n_max, const uint32_t* sel,
+                        const double4* lo, const double4* hi, uint32_t slab,
+                        const WalkOut& o, int64_t hint);
+int launch_expand_sel(nb_ctx* c, int64_t n_max, const uint32_t* sel,
+                      uint32_t slab, const uint32_t* cnt_t,
+                      const uint32_t* n_dev, const uint8_t* ok);
+// per-force-call device counters (refresh mode); refresh_step adds the
+// call's refreshed groups, otherwise they are cleared
+int launch_accum(nb_ctx* c, bool refresh_step);
 int launch_expand_slab(nb_ctx* c, uint32_t slab);
 int walk_tile(int64_t n_walk, bool refresh = false);  // lanes per group of the walk
 bool split_walk(const nb_ctx* c, int64_t n_walk);  // kSplitLanes slabs per group
@@ -317,7 +376,7 @@ int mlp_forward(nb_ctx* c, int64_t n, const float* x, float* p);
 int mlp_grad(nb_ctx* c, int64_t n, const float* x, const float* y, float pw);
 int mlp_adam(nb_ctx* c, const float* g, float lr, float b1, float b2,
              float eps);
-int refresh_selected(nb_ctx* c, int64_t n_sel);
+int refresh_selected(nb_ctx* c);
 int refresh_host_sel(nb_ctx* c, int64_t n_sel, const int64_t* sel);
 int refresh_predicted(nb_ctx* c);
 int refresh_checked(nb_ctx* c);

@@ -182,8 +182,8 @@ k_features(int64_t ng, const uint32_t* __restrict__ g_cell,
            const double4* __restrict__ tau0,
            const double4* __restrict__ shift, const double* __restrict__ g_sa,
            const double* __restrict__ g_so, const uint32_t* __restrict__ age,
-           const uint64_t* __restrict__ epj_off,
-           const uint64_t* __restrict__ spj_off, int kmax,
+           const uint32_t* __restrict__ cnt_e,
+           const uint32_t* __restrict__ cnt_s, int kmax,
            float* __restrict__ feat) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ng) return;
@@ -208,8 +208,7 @@ k_features(int64_t ng, const uint32_t* __restrict__ g_cell,
   const double E = sqrt((e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]);
   const double B = sqrt((dt[0] * dt[0] + dt[1] * dt[1]) + dt[2] * dt[2]);
   const double sa = g_sa[g], so = g_so[g];
-  const double nl = (double)((epj_off[g + 1] - epj_off[g]) +
-                             (spj_off[g + 1] - spj_off[g]));
+  const double nl = (double)cnt_e[g] + (double)cnt_s[g];
   const uint32_t ag = age[g];
   float* f = feat + (int64_t)kNF * g;
   f[0] = (float)((double)(ag < (uint32_t)kmax ? ag : (uint32_t)kmax) / kmax);
@@ -238,6 +237,7 @@ k_check_lists(int64_t ng, const double4* __restrict__ clo,
               const double4* __restrict__ ctr,
               const double4* __restrict__ shift,
               const uint64_t* __restrict__ spj_off,
+              const uint32_t* __restrict__ cnt_s,
               const uint32_t* __restrict__ spj, double th,
               uint8_t* __restrict__ stale) {
   const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -245,7 +245,7 @@ k_check_lists(int64_t ng, const double4* __restrict__ clo,
   if (g >= ng) return;
   const double4 lo = clo[g], hi = chi[g];
   bool bad = false;
-  for (uint64_t j0 = spj_off[g], e = spj_off[g + 1]; j0 < e; j0 += 64) {
+  for (uint64_t j0 = spj_off[g], e = j0 + cnt_s[g]; j0 < e; j0 += 64) {
     const uint64_t j = j0 + lane;
     bool b = false;
     if (j < e) {
@@ -308,53 +308,110 @@ k_compact(int64_t ng, const uint32_t* __restrict__ pick,
   if (g < ng && pick[g]) sel[pos[g]] = (uint32_t)g;
 }
 
-// New list lengths: walked counts for refreshed groups (index pos[g] in the
-// selection), kept lengths for the others.
+// A refreshed list replaces the kept one only where it fits: its tokens in
+// the walk's slab, its particle and superparticle ids in the group's list
+// slot (the slots' offsets are CSR, so a slot ends where the next begins).
+// Counts the refreshed groups and those left as they were.
 __global__ void __launch_bounds__(256)
-k_merge_counts(int64_t ng, const uint32_t* __restrict__ pick,
-               const uint32_t* __restrict__ pos,
-               const uint32_t* __restrict__ cnt_e,
-               const uint32_t* __restrict__ cnt_s,
-               const uint64_t* __restrict__ epj_off,
-               const uint64_t* __restrict__ spj_off,
-               uint32_t* __restrict__ ne2, uint32_t* __restrict__ ns2) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ng) return;
-  if (pick[g]) {
-    ne2[g] = cnt_e[pos[g]];
-    ns2[g] = cnt_s[pos[g]];
-  } else {
-    ne2[g] = (uint32_t)(epj_off[g + 1] - epj_off[g]);
-    ns2[g] = (uint32_t)(spj_off[g + 1] - spj_off[g]);
-  }
+k_refresh_fit(int64_t n_max, const uint32_t* __restrict__ n_dev,
+              const uint32_t* __restrict__ sel,
+              const uint32_t* __restrict__ sel_e,
+              const uint32_t* __restrict__ sel_s,
+              const uint32_t* __restrict__ sel_t, uint32_t slab,
+              const uint64_t* __restrict__ epj_off,
+              const uint64_t* __restrict__ spj_off,
+              uint8_t* __restrict__ ok, unsigned long long* __restrict__ red) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_max || t >= (int64_t)*n_dev) return;
+  const uint32_t g = sel[t];
+  const bool fits = sel_t[t] <= slab &&
+                    (uint64_t)sel_e[t] <= epj_off[g + 1] - epj_off[g] &&
+                    (uint64_t)sel_s[t] <= spj_off[g + 1] - spj_off[g];
+  ok[t] = fits ? 1 : 0;
+  atomicAdd(red + (fits ? kRedRefreshed : kRedOverflow), 1ull);
 }
 
-// Kept lists move to their new offsets: one wave per group.
+// Install what fitted: lengths, the walk's slacks and cell shift, the box the
+// list was walked for, age 0.  A group that did not fit keeps its list and
+// state (and stays due: its age keeps growing).
 __global__ void __launch_bounds__(256)
-k_copy_lists(int64_t ng, const uint32_t* __restrict__ pick,
-             const uint64_t* __restrict__ eo, const uint32_t* __restrict__ e,
-             const uint64_t* __restrict__ so, const uint32_t* __restrict__ s,
-             const uint64_t* __restrict__ eo2, uint32_t* __restrict__ e2,
-             const uint64_t* __restrict__ so2, uint32_t* __restrict__ s2) {
-  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (g >= ng || pick[g]) return;
-  const uint64_t a = eo[g], na = eo[g + 1] - a, a2 = eo2[g];
-  for (uint64_t i = lane; i < na; i += 64) e2[a2 + i] = e[a + i];
-  const uint64_t b = so[g], nb = so[g + 1] - b, b2 = so2[g];
-  for (uint64_t i = lane; i < nb; i += 64) s2[b2 + i] = s[b + i];
-}
-
-__global__ void __launch_bounds__(256)
-k_refresh_meta(int64_t ng, const uint32_t* __restrict__ pick,
-               const double4* __restrict__ clo,
-               const double4* __restrict__ chi, double4* __restrict__ lo,
-               double4* __restrict__ hi, uint32_t* __restrict__ age) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ng || !pick[g]) return;
+k_refresh_commit(int64_t n_max, const uint32_t* __restrict__ n_dev,
+                 const uint32_t* __restrict__ sel,
+                 const uint8_t* __restrict__ ok,
+                 const uint32_t* __restrict__ sel_e,
+                 const uint32_t* __restrict__ sel_s,
+                 const double* __restrict__ sel_sa,
+                 const double* __restrict__ sel_so,
+                 const double4* __restrict__ sel_tau0,
+                 const double4* __restrict__ clo,
+                 const double4* __restrict__ chi,
+                 uint32_t* __restrict__ cnt_e, uint32_t* __restrict__ cnt_s,
+                 double* __restrict__ g_sa, double* __restrict__ g_so,
+                 double4* __restrict__ g_tau0, double4* __restrict__ lo,
+                 double4* __restrict__ hi, uint32_t* __restrict__ age) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_max || t >= (int64_t)*n_dev || !ok[t]) return;
+  const uint32_t g = sel[t];
+  cnt_e[g] = sel_e[t];
+  cnt_s[g] = sel_s[t];
+  g_sa[g] = sel_sa[t];
+  g_so[g] = sel_so[t];
+  g_tau0[g] = sel_tau0[t];
   lo[g] = clo[g];
   hi[g] = chi[g];
   age[g] = 0u;
+}
+
+// Slot sizes after a refresh some of whose lists did not fit: every group
+// keeps its slot's size, a group whose walked list did not fit gets twice
+// that list plus 32 entries; the largest token count of the walk goes to
+// red[kRedMaxTok].
+__global__ void __launch_bounds__(256)
+k_slot_sizes(int64_t ng, const uint64_t* __restrict__ epj_off,
+             const uint64_t* __restrict__ spj_off,
+             uint32_t* __restrict__ cap_e, uint32_t* __restrict__ cap_s) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  cap_e[g] = (uint32_t)(epj_off[g + 1] - epj_off[g]);
+  cap_s[g] = (uint32_t)(spj_off[g + 1] - spj_off[g]);
+}
+
+__global__ void __launch_bounds__(256)
+k_slot_grow(int64_t n_max, const uint32_t* __restrict__ n_dev,
+            const uint32_t* __restrict__ sel, const uint8_t* __restrict__ ok,
+            const uint32_t* __restrict__ sel_e,
+            const uint32_t* __restrict__ sel_s,
+            const uint32_t* __restrict__ sel_t, uint32_t* __restrict__ cap_e,
+            uint32_t* __restrict__ cap_s,
+            unsigned long long* __restrict__ red) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_max || t >= (int64_t)*n_dev || ok[t]) return;
+  const uint32_t g = sel[t];
+  const uint32_t e = 2u * sel_e[t] + 32u, s = 2u * sel_s[t] + 32u;
+  if (e > cap_e[g]) cap_e[g] = e;
+  if (s > cap_s[g]) cap_s[g] = s;
+  atomicMax(red + kRedMaxTok, (unsigned long long)sel_t[t]);
+}
+
+// Every group's list from its old slot to its new one (one wave per group).
+__global__ void __launch_bounds__(256)
+k_slot_move(int64_t ng, const uint32_t* __restrict__ cnt_e,
+            const uint32_t* __restrict__ cnt_s,
+            const uint64_t* __restrict__ eo, const uint32_t* __restrict__ e,
+            const uint64_t* __restrict__ so, const uint32_t* __restrict__ s,
+            const uint64_t* __restrict__ eo2, uint32_t* __restrict__ e2,
+            const uint64_t* __restrict__ so2, uint32_t* __restrict__ s2) {
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= ng) return;
+  const uint64_t a = eo[g], a2 = eo2[g], na = cnt_e[g];
+  for (uint64_t i = lane; i < na; i += 64) e2[a2 + i] = e[a + i];
+  const uint64_t b = so[g], b2 = so2[g], nb = cnt_s[g];
+  for (uint64_t i = lane; i < nb; i += 64) s2[b2 + i] = s[b + i];
+}
+
+__global__ void k_zero_u64s(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
 __global__ void __launch_bounds__(256)
@@ -558,6 +615,13 @@ int learn_reserve_groups(nb_ctx* c) {
   if (!rc) rc = reserve(c, c->feat, (size_t)kNF * ng);
   if (!rc) rc = reserve(c, c->prob, ng);
   if (!rc) rc = reserve(c, c->stale, ng);
+  if (!rc) rc = reserve(c, c->sel_e, ng);
+  if (!rc) rc = reserve(c, c->sel_s, ng);
+  if (!rc) rc = reserve(c, c->sel_t, ng);
+  if (!rc) rc = reserve(c, c->sel_sa, ng);
+  if (!rc) rc = reserve(c, c->sel_so, ng);
+  if (!rc) rc = reserve(c, c->sel_tau0, ng);
+  if (!rc) rc = reserve(c, c->sel_ok, ng);
   return rc;
 }
 
@@ -626,8 +690,8 @@ int launch_features(nb_ctx* c) {
                      (const double4*)c->g_tau0.p,
                      (const double4*)c->c_shift.p, (const double*)c->g_sa.p,
                      (const double*)c->g_so.p, (const uint32_t*)c->g_age.p,
-                     (const uint64_t*)c->epj_off.p,
-                     (const uint64_t*)c->spj_off.p, c->cfg.k_max, c->feat.p);
+                     (const uint32_t*)c->cnt_e.p,
+                     (const uint32_t*)c->cnt_s.p, c->cfg.k_max, c->feat.p);
   return hip_check(c, hipGetLastError(), "feature launch");
 }
 
@@ -639,7 +703,8 @@ int launch_stale(nb_ctx* c, double tau) {
                      dim3(256), 0, c->stream, c->n_groups,
                      (const double4*)c->g_clo.p, (const double4*)c->g_chi.p,
                      (const double4*)c->c_ctr.p, (const double4*)c->c_shift.p,
-                     (const uint64_t*)c->spj_off.p, (const uint32_t*)c->spj.p,
+                     (const uint64_t*)c->spj_off.p,
+                     (const uint32_t*)c->cnt_s.p, (const uint32_t*)c->spj.p,
                      th, c->stale.p);
   return hip_check(c, hipGetLastError(), "list check launch");
 }
@@ -765,70 +830,108 @@ int mlp_ensure(nb_ctx* c) {
   return rc;
 }
 
-// Refresh the lists of the groups flagged in c->pick (n_sel of them, ids in
-// c->sel in ascending order, c->pickpos = exclusive scan of c->pick).  The
-// current boxes must be in g_clo / g_chi.  One host synchronisation (list
-// totals).
-int refresh_selected(nb_ctx* c, int64_t n_sel) {
+// Refresh the lists of the groups flagged in c->pick (their ids compacted
+// into c->sel in ascending order, their number at c->pickpos[n_groups] on
+// the device), without waiting for the host: one walk pass over up to all
+// groups' slots (the kernels read the selection size), tokens into slabs of
+// c->refresh_slab per slot; then each refreshed list that fits its group's
+// list slot is expanded into it and installed (k_refresh_fit / k_expand /
+// k_refresh_commit), the others keep their lists; last, the interaction
+// counts of the current lists (device counters).  The current boxes must be
+// in g_clo / g_chi.  Every buffer was sized by the construction step, so a
+// refresh allocates nothing and can be captured in a HIP graph.
+int refresh_selected(nb_ctx* c) {
   const int64_t G = c->n_groups;
-  int rc;
-  c->last_refreshed = n_sel;
-  if (n_sel == 0) return NB_OK;
-  drop_graph(c);
-  // count pass over the selection (counts indexed by selection slot)
-  rc = launch_walk_sel(c, false, n_sel, c->sel.p, c->g_clo.p, c->g_chi.p,
-                       nullptr, nullptr, nullptr, nullptr);
+  const uint32_t* n_dev = c->pickpos.p + G;
+  const uint32_t slab = c->refresh_slab;
+  if (!slab || !c->red.p || (uint64_t)G * slab > c->tok.cap)
+    return set_err(c, NB_ERR_STATE, "refresh buffers not sized");
+  const WalkOut o{c->sel_e.p, c->sel_s.p, c->sel_t.p, c->sel_sa.p,
+                  c->sel_so.p, c->sel_tau0.p, n_dev, 1};
+  int rc = launch_walk_refresh(c, G, c->sel.p, c->g_clo.p, c->g_chi.p, slab,
+                               o, c->sel_hint);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_merge_counts, dim3(grid_for(G, 256)), dim3(256), 0,
-                     c->stream, G, (const uint32_t*)c->pick.p,
-                     (const uint32_t*)c->pickpos.p,
-                     (const uint32_t*)c->cnt_e.p, (const uint32_t*)c->cnt_s.p,
+  unsigned long long* red = reinterpret_cast<unsigned long long*>(c->red.p);
+  hipLaunchKernelGGL(k_zero_u64s, dim3(1), dim3(64), 0, c->stream,
+                     red + kRedRefreshed, 2);
+  hipLaunchKernelGGL(k_refresh_fit, dim3(grid_for(G, 256)), dim3(256), 0,
+                     c->stream, G, n_dev, (const uint32_t*)c->sel.p,
+                     (const uint32_t*)c->sel_e.p, (const uint32_t*)c->sel_s.p,
+                     (const uint32_t*)c->sel_t.p, slab,
                      (const uint64_t*)c->epj_off.p,
+                     (const uint64_t*)c->spj_off.p, c->sel_ok.p, red);
+  rc = hip_check(c, hipGetLastError(), "refresh fit launch");
+  if (!rc) rc = launch_expand_sel(c, G, c->sel.p, slab, c->sel_t.p, n_dev,
+                                  c->sel_ok.p);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_refresh_commit, dim3(grid_for(G, 256)), dim3(256), 0,
+                     c->stream, G, n_dev, (const uint32_t*)c->sel.p,
+                     (const uint8_t*)c->sel_ok.p, (const uint32_t*)c->sel_e.p,
+                     (const uint32_t*)c->sel_s.p, (const double*)c->sel_sa.p,
+                     (const double*)c->sel_so.p,
+                     (const double4*)c->sel_tau0.p, (const double4*)c->g_clo.p,
+                     (const double4*)c->g_chi.p, c->cnt_e.p, c->cnt_s.p,
+                     c->g_sa.p, c->g_so.p, c->g_tau0.p, c->g_lo.p, c->g_hi.p,
+                     c->g_age.p);
+  rc = hip_check(c, hipGetLastError(), "refresh commit launch");
+  if (!rc) rc = launch_interactions(c, c->cnt_e.p, c->cnt_s.p);
+  return rc;
+}
+
+// After a refresh whose lists did not all fit (the selection and its walk's
+// output are still in place): larger slots for those groups, every list
+// moved to its new slot, and a larger token slab if the walk overflowed
+// it.  Synchronises with the host.  Drops a captured graph (the list
+// buffers change).
+static int grow_slots(nb_ctx* c) {
+  const int64_t G = c->n_groups;
+  const uint32_t* n_dev = c->pickpos.p + G;
+  unsigned long long* red = reinterpret_cast<unsigned long long*>(c->red.p);
+  hipLaunchKernelGGL(k_zero_u64s, dim3(1), dim3(64), 0, c->stream,
+                     red + kRedMaxTok, 1);
+  hipLaunchKernelGGL(k_slot_sizes, dim3(grid_for(G, 256)), dim3(256), 0,
+                     c->stream, G, (const uint64_t*)c->epj_off.p,
                      (const uint64_t*)c->spj_off.p, c->ne2.p, c->ns2.p);
-  rc = hip_check(c, hipGetLastError(), "merge launch");
+  hipLaunchKernelGGL(k_slot_grow, dim3(grid_for(G, 256)), dim3(256), 0,
+                     c->stream, G, n_dev, (const uint32_t*)c->sel.p,
+                     (const uint8_t*)c->sel_ok.p, (const uint32_t*)c->sel_e.p,
+                     (const uint32_t*)c->sel_s.p, (const uint32_t*)c->sel_t.p,
+                     c->ne2.p, c->ns2.p, red);
+  int rc = hip_check(c, hipGetLastError(), "slot size launch");
   if (!rc) rc = reserve(c, c->epj_off2, (size_t)G + 1);
   if (!rc) rc = reserve(c, c->spj_off2, (size_t)G + 1);
   if (!rc) rc = scan_u32_to_u64(c, c->ne2.p, c->epj_off2.p, G);
   if (!rc) rc = scan_u32_to_u64(c, c->ns2.p, c->spj_off2.p, G);
-  if (!rc) rc = scan_u32_to_u64(c, c->cnt_t.p, c->tok_off.p, n_sel);
-  if (!rc) rc = launch_interactions(c, c->ne2.p, c->ns2.p);
+  if (!rc) rc = stage_d2h(c, 0, c->epj_off2.p + G, 8);
+  if (!rc) rc = stage_d2h(c, 8, c->spj_off2.p + G, 8);
+  if (!rc) rc = stage_d2h(c, 16, red + kRedMaxTok, 8);
+  if (!rc) rc = sync_stream(c);
   if (rc) return rc;
-  if ((rc = stage_d2h(c, 0, c->epj_off2.p + G, 8))) return rc;
-  if ((rc = stage_d2h(c, 8, c->spj_off2.p + G, 8))) return rc;
-  if ((rc = stage_d2h(c, 16, c->red.p, 8))) return rc;
-  if ((rc = stage_d2h(c, 24, c->tok_off.p + n_sel, 8))) return rc;
-  if ((rc = stage_d2h(c, 32, c->red.p + 2, 8))) return rc;
-  if ((rc = sync_stream(c))) return rc;
   const uint64_t* h = static_cast<const uint64_t*>(c->h_small);
-  const int64_t ne = (int64_t)h[0], ns = (int64_t)h[1];
-  const int64_t n_inter = (int64_t)h[2], n_tok = (int64_t)h[3];
-  c->n_inter_spj = (int64_t)h[4];
-  if ((rc = reserve(c, c->epj2, (size_t)ne + 1))) return rc;
-  if ((rc = reserve(c, c->spj2, (size_t)ns + 1))) return rc;
-  if ((rc = reserve(c, c->tok, (size_t)n_tok + 1))) return rc;
-  rc = launch_walk_sel(c, true, n_sel, c->sel.p, c->g_clo.p, c->g_chi.p,
-                       c->epj_off2.p, c->spj_off2.p, c->epj2.p, c->spj2.p);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_copy_lists, dim3(grid_for(G, 4)), dim3(256), 0,
-                     c->stream, G, (const uint32_t*)c->pick.p,
-                     (const uint64_t*)c->epj_off.p, (const uint32_t*)c->epj.p,
-                     (const uint64_t*)c->spj_off.p, (const uint32_t*)c->spj.p,
-                     (const uint64_t*)c->epj_off2.p, c->epj2.p,
-                     (const uint64_t*)c->spj_off2.p, c->spj2.p);
-  hipLaunchKernelGGL(k_refresh_meta, dim3(grid_for(G, 256)), dim3(256), 0,
-                     c->stream, G, (const uint32_t*)c->pick.p,
-                     (const double4*)c->g_clo.p, (const double4*)c->g_chi.p,
-                     c->g_lo.p, c->g_hi.p, c->g_age.p);
-  rc = hip_check(c, hipGetLastError(), "list copy launch");
-  if (rc) return rc;
+  const int64_t ce = (int64_t)h[0], cs = (int64_t)h[1];
+  const int64_t max_tok = (int64_t)h[2];
+  drop_graph(c);
+  if ((rc = reserve(c, c->epj2, (size_t)ce + 1))) return rc;
+  if ((rc = reserve(c, c->spj2, (size_t)cs + 1))) return rc;
+  hipLaunchKernelGGL(k_slot_move, dim3(grid_for(G, 4)), dim3(256), 0,
+                     c->stream, G, (const uint32_t*)c->cnt_e.p,
+                     (const uint32_t*)c->cnt_s.p, (const uint64_t*)c->epj_off.p,
+                     (const uint32_t*)c->epj.p, (const uint64_t*)c->spj_off.p,
+                     (const uint32_t*)c->spj.p, (const uint64_t*)c->epj_off2.p,
+                     c->epj2.p, (const uint64_t*)c->spj_off2.p, c->spj2.p);
+  if ((rc = hip_check(c, hipGetLastError(), "slot move launch"))) return rc;
   std::swap(c->epj, c->epj2);
   std::swap(c->spj, c->spj2);
   std::swap(c->epj_off, c->epj_off2);
   std::swap(c->spj_off, c->spj_off2);
-  c->n_epj = ne;
-  c->n_spj = ns;
-  c->n_inter = n_inter;
-  c->total_refreshed += n_sel;
+  c->cap_e = ce;
+  c->cap_s = cs;
+  if (max_tok > (int64_t)c->refresh_slab) {
+    const int64_t most = ((int64_t)1 << 32) / G / 16 * 16;
+    c->refresh_slab = (uint32_t)std::min<int64_t>(
+        (2 * max_tok + 64 + 15) / 16 * 16, most);
+    if ((rc = reserve(c, c->tok, (size_t)G * c->refresh_slab))) return rc;
+  }
   return NB_OK;
 }
 
@@ -858,14 +961,34 @@ int refresh_host_sel(nb_ctx* c, int64_t n_sel, const int64_t* sel) {
     rc = hip_check(c, hipGetLastError(), "mark launch");
   }
   if (!rc) rc = scan_u32(c, c->pick.p, c->pickpos.p, G);
-  if (!rc) rc = sync_stream(c);  // the host vector goes out of scope
-  if (!rc) rc = refresh_selected(c, n_sel);
-  return rc;
+  if (rc) return rc;
+  c->sel_hint = n_sel;
+  // a list that does not fit its slot is walked again into a larger one
+  // (the selection's other groups get the same list again)
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    rc = refresh_selected(c);
+    if (!rc) rc = stage_d2h(c, 0, c->red.p + kRedRefreshed, 16);
+    if (!rc) rc = sync_stream(c);  // also: the host vector goes out of scope
+    if (rc) return rc;
+    const uint64_t* done = static_cast<const uint64_t*>(c->h_small);
+    const uint64_t fitted = done[0], missed = done[1];
+    if (!missed) {
+      c->host_refreshed += n_sel;
+      return NB_OK;
+    }
+    if (attempt == 0 && (rc = grow_slots(c))) return rc;
+    if (attempt == 1)
+      return set_err(c, NB_ERR_LIST,
+                     "%llu of %llu refreshed lists did not fit their groups' "
+                     "list slots (those groups keep their lists)",
+                     (unsigned long long)missed,
+                     (unsigned long long)(fitted + missed));
+  }
+  return NB_OK;
 }
 
 // Predictor-driven refresh: features, perceptron, selection p > p* or
-// age >= k_max.  One host synchronisation for the selection size, one more
-// when anything is refreshed.
+// age >= k_max, and the refresh of the selection; no host synchronisation.
 int refresh_predicted(nb_ctx* c) {
   const int64_t G = c->n_groups;
   int rc = mlp_ensure(c);
@@ -883,11 +1006,7 @@ int refresh_predicted(nb_ctx* c) {
                      c->stream, G, (const uint32_t*)c->pick.p,
                      (const uint32_t*)c->pickpos.p, c->sel.p);
   rc = hip_check(c, hipGetLastError(), "compact launch");
-  if (!rc) rc = stage_d2h(c, 0, c->pickpos.p + G, 4);
-  if (!rc) rc = sync_stream(c);
-  if (rc) return rc;
-  const int64_t n_sel = static_cast<const uint32_t*>(c->h_small)[0];
-  return refresh_selected(c, n_sel);
+  return rc ? rc : refresh_selected(c);
 }
 
 // Refresh driven by the exact check at tolerance cfg.tau (or the age).
@@ -906,10 +1025,7 @@ int refresh_checked(nb_ctx* c) {
                      c->stream, G, (const uint32_t*)c->pick.p,
                      (const uint32_t*)c->pickpos.p, c->sel.p);
   rc = hip_check(c, hipGetLastError(), "compact launch");
-  if (!rc) rc = stage_d2h(c, 0, c->pickpos.p + G, 4);
-  if (!rc) rc = sync_stream(c);
-  if (rc) return rc;
-  return refresh_selected(c, static_cast<const uint32_t*>(c->h_small)[0]);
+  return rc ? rc : refresh_selected(c);
 }
 
 int labels_to_float(nb_ctx* c, float* out) {

@@ -819,12 +819,12 @@ int launch_group_flags(nb_ctx* c) {
 }
 
 // Level lists by counting sort; also stages the bucket starts and the group
-// count in c->red (as u32) for the host to read.
+// count in c->lvl_stage for the host to read.
 int launch_level_lists(nb_ctx* c) {
   const int nblk = (int)grid_for(c->n_cell, kBkTile);
   int rc = reserve(c, c->lvl_cells, (size_t)c->n_cell);
   if (!rc) rc = reserve(c, c->bucket, (size_t)kBuckets * nblk + 1);
-  if (!rc) rc = reserve(c, c->red, 16);
+  if (!rc) rc = reserve(c, c->lvl_stage, kLevels + 2);
   if (rc) return rc;
   hipLaunchKernelGGL(k_bucket_hist, dim3(nblk), dim3(kBkThreads), 0,
                      c->stream, c->n_cell, (const CellRec*)c->c_rec.p,
@@ -839,7 +839,7 @@ int launch_level_lists(nb_ctx* c) {
   hipLaunchKernelGGL(k_bucket_starts, dim3(1), dim3(64), 0, c->stream,
                      (const uint32_t*)c->bucket.p, nblk,
                      (const uint32_t*)c->gflag.p, c->n_cell,
-                     reinterpret_cast<uint32_t*>(c->red.p));
+                     c->lvl_stage.p);
   return hip_check(c, hipGetLastError(), "bucket scatter launch");
 }
 

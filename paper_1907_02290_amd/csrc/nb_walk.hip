@@ -56,7 +56,11 @@ constexpr int kExpandBatch = 4;  // 64-token chunks per round of k_expand
 // groups listed in `sel` (all groups when sel is NULL), the centres come
 // from `ctr` (geometric centre carried by the cell's centre-of-mass shift,
 // and rcrit^2) instead of the cell records, and the count pass records the
-// opening-test slacks and the cell shift of the group for the predictor.
+// opening-test slacks and the cell shift of the group for the predictor
+// (at the group's index, or with `slot_state` at the walk's slot t, for a
+// refresh that installs the new list only if it fits).  With `n_dev` the
+// number of groups walked is *n_dev (at most n_walk), read on the device,
+// so that the launch does not wait for the host.
 template <bool FILL, bool LEARN>
 __global__ void __launch_bounds__(kWalkThreads)
 k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
@@ -69,7 +73,8 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
        const uint32_t* __restrict__ seg, const uint32_t* __restrict__ croot,
        uint32_t* __restrict__ cnt_e, uint32_t* __restrict__ cnt_s,
        uint32_t* __restrict__ cnt_t, const uint64_t* __restrict__ tok_off,
-       uint32_t* __restrict__ tok, uint32_t slab) {
+       uint32_t* __restrict__ tok, uint32_t slab,
+       const uint32_t* __restrict__ n_dev, int slot_state) {
   // per-lane staging of the token stream: a lane writes its tokens out one
   // aligned 64-byte segment at a time, so that partially written lines do
   // not pile up in L2 (one open line per group otherwise)
@@ -77,7 +82,7 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   const int64_t blk = xcd_block(nblk);
   if (blk >= nblk) return;
   const int64_t t = blk * kWalkThreads + threadIdx.x;
-  if (t >= n_walk) return;
+  if (t >= n_walk || (n_dev && t >= (int64_t)*n_dev)) return;
   const int64_t g = (LEARN && sel) ? (int64_t)sel[t] : t;
   const uint32_t gb = g_begin[g];
   const uint32_t ge = gb + g_count[g];
@@ -180,9 +185,10 @@ k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
     cnt_s[t] = ns;
     cnt_t[t] = ns + nl;
     if (LEARN) {
-      g_sa[g] = sa;
-      g_so[g] = so;
-      g_tau0[g] = shift[g_cell[g]];
+      const int64_t o = slot_state ? t : g;
+      g_sa[o] = sa;
+      g_so[o] = so;
+      g_tau0[o] = shift[g_cell[g]];
     }
   }
 }
@@ -437,13 +443,15 @@ k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
             const uint32_t* __restrict__ croot, uint32_t* __restrict__ cnt_e,
             uint32_t* __restrict__ cnt_s, uint32_t* __restrict__ cnt_t,
             const uint64_t* __restrict__ tok_off, uint32_t* __restrict__ tok,
-            uint32_t slab) {
+            uint32_t slab, const uint32_t* __restrict__ n_dev,
+            int slot_state) {
   static_assert(W >= 2 && W <= 64 && (W & (W - 1)) == 0, "tile width");
   const int64_t blk = xcd_block(nblk);
   if (blk >= nblk) return;
   const int64_t t = blk * (256 / W) + (threadIdx.x / W);
   const int lane = threadIdx.x & (W - 1);
-  if (t >= n_walk) return;  // uniform over the tile
+  // uniform over the tile
+  if (t >= n_walk || (n_dev && t >= (int64_t)*n_dev)) return;
   const int64_t g = (LEARN && sel) ? (int64_t)sel[t] : t;
   const uint32_t gb = g_begin[g];
   const uint32_t ge = gb + g_count[g];
@@ -549,9 +557,10 @@ k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
       cnt_s[t] = ns;
       cnt_t[t] = ns + nl;
       if (LEARN) {
-        g_sa[g] = sa;
-        g_so[g] = so;
-        g_tau0[g] = shift[g_cell[g]];
+        const int64_t o = slot_state ? t : g;
+        g_sa[o] = sa;
+        g_so[o] = so;
+        g_tau0[o] = shift[g_cell[g]];
       }
     }
   }
@@ -562,7 +571,8 @@ k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
 // ballot, opened leaves are expanded using a wave scan of their sizes, so
 // every chunk lands in contiguous stretches of both lists.
 // Token offsets are per walked group (index t); output offsets per group id
-// (sel[t], or t when sel is NULL).
+// (sel[t], or t when sel is NULL).  With n_dev only the first *n_dev slots
+// are expanded, and with ok only the slots t with ok[t].
 __global__ void __launch_bounds__(256)
 k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
          const uint64_t* __restrict__ tok_off, uint32_t slab,
@@ -571,12 +581,14 @@ k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
          const uint32_t* __restrict__ tok, const CellRec* __restrict__ rec,
          const uint64_t* __restrict__ epj_off,
          const uint64_t* __restrict__ spj_off, uint32_t* __restrict__ epj,
-         uint32_t* __restrict__ spj) {
+         uint32_t* __restrict__ spj, const uint32_t* __restrict__ n_dev,
+         const uint8_t* __restrict__ ok) {
   const int64_t blk = xcd_block(nblk);
   if (blk >= nblk) return;
   const int64_t t = blk * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (t >= n_walk) return;
+  if (t >= n_walk || (n_dev && t >= (int64_t)*n_dev) || (ok && !ok[t]))
+    return;  // uniform over the wave
   const int64_t g = sel ? (int64_t)sel[t] : t;
   // the token stream: one range, or (slab mode of the walk with `lanes`
   // lanes per group, cnt_tl given) the lanes' slabs one after the other
@@ -640,33 +652,68 @@ k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
 }
 
 // Interactions of the lists: sum over groups of n_i * (n_epj + n_spj) into
-// out[0], and of n_i * n_spj (superparticle interactions) into out[2].
+// out[0], of n_i * n_spj (superparticle interactions) into out[2], and the
+// list entries into out[4] (particles) and out[5] (superparticles).
 __global__ void __launch_bounds__(256)
 k_interactions(int64_t n_groups, const uint32_t* __restrict__ g_count,
                const uint32_t* __restrict__ cnt_e,
                const uint32_t* __restrict__ cnt_s,
                unsigned long long* __restrict__ out) {
-  __shared__ unsigned long long s[4], s2[4];
-  unsigned long long v = 0, v2 = 0;
+  __shared__ unsigned long long s[4][4];
+  unsigned long long v[4] = {0, 0, 0, 0};
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
        g < n_groups; g += (int64_t)gridDim.x * blockDim.x) {
-    v += (unsigned long long)g_count[g] *
-         ((unsigned long long)cnt_e[g] + cnt_s[g]);
-    v2 += (unsigned long long)g_count[g] * cnt_s[g];
+    v[0] += (unsigned long long)g_count[g] *
+            ((unsigned long long)cnt_e[g] + cnt_s[g]);
+    v[1] += (unsigned long long)g_count[g] * cnt_s[g];
+    v[2] += cnt_e[g];
+    v[3] += cnt_s[g];
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    v += __shfl_xor(v, o, 64);
-    v2 += __shfl_xor(v2, o, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    s[threadIdx.x >> 6] = v;
-    s2[threadIdx.x >> 6] = v2;
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    if ((threadIdx.x & 63) == 0) s[q][threadIdx.x >> 6] = v[q];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    atomicAdd(out, s[0] + s[1] + s[2] + s[3]);
-    atomicAdd(out + 2, s2[0] + s2[1] + s2[2] + s2[3]);
+    const int dst[4] = {kRedInter, kRedInterSpj, kRedEpj, kRedSpj};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      atomicAdd(out + dst[q], (s[q][0] + s[q][1]) + (s[q][2] + s[q][3]));
+  }
+}
+
+// List slots of refresh mode: twice the list plus the mean list length of
+// the construction (red[kRedEpj] / groups, at least 32), so that short
+// lists can grow to typical ones.
+__global__ void __launch_bounds__(256)
+k_slot_caps(int64_t n_groups, const uint32_t* __restrict__ cnt_e,
+            const uint32_t* __restrict__ cnt_s,
+            const unsigned long long* __restrict__ red,
+            uint32_t* __restrict__ cap_e, uint32_t* __restrict__ cap_s) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_groups) return;
+  const uint64_t me = red[kRedEpj] / (uint64_t)n_groups + 32u;
+  const uint64_t ms = red[kRedSpj] / (uint64_t)n_groups + 32u;
+  const uint64_t ce = 2u * (uint64_t)cnt_e[g] + me;
+  const uint64_t cs = 2u * (uint64_t)cnt_s[g] + ms;
+  cap_e[g] = ce < 0xFFFFFFFFull ? (uint32_t)ce : 0xFFFFFFFFu;
+  cap_s[g] = cs < 0xFFFFFFFFull ? (uint32_t)cs : 0xFFFFFFFFu;
+}
+
+// Per-force-call counters of refresh mode (see kRed*).
+__global__ void k_accum(unsigned long long* __restrict__ red,
+                        int refresh_step) {
+  if (threadIdx.x != 0) return;
+  red[kRedTotInter] += red[kRedInter];
+  red[kRedTotInterSpj] += red[kRedInterSpj];
+  if (refresh_step) {
+    red[kRedTotRefreshed] += red[kRedRefreshed];
+    red[kRedTotOverflow] += red[kRedOverflow];
+  } else {
+    red[kRedRefreshed] = 0ull;
+    red[kRedOverflow] = 0ull;
   }
 }
 
@@ -907,7 +954,8 @@ int walk_tile(int64_t n_walk, bool refresh) {
 template <int W>
 static void tile_launch(nb_ctx* c, bool fill, bool learn, int64_t launch,
                         int64_t n_walk, int64_t nblk, const uint32_t* sel,
-                        const double4* lo, const double4* hi, uint32_t slab) {
+                        const double4* lo, const double4* hi, uint32_t slab,
+                        const WalkOut& o) {
   auto k = fill ? (learn ? k_walk_tile<W, true, true>
                          : k_walk_tile<W, true, false>)
                 : (learn ? k_walk_tile<W, false, true>
@@ -917,26 +965,86 @@ static void tile_launch(nb_ctx* c, bool fill, bool learn, int64_t launch,
                      (const uint32_t*)c->g_count.p, lo, hi,
                      (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
                      (const uint32_t*)c->g_cell.p,
-                     (const double4*)c->c_shift.p, c->g_sa.p, c->g_so.p,
-                     c->g_tau0.p, (const uint32_t*)c->seg.p,
-                     (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
-                     c->cnt_t.p, (const uint64_t*)c->tok_off.p, c->tok.p,
-                     slab);
+                     (const double4*)c->c_shift.p, o.sa, o.so, o.tau0,
+                     (const uint32_t*)c->seg.p, (const uint32_t*)c->croot.p,
+                     o.cnt_e, o.cnt_s, o.cnt_t,
+                     (const uint64_t*)c->tok_off.p, c->tok.p, slab, o.n_dev,
+                     o.slot_state);
 }
 
 static int launch_tile(nb_ctx* c, int w, bool fill, bool learn,
                        int64_t launch, int64_t n_walk, int64_t nblk,
                        const uint32_t* sel, const double4* lo,
-                       const double4* hi, uint32_t slab) {
+                       const double4* hi, uint32_t slab, const WalkOut& o) {
   switch (w) {
-    case 2: tile_launch<2>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
-    case 4: tile_launch<4>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
-    case 8: tile_launch<8>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
-    case 16: tile_launch<16>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
-    case 32: tile_launch<32>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
-    default: tile_launch<64>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab); break;
+    case 2: tile_launch<2>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
+    case 4: tile_launch<4>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
+    case 8: tile_launch<8>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
+    case 16: tile_launch<16>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
+    case 32: tile_launch<32>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
+    default: tile_launch<64>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
   }
   return NB_OK;
+}
+
+static WalkOut group_out(nb_ctx* c) {
+  return WalkOut{c->cnt_e.p, c->cnt_s.p, c->cnt_t.p, c->g_sa.p, c->g_so.p,
+                 c->g_tau0.p, nullptr, 0};
+}
+
+// The refresh-mode walk (LEARN) over up to n_walk selected groups, lanes per
+// group from walk_tile(hint), outputs as o says.
+static int launch_learn_walk(nb_ctx* c, bool fill, int64_t n_walk,
+                             const uint32_t* sel, const double4* lo,
+                             const double4* hi, uint32_t slab,
+                             const WalkOut& o, int64_t hint) {
+  const int w = walk_tile(hint, true);
+  if (w > 1) {
+    const int64_t nblk = grid_for(n_walk, 256 / w);
+    const int64_t launch = (nblk + 7) / 8 * 8;
+    return launch_tile(c, w, fill, true, launch, n_walk, nblk, sel, lo, hi,
+                       slab, o);
+  }
+  const int64_t nblk = grid_for(n_walk, kWalkThreads);
+  const int64_t launch = (nblk + 7) / 8 * 8;
+  auto k = fill ? k_walk<true, true> : k_walk<false, true>;
+  hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
+                     c->stream, n_walk, nblk, sel,
+                     (const uint32_t*)c->g_begin.p,
+                     (const uint32_t*)c->g_count.p, lo, hi,
+                     (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
+                     (const uint32_t*)c->g_cell.p,
+                     (const double4*)c->c_shift.p, o.sa, o.so, o.tau0,
+                     (const uint32_t*)c->seg.p, (const uint32_t*)c->croot.p,
+                     o.cnt_e, o.cnt_s, o.cnt_t, (const uint64_t*)c->tok_off.p,
+                     c->tok.p, slab, o.n_dev, o.slot_state);
+  return NB_OK;
+}
+
+int launch_walk_refresh(nb_ctx* c, int64_t n_max, const uint32_t* sel,
+                        const double4* lo, const double4* hi, uint32_t slab,
+                        const WalkOut& o, int64_t hint) {
+  if (c->n_cell >= (int64_t)kLeafTag)
+    return set_err(c, NB_ERR_INPUT, "too many cells for 31-bit list tokens");
+  if (n_max <= 0) return NB_OK;
+  int rc = launch_learn_walk(c, true, n_max, sel, lo, hi, slab, o, hint);
+  return rc ? rc : hip_check(c, hipGetLastError(), "refresh walk launch");
+}
+
+int launch_expand_sel(nb_ctx* c, int64_t n_max, const uint32_t* sel,
+                      uint32_t slab, const uint32_t* cnt_t,
+                      const uint32_t* n_dev, const uint8_t* ok) {
+  if (n_max <= 0) return NB_OK;
+  const int64_t eblk = grid_for(n_max, 4);
+  const int64_t elaunch = (eblk + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_expand, dim3((unsigned)elaunch), dim3(256), 0,
+                     c->stream, n_max, eblk, sel, (const uint64_t*)nullptr,
+                     slab, cnt_t, (const uint32_t*)nullptr, 1,
+                     (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
+                     (const uint64_t*)c->epj_off.p,
+                     (const uint64_t*)c->spj_off.p, c->epj.p, c->spj.p, n_dev,
+                     ok);
+  return hip_check(c, hipGetLastError(), "refresh expand launch");
 }
 
 int launch_walk(nb_ctx* c, bool fill, uint32_t slab) {
@@ -965,7 +1073,8 @@ int launch_expand_slab(nb_ctx* c, uint32_t slab) {
                      kSplitLanes, (const uint32_t*)c->tok.p,
                      (const CellRec*)c->c_rec.p,
                      (const uint64_t*)c->epj_off.p,
-                     (const uint64_t*)c->spj_off.p, c->epj.p, c->spj.p);
+                     (const uint64_t*)c->spj_off.p, c->epj.p, c->spj.p,
+                     (const uint32_t*)nullptr, (const uint8_t*)nullptr);
   return hip_check(c, hipGetLastError(), "expand launch");
 }
 
@@ -983,13 +1092,17 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
   if (!learn && sel) return set_err(c, NB_ERR_STATE, "selected walk needs refresh mode");
   const int w = walk_tile(n_walk, learn);
   c->walk_split = split_walk(c, n_walk);
-  if (w > 1) {
+  if (learn) {
+    rc = launch_learn_walk(c, fill, n_walk, sel, lo, hi, slab, group_out(c),
+                           n_walk);
+    if (rc) return rc;
+  } else if (w > 1) {
     const int64_t nblk = grid_for(n_walk, 256 / w);
     const int64_t launch = (nblk + 7) / 8 * 8;
     rc = launch_tile(c, w, fill, learn, launch, n_walk, nblk, sel, lo, hi,
-                     slab);
+                     slab, group_out(c));
     if (rc) return rc;
-  } else if (!learn) {
+  } else {
     // kSplitLanes lanes per group
     if ((rc = reserve(c, c->cnt_tl, (size_t)kSplitLanes * n_walk))) return rc;
     const int64_t nblk = grid_for(kSplitLanes * n_walk, kWalkThreads);
@@ -1006,21 +1119,6 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                        (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
                        c->cnt_t.p, c->cnt_tl.p, (const uint64_t*)c->tok_off.p,
                        c->tok.p, slab);
-  } else {
-    const int64_t nblk = grid_for(n_walk, kWalkThreads);
-    const int64_t launch = (nblk + 7) / 8 * 8;
-    auto k = fill ? k_walk<true, true> : k_walk<false, true>;
-    hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
-                       c->stream, n_walk, nblk, sel,
-                       (const uint32_t*)c->g_begin.p,
-                       (const uint32_t*)c->g_count.p, lo, hi,
-                       (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
-                       (const uint32_t*)c->g_cell.p,
-                       (const double4*)c->c_shift.p, c->g_sa.p, c->g_so.p,
-                       c->g_tau0.p, (const uint32_t*)c->seg.p,
-                       (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
-                       c->cnt_t.p, (const uint64_t*)c->tok_off.p, c->tok.p,
-                       slab);
   }
   int rc2 = hip_check(c, hipGetLastError(), "walk launch");
   if (rc2 || !fill || slab) return rc2;
@@ -1031,16 +1129,31 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
                      (const uint64_t*)c->tok_off.p, 0u,
                      (const uint32_t*)c->cnt_t.p, (const uint32_t*)nullptr, 1,
                      (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
-                     epj_off, spj_off, epj, spj);
+                     epj_off, spj_off, epj, spj, (const uint32_t*)nullptr,
+                     (const uint8_t*)nullptr);
   return hip_check(c, hipGetLastError(), "expand launch");
 }
 
-// After the count pass: CSR offsets and the interaction count (red[0]).
+// After the count pass: CSR offsets and the interaction count (red[0]).  In
+// refresh mode the offsets are those of list slots with room to grow.
 int launch_list_stats(nb_ctx* c) {
-  int rc = scan_u32_to_u64(c, c->cnt_e.p, c->epj_off.p, c->n_groups);
-  if (!rc) rc = scan_u32_to_u64(c, c->cnt_s.p, c->spj_off.p, c->n_groups);
+  int rc = launch_interactions(c, c->cnt_e.p, c->cnt_s.p);
+  if (rc) return rc;
+  if (c->learn) {
+    hipLaunchKernelGGL(k_slot_caps, dim3(grid_for(c->n_groups, 256)),
+                       dim3(256), 0, c->stream, c->n_groups,
+                       (const uint32_t*)c->cnt_e.p,
+                       (const uint32_t*)c->cnt_s.p,
+                       (const unsigned long long*)c->red.p, c->ne2.p,
+                       c->ns2.p);
+    rc = hip_check(c, hipGetLastError(), "slot launch");
+    if (!rc) rc = scan_u32_to_u64(c, c->ne2.p, c->epj_off.p, c->n_groups);
+    if (!rc) rc = scan_u32_to_u64(c, c->ns2.p, c->spj_off.p, c->n_groups);
+  } else {
+    rc = scan_u32_to_u64(c, c->cnt_e.p, c->epj_off.p, c->n_groups);
+    if (!rc) rc = scan_u32_to_u64(c, c->cnt_s.p, c->spj_off.p, c->n_groups);
+  }
   if (!rc) rc = scan_u32_to_u64(c, c->cnt_t.p, c->tok_off.p, c->n_groups);
-  if (!rc) rc = launch_interactions(c, c->cnt_e.p, c->cnt_s.p);
   if (rc) return rc;
   unsigned nb = grid_for(c->n_groups, 256);
   if (nb > 1024) nb = 1024;
@@ -1053,13 +1166,23 @@ int launch_list_stats(nb_ctx* c) {
   return hip_check(c, hipGetLastError(), "list max launch");
 }
 
+int launch_accum(nb_ctx* c, bool refresh_step) {
+  hipLaunchKernelGGL(k_accum, dim3(1), dim3(64), 0, c->stream,
+                     (unsigned long long*)c->red.p, refresh_step ? 1 : 0);
+  return hip_check(c, hipGetLastError(), "counter launch");
+}
+
 // Interaction counts of per-group list lengths ne, ns into red[0] (all)
-// and red[2] (superparticles).
+// and red[2] (superparticles), the lengths' sums into red[4] and red[5].
 int launch_interactions(nb_ctx* c, const uint32_t* ne, const uint32_t* ns) {
-  int rc = reserve(c, c->red, 16);
+  int rc = reserve(c, c->red, kRedCount);
   if (rc) return rc;
+  // the persistent counters start at zero once per allocation
+  const bool fresh = c->red_zeroed != c->red.p;
+  c->red_zeroed = c->red.p;
+  // counters 0-5 describe the current lists; 6-11 persist (all start at 0)
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream,
-                     (unsigned long long*)c->red.p, 3);
+                     (unsigned long long*)c->red.p, fresh ? kRedCount : 6);
   unsigned nb = grid_for(c->n_groups, 256);
   if (nb > 1024) nb = 1024;
   hipLaunchKernelGGL(k_interactions, dim3(nb), dim3(256), 0, c->stream,
@@ -1129,7 +1252,8 @@ int launch_nbr_fill(nb_ctx* c, double h) {
                      1, (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
                      (const uint64_t*)c->nb_off.p,
                      (const uint64_t*)c->nb_off.p, c->nb_ids.p,
-                     (uint32_t*)nullptr);
+                     (uint32_t*)nullptr, (const uint32_t*)nullptr,
+                     (const uint8_t*)nullptr);
   return hip_check(c, hipGetLastError(), "neighbour expand launch");
 }
 

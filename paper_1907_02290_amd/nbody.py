@@ -284,12 +284,12 @@ class Context:
         return tuple(out)
 
     def get_info(self):
-        a = np.zeros(15, dtype=np.int64)
+        a = np.zeros(17, dtype=np.int64)
         self._chk(self._lib.nb_get_info(self._h, _ptr(a)))
         keys = ("n", "n_cell", "n_groups", "n_epj", "n_spj", "n_inter",
                 "force_evals", "total_inter", "k", "n_wi", "n_sys",
                 "last_refreshed", "total_refreshed", "n_inter_spj",
-                "total_inter_spj")
+                "total_inter_spj", "last_overflow", "total_overflow")
         return {k: int(v) for k, v in zip(keys, a)}
 
     def get_root(self):

@@ -109,3 +109,71 @@ def test_graph_with_batched_systems():
                          orc.step(g.get_state(),
                                   mode == nb.NB_MAKE_LIST_FOR_REUSE),
                          what="batch step %d" % step)
+
+
+@pytest.mark.parametrize("mode", ["check", "refresh"])
+def test_graph_replays_refresh_steps(mode):
+    """Refresh mode: NB_REUSE_CHECK / NB_REUSE_REFRESH steps, whose
+    selection, walk and in-place list refresh run without the host, are
+    captured in a HIP graph; every replay gives exactly the eager steps'
+    lists, forces, state and counts (readbacks between replays), across a
+    construction step.  With the exact check (pure drifts, so the oracle
+    follows the positions) the lists after every step are the oracle's
+    refresh of the groups it flags at tau or by age."""
+    from test_gpu_learn import THETA, drift, sheared
+    print("case graph refresh mode %s" % mode, flush=True)
+    d = sheared(6000, 5)
+    dt, tau, k_max = 1 / 64, 0.05, 5
+    nbm = nb.NB_REUSE_CHECK if mode == "check" else nb.NB_REUSE_REFRESH
+    rng = np.random.default_rng(3)
+    w = (rng.standard_normal(nb.MLP_NPARAM) * 0.3).astype(np.float32)
+    ctxs = []
+    for graph in (True, False):
+        c = nb.Context(theta=THETA, eps=0.01, n_leaf=8, n_grp=32,
+                       refresh=True, tau=tau, k_max=k_max, p_star=0.5,
+                       graph=graph)
+        c.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
+                        d["m"])
+        c.mlp_set(w)
+        ctxs.append(c)
+    g, e = ctxs
+    t = oracle.Tree(d["x"], d["y"], d["z"], d["m"], 8, 32)
+    t.make_lists(THETA)
+    age = np.zeros(t.n_groups, int)
+    with g, e:
+        for c in (g, e):
+            c.compute_forces(nb.NB_MAKE_LIST_FOR_REUSE)
+        refreshed = 0
+        for s in range(1, 9):
+            for c in (g, e):
+                c.step(nbm, 0.0, dt)
+            ig, ie = g.get_info(), e.get_info()
+            for k in ("n_epj", "n_spj", "n_inter", "last_refreshed",
+                      "total_refreshed", "total_inter", "last_overflow"):
+                assert ig[k] == ie[k], (s, k, ig[k], ie[k])
+            assert ig["last_overflow"] == 0
+            refreshed += ig["last_refreshed"]
+            for a, b in zip(g.get_lists(), e.get_lists()):
+                np.testing.assert_array_equal(a, b, err_msg="step %d" % s)
+            for a, b in zip(g.get_forces(internal=True),
+                            e.get_forces(internal=True)):
+                np.testing.assert_array_equal(a, b, err_msg="step %d" % s)
+            for a, b in zip(g.get_state(internal=True),
+                            e.get_state(internal=True)):
+                np.testing.assert_array_equal(a, b, err_msg="step %d" % s)
+            if mode == "check":
+                x, y, z = drift(d, dt, s)
+                t.refresh(x, y, z, d["m"])
+                age += 1
+                sel = np.flatnonzero(t.stale(THETA, tau)[0] | (age >= k_max))
+                t.refresh_lists(THETA, sel)
+                age[sel] = 0
+                assert ig["last_refreshed"] == sel.size
+                eo, ev, so, sv = g.get_lists()
+                oeo, oe, oso, os_ = t.lists()
+                np.testing.assert_array_equal(eo, oeo)
+                np.testing.assert_array_equal(ev, oe)
+                np.testing.assert_array_equal(so, oso)
+                np.testing.assert_array_equal(sv, os_)
+        assert refreshed > 0
+        assert g.get_info()["total_refreshed"] == refreshed
