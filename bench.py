@@ -322,14 +322,15 @@ def policies_main(args):
     for policy, k, th in runs:
         kw = dict(common, theta=th)
         if policy == "fixed":
-            ctx = nb.Context(**kw)
+            ctx = nb.Context(graph=args.graph, **kw)
             ctx.set_particles(d1["x"], d1["y"], d1["z"], d1["vx"], d1["vy"],
                               d1["vz"], d1["m"])
             if "offsets" in d1:
                 ctx.set_systems(d1["offsets"])
         else:
             ctx = learn.make_context(d1, k_max=k, p_star=p_star, tau=tau,
-                                     offsets=d1.get("offsets"), **kw)
+                                     offsets=d1.get("offsets"),
+                                     graph=args.graph, **kw)
             ctx.mlp_set(w)
         with ctx:
             r = learn.run_policy(ctx, policy, steps, dt, k, check=check,
@@ -347,6 +348,7 @@ def policies_main(args):
         results.append(r)
     out = dict(kind="policies", workload=wl, n=int(d1["x"].size),
                steps=steps, dt=dt, tau=tau, rebuild_frac=args.rebuild_frac,
+               graph=bool(args.graph),
                n_grp=n_grp, n_leaf=n_leaf, training=train,
                error_reference="FP64 oracle direct sum over each particle's "
                                "system, %d sampled targets"

@@ -196,10 +196,12 @@ int nb_make_lists(nb_ctx* ctx, nb_mode mode);
  * computes the predictor inputs of every group (nb_group_features), runs
  * the perceptron and walks again every group with p > cfg.p_star or
  * age >= cfg.k_max, without synchronising with the host.  In refresh mode
- * each group's lists sit in a slot with room for twice the constructed
- * length plus 32 entries; a walked-again list replaces the kept one in
- * place when it fits its slot (and its token slab), otherwise the group
- * keeps its list and age, and is counted in info[15] (nb_get_info).
+ * each group's lists sit in a slot with room for three times the
+ * constructed length plus the mean list length, and each of the 4 lanes of
+ * its walk has room for twice its tokens at construction plus 32; a
+ * walked-again list replaces the kept one in place when it fits both,
+ * otherwise the group keeps its list and age, and is counted in info[15]
+ * (nb_get_info).
  * NB_REUSE_CHECK does the same with the exact staleness check at tolerance
  * cfg.tau (nb_group_stale) in place of the predictor.
  * Errors: NB_ERR_STATE (REUSE_LIST without reusable lists or after
@@ -411,10 +413,13 @@ int nb_group_stale(nb_ctx* ctx, double tau, uint8_t* stale, float* label,
 
 /* Walk again the lists of the n_sel groups listed in sel (host array of
  * ascending group ids) with their current boxes and centres; other lists
- * are kept.  Sets those groups' box, shift, slacks and age (0).  A new list
- * that does not fit its group's list slot (see nb_compute_forces) is not
- * installed: that group keeps its list and state, and the call returns
- * NB_ERR_LIST after installing the others.  Synchronises the stream.
+ * are kept.  Sets those groups' box, shift, slacks and age (0).  When a new
+ * list does not fit its group's room (see nb_compute_forces), the rooms of
+ * those groups grow to twice the new list (every list moves to its new
+ * slot) and the selection is walked again; a list that still does not fit
+ * is not installed: that group keeps its list and state, and the call
+ * returns NB_ERR_LIST after installing the others.  Synchronises the
+ * stream.
  * Errors: NB_ERR_INPUT (ids not ascending or out of range), NB_ERR_LIST. */
 int nb_refresh_lists(nb_ctx* ctx, int64_t n_sel, const int64_t* sel);
 

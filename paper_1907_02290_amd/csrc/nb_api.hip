@@ -279,6 +279,9 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
   if ((rc = stage_d2h(c, 40, c->g_chunks.p + c->n_groups, 4))) return rc;
   if ((rc = stage_d2h(c, 48, c->red.p + 2, 8))) return rc;
   if ((rc = stage_d2h(c, 144, c->red.p + kRedEpj, 16))) return rc;
+  if (c->learn && (rc = stage_d2h(c, 160, c->lane_off.p +
+                                               kSplitLanes * c->n_groups, 8)))
+    return rc;
   if ((rc = sync(c))) return rc;
   int64_t n_tok, max_tok;
   {
@@ -294,6 +297,7 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
     c->n_inter_spj = (int64_t)h[6];
     c->n_wi = static_cast<const uint32_t*>(c->h_small)[10];
     for (int x = 0; x <= 8; ++x) c->xcd_b[x] = (int64_t)h[8 + x];
+    if (c->learn) c->lane_total = (int64_t)h[20];
   }
   // slab for the next construction: 1.25 x the largest token count of one
   // slab (a group's, or one lane's of a split walk), 16-aligned
@@ -313,18 +317,10 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
     Timed t(c, NB_PH_WALK);
     if ((rc = launch_walk(c, true))) return rc;
   }
-  if (c->learn) {
-    // token slabs of the refresh walks (a refreshed list may have twice the
-    // tokens of the largest constructed one), sized here, after the
-    // construction's own tokens have been expanded, so that a refresh step
-    // allocates nothing
-    const int64_t most = ((int64_t)1 << 32) / c->n_groups / 16 * 16;
-    c->refresh_slab = (uint32_t)std::max<int64_t>(
-        16, std::min<int64_t>((2 * max_tok + 64 + 15) / 16 * 16, most));
-    if (c->sel_hint <= 0) c->sel_hint = std::max<int64_t>(1, c->n_groups / 8);
-    if ((rc = reserve(c, c->tok, (size_t)c->n_groups * c->refresh_slab)))
-      return rc;
-  }
+  // the refresh walks' token room, sized here, after the construction's
+  // own tokens have been expanded, so that a refresh step allocates nothing
+  if (c->learn && (rc = reserve(c, c->tok, (size_t)c->lane_total + 1)))
+    return rc;
   c->lists_valid = true;
   c->lists_reusable = mode == NB_MAKE_LIST_FOR_REUSE;
   return NB_OK;
@@ -426,6 +422,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->sel_tau0); release(c->sel_ok); release(c->feat); release(c->prob);
   release(c->epj_off2); release(c->spj_off2); release(c->epj2);
   release(c->spj2);
+  release(c->lane_cap); release(c->lane_off); release(c->lane_off2);
   release(c->stale);
   release(c->mlp_w); release(c->mlp_m); release(c->mlp_v); release(c->mlp_g);
   release(c->mlp_act); release(c->mlp_dz); release(c->mlp_lossp);
@@ -859,9 +856,6 @@ int nb_get_info(nb_ctx* c, int64_t* info) {
     std::memcpy(d, c->h_small, sizeof d);
   }
   const bool dev = c->learn && c->red.p;
-  // the next refresh walks' lane tiles are sized for the last selection
-  if (dev && d[kRedRefreshed] + d[kRedOverflow] > 0)
-    c->sel_hint = (int64_t)(d[kRedRefreshed] + d[kRedOverflow]);
   info[0] = c->n;
   info[1] = c->tree_valid ? c->n_cell : 0;
   info[2] = c->tree_valid ? c->n_groups : 0;
@@ -1109,6 +1103,7 @@ int nb_upload_lists(nb_ctx* c, int64_t n_groups, const int64_t* epj_off,
     c->n_inter_spj = (int64_t)h[6];
     c->n_wi = static_cast<const uint32_t*>(c->h_small)[10];
     for (int x = 0; x <= 8; ++x) c->xcd_b[x] = (int64_t)h[8 + x];
+    if (c->learn) c->lane_total = (int64_t)h[20];
   }
   if ((rc = launch_tail_order(c))) return rc;
   c->lists_valid = true;

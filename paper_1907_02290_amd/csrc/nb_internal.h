@@ -18,6 +18,8 @@ constexpr int kLevels = kMaxLevel + 1;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 // lanes per group of the gravity walk over many groups (2, 4 or 8)
 constexpr int kSplitLanes = 4;
+// Spare tokens of a refresh-walk lane beyond twice its construction count.
+constexpr uint32_t kLaneSpare = 32;
 
 // Root cell of the last construction step, resident on the device.
 struct Root {
@@ -50,10 +52,10 @@ struct __attribute__((aligned(64))) CellRec {
 // FP64 operations as the tree build, so the opening test is unchanged.
 constexpr uint32_t kWalkCountSat = (1u << 27) - 1u;
 
-// Where a walk writes its per-group counts and, in refresh mode, the state
-// of the walk (opening-test slacks, cell shift): at the group's index, or
-// with slot_state at the walk's slot.  With n_dev the number of groups walked
-// is read on the device (at most the launch's n_walk).
+// Where a refresh-mode walk writes its per-slot counts and the state of the
+// walk (opening-test slacks, cell shift): slot t is group t of a
+// construction walk or group sel[t] of a refresh.  With n_dev the number
+// of slots walked is read on the device (at most the launch's n_walk).
 struct WalkOut {
   uint32_t* cnt_e;
   uint32_t* cnt_s;
@@ -62,7 +64,6 @@ struct WalkOut {
   double* so;
   double4* tau0;
   const uint32_t* n_dev;
-  int slot_state;
 };
 
 // Device counters kept in nb_ctx::red (u64):
@@ -239,11 +240,15 @@ struct nb_ctx {
   nb::DBuf<uint32_t> epj2, spj2;
   // refresh mode: each group's lists sit in a slot with room to grow (the
   // offsets are the slots' starts, cnt_e / cnt_s the lengths); the totals of
-  // the slots, the token slab of a refresh walk, and the selection size the
-  // walk's lane tiles were last sized for
+  // the slots
   int64_t cap_e = 0, cap_s = 0;
-  uint32_t refresh_slab = 0;
-  int64_t sel_hint = 0;
+  // refresh mode: room for the tokens of each lane of a refresh walk
+  // (kSplitLanes per group, by group id: CSR offsets into tok, twice the
+  // lane's tokens at construction plus kLaneSpare, 16-aligned), and its
+  // total
+  nb::DBuf<uint32_t> lane_cap;
+  nb::DBuf<uint64_t> lane_off, lane_off2;
+  int64_t lane_total = 0;
   int64_t host_refreshed = 0;  // groups refreshed by nb_refresh_lists
   nb::DBuf<float> feat, prob;       // predictor inputs [G x 12], outputs
   nb::DBuf<uint8_t> stale;          // labels of the last stale walk
@@ -333,24 +338,27 @@ int launch_group_fill(nb_ctx* c);
 int launch_group_box(nb_ctx* c, double4* lo, double4* hi);
 // nb_walk.hip
 int launch_walk(nb_ctx* c, bool fill, uint32_t slab = 0);
-int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
-                    const double4* lo, const double4* hi,
-                    const uint64_t* epj_off, const uint64_t* spj_off,
-                    uint32_t* epj, uint32_t* spj, uint32_t slab = 0);
+int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const double4* lo,
+                    const double4* hi, const uint64_t* epj_off,
+                    const uint64_t* spj_off, uint32_t* epj, uint32_t* spj,
+                    uint32_t slab = 0);
 // Refresh walk over up to n_max selected groups (count *o.n_dev on the
-// device): one pass, tokens in slabs of `slab` per slot, lanes per group
-// sized for about `hint` groups; then the expand of the slots with ok[t].
+// device), kSplitLanes lanes per group, one pass: each lane's tokens into
+// its group's lane range (lane_off), its count into cnt_tl (per slot).
 int launch_walk_refresh(nb_ctx* c, int64_t n_max, const uint32_t* sel,
-                        const double4* lo, const double4* hi, uint32_t slab,
-                        const WalkOut& o, int64_t hint);
+                        const double4* lo, const double4* hi,
+                        const WalkOut& o);
+// Expand of a refresh walk's slots t with ok[t] into their groups' lists.
 int launch_expand_sel(nb_ctx* c, int64_t n_max, const uint32_t* sel,
-                      uint32_t slab, const uint32_t* cnt_t,
                       const uint32_t* n_dev, const uint8_t* ok);
+// Room of each refresh-walk lane from the construction walk's lane counts
+// (lane_cap, then its scan into lane_off; total at lane_off[G S]).
+int launch_lane_room(nb_ctx* c);
 // per-force-call device counters (refresh mode); refresh_step adds the
 // call's refreshed groups, otherwise they are cleared
 int launch_accum(nb_ctx* c, bool refresh_step);
 int launch_expand_slab(nb_ctx* c, uint32_t slab);
-int walk_tile(int64_t n_walk, bool refresh = false);  // lanes per group of the walk
+int walk_tile(int64_t n_walk);  // lanes per tile of the walk (1: split)
 bool split_walk(const nb_ctx* c, int64_t n_walk);  // kSplitLanes slabs per group
 int launch_list_stats(nb_ctx* c);
 // short-range walk: count pass (nb_cnt, nb_tcnt and their scans) and, with

@@ -308,25 +308,30 @@ k_compact(int64_t ng, const uint32_t* __restrict__ pick,
   if (g < ng && pick[g]) sel[pos[g]] = (uint32_t)g;
 }
 
-// A refreshed list replaces the kept one only where it fits: its tokens in
-// the walk's slab, its particle and superparticle ids in the group's list
-// slot (the slots' offsets are CSR, so a slot ends where the next begins).
-// Counts the refreshed groups and those left as they were.
+// A refreshed list replaces the kept one only where it fits: the tokens of
+// each walk lane in the lane's room (lane_off, by group), its particle and
+// superparticle ids in the group's list slot (the slots' offsets are CSR,
+// so a slot ends where the next begins).  Counts the refreshed groups and
+// those left as they were.
 __global__ void __launch_bounds__(256)
 k_refresh_fit(int64_t n_max, const uint32_t* __restrict__ n_dev,
               const uint32_t* __restrict__ sel,
               const uint32_t* __restrict__ sel_e,
               const uint32_t* __restrict__ sel_s,
-              const uint32_t* __restrict__ sel_t, uint32_t slab,
+              const uint32_t* __restrict__ sel_tl,
+              const uint64_t* __restrict__ lane_off,
               const uint64_t* __restrict__ epj_off,
               const uint64_t* __restrict__ spj_off,
               uint8_t* __restrict__ ok, unsigned long long* __restrict__ red) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_max || t >= (int64_t)*n_dev) return;
   const uint32_t g = sel[t];
-  const bool fits = sel_t[t] <= slab &&
-                    (uint64_t)sel_e[t] <= epj_off[g + 1] - epj_off[g] &&
-                    (uint64_t)sel_s[t] <= spj_off[g + 1] - spj_off[g];
+  bool fits = (uint64_t)sel_e[t] <= epj_off[g + 1] - epj_off[g] &&
+              (uint64_t)sel_s[t] <= spj_off[g + 1] - spj_off[g];
+  for (int h = 0; h < kSplitLanes; ++h) {
+    const uint64_t* r = lane_off + (uint64_t)g * kSplitLanes + h;
+    fits = fits && (uint64_t)sel_tl[(uint64_t)t * kSplitLanes + h] <= r[1] - r[0];
+  }
   ok[t] = fits ? 1 : 0;
   atomicAdd(red + (fits ? kRedRefreshed : kRedOverflow), 1ull);
 }
@@ -362,18 +367,24 @@ k_refresh_commit(int64_t n_max, const uint32_t* __restrict__ n_dev,
   age[g] = 0u;
 }
 
-// Slot sizes after a refresh some of whose lists did not fit: every group
-// keeps its slot's size, a group whose walked list did not fit gets twice
-// that list plus 32 entries; the largest token count of the walk goes to
-// red[kRedMaxTok].
+// Slot and lane-room sizes after a refresh some of whose lists did not fit:
+// every group keeps its slot's and its lanes' sizes (k_slot_sizes), a group
+// whose walked list did not fit gets twice that list plus 32 entries, and
+// each of its lanes twice the lane's tokens plus kLaneSpare (k_slot_grow).
 __global__ void __launch_bounds__(256)
 k_slot_sizes(int64_t ng, const uint64_t* __restrict__ epj_off,
              const uint64_t* __restrict__ spj_off,
-             uint32_t* __restrict__ cap_e, uint32_t* __restrict__ cap_s) {
+             const uint64_t* __restrict__ lane_off,
+             uint32_t* __restrict__ cap_e, uint32_t* __restrict__ cap_s,
+             uint32_t* __restrict__ lane_cap) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ng) return;
   cap_e[g] = (uint32_t)(epj_off[g + 1] - epj_off[g]);
   cap_s[g] = (uint32_t)(spj_off[g + 1] - spj_off[g]);
+  for (int h = 0; h < kSplitLanes; ++h) {
+    const uint64_t i = (uint64_t)g * kSplitLanes + h;
+    lane_cap[i] = (uint32_t)(lane_off[i + 1] - lane_off[i]);
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -381,16 +392,20 @@ k_slot_grow(int64_t n_max, const uint32_t* __restrict__ n_dev,
             const uint32_t* __restrict__ sel, const uint8_t* __restrict__ ok,
             const uint32_t* __restrict__ sel_e,
             const uint32_t* __restrict__ sel_s,
-            const uint32_t* __restrict__ sel_t, uint32_t* __restrict__ cap_e,
-            uint32_t* __restrict__ cap_s,
-            unsigned long long* __restrict__ red) {
+            const uint32_t* __restrict__ sel_tl, uint32_t* __restrict__ cap_e,
+            uint32_t* __restrict__ cap_s, uint32_t* __restrict__ lane_cap) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_max || t >= (int64_t)*n_dev || ok[t]) return;
   const uint32_t g = sel[t];
   const uint32_t e = 2u * sel_e[t] + 32u, s = 2u * sel_s[t] + 32u;
   if (e > cap_e[g]) cap_e[g] = e;
   if (s > cap_s[g]) cap_s[g] = s;
-  atomicMax(red + kRedMaxTok, (unsigned long long)sel_t[t]);
+  for (int h = 0; h < kSplitLanes; ++h) {
+    const uint64_t i = (uint64_t)g * kSplitLanes + h;
+    const uint32_t r =
+        (2u * sel_tl[(uint64_t)t * kSplitLanes + h] + kLaneSpare + 15u) & ~15u;
+    if (r > lane_cap[i]) lane_cap[i] = r;
+  }
 }
 
 // Every group's list from its old slot to its new one (one wave per group).
@@ -833,9 +848,10 @@ int mlp_ensure(nb_ctx* c) {
 // Refresh the lists of the groups flagged in c->pick (their ids compacted
 // into c->sel in ascending order, their number at c->pickpos[n_groups] on
 // the device), without waiting for the host: one walk pass over up to all
-// groups' slots (the kernels read the selection size), tokens into slabs of
-// c->refresh_slab per slot; then each refreshed list that fits its group's
-// list slot is expanded into it and installed (k_refresh_fit / k_expand /
+// groups' slots (the kernels read the selection size), kSplitLanes lanes
+// per group, each lane's tokens into its group's lane room; then each
+// refreshed list that fits its lanes' room and its group's list slot is
+// expanded into the slot and installed (k_refresh_fit / k_expand /
 // k_refresh_commit), the others keep their lists; last, the interaction
 // counts of the current lists (device counters).  The current boxes must be
 // in g_clo / g_chi.  Every buffer was sized by the construction step, so a
@@ -843,13 +859,13 @@ int mlp_ensure(nb_ctx* c) {
 int refresh_selected(nb_ctx* c) {
   const int64_t G = c->n_groups;
   const uint32_t* n_dev = c->pickpos.p + G;
-  const uint32_t slab = c->refresh_slab;
-  if (!slab || !c->red.p || (uint64_t)G * slab > c->tok.cap)
+  if (!c->red.p || !c->lane_off.p ||
+      (uint64_t)c->lane_total > c->tok.cap ||
+      (uint64_t)G * kSplitLanes > c->cnt_tl.cap)
     return set_err(c, NB_ERR_STATE, "refresh buffers not sized");
   const WalkOut o{c->sel_e.p, c->sel_s.p, c->sel_t.p, c->sel_sa.p,
-                  c->sel_so.p, c->sel_tau0.p, n_dev, 1};
-  int rc = launch_walk_refresh(c, G, c->sel.p, c->g_clo.p, c->g_chi.p, slab,
-                               o, c->sel_hint);
+                  c->sel_so.p, c->sel_tau0.p, n_dev};
+  int rc = launch_walk_refresh(c, G, c->sel.p, c->g_clo.p, c->g_chi.p, o);
   if (rc) return rc;
   unsigned long long* red = reinterpret_cast<unsigned long long*>(c->red.p);
   hipLaunchKernelGGL(k_zero_u64s, dim3(1), dim3(64), 0, c->stream,
@@ -857,12 +873,12 @@ int refresh_selected(nb_ctx* c) {
   hipLaunchKernelGGL(k_refresh_fit, dim3(grid_for(G, 256)), dim3(256), 0,
                      c->stream, G, n_dev, (const uint32_t*)c->sel.p,
                      (const uint32_t*)c->sel_e.p, (const uint32_t*)c->sel_s.p,
-                     (const uint32_t*)c->sel_t.p, slab,
+                     (const uint32_t*)c->cnt_tl.p,
+                     (const uint64_t*)c->lane_off.p,
                      (const uint64_t*)c->epj_off.p,
                      (const uint64_t*)c->spj_off.p, c->sel_ok.p, red);
   rc = hip_check(c, hipGetLastError(), "refresh fit launch");
-  if (!rc) rc = launch_expand_sel(c, G, c->sel.p, slab, c->sel_t.p, n_dev,
-                                  c->sel_ok.p);
+  if (!rc) rc = launch_expand_sel(c, G, c->sel.p, n_dev, c->sel_ok.p);
   if (rc) return rc;
   hipLaunchKernelGGL(k_refresh_commit, dim3(grid_for(G, 256)), dim3(256), 0,
                      c->stream, G, n_dev, (const uint32_t*)c->sel.p,
@@ -879,37 +895,40 @@ int refresh_selected(nb_ctx* c) {
 }
 
 // After a refresh whose lists did not all fit (the selection and its walk's
-// output are still in place): larger slots for those groups, every list
-// moved to its new slot, and a larger token slab if the walk overflowed
-// it.  Synchronises with the host.  Drops a captured graph (the list
-// buffers change).
+// output are still in place): larger list slots and lane rooms for those
+// groups, every list moved to its new slot, and the token buffer grown to
+// the new rooms.  Synchronises with the host.  Drops a captured graph (the
+// list buffers change).
 static int grow_slots(nb_ctx* c) {
   const int64_t G = c->n_groups;
+  const int64_t nl = (int64_t)kSplitLanes * G;
   const uint32_t* n_dev = c->pickpos.p + G;
-  unsigned long long* red = reinterpret_cast<unsigned long long*>(c->red.p);
-  hipLaunchKernelGGL(k_zero_u64s, dim3(1), dim3(64), 0, c->stream,
-                     red + kRedMaxTok, 1);
   hipLaunchKernelGGL(k_slot_sizes, dim3(grid_for(G, 256)), dim3(256), 0,
                      c->stream, G, (const uint64_t*)c->epj_off.p,
-                     (const uint64_t*)c->spj_off.p, c->ne2.p, c->ns2.p);
+                     (const uint64_t*)c->spj_off.p,
+                     (const uint64_t*)c->lane_off.p, c->ne2.p, c->ns2.p,
+                     c->lane_cap.p);
   hipLaunchKernelGGL(k_slot_grow, dim3(grid_for(G, 256)), dim3(256), 0,
                      c->stream, G, n_dev, (const uint32_t*)c->sel.p,
                      (const uint8_t*)c->sel_ok.p, (const uint32_t*)c->sel_e.p,
-                     (const uint32_t*)c->sel_s.p, (const uint32_t*)c->sel_t.p,
-                     c->ne2.p, c->ns2.p, red);
+                     (const uint32_t*)c->sel_s.p,
+                     (const uint32_t*)c->cnt_tl.p, c->ne2.p, c->ns2.p,
+                     c->lane_cap.p);
   int rc = hip_check(c, hipGetLastError(), "slot size launch");
   if (!rc) rc = reserve(c, c->epj_off2, (size_t)G + 1);
   if (!rc) rc = reserve(c, c->spj_off2, (size_t)G + 1);
+  if (!rc) rc = reserve(c, c->lane_off2, (size_t)nl + 1);
   if (!rc) rc = scan_u32_to_u64(c, c->ne2.p, c->epj_off2.p, G);
   if (!rc) rc = scan_u32_to_u64(c, c->ns2.p, c->spj_off2.p, G);
+  if (!rc) rc = scan_u32_to_u64(c, c->lane_cap.p, c->lane_off2.p, nl);
   if (!rc) rc = stage_d2h(c, 0, c->epj_off2.p + G, 8);
   if (!rc) rc = stage_d2h(c, 8, c->spj_off2.p + G, 8);
-  if (!rc) rc = stage_d2h(c, 16, red + kRedMaxTok, 8);
+  if (!rc) rc = stage_d2h(c, 16, c->lane_off2.p + nl, 8);
   if (!rc) rc = sync_stream(c);
   if (rc) return rc;
   const uint64_t* h = static_cast<const uint64_t*>(c->h_small);
   const int64_t ce = (int64_t)h[0], cs = (int64_t)h[1];
-  const int64_t max_tok = (int64_t)h[2];
+  const int64_t lt = (int64_t)h[2];
   drop_graph(c);
   if ((rc = reserve(c, c->epj2, (size_t)ce + 1))) return rc;
   if ((rc = reserve(c, c->spj2, (size_t)cs + 1))) return rc;
@@ -924,15 +943,11 @@ static int grow_slots(nb_ctx* c) {
   std::swap(c->spj, c->spj2);
   std::swap(c->epj_off, c->epj_off2);
   std::swap(c->spj_off, c->spj_off2);
+  std::swap(c->lane_off, c->lane_off2);
   c->cap_e = ce;
   c->cap_s = cs;
-  if (max_tok > (int64_t)c->refresh_slab) {
-    const int64_t most = ((int64_t)1 << 32) / G / 16 * 16;
-    c->refresh_slab = (uint32_t)std::min<int64_t>(
-        (2 * max_tok + 64 + 15) / 16 * 16, most);
-    if ((rc = reserve(c, c->tok, (size_t)G * c->refresh_slab))) return rc;
-  }
-  return NB_OK;
+  c->lane_total = lt;
+  return reserve(c, c->tok, (size_t)lt + 1);
 }
 
 // Selection from host ids (ascending, unique, in range: checked here).
@@ -962,7 +977,6 @@ int refresh_host_sel(nb_ctx* c, int64_t n_sel, const int64_t* sel) {
   }
   if (!rc) rc = scan_u32(c, c->pick.p, c->pickpos.p, G);
   if (rc) return rc;
-  c->sel_hint = n_sel;
   // a list that does not fit its slot is walked again into a larger one
   // (the selection's other groups get the same list again)
   for (int attempt = 0; attempt < 2; ++attempt) {

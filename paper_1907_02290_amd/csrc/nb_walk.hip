@@ -3,8 +3,10 @@
 // lists hold 32-bit indices, particles by internal slot, superparticles by
 // cell id).
 //
-// One thread walks one group: a stackless DFS over the pre-order cell array,
-// jumping over a subtree with its skip id.  The opening test compares the
+// The walk of one group is a stackless DFS over the pre-order cell array,
+// jumping over a subtree with its skip id, run by a tile of lanes (few
+// groups) or cut into stretches walked by kSplitLanes lanes (many groups,
+// and refresh mode).  The opening test compares the
 // squared distance from the group's tight box to the cell's geometric centre
 // with (side / theta)^2 in FP64, evaluated term by term (no fused
 // multiply-add: this file is built with -ffp-contract=off and uses explicit
@@ -25,19 +27,13 @@ namespace nb {
 namespace {
 
 constexpr int kWalkThreads = 256;
-// Walk layout.  From kThreadWalkFrom groups on, one thread per group (its
-// LDS-staged token writes and lean loop win once the groups fill the
-// device: on MI355X, 58k groups of a 2^22-particle disk walk in 2.0 ms one
-// thread per group, 2.5 / 3.4 / 4.6 ms with tiles of 4 / 8 / 16 lanes);
-// below, tiles of at least kTileWalk lanes, widened until about kTileLanes
-// lanes are in flight (1.8k groups: 0.5 ms against 2.4 ms one thread per
-// group).
+// Walk layout.  From kThreadWalkFrom groups on, kSplitLanes lanes per group,
+// each walking one stretch of the pre-order array (k_walk_c); below, tiles
+// of at least kTileWalk lanes, widened until about kTileLanes lanes are in
+// flight (1.8k groups of a 2^22-particle disk: 0.5 ms in tiles against
+// 2.4 ms one thread per group).  Refresh mode walks kSplitLanes lanes per
+// group at every size (k_walk_r).
 constexpr int64_t kThreadWalkFrom = 8192;
-// The refresh-mode walk reads a 64-byte cell record, its centre and its
-// shift at every visit, so one thread per group stays latency-bound longer:
-// on a 2^20-particle disk about 8.5k selected groups took 8.4 ms one thread
-// per group against 4.7 ms for just under 8192 groups in tiles.
-constexpr int64_t kThreadWalkFromRefresh = 65536;
 constexpr int kTileWalk = 4;
 constexpr int64_t kTileLanes = 1 << 18;
 
@@ -46,152 +42,22 @@ __device__ inline int64_t xcd_block(int64_t nblk) {
   return (int64_t)(blockIdx.x & 7u) * per + (int64_t)(blockIdx.x >> 3);
 }
 
+// Blocks that hold work when only the first *n_dev of n_walk items (`per`
+// items per block) are to be walked: the XCD stretches are cut over those
+// blocks, not over the launch's (sized for n_walk), so the work spreads
+// over every XCD.
+__device__ inline int64_t active_blocks(int64_t nblk, int64_t n_walk,
+                                        const uint32_t* n_dev, int64_t per) {
+  if (!n_dev) return nblk;
+  const int64_t n = (int64_t)*n_dev < n_walk ? (int64_t)*n_dev : n_walk;
+  return (n + per - 1) / per;
+}
+
 // Tokens of the fill pass: an accepted cell (SPJ) is its id, an opened
 // leaf is its id with the top bit set.
 constexpr uint32_t kLeafTag = 0x80000000u;
 constexpr int kSeg = 16;  // tokens per 64-byte output segment
 constexpr int kExpandBatch = 4;  // 64-token chunks per round of k_expand
-
-// LEARN: the variant used with per-group list refresh.  Threads take the
-// groups listed in `sel` (all groups when sel is NULL), the centres come
-// from `ctr` (geometric centre carried by the cell's centre-of-mass shift,
-// and rcrit^2) instead of the cell records, and the count pass records the
-// opening-test slacks and the cell shift of the group for the predictor
-// (at the group's index, or with `slot_state` at the walk's slot t, for a
-// refresh that installs the new list only if it fits).  With `n_dev` the
-// number of groups walked is *n_dev (at most n_walk), read on the device,
-// so that the launch does not wait for the host.
-template <bool FILL, bool LEARN>
-__global__ void __launch_bounds__(kWalkThreads)
-k_walk(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
-       const uint32_t* __restrict__ g_begin,
-       const uint32_t* __restrict__ g_count, const double4* __restrict__ g_lo,
-       const double4* __restrict__ g_hi, const CellRec* __restrict__ rec,
-       const double4* __restrict__ ctr, const uint32_t* __restrict__ g_cell,
-       const double4* __restrict__ shift, double* __restrict__ g_sa,
-       double* __restrict__ g_so, double4* __restrict__ g_tau0,
-       const uint32_t* __restrict__ seg, const uint32_t* __restrict__ croot,
-       uint32_t* __restrict__ cnt_e, uint32_t* __restrict__ cnt_s,
-       uint32_t* __restrict__ cnt_t, const uint64_t* __restrict__ tok_off,
-       uint32_t* __restrict__ tok, uint32_t slab,
-       const uint32_t* __restrict__ n_dev, int slot_state) {
-  // per-lane staging of the token stream: a lane writes its tokens out one
-  // aligned 64-byte segment at a time, so that partially written lines do
-  // not pile up in L2 (one open line per group otherwise)
-  __shared__ uint32_t stage[FILL ? kSeg : 1][kWalkThreads];
-  const int64_t blk = xcd_block(nblk);
-  if (blk >= nblk) return;
-  const int64_t t = blk * kWalkThreads + threadIdx.x;
-  if (t >= n_walk || (n_dev && t >= (int64_t)*n_dev)) return;
-  const int64_t g = (LEARN && sel) ? (int64_t)sel[t] : t;
-  const uint32_t gb = g_begin[g];
-  const uint32_t ge = gb + g_count[g];
-  const double4 lo = g_lo[g], hi = g_hi[g];
-  uint32_t* dst = nullptr;
-  uint64_t out = 0;   // next output slot of this lane
-  uint64_t end = 0;   // slab mode: end of this group's slab
-  int sc = 0;         // staged tokens
-  if (FILL) {
-    // slab mode (slab > 0): counts and tokens in one pass, the tokens into a
-    // fixed slab of `slab` slots per group (a multiple of 16); tokens past
-    // the slab are dropped and the caller sees the overflow in the counts
-    out = slab ? (uint64_t)t * slab : tok_off[t];
-    end = slab ? out + slab : ~0ull;
-    dst = tok;
-  }
-  const bool counts = !FILL || slab != 0;
-  double sa = __builtin_inf(), so = __builtin_inf();
-  uint32_t ne = 0, ns = 0, nl = 0;
-  // the walk covers the cells of the group's own system
-  const uint32_t sys = seg[gb];
-  uint32_t c = croot[sys];
-  const uint32_t nc = croot[sys + 1];
-  while (c < nc) {
-    const uint4 m = rec[c].meta;
-    const double4 cc = LEARN ? ctr[c] : rec[c].geo;
-    bool open;
-    if (m.x <= gb && m.y >= ge) {
-      open = true;
-    } else {
-      double dx = 0.0, dy = 0.0, dz = 0.0, t;
-      t = __dsub_rn(lo.x, cc.x);
-      if (t > dx) dx = t;
-      t = __dsub_rn(cc.x, hi.x);
-      if (t > dx) dx = t;
-      t = __dsub_rn(lo.y, cc.y);
-      if (t > dy) dy = t;
-      t = __dsub_rn(cc.y, hi.y);
-      if (t > dy) dy = t;
-      t = __dsub_rn(lo.z, cc.z);
-      if (t > dz) dz = t;
-      t = __dsub_rn(cc.z, hi.z);
-      if (t > dz) dz = t;
-      const double d2 =
-          __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
-                    __dmul_rn(dz, dz));
-      open = !(d2 > cc.w);
-      if (LEARN && counts) {
-        const double dd = __dsqrt_rn(d2), rr = __dsqrt_rn(cc.w);
-        if (open) {
-          const double v = __dsub_rn(rr, dd);
-          if (v < so) so = v;
-        } else {
-          const double v = __dsub_rn(dd, rr);
-          if (v < sa) sa = v;
-        }
-      }
-    }
-    const bool leaf = (m.w >> 8) & 1u;
-    // skip ids always point past the cell; the guard keeps a damaged tree
-    // from looping forever
-    const uint32_t next = (!open || leaf) ? m.z : c + 1;
-    if (next <= c) break;
-    if (!open || leaf) {
-      if (!open)
-        ++ns;
-      else {
-        ++nl;
-        ne += m.y - m.x;
-      }
-      if (FILL) {
-        stage[sc][threadIdx.x] = open ? (c | kLeafTag) : c;
-        ++sc;
-        if (((out + sc) & (kSeg - 1)) == 0) {
-          if (out + sc > end) {
-            // past the slab: drop
-          } else if (sc == kSeg) {
-            uint4* d4 = reinterpret_cast<uint4*>(dst + out);
-#pragma unroll
-            for (int q = 0; q < kSeg / 4; ++q)
-              d4[q] = make_uint4(stage[4 * q][threadIdx.x],
-                                 stage[4 * q + 1][threadIdx.x],
-                                 stage[4 * q + 2][threadIdx.x],
-                                 stage[4 * q + 3][threadIdx.x]);
-          } else {
-            for (int q = 0; q < sc; ++q) dst[out + q] = stage[q][threadIdx.x];
-          }
-          out += sc;
-          sc = 0;
-        }
-      }
-    }
-    c = next;
-  }
-  if (FILL && out + sc <= end) {
-    for (int q = 0; q < sc; ++q) dst[out + q] = stage[q][threadIdx.x];
-  }
-  if (counts) {
-    cnt_e[t] = ne;
-    cnt_s[t] = ns;
-    cnt_t[t] = ns + nl;
-    if (LEARN) {
-      const int64_t o = slot_state ? t : g;
-      g_sa[o] = sa;
-      g_so[o] = so;
-      g_tau0[o] = shift[g_cell[g]];
-    }
-  }
-}
 
 // The walk over the 16-byte walk records (one load per visit instead of the
 // 64-byte cell record's three), S lanes per group (S = 2, 4 or 8).  The
@@ -415,6 +281,207 @@ k_walk_c(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
   }
 }
 
+// The refresh-mode walk, S lanes per group cut as in k_walk_c (stretches
+// between the ancestors of the deepest cell gd holding the group and past
+// their subtrees), with the refresh-mode geometry: each visit reads the
+// 16-byte walk record (skip, leaf flag, leaf count) and the cell's moved
+// centre and (effective side / theta)^2 from `ctr`; the lanes also record
+// the opening-test slacks of the group (smallest margin of an accepted and
+// of an opened cell that does not hold the group) and its cell's shift.
+// The cut needs only that ancestors of gd hold the group and are opened,
+// which the moved geometry keeps (a cell holding the group's particle range
+// is always opened).  The construction walk of refresh mode (sel NULL, slot
+// t = group t) and the refresh of a selection (slot t = group sel[t], only
+// the first *n_dev slots) are this kernel.  Counts and state go to slot t;
+// lane h's token count to cnt_tl[S t + h].  Tokens (FILL) go to
+//   lane_off given: the group's lane range [lane_off[S g + h],
+//                   lane_off[S g + h + 1]) (the refresh's per-lane room),
+//   slab > 0:       slab S t + h of `slab` tokens,
+//   else:           after the tokens of lanes 0 .. h - 1 from tok_off[t]
+//                   (exact fill after a count pass, counts left as they are).
+// Tokens past a lane's room are dropped; its count says so.
+template <bool FILL, int S>
+__global__ void __launch_bounds__(kWalkThreads)
+k_walk_r(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
+         const uint32_t* __restrict__ n_dev,
+         const uint32_t* __restrict__ g_begin,
+         const uint32_t* __restrict__ g_count,
+         const double4* __restrict__ g_lo, const double4* __restrict__ g_hi,
+         const uint32_t* __restrict__ g_cell, const CellRec* __restrict__ rec,
+         const uint4* __restrict__ wrec, const double4* __restrict__ ctr,
+         const double4* __restrict__ shift, const uint32_t* __restrict__ seg,
+         const uint32_t* __restrict__ croot, uint32_t* __restrict__ cnt_e,
+         uint32_t* __restrict__ cnt_s, uint32_t* __restrict__ cnt_t,
+         uint32_t* __restrict__ cnt_tl, double* __restrict__ o_sa,
+         double* __restrict__ o_so, double4* __restrict__ o_tau0,
+         const uint64_t* __restrict__ lane_off,
+         const uint64_t* __restrict__ tok_off, uint32_t* __restrict__ tok,
+         uint32_t slab) {
+  static_assert(S == 2 || S == 4 || S == 8, "lanes per group");
+  constexpr int H = S / 2;
+  __shared__ uint32_t stage[FILL ? kSeg : 1][kWalkThreads];
+  const int64_t n_sel =
+      (n_dev && (int64_t)*n_dev < n_walk) ? (int64_t)*n_dev : n_walk;
+  const int64_t nact = active_blocks(nblk, n_walk, n_dev, kWalkThreads / S);
+  const int64_t blk = xcd_block(nact);
+  if (blk >= nact) return;
+  const int64_t tt = blk * kWalkThreads + threadIdx.x;
+  if (tt >= n_sel * S) return;  // the S lanes of a slot leave together
+  const int64_t t = tt / S;
+  const int h = (int)(tt % S);
+  const uint32_t g = sel ? sel[t] : (uint32_t)t;
+  const uint32_t gb = g_begin[g];
+  const uint32_t ge = gb + g_count[g];
+  const double4 lo = g_lo[g], hi = g_hi[g];
+  uint32_t gd = g_cell[g];
+  for (;;) {
+    if ((rec[gd].meta.w >> 8) & 1u) break;
+    const uint4 m1 = rec[gd + 1].meta;
+    if (m1.x != gb || m1.y != ge) break;
+    ++gd;
+  }
+  const uint32_t sys = seg[gb];
+  const uint32_t r0 = croot[sys], r1 = croot[sys + 1];
+  uint32_t c, nc;
+  if (S == 2) {
+    c = h ? gd : r0;
+    nc = h ? r1 : gd;
+  } else {
+    const int D = (int)(rec[gd].meta.w & 255u);
+    uint32_t a[H + 1];
+    a[0] = r0;
+    a[H] = gd;
+    uint32_t x = gd;
+    int lx = D;
+#pragma unroll
+    for (int q = H - 1; q >= 1; --q) {
+      const int want = (D * q) / H;
+      while (lx > want) {
+        x = rec[x].aux.x;
+        --lx;
+      }
+      a[q] = x;
+    }
+    if (h < H) {
+      c = a[h];
+      nc = a[h + 1];
+    } else {
+      const int k2 = h - H;
+      c = k2 == 0 ? gd : wrec[a[H - k2]].z;
+      nc = k2 == H - 1 ? r1 : wrec[a[H - 1 - k2]].z;
+    }
+  }
+  uint64_t out = 0, end = ~0ull;
+  if (FILL) {
+    if (lane_off) {
+      out = lane_off[(uint64_t)g * S + h];
+      end = lane_off[(uint64_t)g * S + h + 1];
+    } else if (slab) {
+      out = ((uint64_t)t * S + (uint64_t)h) * slab;
+      end = out + slab;
+    } else {
+      out = tok_off[t];
+      for (int q = 0; q < h; ++q) out += cnt_tl[(uint64_t)t * S + q];
+    }
+  }
+  const bool counts = !FILL || lane_off || slab;
+  int sc = 0;
+  double sa = __builtin_inf(), so = __builtin_inf();
+  uint32_t ne = 0, ns = 0, nl = 0;
+  while (c < nc) {
+    const uint4 w = wrec[c];
+    const double4 cc = ctr[c];
+    const uint32_t skip = w.z;
+    const bool leaf = (w.y >> 31) != 0u;
+    const bool holds = c <= gd && gd < skip;
+    double dx = 0.0, dy = 0.0, dz = 0.0, u;
+    u = __dsub_rn(lo.x, cc.x);
+    if (u > dx) dx = u;
+    u = __dsub_rn(cc.x, hi.x);
+    if (u > dx) dx = u;
+    u = __dsub_rn(lo.y, cc.y);
+    if (u > dy) dy = u;
+    u = __dsub_rn(cc.y, hi.y);
+    if (u > dy) dy = u;
+    u = __dsub_rn(lo.z, cc.z);
+    if (u > dz) dz = u;
+    u = __dsub_rn(cc.z, hi.z);
+    if (u > dz) dz = u;
+    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                __dmul_rn(dz, dz));
+    const bool open = holds || !(d2 > cc.w);
+    if (counts && !holds) {
+      const double dd = __dsqrt_rn(d2), rr = __dsqrt_rn(cc.w);
+      if (open) {
+        const double v = __dsub_rn(rr, dd);
+        if (v < so) so = v;
+      } else {
+        const double v = __dsub_rn(dd, rr);
+        if (v < sa) sa = v;
+      }
+    }
+    const bool term = !open || leaf;
+    // skip ids always point past the cell; the guard keeps a damaged tree
+    // from looping forever
+    const uint32_t next = term ? skip : c + 1;
+    if (next <= c) break;
+    if (term) {
+      if (!open) {
+        ++ns;
+      } else {
+        ++nl;
+        uint32_t cnt = w.w >> 5;
+        if (cnt == kWalkCountSat) cnt = rec[c].meta.y - rec[c].meta.x;
+        ne += cnt;
+      }
+      if (FILL) {
+        stage[sc][threadIdx.x] = open ? (c | kLeafTag) : c;
+        ++sc;
+        if (((out + sc) & (kSeg - 1)) == 0) {
+          if (out + sc > end) {
+            // past the lane's room: drop
+          } else if (sc == kSeg) {
+            uint4* d4 = reinterpret_cast<uint4*>(tok + out);
+#pragma unroll
+            for (int q = 0; q < kSeg / 4; ++q)
+              d4[q] = make_uint4(stage[4 * q][threadIdx.x],
+                                 stage[4 * q + 1][threadIdx.x],
+                                 stage[4 * q + 2][threadIdx.x],
+                                 stage[4 * q + 3][threadIdx.x]);
+          } else {
+            for (int q = 0; q < sc; ++q) tok[out + q] = stage[q][threadIdx.x];
+          }
+          out += sc;
+          sc = 0;
+        }
+      }
+    }
+    c = next;
+  }
+  if (FILL && out + sc <= end)
+    for (int q = 0; q < sc; ++q) tok[out + q] = stage[q][threadIdx.x];
+  if (!counts) return;  // after the exact fill: uniform over the S lanes
+  const uint32_t ta = ns + nl;
+  cnt_tl[(uint64_t)t * S + h] = ta;
+  uint32_t e2 = ne, s2 = ns, t2 = ta;
+#pragma unroll
+  for (int o = S / 2; o > 0; o >>= 1) {
+    e2 += __shfl_xor(e2, o, 64);
+    s2 += __shfl_xor(s2, o, 64);
+    t2 += __shfl_xor(t2, o, 64);
+    sa = fmin(sa, __shfl_xor(sa, o, 64));
+    so = fmin(so, __shfl_xor(so, o, 64));
+  }
+  if (h == 0) {
+    cnt_e[t] = e2;
+    cnt_s[t] = s2;
+    cnt_t[t] = t2;
+    o_sa[t] = sa;
+    o_so[t] = so;
+    o_tau0[t] = shift[g_cell[g]];
+  }
+}
+
 // Tile walk: W lanes per group (W = 4 .. 64, a power of two), for more
 // parallelism than one thread per group.  The lanes of a tile take W
 // consecutive cells of the pre-order array and evaluate the opening test of
@@ -429,30 +496,23 @@ k_walk_c(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
 // window; large tiles give more lanes when there are few groups.
 // slab > 0 (fill pass only): counts and tokens in one pass, the tokens into
 // `slab` slots per group, as in the one-thread walk.
-template <int W, bool FILL, bool LEARN>
+template <int W, bool FILL>
 __global__ void __launch_bounds__(256)
-k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
-            const uint32_t* __restrict__ g_begin,
+k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ g_begin,
             const uint32_t* __restrict__ g_count,
             const double4* __restrict__ g_lo, const double4* __restrict__ g_hi,
-            const CellRec* __restrict__ rec, const double4* __restrict__ ctr,
-            const uint32_t* __restrict__ g_cell,
-            const double4* __restrict__ shift, double* __restrict__ g_sa,
-            double* __restrict__ g_so, double4* __restrict__ g_tau0,
-            const uint32_t* __restrict__ seg,
+            const CellRec* __restrict__ rec, const uint32_t* __restrict__ seg,
             const uint32_t* __restrict__ croot, uint32_t* __restrict__ cnt_e,
             uint32_t* __restrict__ cnt_s, uint32_t* __restrict__ cnt_t,
             const uint64_t* __restrict__ tok_off, uint32_t* __restrict__ tok,
-            uint32_t slab, const uint32_t* __restrict__ n_dev,
-            int slot_state) {
+            uint32_t slab) {
   static_assert(W >= 2 && W <= 64 && (W & (W - 1)) == 0, "tile width");
   const int64_t blk = xcd_block(nblk);
   if (blk >= nblk) return;
   const int64_t t = blk * (256 / W) + (threadIdx.x / W);
   const int lane = threadIdx.x & (W - 1);
-  // uniform over the tile
-  if (t >= n_walk || (n_dev && t >= (int64_t)*n_dev)) return;
-  const int64_t g = (LEARN && sel) ? (int64_t)sel[t] : t;
+  if (t >= n_walk) return;  // uniform over the tile
+  const int64_t g = t;
   const uint32_t gb = g_begin[g];
   const uint32_t ge = gb + g_count[g];
   const double4 lo = g_lo[g], hi = g_hi[g];
@@ -467,7 +527,6 @@ k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   }
   const bool counts = !FILL || slab != 0;
   uint32_t ne = 0, ns = 0, nl = 0;  // per lane
-  double sa = __builtin_inf(), so = __builtin_inf();
   const uint32_t sys = seg[gb];
   uint32_t c = croot[sys];
   const uint32_t nc = croot[sys + 1];
@@ -475,13 +534,11 @@ k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
     const uint32_t i = c + (uint32_t)lane;
     const bool valid = i < nc;
     uint4 m = make_uint4(0u, 0u, 0u, 0u);
-    bool open = false, stop = false, holds = false;
-    double d2 = 0.0, rc2 = 0.0;
+    bool open = false, stop = false;
     if (valid) {
       m = rec[i].meta;
-      const double4 cc = LEARN ? ctr[i] : rec[i].geo;
-      holds = m.x <= gb && m.y >= ge;
-      if (holds) {
+      const double4 cc = rec[i].geo;
+      if (m.x <= gb && m.y >= ge) {
         open = true;
       } else {
         double dx = 0.0, dy = 0.0, dz = 0.0, u;
@@ -497,10 +554,10 @@ k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
         if (u > dz) dz = u;
         u = __dsub_rn(cc.z, hi.z);
         if (u > dz) dz = u;
-        d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
-                       __dmul_rn(dz, dz));
-        rc2 = cc.w;
-        open = !(d2 > rc2);
+        const double d2 =
+            __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                      __dmul_rn(dz, dz));
+        open = !(d2 > cc.w);
       }
       stop = !open || ((m.w >> 8) & 1u);
     }
@@ -516,16 +573,6 @@ k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
     const bool visited = valid && !(excl > i);
     const bool acc = visited && !open;
     const bool lf = visited && open && stop;
-    if (LEARN && counts && visited && !holds) {
-      const double dd = __dsqrt_rn(d2), rr = __dsqrt_rn(rc2);
-      if (open) {
-        const double v = __dsub_rn(rr, dd);
-        if (v < so) so = v;
-      } else {
-        const double v = __dsub_rn(dd, rr);
-        if (v < sa) sa = v;
-      }
-    }
     if (counts) {
       ns += acc ? 1u : 0u;
       nl += lf ? 1u : 0u;
@@ -547,21 +594,11 @@ k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
       ne += __shfl_xor(ne, o, W);
       ns += __shfl_xor(ns, o, W);
       nl += __shfl_xor(nl, o, W);
-      if (LEARN) {
-        sa = fmin(sa, __shfl_xor(sa, o, W));
-        so = fmin(so, __shfl_xor(so, o, W));
-      }
     }
     if (lane == 0) {
       cnt_e[t] = ne;
       cnt_s[t] = ns;
       cnt_t[t] = ns + nl;
-      if (LEARN) {
-        const int64_t o = slot_state ? t : g;
-        g_sa[o] = sa;
-        g_so[o] = so;
-        g_tau0[o] = shift[g_cell[g]];
-      }
     }
   }
 }
@@ -570,12 +607,14 @@ k_walk_tile(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
 // Tokens are read in chunks of 64; accepted cells are compacted with a
 // ballot, opened leaves are expanded using a wave scan of their sizes, so
 // every chunk lands in contiguous stretches of both lists.
-// Token offsets are per walked group (index t); output offsets per group id
-// (sel[t], or t when sel is NULL).  With n_dev only the first *n_dev slots
-// are expanded, and with ok only the slots t with ok[t].
+// Token offsets and counts are per walked group (index t), except the
+// per-lane ranges lane_off, which belong to the group id like the output
+// offsets (sel[t], or t when sel is NULL).  With n_dev only the first
+// *n_dev slots are expanded, and with ok only the slots t with ok[t].
 __global__ void __launch_bounds__(256)
 k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
-         const uint64_t* __restrict__ tok_off, uint32_t slab,
+         const uint64_t* __restrict__ tok_off,
+         const uint64_t* __restrict__ lane_off, uint32_t slab,
          const uint32_t* __restrict__ cnt_t,
          const uint32_t* __restrict__ cnt_tl, int lanes,
          const uint32_t* __restrict__ tok, const CellRec* __restrict__ rec,
@@ -583,16 +622,18 @@ k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
          const uint64_t* __restrict__ spj_off, uint32_t* __restrict__ epj,
          uint32_t* __restrict__ spj, const uint32_t* __restrict__ n_dev,
          const uint8_t* __restrict__ ok) {
-  const int64_t blk = xcd_block(nblk);
-  if (blk >= nblk) return;
+  const int64_t nact = active_blocks(nblk, n_walk, n_dev, 4);
+  const int64_t blk = xcd_block(nact);
+  if (blk >= nact) return;
   const int64_t t = blk * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= n_walk || (n_dev && t >= (int64_t)*n_dev) || (ok && !ok[t]))
     return;  // uniform over the wave
   const int64_t g = sel ? (int64_t)sel[t] : t;
-  // the token stream: one range, or (slab mode of the walk with `lanes`
-  // lanes per group, cnt_tl given) the lanes' slabs one after the other
-  const int nr = (slab && cnt_tl) ? lanes : 1;
+  // the token stream: one range, or (a walk with `lanes` lanes per group
+  // whose tokens sit in per-lane slabs or per-lane ranges, cnt_tl given)
+  // the lanes' ranges one after the other
+  const int nr = ((slab || lane_off) && cnt_tl) ? lanes : 1;
   uint64_t oe = epj_off[g], os = spj_off[g];
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   // kExpandBatch chunks of 64 tokens per round: their token loads, then
@@ -600,7 +641,10 @@ k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
   // two memory latencies instead of two per chunk
   for (int ri = 0; ri < nr; ++ri) {
     uint64_t t0, t1;
-    if (!slab) {
+    if (lane_off) {
+      t0 = lane_off[(uint64_t)g * (uint64_t)lanes + (uint64_t)ri];
+      t1 = t0 + cnt_tl[(uint64_t)t * (uint64_t)lanes + (uint64_t)ri];
+    } else if (!slab) {
       t0 = tok_off[t];
       t1 = tok_off[t + 1];
     } else if (!cnt_tl) {
@@ -684,9 +728,9 @@ k_interactions(int64_t n_groups, const uint32_t* __restrict__ g_count,
   }
 }
 
-// List slots of refresh mode: twice the list plus the mean list length of
-// the construction (red[kRedEpj] / groups, at least 32), so that short
-// lists can grow to typical ones.
+// List slots of refresh mode: three times the list plus the mean list
+// length of the construction (red[kRedEpj] / groups, plus 32), so that
+// short lists can grow to typical ones.
 __global__ void __launch_bounds__(256)
 k_slot_caps(int64_t n_groups, const uint32_t* __restrict__ cnt_e,
             const uint32_t* __restrict__ cnt_s,
@@ -696,10 +740,21 @@ k_slot_caps(int64_t n_groups, const uint32_t* __restrict__ cnt_e,
   if (g >= n_groups) return;
   const uint64_t me = red[kRedEpj] / (uint64_t)n_groups + 32u;
   const uint64_t ms = red[kRedSpj] / (uint64_t)n_groups + 32u;
-  const uint64_t ce = 2u * (uint64_t)cnt_e[g] + me;
-  const uint64_t cs = 2u * (uint64_t)cnt_s[g] + ms;
+  const uint64_t ce = 3u * (uint64_t)cnt_e[g] + me;
+  const uint64_t cs = 3u * (uint64_t)cnt_s[g] + ms;
   cap_e[g] = ce < 0xFFFFFFFFull ? (uint32_t)ce : 0xFFFFFFFFu;
   cap_s[g] = cs < 0xFFFFFFFFull ? (uint32_t)cs : 0xFFFFFFFFu;
+}
+
+// Room of each refresh-walk lane: twice its tokens at construction plus
+// kLaneSpare, rounded up to whole 64-byte segments.
+__global__ void __launch_bounds__(256)
+k_lane_room(int64_t n, const uint32_t* __restrict__ cnt_tl,
+            uint32_t* __restrict__ cap) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t r = (2ull * cnt_tl[i] + kLaneSpare + 15ull) & ~15ull;
+  cap[i] = r < 0xFFFFFFF0ull ? (uint32_t)r : 0xFFFFFFF0u;
 }
 
 // Per-force-call counters of refresh mode (see kRed*).
@@ -937,110 +992,91 @@ int launch_check_lists(nb_ctx* c, unsigned* flag) {
   return hip_check(c, hipGetLastError(), "list check launch");
 }
 
-// Whether a walk over n_walk groups runs two lanes per group (k_walk_c),
-// whose slab mode takes two slabs per group.
+// Whether a walk over n_walk groups runs kSplitLanes lanes per group
+// (k_walk_c, and k_walk_r in refresh mode), whose slab mode takes that many
+// slabs per group.
 bool split_walk(const nb_ctx* c, int64_t n_walk) {
-  return !c->learn && walk_tile(n_walk) == 1;
+  return c->learn || walk_tile(n_walk) == 1;
 }
 
-// Lanes per group of a walk over n_walk groups (see kThreadWalkFrom).
-int walk_tile(int64_t n_walk, bool refresh) {
-  if (n_walk >= (refresh ? kThreadWalkFromRefresh : kThreadWalkFrom)) return 1;
+// Lanes per tile of a walk over n_walk groups (1: split walk; see
+// kThreadWalkFrom).
+int walk_tile(int64_t n_walk) {
+  if (n_walk >= kThreadWalkFrom) return 1;
   int w = kTileWalk;
   while (w < 64 && (int64_t)w * n_walk < kTileLanes) w <<= 1;
   return w;
 }
 
 template <int W>
-static void tile_launch(nb_ctx* c, bool fill, bool learn, int64_t launch,
-                        int64_t n_walk, int64_t nblk, const uint32_t* sel,
-                        const double4* lo, const double4* hi, uint32_t slab,
-                        const WalkOut& o) {
-  auto k = fill ? (learn ? k_walk_tile<W, true, true>
-                         : k_walk_tile<W, true, false>)
-                : (learn ? k_walk_tile<W, false, true>
-                         : k_walk_tile<W, false, false>);
+static void tile_launch(nb_ctx* c, bool fill, int64_t launch, int64_t n_walk,
+                        int64_t nblk, const double4* lo, const double4* hi,
+                        uint32_t slab) {
+  auto k = fill ? k_walk_tile<W, true> : k_walk_tile<W, false>;
   hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(256), 0, c->stream,
-                     n_walk, nblk, sel, (const uint32_t*)c->g_begin.p,
+                     n_walk, nblk, (const uint32_t*)c->g_begin.p,
                      (const uint32_t*)c->g_count.p, lo, hi,
-                     (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
-                     (const uint32_t*)c->g_cell.p,
-                     (const double4*)c->c_shift.p, o.sa, o.so, o.tau0,
-                     (const uint32_t*)c->seg.p, (const uint32_t*)c->croot.p,
-                     o.cnt_e, o.cnt_s, o.cnt_t,
-                     (const uint64_t*)c->tok_off.p, c->tok.p, slab, o.n_dev,
-                     o.slot_state);
+                     (const CellRec*)c->c_rec.p, (const uint32_t*)c->seg.p,
+                     (const uint32_t*)c->croot.p, c->cnt_e.p, c->cnt_s.p,
+                     c->cnt_t.p, (const uint64_t*)c->tok_off.p, c->tok.p,
+                     slab);
 }
 
-static int launch_tile(nb_ctx* c, int w, bool fill, bool learn,
-                       int64_t launch, int64_t n_walk, int64_t nblk,
-                       const uint32_t* sel, const double4* lo,
-                       const double4* hi, uint32_t slab, const WalkOut& o) {
+static void launch_tile(nb_ctx* c, int w, bool fill, int64_t launch,
+                        int64_t n_walk, int64_t nblk, const double4* lo,
+                        const double4* hi, uint32_t slab) {
   switch (w) {
-    case 2: tile_launch<2>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
-    case 4: tile_launch<4>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
-    case 8: tile_launch<8>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
-    case 16: tile_launch<16>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
-    case 32: tile_launch<32>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
-    default: tile_launch<64>(c, fill, learn, launch, n_walk, nblk, sel, lo, hi, slab, o); break;
+    case 4: tile_launch<4>(c, fill, launch, n_walk, nblk, lo, hi, slab); break;
+    case 8: tile_launch<8>(c, fill, launch, n_walk, nblk, lo, hi, slab); break;
+    case 16: tile_launch<16>(c, fill, launch, n_walk, nblk, lo, hi, slab); break;
+    case 32: tile_launch<32>(c, fill, launch, n_walk, nblk, lo, hi, slab); break;
+    default: tile_launch<64>(c, fill, launch, n_walk, nblk, lo, hi, slab); break;
   }
-  return NB_OK;
 }
 
-static WalkOut group_out(nb_ctx* c) {
-  return WalkOut{c->cnt_e.p, c->cnt_s.p, c->cnt_t.p, c->g_sa.p, c->g_so.p,
-                 c->g_tau0.p, nullptr, 0};
-}
-
-// The refresh-mode walk (LEARN) over up to n_walk selected groups, lanes per
-// group from walk_tile(hint), outputs as o says.
-static int launch_learn_walk(nb_ctx* c, bool fill, int64_t n_walk,
-                             const uint32_t* sel, const double4* lo,
-                             const double4* hi, uint32_t slab,
-                             const WalkOut& o, int64_t hint) {
-  const int w = walk_tile(hint, true);
-  if (w > 1) {
-    const int64_t nblk = grid_for(n_walk, 256 / w);
-    const int64_t launch = (nblk + 7) / 8 * 8;
-    return launch_tile(c, w, fill, true, launch, n_walk, nblk, sel, lo, hi,
-                       slab, o);
-  }
-  const int64_t nblk = grid_for(n_walk, kWalkThreads);
+// k_walk_r over n_walk slots (selected groups when sel is given, their
+// number *o.n_dev on the device), outputs as o says.
+static void launch_walk_r(nb_ctx* c, bool fill, int64_t n_walk,
+                          const uint32_t* sel, const double4* lo,
+                          const double4* hi, const WalkOut& o,
+                          const uint64_t* lane_off, uint32_t slab) {
+  const int64_t nblk = grid_for(kSplitLanes * n_walk, kWalkThreads);
   const int64_t launch = (nblk + 7) / 8 * 8;
-  auto k = fill ? k_walk<true, true> : k_walk<false, true>;
+  auto k = fill ? k_walk_r<true, kSplitLanes> : k_walk_r<false, kSplitLanes>;
   hipLaunchKernelGGL(k, dim3((unsigned)launch), dim3(kWalkThreads), 0,
-                     c->stream, n_walk, nblk, sel,
+                     c->stream, n_walk, nblk, sel, o.n_dev,
                      (const uint32_t*)c->g_begin.p,
                      (const uint32_t*)c->g_count.p, lo, hi,
-                     (const CellRec*)c->c_rec.p, (const double4*)c->c_ctr.p,
-                     (const uint32_t*)c->g_cell.p,
-                     (const double4*)c->c_shift.p, o.sa, o.so, o.tau0,
-                     (const uint32_t*)c->seg.p, (const uint32_t*)c->croot.p,
-                     o.cnt_e, o.cnt_s, o.cnt_t, (const uint64_t*)c->tok_off.p,
-                     c->tok.p, slab, o.n_dev, o.slot_state);
-  return NB_OK;
+                     (const uint32_t*)c->g_cell.p, (const CellRec*)c->c_rec.p,
+                     (const uint4*)c->c_wrec.p, (const double4*)c->c_ctr.p,
+                     (const double4*)c->c_shift.p, (const uint32_t*)c->seg.p,
+                     (const uint32_t*)c->croot.p, o.cnt_e, o.cnt_s, o.cnt_t,
+                     c->cnt_tl.p, o.sa, o.so, o.tau0, lane_off,
+                     (const uint64_t*)c->tok_off.p, c->tok.p, slab);
 }
 
 int launch_walk_refresh(nb_ctx* c, int64_t n_max, const uint32_t* sel,
-                        const double4* lo, const double4* hi, uint32_t slab,
-                        const WalkOut& o, int64_t hint) {
+                        const double4* lo, const double4* hi,
+                        const WalkOut& o) {
   if (c->n_cell >= (int64_t)kLeafTag)
     return set_err(c, NB_ERR_INPUT, "too many cells for 31-bit list tokens");
   if (n_max <= 0) return NB_OK;
-  int rc = launch_learn_walk(c, true, n_max, sel, lo, hi, slab, o, hint);
-  return rc ? rc : hip_check(c, hipGetLastError(), "refresh walk launch");
+  launch_walk_r(c, true, n_max, sel, lo, hi, o,
+                (const uint64_t*)c->lane_off.p, 0u);
+  return hip_check(c, hipGetLastError(), "refresh walk launch");
 }
 
 int launch_expand_sel(nb_ctx* c, int64_t n_max, const uint32_t* sel,
-                      uint32_t slab, const uint32_t* cnt_t,
                       const uint32_t* n_dev, const uint8_t* ok) {
   if (n_max <= 0) return NB_OK;
   const int64_t eblk = grid_for(n_max, 4);
   const int64_t elaunch = (eblk + 7) / 8 * 8;
   hipLaunchKernelGGL(k_expand, dim3((unsigned)elaunch), dim3(256), 0,
                      c->stream, n_max, eblk, sel, (const uint64_t*)nullptr,
-                     slab, cnt_t, (const uint32_t*)nullptr, 1,
-                     (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
+                     (const uint64_t*)c->lane_off.p, 0u,
+                     (const uint32_t*)nullptr, (const uint32_t*)c->cnt_tl.p,
+                     kSplitLanes, (const uint32_t*)c->tok.p,
+                     (const CellRec*)c->c_rec.p,
                      (const uint64_t*)c->epj_off.p,
                      (const uint64_t*)c->spj_off.p, c->epj.p, c->spj.p, n_dev,
                      ok);
@@ -1056,7 +1092,7 @@ int launch_walk(nb_ctx* c, bool fill, uint32_t slab) {
   if (!rc) rc = reserve(c, c->spj_off, ng + 1);
   if (!rc) rc = reserve(c, c->tok_off, ng + 1);
   if (rc) return rc;
-  return launch_walk_sel(c, fill, c->n_groups, nullptr, c->g_lo.p, c->g_hi.p,
+  return launch_walk_sel(c, fill, c->n_groups, c->g_lo.p, c->g_hi.p,
                          c->epj_off.p, c->spj_off.p, c->epj.p, c->spj.p,
                          slab);
 }
@@ -1067,8 +1103,8 @@ int launch_expand_slab(nb_ctx* c, uint32_t slab) {
   const int64_t elaunch = (eblk + 7) / 8 * 8;
   hipLaunchKernelGGL(k_expand, dim3((unsigned)elaunch), dim3(256), 0,
                      c->stream, c->n_groups, eblk, (const uint32_t*)nullptr,
-                     (const uint64_t*)c->tok_off.p, slab,
-                     (const uint32_t*)c->cnt_t.p,
+                     (const uint64_t*)c->tok_off.p, (const uint64_t*)nullptr,
+                     slab, (const uint32_t*)c->cnt_t.p,
                      (const uint32_t*)(c->walk_split ? c->cnt_tl.p : nullptr),
                      kSplitLanes, (const uint32_t*)c->tok.p,
                      (const CellRec*)c->c_rec.p,
@@ -1078,33 +1114,29 @@ int launch_expand_slab(nb_ctx* c, uint32_t slab) {
   return hip_check(c, hipGetLastError(), "expand launch");
 }
 
-
-
-int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
-                    const double4* lo, const double4* hi,
-                    const uint64_t* epj_off, const uint64_t* spj_off,
-                    uint32_t* epj, uint32_t* spj, uint32_t slab) {
+int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const double4* lo,
+                    const double4* hi, const uint64_t* epj_off,
+                    const uint64_t* spj_off, uint32_t* epj, uint32_t* spj,
+                    uint32_t slab) {
   if (c->n_cell >= (int64_t)kLeafTag)
     return set_err(c, NB_ERR_INPUT, "too many cells for 31-bit list tokens");
   if (n_walk <= 0) return NB_OK;
   int rc = NB_OK;
-  const bool learn = c->learn;
-  if (!learn && sel) return set_err(c, NB_ERR_STATE, "selected walk needs refresh mode");
-  const int w = walk_tile(n_walk, learn);
   c->walk_split = split_walk(c, n_walk);
-  if (learn) {
-    rc = launch_learn_walk(c, fill, n_walk, sel, lo, hi, slab, group_out(c),
-                           n_walk);
-    if (rc) return rc;
-  } else if (w > 1) {
+  if (c->walk_split &&
+      (rc = reserve(c, c->cnt_tl, (size_t)kSplitLanes * n_walk)))
+    return rc;
+  if (c->learn) {
+    // refresh mode: moved-centre geometry, slacks and shifts per group
+    const WalkOut o{c->cnt_e.p, c->cnt_s.p, c->cnt_t.p, c->g_sa.p,
+                    c->g_so.p, c->g_tau0.p, nullptr};
+    launch_walk_r(c, fill, n_walk, nullptr, lo, hi, o, nullptr, slab);
+  } else if (!c->walk_split) {
+    const int w = walk_tile(n_walk);
     const int64_t nblk = grid_for(n_walk, 256 / w);
     const int64_t launch = (nblk + 7) / 8 * 8;
-    rc = launch_tile(c, w, fill, learn, launch, n_walk, nblk, sel, lo, hi,
-                     slab, group_out(c));
-    if (rc) return rc;
+    launch_tile(c, w, fill, launch, n_walk, nblk, lo, hi, slab);
   } else {
-    // kSplitLanes lanes per group
-    if ((rc = reserve(c, c->cnt_tl, (size_t)kSplitLanes * n_walk))) return rc;
     const int64_t nblk = grid_for(kSplitLanes * n_walk, kWalkThreads);
     const int64_t launch = (nblk + 7) / 8 * 8;
     auto kw = fill ? k_walk_c<true, kSplitLanes>
@@ -1125,10 +1157,10 @@ int launch_walk_sel(nb_ctx* c, bool fill, int64_t n_walk, const uint32_t* sel,
   const int64_t eblk = grid_for(n_walk, 4);
   const int64_t elaunch = (eblk + 7) / 8 * 8;
   hipLaunchKernelGGL(k_expand, dim3((unsigned)elaunch), dim3(256), 0,
-                     c->stream, n_walk, eblk, sel,
-                     (const uint64_t*)c->tok_off.p, 0u,
-                     (const uint32_t*)c->cnt_t.p, (const uint32_t*)nullptr, 1,
-                     (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
+                     c->stream, n_walk, eblk, (const uint32_t*)nullptr,
+                     (const uint64_t*)c->tok_off.p, (const uint64_t*)nullptr,
+                     0u, (const uint32_t*)c->cnt_t.p, (const uint32_t*)nullptr,
+                     1, (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
                      epj_off, spj_off, epj, spj, (const uint32_t*)nullptr,
                      (const uint8_t*)nullptr);
   return hip_check(c, hipGetLastError(), "expand launch");
@@ -1154,6 +1186,7 @@ int launch_list_stats(nb_ctx* c) {
     if (!rc) rc = scan_u32_to_u64(c, c->cnt_s.p, c->spj_off.p, c->n_groups);
   }
   if (!rc) rc = scan_u32_to_u64(c, c->cnt_t.p, c->tok_off.p, c->n_groups);
+  if (!rc && c->learn) rc = launch_lane_room(c);
   if (rc) return rc;
   unsigned nb = grid_for(c->n_groups, 256);
   if (nb > 1024) nb = 1024;
@@ -1164,6 +1197,18 @@ int launch_list_stats(nb_ctx* c) {
                      (const uint32_t*)(lanes ? c->cnt_tl.p : c->cnt_t.p),
                      (unsigned long long*)c->red.p + 1);
   return hip_check(c, hipGetLastError(), "list max launch");
+}
+
+int launch_lane_room(nb_ctx* c) {
+  const int64_t n = (int64_t)kSplitLanes * c->n_groups;
+  int rc = reserve(c, c->lane_cap, (size_t)n);
+  if (!rc) rc = reserve(c, c->lane_off, (size_t)n + 1);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_lane_room, dim3(grid_for(n, 256)), dim3(256), 0,
+                     c->stream, n, (const uint32_t*)c->cnt_tl.p,
+                     c->lane_cap.p);
+  rc = hip_check(c, hipGetLastError(), "lane room launch");
+  return rc ? rc : scan_u32_to_u64(c, c->lane_cap.p, c->lane_off.p, n);
 }
 
 int launch_accum(nb_ctx* c, bool refresh_step) {
@@ -1248,7 +1293,8 @@ int launch_nbr_fill(nb_ctx* c, double h) {
   hipLaunchKernelGGL(k_expand, dim3((unsigned)((eblk + 7) / 8 * 8)),
                      dim3(256), 0, c->stream, c->n_groups, eblk,
                      (const uint32_t*)nullptr, (const uint64_t*)c->nb_toff.p,
-                     0u, (const uint32_t*)c->nb_tcnt.p, (const uint32_t*)nullptr,
+                     (const uint64_t*)nullptr, 0u,
+                     (const uint32_t*)c->nb_tcnt.p, (const uint32_t*)nullptr,
                      1, (const uint32_t*)c->tok.p, (const CellRec*)c->c_rec.p,
                      (const uint64_t*)c->nb_off.p,
                      (const uint64_t*)c->nb_off.p, c->nb_ids.p,

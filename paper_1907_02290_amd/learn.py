@@ -34,10 +34,12 @@ def _torch():
 
 
 def make_context(d, theta, eps, n_leaf=8, n_grp=64, order=1, ext_mass=0.0,
-                 k_max=16, p_star=0.5, tau=0.1, offsets=None, timing=False):
+                 k_max=16, p_star=0.5, tau=0.1, offsets=None, timing=False,
+                 graph=False):
     ctx = nb.Context(theta=theta, eps=eps, n_leaf=n_leaf, n_grp=n_grp,
                      order=order, ext_mass=ext_mass, refresh=True,
-                     k_max=k_max, p_star=p_star, tau=tau, timing=timing)
+                     k_max=k_max, p_star=p_star, tau=tau, timing=timing,
+                     graph=graph)
     ctx.set_particles(d["x"], d["y"], d["z"], d["vx"], d["vy"], d["vz"],
                       d["m"])
     if offsets is not None:
@@ -146,10 +148,12 @@ def run_policy(ctx, policy, steps, dt, k, tau=None, check=None,
     called at step 0, at every ``check_every``-th step and at the last one.
     Both happen outside the timed steps.  ``rebuild_frac`` (refresh
     policies): when a step walks more than that fraction of the groups
-    again, the next step is a construction step.  Returns ms/step, list walks
+    again, or a walked-again list did not fit its group's list slot, the
+    next step is a construction step.  Returns ms/step, list walks
     per step (all groups at a construction step, refreshed groups
-    otherwise), construction steps, stale fractions and the check results
-    (a list of dicts)."""
+    otherwise), construction steps, the rebuilds each trigger asked for,
+    the refreshed and overflowed groups of every step, stale fractions and
+    the check results (a list of dicts)."""
     import torch
     times = []
     stale = []
@@ -171,6 +175,8 @@ def run_policy(ctx, policy, steps, dt, k, tau=None, check=None,
         checks.append(dict(step=0, **check(ctx)))
     since = 0
     rebuild_next = False
+    by_frac = by_overflow = 0
+    per_step = []
     reuse_mode = {"fixed": nb.NB_REUSE_LIST, "learned": nb.NB_REUSE_REFRESH,
                   "checked": nb.NB_REUSE_CHECK}[policy]
     for s in range(1, steps + 1):
@@ -187,10 +193,17 @@ def run_policy(ctx, policy, steps, dt, k, tau=None, check=None,
             constructions += 1
         elif policy != "fixed":
             r = info["last_refreshed"]
+            ovf = info["last_overflow"]
             walks += r
             refreshed += r
+            per_step.append((s, r, ovf))
             if rebuild_frac is not None:
-                rebuild_next = r > rebuild_frac * info["n_groups"]
+                # too many lists to walk again, or a walked list that no
+                # longer fits its slot: the tree has aged, build a new one
+                frac = r > rebuild_frac * info["n_groups"]
+                rebuild_next = frac or ovf > 0
+                by_frac += int(frac)
+                by_overflow += int(ovf > 0 and not frac)
             if tau is not None:
                 stale.append(float(np.mean(ctx.group_stale(tau))))
         elif tau is not None:
@@ -200,6 +213,8 @@ def run_policy(ctx, policy, steps, dt, k, tau=None, check=None,
     return dict(policy=policy, k=k, steps=steps,
                 ms_per_step=1e3 * float(np.sum(times)) / len(times),
                 construction_steps=constructions,
+                rebuilds_by_fraction=by_frac, rebuilds_by_overflow=by_overflow,
+                refresh_steps=per_step,
                 walks_per_step=walks / len(times),
                 walk_fraction=walks / len(times) / max(1, ng),
                 refreshed=refreshed,

@@ -138,19 +138,20 @@ def _refresh_many(d, n_grp, min_groups, min_sel):
         assert ctx.get_info()["last_refreshed"] == sel.size
 
 
-def test_refresh_mode_tile_walk_many_groups():
-    """Refresh-mode walks over 8192 or more groups (the construction walk
-    and a large refresh selection) run in lane tiles; their lists and the
-    opening-test slacks they record must be the oracle's."""
-    say("case refresh mode, tile walk over many groups")
+def test_refresh_mode_walk_many_groups():
+    """Refresh-mode walks (several lanes per group, cut at the group's
+    ancestors) over 8192 or more groups: the construction walk and a
+    refresh of 8192 or more groups; their lists and the opening-test slacks
+    they record must be the oracle's."""
+    say("case refresh mode, walk over many groups")
     _refresh_many(sheared(200000, 4), 16, 8192, 8192)
 
 
-def test_refresh_mode_thread_walk_over_65536_groups():
-    """From 65536 groups on, refresh-mode walks run one thread per group:
-    the construction walk and a selection of more than 65536 groups, with
-    their slacks, against the oracle."""
-    say("case refresh mode, one-thread walk over 65536+ groups")
+def test_refresh_mode_walk_over_65536_groups():
+    """The refresh-mode construction walk over more than 65536 groups and a
+    refresh of more than 65536 of them, with their slacks, against the
+    oracle."""
+    say("case refresh mode, walk over 65536+ groups")
     _refresh_many(sheared(500000, 6), 8, 1 << 16, 1 << 16)
 
 

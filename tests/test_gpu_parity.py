@@ -153,10 +153,10 @@ def test_lists_bit_exact_theta_and_sizes(theta, n_leaf, n_grp):
     ("plummer", 20000, 1, 1, 1.0), ("plummer", 40000, 2, 4, 0.3),
     ("clustered", 60000, 1, 2, 0.5), ("disk", 60000, 4, 4, 0.7),
     ("ring", 50000, 8, 4, 0.5)])
-def test_lists_bit_exact_one_thread_walk(kind, n, n_leaf, n_grp, theta):
-    """Enough groups for the one-thread-per-group walk (over the 16-byte
-    walk records), whole lists against the oracle."""
-    say("case one-thread walk %s n=%d n_leaf=%d n_grp=%d theta=%g"
+def test_lists_bit_exact_split_walk(kind, n, n_leaf, n_grp, theta):
+    """Enough groups for the split walk (several lanes per group over the
+    16-byte walk records), whole lists against the oracle."""
+    say("case split walk %s n=%d n_leaf=%d n_grp=%d theta=%g"
         % (kind, n, n_leaf, n_grp, theta))
     d = system(kind, n)
     with gpu_ctx(d, theta=theta, n_leaf=n_leaf, n_grp=n_grp) as ctx:
