@@ -122,7 +122,15 @@ enum {
    * per-group contiguous array (16 bytes per entry), and the force kernel
    * reads that.  Same forces bit for bit.  Order 1 only, not with
    * NB_FLAG_REFRESH or NB_FLAG_PERSISTENT (NB_ERR_INPUT). */
-  NB_FLAG_COPIED_LISTS = 16
+  NB_FLAG_COPIED_LISTS = 16,
+  /* Multipole moments (section 4.3, recomputed at every step) with one
+   * launch per tree level, leaves first, as the level-by-level link order
+   * suggests; without it they take two launches (subtrees of at most 512
+   * cells per workgroup in LDS, then the cells above them by one workgroup
+   * through a table of child ids).  Both form every sum in the same order
+   * and precision: the moments, and so the forces, are the same bit for
+   * bit.  Kept for that comparison. */
+  NB_FLAG_LEVEL_MOMENTS = 32
 };
 
 /* Rebuild predictor: inputs per group and parameter count of the

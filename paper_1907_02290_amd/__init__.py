@@ -8,7 +8,8 @@ from .nbody import (Context, NbError, NB_MAKE_LIST, NB_MAKE_LIST_FOR_REUSE,
                     NB_REUSE_LIST, NB_REUSE_REFRESH, NB_REUSE_CHECK, NB_OK,
                     NB_ERR_INPUT, NB_ERR_OOM, NB_ERR_LIST, NB_ERR_STATE,
                     NB_ERR_HIP, NB_FLAG_TIMING, NB_FLAG_GRAPH,
-                    NB_FLAG_REFRESH, NB_FLAG_PERSISTENT, NB_FLAG_COPIED_LISTS, MLP_NIN,
+                    NB_FLAG_REFRESH, NB_FLAG_PERSISTENT, NB_FLAG_COPIED_LISTS,
+                    NB_FLAG_LEVEL_MOMENTS, MLP_NIN,
                     MLP_NPARAM, MLP_STATIC_MAX_ROWS, PHASES, load,
                     version, LIB_PATH)
 
@@ -16,5 +17,5 @@ __all__ = ["Context", "NbError", "NB_MAKE_LIST", "NB_MAKE_LIST_FOR_REUSE",
            "NB_REUSE_LIST", "NB_REUSE_REFRESH", "NB_REUSE_CHECK", "NB_OK",
            "NB_ERR_INPUT", "NB_ERR_OOM", "NB_ERR_LIST", "NB_ERR_STATE",
            "NB_ERR_HIP", "NB_FLAG_TIMING", "NB_FLAG_GRAPH", "NB_FLAG_REFRESH",
-           "NB_FLAG_PERSISTENT", "NB_FLAG_COPIED_LISTS",
+           "NB_FLAG_PERSISTENT", "NB_FLAG_COPIED_LISTS", "NB_FLAG_LEVEL_MOMENTS",
            "MLP_NIN", "MLP_NPARAM", "MLP_STATIC_MAX_ROWS", "PHASES", "load", "version", "LIB_PATH"]

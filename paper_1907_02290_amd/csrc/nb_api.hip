@@ -197,10 +197,12 @@ static int build_tree(nb_ctx* c) {
     Timed t(c, NB_PH_GROUPS);
     if ((rc = launch_group_flags(c))) return rc;
     if ((rc = launch_level_lists(c))) return rc;
+    if ((rc = launch_mom_plan(c))) return rc;
   }
   // sync 2: where each level starts in the level lists (the leaves are
-  // bucket kLevels) and the group count
-  if ((rc = stage_d2h(c, 0, c->lvl_stage.p, (kLevels + 2) * sizeof(uint32_t))))
+  // bucket kLevels), the group count, and the block and top-cell counts of
+  // the moment pass
+  if ((rc = stage_d2h(c, 0, c->lvl_stage.p, (kLevels + 4) * sizeof(uint32_t))))
     return rc;
   if ((rc = sync(c))) return rc;
   {
@@ -214,6 +216,8 @@ static int build_tree(nb_ctx* c) {
     }
     c->n_leaves = c->lvl_count[kLevels];
     c->n_groups = h[kLevels + 1];
+    c->mp_nblk = h[kLevels + 2];
+    c->mp_ntop = h[kLevels + 3];
     if (c->n_groups < 1 || h[0] != 0)
       return set_err(c, NB_ERR_HIP, "inconsistent tree (%lld groups)",
                      (long long)c->n_groups);
@@ -400,6 +404,8 @@ void nb_destroy(nb_ctx* c) {
   release(c->c_rec); release(c->c_wrec);
   release(c->c_mom); release(c->c_quad); release(c->c_pm);
   release(c->lvl_cells); release(c->bucket);
+  release(c->mp_bflag); release(c->mp_tflag); release(c->mp_blocks);
+  release(c->mp_top); release(c->mp_tlo); release(c->mp_ctab);
   release(c->gflag); release(c->g_cell); release(c->g_begin);
   release(c->g_count); release(c->g_lo); release(c->g_hi);
   release(c->g_chunks); release(c->wi); release(c->queue);

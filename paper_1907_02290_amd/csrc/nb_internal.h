@@ -169,6 +169,12 @@ struct nb_ctx {
   nb::DBuf<uint32_t> lvl_cells;  // cell ids grouped by level, leaves last
   nb::DBuf<uint32_t> bucket;     // per-block level histograms, scanned
   nb::DBuf<uint32_t> lvl_stage;  // level starts and group count, for the host
+  // moments in two launches: blocks (maximal subtrees of at most
+  // kMomBlock cells, by root id) and the cells above them (top cells, by
+  // level; tlo = where each level starts) with their child table (8 ids per
+  // top cell, by octant); the scanned flags that made them; their counts
+  nb::DBuf<uint32_t> mp_bflag, mp_tflag, mp_blocks, mp_top, mp_tlo, mp_ctab;
+  int64_t mp_nblk = 0, mp_ntop = 0;
 
   // groups
   nb::DBuf<uint32_t> gflag;  // n_cell + 1, scanned
@@ -330,6 +336,9 @@ int launch_reorder(nb_ctx* c);
 int launch_link_count(nb_ctx* c);
 int launch_link_fill(nb_ctx* c);
 int launch_level_lists(nb_ctx* c);  // enqueues; no host sync
+// blocks and top cells of the two-launch moments, after the level lists;
+// stages their counts after the level starts and group count
+int launch_mom_plan(nb_ctx* c);
 int launch_moments(nb_ctx* c);
 int launch_group_flags(nb_ctx* c);
 int launch_sys_roots(nb_ctx* c);

@@ -679,6 +679,518 @@ k_mom_internal(int64_t cnt, const uint32_t* __restrict__ list,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Moments in two launches instead of one per level.  A block is a maximal
+// subtree of at most kMomBlock cells (its cells are a contiguous stretch of
+// the pre-order array); one workgroup computes a block bottom-up in LDS,
+// leaves from their particles, then one level per barrier, and writes the
+// block's moments out at the end.  The cells above the blocks (subtrees of
+// more than kMomBlock cells, the "top" cells) are then summed by a single
+// workgroup, level by level, each reading its children through a table of
+// child ids by octant (top children from LDS).  Every cell's sums are formed
+// in the same order and precision as the per-level kernels above (leaves:
+// four interleaved partial sums added pairwise; internal cells: children in
+// pre-order), so the moments are the same bit for bit.
+constexpr int kMomBlock = 1024;
+constexpr int kMomThreads = 256;
+constexpr int kMomPer = kMomBlock / kMomThreads;
+constexpr int kMomTopThreads = 1024;
+// top cells kept in LDS by the top launch, monopole (half with quadrupoles;
+// more: it works from global memory); the child table marks a child that is a top cell with kTopTag
+// and its position in the top list
+constexpr int kMomTopLds = 2048;
+constexpr uint32_t kTopTag = 0x80000000u;
+// particles of a leaf loaded together
+constexpr int kLeafChunk = 8;
+
+__device__ inline uint32_t subtree_cells(const uint4 m, uint32_t c) {
+  return m.z - c;  // the skip id is always past the cell
+}
+
+// Block roots: at most kMomBlock cells in the subtree, and a system root or
+// a parent with more.
+__global__ void __launch_bounds__(256)
+k_mp_flags(int64_t n_cell, const CellRec* __restrict__ rec,
+           uint32_t* __restrict__ bflag) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cell) return;
+  const uint4 m = rec[c].meta;
+  bool root = subtree_cells(m, (uint32_t)c) <= (uint32_t)kMomBlock;
+  if (root && (m.w & 255u) != 0) {
+    const uint32_t p = rec[c].aux.x;
+    root = subtree_cells(rec[p].meta, p) > (uint32_t)kMomBlock;
+  }
+  bflag[c] = root ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256)
+k_mp_blocks(int64_t n_cell, const uint32_t* __restrict__ bscan,
+            uint32_t* __restrict__ blocks) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cell) return;
+  const uint32_t b = bscan[c];
+  if (bscan[c + 1] != b) blocks[b] = (uint32_t)c;
+}
+
+// Top cells over the level-sorted cell list (leaves, never top, come last).
+__global__ void __launch_bounds__(256)
+k_mp_tflags(int64_t n_cell, const uint32_t* __restrict__ lvl,
+            const CellRec* __restrict__ rec, uint32_t* __restrict__ tflag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cell) return;
+  const uint32_t c = lvl[i];
+  tflag[i] = subtree_cells(rec[c].meta, c) > (uint32_t)kMomBlock ? 1u : 0u;
+}
+
+// Top list by level (ascending), and each top cell's position in it
+// (rec.aux.y), by which the child table is indexed.
+__global__ void __launch_bounds__(256)
+k_mp_top(int64_t n_cell, const uint32_t* __restrict__ lvl,
+         const uint32_t* __restrict__ tscan, uint32_t* __restrict__ top,
+         int64_t top_cap, CellRec* __restrict__ rec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_cell) return;
+  const uint32_t j = tscan[i];
+  if (tscan[i + 1] == j || (int64_t)j >= top_cap) return;
+  const uint32_t c = lvl[i];
+  top[j] = c;
+  rec[c].aux.y = j;
+}
+
+// Where each level starts in the top list (tlo[0 .. kLevels]; the level
+// buckets start at bstart[0 .. kLevels], leaves last), and the block and top
+// counts for the host (stage[0], stage[1]); clears the child table.
+__global__ void __launch_bounds__(256)
+k_mp_tlo(int64_t n_cell, const uint32_t* __restrict__ bstart,
+         const uint32_t* __restrict__ tscan,
+         const uint32_t* __restrict__ bscan, uint32_t* __restrict__ tlo,
+         uint32_t* __restrict__ stage, uint32_t* __restrict__ ctab,
+         int64_t top_cap) {
+  // (top_cap bounds the top cells; a count past it would be a broken tree:
+  // the list is cut there, so that no launch reads past the buffers)
+  const uint32_t n_top = (int64_t)tscan[n_cell] < top_cap
+                             ? tscan[n_cell] : (uint32_t)top_cap;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t <= kLevels) {
+    const uint32_t v = tscan[bstart[t] < n_cell ? bstart[t] : n_cell];
+    tlo[t] = v < n_top ? v : n_top;
+  }
+  if (t == 0) {
+    stage[0] = bscan[n_cell];
+    stage[1] = n_top;
+  }
+  for (int64_t k = t; k < 8 * (int64_t)n_top;
+       k += (int64_t)gridDim.x * blockDim.x)
+    ctab[k] = kNone;
+}
+
+// Child table of the top cells: slot 8 j + octant of the top cell at
+// position j holds that child: its id, or kTopTag | its position when it is
+// a top cell itself (kNone: no child there).  The octant comes from the
+// child's integer coordinates (x the high bit), so slot order is pre-order.
+__global__ void __launch_bounds__(256)
+k_mp_ctab(int64_t n_cell, const CellRec* __restrict__ rec,
+          const uint4* __restrict__ wrec, uint32_t* __restrict__ ctab,
+          int64_t ctab_cap) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cell) return;
+  const uint4 m = rec[c].meta;
+  if ((m.w & 255u) == 0) return;
+  const uint32_t p = rec[c].aux.x;
+  if (subtree_cells(rec[p].meta, p) <= (uint32_t)kMomBlock) return;
+  const uint4 w = wrec[c];
+  const uint64_t q = (uint64_t)w.x | ((uint64_t)(w.y & 0x7FFFFFFFu) << 32);
+  const uint32_t oct = (uint32_t)(((q & 1u) << 2) | (((q >> 21) & 1u) << 1) |
+                                  ((q >> 42) & 1u));
+  const int64_t slot = 8 * (int64_t)rec[p].aux.y + oct;
+  const bool is_top = subtree_cells(m, (uint32_t)c) > (uint32_t)kMomBlock;
+  if (slot < ctab_cap)
+    ctab[slot] = is_top ? (kTopTag | rec[c].aux.y) : (uint32_t)c;
+}
+
+// A leaf's sums from its particles: the four interleaved partial sums of
+// k_mom_leaf's lanes (particle i of the leaf goes to sum i % 4), added
+// pairwise as its exchanges add them.  The particles are loaded eight at a
+// time, so that a leaf waits for one load latency per eight.
+template <bool QUAD>
+__device__ __forceinline__ void leaf_sums(const uint4 m, const double4 g,
+                                          const double4* __restrict__ pos,
+                                          float4& mo, float4& qa,
+                                          float4& qb) {
+  float pM[4] = {0.f, 0.f, 0.f, 0.f}, px[4] = {0.f, 0.f, 0.f, 0.f},
+        py[4] = {0.f, 0.f, 0.f, 0.f}, pz[4] = {0.f, 0.f, 0.f, 0.f};
+  for (uint32_t b = m.x; b < m.y; b += kLeafChunk) {
+    double4 P[kLeafChunk];
+#pragma unroll
+    for (int i = 0; i < kLeafChunk; ++i)
+      if (b + i < m.y) P[i] = pos[b + i];
+#pragma unroll
+    for (int i = 0; i < kLeafChunk; ++i) {
+      if (b + i >= m.y) break;
+      const int s = i & (kLeafLanes - 1);
+      const float w = (float)P[i].w;
+      const float dx = (float)(P[i].x - g.x), dy = (float)(P[i].y - g.y),
+                  dz = (float)(P[i].z - g.z);
+      pM[s] += w;
+      px[s] = fmaf(w, dx, px[s]);
+      py[s] = fmaf(w, dy, py[s]);
+      pz[s] = fmaf(w, dz, pz[s]);
+    }
+  }
+  const float M = (pM[0] + pM[1]) + (pM[2] + pM[3]);
+  const float sx = (px[0] + px[1]) + (px[2] + px[3]);
+  const float sy = (py[0] + py[1]) + (py[2] + py[3]);
+  const float sz = (pz[0] + pz[1]) + (pz[2] + pz[3]);
+  const float inv = M > 0.f ? 1.0f / M : 0.f;
+  const float ox = sx * inv, oy = sy * inv, oz = sz * inv;
+  mo = make_float4(ox, oy, oz, M);
+  if (!QUAD) return;
+  float q[6][4];
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) q[k][s] = 0.f;
+  for (uint32_t b = m.x; b < m.y; b += kLeafChunk) {
+    double4 P[kLeafChunk];
+#pragma unroll
+    for (int i = 0; i < kLeafChunk; ++i)
+      if (b + i < m.y) P[i] = pos[b + i];
+#pragma unroll
+    for (int i = 0; i < kLeafChunk; ++i) {
+      if (b + i >= m.y) break;
+      const int s = i & (kLeafLanes - 1);
+      const float w = (float)P[i].w;
+      const float dx = (float)(P[i].x - g.x) - ox,
+                  dy = (float)(P[i].y - g.y) - oy,
+                  dz = (float)(P[i].z - g.z) - oz;
+      q[0][s] = fmaf(w * dx, dx, q[0][s]);
+      q[1][s] = fmaf(w * dy, dy, q[1][s]);
+      q[2][s] = fmaf(w * dz, dz, q[2][s]);
+      q[3][s] = fmaf(w * dx, dy, q[3][s]);
+      q[4][s] = fmaf(w * dx, dz, q[4][s]);
+      q[5][s] = fmaf(w * dy, dz, q[5][s]);
+    }
+  }
+  float r[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r[k] = (q[k][0] + q[k][1]) + (q[k][2] + q[k][3]);
+  qa = make_float4(r[0], r[1], r[2], r[3]);
+  qb = make_float4(r[4], r[5], 0.f, 0.f);
+}
+
+// One block per workgroup.  Cell p of the block (id c0 + p) is taken by
+// thread p % kMomThreads.  LDS holds per cell its skip id (relative to c0)
+// with its level and leaf flag, the FP32 offset of its centre from its
+// parent's (the term (float)(child centre - parent centre) of the parent's
+// sums, formed in FP64 and rounded once, as k_mom_internal forms it) and its
+// moments.  Nothing is written to global memory before the last barrier, so
+// the barriers wait for LDS only.
+template <bool QUAD>
+__global__ void __launch_bounds__(kMomThreads)
+k_mom_block(const uint32_t* __restrict__ blocks,
+            const CellRec* __restrict__ rec, const double4* __restrict__ pos,
+            float4* __restrict__ mom, float4* __restrict__ quad,
+            double4* __restrict__ pm) {
+  __shared__ uint32_t s_word[kMomBlock];  // skip | level << 16 | leaf << 24
+  __shared__ float s_ox[kMomBlock], s_oy[kMomBlock], s_oz[kMomBlock];
+  __shared__ float4 s_mom[kMomBlock];
+  __shared__ float4 s_q[QUAD ? 2 * kMomBlock : 1];
+  __shared__ int s_lmax;
+  const uint32_t c0 = blocks[blockIdx.x];
+  const int tid = threadIdx.x;
+  const uint4 m0 = rec[c0].meta;
+  const uint32_t size = subtree_cells(m0, c0);
+  if (size > (uint32_t)kMomBlock) return;  // not a block (uniform)
+  if (tid == 0) s_lmax = -1;
+  __syncthreads();
+  int lmax = -1;
+  double gx[kMomPer], gy[kMomPer], gz[kMomPer];
+#pragma unroll
+  for (int u = 0; u < kMomPer; ++u) {
+    const uint32_t p = (uint32_t)(u * kMomThreads + tid);
+    if (p >= size) continue;
+    const uint32_t c = c0 + p;
+    const uint4 m = rec[c].meta;
+    const double4 g = rec[c].geo;
+    gx[u] = g.x;
+    gy[u] = g.y;
+    gz[u] = g.z;
+    const uint32_t lev = m.w & 255u;
+    const bool leaf = (m.w >> 8) & 1u;
+    s_word[p] = (m.z - c0) | (lev << 16) | (leaf ? (1u << 24) : 0u);
+    if (p > 0) {
+      const double4 gp = rec[rec[c].aux.x].geo;
+      s_ox[p] = (float)(g.x - gp.x);
+      s_oy[p] = (float)(g.y - gp.y);
+      s_oz[p] = (float)(g.z - gp.z);
+    }
+    if (!leaf) {
+      lmax = (int)lev > lmax ? (int)lev : lmax;
+      continue;
+    }
+    float4 mo, qa, qb;
+    leaf_sums<QUAD>(m, g, pos, mo, qa, qb);
+    s_mom[p] = mo;
+    if (QUAD) {
+      s_q[2 * p] = qa;
+      s_q[2 * p + 1] = qb;
+    }
+  }
+  if (lmax >= 0) atomicMax(&s_lmax, lmax);
+  __syncthreads();
+  const int l_hi = s_lmax;
+  const int l_lo = (int)(m0.w & 255u);
+  for (int l = l_hi; l >= l_lo; --l) {
+#pragma unroll
+    for (int u = 0; u < kMomPer; ++u) {
+      const uint32_t p = (uint32_t)(u * kMomThreads + tid);
+      if (p >= size) continue;
+      const uint32_t w = s_word[p];
+      if ((w >> 24) || (int)((w >> 16) & 255u) != l) continue;
+      const uint32_t stop = w & 0xFFFFu;
+      float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+      for (uint32_t k = p + 1; k < stop;) {
+        const float4 mk = s_mom[k];
+        const float dx = s_ox[k] + mk.x;
+        const float dy = s_oy[k] + mk.y;
+        const float dz = s_oz[k] + mk.z;
+        M += mk.w;
+        sx = fmaf(mk.w, dx, sx);
+        sy = fmaf(mk.w, dy, sy);
+        sz = fmaf(mk.w, dz, sz);
+        const uint32_t s = s_word[k] & 0xFFFFu;
+        k = s > k ? s : stop;
+      }
+      const float inv = M > 0.f ? 1.0f / M : 0.f;
+      const float ox = sx * inv, oy = sy * inv, oz = sz * inv;
+      s_mom[p] = make_float4(ox, oy, oz, M);
+      if (QUAD) {
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
+        for (uint32_t k = p + 1; k < stop;) {
+          const float4 mk = s_mom[k];
+          const float4 qa = s_q[2 * k];
+          const float4 qb = s_q[2 * k + 1];
+          const float dx = s_ox[k] + mk.x - ox;
+          const float dy = s_oy[k] + mk.y - oy;
+          const float dz = s_oz[k] + mk.z - oz;
+          const float wk = mk.w;
+          s0 += qa.x + wk * dx * dx;
+          s1 += qa.y + wk * dy * dy;
+          s2 += qa.z + wk * dz * dz;
+          s3 += qa.w + wk * dx * dy;
+          s4 += qb.x + wk * dx * dz;
+          s5 += qb.y + wk * dy * dz;
+          const uint32_t s = s_word[k] & 0xFFFFu;
+          k = s > k ? s : stop;
+        }
+        s_q[2 * p] = make_float4(s0, s1, s2, s3);
+        s_q[2 * p + 1] = make_float4(s4, s5, 0.f, 0.f);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < kMomPer; ++u) {
+    const uint32_t p = (uint32_t)(u * kMomThreads + tid);
+    if (p >= size) continue;
+    const uint32_t c = c0 + p;
+    const float4 mo = s_mom[p];
+    mom[c] = mo;
+    pm[c] = make_double4(gx[u] + (double)mo.x, gy[u] + (double)mo.y,
+                         gz[u] + (double)mo.z, (double)mo.w);
+    if (QUAD) {
+      quad[2 * (int64_t)c] = s_q[2 * p];
+      quad[2 * (int64_t)c + 1] = s_q[2 * p + 1];
+    }
+  }
+}
+
+// A top cell's sums from its children (ch: by octant, kNone where there is
+// none), in pre-order as k_mom_internal takes them.  A child tagged kTopTag
+// is a top cell: with LDS (s_mom != nullptr) its moments and centre come
+// from there by top position, otherwise from global memory (its id from
+// the top list).
+template <bool QUAD>
+__device__ __forceinline__ void top_sums(double gx, double gy, double gz,
+                                         const uint32_t* ch,
+                                         const uint32_t* __restrict__ top,
+                                         const CellRec* __restrict__ rec,
+                                         const float4* __restrict__ mom,
+                                         const float4* __restrict__ quad,
+                                         const float4* s_mom,
+                                         const double* s_gx,
+                                         const double* s_gy,
+                                         const double* s_gz,
+                                         const float4* s_q, float4& mo,
+                                         float4& qa_out, float4& qb_out) {
+  // per child: its moments and the FP32 offset of its centre from this
+  // cell's (formed in FP64 and rounded once, as k_mom_internal forms it)
+  float4 mk[8];
+  float ex[8], ey[8], ez[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const uint32_t e = ch[o];
+    if (e == kNone) continue;
+    double kx, ky, kz;
+    if ((e & kTopTag) && s_mom) {
+      const uint32_t t = e & ~kTopTag;
+      mk[o] = s_mom[t];
+      kx = s_gx[t];
+      ky = s_gy[t];
+      kz = s_gz[t];
+    } else {
+      const uint32_t k = (e & kTopTag) ? top[e & ~kTopTag] : e;
+      mk[o] = mom[k];
+      const double4 gk = rec[k].geo;
+      kx = gk.x;
+      ky = gk.y;
+      kz = gk.z;
+    }
+    ex[o] = (float)(kx - gx);
+    ey[o] = (float)(ky - gy);
+    ez[o] = (float)(kz - gz);
+  }
+  float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    if (ch[o] == kNone) continue;
+    const float dx = ex[o] + mk[o].x;
+    const float dy = ey[o] + mk[o].y;
+    const float dz = ez[o] + mk[o].z;
+    M += mk[o].w;
+    sx = fmaf(mk[o].w, dx, sx);
+    sy = fmaf(mk[o].w, dy, sy);
+    sz = fmaf(mk[o].w, dz, sz);
+  }
+  const float inv = M > 0.f ? 1.0f / M : 0.f;
+  const float ox = sx * inv, oy = sy * inv, oz = sz * inv;
+  mo = make_float4(ox, oy, oz, M);
+  if (!QUAD) return;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const uint32_t e = ch[o];
+    if (e == kNone) continue;
+    float4 qa, qb;
+    if ((e & kTopTag) && s_mom) {
+      qa = s_q[2 * (e & ~kTopTag)];
+      qb = s_q[2 * (e & ~kTopTag) + 1];
+    } else {
+      const uint32_t k = (e & kTopTag) ? top[e & ~kTopTag] : e;
+      qa = quad[2 * (int64_t)k];
+      qb = quad[2 * (int64_t)k + 1];
+    }
+    const float dx = ex[o] + mk[o].x - ox;
+    const float dy = ey[o] + mk[o].y - oy;
+    const float dz = ez[o] + mk[o].z - oz;
+    const float w = mk[o].w;
+    s0 += qa.x + w * dx * dx;
+    s1 += qa.y + w * dy * dy;
+    s2 += qa.z + w * dz * dz;
+    s3 += qa.w + w * dx * dy;
+    s4 += qb.x + w * dx * dz;
+    s5 += qb.y + w * dy * dz;
+  }
+  qa_out = make_float4(s0, s1, s2, s3);
+  qb_out = make_float4(s4, s5, 0.f, 0.f);
+}
+
+// The top cells, deepest level first, by one workgroup: a cell's children
+// are blocks' roots (summed by the previous launch, read from global
+// memory) or top cells one level deeper (summed before the last barrier by
+// this workgroup).  Up to top_lds<QUAD>() top cells keep their centres,
+// child tables and moments in LDS, by top position, and are written out
+// after the last barrier; with more, the top cells go through global
+// memory.
+template <bool QUAD>
+constexpr int top_lds() { return QUAD ? kMomTopLds / 2 : kMomTopLds; }
+
+template <bool QUAD>
+__global__ void __launch_bounds__(kMomTopThreads)
+k_mom_top(const uint32_t* __restrict__ top, const uint32_t* __restrict__ tlo,
+          const uint32_t* __restrict__ ctab, const CellRec* __restrict__ rec,
+          float4* __restrict__ mom, float4* __restrict__ quad,
+          double4* __restrict__ pm) {
+  constexpr int kCap = top_lds<QUAD>();
+  __shared__ double s_gx[kCap], s_gy[kCap], s_gz[kCap];
+  __shared__ float4 s_mom[kCap];
+  __shared__ uint32_t s_ch[8 * kCap];
+  __shared__ float4 s_q[QUAD ? 2 * kCap : 1];
+  const uint32_t n_top = tlo[kLevels];
+  if (n_top <= (uint32_t)kCap) {
+    for (uint32_t i = threadIdx.x; i < 8 * n_top; i += kMomTopThreads)
+      s_ch[i] = ctab[i];
+    constexpr int kPer = (kCap + kMomTopThreads - 1) / kMomTopThreads;
+    int lv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const uint32_t j = threadIdx.x + (uint32_t)(u * kMomTopThreads);
+      lv[u] = -1;
+      if (j >= n_top) continue;
+      const uint32_t c = top[j];
+      const double4 g = rec[c].geo;
+      lv[u] = (int)(rec[c].meta.w & 255u);
+      s_gx[j] = g.x;
+      s_gy[j] = g.y;
+      s_gz[j] = g.z;
+    }
+    __syncthreads();
+    for (int l = kLevels - 1; l >= 0; --l) {
+      if (tlo[l] >= tlo[l + 1]) continue;  // uniform
+#pragma unroll 1
+      for (int u = 0; u < kPer; ++u) {
+        if (lv[u] != l) continue;
+        const uint32_t j = threadIdx.x + (uint32_t)(u * kMomTopThreads);
+        uint32_t ch[8];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) ch[o] = s_ch[8 * j + o];
+        float4 mo, qa, qb;
+        top_sums<QUAD>(s_gx[j], s_gy[j], s_gz[j], ch, top, rec, mom, quad,
+                       s_mom, s_gx, s_gy, s_gz, s_q, mo, qa, qb);
+        s_mom[j] = mo;
+        if (QUAD) {
+          s_q[2 * j] = qa;
+          s_q[2 * j + 1] = qb;
+        }
+      }
+      __syncthreads();
+    }
+    for (uint32_t j = threadIdx.x; j < n_top; j += kMomTopThreads) {
+      const uint32_t c = top[j];
+      const float4 mo = s_mom[j];
+      mom[c] = mo;
+      pm[c] = make_double4(s_gx[j] + (double)mo.x, s_gy[j] + (double)mo.y,
+                           s_gz[j] + (double)mo.z, (double)mo.w);
+      if (QUAD) {
+        quad[2 * (int64_t)c] = s_q[2 * j];
+        quad[2 * (int64_t)c + 1] = s_q[2 * j + 1];
+      }
+    }
+    return;
+  }
+  for (int l = kLevels - 1; l >= 0; --l) {
+    const uint32_t a = tlo[l], b = tlo[l + 1];
+    if (a >= b) continue;  // uniform
+    for (uint32_t j = a + threadIdx.x; j < b; j += kMomTopThreads) {
+      const uint32_t c = top[j];
+      const double4 g = rec[c].geo;
+      uint32_t ch[8];
+#pragma unroll
+      for (int o = 0; o < 8; ++o) ch[o] = ctab[8 * (int64_t)j + o];
+      float4 mo, qa, qb;
+      top_sums<QUAD>(g.x, g.y, g.z, ch, top, rec, mom, quad, nullptr, nullptr,
+                     nullptr, nullptr, nullptr, mo, qa, qb);
+      mom[c] = mo;
+      pm[c] = make_double4(g.x + (double)mo.x, g.y + (double)mo.y,
+                           g.z + (double)mo.z, (double)mo.w);
+      if (QUAD) {
+        quad[2 * (int64_t)c] = qa;
+        quad[2 * (int64_t)c + 1] = qb;
+      }
+    }
+    __syncthreads();
+  }
+}
 }  // namespace
 
 // The chunk table (system, first, end) of the bounding-box pass is built on
@@ -824,7 +1336,7 @@ int launch_level_lists(nb_ctx* c) {
   const int nblk = (int)grid_for(c->n_cell, kBkTile);
   int rc = reserve(c, c->lvl_cells, (size_t)c->n_cell);
   if (!rc) rc = reserve(c, c->bucket, (size_t)kBuckets * nblk + 1);
-  if (!rc) rc = reserve(c, c->lvl_stage, kLevels + 2);
+  if (!rc) rc = reserve(c, c->lvl_stage, kLevels + 4);
   if (rc) return rc;
   hipLaunchKernelGGL(k_bucket_hist, dim3(nblk), dim3(kBkThreads), 0,
                      c->stream, c->n_cell, (const CellRec*)c->c_rec.p,
@@ -843,6 +1355,50 @@ int launch_level_lists(nb_ctx* c) {
   return hip_check(c, hipGetLastError(), "bucket scatter launch");
 }
 
+// Blocks and top cells of the moment pass (the tree's topology is fixed
+// until the next construction).  Top cells at one level have disjoint
+// subtrees of more than kMomBlock cells, so there are at most
+// kLevels n_cell / (kMomBlock + 1) of them.
+int launch_mom_plan(nb_ctx* c) {
+  const int64_t nc = c->n_cell;
+  const int64_t top_cap = kLevels * nc / (kMomBlock + 1) + 1;
+  int rc = reserve(c, c->mp_bflag, (size_t)nc + 1);
+  if (!rc) rc = reserve(c, c->mp_tflag, (size_t)nc + 1);
+  if (!rc) rc = reserve(c, c->mp_blocks, (size_t)nc);
+  if (!rc) rc = reserve(c, c->mp_top, (size_t)top_cap);
+  if (!rc) rc = reserve(c, c->mp_tlo, kLevels + 1);
+  if (!rc) rc = reserve(c, c->mp_ctab, 8 * (size_t)top_cap);
+  if (rc) return rc;
+  const unsigned grid = grid_for(nc, 256);
+  hipLaunchKernelGGL(k_mp_flags, dim3(grid), dim3(256), 0, c->stream, nc,
+                     (const CellRec*)c->c_rec.p, c->mp_bflag.p);
+  rc = hip_check(c, hipGetLastError(), "block flags launch");
+  if (!rc) rc = scan_u32(c, c->mp_bflag.p, c->mp_bflag.p, nc);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_mp_blocks, dim3(grid), dim3(256), 0, c->stream, nc,
+                     (const uint32_t*)c->mp_bflag.p, c->mp_blocks.p);
+  hipLaunchKernelGGL(k_mp_tflags, dim3(grid), dim3(256), 0, c->stream, nc,
+                     (const uint32_t*)c->lvl_cells.p,
+                     (const CellRec*)c->c_rec.p, c->mp_tflag.p);
+  rc = hip_check(c, hipGetLastError(), "top flags launch");
+  if (!rc) rc = scan_u32(c, c->mp_tflag.p, c->mp_tflag.p, nc);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_mp_top, dim3(grid), dim3(256), 0, c->stream, nc,
+                     (const uint32_t*)c->lvl_cells.p,
+                     (const uint32_t*)c->mp_tflag.p, c->mp_top.p, top_cap,
+                     c->c_rec.p);
+  const int64_t ctab_cap = 8 * top_cap;
+  hipLaunchKernelGGL(k_mp_tlo, dim3(grid_for(ctab_cap, 256)), dim3(256), 0,
+                     c->stream, nc, (const uint32_t*)c->lvl_stage.p,
+                     (const uint32_t*)c->mp_tflag.p,
+                     (const uint32_t*)c->mp_bflag.p, c->mp_tlo.p,
+                     c->lvl_stage.p + kLevels + 2, c->mp_ctab.p, top_cap);
+  hipLaunchKernelGGL(k_mp_ctab, dim3(grid), dim3(256), 0, c->stream, nc,
+                     (const CellRec*)c->c_rec.p, (const uint4*)c->c_wrec.p,
+                     c->mp_ctab.p, ctab_cap);
+  return hip_check(c, hipGetLastError(), "moment plan launch");
+}
+
 int launch_moments(nb_ctx* c) {
   const size_t nc = (size_t)c->n_cell;
   int rc = reserve(c, c->c_mom, nc);
@@ -850,23 +1406,44 @@ int launch_moments(nb_ctx* c) {
   if (!rc) rc = reserve(c, c->c_quad, 2 * nc);
   if (rc) return rc;
   const bool quad = c->cfg.order == 2;
-  auto leaf = quad ? k_mom_leaf<true> : k_mom_leaf<false>;
-  auto inner = quad ? k_mom_internal<true> : k_mom_internal<false>;
-  if (c->n_leaves > 0)
-    hipLaunchKernelGGL(leaf, dim3(grid_for(kLeafLanes * c->n_leaves, 256)),
-                       dim3(256), 0,
-                       c->stream, c->n_leaves,
-                       (const uint32_t*)c->lvl_cells.p + c->lvl_off[kLevels],
-                       (const CellRec*)c->c_rec.p, (const double4*)c->pos.p,
-                       c->c_mom.p, c->c_quad.p, c->c_pm.p);
-  for (int l = kMaxLevel - 1; l >= 0; --l) {
-    const int64_t cnt = c->lvl_count[l];
-    if (cnt == 0) continue;
-    hipLaunchKernelGGL(inner, dim3(grid_for(cnt, 256)), dim3(256), 0,
-                       c->stream, cnt,
-                       (const uint32_t*)c->lvl_cells.p + c->lvl_off[l],
-                       (const CellRec*)c->c_rec.p, c->c_mom.p, c->c_quad.p,
-                       c->c_pm.p);
+  if (!(c->cfg.flags & NB_FLAG_LEVEL_MOMENTS)) {
+    // two launches: the blocks (leaves included), then the top cells
+    if (c->mp_nblk > 0) {
+      auto blk = quad ? k_mom_block<true> : k_mom_block<false>;
+      hipLaunchKernelGGL(blk, dim3((unsigned)c->mp_nblk), dim3(kMomThreads),
+                         0, c->stream, (const uint32_t*)c->mp_blocks.p,
+                         (const CellRec*)c->c_rec.p, (const double4*)c->pos.p,
+                         c->c_mom.p, c->c_quad.p, c->c_pm.p);
+    }
+    if (c->mp_ntop > 0) {
+      auto top = quad ? k_mom_top<true> : k_mom_top<false>;
+      hipLaunchKernelGGL(top, dim3(1), dim3(kMomTopThreads), 0, c->stream,
+                         (const uint32_t*)c->mp_top.p,
+                         (const uint32_t*)c->mp_tlo.p,
+                         (const uint32_t*)c->mp_ctab.p,
+                         (const CellRec*)c->c_rec.p, c->c_mom.p, c->c_quad.p,
+                         c->c_pm.p);
+    }
+  } else {
+    // one launch per level (leaves, then the internal levels bottom-up)
+    auto leaf = quad ? k_mom_leaf<true> : k_mom_leaf<false>;
+    auto inner = quad ? k_mom_internal<true> : k_mom_internal<false>;
+    if (c->n_leaves > 0)
+      hipLaunchKernelGGL(leaf, dim3(grid_for(kLeafLanes * c->n_leaves, 256)),
+                         dim3(256), 0,
+                         c->stream, c->n_leaves,
+                         (const uint32_t*)c->lvl_cells.p + c->lvl_off[kLevels],
+                         (const CellRec*)c->c_rec.p, (const double4*)c->pos.p,
+                         c->c_mom.p, c->c_quad.p, c->c_pm.p);
+    for (int l = kMaxLevel - 1; l >= 0; --l) {
+      const int64_t cnt = c->lvl_count[l];
+      if (cnt == 0) continue;
+      hipLaunchKernelGGL(inner, dim3(grid_for(cnt, 256)), dim3(256), 0,
+                         c->stream, cnt,
+                         (const uint32_t*)c->lvl_cells.p + c->lvl_off[l],
+                         (const CellRec*)c->c_rec.p, c->c_mom.p, c->c_quad.p,
+                         c->c_pm.p);
+    }
   }
   rc = hip_check(c, hipGetLastError(), "moments launch");
   if (!rc && c->learn) rc = launch_com(c);

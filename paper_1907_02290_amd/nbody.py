@@ -34,6 +34,7 @@ NB_FLAG_GRAPH = 2
 NB_FLAG_REFRESH = 4
 NB_FLAG_PERSISTENT = 8
 NB_FLAG_COPIED_LISTS = 16
+NB_FLAG_LEVEL_MOMENTS = 32
 MLP_NIN = 12
 MLP_NPARAM = 5057
 MLP_STATIC_MAX_ROWS = 8192
@@ -152,13 +153,14 @@ class Context:
                  order=1, ext_mass=0.0, timing=False, graph=False,
                  refresh=False, k_max=8, p_star=0.5, tau=0.0,
                  persistent=False, copied_lists=False, tile_j=0,
-                 waves_per_simd=0, stream=None):
+                 waves_per_simd=0, stream=None, level_moments=False):
         self._lib = load()
         flags = (NB_FLAG_TIMING if timing else 0) | \
             (NB_FLAG_GRAPH if graph else 0) | \
             (NB_FLAG_REFRESH if refresh else 0) | \
             (NB_FLAG_PERSISTENT if persistent else 0) | \
-            (NB_FLAG_COPIED_LISTS if copied_lists else 0)
+            (NB_FLAG_COPIED_LISTS if copied_lists else 0) | \
+            (NB_FLAG_LEVEL_MOMENTS if level_moments else 0)
         self._cfg = nb_config(theta, eps, G, ext_mass, n_leaf, n_grp, order,
                               flags, k_max, p_star, tau, tile_j,
                               waves_per_simd, stream)
@@ -218,6 +220,9 @@ class Context:
             elif k == "copied_lists":
                 self._cfg.flags = (self._cfg.flags & ~NB_FLAG_COPIED_LISTS) | \
                     (NB_FLAG_COPIED_LISTS if v else 0)
+            elif k == "level_moments":
+                self._cfg.flags = (self._cfg.flags & ~NB_FLAG_LEVEL_MOMENTS) | \
+                    (NB_FLAG_LEVEL_MOMENTS if v else 0)
             else:
                 setattr(self._cfg, k, v)
         self._chk(self._lib.nb_set_config(self._h, C.byref(self._cfg)))
