@@ -22,7 +22,8 @@ The result is a small JSON record that ``bench.py --n-grp auto`` and users
 can pass back as configuration.
 
   python -m paper_1907_02290_amd.tune --workload disk_4m [--n N]
-         [--n-grp 32,64,128,256,512] [--n-leaf 8] [--tile-j 64,128,192,256]
+         [--n-grp 32,48,64,96,128,192,256,384,512] [--n-leaf 8]
+         [--tile-j 64,128,192,256]
          [--waves 4,6,8] [--cycles 2] [--theta T] [--out F]
 """
 from __future__ import annotations
@@ -68,7 +69,8 @@ def time_config(d_dev, p, n_grp, n_leaf, reuse, cycles, offsets=None,
     return ms, info, err
 
 
-def tune(workload, n=None, n_grps=(32, 64, 128, 256, 512), n_leafs=(8,),
+def tune(workload, n=None, n_grps=(32, 48, 64, 96, 128, 192, 256, 384, 512),
+         n_leafs=(8,),
          tiles=(64, 128, 192, 256), waves=(4, 6, 8), cycles=2, reuse=None,
          theta=None, error=None, guard=1.05, max_err=None, log=None):
     import torch
@@ -135,7 +137,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="disk_4m")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--theta", type=float, default=None)
-    ap.add_argument("--n-grp", default="32,64,128,256,512")
+    ap.add_argument("--n-grp", default="32,48,64,96,128,192,256,384,512")
     ap.add_argument("--n-leaf", default="8")
     ap.add_argument("--tile-j", default="64,128,192,256")
     ap.add_argument("--waves", default="4,6,8")

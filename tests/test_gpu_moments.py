@@ -126,3 +126,22 @@ def test_two_launch_moments_match_oracle(order):
     if order == 2:
         scale = (oM * side ** 2)[:, None]
         assert np.all(np.abs(S - oS) <= 1e-5 * scale + 1e-30)
+
+
+@pytest.mark.parametrize("kind,n,n_leaf,order", [
+    # more than 2048 cells above the blocks (one-particle leaves): the top
+    # launch works from global memory
+    ("plummer", 1 << 22, 1, 1),
+    # more than 1024 with quadrupoles: the same
+    ("ring", 1 << 22, 8, 2)])
+def test_two_launch_moments_many_top_cells(kind, n, n_leaf, order):
+    say("case moments two-launch vs levels, many top cells %s n=%d" % (kind, n))
+    d = system(kind, n)
+    a, b = _pair(d, order, n_leaf)
+    try:
+        for ctx in (a, b):
+            ctx.build_tree()
+        _same_moments(a, b)
+    finally:
+        a.close()
+        b.close()
