@@ -406,6 +406,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->lvl_cells); release(c->bucket);
   release(c->mp_bflag); release(c->mp_tflag); release(c->mp_blocks);
   release(c->mp_top); release(c->mp_tlo); release(c->mp_ctab);
+  release(c->mp_slot);
   release(c->gflag); release(c->g_cell); release(c->g_begin);
   release(c->g_count); release(c->g_lo); release(c->g_hi);
   release(c->g_chunks); release(c->wi); release(c->queue);

@@ -174,7 +174,10 @@ struct nb_ctx {
   // level; tlo = where each level starts) with their child table (8 ids per
   // top cell, by octant); the scanned flags that made them; their counts
   nb::DBuf<uint32_t> mp_bflag, mp_tflag, mp_blocks, mp_top, mp_tlo, mp_ctab;
-  int64_t mp_nblk = 0, mp_ntop = 0;
+  // the terms each block's root adds to its parent's sums, by child-table
+  // slot (monopole moments; written by the block launch for the top launch)
+  nb::DBuf<float4> mp_slot;
+  int64_t mp_nblk = 0, mp_ntop = 0, mp_slot_cap = 0;
 
   // groups
   nb::DBuf<uint32_t> gflag;  // n_cell + 1, scanned

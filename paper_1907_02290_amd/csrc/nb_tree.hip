@@ -696,15 +696,24 @@ constexpr int kMomThreads = 256;
 constexpr int kMomPer = kMomBlock / kMomThreads;
 constexpr int kMomTopThreads = 1024;
 // top cells kept in LDS by the top launch, monopole (half with quadrupoles;
-// more: it works from global memory); the child table marks a child that is a top cell with kTopTag
-// and its position in the top list
+// more: it works from global memory); the child table marks a child that is
+// a top cell with kTopTag and its position in the top list
 constexpr int kMomTopLds = 2048;
 constexpr uint32_t kTopTag = 0x80000000u;
 // particles of a leaf loaded together
-constexpr int kLeafChunk = 8;
+constexpr int kLeafChunk = 4;
 
 __device__ inline uint32_t subtree_cells(const uint4 m, uint32_t c) {
   return m.z - c;  // the skip id is always past the cell
+}
+
+// Octant of a cell inside its parent, from its integer coordinates in the
+// walk record (x the high bit, as in the keys): children in octant order
+// are children in pre-order.
+__device__ inline uint32_t cell_octant(const uint4 w) {
+  const uint64_t q = (uint64_t)w.x | ((uint64_t)(w.y & 0x7FFFFFFFu) << 32);
+  return (uint32_t)(((q & 1u) << 2) | (((q >> 21) & 1u) << 1) |
+                    ((q >> 42) & 1u));
 }
 
 // Block roots: at most kMomBlock cells in the subtree, and a system root or
@@ -798,11 +807,7 @@ k_mp_ctab(int64_t n_cell, const CellRec* __restrict__ rec,
   if ((m.w & 255u) == 0) return;
   const uint32_t p = rec[c].aux.x;
   if (subtree_cells(rec[p].meta, p) <= (uint32_t)kMomBlock) return;
-  const uint4 w = wrec[c];
-  const uint64_t q = (uint64_t)w.x | ((uint64_t)(w.y & 0x7FFFFFFFu) << 32);
-  const uint32_t oct = (uint32_t)(((q & 1u) << 2) | (((q >> 21) & 1u) << 1) |
-                                  ((q >> 42) & 1u));
-  const int64_t slot = 8 * (int64_t)rec[p].aux.y + oct;
+  const int64_t slot = 8 * (int64_t)rec[p].aux.y + cell_octant(wrec[c]);
   const bool is_top = subtree_cells(m, (uint32_t)c) > (uint32_t)kMomBlock;
   if (slot < ctab_cap)
     ctab[slot] = is_top ? (kTopTag | rec[c].aux.y) : (uint32_t)c;
@@ -810,8 +815,9 @@ k_mp_ctab(int64_t n_cell, const CellRec* __restrict__ rec,
 
 // A leaf's sums from its particles: the four interleaved partial sums of
 // k_mom_leaf's lanes (particle i of the leaf goes to sum i % 4), added
-// pairwise as its exchanges add them.  The particles are loaded eight at a
-// time, so that a leaf waits for one load latency per eight.
+// pairwise as its exchanges add them.  The particles are loaded four at a
+// time (a leaf of the disk holds 2.8 on average), so that a leaf waits for
+// one load latency per four.
 template <bool QUAD>
 __device__ __forceinline__ void leaf_sums(const uint4 m, const double4 g,
                                           const double4* __restrict__ pos,
@@ -823,7 +829,7 @@ __device__ __forceinline__ void leaf_sums(const uint4 m, const double4 g,
     double4 P[kLeafChunk];
 #pragma unroll
     for (int i = 0; i < kLeafChunk; ++i)
-      if (b + i < m.y) P[i] = pos[b + i];
+      P[i] = pos[b + i < m.y ? b + i : m.y - 1];
 #pragma unroll
     for (int i = 0; i < kLeafChunk; ++i) {
       if (b + i >= m.y) break;
@@ -854,7 +860,7 @@ __device__ __forceinline__ void leaf_sums(const uint4 m, const double4 g,
     double4 P[kLeafChunk];
 #pragma unroll
     for (int i = 0; i < kLeafChunk; ++i)
-      if (b + i < m.y) P[i] = pos[b + i];
+      P[i] = pos[b + i < m.y ? b + i : m.y - 1];
 #pragma unroll
     for (int i = 0; i < kLeafChunk; ++i) {
       if (b + i >= m.y) break;
@@ -888,9 +894,10 @@ __device__ __forceinline__ void leaf_sums(const uint4 m, const double4 g,
 template <bool QUAD>
 __global__ void __launch_bounds__(kMomThreads)
 k_mom_block(const uint32_t* __restrict__ blocks,
-            const CellRec* __restrict__ rec, const double4* __restrict__ pos,
-            float4* __restrict__ mom, float4* __restrict__ quad,
-            double4* __restrict__ pm) {
+            const CellRec* __restrict__ rec, const uint4* __restrict__ wrec,
+            const double4* __restrict__ pos, float4* __restrict__ mom,
+            float4* __restrict__ quad, double4* __restrict__ pm,
+            float4* __restrict__ slot, int64_t slot_cap) {
   __shared__ uint32_t s_word[kMomBlock];  // skip | level << 16 | leaf << 24
   __shared__ float s_ox[kMomBlock], s_oy[kMomBlock], s_oz[kMomBlock];
   __shared__ float4 s_mom[kMomBlock];
@@ -989,6 +996,18 @@ k_mom_block(const uint32_t* __restrict__ blocks,
     }
     __syncthreads();
   }
+  // the root's terms in its parent's sums, for the top launch (a block's
+  // root that is not a system's root has a top cell as parent)
+  if (!QUAD && tid == 0 && (m0.w & 255u) != 0) {
+    const uint32_t par = rec[c0].aux.x;
+    const double4 gp = rec[par].geo;
+    const int64_t k = 8 * (int64_t)rec[par].aux.y + cell_octant(wrec[c0]);
+    const float4 mo = s_mom[0];
+    if (k < slot_cap)
+      slot[k] = make_float4((float)(gx[0] - gp.x) + mo.x,
+                            (float)(gy[0] - gp.y) + mo.y,
+                            (float)(gz[0] - gp.z) + mo.z, mo.w);
+  }
 #pragma unroll
   for (int u = 0; u < kMomPer; ++u) {
     const uint32_t p = (uint32_t)(u * kMomThreads + tid);
@@ -1006,11 +1025,10 @@ k_mom_block(const uint32_t* __restrict__ blocks,
 }
 
 // A top cell's sums from its children (ch: by octant, kNone where there is
-// none), in pre-order as k_mom_internal takes them.  A child tagged kTopTag
-// is a top cell: with LDS (s_mom != nullptr) its moments and centre come
-// from there by top position, otherwise from global memory (its id from
-// the top list).
-template <bool QUAD>
+// none), in pre-order as k_mom_internal takes them.  A child tagged
+// kTopTag is a top cell: its moments are in LDS (s_mom, s_q) by top
+// position when LDS, otherwise in global memory (its id from the top list).
+template <bool QUAD, bool LDS>
 __device__ __forceinline__ void top_sums(double gx, double gy, double gz,
                                          const uint32_t* ch,
                                          const uint32_t* __restrict__ top,
@@ -1018,37 +1036,34 @@ __device__ __forceinline__ void top_sums(double gx, double gy, double gz,
                                          const float4* __restrict__ mom,
                                          const float4* __restrict__ quad,
                                          const float4* s_mom,
-                                         const double* s_gx,
-                                         const double* s_gy,
-                                         const double* s_gz,
                                          const float4* s_q, float4& mo,
                                          float4& qa_out, float4& qb_out) {
-  // per child: its moments and the FP32 offset of its centre from this
-  // cell's (formed in FP64 and rounded once, as k_mom_internal forms it)
+  // per child: its moments, the FP32 offset of its centre from this cell's
+  // (formed in FP64 and rounded once, as k_mom_internal forms it), and its
+  // top position (kNone: not a top cell, or no LDS)
   float4 mk[8];
   float ex[8], ey[8], ez[8];
+  uint32_t tp[8], kid[8];
+  // kid: the child's cell id (a top child's from the top list; an absent
+  // child reads cell 0 instead, so that its loads need no branch, and its
+  // values are never used)
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
     const uint32_t e = ch[o];
-    if (e == kNone) continue;
-    double kx, ky, kz;
-    if ((e & kTopTag) && s_mom) {
-      const uint32_t t = e & ~kTopTag;
-      mk[o] = s_mom[t];
-      kx = s_gx[t];
-      ky = s_gy[t];
-      kz = s_gz[t];
-    } else {
-      const uint32_t k = (e & kTopTag) ? top[e & ~kTopTag] : e;
-      mk[o] = mom[k];
-      const double4 gk = rec[k].geo;
-      kx = gk.x;
-      ky = gk.y;
-      kz = gk.z;
-    }
-    ex[o] = (float)(kx - gx);
-    ey[o] = (float)(ky - gy);
-    ez[o] = (float)(kz - gz);
+    const bool tagged = e != kNone && (e & kTopTag);
+    const uint32_t k = e == kNone ? 0u : (tagged ? top[e & ~kTopTag] : e);
+    kid[o] = k;
+    const double4 gk = rec[k].geo;
+    mk[o] = mom[k];
+    ex[o] = (float)(gk.x - gx);
+    ey[o] = (float)(gk.y - gy);
+    ez[o] = (float)(gk.z - gz);
+    tp[o] = (LDS && tagged) ? (e & ~kTopTag) : kNone;
+  }
+  if (LDS) {
+#pragma unroll
+    for (int o = 0; o < 8; ++o)
+      if (tp[o] != kNone) mk[o] = s_mom[tp[o]];
   }
   float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
 #pragma unroll
@@ -1069,16 +1084,14 @@ __device__ __forceinline__ void top_sums(double gx, double gy, double gz,
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f;
 #pragma unroll
   for (int o = 0; o < 8; ++o) {
-    const uint32_t e = ch[o];
-    if (e == kNone) continue;
+    if (ch[o] == kNone) continue;
     float4 qa, qb;
-    if ((e & kTopTag) && s_mom) {
-      qa = s_q[2 * (e & ~kTopTag)];
-      qb = s_q[2 * (e & ~kTopTag) + 1];
+    if (LDS && tp[o] != kNone) {
+      qa = s_q[2 * tp[o]];
+      qb = s_q[2 * tp[o] + 1];
     } else {
-      const uint32_t k = (e & kTopTag) ? top[e & ~kTopTag] : e;
-      qa = quad[2 * (int64_t)k];
-      qb = quad[2 * (int64_t)k + 1];
+      qa = quad[2 * (int64_t)kid[o]];
+      qb = quad[2 * (int64_t)kid[o] + 1];
     }
     const float dx = ex[o] + mk[o].x - ox;
     const float dy = ey[o] + mk[o].y - oy;
@@ -1099,9 +1112,93 @@ __device__ __forceinline__ void top_sums(double gx, double gy, double gz,
 // are blocks' roots (summed by the previous launch, read from global
 // memory) or top cells one level deeper (summed before the last barrier by
 // this workgroup).  Up to top_lds<QUAD>() top cells keep their centres,
-// child tables and moments in LDS, by top position, and are written out
-// after the last barrier; with more, the top cells go through global
-// memory.
+// child tables and moments in LDS and are written out after the last
+// barrier; beyond that the top cells go through global memory.
+// Monopole moments of at most kMomTopThreads top cells (the common case):
+// one per thread.  A child that is a block's root left its terms in the
+// parent's slot (slot 8 j + octant: the FP32 centre offset plus COM offset,
+// and the mass, as k_mom_internal forms them), so the loads before the
+// level loop are contiguous per thread; a top child's centre and moments
+// come from LDS by top position.  Only 40 KiB of LDS are allocated.
+__global__ void __launch_bounds__(kMomTopThreads)
+k_mom_top_one(const uint32_t* __restrict__ top,
+              const uint32_t* __restrict__ tlo,
+              const uint32_t* __restrict__ ctab,
+              const float4* __restrict__ slot,
+              const CellRec* __restrict__ rec, float4* __restrict__ mom,
+              double4* __restrict__ pm) {
+  __shared__ float4 s_mom[kMomTopThreads];
+  __shared__ double s_gx[kMomTopThreads], s_gy[kMomTopThreads],
+      s_gz[kMomTopThreads];
+  const uint32_t n_top = tlo[kLevels];
+  const uint32_t j = threadIdx.x;
+  // a thread past the top cells works on the last one and writes nothing
+  const uint32_t jj = j < n_top ? j : n_top - 1;
+  const uint32_t c = top[jj];
+  const double4 g = rec[c].geo;
+  const int lv = j < n_top ? (int)(rec[c].meta.w & 255u) : -1;
+  uint32_t ch[8];
+  // per child: (dx, dy, dz, m) of a block root; (ex, ey, ez) of a top child
+  float tx[8], ty[8], tz[8], tw[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    ch[o] = ctab[8 * (int64_t)jj + o];
+    const float4 v = slot[8 * (int64_t)jj + o];
+    tx[o] = v.x;
+    ty[o] = v.y;
+    tz[o] = v.z;
+    tw[o] = v.w;
+  }
+  if (j < n_top) {
+    s_gx[j] = g.x;
+    s_gy[j] = g.y;
+    s_gz[j] = g.z;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const uint32_t e = ch[o];
+    if (e != kNone && (e & kTopTag)) {
+      const uint32_t tq = e & ~kTopTag;
+      tx[o] = (float)(s_gx[tq] - g.x);
+      ty[o] = (float)(s_gy[tq] - g.y);
+      tz[o] = (float)(s_gz[tq] - g.z);
+    }
+  }
+  for (int l = kLevels - 1; l >= 0; --l) {
+    if (tlo[l] >= tlo[l + 1]) continue;  // uniform
+    if (lv == l) {
+      float M = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const uint32_t e = ch[o];
+        if (e == kNone) continue;
+        float dx = tx[o], dy = ty[o], dz = tz[o], w = tw[o];
+        if (e & kTopTag) {
+          const float4 m = s_mom[e & ~kTopTag];
+          dx = tx[o] + m.x;
+          dy = ty[o] + m.y;
+          dz = tz[o] + m.z;
+          w = m.w;
+        }
+        M += w;
+        sx = fmaf(w, dx, sx);
+        sy = fmaf(w, dy, sy);
+        sz = fmaf(w, dz, sz);
+      }
+      const float inv = M > 0.f ? 1.0f / M : 0.f;
+      s_mom[j] = make_float4(sx * inv, sy * inv, sz * inv, M);
+    }
+    __syncthreads();
+  }
+  if (j < n_top) {
+    const float4 mo = s_mom[j];
+    mom[c] = mo;
+    pm[c] = make_double4(g.x + (double)mo.x, g.y + (double)mo.y,
+                         g.z + (double)mo.z, (double)mo.w);
+  }
+}
+
 template <bool QUAD>
 constexpr int top_lds() { return QUAD ? kMomTopLds / 2 : kMomTopLds; }
 
@@ -1145,8 +1242,8 @@ k_mom_top(const uint32_t* __restrict__ top, const uint32_t* __restrict__ tlo,
 #pragma unroll
         for (int o = 0; o < 8; ++o) ch[o] = s_ch[8 * j + o];
         float4 mo, qa, qb;
-        top_sums<QUAD>(s_gx[j], s_gy[j], s_gz[j], ch, top, rec, mom, quad,
-                       s_mom, s_gx, s_gy, s_gz, s_q, mo, qa, qb);
+        top_sums<QUAD, true>(s_gx[j], s_gy[j], s_gz[j], ch, top, rec, mom,
+                             quad, s_mom, s_q, mo, qa, qb);
         s_mom[j] = mo;
         if (QUAD) {
           s_q[2 * j] = qa;
@@ -1178,8 +1275,8 @@ k_mom_top(const uint32_t* __restrict__ top, const uint32_t* __restrict__ tlo,
 #pragma unroll
       for (int o = 0; o < 8; ++o) ch[o] = ctab[8 * (int64_t)j + o];
       float4 mo, qa, qb;
-      top_sums<QUAD>(g.x, g.y, g.z, ch, top, rec, mom, quad, nullptr, nullptr,
-                     nullptr, nullptr, nullptr, mo, qa, qb);
+      top_sums<QUAD, false>(g.x, g.y, g.z, ch, top, rec, mom, quad, nullptr,
+                            nullptr, mo, qa, qb);
       mom[c] = mo;
       pm[c] = make_double4(g.x + (double)mo.x, g.y + (double)mo.y,
                            g.z + (double)mo.z, (double)mo.w);
@@ -1368,6 +1465,8 @@ int launch_mom_plan(nb_ctx* c) {
   if (!rc) rc = reserve(c, c->mp_top, (size_t)top_cap);
   if (!rc) rc = reserve(c, c->mp_tlo, kLevels + 1);
   if (!rc) rc = reserve(c, c->mp_ctab, 8 * (size_t)top_cap);
+  if (!rc) rc = reserve(c, c->mp_slot, 8 * (size_t)top_cap);
+  c->mp_slot_cap = 8 * top_cap;
   if (rc) return rc;
   const unsigned grid = grid_for(nc, 256);
   hipLaunchKernelGGL(k_mp_flags, dim3(grid), dim3(256), 0, c->stream, nc,
@@ -1412,10 +1511,18 @@ int launch_moments(nb_ctx* c) {
       auto blk = quad ? k_mom_block<true> : k_mom_block<false>;
       hipLaunchKernelGGL(blk, dim3((unsigned)c->mp_nblk), dim3(kMomThreads),
                          0, c->stream, (const uint32_t*)c->mp_blocks.p,
-                         (const CellRec*)c->c_rec.p, (const double4*)c->pos.p,
-                         c->c_mom.p, c->c_quad.p, c->c_pm.p);
+                         (const CellRec*)c->c_rec.p, (const uint4*)c->c_wrec.p,
+                         (const double4*)c->pos.p, c->c_mom.p, c->c_quad.p,
+                         c->c_pm.p, c->mp_slot.p, c->mp_slot_cap);
     }
-    if (c->mp_ntop > 0) {
+    if (c->mp_ntop > 0 && !quad && c->mp_ntop <= kMomTopThreads) {
+      hipLaunchKernelGGL(k_mom_top_one, dim3(1), dim3(kMomTopThreads), 0,
+                         c->stream, (const uint32_t*)c->mp_top.p,
+                         (const uint32_t*)c->mp_tlo.p,
+                         (const uint32_t*)c->mp_ctab.p,
+                         (const float4*)c->mp_slot.p,
+                         (const CellRec*)c->c_rec.p, c->c_mom.p, c->c_pm.p);
+    } else if (c->mp_ntop > 0) {
       auto top = quad ? k_mom_top<true> : k_mom_top<false>;
       hipLaunchKernelGGL(top, dim3(1), dim3(kMomTopThreads), 0, c->stream,
                          (const uint32_t*)c->mp_top.p,
