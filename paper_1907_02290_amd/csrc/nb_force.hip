@@ -133,6 +133,9 @@ template <int KMAX>
 struct Tiles {
   static constexpr int kMaxSlices = KMAX;
   static constexpr int kBig = kTile * KMAX;
+  // LDS entries of a tile: one pad entry after each slice's block (up to
+  // 64 blocks, one per slice of single-particle chunks)
+  static constexpr int kLds = kBig + kTile;
 };
 
 // One group chunk per wavefront.  With r = 64 / n_i lane slices (r up to
@@ -161,6 +164,14 @@ struct ForceArgs {
   float eps2, G;
   float4* __restrict__ acc;
 };
+
+// LDS position of entry e = 64 u + lane of a tile (see force_item): in
+// block u when the blocks are the tile's 64-entry thirds, quarters...
+// (r <= KMAX), else in block (r (e + 1) - 1) / (64 KMAX) of r equal blocks.
+template <int KMAX>
+__device__ __forceinline__ int tile_pos(int e, int u, int r) {
+  return e + (r <= KMAX ? u : (r * (e + 1) - 1) / (kTile * KMAX));
+}
 
 // One slice's share of a tile of T entries of which `valid` are filled.
 __device__ __forceinline__ int block_count(int valid, int blk0, int blk1) {
@@ -197,6 +208,12 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
   // this slice's block of a full tile
   const int blk0 = r <= kMaxSlices ? sl * kTile : (sl * T) / r;
   const int blk1 = r <= kMaxSlices ? blk0 + kTile : ((sl + 1) * T) / r;
+  // In LDS each block is followed by one pad entry, so that block s starts
+  // at blk0 + s: the slices of a wave read their blocks at the same time,
+  // and blocks 64 entries apart would otherwise sit on the same LDS banks
+  // (16-byte entries; one pad shifts the next block by four banks).  Entry
+  // e of a tile, in block (r (e + 1) - 1) / T, goes to e + that block.
+  const int tbase = blk0 + sl;
   const uint32_t g = it.x;
   const double4 cg = rec[g_cell[g]].geo;
 
@@ -234,7 +251,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kMaxSlices; ++u)
-          if (u < q) tile[u * kTile + lane] = J[u];
+          if (u < q) tile[tile_pos<KMAX>(u * kTile + lane, u, r)] = J[u];
         const uint32_t nb = tb + (uint32_t)T;
         if (nb < n) {
 #pragma unroll
@@ -248,7 +265,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
         __syncthreads();
         if (act) {
           const int valid = n - tb < (uint32_t)T ? (int)(n - tb) : T;
-          slice_sum<1>(tile + blk0, nullptr, block_count(valid, blk0, blk1),
+          slice_sum<1>(tile + tbase, nullptr, block_count(valid, blk0, blk1),
                        xi, yi, zi, eps2, ax, ay, az, ph);
         }
       }
@@ -276,7 +293,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
 #pragma unroll
       for (int u = 0; u < kMaxSlices; ++u)
         if (u < q)
-          tile[u * kTile + lane] = make_float4(
+          tile[tile_pos<KMAX>(u * kTile + lane, u, r)] = make_float4(
               (float)(P[u].x - cg.x), (float)(P[u].y - cg.y),
               (float)(P[u].z - cg.z), (float)P[u].w);
       // the next tile's records and the ids of the one after arrive while
@@ -295,7 +312,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
       __syncthreads();
       if (act) {
         const int valid = n - tb < (uint32_t)T ? (int)(n - tb) : T;
-        slice_sum<1>(tile + blk0, nullptr, block_count(valid, blk0, blk1),
+        slice_sum<1>(tile + tbase, nullptr, block_count(valid, blk0, blk1),
                      xi, yi, zi, eps2, ax, ay, az, ph);
       }
     }
@@ -320,7 +337,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
           float4 qa = quad[2 * (int64_t)cid[u]];
           float4 qb = quad[2 * (int64_t)cid[u] + 1];
           qb.z = qa.x + qa.y + qa.z;
-          const int slot = u * kTile + lane;
+          const int slot = tile_pos<KMAX>(u * kTile + lane, u, r);
           tile[slot] = make_float4((float)(Q.x - cg.x), (float)(Q.y - cg.y),
                                    (float)(Q.z - cg.z), (float)Q.w);
           tq[2 * slot] = qa;
@@ -330,7 +347,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
       __syncthreads();
       if (act) {
         const int valid = ns - tb < (uint32_t)T ? (int)(ns - tb) : T;
-        slice_sum<2>(tile + blk0, tq + 2 * blk0,
+        slice_sum<2>(tile + tbase, tq + 2 * tbase,
                      block_count(valid, blk0, blk1), xi, yi, zi, eps2, ax,
                      ay, az, ph);
       }
@@ -418,8 +435,8 @@ template <int ORDER, bool COPIED, int KMAX, int WAVES>
 __global__ void __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_force(const uint4* __restrict__ wi, XcdPlan plan, ForceArgs A) {
-  __shared__ float4 tile[Tiles<KMAX>::kBig];
-  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<KMAX>::kBig : 1];
+  __shared__ float4 tile[Tiles<KMAX>::kLds];
+  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<KMAX>::kLds : 1];
   const uint32_t bid = blockIdx.x;
   const uint32_t x = bid & 7u;
   const int64_t j = plan.b[x] + (int64_t)(bid >> 3);
@@ -572,8 +589,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_force_queue(const uint4* __restrict__ wi, XcdPlan plan,
               unsigned int* __restrict__ queue, ForceArgs A) {
   constexpr int K = kDefaultSlices[ORDER];
-  __shared__ float4 tile[Tiles<K>::kBig];
-  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<K>::kBig : 1];
+  __shared__ float4 tile[Tiles<K>::kLds];
+  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<K>::kLds : 1];
   const uint32_t x = blockIdx.x & 7u;
   const int64_t lo = plan.b[x];
   const int64_t hi = plan.b[x + 1];
