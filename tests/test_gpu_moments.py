@@ -129,8 +129,10 @@ def test_two_launch_moments_match_oracle(order):
 
 
 @pytest.mark.parametrize("kind,n,n_leaf,order", [
-    # more than 2048 cells above the blocks (one-particle leaves): the top
-    # launch works from global memory
+    # 1447 cells above the blocks (one-particle leaves): more than one per
+    # thread of the top launch, which keeps them in LDS
+    ("plummer", 1 << 21, 1, 1),
+    # more than 2048: the top launch works from global memory
     ("plummer", 1 << 22, 1, 1),
     # more than 1024 with quadrupoles: the same
     ("ring", 1 << 22, 8, 2)])
