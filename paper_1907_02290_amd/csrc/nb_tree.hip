@@ -686,8 +686,10 @@ k_mom_internal(int64_t cnt, const uint32_t* __restrict__ list,
 // leaves from their particles, then one level per barrier, and writes the
 // block's moments out at the end.  The cells above the blocks (subtrees of
 // more than kMomBlock cells, the "top" cells) are then summed by a single
-// workgroup, level by level, each reading its children through a table of
-// child ids by octant (top children from LDS).  Every cell's sums are formed
+// workgroup, level by level, through a table of eight children by octant
+// per top cell: a block's root leaves the terms it adds to its parent's sums
+// in its slot of that table, and top children are exchanged through LDS.
+// Every cell's sums are formed
 // in the same order and precision as the per-level kernels above (leaves:
 // four interleaved partial sums added pairwise; internal cells: children in
 // pre-order), so the moments are the same bit for bit.
