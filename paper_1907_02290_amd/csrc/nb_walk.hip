@@ -687,8 +687,19 @@ k_expand(int64_t n_walk, int64_t nblk, const uint32_t* __restrict__ sel,
           if (lane >= d) inc += v;
         }
         const uint32_t total = __shfl(inc, 63, 64);
-        uint32_t* dst = epj + oe + (inc - n);
-        for (uint32_t j = 0; j < n; ++j) dst[j] = b + j;
+        // the chunk's particle ids, written by the whole wave in contiguous
+        // runs of 64: entry k belongs to the first lane whose inclusive
+        // size sum exceeds k (a binary search over the lanes' sums)
+        for (uint32_t k0 = 0; k0 < total; k0 += 64) {
+          const uint32_t k = k0 + (uint32_t)lane;
+          int L = 0;
+#pragma unroll
+          for (int step = 32; step > 0; step >>= 1)
+            if (__shfl(inc, L + step - 1, 64) <= k) L += step;
+          const uint32_t first = __shfl(b, L, 64);
+          const uint32_t before = __shfl(inc - n, L, 64);
+          if (k < total) epj[oe + k] = first + (k - before);
+        }
         oe += total;
       }
     }
