@@ -133,6 +133,16 @@ int stage_d2h(nb_ctx* c, size_t off, const void* src, size_t bytes) {
                    "staging copy");
 }
 
+void join_moments(nb_ctx* c) {
+  if (!c->mom_pending) return;
+  c->mom_pending = false;
+  if (hipStreamWaitEvent(c->stream, c->mom_done, 0) != hipSuccess) {
+    // ordering by a full wait instead
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(c->side);
+  }
+}
+
 int sync_stream(nb_ctx* c) {
   return hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
 }
@@ -223,10 +233,32 @@ static int build_tree(nb_ctx* c) {
                      (long long)c->n_groups);
   }
   {
-    Timed t(c, NB_PH_MOMENTS);
-    c->in_build = true;
-    rc = launch_moments(c);
-    c->in_build = false;
+    // The moment pass goes to the side stream and runs beside the group
+    // boxes and the walk; the force launch and every reader of the moments
+    // join it first.  In refresh mode the walk reads the centres this pass
+    // sets, so there it stays on the stream.
+    const bool side = !c->learn && c->side;
+    hipStream_t main = c->stream;
+    if (side) {
+      if ((rc = hip_check(c, hipEventRecord(c->mom_fork, main),
+                          "moment fork")) ||
+          (rc = hip_check(c, hipStreamWaitEvent(c->side, c->mom_fork, 0),
+                          "moment fork wait")))
+        return rc;
+      c->stream = c->side;
+    }
+    {
+      Timed t(c, NB_PH_MOMENTS);
+      c->in_build = true;
+      rc = launch_moments(c);
+      c->in_build = false;
+    }
+    if (side) {
+      const hipError_t e = hipEventRecord(c->mom_done, c->side);
+      c->stream = main;
+      c->mom_pending = true;
+      if (!rc) rc = hip_check(c, e, "moment join event");
+    }
     if (rc) return rc;
   }
   {
@@ -330,6 +362,15 @@ static int make_lists(nb_ctx* c, nb_mode mode) {
   return NB_OK;
 }
 
+// The side stream of the moment pass and its two events.
+static void release_side(nb_ctx* c) {
+  if (c->mom_fork) (void)hipEventDestroy(c->mom_fork);
+  if (c->mom_done) (void)hipEventDestroy(c->mom_done);
+  if (c->side) (void)hipStreamDestroy(c->side);
+  c->mom_fork = c->mom_done = nullptr;
+  c->side = nullptr;
+}
+
 }  // namespace nb
 
 using namespace nb;
@@ -367,13 +408,27 @@ int nb_create(const nb_config* cfg, nb_ctx** out) {
     }
     c->own_stream = true;
   }
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&c->mom_fork, hipEventDisableTiming) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&c->mom_done, hipEventDisableTiming) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    release_side(c);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return NB_ERR_HIP;
+  }
   if (static_scratch_init(c)) {
+    release_side(c);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return NB_ERR_HIP;
   }
   if (hipHostMalloc(&c->h_small, 4096, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
+    release_side(c);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return NB_ERR_OOM;
@@ -384,6 +439,7 @@ int nb_create(const nb_config* cfg, nb_ctx** out) {
 
 void nb_destroy(nb_ctx* c) {
   if (!c) return;
+  if (c->side) (void)hipStreamSynchronize(c->side);
   (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
   for (auto& t : c->timers) {
@@ -435,6 +491,7 @@ void nb_destroy(nb_ctx* c) {
   release(c->mlp_act); release(c->mlp_dz); release(c->mlp_lossp);
   release(c->mlp_part); release(c->mlp_x); release(c->mlp_y);
   if (c->h_small) (void)hipHostFree(c->h_small);
+  release_side(c);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -544,7 +601,9 @@ int nb_set_systems(nb_ctx* c, int64_t n_sys, const int64_t* off) {
 
 int nb_build_tree(nb_ctx* c) {
   if (!c) return NB_ERR_INPUT;
-  return build_tree(c);
+  const int rc = build_tree(c);
+  join_moments(c);
+  return rc;
 }
 
 int nb_make_lists(nb_ctx* c, nb_mode mode) {
@@ -581,8 +640,10 @@ int nb_compute_forces(nb_ctx* c, nb_mode mode) {
       if ((rc = refresh_checked(c))) return rc;
     }
   } else if (mode == NB_MAKE_LIST || mode == NB_MAKE_LIST_FOR_REUSE) {
-    if ((rc = build_tree(c))) return rc;
-    if ((rc = make_lists(c, mode))) return rc;
+    rc = build_tree(c);
+    if (!rc) rc = make_lists(c, mode);
+    join_moments(c);
+    if (rc) return rc;
   } else {
     return set_err(c, NB_ERR_INPUT, "bad mode %d", (int)mode);
   }

@@ -106,6 +106,13 @@ struct nb_ctx {
   nb_config cfg;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // A construction step's moment pass runs on `side`, beside the walk that
+  // follows it on `stream` (the walk needs the cells and group boxes, not
+  // the moments); mom_done marks its end, and join_moments makes `stream`
+  // wait for it before anything reads the moments.
+  hipStream_t side = nullptr;
+  hipEvent_t mom_fork = nullptr, mom_done = nullptr;
+  bool mom_pending = false;
   int device = 0;
   std::string err;
 
@@ -325,6 +332,7 @@ struct Timed {
 };
 int stage_d2h(nb_ctx* c, size_t off, const void* src, size_t bytes);
 int sync_stream(nb_ctx* c);
+void join_moments(nb_ctx* c);  // stream waits for a side-stream moment pass
 void drop_graph(nb_ctx* c);  // a captured step refers to the list buffers
 
 // ---- stage launchers; all enqueue on c->stream and return a status ----
