@@ -20,7 +20,11 @@
  *     of the last tree build; list ids refer to that internal order.
  *   - Work is enqueued on the context's HIP stream (the one given in
  *     nb_config.stream, or a stream the library creates).  Calls that return
- *     data to host memory synchronise that stream.
+ *     data to host memory synchronise that stream.  The moment pass of a
+ *     construction step runs on a second stream the library owns, forked
+ *     from and joined back into the context's stream by events before any
+ *     work that reads the moments, so everything enqueued on the context's
+ *     stream afterwards is ordered after it.
  *   - A context is not thread-safe; use one context per host thread.
  */
 #ifndef NBODY_H
