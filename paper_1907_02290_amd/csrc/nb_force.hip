@@ -129,13 +129,17 @@ __device__ __forceinline__ void slice_sum(const float4* __restrict__ t,
 constexpr int kDefaultSlices[3] = {0, 3, 2};
 constexpr int kDefaultWaves = 6;
 
-template <int KMAX>
+template <int ORDER, int KMAX>
 struct Tiles {
   static constexpr int kMaxSlices = KMAX;
   static constexpr int kBig = kTile * KMAX;
-  // LDS entries of a tile: one pad entry after each slice's block (up to
-  // 64 blocks, one per slice of single-particle chunks)
-  static constexpr int kLds = kBig + kTile;
+  // LDS entries of a tile: one pad entry after each slice's block, for up
+  // to kPad blocks (the slices past that share the last shift).  The
+  // quadrupole kernel stages 48 bytes per entry, and 64 pads would cost it
+  // a quarter of its occupancy; its slices past 16 (chunks of three
+  // particles or fewer) share one shift.
+  static constexpr int kPad = ORDER == 2 ? 16 : kTile;
+  static constexpr int kLds = kBig + kPad;
 };
 
 // One group chunk per wavefront.  With r = 64 / n_i lane slices (r up to
@@ -168,9 +172,11 @@ struct ForceArgs {
 // LDS position of entry e = 64 u + lane of a tile (see force_item): in
 // block u when the blocks are the tile's 64-entry thirds, quarters...
 // (r <= KMAX), else in block (r (e + 1) - 1) / (64 KMAX) of r equal blocks.
-template <int KMAX>
+template <int KMAX, int PAD>
 __device__ __forceinline__ int tile_pos(int e, int u, int r) {
-  return e + (r <= KMAX ? u : (r * (e + 1) - 1) / (kTile * KMAX));
+  int b = r <= KMAX ? u : (r * (e + 1) - 1) / (kTile * KMAX);
+  if constexpr (PAD < kTile) b = b < PAD - 1 ? b : PAD - 1;
+  return e + b;
 }
 
 // One slice's share of a tile of T entries of which `valid` are filled.
@@ -202,7 +208,8 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
   const int sl = lane / ni;
   const int ii = lane - sl * ni;
   const bool act = sl < r;
-  constexpr int kMaxSlices = Tiles<KMAX>::kMaxSlices;
+  constexpr int kMaxSlices = Tiles<ORDER, KMAX>::kMaxSlices;
+  constexpr int kPad = Tiles<ORDER, KMAX>::kPad;
   const int q = r < kMaxSlices ? r : kMaxSlices;  // tile = 64 q entries
   const int T = kTile * q;
   // this slice's block of a full tile
@@ -212,8 +219,9 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
   // at blk0 + s: the slices of a wave read their blocks at the same time,
   // and blocks 64 entries apart would otherwise sit on the same LDS banks
   // (16-byte entries; one pad shifts the next block by four banks).  Entry
-  // e of a tile, in block (r (e + 1) - 1) / T, goes to e + that block.
-  const int tbase = blk0 + sl;
+  // e of a tile, in block (r (e + 1) - 1) / T, goes to e + that block, or
+  // e + kPad - 1 past kPad - 1 blocks.
+  const int tbase = blk0 + (kPad < kTile && sl > kPad - 1 ? kPad - 1 : sl);
   const uint32_t g = it.x;
   const double4 cg = rec[g_cell[g]].geo;
 
@@ -251,7 +259,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < kMaxSlices; ++u)
-          if (u < q) tile[tile_pos<KMAX>(u * kTile + lane, u, r)] = J[u];
+          if (u < q) tile[tile_pos<KMAX, kPad>(u * kTile + lane, u, r)] = J[u];
         const uint32_t nb = tb + (uint32_t)T;
         if (nb < n) {
 #pragma unroll
@@ -293,7 +301,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
 #pragma unroll
       for (int u = 0; u < kMaxSlices; ++u)
         if (u < q)
-          tile[tile_pos<KMAX>(u * kTile + lane, u, r)] = make_float4(
+          tile[tile_pos<KMAX, kPad>(u * kTile + lane, u, r)] = make_float4(
               (float)(P[u].x - cg.x), (float)(P[u].y - cg.y),
               (float)(P[u].z - cg.z), (float)P[u].w);
       // the next tile's records and the ids of the one after arrive while
@@ -337,7 +345,7 @@ __device__ __forceinline__ void force_item(const uint4 it, const ForceArgs& A,
           float4 qa = quad[2 * (int64_t)cid[u]];
           float4 qb = quad[2 * (int64_t)cid[u] + 1];
           qb.z = qa.x + qa.y + qa.z;
-          const int slot = tile_pos<KMAX>(u * kTile + lane, u, r);
+          const int slot = tile_pos<KMAX, kPad>(u * kTile + lane, u, r);
           tile[slot] = make_float4((float)(Q.x - cg.x), (float)(Q.y - cg.y),
                                    (float)(Q.z - cg.z), (float)Q.w);
           tq[2 * slot] = qa;
@@ -435,8 +443,8 @@ template <int ORDER, bool COPIED, int KMAX, int WAVES>
 __global__ void __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu(WAVES, 8)))
 k_force(const uint4* __restrict__ wi, XcdPlan plan, ForceArgs A) {
-  __shared__ float4 tile[Tiles<KMAX>::kLds];
-  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<KMAX>::kLds : 1];
+  __shared__ float4 tile[Tiles<ORDER, KMAX>::kLds];
+  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<ORDER, KMAX>::kLds : 1];
   const uint32_t bid = blockIdx.x;
   const uint32_t x = bid & 7u;
   const int64_t j = plan.b[x] + (int64_t)(bid >> 3);
@@ -589,8 +597,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_force_queue(const uint4* __restrict__ wi, XcdPlan plan,
               unsigned int* __restrict__ queue, ForceArgs A) {
   constexpr int K = kDefaultSlices[ORDER];
-  __shared__ float4 tile[Tiles<K>::kLds];
-  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<K>::kLds : 1];
+  __shared__ float4 tile[Tiles<ORDER, K>::kLds];
+  __shared__ float4 tq[ORDER == 2 ? 2 * Tiles<ORDER, K>::kLds : 1];
   const uint32_t x = blockIdx.x & 7u;
   const int64_t lo = plan.b[x];
   const int64_t hi = plan.b[x + 1];
