@@ -10,11 +10,13 @@
 //  * a group of n_i < 33 particles is replicated over r = 64 / n_i lane
 //    slices; each slice sums its own block of every tile and the slices are
 //    added through LDS at the end;
-//  * the list is walked in tiles of 64 min(r, 4) entries, first its
+//  * the list is walked in tiles of 64 min(r, KMAX) entries (KMAX 3 for
+//    the monopole and 2 for the quadrupole kernel by default), first its
 //    particles (by slot), then its superparticles (by cell id; the same
 //    {x, y, z, m} FP64 record): each lane gathers entries by index, converts
 //    them to FP32 offsets and stores them in LDS; the lanes of a slice then
-//    read its block back as broadcasts;
+//    read its block back as broadcasts, each block shifted by one pad entry
+//    so that the slices' simultaneous reads fall on different LDS banks;
 //  * FP32 arithmetic with per-tile partial sums added into the totals;
 //    the potential of the particle on itself is removed at the end;
 //  * workgroup ids are remapped so that each XCD (workgroups are dealt out
@@ -119,7 +121,7 @@ __device__ __forceinline__ void slice_sum(const float4* __restrict__ t,
 
 // Largest tile, in 64-entry blocks (KMAX): by default 3 for the monopole
 // kernel, whose prefetched records (one FP64 record per slice and lane) then
-// fit six waves per SIMD (77 VGPRs; with 4 blocks it needed 93, five
+// fit six waves per SIMD (79 VGPRs; with 4 blocks it needed 93, five
 // waves), and 2 for the quadrupole kernel, which stages 2 x 16 bytes of
 // second moments per entry besides the record, so that its LDS (and so its
 // occupancy) stays in line with its registers.  The configuration can pick
@@ -169,9 +171,11 @@ struct ForceArgs {
   float4* __restrict__ acc;
 };
 
-// LDS position of entry e = 64 u + lane of a tile (see force_item): in
-// block u when the blocks are the tile's 64-entry thirds, quarters...
-// (r <= KMAX), else in block (r (e + 1) - 1) / (64 KMAX) of r equal blocks.
+// LDS position of entry e = 64 u + lane of a tile (see force_item): e plus
+// one pad entry per block before its own, where its block is u when the
+// blocks are the tile's 64-entry thirds, quarters... (r <= KMAX), else
+// (r (e + 1) - 1) / (64 KMAX) of r equal blocks; blocks past PAD - 1 share
+// the shift of block PAD - 1.
 template <int KMAX, int PAD>
 __device__ __forceinline__ int tile_pos(int e, int u, int r) {
   int b = r <= KMAX ? u : (r * (e + 1) - 1) / (kTile * KMAX);
